@@ -1,0 +1,135 @@
+"""Gaussian random field on a periodic box (oracle, FP64).
+
+Follows section "Mock generation" and eq:deltaL, eq:eta of the paper:
+
+* the noise is drawn directly in k-space (the footnote of "Mock generation"
+  notes this is equivalent and saves one FFT), as unit-variance complex
+  normals W(k) obeying W(-k) = conj(W(k)) so the real-space field is real;
+* delta_hat(k) = s(n^2) W(k) with s = sqrt(P/V_box) (see oracle.power);
+* eta_pq_hat(k) = f k_p k_q / k^2 delta_hat(k) (eq:eta), and the
+  line-of-sight component for a fixed line of sight z is
+  eta_par_hat = f mu_z^2 delta_hat (section "The expected auto-correlation
+  function of the mocks" writes eta_par_hat = f mu_k^2 delta_hat);
+* real space: delta(m) = sum_k delta_hat(k) exp(+2 pi i n.m / N), the
+  unnormalised inverse DFT; grid point m sits at x = m dx.
+
+Mode bookkeeping (paper silent; reading chosen here):
+* index i in [0, N) per axis, signed frequency n = i for i < N/2, else i - N
+  (so the Nyquist index N/2 has n = -N/2);
+* linear index lin(i) = (ix N + iy) N + iz; partner i' = (-i) mod N;
+* the owner of a pair is the mode with the lower linear index; its normals
+  come from oracle.philox.normal_pair(seed, 0, lin(owner));
+* W(owner) = (z1 + i z2)/sqrt(2), W(partner) = conj(W(owner)); a
+  self-conjugate mode (every index 0 or N/2) takes W = z1;
+* fixed_amp (Angulo & Pontzen 2016 test hook): W <- W/|W|;
+* only_n2 (test hook): keep only modes with n^2 == only_n2;
+* k = 0 carries no power (s(0) = 0);
+* cross components (p != q) vanish on the Nyquist plane of p or q, where
+  k_p k_q would break the Hermitian symmetry.
+
+The packed output of the hot path is the complex field delta + i eta_par,
+obtained from one inverse transform of delta_hat + i eta_par_hat.
+"""
+import numpy as np
+
+from . import philox
+
+COMPONENTS = ("delta", "xx", "yy", "zz", "xy", "xz", "yz")
+
+
+def signed_freq(i, n):
+    i = np.asarray(i, dtype=np.int64)
+    return np.where(i < n // 2, i, i - n)
+
+
+def mode_grid(n, ix_slice=None):
+    """Integer index grids (ix, iy, iz) for all modes, or for a slab of ix."""
+    ix = np.arange(n, dtype=np.int64) if ix_slice is None else \
+        np.arange(n, dtype=np.int64)[ix_slice]
+    iy = np.arange(n, dtype=np.int64)
+    iz = np.arange(n, dtype=np.int64)
+    return np.meshgrid(ix, iy, iz, indexing="ij")
+
+
+def white_noise(n, seed, ix_slice=None, fixed_amp=False):
+    """Hermitian-paired unit complex noise W for all modes (or an ix slab)."""
+    gx, gy, gz = mode_grid(n, ix_slice)
+    lin = (gx * n + gy) * n + gz
+    px, py, pz = (-gx) % n, (-gy) % n, (-gz) % n
+    plin = (px * n + py) * n + pz
+    owner = np.minimum(lin, plin)
+    z1, z2 = philox.normal_pair(seed, 0, owner.astype(np.uint64))
+    w = (z1 + 1j * z2) / np.sqrt(2.0)
+    w = np.where(lin > plin, np.conj(w), w)
+    w = np.where(lin == plin, z1 + 0j, w)
+    if fixed_amp:
+        w = w / np.abs(w)
+    return w
+
+
+def component_multiplier(n, comp, f=1.0, ix_slice=None):
+    """Real multiplier turning delta_hat into the requested component."""
+    if comp == "delta":
+        return None
+    gx, gy, gz = mode_grid(n, ix_slice)
+    nv = [signed_freq(gx, n), signed_freq(gy, n), signed_freq(gz, n)]
+    n2 = nv[0] ** 2 + nv[1] ** 2 + nv[2] ** 2
+    axis = {"x": 0, "y": 1, "z": 2}
+    p, q = axis[comp[0]], axis[comp[1]]
+    num = (nv[p] * nv[q]).astype(np.float64)
+    if p != q:
+        nyq = (nv[p] == -(n // 2)) | (nv[q] == -(n // 2))
+        num = np.where(nyq, 0.0, num)
+    return f * np.where(n2 > 0, num / np.where(n2 > 0, n2, 1), 0.0)
+
+
+def amplitudes(n, table, ix_slice=None, only_n2=-1):
+    gx, gy, gz = mode_grid(n, ix_slice)
+    n2 = signed_freq(gx, n) ** 2 + signed_freq(gy, n) ** 2 + signed_freq(gz, n) ** 2
+    s = table[n2]
+    if only_n2 >= 0:
+        s = np.where(n2 == only_n2, s, 0.0)
+    return s
+
+
+def spectrum(n, seed, table, comps=("delta", "zz"), f=1.0, fixed_amp=False,
+             only_n2=-1, ix_slice=None):
+    """Packed k-space field X = C_a + i C_b for the component pair comps."""
+    w = white_noise(n, seed, ix_slice, fixed_amp)
+    s = amplitudes(n, table, ix_slice, only_n2)
+    base = s * w
+    out = []
+    for c in comps:
+        m = component_multiplier(n, c, f, ix_slice)
+        out.append(base if m is None else m * base)
+    if len(out) == 1:
+        return out[0]
+    return out[0] + 1j * out[1]
+
+
+def inverse_dft3(x):
+    """Unnormalised inverse DFT with exp(+2 pi i n.m/N)."""
+    n = x.shape[0]
+    return np.fft.ifftn(x) * float(n) ** 3
+
+
+def make_box(n, seed, table, comps=("delta", "zz"), f=1.0, fixed_amp=False,
+             only_n2=-1):
+    """Complex field C_a + i C_b on the grid (for comps=("delta","zz"),
+    real part = delta, imaginary part = eta_par along z)."""
+    x = spectrum(n, seed, table, comps, f, fixed_amp, only_n2)
+    return inverse_dft3(x)
+
+
+def brute_force_field(n, xhat):
+    """Direct triple sum of the inverse DFT (test pin, tiny n only)."""
+    m = np.arange(n)
+    nn = signed_freq(m, n)
+    ph = np.exp(2j * np.pi * np.outer(nn, m) / n)   # [freq, grid]
+    out = np.zeros((n, n, n), dtype=np.complex128)
+    for a in range(n):
+        for b in range(n):
+            for c in range(n):
+                out += xhat[a, b, c] * (ph[a][:, None, None] * ph[b][None, :, None]
+                                        * ph[c][None, None, :])
+    return out
