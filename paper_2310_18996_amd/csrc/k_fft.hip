@@ -1,0 +1,277 @@
+// Box synthesis and inverse 3D FFT (gfx950).
+//
+// Computes the packed real-space field C_a + i C_b = IDFT3(X) with
+//   X(k) = s(n^2) W(k) (m_a(k) + i m_b(k))      (eq:deltaL, eq:eta)
+// where W is Hermitian-paired unit complex noise drawn from Philox in
+// k-space (the footnote of section "Mock generation" allows drawing in
+// k-space directly), s the amplitude table and m the component multiplier
+// (1 for delta, f k_p k_q/k^2 for eta_pq).  For the pair (delta, eta_zz) the
+// real part is delta and the imaginary part eta_par along z, both real fields
+// because X_a and X_b are each Hermitian.
+//
+// Three passes over the row-major [x][y][z] complex64 box, in place:
+//   pass Z: synthesises the modes of T pencils along z straight into
+//           registers (no spectrum is ever written to memory), FFT along z;
+//   pass Y: tiles of N (y) x T (z contiguous) elements, FFT along y;
+//   pass X: tiles of N (x) x T (z contiguous) elements, FFT along x.
+// Each tile is transformed by a Stockham autosort FFT with radix-4/8/16
+// butterflies: stage 0 works on registers filled from global memory (or the
+// synthesiser), middle stages exchange through LDS, the last stage writes
+// global memory directly in natural order.  Tiles are mapped to blocks so that
+// each XCD walks a contiguous range of tiles (neighbouring z chunks share
+// cache lines).
+#include "lya_internal.h"
+
+namespace lya {
+
+enum { KIND_GENZ = 0, KIND_Y = 1, KIND_X = 2 };
+
+constexpr int radix_of(int n, int s) {
+  return n == 2048 ? (s < 2 ? 16 : 8)
+       : n == 1024 ? (s < 2 ? 16 : 4)
+       : n == 512  ? 8
+       : n == 256  ? 16
+       : n == 128  ? (s == 0 ? 16 : 8)
+       : n == 64   ? 8
+       : n == 32   ? (s == 0 ? 8 : 4)
+       : 0;
+}
+constexpr int nstages_of(int n) {
+  return (n == 2048 || n == 1024 || n == 512) ? 3 : 2;
+}
+constexpr int ns_before(int n, int s) { return s == 0 ? 1 : ns_before(n, s - 1) * radix_of(n, s - 1); }
+
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
+__device__ __forceinline__ int sfreq(int i, int n) { return i < n / 2 ? i : i - n; }
+
+__device__ __forceinline__ float comp_mult(int comp, int nx, int ny, int nz, int n2, int n, float f) {
+  if (comp == 0) return 1.0f;
+  if (comp < 0 || n2 == 0) return 0.0f;
+  int a, b;
+  switch (comp) {
+    case 1: a = nx; b = nx; break;
+    case 2: a = ny; b = ny; break;
+    case 3: a = nz; b = nz; break;
+    case 4: a = nx; b = ny; break;
+    case 5: a = nx; b = nz; break;
+    default: a = ny; b = nz; break;
+  }
+  if (comp >= 4 && (a == -(n / 2) || b == -(n / 2))) return 0.0f;
+  return f * static_cast<float>(a * b) / static_cast<float>(n2);
+}
+
+// Mode (ix, iy, iz) of the packed spectrum.
+template <int N>
+__device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, int iz) {
+  const int nx = sfreq(ix, N), ny = sfreq(iy, N), nz = sfreq(iz, N);
+  const int n2 = nx * nx + ny * ny + nz * nz;
+  float s = g.table[n2];
+  if (g.only_n2 >= 0 && n2 != g.only_n2) s = 0.0f;
+  if (s == 0.0f) return make_float2(0.0f, 0.0f);
+  const uint64_t lin = (static_cast<uint64_t>(ix) * N + iy) * N + iz;
+  const uint64_t plin = (static_cast<uint64_t>((N - ix) & (N - 1)) * N + ((N - iy) & (N - 1))) * N + ((N - iz) & (N - 1));
+  const uint64_t own = lin < plin ? lin : plin;
+  const float2 z = normal_pair(g.seed, 0u, own);
+  float2 w;
+  if (lin == plin) {
+    w = make_float2(z.x, 0.0f);
+  } else {
+    w = make_float2(z.x * kSqrtHalf, (lin == own ? z.y : -z.y) * kSqrtHalf);
+  }
+  if (g.fixed_amp) {
+    const float m = rsqrtf(w.x * w.x + w.y * w.y);
+    w.x *= m;
+    w.y *= m;
+  }
+  const float ma = comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
+  const float mb = comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
+  return make_float2(s * (w.x * ma - w.y * mb), s * (w.y * ma + w.x * mb));
+}
+
+template <int N, int T, int E, int KIND>
+struct Pass {
+  static constexpr int NT = N * T / E;
+  static constexpr bool PF = KIND != KIND_GENZ;  // lanes walk the T contiguous pencils first
+  static constexpr int NSTAGE = nstages_of(N);
+
+  // global element index of element i of pencil p in tile (outer, t0)
+  __device__ static __forceinline__ size_t gidx(int outer, int t0, int i, int p) {
+    if (KIND == KIND_GENZ) return (static_cast<size_t>(outer) * N + t0 + p) * N + i;
+    if (KIND == KIND_Y) return (static_cast<size_t>(outer) * N + i) * N + t0 + p;
+    return (static_cast<size_t>(i) * N + outer) * N + t0 + p;
+  }
+  __device__ static __forceinline__ int lidx(int i, int p) { return PF ? i * T + p : p * N + i; }
+
+  template <int R>
+  __device__ static __forceinline__ void coords(int w, int& p, int& j) {
+    if (PF) {
+      p = w % T;
+      j = w / T;
+    } else {
+      j = w % (N / R);
+      p = w / (N / R);
+    }
+  }
+
+  template <int S>
+  __device__ static __forceinline__ void butterflies(float2 (&v)[E], const float2* __restrict__ tw, int tid) {
+    constexpr int R = radix_of(N, S), NS = ns_before(N, S), B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      int p, j;
+      coords<R>(tid + b * NT, p, j);
+      if (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[r * k * (N / (NS * R))]);
+      }
+      dft<R>(&v[b * R]);
+    }
+  }
+
+  template <int S>
+  __device__ static __forceinline__ void load_lds(float2 (&v)[E], const float2* lds, int tid) {
+    constexpr int R = radix_of(N, S), B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      int p, j;
+      coords<R>(tid + b * NT, p, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b * R + r] = lds[lidx(j + r * (N / R), p)];
+    }
+  }
+
+  // outputs of stage S go to element (j/NS)*NS*R + j%NS + r*NS
+  template <int S>
+  __device__ static __forceinline__ void store_lds(const float2 (&v)[E], float2* lds, int tid) {
+    constexpr int R = radix_of(N, S), NS = ns_before(N, S), B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      int p, j;
+      coords<R>(tid + b * NT, p, j);
+      const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lidx(base + r * NS, p)] = v[b * R + r];
+    }
+  }
+
+  template <int S>
+  __device__ static __forceinline__ void store_global(const float2 (&v)[E], float2* data, uint32_t* out_bf16,
+                                                      bool zero_b, int outer, int t0, int tid) {
+    constexpr int R = radix_of(N, S), B = E / R;
+    static_assert(ns_before(N, S) * R == N, "last stage");
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      int p, j;
+      coords<R>(tid + b * NT, p, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const size_t gi = gidx(outer, t0, j + r * (N / R), p);
+        // a single requested component: the other half is exactly zero, not FFT rounding residue
+        const float2 o = make_float2(v[b * R + r].x, zero_b ? 0.0f : v[b * R + r].y);
+        if (out_bf16) {
+          out_bf16[gi] = pack_bf16x2(o.x, o.y);
+        } else {
+          data[gi] = o;
+        }
+      }
+    }
+  }
+};
+
+template <int N, int T, int E, int KIND>
+__global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ data, uint32_t* __restrict__ out_bf16,
+                                                        const float2* __restrict__ tw, GenParams g) {
+  using P = Pass<N, T, E, KIND>;
+  constexpr int NT = P::NT;
+  __shared__ float2 lds[N * T];
+  float2 v[E];
+  const int tid = threadIdx.x;
+  const int ntiles = N * (N / T);
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int outer = tile / (N / T);
+  const int t0 = (tile % (N / T)) * T;
+
+  // stage 0: registers from global memory or from the synthesiser
+  {
+    constexpr int R = radix_of(N, 0), B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      int p, j;
+      P::template coords<R>(tid + b * NT, p, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = j + r * (N / R);
+        if (KIND == KIND_GENZ) {
+          v[b * R + r] = gen_mode<N>(g, outer, t0 + p, i);
+        } else {
+          v[b * R + r] = data[P::gidx(outer, t0, i, p)];
+        }
+      }
+    }
+  }
+  P::template butterflies<0>(v, tw, tid);
+  P::template store_lds<0>(v, lds, tid);
+  __syncthreads();
+  P::template load_lds<1>(v, lds, tid);
+  P::template butterflies<1>(v, tw, tid);
+  if constexpr (P::NSTAGE == 2) {
+    P::template store_global<1>(v, data, KIND == KIND_X ? out_bf16 : nullptr, KIND == KIND_X && g.comp_b < 0,
+                                 outer, t0, tid);
+  } else {
+    __syncthreads();
+    P::template store_lds<1>(v, lds, tid);
+    __syncthreads();
+    P::template load_lds<2>(v, lds, tid);
+    P::template butterflies<2>(v, tw, tid);
+    P::template store_global<2>(v, data, KIND == KIND_X ? out_bf16 : nullptr, KIND == KIND_X && g.comp_b < 0,
+                                 outer, t0, tid);
+  }
+}
+
+// Tile shapes: (pencils per tile T, elements per thread E) for the
+// synthesising pass and the strided passes.
+template <int N>
+struct Shape;
+template <> struct Shape<32>   { static constexpr int TZ = 16, EZ = 8,  TS = 16, ES = 8; };
+template <> struct Shape<64>   { static constexpr int TZ = 16, EZ = 8,  TS = 16, ES = 8; };
+template <> struct Shape<128>  { static constexpr int TZ = 8,  EZ = 16, TS = 16, ES = 16; };
+template <> struct Shape<256>  { static constexpr int TZ = 8,  EZ = 16, TS = 16, ES = 16; };
+template <> struct Shape<512>  { static constexpr int TZ = 8,  EZ = 16, TS = 16, ES = 16; };
+template <> struct Shape<1024> { static constexpr int TZ = 4,  EZ = 16, TS = 16, ES = 32; };
+template <> struct Shape<2048> { static constexpr int TZ = 2,  EZ = 16, TS = 8,  ES = 32; };
+
+template <int N>
+hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16, hipStream_t st) {
+  using S = Shape<N>;
+  const int tz = N * (N / S::TZ), ts = N * (N / S::TS);
+  LYA_TIMED("fft_z_gen", st,
+            hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ>), dim3(tz), dim3(N * S::TZ / S::EZ), 0, st,
+                               field, nullptr, tw, g));
+  LYA_TIMED("fft_y", st,
+            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_Y>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
+                               field, nullptr, tw, g));
+  LYA_TIMED("fft_x", st,
+            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_X>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
+                               field, field_bf16, tw, g));
+  return hipGetLastError();
+}
+
+hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
+                          hipStream_t st) {
+  switch (n) {
+    case 32: return run_box_fft<32>(g, tw, field, field_bf16, st);
+    case 64: return run_box_fft<64>(g, tw, field, field_bf16, st);
+    case 128: return run_box_fft<128>(g, tw, field, field_bf16, st);
+    case 256: return run_box_fft<256>(g, tw, field, field_bf16, st);
+    case 512: return run_box_fft<512>(g, tw, field, field_bf16, st);
+    case 1024: return run_box_fft<1024>(g, tw, field, field_bf16, st);
+    case 2048: return run_box_fft<2048>(g, tw, field, field_bf16, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lya

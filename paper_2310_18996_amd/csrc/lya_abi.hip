@@ -1,0 +1,253 @@
+// C-ABI of the lyamock library: argument checks, workspace carve-up and
+// launch sequencing.  All compute happens in the kernels of k_tables.hip,
+// k_fft.hip and k_skewers.hip.
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/lyamock.h"
+#include "lya_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, const char* a = "") {
+  snprintf(g_err, sizeof(g_err), fmt, a);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
+  return LYA_EHIP;
+}
+
+bool pow2_in_range(int n) { return n >= 32 && n <= 2048 && (n & (n - 1)) == 0; }
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+struct BoxCarve {
+  size_t partial, amp, tw, table, staging, total;
+};
+
+BoxCarve carve_box(const lya_box* b) {
+  BoxCarve c{};
+  size_t o = 0;
+  c.partial = o; o += align256(sizeof(double) * lya::kSigmaBlocks);
+  c.amp = o;     o += align256(sizeof(double));
+  c.tw = o;      o += align256(sizeof(float2) * b->n);
+  c.table = o;   o += align256(sizeof(float) * lya::amp_table_entries(b->n));
+  c.staging = o;
+  if (b->storage == LYA_BF16) o += align256(sizeof(float2) * static_cast<size_t>(b->n) * b->n * b->n);
+  c.total = o;
+  return c;
+}
+
+struct SkCarve {
+  size_t ztab, tw, queue, bsum, bcnt, total;
+};
+
+SkCarve carve_sk() {
+  SkCarve c{};
+  size_t o = 0;
+  c.ztab = o;  o += align256(sizeof(float) * lya::kZTabN);
+  c.tw = o;    o += align256(sizeof(float2) * lya::kTw2048);
+  c.queue = o; o += 256;
+  c.bsum = o;  o += align256(sizeof(unsigned long long) * lya::kMaxZBins);
+  c.bcnt = o;  o += align256(sizeof(unsigned long long) * lya::kMaxZBins);
+  c.total = o;
+  return c;
+}
+
+int check_box(const lya_box* box) {
+  if (!box) return fail(LYA_EINVAL, "box is NULL%s");
+  if (box->n < 32 || box->n > 2048) return fail(LYA_EINVAL, "box n must be in [32, 2048]%s");
+  if (!pow2_in_range(box->n)) return fail(LYA_EUNSUPPORTED, "box n must be a power of two%s");
+  if (!(box->dx > 0.0)) return fail(LYA_EINVAL, "box dx must be > 0%s");
+  if (box->storage != LYA_F32 && box->storage != LYA_BF16) return fail(LYA_EINVAL, "unknown storage type%s");
+  return LYA_OK;
+}
+
+int make_pair(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int ca, int cb, void* field,
+              void* work, size_t work_bytes, void* stream) {
+  int rc = check_box(box);
+  if (rc) return rc;
+  if (!pk) return fail(LYA_EINVAL, "pk is NULL%s");
+  if (!field) return fail(LYA_EINVAL, "field is NULL%s");
+  if (!work) return fail(LYA_EINVAL, "work is NULL%s");
+  if (ca < LYA_C_DELTA || ca > LYA_C_YZ || cb < LYA_C_NONE || cb > LYA_C_YZ)
+    return fail(LYA_EINVAL, "unknown field component%s");
+  if (!(pk->sigma8 > 0.0) || !(pk->gamma > 0.0) || !(pk->wig_kd > 0.0) || pk->smooth < 0.0)
+    return fail(LYA_EINVAL, "invalid power-spectrum parameters%s");
+  const BoxCarve c = carve_box(box);
+  if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the box%s");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(work);
+  lya::TableWork tw{reinterpret_cast<double*>(w + c.partial), reinterpret_cast<double*>(w + c.amp),
+                    reinterpret_cast<float2*>(w + c.tw), reinterpret_cast<float*>(w + c.table)};
+  lya::PkParams p{pk->sigma8, pk->ns, pk->gamma, pk->wig_amp, pk->wig_r, pk->wig_kd, pk->smooth};
+  hipError_t e = lya::launch_pk_table(p, box->n, box->dx, tw, st);
+  if (e != hipSuccess) return hip_fail(e, "power-spectrum table");
+  lya::GenParams g{tw.table, seed, static_cast<float>(f), ca, cb, pk->fixed_amp ? 1 : 0, pk->only_n2};
+  float2* f32 = box->storage == LYA_F32 ? static_cast<float2*>(field) : reinterpret_cast<float2*>(w + c.staging);
+  uint32_t* b16 = box->storage == LYA_BF16 ? static_cast<uint32_t*>(field) : nullptr;
+  e = lya::launch_box_fft(box->n, g, tw.tw, f32, b16, st);
+  if (e != hipSuccess) return hip_fail(e, "box FFT");
+  return LYA_OK;
+}
+
+int check_skewers(const lya_skewers* sk, bool need_geometry) {
+  if (!sk) return fail(LYA_EINVAL, "skewers is NULL%s");
+  if (sk->n_sk < 0) return fail(LYA_EINVAL, "n_sk < 0%s");
+  if (sk->n_sk > (int64_t(1) << 40)) return fail(LYA_EINVAL, "n_sk too large%s");
+  if (sk->n_sk == 0) return LYA_OK;
+  if (!sk->npix || !sk->offset || !sk->chi0) return fail(LYA_EINVAL, "skewer arrays are NULL%s");
+  if (need_geometry && (!sk->origin_fx || !sk->step_fx)) return fail(LYA_EINVAL, "skewer geometry is NULL%s");
+  if (!(sk->dchi >= 0.0)) return fail(LYA_EINVAL, "dchi must be >= 0%s");
+  if (sk->id_base < 0 || sk->id_base > (int64_t(1) << 30)) return fail(LYA_EINVAL, "id_base out of range%s");
+  return LYA_OK;
+}
+
+int check_zbins(const lya_zbins* zb) {
+  if (!zb) return LYA_OK;
+  if (zb->n_bins < 0 || zb->n_bins > lya::kMaxZBins) return fail(LYA_EINVAL, "n_bins must be in [0, 64]%s");
+  if (zb->n_bins > 0 && (!zb->chi_edges || (!zb->fsum && !zb->count)))
+    return fail(LYA_EINVAL, "redshift-bin arrays are NULL%s");
+  return LYA_OK;
+}
+
+void fill_fgpa(lya::SkewerArgs& a, const lya_fgpa* fg) {
+  a.do_flux = fg ? 1 : 0;
+  for (int p = 0; p < 3; ++p)
+    for (int i = 0; i < 3; ++i) a.coef[p][i] = fg ? fg->coef[p][i] : 0.0;
+}
+
+int run_skewers(lya::SkewerArgs& a, const lya_cosmo* cosmo, const lya_zbins* zb, void* work, size_t work_bytes,
+                void* stream) {
+  const SkCarve c = carve_sk();
+  if (!work) return fail(LYA_EINVAL, "work is NULL%s");
+  if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the skewers%s");
+  if (a.do_flux && !cosmo) return fail(LYA_EINVAL, "cosmo is NULL%s");
+  if (cosmo && !(cosmo->omega_m >= 0.0 && cosmo->omega_m <= 1.0)) return fail(LYA_EINVAL, "omega_m out of [0,1]%s");
+  char* w = static_cast<char*>(work);
+  a.ztab = reinterpret_cast<float*>(w + c.ztab);
+  a.tw2048 = reinterpret_cast<float2*>(w + c.tw);
+  a.queue = reinterpret_cast<unsigned int*>(w + c.queue);
+  a.bin_sum = reinterpret_cast<unsigned long long*>(w + c.bsum);
+  a.bin_cnt = reinterpret_cast<unsigned long long*>(w + c.bcnt);
+  a.n_bins = zb ? zb->n_bins : 0;
+  a.chi_edges = zb ? zb->chi_edges : nullptr;
+  a.out_fsum = zb ? zb->fsum : nullptr;
+  a.out_count = zb ? zb->count : nullptr;
+  a.chunk = 8;
+  if (a.n_sk == 0) {
+    if (a.n_bins > 0 && a.do_flux) {
+      // still produce zero sums
+    } else {
+      return LYA_OK;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (a.do_flux) {
+    e = lya::launch_zchi_table(cosmo->omega_m, const_cast<float*>(a.ztab), st);
+    if (e != hipSuccess) return hip_fail(e, "redshift table");
+  }
+  if (a.field || a.field_bf16) {
+    e = lya::launch_twiddles(const_cast<float2*>(a.tw2048), lya::kTw2048, st);
+    if (e != hipSuccess) return hip_fail(e, "twiddles");
+  }
+  e = lya::launch_skewers(a, st);
+  if (e != hipSuccess) return hip_fail(e, "skewer kernel");
+  return LYA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lya_last_error(void) { return g_err; }
+
+const char* lya_version(void) { return "lyamock 0.1 gfx950"; }
+
+size_t lya_workspace_size(int op, const lya_box* box) {
+  if (op == LYA_OP_BOX) {
+    if (!box || !pow2_in_range(box->n) || (box->storage != LYA_F32 && box->storage != LYA_BF16)) return 0;
+    return carve_box(box).total;
+  }
+  if (op == LYA_OP_SKEWERS) return carve_sk().total;
+  return 0;
+}
+
+int lya_make_box(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int with_eta, void* field,
+                 void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  return make_pair(box, pk, seed, f, LYA_C_DELTA, with_eta ? LYA_C_ZZ : LYA_C_NONE, field, work, work_bytes,
+                   stream);
+}
+
+int lya_make_eta(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int comp_a, int comp_b,
+                 void* field, void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  return make_pair(box, pk, seed, f, comp_a, comp_b, field, work, work_bytes, stream);
+}
+
+int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                     uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                     float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_box(box);
+  if (rc) return rc;
+  if (!field) return fail(LYA_EINVAL, "field is NULL%s");
+  if ((rc = check_skewers(sk, true))) return rc;
+  if ((rc = check_zbins(zb))) return rc;
+  if (ps && ps->amp > 0.0 && (!(ps->kcut > 0.0) || !(ps->dpix > 0.0)))
+    return fail(LYA_EINVAL, "invalid small-scale spectrum%s");
+  lya::SkewerArgs a{};
+  a.n_sk = sk->n_sk;
+  a.origin_fx = sk->origin_fx;
+  a.step_fx = sk->step_fx;
+  a.npix = sk->npix;
+  a.offset = sk->offset;
+  a.chi0 = sk->chi0;
+  a.dchi = sk->dchi;
+  a.id_base = sk->id_base;
+  a.n = box->n;
+  a.field = box->storage == LYA_F32 ? static_cast<const float2*>(field) : nullptr;
+  a.field_bf16 = box->storage == LYA_BF16 ? static_cast<const uint32_t*>(field) : nullptr;
+  a.ps_amp = ps ? ps->amp : 0.0;
+  a.ps_kcut = ps ? ps->kcut : 1.0;
+  a.dpix = ps ? ps->dpix : 1.0;
+  a.ps_fixed_amp = ps ? ps->fixed_amp : 0;
+  a.seed = seed;
+  fill_fgpa(a, fgpa);
+  a.dens = dens;
+  a.eta = eta;
+  a.flux = fgpa ? flux : nullptr;
+  return run_skewers(a, cosmo, fgpa ? zb : nullptr, work, work_bytes, stream);
+}
+
+int lya_apply_fgpa(const lya_skewers* sk, const lya_cosmo* cosmo, const float* dens, const float* eta,
+                   const lya_fgpa* fgpa, float* flux, const lya_zbins* zb, void* work, size_t work_bytes,
+                   void* stream) {
+  g_err[0] = 0;
+  int rc = check_skewers(sk, false);
+  if (rc) return rc;
+  if ((rc = check_zbins(zb))) return rc;
+  if (!fgpa) return fail(LYA_EINVAL, "fgpa is NULL%s");
+  if (sk->n_sk > 0 && (!dens || !eta)) return fail(LYA_EINVAL, "dens/eta are NULL%s");
+  lya::SkewerArgs a{};
+  a.n_sk = sk->n_sk;
+  a.npix = sk->npix;
+  a.offset = sk->offset;
+  a.chi0 = sk->chi0;
+  a.dchi = sk->dchi;
+  a.id_base = sk->id_base;
+  a.n = 32;
+  a.in_dens = dens;
+  a.in_eta = eta;
+  fill_fgpa(a, fgpa);
+  a.flux = flux;
+  return run_skewers(a, cosmo, zb, work, work_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal declarations of the lyamock HIP library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lya_device.h"
+
+namespace lya {
+
+constexpr double kCOverH0 = 2997.92458;  // Mpc/h
+constexpr int kSigmaBlocks = 64;          // partial sums of the sigma8 integral
+constexpr double kZTabH = 0.5;            // Mpc/h spacing of the z(chi) table
+constexpr int kZTabN = 20001;             // covers chi in [0, 10000] Mpc/h
+constexpr int kMaxZBins = 64;
+constexpr int kTw2048 = 2048;             // twiddles for the small-scale 1D FFTs
+
+struct PkParams {
+  double sigma8, ns, gamma, wig_amp, wig_r, wig_kd, smooth;
+};
+
+inline int amp_table_entries(int n) { return 3 * (n / 2) * (n / 2) + 1; }
+
+// Workspace carve-up of lya_make_box / lya_make_eta.
+struct TableWork {
+  double* partial;  // kSigmaBlocks
+  double* amp;      // 1
+  float2* tw;       // n twiddles exp(+2 pi i k/n)
+  float* table;     // amp_table_entries(n)
+};
+
+// What the first FFT pass synthesises for each mode.
+struct GenParams {
+  const float* table;
+  uint64_t seed;
+  float f;
+  int comp_a, comp_b;  // 0 delta, 1 xx, 2 yy, 3 zz, 4 xy, 5 xz, 6 yz; -1 none
+  int fixed_amp;
+  int only_n2;
+};
+
+// Optional event timing around each launch (see lya_timing_enable).
+void timer_begin(const char* name, hipStream_t st);
+void timer_end(hipStream_t st);
+#define LYA_TIMED(name, st, ...)     \
+  do {                               \
+    ::lya::timer_begin(name, st);    \
+    __VA_ARGS__;                     \
+    ::lya::timer_end(st);            \
+  } while (0)
+
+hipError_t launch_pk_table(const PkParams& p, int n, double dx, TableWork& w, hipStream_t st);
+hipError_t launch_zchi_table(double omega_m, float* ztab, hipStream_t st);
+hipError_t launch_twiddles(float2* tw, int ntw, hipStream_t st);
+hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
+                          hipStream_t st);
+
+// Skewer stage.
+struct SkewerArgs {
+  // geometry
+  int64_t n_sk;
+  const int64_t* origin_fx;
+  const int64_t* step_fx;
+  const int32_t* npix;
+  const int64_t* offset;
+  const double* chi0;
+  double dchi;
+  int64_t id_base;
+  // field
+  int n;
+  const float2* field;         // FP32 {delta, eta} or null
+  const uint32_t* field_bf16;  // BF16 {delta, eta} or null
+  // small-scale field
+  double ps_amp, ps_kcut, dpix;
+  int ps_fixed_amp;
+  uint64_t seed;
+  // FGPA (valid when do_flux)
+  int do_flux;
+  double coef[3][3];
+  // pre-FGPA inputs for apply_fgpa (gather skipped when non-null)
+  const float* in_dens;
+  const float* in_eta;
+  // outputs (each may be null)
+  float* dens;
+  float* eta;
+  float* flux;
+  // redshift bins
+  int n_bins;
+  const double* chi_edges;
+  unsigned long long* bin_sum;  // workspace, fixed point F * 2^32
+  unsigned long long* bin_cnt;
+  double* out_fsum;
+  int64_t* out_count;
+  // tables and scheduling
+  const float* ztab;
+  const float2* tw2048;
+  unsigned int* queue;
+  int chunk;
+};
+
+hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st);
+
+}  // namespace lya

@@ -1,0 +1,204 @@
+"""ctypes binding of liblyamock.so (include/lyamock.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of the library.  Device buffers are torch tensors on the current HIP
+device; the stream is torch's current stream unless one is given.  A missing
+or unloadable library raises immediately: there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblyamock.so")
+
+LYA_OK, LYA_EINVAL, LYA_EWORKSPACE, LYA_EUNSUPPORTED, LYA_EHIP = 0, -1, -2, -3, -4
+LYA_F32, LYA_BF16 = 0, 1
+LYA_OP_BOX, LYA_OP_SKEWERS = 0, 1
+COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6}
+
+EXPORTS = ("lya_workspace_size", "lya_make_box", "lya_make_eta", "lya_draw_skewers",
+           "lya_apply_fgpa", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
+           "lya_last_error", "lya_version")
+
+
+class LyaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lyamock error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dx", ctypes.c_double), ("storage", ctypes.c_int32)]
+
+
+class Pk(ctypes.Structure):
+    _fields_ = [("sigma8", ctypes.c_double), ("ns", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("wig_amp", ctypes.c_double), ("wig_r", ctypes.c_double), ("wig_kd", ctypes.c_double),
+                ("smooth", ctypes.c_double), ("fixed_amp", ctypes.c_int32), ("only_n2", ctypes.c_int32)]
+
+
+class Skewers(ctypes.Structure):
+    _fields_ = [("n_sk", ctypes.c_int64), ("origin_fx", ctypes.c_void_p), ("step_fx", ctypes.c_void_p),
+                ("npix", ctypes.c_void_p), ("offset", ctypes.c_void_p), ("chi0", ctypes.c_void_p),
+                ("dchi", ctypes.c_double), ("id_base", ctypes.c_int64)]
+
+
+class Ps1d(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("kcut", ctypes.c_double), ("dpix", ctypes.c_double),
+                ("fixed_amp", ctypes.c_int32)]
+
+
+class Fgpa(ctypes.Structure):
+    _fields_ = [("coef", (ctypes.c_double * 3) * 3)]
+
+
+class Cosmo(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double)]
+
+
+class ZBins(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("chi_edges", ctypes.c_void_p), ("fsum", ctypes.c_void_p),
+                ("count", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblyamock.so not built at %s (run __graft_entry__.build())" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, VP = ctypes.POINTER, ctypes.c_void_p
+    lib.lya_workspace_size.restype = ctypes.c_size_t
+    lib.lya_workspace_size.argtypes = [ctypes.c_int, P(Box)]
+    lib.lya_make_box.restype = ctypes.c_int
+    lib.lya_make_box.argtypes = [P(Box), P(Pk), ctypes.c_uint64, ctypes.c_double, ctypes.c_int, VP, VP,
+                                 ctypes.c_size_t, VP]
+    lib.lya_make_eta.restype = ctypes.c_int
+    lib.lya_make_eta.argtypes = [P(Box), P(Pk), ctypes.c_uint64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                 VP, VP, ctypes.c_size_t, VP]
+    lib.lya_draw_skewers.restype = ctypes.c_int
+    lib.lya_draw_skewers.argtypes = [P(Box), VP, P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo), P(Fgpa),
+                                     VP, VP, VP, P(ZBins), VP, ctypes.c_size_t, VP]
+    lib.lya_apply_fgpa.restype = ctypes.c_int
+    lib.lya_apply_fgpa.argtypes = [P(Skewers), P(Cosmo), VP, VP, P(Fgpa), VP, P(ZBins), VP, ctypes.c_size_t, VP]
+    lib.lya_timing_enable.restype = ctypes.c_int
+    lib.lya_timing_enable.argtypes = [ctypes.c_int]
+    lib.lya_timing_collect.restype = ctypes.c_int
+    lib.lya_timing_get.restype = ctypes.c_int
+    lib.lya_timing_get.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64)]
+    lib.lya_last_error.restype = ctypes.c_char_p
+    lib.lya_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error():
+    return load().lya_last_error().decode()
+
+
+def _check(rc):
+    if rc != LYA_OK:
+        raise LyaError(rc, last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def box_struct(n, dx, storage=LYA_F32):
+    return Box(int(n), float(dx), int(storage))
+
+
+def pk_struct(sigma8=0.8, ns=0.96, gamma=0.21, wig_amp=0.05, wig_r=105.0, wig_kd=0.2, smooth=0.0,
+              fixed_amp=False, only_n2=-1):
+    return Pk(sigma8, ns, gamma, wig_amp, wig_r, wig_kd, smooth, int(bool(fixed_amp)), int(only_n2))
+
+
+def workspace_size(op, box=None):
+    return int(load().lya_workspace_size(int(op), ctypes.byref(box) if box is not None else None))
+
+
+def make_box(box, pk, seed, f, with_eta, field, work, stream=None):
+    """lya_make_box: field (n^3 x 2 float32, or n^3 int32 for BF16) on device."""
+    _check(load().lya_make_box(ctypes.byref(box), ctypes.byref(pk), int(seed), float(f), int(bool(with_eta)),
+                               _ptr(field), _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def make_eta(box, pk, seed, f, comp_a, comp_b, field, work, stream=None):
+    """lya_make_eta: {comp_a, comp_b} of the same modes (component names as in COMPONENTS)."""
+    ca = COMPONENTS[comp_a] if isinstance(comp_a, str) else int(comp_a)
+    cb = COMPONENTS[comp_b] if isinstance(comp_b, str) else int(comp_b)
+    _check(load().lya_make_eta(ctypes.byref(box), ctypes.byref(pk), int(seed), float(f), ca, cb, _ptr(field),
+                               _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def skewers_struct(n_sk, origin_fx, step_fx, npix, offset, chi0, dchi, id_base=0):
+    return Skewers(int(n_sk), _ptr(origin_fx), _ptr(step_fx), _ptr(npix), _ptr(offset), _ptr(chi0),
+                   float(dchi), int(id_base))
+
+
+def fgpa_struct(coef):
+    fg = Fgpa()
+    for p in range(3):
+        for i in range(3):
+            fg.coef[p][i] = float(coef[p][i])
+    return fg
+
+
+def zbins_struct(chi_edges, fsum, count):
+    if chi_edges is None:
+        return None
+    return ZBins(int(chi_edges.numel() - 1), _ptr(chi_edges), _ptr(fsum), _ptr(count))
+
+
+def draw_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, work, stream=None):
+    """lya_draw_skewers (see include/lyamock.h)."""
+    _check(load().lya_draw_skewers(ctypes.byref(box), _ptr(field), ctypes.byref(sk),
+                                   ctypes.byref(ps) if ps is not None else None, int(seed),
+                                   ctypes.byref(cosmo) if cosmo is not None else None,
+                                   ctypes.byref(fgpa) if fgpa is not None else None,
+                                   _ptr(dens), _ptr(eta), _ptr(flux),
+                                   ctypes.byref(zbins) if zbins is not None else None,
+                                   _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def apply_fgpa(sk, cosmo, dens, eta, fgpa, flux, zbins, work, stream=None):
+    """lya_apply_fgpa (see include/lyamock.h)."""
+    _check(load().lya_apply_fgpa(ctypes.byref(sk), ctypes.byref(cosmo) if cosmo is not None else None,
+                                 _ptr(dens), _ptr(eta), ctypes.byref(fgpa) if fgpa is not None else None,
+                                 _ptr(flux), ctypes.byref(zbins) if zbins is not None else None,
+                                 _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def timing_enable(on=True):
+    _check(load().lya_timing_enable(int(bool(on))))
+
+
+def timing_read():
+    """{kernel name: (total ms, launches)} of the launches recorded since
+    timing_enable(True)."""
+    lib = load()
+    n = lib.lya_timing_collect()
+    if n < 0:
+        raise LyaError(n, "timing collection failed")
+    out = {}
+    buf = ctypes.create_string_buffer(64)
+    for i in range(n):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib.lya_timing_get(i, buf, 64, ctypes.byref(ms), ctypes.byref(cnt)))
+        out[buf.value.decode()] = (ms.value, cnt.value)
+    return out

@@ -1,0 +1,118 @@
+"""Shared helpers of the GPU parity tests: device buffers and calls through
+the C-ABI binding, plus the oracle side on the same seeded inputs."""
+import numpy as np
+
+import mockinputs
+from oracle import power
+
+try:
+    import torch
+except ImportError:  # pragma: no cover
+    torch = None
+
+
+def rel_rms(x, y):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    den = np.sqrt(np.sum(y ** 2))
+    return float(np.sqrt(np.sum((x - y) ** 2)) / (den if den > 0 else 1.0))
+
+
+def oracle_table(cfg_pk, n, dx, smooth=0.0):
+    pk = power.PowerSpectrum(**cfg_pk)
+    return power.amplitude_table(pk, n, dx, smooth)
+
+
+def gpu_box(L, n, dx, seed, f=1.0, with_eta=True, storage=0, comps=None, **pkkw):
+    """Run lya_make_box (or lya_make_eta when comps is given) and return the
+    device field tensor."""
+    box = L.box_struct(n, dx, storage)
+    pk = L.pk_struct(**pkkw)
+    ws = L.workspace_size(L.LYA_OP_BOX, box)
+    work = torch.empty(ws, dtype=torch.uint8, device="cuda")
+    if storage == L.LYA_F32:
+        field = torch.empty((n, n, n, 2), dtype=torch.float32, device="cuda")
+    else:
+        field = torch.empty((n, n, n), dtype=torch.int32, device="cuda")
+    if comps is None:
+        L.make_box(box, pk, seed, f, with_eta, field, work)
+    else:
+        L.make_eta(box, pk, seed, f, comps[0], comps[1], field, work)
+    torch.cuda.synchronize()
+    return field
+
+
+def bf16_to_f32(field_i32):
+    """Unpack a BF16x2 box (int32 words) into float32 [..., 2] on the host."""
+    w = field_i32.cpu().numpy().view(np.uint32)
+    lo = (w << 16).view(np.float32)
+    hi = (w & 0xFFFF0000).view(np.float32)
+    return np.stack([lo, hi], axis=-1)
+
+
+def skewer_tensors(L, sk):
+    dev = "cuda"
+    t = dict(origin_fx=torch.from_numpy(np.ascontiguousarray(sk["origin_fx"])).to(dev),
+             step_fx=torch.from_numpy(np.ascontiguousarray(sk["step_fx"])).to(dev),
+             npix=torch.from_numpy(np.ascontiguousarray(sk["npix"], dtype=np.int32)).to(dev),
+             offset=torch.from_numpy(np.ascontiguousarray(sk["offset"], dtype=np.int64)).to(dev),
+             chi0=torch.from_numpy(np.ascontiguousarray(sk["chi0"], dtype=np.float64)).to(dev))
+    s = L.skewers_struct(len(sk["npix"]), t["origin_fx"], t["step_fx"], t["npix"], t["offset"], t["chi0"],
+                         sk["dchi"], sk.get("id_base", 0))
+    return s, t
+
+
+def total_pixels(sk):
+    npix = np.asarray(sk["npix"], dtype=np.int64)
+    off = np.asarray(sk["offset"], dtype=np.int64)
+    return int(np.max(off + npix)) if len(npix) else 0
+
+
+def gpu_skewers(L, field, n, dx, sk, seed, ps_amp, ps_kcut, dpix, coef=None, chi_edges=None, omega_m=0.3147,
+                storage=0, want=("dens", "eta", "flux"), ps_fixed=False):
+    box = L.box_struct(n, dx, storage)
+    s, keep = skewer_tensors(L, sk)
+    tot = max(total_pixels(sk), 1)
+    dens = torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") if "dens" in want else None
+    eta = torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") if "eta" in want else None
+    flux = torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") if ("flux" in want and coef is not None) else None
+    zb = None
+    fsum = cnt = edges = None
+    if chi_edges is not None:
+        edges = torch.from_numpy(np.asarray(chi_edges, dtype=np.float64)).cuda()
+        fsum = torch.zeros(len(chi_edges) - 1, dtype=torch.float64, device="cuda")
+        cnt = torch.zeros(len(chi_edges) - 1, dtype=torch.int64, device="cuda")
+        zb = L.zbins_struct(edges, fsum, cnt)
+    ws = L.workspace_size(L.LYA_OP_SKEWERS, box)
+    work = torch.empty(ws, dtype=torch.uint8, device="cuda")
+    ps = L.Ps1d(float(ps_amp), float(ps_kcut), float(dpix), int(bool(ps_fixed)))
+    fg = L.fgpa_struct(coef) if coef is not None else None
+    L.draw_skewers(box, field, s, ps, seed, L.Cosmo(omega_m), fg, dens, eta, flux, zb, work)
+    torch.cuda.synchronize()
+    out = {}
+    for k, v in (("dens", dens), ("eta", eta), ("flux", flux), ("fsum", fsum), ("count", cnt)):
+        if v is not None:
+            out[k] = v.cpu().numpy()
+    return out
+
+
+def gpu_apply_fgpa(L, sk, dens, eta, coef, chi_edges=None, omega_m=0.3147):
+    s, keep = skewer_tensors(L, sk)
+    d = torch.from_numpy(np.asarray(dens, dtype=np.float32)).cuda()
+    e = torch.from_numpy(np.asarray(eta, dtype=np.float32)).cuda()
+    flux = torch.full_like(d, float("nan"))
+    zb = None
+    fsum = cnt = None
+    if chi_edges is not None:
+        edges = torch.from_numpy(np.asarray(chi_edges, dtype=np.float64)).cuda()
+        fsum = torch.zeros(len(chi_edges) - 1, dtype=torch.float64, device="cuda")
+        cnt = torch.zeros(len(chi_edges) - 1, dtype=torch.int64, device="cuda")
+        zb = L.zbins_struct(edges, fsum, cnt)
+    work = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS), dtype=torch.uint8, device="cuda")
+    L.apply_fgpa(s, L.Cosmo(omega_m), d, e, L.fgpa_struct(coef), flux, zb, work)
+    torch.cuda.synchronize()
+    out = dict(flux=flux.cpu().numpy())
+    if fsum is not None:
+        out["fsum"] = fsum.cpu().numpy()
+        out["count"] = cnt.cpu().numpy()
+    return out

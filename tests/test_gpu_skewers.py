@@ -1,0 +1,174 @@
+"""GPU parity of lya_draw_skewers / lya_apply_fgpa against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import mockinputs
+from oracle import cosmology, fgpa, field, skewers
+from tests.lyahelp import gpu_apply_fgpa, gpu_box, gpu_skewers, oracle_table, rel_rms
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+T32 = 2 ** 32
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_18996_amd import lyamock
+    lyamock.load()
+    return lyamock
+
+
+@pytest.fixture(scope="module")
+def tiny(L):
+    cfg = mockinputs.config("tiny")
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    fld = gpu_box(L, n, dx, seed, cfg["f"], **cfg["pk"])
+    tab = oracle_table(cfg["pk"], n, dx)
+    ref = field.make_box(n, seed, tab, ("delta", "zz"), f=cfg["f"])
+    sk = mockinputs.skewer_table(cfg)
+    return cfg, fld, ref, sk
+
+
+def test_tiny_pipeline_matches_oracle(L, tiny):
+    cfg, fld, ref, sk = tiny
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    print("tiny skewers: %d skewers, %d pixels" % (len(sk["npix"]), sk["total"]), flush=True)
+    edges = fgpa.chi_edges_for_z(cfg["z_edges"])
+    out = gpu_skewers(L, fld, n, dx, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], cfg["fgpa"], edges)
+    rd, re_ = skewers.draw_skewers(ref.real, ref.imag, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"])
+    rf, z = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
+    e = dict(dens=rel_rms(out["dens"], rd), eta=rel_rms(out["eta"], re_), flux=rel_rms(out["flux"], rf))
+    print("tiny rel rms", e)
+    assert all(v < TOL for v in e.values()), e
+    chi = fgpa.pixel_chi(sk)
+    fs, cnt = fgpa.mean_flux_bins(rf, chi, edges)
+    np.testing.assert_array_equal(out["count"], cnt)
+    np.testing.assert_allclose(out["fsum"], fs, rtol=1e-5, atol=1e-6 * max(1.0, fs.max()))
+
+
+def test_outputs_optional_and_consistent(L, tiny):
+    cfg, fld, ref, sk = tiny
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    a = gpu_skewers(L, fld, n, dx, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], None, want=("dens", "eta"))
+    b = gpu_skewers(L, fld, n, dx, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], cfg["fgpa"], want=("flux",))
+    c = gpu_skewers(L, fld, n, dx, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], cfg["fgpa"])
+    np.testing.assert_array_equal(a["dens"], c["dens"])
+    np.testing.assert_array_equal(a["eta"], c["eta"])
+    np.testing.assert_array_equal(b["flux"], c["flux"])
+    # post-production on the stored pixels reproduces the fused flux exactly
+    d = gpu_apply_fgpa(L, sk, a["dens"], a["eta"], cfg["fgpa"])
+    np.testing.assert_array_equal(d["flux"], c["flux"])
+
+
+def test_small_scale_field_alone(L):
+    """A zero box isolates delta_S: compare with the oracle's 1D field,
+    including lengths that are not powers of two and the fixed-amplitude hook."""
+    import torch
+    n, dx = 32, 2.19
+    fld = torch.zeros((n, n, n, 2), dtype=torch.float32, device="cuda")
+    npix = np.array([1, 2, 3, 200, 256, 257, 700, 1024, 1500, 2048], dtype=np.int32)
+    off = np.concatenate([[0], np.cumsum(npix[:-1])]).astype(np.int64)
+    S = len(npix)
+    sk = dict(origin_fx=np.zeros((S, 3), np.int64), step_fx=np.zeros((S, 3), np.int64), npix=npix, offset=off,
+              chi0=np.full(S, 4000.0), dchi=0.2, id_base=11)
+    for fixed in (False, True):
+        out = gpu_skewers(L, fld, n, dx, sk, 99, 1.7, 1.5, 0.2, None, want=("dens",), ps_fixed=fixed)
+        for q in range(S):
+            ref = skewers.delta_s(99, 11 + q, int(npix[q]), 0.2, 1.7, 1.5, fixed_amp=fixed)
+            got = out["dens"][off[q]:off[q] + npix[q]]
+            # modes far above kcut have amplitudes below FP32 range: measure
+            # the error against the field's own scale sqrt(sigma_S^2)
+            scale = max(np.sqrt(np.mean(ref ** 2)), np.sqrt(0.423 * 1.7))
+            assert np.sqrt(np.mean((got - ref) ** 2)) < TOL * scale, (q, npix[q])
+            if npix[q] == 1:
+                assert got[0] == 0.0
+
+
+def test_trilinear_exact_on_linear_field(L):
+    """A field linear in the grid index is reproduced exactly (in a region that
+    does not wrap), and grid-point pixels return the voxel."""
+    import torch
+    n, dx = 64, 2.19
+    m = np.arange(n, dtype=np.float64)
+    X, Y, Z = np.meshgrid(m, m, m, indexing="ij")
+    d = (0.01 * X - 0.02 * Y + 0.03 * Z).astype(np.float32)
+    e = (0.5 - 0.01 * Z + 0.004 * X).astype(np.float32)
+    fld = torch.from_numpy(np.stack([d, e], axis=-1)).cuda()
+    rng = np.random.default_rng(4)
+    S = 300
+    o = rng.uniform(5, 50, (S, 3))
+    st = rng.normal(size=(S, 3)) * 0.05
+    sk = dict(origin_fx=np.round(o * T32).astype(np.int64), step_fx=np.round(st * T32).astype(np.int64),
+              npix=np.full(S, 100, np.int32), offset=np.arange(S, dtype=np.int64) * 100, chi0=np.full(S, 4000.0),
+              dchi=0.2, id_base=0)
+    out = gpu_skewers(L, fld, n, dx, sk, 1, 0.0, 1.5, 0.2, None, want=("dens", "eta"))
+    rd, re_ = skewers.draw_skewers(d.astype(np.float64), e.astype(np.float64), sk, 1)
+    assert np.max(np.abs(out["dens"] - rd)) < 2e-6
+    assert np.max(np.abs(out["eta"] - re_)) < 2e-6
+
+
+def test_periodic_wrap_and_negative_positions(L, tiny):
+    cfg, fld, ref, sk = tiny
+    n, dx = cfg["n"], cfg["dx"]
+    sk2 = dict(sk)
+    shift = np.array([[-3 * n, 5 * n, -7 * n]], dtype=np.int64) * T32
+    sk2["origin_fx"] = sk["origin_fx"] + shift
+    a = gpu_skewers(L, fld, n, dx, sk, 7, 0.0, 1.5, 0.2, None, want=("dens", "eta"))
+    b = gpu_skewers(L, fld, n, dx, sk2, 7, 0.0, 1.5, 0.2, None, want=("dens", "eta"))
+    np.testing.assert_array_equal(a["dens"], b["dens"])
+    np.testing.assert_array_equal(a["eta"], b["eta"])
+
+
+def test_apply_fgpa_on_oracle_pixels(L):
+    """Same pre-FGPA pixels (from the oracle) into both: flux and bin sums."""
+    cfg = mockinputs.config("mid", n_sk=3000)
+    sk = mockinputs.skewer_table(cfg)
+    rng = np.random.default_rng(8)
+    dens = rng.normal(0, 1.0, sk["total"]).astype(np.float32)
+    eta = rng.normal(0, 0.5, sk["total"]).astype(np.float32)
+    edges = fgpa.chi_edges_for_z(cfg["z_edges"])
+    out = gpu_apply_fgpa(L, sk, dens, eta, cfg["fgpa"], edges)
+    rf, z = fgpa.apply_fgpa(dens.astype(np.float64), eta.astype(np.float64), sk, cfg["fgpa"])
+    assert rel_rms(out["flux"], rf) < TOL
+    chi = fgpa.pixel_chi(sk)
+    fs, cnt = fgpa.mean_flux_bins(rf, chi, edges)
+    np.testing.assert_array_equal(out["count"], cnt)
+    ok = cnt > 0
+    np.testing.assert_allclose(out["fsum"][ok] / cnt[ok], fs[ok] / cnt[ok], rtol=1e-6)
+
+
+def test_empty_and_degenerate(L):
+    import torch
+    n, dx = 32, 2.19
+    fld = torch.zeros((n, n, n, 2), dtype=torch.float32, device="cuda")
+    sk = dict(origin_fx=np.zeros((0, 3), np.int64), step_fx=np.zeros((0, 3), np.int64),
+              npix=np.zeros(0, np.int32), offset=np.zeros(0, np.int64), chi0=np.zeros(0), dchi=0.2, id_base=0)
+    edges = np.array([1000.0, 2000.0, 3000.0])
+    out = gpu_skewers(L, fld, n, dx, sk, 1, 1.0, 1.5, 0.2, mockinputs.FGPA_MID, edges)
+    np.testing.assert_array_equal(out["count"], [0, 0])
+    np.testing.assert_array_equal(out["fsum"], [0.0, 0.0])
+    # zero-length skewers among others
+    sk = dict(origin_fx=np.zeros((3, 3), np.int64), step_fx=np.zeros((3, 3), np.int64),
+              npix=np.array([0, 5, 0], np.int32), offset=np.array([0, 0, 5], np.int64),
+              chi0=np.full(3, 2500.0), dchi=0.2, id_base=0)
+    edges = np.array([2000.0, 3000.0])
+    out = gpu_skewers(L, fld, n, dx, sk, 1, 0.0, 1.5, 0.2, [[0.5, 0, 0], [1.6, 0, 0], [1.0, 0, 0]], edges)
+    np.testing.assert_array_equal(out["count"], [5])
+    np.testing.assert_allclose(out["flux"][:5], np.exp(-0.5), rtol=1e-6)
+
+
+def test_error_paths(L):
+    import ctypes
+    import torch
+    box = L.box_struct(64, 2.19)
+    with pytest.raises(L.LyaError) as ei:
+        L.make_box(L.box_struct(64, 2.19), L.pk_struct(), 1, 1.0, True, None,
+                   torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == L.LYA_EINVAL
+    f = torch.empty((64, 64, 64, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.LyaError) as ei:
+        L.make_box(box, L.pk_struct(), 1, 1.0, True, f, torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == L.LYA_EWORKSPACE
