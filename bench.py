@@ -122,7 +122,7 @@ def main():
     n_sk = len(sk["npix"])
     box = L.box_struct(n, dx)
     pk = L.pk_struct(**cfg["pk"])
-    field = torch.empty((n, n, n, 2), dtype=torch.float32, device="cuda")
+    field = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
     bwork = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
     swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
     dev = {k: torch.from_numpy(np.ascontiguousarray(sk[k])).cuda()

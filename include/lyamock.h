@@ -13,10 +13,13 @@
  *     non-zero return nothing was enqueued (LYA_EINVAL, LYA_EWORKSPACE,
  *     LYA_EUNSUPPORTED) or the state of the outputs is undefined (LYA_EHIP).
  *     lya_last_error() then returns a message (thread-local).
- *   - Real-space boxes are row-major [x][y][z] with z fastest; grid point
- *     (i, j, k) sits at (i, j, k) * dx.  Element type: LYA_F32 -> float2
- *     {C_a, C_b} (8 bytes per cell); LYA_BF16 -> two bfloat16 packed in a
- *     uint32, C_a in the low half (4 bytes per cell).
+ *   - Real-space boxes are [x][y][z] with z fastest: grid point (i, j, k),
+ *     at position (i, j, k) * dx, is element i * pitch + j * n + k, where
+ *     pitch = lya_plane_pitch(box) = n^2 + 32 (each x plane is followed by 32
+ *     unused elements, which keeps the x-direction FFT pass off a
+ *     power-of-two stride).  A box holds lya_field_elems(box) = n * pitch
+ *     elements.  Element type: LYA_F32 -> float2 {C_a, C_b} (8 bytes);
+ *     LYA_BF16 -> two bfloat16 packed in a uint32, C_a in the low half (4 bytes).
  */
 #ifndef LYAMOCK_H
 #define LYAMOCK_H
@@ -106,6 +109,10 @@ typedef struct {
   double* fsum;             /* device [n_bins] */
   int64_t* count;           /* device [n_bins] */
 } lya_zbins;
+
+/* Elements of a box (n * plane pitch) and the plane pitch; 0 for an invalid box. */
+size_t lya_field_elems(const lya_box* box);
+size_t lya_plane_pitch(const lya_box* box);
 
 /* Bytes of device workspace a call needs.  op = LYA_OP_BOX for lya_make_box and
  * lya_make_eta (for LYA_BF16 storage this includes an n^3 complex64 staging box),

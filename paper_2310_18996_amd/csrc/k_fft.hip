@@ -9,7 +9,8 @@
 // real part is delta and the imaginary part eta_par along z, both real fields
 // because X_a and X_b are each Hermitian.
 //
-// Three passes over the row-major [x][y][z] complex64 box, in place:
+// Three passes over the [x][y][z] complex64 box (x planes padded, see
+// plane_pitch), in place:
 //   pass Z: synthesises the modes of T pencils along z straight into
 //           registers (no spectrum is ever written to memory), FFT along z;
 //   pass Y: tiles of N (y) x T (z contiguous) elements, FFT along y;
@@ -45,6 +46,35 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
+// Tile order of the strided passes (block -> (outer, z0)):
+//   0: each XCD walks consecutive tiles, z chunks fastest;
+//   1: each XCD walks pairs of neighbouring z chunks (which share cache lines)
+//      with the outer index changing between pairs, so the requests in flight
+//      spread over more rows of the box;
+//   2: plain order, z chunks fastest;
+//   3: each XCD walks tiles with the outer index fastest.
+template <int N, int T, int ORDER>
+__device__ __forceinline__ void strided_tile(int b, int& outer, int& t0) {
+  constexpr int nb = N * (N / T);
+  if (ORDER == 2) {
+    outer = b / (N / T);
+    t0 = (b % (N / T)) * T;
+    return;
+  }
+  const int u = xcd_tile(b, nb);
+  if (ORDER == 0) {
+    outer = u / (N / T);
+    t0 = (u % (N / T)) * T;
+  } else if (ORDER == 1) {
+    const int rest = u >> 1;
+    outer = rest % N;
+    t0 = (2 * (rest / N) + (u & 1)) * T;
+  } else {
+    outer = u % N;
+    t0 = (u / N) * T;
+  }
+}
+
 __device__ __forceinline__ int sfreq(int i, int n) { return i < n / 2 ? i : i - n; }
 
 __device__ __forceinline__ float comp_mult(int comp, int nx, int ny, int nz, int n2, int n, float f) {
@@ -60,7 +90,8 @@ __device__ __forceinline__ float comp_mult(int comp, int nx, int ny, int nz, int
     default: a = ny; b = nz; break;
   }
   if (comp >= 4 && (a == -(n / 2) || b == -(n / 2))) return 0.0f;
-  return f * static_cast<float>(a * b) / static_cast<float>(n2);
+  // a*b and n2 are exact in FP32 (|n|^2 < 2^24); reciprocal good to 1 ulp
+  return f * static_cast<float>(a * b) * __builtin_amdgcn_rcpf(static_cast<float>(n2));
 }
 
 // Mode (ix, iy, iz) of the packed spectrum.
@@ -97,13 +128,33 @@ struct Pass {
   static constexpr bool PF = KIND != KIND_GENZ;  // lanes walk the T contiguous pencils first
   static constexpr int NSTAGE = nstages_of(N);
 
-  // global element index of element i of pencil p in tile (outer, t0)
-  __device__ static __forceinline__ size_t gidx(int outer, int t0, int i, int p) {
-    if (KIND == KIND_GENZ) return (static_cast<size_t>(outer) * N + t0 + p) * N + i;
-    if (KIND == KIND_Y) return (static_cast<size_t>(outer) * N + i) * N + t0 + p;
-    return (static_cast<size_t>(i) * N + outer) * N + t0 + p;
+  // Synthesising pass: a tile holds T pencils along z.  "Paired" tiles hold
+  // H = T/2 pencils (ix, iy0..iy0+H-1) with 0 < ix < N/2, which own all their
+  // modes, followed by their Hermitian partner pencils (N-ix, -iy mod N); the
+  // remaining rows ix = 0 and ix = N/2 are cut into unpaired tiles of T pencils.
+  static constexpr int H = T / 2;
+  static constexpr size_t kPitch = plane_pitch(N);
+  static constexpr int kPairedTiles = (N / 2 - 1) * (N / H);
+
+  // global element index of element i of pencil p in tile (outer, t0); for the
+  // synthesising pass outer is ix and t0 is iy0 (paired flags the tile kind)
+  __device__ static __forceinline__ size_t gidx(int outer, int t0, int i, int p, bool paired = false) {
+    if (KIND == KIND_GENZ) {
+      if (paired && p >= H)
+        return static_cast<size_t>(N - outer) * kPitch + static_cast<size_t>((N - t0 - (p - H)) & (N - 1)) * N + i;
+      return static_cast<size_t>(outer) * kPitch + static_cast<size_t>(t0 + p) * N + i;
+    }
+    if (KIND == KIND_Y) return static_cast<size_t>(outer) * kPitch + static_cast<size_t>(i) * N + t0 + p;
+    return static_cast<size_t>(i) * kPitch + static_cast<size_t>(outer) * N + t0 + p;
   }
-  __device__ static __forceinline__ int lidx(int i, int p) { return PF ? i * T + p : p * N + i; }
+  // LDS layout with one padding slot per R0 elements along the FFT axis (R0 =
+  // first radix): the first stage scatters its outputs with stride R0, which
+  // without padding lands every lane group on the same banks.
+  static constexpr int R0 = radix_of(N, 0);
+  static constexpr int LDS_ELEMS = T * (N + N / R0);
+  __device__ static __forceinline__ int lidx(int i, int p) {
+    return PF ? (i + i / R0) * T + p : p * (N + N / R0) + i + i / R0;
+  }
 
   template <int R>
   __device__ static __forceinline__ void coords(int w, int& p, int& j) {
@@ -160,7 +211,7 @@ struct Pass {
 
   template <int S>
   __device__ static __forceinline__ void store_global(const float2 (&v)[E], float2* data, uint32_t* out_bf16,
-                                                      bool zero_b, int outer, int t0, int tid) {
+                                                      bool zero_b, int outer, int t0, bool paired, int tid) {
     constexpr int R = radix_of(N, S), B = E / R;
     static_assert(ns_before(N, S) * R == N, "last stage");
 #pragma unroll
@@ -169,7 +220,7 @@ struct Pass {
       coords<R>(tid + b * NT, p, j);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const size_t gi = gidx(outer, t0, j + r * (N / R), p);
+        const size_t gi = gidx(outer, t0, j + r * (N / R), p, paired);
         // a single requested component: the other half is exactly zero, not FFT rounding residue
         const float2 o = make_float2(v[b * R + r].x, zero_b ? 0.0f : v[b * R + r].y);
         if (out_bf16) {
@@ -182,21 +233,77 @@ struct Pass {
   }
 };
 
-template <int N, int T, int E, int KIND>
+// Paired synthesis: one Philox call per two consecutive owner modes (counter
+// lin >> 1, words (x, y) for even iz and (z, w) for odd iz), one Box-Muller per
+// owner mode, and each owner mode also fills its partner (N-ix, -iy, -iz) with
+// the conjugate noise.  Result goes to LDS in pencil-major order.
+template <int N, int T, int NT, typename LIDX>
+__device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, float2* lds, LIDX lidx) {
+  constexpr int H = T / 2;
+  const int nx = ix;  // 0 < ix < N/2
+  for (int w = threadIdx.x; w < H * (N / 2); w += NT) {
+    const int po = w / (N / 2), m = w % (N / 2);
+    const int iy = iy0 + po;
+    const int ny = sfreq(iy, N);
+    const uint64_t ctr = (static_cast<uint64_t>(ix) * N + iy) * (N / 2) + m;
+    const uint4 wd = philox10(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 0u, 0u),
+                              static_cast<uint32_t>(g.seed), static_cast<uint32_t>(g.seed >> 32));
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int iz = 2 * m + e;
+      const int nz = sfreq(iz, N);
+      const int n2 = nx * nx + ny * ny + nz * nz;
+      float s = g.table[n2];
+      if (g.only_n2 >= 0 && n2 != g.only_n2) s = 0.0f;
+      const float2 z = e ? box_muller(wd.z, wd.w) : box_muller(wd.x, wd.y);
+      float2 wv = make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
+      if (g.fixed_amp) {
+        const float r = rsqrtf(wv.x * wv.x + wv.y * wv.y);
+        wv.x *= r;
+        wv.y *= r;
+      }
+      const float ma = s * comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
+      const float mb = s * comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
+      // X = W (ma + i mb), X' = conj(W) (ma + i mb)
+      lds[lidx(iz, po)] = make_float2(wv.x * ma - wv.y * mb, wv.y * ma + wv.x * mb);
+      lds[lidx((N - iz) & (N - 1), H + po)] = make_float2(wv.x * ma + wv.y * mb, wv.x * mb - wv.y * ma);
+    }
+  }
+}
+
+template <int N, int T, int E, int KIND, int ORDER = 1>
 __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ data, uint32_t* __restrict__ out_bf16,
                                                         const float2* __restrict__ tw, GenParams g) {
   using P = Pass<N, T, E, KIND>;
   constexpr int NT = P::NT;
-  __shared__ float2 lds[N * T];
+  __shared__ float2 lds[P::LDS_ELEMS];
   float2 v[E];
   const int tid = threadIdx.x;
   const int ntiles = N * (N / T);
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  const int outer = tile / (N / T);
-  const int t0 = (tile % (N / T)) * T;
+  const int tile = xcd_tile(blockIdx.x, ntiles);  // synthesising pass
+  int outer, t0;
+  bool paired = false;
+  if (KIND == KIND_GENZ) {
+    if (tile < P::kPairedTiles) {
+      paired = true;
+      outer = 1 + tile / (N / P::H);
+      t0 = (tile % (N / P::H)) * P::H;
+    } else {
+      const int u = tile - P::kPairedTiles;
+      outer = u < N / T ? 0 : N / 2;
+      t0 = (u % (N / T)) * T;
+    }
+  } else {
+    strided_tile<N, T, ORDER>(blockIdx.x, outer, t0);
+  }
 
   // stage 0: registers from global memory or from the synthesiser
-  {
+  if (KIND == KIND_GENZ && paired) {
+    gen_paired<N, T, NT>(g, outer, t0, lds, [](int i, int p) { return P::lidx(i, p); });
+    __syncthreads();
+    P::template load_lds<0>(v, lds, tid);
+    __syncthreads();
+  } else {
     constexpr int R = radix_of(N, 0), B = E / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -220,7 +327,7 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
   P::template butterflies<1>(v, tw, tid);
   if constexpr (P::NSTAGE == 2) {
     P::template store_global<1>(v, data, KIND == KIND_X ? out_bf16 : nullptr, KIND == KIND_X && g.comp_b < 0,
-                                 outer, t0, tid);
+                                 outer, t0, paired, tid);
   } else {
     __syncthreads();
     P::template store_lds<1>(v, lds, tid);
@@ -228,7 +335,7 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
     P::template load_lds<2>(v, lds, tid);
     P::template butterflies<2>(v, tw, tid);
     P::template store_global<2>(v, data, KIND == KIND_X ? out_bf16 : nullptr, KIND == KIND_X && g.comp_b < 0,
-                                 outer, t0, tid);
+                                 outer, t0, paired, tid);
   }
 }
 

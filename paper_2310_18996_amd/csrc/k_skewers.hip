@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
   if (a.n_bins > 0 && a.chi_edges)
     for (int b = tid; b <= a.n_bins; b += kSkNT) s_edges[b] = a.chi_edges[b];
   const int N = a.n;
-  const size_t NN = static_cast<size_t>(N) * N;
+  const size_t NN = plane_pitch(N);
   const bool gather = a.in_dens == nullptr;
   const bool want_bins = a.n_bins > 0 && a.do_flux;
   for (;;) {

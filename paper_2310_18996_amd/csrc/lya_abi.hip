@@ -37,7 +37,7 @@ BoxCarve carve_box(const lya_box* b) {
   c.tw = o;      o += align256(sizeof(float2) * b->n);
   c.table = o;   o += align256(sizeof(float) * lya::amp_table_entries(b->n));
   c.staging = o;
-  if (b->storage == LYA_BF16) o += align256(sizeof(float2) * static_cast<size_t>(b->n) * b->n * b->n);
+  if (b->storage == LYA_BF16) o += align256(sizeof(float2) * lya::box_elems(b->n));
   c.total = o;
   return c;
 }
@@ -168,6 +168,16 @@ extern "C" {
 const char* lya_last_error(void) { return g_err; }
 
 const char* lya_version(void) { return "lyamock 0.1 gfx950"; }
+
+size_t lya_field_elems(const lya_box* box) {
+  if (!box || !pow2_in_range(box->n)) return 0;
+  return lya::box_elems(box->n);
+}
+
+size_t lya_plane_pitch(const lya_box* box) {
+  if (!box || !pow2_in_range(box->n)) return 0;
+  return lya::plane_pitch(box->n);
+}
 
 size_t lya_workspace_size(int op, const lya_box* box) {
   if (op == LYA_OP_BOX) {

@@ -22,6 +22,16 @@ struct PkParams {
 
 inline int amp_table_entries(int n) { return 3 * (n / 2) * (n / 2) + 1; }
 
+// Box layout: element (x, y, z) at x * plane_pitch(n) + y * n + z.  The x
+// planes are padded by kPlanePad elements: without it the x-direction FFT pass
+// walks memory with a stride of a large power of two and its requests pile up
+// on few HBM channels.
+constexpr int kPlanePad = 32;
+__host__ __device__ constexpr size_t plane_pitch(int n) {
+  return static_cast<size_t>(n) * static_cast<size_t>(n) + kPlanePad;
+}
+__host__ __device__ constexpr size_t box_elems(int n) { return static_cast<size_t>(n) * plane_pitch(n); }
+
 // Workspace carve-up of lya_make_box / lya_make_eta.
 struct TableWork {
   double* partial;  // kSigmaBlocks

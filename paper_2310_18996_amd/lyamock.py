@@ -16,7 +16,7 @@ LYA_F32, LYA_BF16 = 0, 1
 LYA_OP_BOX, LYA_OP_SKEWERS = 0, 1
 COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6}
 
-EXPORTS = ("lya_workspace_size", "lya_make_box", "lya_make_eta", "lya_draw_skewers",
+EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta", "lya_draw_skewers",
            "lya_apply_fgpa", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
            "lya_last_error", "lya_version")
 
@@ -73,6 +73,10 @@ def load():
         raise ImportError("liblyamock.so not built at %s (run __graft_entry__.build())" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     P, VP = ctypes.POINTER, ctypes.c_void_p
+    lib.lya_field_elems.restype = ctypes.c_size_t
+    lib.lya_field_elems.argtypes = [P(Box)]
+    lib.lya_plane_pitch.restype = ctypes.c_size_t
+    lib.lya_plane_pitch.argtypes = [P(Box)]
     lib.lya_workspace_size.restype = ctypes.c_size_t
     lib.lya_workspace_size.argtypes = [ctypes.c_int, P(Box)]
     lib.lya_make_box.restype = ctypes.c_int
@@ -125,6 +129,21 @@ def box_struct(n, dx, storage=LYA_F32):
 def pk_struct(sigma8=0.8, ns=0.96, gamma=0.21, wig_amp=0.05, wig_r=105.0, wig_kd=0.2, smooth=0.0,
               fixed_amp=False, only_n2=-1):
     return Pk(sigma8, ns, gamma, wig_amp, wig_r, wig_kd, smooth, int(bool(fixed_amp)), int(only_n2))
+
+
+def field_elems(box):
+    return int(load().lya_field_elems(ctypes.byref(box)))
+
+
+def plane_pitch(box):
+    return int(load().lya_plane_pitch(ctypes.byref(box)))
+
+
+def box_view(field, n):
+    """[n, n, n, ...] view (no copy) of a box tensor whose first dimension holds
+    the field_elems elements; the plane padding is sliced away."""
+    pitch = field.shape[0] // n
+    return field.view(n, pitch, *field.shape[1:])[:, :n * n].unflatten(1, (n, n))
 
 
 def workspace_size(op, box=None):

@@ -30,15 +30,26 @@ def gpu_box(L, n, dx, seed, f=1.0, with_eta=True, storage=0, comps=None, **pkkw)
     pk = L.pk_struct(**pkkw)
     ws = L.workspace_size(L.LYA_OP_BOX, box)
     work = torch.empty(ws, dtype=torch.uint8, device="cuda")
+    elems = L.field_elems(box)
     if storage == L.LYA_F32:
-        field = torch.empty((n, n, n, 2), dtype=torch.float32, device="cuda")
+        field = torch.empty((elems, 2), dtype=torch.float32, device="cuda")
     else:
-        field = torch.empty((n, n, n), dtype=torch.int32, device="cuda")
+        field = torch.empty((elems,), dtype=torch.int32, device="cuda")
     if comps is None:
         L.make_box(box, pk, seed, f, with_eta, field, work)
     else:
         L.make_eta(box, pk, seed, f, comps[0], comps[1], field, work)
     torch.cuda.synchronize()
+    return L.box_view(field, n)
+
+
+def padded_box(L, arr):
+    """Device box in the library layout (padded x planes) holding the host
+    array arr [n, n, n, 2] float32."""
+    n = arr.shape[0]
+    box = L.box_struct(n, 1.0)
+    field = torch.zeros((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
+    L.box_view(field, n).copy_(torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float32)))
     return field
 
 

@@ -104,7 +104,7 @@ def test_box_lines_against_c_oracle(L, n):
     """Sampled whole z-lines (exact FP64, plain C oracle) plus Parseval."""
     dx, seed = 2.19, 1234
     print("line parity n=%d" % n, flush=True)
-    gt = gpu_box(L, n, dx, seed, 1.0, **PK)
+    gt = gpu_box(L, n, dx, seed, 1.0, **PK)   # [n, n, n, 2] view of the padded box
     cols = [(0, 0), (1, n - 1), (n // 2, 3), (n - 1, n // 2)]
     tab = oracle_table(PK, n, dx)
     re, im = lines.field_lines(n, seed, tab, cols)

@@ -4,7 +4,7 @@ import pytest
 
 import mockinputs
 from oracle import cosmology, fgpa, field, skewers
-from tests.lyahelp import gpu_apply_fgpa, gpu_box, gpu_skewers, oracle_table, rel_rms
+from tests.lyahelp import gpu_apply_fgpa, gpu_box, gpu_skewers, oracle_table, padded_box, rel_rms
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -68,7 +68,7 @@ def test_small_scale_field_alone(L):
     including lengths that are not powers of two and the fixed-amplitude hook."""
     import torch
     n, dx = 32, 2.19
-    fld = torch.zeros((n, n, n, 2), dtype=torch.float32, device="cuda")
+    fld = padded_box(L, np.zeros((n, n, n, 2), np.float32))
     npix = np.array([1, 2, 3, 200, 256, 257, 700, 1024, 1500, 2048], dtype=np.int32)
     off = np.concatenate([[0], np.cumsum(npix[:-1])]).astype(np.int64)
     S = len(npix)
@@ -96,7 +96,7 @@ def test_trilinear_exact_on_linear_field(L):
     X, Y, Z = np.meshgrid(m, m, m, indexing="ij")
     d = (0.01 * X - 0.02 * Y + 0.03 * Z).astype(np.float32)
     e = (0.5 - 0.01 * Z + 0.004 * X).astype(np.float32)
-    fld = torch.from_numpy(np.stack([d, e], axis=-1)).cuda()
+    fld = padded_box(L, np.stack([d, e], axis=-1))
     rng = np.random.default_rng(4)
     S = 300
     o = rng.uniform(5, 50, (S, 3))
@@ -143,7 +143,7 @@ def test_apply_fgpa_on_oracle_pixels(L):
 def test_empty_and_degenerate(L):
     import torch
     n, dx = 32, 2.19
-    fld = torch.zeros((n, n, n, 2), dtype=torch.float32, device="cuda")
+    fld = padded_box(L, np.zeros((n, n, n, 2), np.float32))
     sk = dict(origin_fx=np.zeros((0, 3), np.int64), step_fx=np.zeros((0, 3), np.int64),
               npix=np.zeros(0, np.int32), offset=np.zeros(0, np.int64), chi0=np.zeros(0), dchi=0.2, id_base=0)
     edges = np.array([1000.0, 2000.0, 3000.0])
@@ -168,7 +168,7 @@ def test_error_paths(L):
         L.make_box(L.box_struct(64, 2.19), L.pk_struct(), 1, 1.0, True, None,
                    torch.empty(16, dtype=torch.uint8, device="cuda"))
     assert ei.value.code == L.LYA_EINVAL
-    f = torch.empty((64, 64, 64, 2), dtype=torch.float32, device="cuda")
+    f = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
     with pytest.raises(L.LyaError) as ei:
         L.make_box(box, L.pk_struct(), 1, 1.0, True, f, torch.empty(16, dtype=torch.uint8, device="cuda"))
     assert ei.value.code == L.LYA_EWORKSPACE
