@@ -237,7 +237,12 @@ struct Pass {
 // lin >> 1, words (x, y) for even iz and (z, w) for odd iz), one Box-Muller per
 // owner mode, and each owner mode also fills its partner (N-ix, -iy, -iz) with
 // the conjugate noise.  Result goes to LDS in pencil-major order.
-template <int N, int T, int NT, typename LIDX>
+// GM selects the synthesiser: GEN_GENERIC handles any component pair and the
+// test hooks; GEN_DELTA_ETAZ ({delta, f mu_z^2 delta}) and GEN_DELTA ({delta, 0})
+// are the branch-free forms used by lya_make_box.
+enum { GEN_GENERIC = 0, GEN_DELTA_ETAZ = 1, GEN_DELTA = 2 };
+
+template <int N, int T, int NT, int GM, typename LIDX>
 __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, float2* lds, LIDX lidx) {
   constexpr int H = T / 2;
   const int nx = ix;  // 0 < ix < N/2
@@ -254,16 +259,23 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
       const int nz = sfreq(iz, N);
       const int n2 = nx * nx + ny * ny + nz * nz;
       float s = g.table[n2];
-      if (g.only_n2 >= 0 && n2 != g.only_n2) s = 0.0f;
       const float2 z = e ? box_muller(wd.z, wd.w) : box_muller(wd.x, wd.y);
       float2 wv = make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
-      if (g.fixed_amp) {
-        const float r = rsqrtf(wv.x * wv.x + wv.y * wv.y);
-        wv.x *= r;
-        wv.y *= r;
+      float ma, mb;
+      if (GM == GEN_GENERIC) {
+        if (g.only_n2 >= 0 && n2 != g.only_n2) s = 0.0f;
+        if (g.fixed_amp) {
+          const float r = rsqrtf(wv.x * wv.x + wv.y * wv.y);
+          wv.x *= r;
+          wv.y *= r;
+        }
+        ma = s * comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
+        mb = s * comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
+      } else {
+        ma = s;  // n2 > 0 here (ix > 0)
+        mb = GM == GEN_DELTA_ETAZ ? s * g.f * static_cast<float>(nz * nz) * __builtin_amdgcn_rcpf(static_cast<float>(n2))
+                                  : 0.0f;
       }
-      const float ma = s * comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
-      const float mb = s * comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
       // X = W (ma + i mb), X' = conj(W) (ma + i mb)
       lds[lidx(iz, po)] = make_float2(wv.x * ma - wv.y * mb, wv.y * ma + wv.x * mb);
       lds[lidx((N - iz) & (N - 1), H + po)] = make_float2(wv.x * ma + wv.y * mb, wv.x * mb - wv.y * ma);
@@ -271,7 +283,7 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
   }
 }
 
-template <int N, int T, int E, int KIND, int ORDER = 1>
+template <int N, int T, int E, int KIND, int ORDER = 1, int GM = GEN_GENERIC>
 __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ data, uint32_t* __restrict__ out_bf16,
                                                         const float2* __restrict__ tw, GenParams g) {
   using P = Pass<N, T, E, KIND>;
@@ -299,7 +311,7 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
 
   // stage 0: registers from global memory or from the synthesiser
   if (KIND == KIND_GENZ && paired) {
-    gen_paired<N, T, NT>(g, outer, t0, lds, [](int i, int p) { return P::lidx(i, p); });
+    gen_paired<N, T, NT, GM>(g, outer, t0, lds, [](int i, int p) { return P::lidx(i, p); });
     __syncthreads();
     P::template load_lds<0>(v, lds, tid);
     __syncthreads();
@@ -355,14 +367,28 @@ template <int N>
 hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16, hipStream_t st) {
   using S = Shape<N>;
   const int tz = N * (N / S::TZ), ts = N * (N / S::TS);
-  LYA_TIMED("fft_z_gen", st,
-            hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ>), dim3(tz), dim3(N * S::TZ / S::EZ), 0, st,
-                               field, nullptr, tw, g));
+  const bool hooks = g.fixed_amp || g.only_n2 >= 0;
+  const int gm = (!hooks && g.comp_a == 0 && g.comp_b == 3)    ? GEN_DELTA_ETAZ
+                 : (!hooks && g.comp_a == 0 && g.comp_b == -1) ? GEN_DELTA
+                                                               : GEN_GENERIC;
+  if (gm == GEN_DELTA_ETAZ) {
+    LYA_TIMED("fft_z_gen", st,
+              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_DELTA_ETAZ>), dim3(tz),
+                                 dim3(N * S::TZ / S::EZ), 0, st, field, nullptr, tw, g));
+  } else if (gm == GEN_DELTA) {
+    LYA_TIMED("fft_z_gen", st,
+              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_DELTA>), dim3(tz),
+                                 dim3(N * S::TZ / S::EZ), 0, st, field, nullptr, tw, g));
+  } else {
+    LYA_TIMED("fft_z_gen", st,
+              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_GENERIC>), dim3(tz),
+                                 dim3(N * S::TZ / S::EZ), 0, st, field, nullptr, tw, g));
+  }
   LYA_TIMED("fft_y", st,
-            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_Y>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
+            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_Y, 0>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
                                field, nullptr, tw, g));
   LYA_TIMED("fft_x", st,
-            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_X>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
+            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_X, 1>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
                                field, field_bf16, tw, g));
   return hipGetLastError();
 }

@@ -7,19 +7,35 @@
 //     interpolation of the packed {delta, eta} box;
 //   * delta_S: Philox normals (stream 1, counter (q<<33)+m) on modes
 //     m = 0..N_S/2 of a length N_S = next_pow2(n_q) line, scaled by
-//     sqrt(P_s(k_m)/(N_S dpix)), P_s = amp exp(-(k/kcut)^2), inverse FFT in LDS;
+//     sqrt(P_s(k_m)/(N_S dpix)), P_s = amp exp(-(k/kcut)^2), then the real
+//     inverse DFT, computed as one complex inverse FFT of length N_S/2 whose
+//     output holds the even pixels in its real part and the odd pixels in
+//     its imaginary part;
 //   * g = delta_L + delta_S + c(z) eta_par, F = exp(-a(z) exp(b(z) g)), with
 //     a, b, c quadratics in (1+z) and z the unperturbed redshift of
 //     chi_j = chi0 - j*dchi (section "FGPA");
 //   * per redshift bin, the sum of F and the pixel count, accumulated as
 //     exact 64-bit integers of round(F 2^32), so the result does not depend on
 //     the order in which work is scheduled.
-// One persistent launch: blocks pull chunks of skewers from an atomic queue.
+// One persistent launch; each wavefront pulls chunks of skewers from an
+// atomic queue and owns a skewer at a time (its small-scale FFT lives in the
+// wave's slice of LDS, so no block-wide barrier is needed per skewer).
 #include "lya_internal.h"
 
 namespace lya {
 
-constexpr int kSkNT = 256;
+constexpr int kSkWaves = 4;
+constexpr int kSkNT = 64 * kSkWaves;
+constexpr int kHalfMax = 1024;                        // N_S/2 <= 1024
+constexpr int kHalfBuf = kHalfMax + kHalfMax / 16;    // one padding slot per 16
+
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ void __launch_bounds__(256) k_skewer_reset(unsigned int* queue, unsigned long long* bsum,
                                                       unsigned long long* bcnt) {
@@ -46,60 +62,93 @@ __device__ __forceinline__ float2 ld_field(const SkewerArgs& a, size_t i) {
   return unpack_bf16x2(a.field_bf16[i]);
 }
 
-// delta_S of skewer (qid, npix) into one of the two LDS buffers; returns it.
-__device__ float2* small_scale(const SkewerArgs& a, int64_t qid, int npix, float2 (*buf)[2048]) {
-  int ns = 1;
-  while (ns < npix) ns <<= 1;
-  const int tid = threadIdx.x;
-  const float amp_scale = static_cast<float>(a.ps_amp / (ns * a.dpix));
-  const float dk = static_cast<float>(2.0 * M_PI / (ns * a.dpix));
-  const float ikc = static_cast<float>(1.0 / a.ps_kcut);
-  for (int m = tid; m <= ns / 2; m += kSkNT) {
-    float2 y = make_float2(0.0f, 0.0f);
-    if (m > 0) {
-      const float k = dk * m;
-      const float kk = k * ikc;
-      const float amp = sqrtf(amp_scale * expf(-kk * kk));
-      const float2 z = normal_pair(a.seed, 1u, (static_cast<uint64_t>(qid) << 33) + static_cast<uint64_t>(m));
-      float2 w = (m == ns / 2) ? make_float2(z.x, 0.0f) : make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
-      if (a.ps_fixed_amp) {
-        const float r = rsqrtf(w.x * w.x + w.y * w.y);
-        w.x *= r;
-        w.y *= r;
-      }
-      y = make_float2(amp * w.x, amp * w.y);
-    }
-    buf[0][m] = y;
-    if (m > 0 && m < ns / 2) buf[0][ns - m] = make_float2(y.x, -y.y);
+// Mode Y_m of the small-scale spectrum (0 < m <= ns/2).
+__device__ __forceinline__ float2 ps_mode(const SkewerArgs& a, uint64_t qid, int m, int ns, float amp_scale,
+                                          float dk2) {
+  const float kk = static_cast<float>(m) * static_cast<float>(m) * dk2;   // (k/kcut)^2
+  const float amp = __builtin_amdgcn_sqrtf(amp_scale * __expf(-kk));
+  const float2 z = normal_pair(a.seed, 1u, (qid << 33) + static_cast<uint64_t>(m));
+  float2 w = (m == ns / 2) ? make_float2(z.x, 0.0f) : make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
+  if (a.ps_fixed_amp) {
+    const float r = rsqrtf(w.x * w.x + w.y * w.y);
+    w.x *= r;
+    w.y *= r;
   }
-  __syncthreads();
-  int src = 0;
-  for (int s = 1; s < ns;) {
-    const int R = (ns / s >= 4) ? 4 : 2;
-    const int nb = ns / R;
-    const float2* in = buf[src];
-    float2* out = buf[src ^ 1];
-    for (int j = tid; j < nb; j += kSkNT) {
-      const int k = j % s;
-      float2 v[4];
-      for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
-      if (s > 1) {
-        const int step = kTw2048 / (s * R);
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], a.tw2048[r * k * step]);
-      }
-      if (R == 4) {
-        dft4(v[0], v[1], v[2], v[3]);
-      } else {
-        dft2(v[0], v[1]);
-      }
-      const int base = (j / s) * s * R + k;
-      for (int r = 0; r < R; ++r) out[base + r * s] = v[r];
+  return make_float2(amp * w.x, amp * w.y);
+}
+
+// delta_S of one skewer by one wavefront into buf (pixel 2n in .x and pixel
+// 2n+1 in .y of element pidx(n)); ns = next_pow2(npix) >= 2.
+__device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, float2* buf, int lane) {
+  const int M = ns / 2;
+  const float amp_scale = static_cast<float>(a.ps_amp / (ns * a.dpix));
+  const double dk = 2.0 * M_PI / (ns * a.dpix) / a.ps_kcut;
+  const float dk2 = static_cast<float>(dk * dk);
+  const int twstep = kTw2048 / ns;  // w^k = exp(2 pi i k / ns)
+  // Z_k = (Y_k + Y_{k+M}) + i (Y_k - Y_{k+M}) w^k with Y_{k+M} = conj(Y_{M-k})
+  for (int k = lane; k <= M / 2; k += 64) {
+    if (k == 0) {
+      const float2 yM = ps_mode(a, qid, M, ns, amp_scale, dk2);  // real Nyquist mode
+      buf[pidx(0)] = make_float2(yM.x, -yM.x);
+      continue;
     }
-    __syncthreads();
-    src ^= 1;
+    const float2 yk = ps_mode(a, qid, k, ns, amp_scale, dk2);
+    const float2 ymk = (M - k == k) ? yk : ps_mode(a, qid, M - k, ns, amp_scale, dk2);
+    {
+      const float2 s = make_float2(yk.x + ymk.x, yk.y - ymk.y);   // Y_k + conj(Y_{M-k})
+      const float2 d = make_float2(yk.x - ymk.x, yk.y + ymk.y);   // Y_k - conj(Y_{M-k})
+      const float2 t = cmul(d, a.tw2048[k * twstep]);
+      buf[pidx(k)] = make_float2(s.x - t.y, s.y + t.x);
+    }
+    if (M - k != k) {
+      const float2 s = make_float2(ymk.x + yk.x, ymk.y - yk.y);
+      const float2 d = make_float2(ymk.x - yk.x, ymk.y + yk.y);
+      const float2 t = cmul(d, a.tw2048[(M - k) * twstep]);
+      buf[pidx(M - k)] = make_float2(s.x - t.y, s.y + t.x);
+    }
+  }
+  wave_sync();
+  // in-place Stockham inverse FFT of length M: every stage first reads all of
+  // the lane's inputs, then writes (the wave executes in lockstep)
+  for (int s = 1; s < M;) {
+    const int R = (M / s >= 4) ? 4 : 2;
+    const int nb = M / R;
+    float2 v[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = lane + 64 * t;
+      if (j < nb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (r < R) v[t][r] = buf[pidx(j + r * nb)];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = lane + 64 * t;
+      if (j < nb) {
+        const int k = j % s;
+        if (s > 1) {
+          const int step = kTw2048 / (s * R);
+#pragma unroll
+          for (int r = 1; r < 4; ++r)
+            if (r < R) v[t][r] = cmul(v[t][r], a.tw2048[r * k * step]);
+        }
+        if (R == 4) {
+          dft4(v[t][0], v[t][1], v[t][2], v[t][3]);
+        } else {
+          dft2(v[t][0], v[t][1]);
+        }
+        const int base = (j / s) * s * R + k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (r < R) buf[pidx(base + r * s)] = v[t][r];
+      }
+    }
+    wave_sync();
     s *= R;
   }
-  return buf[src];
 }
 
 __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c000, float c001, float c010, float c011,
@@ -113,35 +162,55 @@ __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c00
   return c0 + tx * (c1 - c0);
 }
 
+__device__ __forceinline__ double pixel_chi(double chi0, int j, double dchi) {
+  return __dsub_rn(chi0, __dmul_rn(static_cast<double>(j), dchi));
+}
+
 __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
-  __shared__ float2 sbuf[2][2048];
+  __shared__ float2 sbuf[kSkWaves][kHalfBuf];
+  __shared__ int sjb[kSkWaves][kMaxZBins + 1];
   __shared__ unsigned long long s_sum[kMaxZBins], s_cnt[kMaxZBins];
-  __shared__ double s_edges[kMaxZBins + 1];
-  __shared__ int s_chunk;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int b = tid; b < kMaxZBins; b += kSkNT) {
     s_sum[b] = 0ull;
     s_cnt[b] = 0ull;
   }
-  if (a.n_bins > 0 && a.chi_edges)
-    for (int b = tid; b <= a.n_bins; b += kSkNT) s_edges[b] = a.chi_edges[b];
+  __syncthreads();
   const int N = a.n;
   const size_t NN = plane_pitch(N);
   const bool gather = a.in_dens == nullptr;
   const bool want_bins = a.n_bins > 0 && a.do_flux;
+  float2* buf = sbuf[wv];
+  int* jb = sjb[wv];
   for (;;) {
-    __syncthreads();
-    if (tid == 0) s_chunk = static_cast<int>(atomicAdd(a.queue, 1u));
-    __syncthreads();
-    const int64_t q0 = static_cast<int64_t>(s_chunk) * a.chunk;
+    int c = 0;
+    if (lane == 0) c = static_cast<int>(atomicAdd(a.queue, 1u));
+    c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));
+    const int64_t q0 = static_cast<int64_t>(c) * a.chunk;
     if (q0 >= a.n_sk) break;
     const int64_t q1 = q0 + a.chunk < a.n_sk ? q0 + a.chunk : a.n_sk;
     for (int64_t q = q0; q < q1; ++q) {
       const int np = a.npix[q];
       const int64_t off = a.offset[q];
-      const float2* ds = nullptr;
-      // delta_S needs next_pow2(npix) <= 2048 (the LDS line); longer skewers get none
-      if (gather && a.ps_amp > 0.0 && np <= 2048) ds = small_scale(a, a.id_base + q, np, sbuf);
+      const double chi0 = a.chi0[q];
+      int ns = 1;
+      while (ns < np) ns <<= 1;
+      // delta_S needs next_pow2(npix) <= 2048 (the wave's LDS line); longer skewers get none
+      const bool with_ds = gather && a.ps_amp > 0.0 && ns >= 2 && ns <= 2 * kHalfMax;
+      if (with_ds) small_scale_wave(a, a.id_base + q, ns, buf, lane);
+      // bin boundaries: jb[b] = first pixel with chi_j < edges[b] (chi_j decreases with j)
+      if (want_bins) {
+        for (int b = lane; b <= a.n_bins; b += 64) {
+          const double e = a.chi_edges[b];
+          double j0 = a.dchi > 0.0 ? ceil((chi0 - e) / a.dchi) : 0.0;
+          j0 = j0 < 0.0 ? 0.0 : (j0 > np ? np : j0);
+          int j = static_cast<int>(j0);
+          while (j < np && pixel_chi(chi0, j, a.dchi) >= e) ++j;
+          while (j > 0 && pixel_chi(chi0, j - 1, a.dchi) < e) --j;
+          jb[b] = j;
+        }
+        wave_sync();
+      }
       int64_t ox = 0, oy = 0, oz = 0, sx = 0, sy = 0, sz = 0;
       if (gather) {
         ox = a.origin_fx[3 * q];
@@ -151,8 +220,12 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
         sy = a.step_fx[3 * q + 1];
         sz = a.step_fx[3 * q + 2];
       }
-      const double chi0 = a.chi0[q];
-      for (int j = tid; j < np; j += kSkNT) {
+      // pixel j is in bin b when jb[b+1] <= j < jb[b]; each lane walks j upward
+      // and therefore the bins downward, accumulating one bin at a time
+      int bin = a.n_bins - 1;
+      int cur = -1;
+      unsigned long long acc = 0ull, cnt = 0ull;
+      for (int j = lane; j < np; j += 64) {
         float d, e;
         if (gather) {
           const int64_t px = ox + j * sx, py = oy + j * sy, pz = oz + j * sz;
@@ -173,7 +246,10 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
           const float2 c110 = ld_field(a, r11 + iz), c111 = ld_field(a, r11 + jz);
           d = trilerp(tx, ty, tz, c000.x, c001.x, c010.x, c011.x, c100.x, c101.x, c110.x, c111.x);
           e = trilerp(tx, ty, tz, c000.y, c001.y, c010.y, c011.y, c100.y, c101.y, c110.y, c111.y);
-          if (ds) d += ds[j].x;
+          if (with_ds) {
+            const float2 z2 = buf[pidx(j >> 1)];
+            d += (j & 1) ? z2.y : z2.x;
+          }
           if (a.dens) a.dens[off + j] = d;
           if (a.eta) a.eta[off + j] = e;
         } else {
@@ -181,30 +257,41 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
           e = a.in_eta[off + j];
         }
         if (a.do_flux) {
-          const double chi = __dsub_rn(chi0, __dmul_rn(static_cast<double>(j), a.dchi));
-          const double u = chi * (1.0 / kZTabH);
+          const double u = pixel_chi(chi0, j, a.dchi) * (1.0 / kZTabH);
           int iu = static_cast<int>(u);
           iu = iu < 0 ? 0 : (iu > kZTabN - 2 ? kZTabN - 2 : iu);
           const float t = static_cast<float>(u - iu);
           const float zt0 = a.ztab[iu], zt1 = a.ztab[iu + 1];
-          const double x = 1.0 + static_cast<double>(zt0 + t * (zt1 - zt0));
-          const float ca = static_cast<float>(a.coef[0][0] + x * (a.coef[0][1] + x * a.coef[0][2]));
-          const float cb = static_cast<float>(a.coef[1][0] + x * (a.coef[1][1] + x * a.coef[1][2]));
-          const float cc = static_cast<float>(a.coef[2][0] + x * (a.coef[2][1] + x * a.coef[2][2]));
-          const float F = expf(-ca * expf(cb * (d + cc * e)));
+          const float x = (zt0 + t * (zt1 - zt0)) + (1.0f - kFgpaX0);   // (1+z) - x0
+          const float ca = a.cf[0][0] + x * (a.cf[0][1] + x * a.cf[0][2]);
+          const float cb = a.cf[1][0] + x * (a.cf[1][1] + x * a.cf[1][2]);
+          const float cc = a.cf[2][0] + x * (a.cf[2][1] + x * a.cf[2][2]);
+          const float F = __expf(-ca * __expf(cb * (d + cc * e)));
           if (a.flux) a.flux[off + j] = F;
-          if (want_bins && chi >= s_edges[0] && chi < s_edges[a.n_bins]) {
-            int lo = 0, hi = a.n_bins;  // edges[lo] <= chi < edges[hi]
-            while (hi - lo > 1) {
-              const int mid = (lo + hi) >> 1;
-              if (chi >= s_edges[mid]) lo = mid; else hi = mid;
+          if (want_bins) {
+            while (bin >= 0 && j >= jb[bin]) --bin;  // pixel j lies below bin's upper edge
+            const int key = (bin >= 0 && j >= jb[bin + 1]) ? bin : -1;
+            if (key != cur) {
+              if (cnt) {
+                atomicAdd(&s_sum[cur], acc);
+                atomicAdd(&s_cnt[cur], cnt);
+              }
+              acc = 0ull;
+              cnt = 0ull;
+              cur = key;
             }
-            atomicAdd(&s_sum[lo], static_cast<unsigned long long>(__float2ull_rn(F * 4294967296.0f)));
-            atomicAdd(&s_cnt[lo], 1ull);
+            if (key >= 0) {
+              acc += __float2ull_rn(F * 4294967296.0f);
+              cnt += 1ull;
+            }
           }
         }
       }
-      __syncthreads();  // the small-scale buffers are reused by the next skewer
+      if (cnt) {
+        atomicAdd(&s_sum[cur], acc);
+        atomicAdd(&s_cnt[cur], cnt);
+      }
+      wave_sync();  // the wave's LDS slice is reused by its next skewer
     }
   }
   if (want_bins) {
@@ -218,7 +305,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
   }
 }
 
-static int device_cus() {
+int device_cus() {
   static int cached[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
@@ -235,7 +322,7 @@ hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st) {
             hipLaunchKernelGGL(k_skewer_reset, dim3(1), dim3(256), 0, st, a.queue, a.bin_sum, a.bin_cnt));
   const int64_t nchunks = (a.n_sk + a.chunk - 1) / a.chunk;
   int64_t blocks = static_cast<int64_t>(device_cus()) * 4;
-  if (blocks > nchunks) blocks = nchunks;
+  if (blocks * kSkWaves > nchunks) blocks = (nchunks + kSkWaves - 1) / kSkWaves;
   if (blocks < 1) blocks = 1;
   LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
             hipLaunchKernelGGL(k_skewers, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));

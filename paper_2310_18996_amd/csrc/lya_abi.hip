@@ -115,10 +115,18 @@ int check_zbins(const lya_zbins* zb) {
   return LYA_OK;
 }
 
+// a, b, c = c0 + c1 x + c2 x^2 in x = 1+z are re-centred at x0 (FP64) so that
+// the device evaluates d0 + d1 t + d2 t^2, t = x - x0, in FP32 without the
+// cancellation between large powers of x.
 void fill_fgpa(lya::SkewerArgs& a, const lya_fgpa* fg) {
   a.do_flux = fg ? 1 : 0;
-  for (int p = 0; p < 3; ++p)
-    for (int i = 0; i < 3; ++i) a.coef[p][i] = fg ? fg->coef[p][i] : 0.0;
+  const double x0 = lya::kFgpaX0;
+  for (int p = 0; p < 3; ++p) {
+    const double c0 = fg ? fg->coef[p][0] : 0.0, c1 = fg ? fg->coef[p][1] : 0.0, c2 = fg ? fg->coef[p][2] : 0.0;
+    a.cf[p][0] = static_cast<float>(c0 + x0 * (c1 + x0 * c2));
+    a.cf[p][1] = static_cast<float>(c1 + 2.0 * x0 * c2);
+    a.cf[p][2] = static_cast<float>(c2);
+  }
 }
 
 int run_skewers(lya::SkewerArgs& a, const lya_cosmo* cosmo, const lya_zbins* zb, void* work, size_t work_bytes,

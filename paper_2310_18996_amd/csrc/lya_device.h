@@ -37,12 +37,16 @@ __device__ __forceinline__ float u01(uint32_t w) {
   return (static_cast<float>(w >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
 }
 
-// Box-Muller in FP32: (z1, z2) from the word pair (wa, wb).
+// Box-Muller in FP32: (z1, z2) from the word pair (wa, wb), on the hardware
+// transcendental units: v_log_f32 (log2), v_sqrt_f32, and v_sin_f32/v_cos_f32,
+// which take their argument in revolutions, so sin(2 pi u) is one instruction.
+// On gfx950 these agree with FP64 to ~1.2e-7 relative (log2) and ~1.3e-7
+// absolute (sin, cos) over the uniforms used here.
 __device__ __forceinline__ float2 box_muller(uint32_t wa, uint32_t wb) {
-  const float r = sqrtf(-2.0f * logf(u01(wa)));
-  float s, c;
-  sincospif(2.0f * u01(wb), &s, &c);
-  return make_float2(r * c, r * s);
+  constexpr float kMinus2Ln2 = -1.3862943611198906f;  // -2 ln 2
+  const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u01(wa)));
+  const float t = u01(wb);
+  return make_float2(r * __builtin_amdgcn_cosf(t), r * __builtin_amdgcn_sinf(t));
 }
 
 // Normal pair for linear index lin of a stream.

@@ -15,6 +15,7 @@ constexpr double kZTabH = 0.5;            // Mpc/h spacing of the z(chi) table
 constexpr int kZTabN = 20001;             // covers chi in [0, 10000] Mpc/h
 constexpr int kMaxZBins = 64;
 constexpr int kTw2048 = 2048;             // twiddles for the small-scale 1D FFTs
+constexpr float kFgpaX0 = 3.5f;           // centre (in 1+z) of the FGPA quadratics
 
 struct PkParams {
   double sigma8, ns, gamma, wig_amp, wig_r, wig_kd, smooth;
@@ -60,6 +61,9 @@ void timer_end(hipStream_t st);
     ::lya::timer_end(st);            \
   } while (0)
 
+// Compute units of the current device (cached per device).
+int device_cus();
+
 hipError_t launch_pk_table(const PkParams& p, int n, double dx, TableWork& w, hipStream_t st);
 hipError_t launch_zchi_table(double omega_m, float* ztab, hipStream_t st);
 hipError_t launch_twiddles(float2* tw, int ntw, hipStream_t st);
@@ -85,9 +89,10 @@ struct SkewerArgs {
   double ps_amp, ps_kcut, dpix;
   int ps_fixed_amp;
   uint64_t seed;
-  // FGPA (valid when do_flux)
+  // FGPA (valid when do_flux): a, b, c as quadratics in t = (1+z) - kFgpaX0,
+  // converted on the host in FP64 from the powers of (1+z)
   int do_flux;
-  double coef[3][3];
+  float cf[3][3];
   // pre-FGPA inputs for apply_fgpa (gather skipped when non-null)
   const float* in_dens;
   const float* in_eta;
