@@ -100,7 +100,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="big", choices=["tiny", "mid", "big", "precision", "emulator"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--cpu-n", type=int, default=192)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 4 GiB device copy first (reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path is single-GPU (multi-GPU sharding is "
@@ -141,6 +143,14 @@ def main():
     cosmo = L.Cosmo(cfg["omega_m"])
     fg = L.fgpa_struct(cfg["fgpa"])
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        # a plain copy of known size: 4 GiB read, 4 GiB written
+        src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         L.make_box(box, pk, seed, cfg["f"], True, field, bwork, stream)

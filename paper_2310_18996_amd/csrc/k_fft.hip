@@ -225,6 +225,14 @@ struct Pass {
         const float2 o = make_float2(v[b * R + r].x, zero_b ? 0.0f : v[b * R + r].y);
         if (out_bf16) {
           out_bf16[gi] = pack_bf16x2(o.x, o.y);
+        } else if (KIND == KIND_GENZ) {
+          // nontemporal: the synthesising pass writes lines it never read, and a
+          // plain store first fetches each line into L2 (counter-measured)
+          typedef float f2v __attribute__((ext_vector_type(2)));
+          f2v w;
+          w.x = o.x;
+          w.y = o.y;
+          __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(data + gi));
         } else {
           data[gi] = o;
         }
