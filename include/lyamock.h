@@ -157,6 +157,74 @@ int lya_apply_fgpa(const lya_skewers* sk, const lya_cosmo* cosmo, const float* d
                    const lya_fgpa* fgpa, float* flux, const lya_zbins* zb, void* work, size_t work_bytes,
                    void* stream);
 
+/* 1D flux power spectrum (the statistic the paper's tuning matches, section
+ * "Adjusting mock parameters"; delta_F = F/Fbar - 1 of
+ * equation::definition_delta).  Per skewer the first
+ * N_P = min(2^floor(log2 npix), 2048) pixels (skewers with npix < 2 add
+ * nothing); Fbar of a pixel = fsum/count of its distance bin in `fbar` (pixels
+ * outside the bins take the nearest one; the sums are the output of
+ * lya_draw_skewers / lya_apply_fgpa); velocity pixel
+ * Dv = dpix 100 E(z_ref)/(1+z_ref) km/s for all skewers; P(k_m) = Dv |X_m|^2/N_P
+ * for m = 1..N_P/2, k_m = 2 pi m/(N_P Dv) s/km, summed into bins
+ * k_edges[b] <= k_m < k_edges[b+1].  Outputs (device): psum[b] (FP64 sum of P)
+ * and pcount[b] (modes); mean = psum/pcount.  Deterministic: per-skewer sums
+ * in a fixed order, then a fixed-order sum over skewers. */
+typedef struct {
+  int32_t n_kbins;         /* 1..64 */
+  const double* k_edges;   /* device [n_kbins + 1], s/km, increasing */
+  double z_ref;            /* redshift of the velocity units */
+  double dpix;             /* pixel length, Mpc/h */
+} lya_p1d_spec;
+
+size_t lya_p1d_workspace_size(int64_t n_sk, int32_t n_kbins);
+int lya_p1d(const lya_skewers* sk, const lya_cosmo* cosmo, const float* flux, const lya_zbins* fbar,
+            const lya_p1d_spec* spec, double* psum, int64_t* pcount, void* work, size_t work_bytes, void* stream);
+
+/* FGPA parameter tuning (section "Adjusting mock parameters").  At each tuning
+ * redshift z_t, with c fixed to c_t, (a, b) are chosen to minimise
+ *   chi^2 = ((Fbar - fbar_t)/(s fbar_t))^2 + sum_b ((P_b - P_t,b)/(s P_t,b))^2
+ * (s = sigma_rel, bins with a non-finite target skipped), where Fbar and P_b
+ * (mean P1D of bin b, velocity units at z_t, delta_F = F/Fbar - 1) are measured
+ * on the stored pre-FGPA pixels under constant (a, b, c): the paper's reuse of
+ * saved forests in post-production.  Search: Nelder-Mead in (ln a, ln b) from
+ * (a0, b0), initial steps 0.3, stopping when all vertices lie within xatol
+ * (coordinates) and fatol (chi^2) of the best or after max_evals evaluations.
+ * Mode LYA_TUNE_PLAIN evaluates every point on the GPU; LYA_TUNE_EMULATOR
+ * searches on the emulator's predictions (see lya_emulator_*) and spends one
+ * GPU evaluation per z_t to report the statistics reached.  a(z), b(z), c(z)
+ * are then least-squares quadratics in (1+z).  Synchronous (reads back the
+ * statistics of every evaluation); all GPU work runs on `stream`. */
+#define LYA_TUNE_MAX_Z 16
+enum { LYA_TUNE_PLAIN = 0, LYA_TUNE_EMULATOR = 1 };
+
+typedef struct {
+  const lya_skewers* sk;     /* table of the stored pixels (npix, offset, chi0, dchi used) */
+  const float* dens;         /* device: delta_L + delta_S per pixel */
+  const float* eta;          /* device: eta_par per pixel */
+  lya_cosmo cosmo;
+  int32_t n_zt;              /* 1..16 */
+  double z_t[LYA_TUNE_MAX_Z], c_t[LYA_TUNE_MAX_Z], fbar_t[LYA_TUNE_MAX_Z];
+  const double* p1d_t;       /* host [n_zt][p1d.n_kbins] target mean P1D (NaN: bin unused) */
+  lya_p1d_spec p1d;          /* k bins (device edges) and dpix; z_ref is z_t */
+  double a0, b0;             /* starting point */
+  double sigma_rel;          /* relative error of each statistic (e.g. 0.002) */
+  double xatol, fatol;
+  int32_t max_evals;         /* per z_t */
+  const void* emulator;      /* emulator state (device) for LYA_TUNE_EMULATOR, else NULL */
+} lya_tune_spec;
+
+typedef struct {
+  double a[LYA_TUNE_MAX_Z], b[LYA_TUNE_MAX_Z], chi2[LYA_TUNE_MAX_Z], fbar[LYA_TUNE_MAX_Z];
+  double p1d[LYA_TUNE_MAX_Z * 64];   /* reached mean P1D, [z_t][bin] with row length 64 */
+  int32_t evals[LYA_TUNE_MAX_Z];     /* search evaluations per z_t (GPU or emulator) */
+  double coef[3][3];                 /* a, b, c = sum_i coef[p][i] (1+z)^i */
+  double seconds;                    /* wall time of the call */
+} lya_tune_result;
+
+size_t lya_tune_workspace_size(int64_t n_sk, int32_t n_kbins);
+int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void* work, size_t work_bytes,
+                    void* stream);
+
 /* Kernel timing for benchmarks.  lya_timing_enable(1) clears the records and
  * brackets every kernel the library launches afterwards with two HIP events on
  * the launch stream; lya_timing_enable(0) clears and stops.

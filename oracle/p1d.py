@@ -6,7 +6,7 @@ contrast delta_F = F / Fbar - 1 of equation::definition_delta (section
 "Analysis procedure of forest correlations").  The estimator itself is not
 given in the paper; the reading taken here is a plain periodogram:
 
-* per skewer, the first N_P = 2^floor(log2 n_q) pixels (n_q >= 2);
+* per skewer, the first N_P = min(2^floor(log2 n_q), 2048) pixels (n_q >= 2);
 * delta_F = F / Fbar(bin) - 1, Fbar given per redshift bin (bins in comoving
   distance as for the mean-flux reduction; a pixel outside the bins takes
   the nearest one);
@@ -48,7 +48,7 @@ def p1d(flux, sk, chi_edges, fmean, k_edges, z_ref, dpix, omega_m=cosmology.OMEG
         nq = int(sk["npix"][q])
         if nq < 2:
             continue
-        n_p = 1 << int(np.floor(np.log2(nq)))
+        n_p = min(1 << int(np.floor(np.log2(nq))), 2048)
         o = int(sk["offset"][q])
         F = np.asarray(flux[o:o + n_p], dtype=np.float64)
         b = np.searchsorted(edges, chi_all[o:o + n_p], side="right") - 1

@@ -21,21 +21,12 @@
 // atomic queue and owns a skewer at a time (its small-scale FFT lives in the
 // wave's slice of LDS, so no block-wide barrier is needed per skewer).
 #include "lya_internal.h"
+#include "lya_wavefft.h"
 
 namespace lya {
 
 constexpr int kSkWaves = 4;
 constexpr int kSkNT = 64 * kSkWaves;
-constexpr int kHalfMax = 1024;                        // N_S/2 <= 1024
-constexpr int kHalfBuf = kHalfMax + kHalfMax / 16;    // one padding slot per 16
-
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __global__ void __launch_bounds__(256) k_skewer_reset(unsigned int* queue, unsigned long long* bsum,
                                                       unsigned long long* bcnt) {
@@ -108,47 +99,7 @@ __device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, floa
     }
   }
   wave_sync();
-  // in-place Stockham inverse FFT of length M: every stage first reads all of
-  // the lane's inputs, then writes (the wave executes in lockstep)
-  for (int s = 1; s < M;) {
-    const int R = (M / s >= 4) ? 4 : 2;
-    const int nb = M / R;
-    float2 v[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = lane + 64 * t;
-      if (j < nb) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (r < R) v[t][r] = buf[pidx(j + r * nb)];
-      }
-    }
-    wave_sync();
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int j = lane + 64 * t;
-      if (j < nb) {
-        const int k = j % s;
-        if (s > 1) {
-          const int step = kTw2048 / (s * R);
-#pragma unroll
-          for (int r = 1; r < 4; ++r)
-            if (r < R) v[t][r] = cmul(v[t][r], a.tw2048[r * k * step]);
-        }
-        if (R == 4) {
-          dft4(v[t][0], v[t][1], v[t][2], v[t][3]);
-        } else {
-          dft2(v[t][0], v[t][1]);
-        }
-        const int base = (j / s) * s * R + k;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (r < R) buf[pidx(base + r * s)] = v[t][r];
-      }
-    }
-    wave_sync();
-    s *= R;
-  }
+  wave_ifft(buf, M, a.tw2048, lane);
 }
 
 __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c000, float c001, float c010, float c011,
@@ -160,10 +111,6 @@ __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c00
   const float c0 = c00 + ty * (c01 - c00);
   const float c1 = c10 + ty * (c11 - c10);
   return c0 + tx * (c1 - c0);
-}
-
-__device__ __forceinline__ double pixel_chi(double chi0, int j, double dchi) {
-  return __dsub_rn(chi0, __dmul_rn(static_cast<double>(j), dchi));
 }
 
 __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
@@ -200,15 +147,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
       if (with_ds) small_scale_wave(a, a.id_base + q, ns, buf, lane);
       // bin boundaries: jb[b] = first pixel with chi_j < edges[b] (chi_j decreases with j)
       if (want_bins) {
-        for (int b = lane; b <= a.n_bins; b += 64) {
-          const double e = a.chi_edges[b];
-          double j0 = a.dchi > 0.0 ? ceil((chi0 - e) / a.dchi) : 0.0;
-          j0 = j0 < 0.0 ? 0.0 : (j0 > np ? np : j0);
-          int j = static_cast<int>(j0);
-          while (j < np && pixel_chi(chi0, j, a.dchi) >= e) ++j;
-          while (j > 0 && pixel_chi(chi0, j - 1, a.dchi) < e) --j;
-          jb[b] = j;
-        }
+        bin_bounds(a.chi_edges, a.n_bins, chi0, a.dchi, np, jb, lane);
         wave_sync();
       }
       int64_t ox = 0, oy = 0, oz = 0, sx = 0, sy = 0, sz = 0;

@@ -169,9 +169,129 @@ int run_skewers(lya::SkewerArgs& a, const lya_cosmo* cosmo, const lya_zbins* zb,
   return LYA_OK;
 }
 
+struct PdCarve {
+  size_t sum, cnt, tw, queue, total;
+};
+
+PdCarve carve_p1d(int64_t n_sk, int nk) {
+  PdCarve c{};
+  size_t o = 0;
+  c.sum = o;   o += align256(sizeof(double) * static_cast<size_t>(n_sk) * nk);
+  c.cnt = o;   o += align256(sizeof(int) * static_cast<size_t>(n_sk) * nk);
+  c.tw = o;    o += align256(sizeof(float2) * lya::kTw2048);
+  c.queue = o; o += 256;
+  c.total = o;
+  return c;
+}
+
+// velocity pixel in km/s: dpix 100 E(z)/(1+z), E^2 = Om (1+z)^3 + 1 - Om
+double velocity_pixel(double dpix, double z, double om) {
+  const double x = 1.0 + z;
+  return dpix * (100.0 * sqrt(om * (x * x * x) + (1.0 - om)) / x);
+}
+
+}  // namespace
+
+namespace lya {
+size_t tune_workspace_bytes(int64_t n_sk, int nk);
+int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void* work, size_t work_bytes,
+                hipStream_t st, char* err, size_t errlen);
+int emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t n, float* y, void* work,
+                    size_t work_bytes, hipStream_t st, char* err, size_t errlen);
+}  // namespace lya
+
+namespace {
+int check_tune_spec(const lya_tune_spec* spec) {
+  if (!spec) return fail(LYA_EINVAL, "spec is NULL%s");
+  int rc = check_skewers(spec->sk, false);
+  if (rc) return rc;
+  if (spec->sk->n_sk > 0 && (!spec->dens || !spec->eta)) return fail(LYA_EINVAL, "stored pixels are NULL%s");
+  if (!(spec->cosmo.omega_m >= 0.0 && spec->cosmo.omega_m <= 1.0)) return fail(LYA_EINVAL, "omega_m out of [0,1]%s");
+  if (spec->p1d.n_kbins < 1 || spec->p1d.n_kbins > lya::kMaxKBins || !spec->p1d.k_edges || !(spec->p1d.dpix > 0.0))
+    return fail(LYA_EINVAL, "invalid p1d spec%s");
+  return LYA_OK;
+}
 }  // namespace
 
 extern "C" {
+
+size_t lya_tune_workspace_size(int64_t n_sk, int32_t n_kbins) {
+  if (n_sk < 0 || n_kbins < 1 || n_kbins > lya::kMaxKBins) return 0;
+  return lya::tune_workspace_bytes(n_sk, n_kbins);
+}
+
+int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void* work, size_t work_bytes,
+                    void* stream) {
+  g_err[0] = 0;
+  int rc = check_tune_spec(spec);
+  if (rc) return rc;
+  if (!res || !work) return fail(LYA_EINVAL, "result or work is NULL%s");
+  if (spec->n_zt < 1 || spec->n_zt > LYA_TUNE_MAX_Z || !spec->p1d_t) return fail(LYA_EINVAL, "invalid tuning redshifts%s");
+  if (!(spec->a0 > 0.0) || !(spec->b0 > 0.0) || !(spec->sigma_rel > 0.0) || spec->max_evals < 4)
+    return fail(LYA_EINVAL, "invalid start point, sigma_rel or max_evals%s");
+  if (mode != LYA_TUNE_PLAIN && mode != LYA_TUNE_EMULATOR) return fail(LYA_EINVAL, "unknown tuning mode%s");
+  if (mode == LYA_TUNE_EMULATOR && !spec->emulator) return fail(LYA_EINVAL, "emulator is NULL%s");
+  return lya::tune_params(spec, res, mode, work, work_bytes, static_cast<hipStream_t>(stream), g_err, sizeof(g_err));
+}
+
+int lya_emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t n, float* y, void* work,
+                        size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_tune_spec(spec);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && (!draws || !y)) || !work) return fail(LYA_EINVAL, "invalid label arguments%s");
+  return lya::emulator_labels(spec, draws, n, y, work, work_bytes, static_cast<hipStream_t>(stream), g_err,
+                              sizeof(g_err));
+}
+
+size_t lya_p1d_workspace_size(int64_t n_sk, int32_t n_kbins) {
+  if (n_sk < 0 || n_kbins < 1 || n_kbins > lya::kMaxKBins) return 0;
+  return carve_p1d(n_sk, n_kbins).total;
+}
+
+int lya_p1d(const lya_skewers* sk, const lya_cosmo* cosmo, const float* flux, const lya_zbins* fbar,
+            const lya_p1d_spec* spec, double* psum, int64_t* pcount, void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_skewers(sk, false);
+  if (rc) return rc;
+  if (!cosmo || !(cosmo->omega_m >= 0.0 && cosmo->omega_m <= 1.0)) return fail(LYA_EINVAL, "invalid cosmo%s");
+  if (!spec || spec->n_kbins < 1 || spec->n_kbins > lya::kMaxKBins || !spec->k_edges)
+    return fail(LYA_EINVAL, "invalid p1d spec (1..64 k bins and their edges)%s");
+  if (!(spec->dpix > 0.0) || !(spec->z_ref > -1.0)) return fail(LYA_EINVAL, "invalid dpix or z_ref%s");
+  if (!fbar || fbar->n_bins < 1 || fbar->n_bins > lya::kMaxZBins || !fbar->chi_edges || !fbar->fsum || !fbar->count)
+    return fail(LYA_EINVAL, "mean-flux bins (1..64 with sums and counts) are required%s");
+  if (sk->n_sk > 0 && !flux) return fail(LYA_EINVAL, "flux is NULL%s");
+  if (!psum && !pcount) return fail(LYA_EINVAL, "no output%s");
+  const PdCarve c = carve_p1d(sk->n_sk, spec->n_kbins);
+  if (!work) return fail(LYA_EINVAL, "work is NULL%s");
+  if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the 1D power%s");
+  char* w = static_cast<char*>(work);
+  lya::P1dArgs a{};
+  a.n_sk = sk->n_sk;
+  a.npix = sk->npix;
+  a.offset = sk->offset;
+  a.chi0 = sk->chi0;
+  a.dchi = sk->dchi;
+  a.flux = flux;
+  a.n_fbins = fbar->n_bins;
+  a.chi_edges = fbar->chi_edges;
+  a.fsum = fbar->fsum;
+  a.fcount = fbar->count;
+  a.n_kbins = spec->n_kbins;
+  a.k_edges = spec->k_edges;
+  a.dv = velocity_pixel(spec->dpix, spec->z_ref, cosmo->omega_m);
+  a.part_sum = reinterpret_cast<double*>(w + c.sum);
+  a.part_cnt = reinterpret_cast<int*>(w + c.cnt);
+  a.tw2048 = reinterpret_cast<float2*>(w + c.tw);
+  a.queue = reinterpret_cast<unsigned int*>(w + c.queue);
+  a.chunk = 4;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = lya::launch_twiddles(const_cast<float2*>(a.tw2048), lya::kTw2048, st);
+  if (e != hipSuccess) return hip_fail(e, "twiddles");
+  e = lya::launch_p1d(a, psum, pcount, st);
+  if (e != hipSuccess) return hip_fail(e, "1D power kernel");
+  return LYA_OK;
+}
 
 const char* lya_last_error(void) { return g_err; }
 

@@ -116,4 +116,36 @@ struct SkewerArgs {
 
 hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st);
 
+// 1D flux power spectrum.
+constexpr int kMaxKBins = 64;
+struct P1dArgs {
+  int64_t n_sk;
+  const int32_t* npix;
+  const int64_t* offset;
+  const double* chi0;
+  double dchi;
+  const float* flux;         // or null: F from dens/eta under constant (fa, fb, fc)
+  const float* dens;
+  const float* eta;
+  float fa, fb, fc;
+  int n_fbins;               // mean-flux bins in comoving distance
+  const double* chi_edges;   // [n_fbins + 1]
+  const double* fsum;        // [n_fbins]
+  const int64_t* fcount;     // [n_fbins]
+  int n_kbins;
+  const double* k_edges;     // [n_kbins + 1], s/km
+  double dv;                 // velocity pixel, km/s
+  double* part_sum;          // workspace [n_sk][n_kbins]
+  int* part_cnt;             // workspace [n_sk][n_kbins]
+  const float2* tw2048;
+  unsigned int* queue;
+  int chunk;
+};
+hipError_t launch_p1d(const P1dArgs& a, double* psum, int64_t* pcount, hipStream_t st);
+
+// Tuning (lya_tune.hip) and the emulator used by it (lya_mlp.hip).
+size_t emulator_eval_bytes();
+hipError_t emulator_predict(const void* emu, double a, double b, double c, double z, double* fbar, double* pk,
+                            int nk, char* scratch, hipStream_t st);
+
 }  // namespace lya

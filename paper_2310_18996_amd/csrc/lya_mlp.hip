@@ -1,0 +1,598 @@
+// Tuning emulator: a 4 -> 256 -> 256 -> 256 -> n_out MLP (GELU hidden layers,
+// linear output) mapping FGPA parameters and redshift (a, b, c, z) to the
+// statistics the tuning loop matches (mean flux and ln P1D per k bin).
+// Training: MSE on standardised inputs and outputs, Adam (Kingma & Ba 2014),
+// FP32 master weights; the matrix products run on MFMA in bfloat16 with FP32
+// accumulation (v_mfma_f32_16x16x16_bf16), or in plain FP32 for checks.
+// Row-vector convention: h = gelu(x W + b), W stored [in][out] row-major.
+// GELU is the exact form x Phi(x) = x erfc(-x / sqrt 2) / 2.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/lyamock.h"
+#include "lya_internal.h"
+
+namespace lya {
+
+constexpr int kIn = 4, kHid = 256, kMaxOut = 64;
+
+struct EmuHeader {
+  int32_t n_out;
+  int32_t step;  // Adam steps taken
+  int32_t log_from;
+  int32_t pad0;
+  float in_lo[4], in_hi[4];
+  float out_mean[kMaxOut], out_std[kMaxOut], out_mask[kMaxOut];
+};
+constexpr size_t kHeaderBytes = 2048;
+static_assert(sizeof(EmuHeader) <= kHeaderBytes, "header");
+
+__host__ __device__ inline size_t n_params(int n_out) {
+  return static_cast<size_t>(kIn) * kHid + kHid + 2 * (static_cast<size_t>(kHid) * kHid + kHid) +
+         static_cast<size_t>(kHid) * n_out + n_out;
+}
+
+struct Offs {
+  size_t W[4], b[4];
+};
+__host__ __device__ inline Offs param_offsets(int n_out) {
+  Offs o;
+  size_t p = 0;
+  const int fin[4] = {kIn, kHid, kHid, kHid};
+  const int fout[4] = {kHid, kHid, kHid, n_out};
+  for (int l = 0; l < 4; ++l) {
+    o.W[l] = p;
+    p += static_cast<size_t>(fin[l]) * fout[l];
+    o.b[l] = p;
+    p += fout[l];
+  }
+  return o;
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * erfcf(-x * 0.70710678118654752f); }
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * erfcf(-x * 0.70710678118654752f) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// ---------------------------------------------------------------- init
+__global__ void __launch_bounds__(256) k_emu_init(float* params, float* m, float* v, int n_out, uint64_t seed) {
+  const Offs o = param_offsets(n_out);
+  const size_t np = n_params(n_out);
+  const int fin[4] = {kIn, kHid, kHid, kHid};
+  for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < np; i += static_cast<size_t>(gridDim.x) * 256) {
+    int l = 3;
+    while (l > 0 && i < o.W[l]) --l;
+    float val = 0.0f;
+    if (i < o.b[l]) {  // weight of layer l: He normal, std sqrt(2 / fan_in)
+      const float2 z = normal_pair(seed, 3u, static_cast<uint64_t>(i) << 1);
+      val = z.x * sqrtf(2.0f / fin[l]);
+    }
+    params[i] = val;
+    m[i] = 0.0f;
+    v[i] = 0.0f;
+  }
+}
+
+// per output column: mean and std over the labels (ln for columns >= log_from),
+// mask 0 if any label is not finite; one block per column, fixed-order FP64 sums
+__global__ void __launch_bounds__(256) k_emu_stats(const float* __restrict__ y, int64_t n, int n_out, int log_from,
+                                                   EmuHeader* h) {
+  __shared__ double s1[256], s2[256];
+  __shared__ int sbad[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  int bad = 0;
+  for (int64_t i = t; i < n; i += 256) {
+    float v = y[i * n_out + c];
+    if (c >= log_from) v = logf(v);
+    if (!isfinite(v)) {
+      bad = 1;
+      continue;
+    }
+    a += v;
+    b += static_cast<double>(v) * v;
+  }
+  s1[t] = a;
+  s2[t] = b;
+  sbad[t] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      s1[t] += s1[t + w];
+      s2[t] += s2[t + w];
+      sbad[t] |= sbad[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double mean = s1[0] / static_cast<double>(n);
+    const double var = s2[0] / static_cast<double>(n) - mean * mean;
+    h->out_mean[c] = static_cast<float>(mean);
+    h->out_std[c] = static_cast<float>(var > 1e-30 ? sqrt(var) : 1.0);
+    h->out_mask[c] = sbad[0] ? 0.0f : 1.0f;
+  }
+}
+
+// training batch of step s: rows (s B + i) mod n, standardised
+__global__ void __launch_bounds__(256) k_emu_gather(const float* __restrict__ x, const float* __restrict__ y, int64_t n,
+                                                    int64_t s, int B, const EmuHeader* __restrict__ h, float* x0,
+                                                    float* tgt) {
+  const int n_out = h->n_out;
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < B * (kIn + n_out); k += gridDim.x * 256) {
+    const int i = k / (kIn + n_out), c = k % (kIn + n_out);
+    const int64_t r = (s * B + i) % n;
+    if (c < kIn) {
+      x0[i * kIn + c] = 2.0f * (x[r * kIn + c] - h->in_lo[c]) / (h->in_hi[c] - h->in_lo[c]) - 1.0f;
+    } else {
+      const int o = c - kIn;
+      float v = y[r * n_out + o];
+      if (o >= h->log_from) v = logf(v);
+      v = (v - h->out_mean[o]) / h->out_std[o];
+      tgt[i * n_out + o] = (h->out_mask[o] > 0.0f && isfinite(v)) ? v : 0.0f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- GEMM
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+
+// C = op(A) op(B) with epilogue.  op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k],
+// op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n].  EPI_BIAS_GELU also writes the
+// pre-activation to aux; EPI_GELU_GRAD multiplies by gelu'(aux).
+__device__ __forceinline__ float epilogue(int epi, float acc, int m, int n, const float* bias, float* aux, int ldaux,
+                                          float& out_aux) {
+  (void)out_aux;
+  if (epi == EPI_BIAS) return acc + bias[n];
+  if (epi == EPI_BIAS_GELU) {
+    const float zv = acc + bias[n];
+    aux[static_cast<size_t>(m) * ldaux + n] = zv;
+    return gelu(zv);
+  }
+  if (epi == EPI_GELU_GRAD) return acc * gelu_grad(aux[static_cast<size_t>(m) * ldaux + n]);
+  return acc;
+}
+
+// FP32 reference product: one output per thread
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_f32(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                  const float* __restrict__ B, int ldb, float* C, int ldc,
+                                                  const float* bias, int epi, float* aux, int ldaux) {
+  const int64_t id = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (id >= static_cast<int64_t>(M) * N) return;
+  const int m = static_cast<int>(id / N), n = static_cast<int>(id % N);
+  float acc = 0.0f;
+  for (int k = 0; k < K; ++k) {
+    const float a = TA ? A[static_cast<size_t>(k) * lda + m] : A[static_cast<size_t>(m) * lda + k];
+    const float b = TB ? B[static_cast<size_t>(n) * ldb + k] : B[static_cast<size_t>(k) * ldb + n];
+    acc = fmaf(a, b, acc);
+  }
+  float dummy;
+  C[static_cast<size_t>(m) * ldc + n] = epilogue(epi, acc, m, n, bias, aux, ldaux, dummy);
+}
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<unsigned short>(u >> 16);
+}
+
+// 64x64 output tile per block of 4 waves (2x2, 32x32 each = 2x2 MFMA 16x16
+// tiles); K in steps of 16 through LDS in bfloat16.  MFMA 16x16x16 operand
+// layout: lane l supplies A rows (l % 16), k = 4 (l / 16) .. +3, and B columns
+// (l % 16), k = 4 (l / 16) .. +3; result element r of lane l is row
+// 4 (l / 16) + r, column l % 16.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                   const float* __restrict__ B, int ldb, float* C, int ldc,
+                                                   const float* bias, int epi, float* aux, int ldaux) {
+  __shared__ unsigned short As[64][16 + 4];
+  __shared__ unsigned short Bs[16][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  v4f32 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f32{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + 256 * e;  // 0..1023
+      {
+        const int mm = idx / 16, kk = idx % 16;
+        const int m = m0 + mm, k = k0 + kk;
+        float v = 0.0f;
+        if (m < M && k < K) v = TA ? A[static_cast<size_t>(k) * lda + m] : A[static_cast<size_t>(m) * lda + k];
+        As[mm][kk] = to_bf16(v);
+      }
+      {
+        const int kk = idx / 64, nn = idx % 64;
+        const int k = k0 + kk, n = n0 + nn;
+        float v = 0.0f;
+        if (n < N && k < K) v = TB ? B[static_cast<size_t>(n) * ldb + k] : B[static_cast<size_t>(k) * ldb + n];
+        Bs[kk][nn] = to_bf16(v);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      v4i16 af;
+      const int r = wm + 16 * i + (lane & 15), kb = 4 * (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) af[q] = static_cast<short>(As[r][kb + q]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        v4i16 bfr;
+        const int cidx = wn + 16 * j + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bfr[q] = static_cast<short>(Bs[kb + q][cidx]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bfr, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + 16 * j + (lane & 15);
+        if (m < M && n < N) {
+          float dummy;
+          C[static_cast<size_t>(m) * ldc + n] = epilogue(epi, acc[i][j][r], m, n, bias, aux, ldaux, dummy);
+        }
+      }
+}
+
+template <bool TA, bool TB>
+hipError_t gemm(bool bf16, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+                const float* bias, int epi, float* aux, int ldaux, hipStream_t st) {
+  if (bf16) {
+    hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, M, N, K, A, lda,
+                       B, ldb, C, ldc, bias, epi, aux, ldaux);
+  } else {
+    const int64_t tot = static_cast<int64_t>(M) * N;
+    hipLaunchKernelGGL((k_gemm_f32<TA, TB>), dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, M, N,
+                       K, A, lda, B, ldb, C, ldc, bias, epi, aux, ldaux);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- loss, bias grads, Adam
+// dY = 2 (Y - T) mask / (B n_eff); loss partial sums (FP64, one block)
+__global__ void __launch_bounds__(256) k_emu_dloss(const float* __restrict__ y, const float* __restrict__ t, int B,
+                                                   const EmuHeader* __restrict__ h, float* dy, float* loss) {
+  __shared__ double sl[256];
+  const int n_out = h->n_out;
+  float neff = 0.0f;
+  for (int o = 0; o < n_out; ++o) neff += h->out_mask[o];
+  const float scale = 2.0f / (static_cast<float>(B) * (neff > 0.0f ? neff : 1.0f));
+  double l = 0.0;
+  for (int k = threadIdx.x; k < B * n_out; k += 256) {
+    const int o = k % n_out;
+    const float d = (y[k] - t[k]) * h->out_mask[o];
+    dy[k] = scale * d;
+    l += static_cast<double>(d) * d;
+  }
+  sl[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sl[threadIdx.x] += sl[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) loss[0] = static_cast<float>(sl[0] / (static_cast<double>(B) * (neff > 0 ? neff : 1)));
+}
+
+// db[n] = sum over rows of d[m][n] (fixed order per column)
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ d, int M, int N, float* db) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int m = 0; m < M; ++m) s += d[static_cast<size_t>(m) * N + n];
+  db[n] = s;
+}
+
+__global__ void __launch_bounds__(256) k_adam(float* p, float* m, float* v, const float* __restrict__ g, size_t np,
+                                              float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < np; i += static_cast<size_t>(gridDim.x) * 256) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------- small-batch FP32 forward (prediction)
+// one block per group of up to 8 samples: each thread owns one hidden unit;
+// outputs are un-standardised (exp for columns >= log_from)
+__global__ void __launch_bounds__(256) k_emu_predict(const EmuHeader* __restrict__ h, const float* __restrict__ params,
+                                                     const float* __restrict__ x, int64_t n, float* y) {
+  __shared__ float hs[2][8][kHid];
+  const int n_out = h->n_out;
+  const Offs o = param_offsets(n_out);
+  const int t = threadIdx.x;
+  const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 8;
+  const int ns = n - s0 < 8 ? static_cast<int>(n - s0) : 8;
+  float acc[8];
+  // layer 1
+  for (int s = 0; s < ns; ++s) {
+    float a = params[o.b[0] + t];
+    for (int i = 0; i < kIn; ++i) {
+      const float u = 2.0f * (x[(s0 + s) * kIn + i] - h->in_lo[i]) / (h->in_hi[i] - h->in_lo[i]) - 1.0f;
+      a = fmaf(u, params[o.W[0] + i * kHid + t], a);
+    }
+    hs[0][s][t] = gelu(a);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int l = 1; l < 3; ++l) {
+    for (int s = 0; s < ns; ++s) acc[s] = params[o.b[l] + t];
+    for (int k = 0; k < kHid; ++k) {
+      const float w = params[o.W[l] + static_cast<size_t>(k) * kHid + t];
+      for (int s = 0; s < ns; ++s) acc[s] = fmaf(hs[cur][s][k], w, acc[s]);
+    }
+    for (int s = 0; s < ns; ++s) hs[cur ^ 1][s][t] = gelu(acc[s]);
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (t < n_out) {
+    for (int s = 0; s < ns; ++s) acc[s] = params[o.b[3] + t];
+    for (int k = 0; k < kHid; ++k) {
+      const float w = params[o.W[3] + static_cast<size_t>(k) * n_out + t];
+      for (int s = 0; s < ns; ++s) acc[s] = fmaf(hs[cur][s][k], w, acc[s]);
+    }
+    for (int s = 0; s < ns; ++s) {
+      float v = acc[s] * h->out_std[t] + h->out_mean[t];
+      if (t >= h->log_from) v = expf(v);
+      y[(s0 + s) * n_out + t] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host side
+struct TrainBufs {
+  float *x0, *tgt, *z[3], *hh[3], *y, *dy, *dz[3], *grad, *loss;
+  size_t total;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+static TrainBufs carve_train(char* w, int B, int n_out) {
+  TrainBufs t{};
+  size_t o = 0;
+  auto take = [&](size_t nfloat) {
+    float* p = w ? reinterpret_cast<float*>(w + o) : nullptr;
+    o += al(nfloat * sizeof(float));
+    return p;
+  };
+  t.x0 = take(static_cast<size_t>(B) * kIn);
+  t.tgt = take(static_cast<size_t>(B) * n_out);
+  for (int l = 0; l < 3; ++l) {
+    t.z[l] = take(static_cast<size_t>(B) * kHid);
+    t.hh[l] = take(static_cast<size_t>(B) * kHid);
+    t.dz[l] = take(static_cast<size_t>(B) * kHid);
+  }
+  t.y = take(static_cast<size_t>(B) * n_out);
+  t.dy = take(static_cast<size_t>(B) * n_out);
+  t.grad = take(n_params(n_out));
+  t.loss = take(1);
+  t.total = o;
+  return t;
+}
+
+// Forward and backward of one batch (x0, tgt already standardised); gradients
+// into t.grad, loss into t.loss.
+static hipError_t emu_fwd_bwd(const EmuHeader* h_dev, const float* params, int n_out, int B, bool bf16,
+                              const TrainBufs& t, hipStream_t st) {
+  const Offs o = param_offsets(n_out);
+  hipError_t e;
+  // forward
+  if ((e = gemm<false, false>(false, B, kHid, kIn, t.x0, kIn, params + o.W[0], kHid, t.hh[0], kHid, params + o.b[0],
+                              EPI_BIAS_GELU, t.z[0], kHid, st)) != hipSuccess) return e;
+  for (int l = 1; l < 3; ++l)
+    if ((e = gemm<false, false>(bf16, B, kHid, kHid, t.hh[l - 1], kHid, params + o.W[l], kHid, t.hh[l], kHid,
+                                params + o.b[l], EPI_BIAS_GELU, t.z[l], kHid, st)) != hipSuccess) return e;
+  if ((e = gemm<false, false>(bf16, B, n_out, kHid, t.hh[2], kHid, params + o.W[3], n_out, t.y, n_out,
+                              params + o.b[3], EPI_BIAS, nullptr, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_emu_dloss, dim3(1), dim3(256), 0, st, t.y, t.tgt, B, h_dev, t.dy, t.loss);
+  // backward: output layer
+  if ((e = gemm<true, false>(bf16, kHid, n_out, B, t.hh[2], kHid, t.dy, n_out, t.grad + o.W[3], n_out, nullptr,
+                             EPI_STORE, nullptr, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3((n_out + 255) / 256), dim3(256), 0, st, t.dy, B, n_out, t.grad + o.b[3]);
+  // dZ3 = (dY W4^T) * gelu'(Z3)
+  if ((e = gemm<false, true>(bf16, B, kHid, n_out, t.dy, n_out, params + o.W[3], n_out, t.dz[2], kHid, nullptr,
+                             EPI_GELU_GRAD, t.z[2], kHid, st)) != hipSuccess) return e;
+  for (int l = 2; l >= 1; --l) {
+    if ((e = gemm<true, false>(bf16, kHid, kHid, B, t.hh[l - 1], kHid, t.dz[l], kHid, t.grad + o.W[l], kHid, nullptr,
+                               EPI_STORE, nullptr, 0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, t.dz[l], B, kHid, t.grad + o.b[l]);
+    if ((e = gemm<false, true>(bf16, B, kHid, kHid, t.dz[l], kHid, params + o.W[l], kHid, t.dz[l - 1], kHid, nullptr,
+                               EPI_GELU_GRAD, t.z[l - 1], kHid, st)) != hipSuccess) return e;
+  }
+  if ((e = gemm<true, false>(false, kIn, kHid, B, t.x0, kIn, t.dz[0], kHid, t.grad + o.W[0], kHid, nullptr,
+                             EPI_STORE, nullptr, 0, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, t.dz[0], B, kHid, t.grad + o.b[0]);
+  return hipGetLastError();
+}
+
+size_t emulator_bytes(int n_out) { return kHeaderBytes + 3 * al(n_params(n_out) * sizeof(float)); }
+static float* emu_params(void* emu) { return reinterpret_cast<float*>(static_cast<char*>(emu) + kHeaderBytes); }
+static const float* emu_params(const void* emu) {
+  return reinterpret_cast<const float*>(static_cast<const char*>(emu) + kHeaderBytes);
+}
+
+size_t emulator_eval_bytes() { return 256 + 64 * sizeof(float) * 2; }
+
+// one prediction for the tuning search: (a, b, c, z) -> Fbar, P1D[nk]
+hipError_t emulator_predict(const void* emu, double a, double b, double c, double z, double* fbar, double* pk, int nk,
+                            char* scratch, hipStream_t st) {
+  if (!emu) return hipErrorInvalidValue;
+  float hx[4] = {static_cast<float>(a), static_cast<float>(b), static_cast<float>(c), static_cast<float>(z)};
+  float* dx = reinterpret_cast<float*>(scratch);
+  float* dy = dx + 64;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(dx, hx, sizeof(hx), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_emu_predict, dim3(1), dim3(256), 0, st, static_cast<const EmuHeader*>(emu), emu_params(emu),
+                     dx, int64_t(1), dy);
+  float hy[kMaxOut];
+  if ((e = hipMemcpyAsync(hy, dy, sizeof(float) * (nk + 1), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  *fbar = hy[0];
+  for (int i = 0; i < nk; ++i) pk[i] = hy[1 + i];
+  return hipGetLastError();
+}
+
+}  // namespace lya
+
+// ---------------------------------------------------------------- C-ABI
+namespace {
+thread_local char g_emu_err[256] = "";
+int efail(int code, const char* msg) {
+  snprintf(g_emu_err, sizeof(g_emu_err), "%s", msg);
+  return code;
+}
+}  // namespace
+
+extern "C" {
+
+const char* lya_emulator_last_error(void) { return g_emu_err; }
+
+size_t lya_emulator_bytes(int32_t n_out) {
+  if (n_out < 1 || n_out > lya::kMaxOut) return 0;
+  return lya::emulator_bytes(n_out);
+}
+
+size_t lya_emulator_param_offset(void) { return lya::kHeaderBytes; }
+size_t lya_emulator_param_count(int32_t n_out) {
+  return (n_out < 1 || n_out > lya::kMaxOut) ? 0 : lya::n_params(n_out);
+}
+
+int lya_emulator_init(void* emu, int32_t n_out, int32_t log_from, uint64_t seed, const double in_lo[4],
+                      const double in_hi[4], void* stream) {
+  if (!emu || n_out < 1 || n_out > lya::kMaxOut || !in_lo || !in_hi || log_from < 0)
+    return efail(LYA_EINVAL, "invalid emulator arguments");
+  for (int i = 0; i < 4; ++i)
+    if (!(in_hi[i] > in_lo[i])) return efail(LYA_EINVAL, "input ranges must be increasing");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  lya::EmuHeader h{};
+  h.n_out = n_out;
+  h.log_from = log_from;
+  for (int i = 0; i < 4; ++i) {
+    h.in_lo[i] = static_cast<float>(in_lo[i]);
+    h.in_hi[i] = static_cast<float>(in_hi[i]);
+  }
+  for (int o = 0; o < lya::kMaxOut; ++o) {
+    h.out_mean[o] = 0.0f;
+    h.out_std[o] = 1.0f;
+    h.out_mask[o] = o < n_out ? 1.0f : 0.0f;
+  }
+  hipError_t e = hipMemcpyAsync(emu, &h, sizeof(h), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return efail(LYA_EHIP, hipGetErrorString(e));
+  const size_t np = lya::n_params(n_out);
+  float* p = lya::emu_params(emu);
+  const size_t stride = lya::al(np * sizeof(float)) / sizeof(float);
+  hipLaunchKernelGGL(lya::k_emu_init, dim3(256), dim3(256), 0, st, p, p + stride, p + 2 * stride, n_out, seed);
+  e = hipGetLastError();
+  if (e != hipSuccess) return efail(LYA_EHIP, hipGetErrorString(e));
+  return LYA_OK;
+}
+
+size_t lya_emulator_train_workspace_size(int32_t batch, int32_t n_out) {
+  if (batch < 1 || n_out < 1 || n_out > lya::kMaxOut) return 0;
+  return lya::carve_train(nullptr, batch, n_out).total;
+}
+
+int lya_emulator_set_scaling(void* emu, const float* y, int64_t n, void* stream) {
+  if (!emu || !y || n < 1) return efail(LYA_EINVAL, "invalid scaling arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  lya::EmuHeader h;
+  hipError_t e = hipMemcpyAsync(&h, emu, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return efail(LYA_EHIP, hipGetErrorString(e));
+  hipLaunchKernelGGL(lya::k_emu_stats, dim3(h.n_out), dim3(256), 0, st, y, n, h.n_out, h.log_from,
+                     static_cast<lya::EmuHeader*>(emu));
+  e = hipGetLastError();
+  return e == hipSuccess ? LYA_OK : efail(LYA_EHIP, hipGetErrorString(e));
+}
+
+int lya_emulator_loss_grad(const void* emu, const float* x0, const float* t, int32_t batch, int32_t use_bf16,
+                           float* grad, float* loss, void* work, size_t work_bytes, void* stream) {
+  if (!emu || !x0 || !t || batch < 1 || !grad) return efail(LYA_EINVAL, "invalid gradient arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  lya::EmuHeader h;
+  hipError_t e = hipMemcpyAsync(&h, emu, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return efail(LYA_EHIP, hipGetErrorString(e));
+  lya::TrainBufs tb = lya::carve_train(static_cast<char*>(work), batch, h.n_out);
+  if (!work || work_bytes < tb.total) return efail(LYA_EWORKSPACE, "workspace too small for the emulator batch");
+  const size_t np = lya::n_params(h.n_out);
+  e = hipMemcpyAsync(tb.x0, x0, sizeof(float) * batch * lya::kIn, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(tb.tgt, t, sizeof(float) * batch * h.n_out, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = lya::emu_fwd_bwd(static_cast<const lya::EmuHeader*>(emu), lya::emu_params(emu), h.n_out, batch, use_bf16 != 0,
+                         tb, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(grad, tb.grad, sizeof(float) * np, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, tb.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+  return e == hipSuccess ? LYA_OK : efail(LYA_EHIP, hipGetErrorString(e));
+}
+
+int lya_emulator_train(void* emu, const float* x, const float* y, int64_t n, int32_t steps, int32_t batch,
+                       double lr, int32_t use_bf16, float* loss_hist, void* work, size_t work_bytes, void* stream) {
+  if (!emu || !x || !y || n < 1 || steps < 0 || batch < 1 || !(lr > 0.0))
+    return efail(LYA_EINVAL, "invalid training arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  lya::EmuHeader h;
+  hipError_t e = hipMemcpyAsync(&h, emu, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return efail(LYA_EHIP, hipGetErrorString(e));
+  lya::TrainBufs tb = lya::carve_train(static_cast<char*>(work), batch, h.n_out);
+  if (!work || work_bytes < tb.total) return efail(LYA_EWORKSPACE, "workspace too small for the emulator batch");
+  const size_t np = lya::n_params(h.n_out);
+  float* p = lya::emu_params(emu);
+  const size_t stride = lya::al(np * sizeof(float)) / sizeof(float);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  int step = h.step;
+  for (int s = 0; s < steps; ++s) {
+    hipLaunchKernelGGL(lya::k_emu_gather, dim3(64), dim3(256), 0, st, x, y, n, static_cast<int64_t>(step), batch,
+                       static_cast<const lya::EmuHeader*>(emu), tb.x0, tb.tgt);
+    e = lya::emu_fwd_bwd(static_cast<const lya::EmuHeader*>(emu), p, h.n_out, batch, use_bf16 != 0, tb, st);
+    if (e != hipSuccess) return efail(LYA_EHIP, hipGetErrorString(e));
+    ++step;
+    const float bc1 = 1.0f - powf(b1, static_cast<float>(step));
+    const float bc2 = 1.0f - powf(b2, static_cast<float>(step));
+    hipLaunchKernelGGL(lya::k_adam, dim3(512), dim3(256), 0, st, p, p + stride, p + 2 * stride, tb.grad, np,
+                       static_cast<float>(lr), b1, b2, eps, bc1, bc2);
+    if (loss_hist) {
+      e = hipMemcpyAsync(loss_hist + s, tb.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return efail(LYA_EHIP, hipGetErrorString(e));
+    }
+  }
+  e = hipMemcpyAsync(reinterpret_cast<char*>(emu) + offsetof(lya::EmuHeader, step), &step, sizeof(step),
+                     hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipGetLastError();
+  return e == hipSuccess ? LYA_OK : efail(LYA_EHIP, hipGetErrorString(e));
+}
+
+int lya_emulator_predict(const void* emu, const float* x, int64_t n, float* y, void* stream) {
+  if (!emu || !x || !y || n < 0) return efail(LYA_EINVAL, "invalid prediction arguments");
+  if (n == 0) return LYA_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(lya::k_emu_predict, dim3(static_cast<unsigned>((n + 7) / 8)), dim3(256), 0, st,
+                     static_cast<const lya::EmuHeader*>(emu), lya::emu_params(emu), x, n, y);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LYA_OK : efail(LYA_EHIP, hipGetErrorString(e));
+}
+
+}  // extern "C"

@@ -1,0 +1,417 @@
+// FGPA parameter tuning (section "Adjusting mock parameters"): host-side FP64
+// Nelder-Mead over (ln a, ln b) at each tuning redshift z_t with c fixed,
+// driving GPU evaluations of the mean flux and the 1D power of the stored
+// pre-FGPA pixels under constant (a, b, c) (the paper's post-production reuse
+// of saved forests), then least-squares quadratics in (1+z).  The emulator
+// mode runs the same search on the MLP's predictions and spends one GPU
+// evaluation per redshift to report the statistics actually reached.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "../../include/lyamock.h"
+#include "lya_internal.h"
+
+namespace lya {
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+struct TuneCarve {
+  size_t edges, fsum, fcnt, psum, pcnt, ztab, tw, queue, bsum, bcnt, part_sum, part_cnt, emu, total;
+};
+
+TuneCarve carve_tune(int64_t n_sk, int nk) {
+  TuneCarve c{};
+  size_t o = 0;
+  c.edges = o;    o += 256;
+  c.fsum = o;     o += 256;
+  c.fcnt = o;     o += 256;
+  c.psum = o;     o += al256(sizeof(double) * kMaxKBins);
+  c.pcnt = o;     o += al256(sizeof(int64_t) * kMaxKBins);
+  c.ztab = o;     o += al256(sizeof(float) * kZTabN);
+  c.tw = o;       o += al256(sizeof(float2) * kTw2048);
+  c.queue = o;    o += 256;
+  c.bsum = o;     o += al256(sizeof(unsigned long long) * kMaxZBins);
+  c.bcnt = o;     o += al256(sizeof(unsigned long long) * kMaxZBins);
+  c.part_sum = o; o += al256(sizeof(double) * static_cast<size_t>(n_sk) * nk);
+  c.part_cnt = o; o += al256(sizeof(int) * static_cast<size_t>(n_sk) * nk);
+  c.emu = o;      o += al256(emulator_eval_bytes());
+  c.total = o;
+  return c;
+}
+
+struct Evaluator {
+  const lya_tune_spec* spec;
+  char* w;
+  TuneCarve c;
+  hipStream_t st;
+  int nk;
+  double* h_stats;  // pinned-free host staging: fsum, fcnt, psum[nk], pcnt[nk]
+
+  // Mean flux and mean P1D per bin of the stored pixels under constant (a, b, c).
+  hipError_t eval(double a, double b, double cc, double z, double* fbar, double* pk) {
+    const lya_skewers* sk = spec->sk;
+    SkewerArgs sa{};
+    sa.n_sk = sk->n_sk;
+    sa.npix = sk->npix;
+    sa.offset = sk->offset;
+    sa.chi0 = sk->chi0;
+    sa.dchi = sk->dchi;
+    sa.n = 32;
+    sa.in_dens = spec->dens;
+    sa.in_eta = spec->eta;
+    sa.do_flux = 1;
+    sa.cf[0][0] = static_cast<float>(a);
+    sa.cf[1][0] = static_cast<float>(b);
+    sa.cf[2][0] = static_cast<float>(cc);
+    sa.n_bins = 1;
+    sa.chi_edges = reinterpret_cast<const double*>(w + c.edges);
+    sa.bin_sum = reinterpret_cast<unsigned long long*>(w + c.bsum);
+    sa.bin_cnt = reinterpret_cast<unsigned long long*>(w + c.bcnt);
+    sa.out_fsum = reinterpret_cast<double*>(w + c.fsum);
+    sa.out_count = reinterpret_cast<int64_t*>(w + c.fcnt);
+    sa.ztab = reinterpret_cast<const float*>(w + c.ztab);
+    sa.tw2048 = reinterpret_cast<const float2*>(w + c.tw);
+    sa.queue = reinterpret_cast<unsigned int*>(w + c.queue);
+    sa.chunk = 8;
+    hipError_t e = launch_skewers(sa, st);
+    if (e != hipSuccess) return e;
+    P1dArgs pa{};
+    pa.n_sk = sk->n_sk;
+    pa.npix = sk->npix;
+    pa.offset = sk->offset;
+    pa.chi0 = sk->chi0;
+    pa.dchi = sk->dchi;
+    pa.dens = spec->dens;
+    pa.eta = spec->eta;
+    pa.fa = sa.cf[0][0];
+    pa.fb = sa.cf[1][0];
+    pa.fc = sa.cf[2][0];
+    pa.n_fbins = 1;
+    pa.chi_edges = sa.chi_edges;
+    pa.fsum = sa.out_fsum;
+    pa.fcount = sa.out_count;
+    pa.n_kbins = nk;
+    pa.k_edges = spec->p1d.k_edges;
+    const double x = 1.0 + z, om = spec->cosmo.omega_m;
+    pa.dv = spec->p1d.dpix * (100.0 * sqrt(om * (x * x * x) + (1.0 - om)) / x);
+    pa.part_sum = reinterpret_cast<double*>(w + c.part_sum);
+    pa.part_cnt = reinterpret_cast<int*>(w + c.part_cnt);
+    pa.tw2048 = sa.tw2048;
+    pa.queue = sa.queue;
+    pa.chunk = 4;
+    double* d_psum = reinterpret_cast<double*>(w + c.psum);
+    int64_t* d_pcnt = reinterpret_cast<int64_t*>(w + c.pcnt);
+    if ((e = launch_p1d(pa, d_psum, d_pcnt, st)) != hipSuccess) return e;
+    double* h = h_stats;
+    if ((e = hipMemcpyAsync(h, w + c.fsum, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h + 1, w + c.fcnt, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h + 2, d_psum, sizeof(double) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h + 2 + nk, d_pcnt, sizeof(int64_t) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    int64_t fc;
+    memcpy(&fc, h + 1, sizeof(fc));
+    *fbar = fc > 0 ? h[0] / static_cast<double>(fc) : NAN;
+    for (int i = 0; i < nk; ++i) {
+      int64_t pc;
+      memcpy(&pc, h + 2 + nk + i, sizeof(pc));
+      pk[i] = pc > 0 ? h[2 + i] / static_cast<double>(pc) : NAN;
+    }
+    return hipSuccess;
+  }
+};
+
+double chi2_of(double fbar, const double* pk, double fbar_t, const double* pk_t, int nk, double s) {
+  double r = (fbar - fbar_t) / (s * fbar_t);
+  r *= r;
+  for (int i = 0; i < nk; ++i) {
+    if (!isfinite(pk_t[i]) || !isfinite(pk[i])) continue;
+    const double d = (pk[i] - pk_t[i]) / (s * pk_t[i]);
+    r += d * d;
+  }
+  return r;
+}
+
+// Nelder-Mead (reflection 1, expansion 2, contraction 1/2, shrink 1/2), 2D;
+// stops when every vertex is within xatol of the best one in each coordinate
+// and within fatol in value, or after max_evals evaluations.
+template <typename F>
+int nelder_mead2(F&& f, double x[2], double step, double xatol, double fatol, int max_evals, double* fbest,
+                 int* nev, bool* failed) {
+  double s[3][2] = {{x[0], x[1]}, {x[0] + step, x[1]}, {x[0], x[1] + step}};
+  double fv[3];
+  int n = 0;
+  for (int i = 0; i < 3; ++i) {
+    fv[i] = f(s[i]);
+    ++n;
+    if (*failed) return n;
+  }
+  while (n < max_evals) {
+    // order
+    for (int i = 0; i < 2; ++i)
+      for (int j = i + 1; j < 3; ++j)
+        if (fv[j] < fv[i]) {
+          double t = fv[i]; fv[i] = fv[j]; fv[j] = t;
+          for (int d = 0; d < 2; ++d) { t = s[i][d]; s[i][d] = s[j][d]; s[j][d] = t; }
+        }
+    double dx = 0.0, df = 0.0;
+    for (int i = 1; i < 3; ++i) {
+      for (int d = 0; d < 2; ++d) dx = fmax(dx, fabs(s[i][d] - s[0][d]));
+      df = fmax(df, fabs(fv[i] - fv[0]));
+    }
+    if (dx <= xatol && df <= fatol) break;
+    const double cx[2] = {0.5 * (s[0][0] + s[1][0]), 0.5 * (s[0][1] + s[1][1])};
+    double xr[2] = {2.0 * cx[0] - s[2][0], 2.0 * cx[1] - s[2][1]};
+    const double fr = f(xr);
+    ++n;
+    if (*failed) return n;
+    if (fr < fv[0]) {
+      double xe[2] = {3.0 * cx[0] - 2.0 * s[2][0], 3.0 * cx[1] - 2.0 * s[2][1]};
+      const double fe = f(xe);
+      ++n;
+      if (*failed) return n;
+      if (fe < fr) { s[2][0] = xe[0]; s[2][1] = xe[1]; fv[2] = fe; }
+      else { s[2][0] = xr[0]; s[2][1] = xr[1]; fv[2] = fr; }
+    } else if (fr < fv[1]) {
+      s[2][0] = xr[0]; s[2][1] = xr[1]; fv[2] = fr;
+    } else {
+      const bool outside = fr < fv[2];
+      double xc[2];
+      if (outside) { xc[0] = 1.5 * cx[0] - 0.5 * s[2][0]; xc[1] = 1.5 * cx[1] - 0.5 * s[2][1]; }
+      else { xc[0] = 0.5 * (cx[0] + s[2][0]); xc[1] = 0.5 * (cx[1] + s[2][1]); }
+      const double fc = f(xc);
+      ++n;
+      if (*failed) return n;
+      if (fc < (outside ? fr : fv[2])) {
+        s[2][0] = xc[0]; s[2][1] = xc[1]; fv[2] = fc;
+      } else {
+        for (int i = 1; i < 3; ++i) {
+          for (int d = 0; d < 2; ++d) s[i][d] = s[0][d] + 0.5 * (s[i][d] - s[0][d]);
+          fv[i] = f(s[i]);
+          ++n;
+          if (*failed) return n;
+        }
+      }
+    }
+  }
+  int best = 0;
+  for (int i = 1; i < 3; ++i) if (fv[i] < fv[best]) best = i;
+  x[0] = s[best][0];
+  x[1] = s[best][1];
+  *fbest = fv[best];
+  *nev = n;
+  return n;
+}
+
+// least squares y = p0 + p1 x + p2 x^2 through (x_i, y_i), normal equations in FP64
+void quad_fit(const double* x, const double* y, int n, double out[3]) {
+  double A[3][4] = {{0}};
+  for (int i = 0; i < n; ++i) {
+    const double p[3] = {1.0, x[i], x[i] * x[i]};
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) A[r][k] += p[r] * p[k];
+      A[r][3] += p[r] * y[i];
+    }
+  }
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r) if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    for (int k = 0; k < 4; ++k) { const double t = A[col][k]; A[col][k] = A[piv][k]; A[piv][k] = t; }
+    if (A[col][col] == 0.0) { out[0] = out[1] = out[2] = NAN; return; }
+    for (int r = 0; r < 3; ++r) {
+      if (r == col) continue;
+      const double fct = A[r][col] / A[col][col];
+      for (int k = col; k < 4; ++k) A[r][k] -= fct * A[col][k];
+    }
+  }
+  for (int r = 0; r < 3; ++r) out[r] = A[r][3] / A[r][r];
+}
+
+__global__ void __launch_bounds__(64) k_label_row(const double* fsum, const int64_t* fcnt, const double* psum,
+                                                  const int64_t* pcnt, int nk, float* row) {
+  const int t = threadIdx.x;
+  if (t == 0) row[0] = fcnt[0] > 0 ? static_cast<float>(fsum[0] / static_cast<double>(fcnt[0])) : NAN;
+  if (t < nk) row[1 + t] = pcnt[t] > 0 ? static_cast<float>(psum[t] / static_cast<double>(pcnt[t])) : NAN;
+}
+
+}  // namespace
+
+size_t tune_workspace_bytes(int64_t n_sk, int nk) { return carve_tune(n_sk, nk).total; }
+
+// Emulator training labels: for each host draw (a, b, c, z) the mean flux and
+// mean P1D per bin (velocity units at z) of the stored pixels, written to
+// y[i][0] and y[i][1 + b] on the device; no host synchronisation per draw.
+int emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t n, float* y, void* work, size_t work_bytes,
+                    hipStream_t st, char* err, size_t errlen) {
+  const int nk = spec->p1d.n_kbins;
+  const TuneCarve c = carve_tune(spec->sk->n_sk, nk);
+  if (work_bytes < c.total) {
+    snprintf(err, errlen, "workspace too small for labels");
+    return LYA_EWORKSPACE;
+  }
+  char* w = static_cast<char*>(work);
+  const double edges[2] = {-1e300, 1e300};
+  hipError_t e;
+  if ((e = hipMemcpyAsync(w + c.edges, edges, sizeof(edges), hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess ||
+      (e = launch_zchi_table(spec->cosmo.omega_m, reinterpret_cast<float*>(w + c.ztab), st)) != hipSuccess ||
+      (e = launch_twiddles(reinterpret_cast<float2*>(w + c.tw), kTw2048, st)) != hipSuccess) {
+    snprintf(err, errlen, "label set-up: %s", hipGetErrorString(e));
+    return LYA_EHIP;
+  }
+  const lya_skewers* sk = spec->sk;
+  for (int64_t i = 0; i < n; ++i) {
+    const double a = draws[4 * i], b = draws[4 * i + 1], cc = draws[4 * i + 2], z = draws[4 * i + 3];
+    SkewerArgs sa{};
+    sa.n_sk = sk->n_sk;
+    sa.npix = sk->npix;
+    sa.offset = sk->offset;
+    sa.chi0 = sk->chi0;
+    sa.dchi = sk->dchi;
+    sa.n = 32;
+    sa.in_dens = spec->dens;
+    sa.in_eta = spec->eta;
+    sa.do_flux = 1;
+    sa.cf[0][0] = static_cast<float>(a);
+    sa.cf[1][0] = static_cast<float>(b);
+    sa.cf[2][0] = static_cast<float>(cc);
+    sa.n_bins = 1;
+    sa.chi_edges = reinterpret_cast<const double*>(w + c.edges);
+    sa.bin_sum = reinterpret_cast<unsigned long long*>(w + c.bsum);
+    sa.bin_cnt = reinterpret_cast<unsigned long long*>(w + c.bcnt);
+    sa.out_fsum = reinterpret_cast<double*>(w + c.fsum);
+    sa.out_count = reinterpret_cast<int64_t*>(w + c.fcnt);
+    sa.ztab = reinterpret_cast<const float*>(w + c.ztab);
+    sa.tw2048 = reinterpret_cast<const float2*>(w + c.tw);
+    sa.queue = reinterpret_cast<unsigned int*>(w + c.queue);
+    sa.chunk = 8;
+    if ((e = launch_skewers(sa, st)) != hipSuccess) break;
+    P1dArgs pa{};
+    pa.n_sk = sk->n_sk;
+    pa.npix = sk->npix;
+    pa.offset = sk->offset;
+    pa.chi0 = sk->chi0;
+    pa.dchi = sk->dchi;
+    pa.dens = spec->dens;
+    pa.eta = spec->eta;
+    pa.fa = sa.cf[0][0];
+    pa.fb = sa.cf[1][0];
+    pa.fc = sa.cf[2][0];
+    pa.n_fbins = 1;
+    pa.chi_edges = sa.chi_edges;
+    pa.fsum = sa.out_fsum;
+    pa.fcount = sa.out_count;
+    pa.n_kbins = nk;
+    pa.k_edges = spec->p1d.k_edges;
+    const double x = 1.0 + z, om = spec->cosmo.omega_m;
+    pa.dv = spec->p1d.dpix * (100.0 * sqrt(om * (x * x * x) + (1.0 - om)) / x);
+    pa.part_sum = reinterpret_cast<double*>(w + c.part_sum);
+    pa.part_cnt = reinterpret_cast<int*>(w + c.part_cnt);
+    pa.tw2048 = sa.tw2048;
+    pa.queue = sa.queue;
+    pa.chunk = 4;
+    double* d_psum = reinterpret_cast<double*>(w + c.psum);
+    int64_t* d_pcnt = reinterpret_cast<int64_t*>(w + c.pcnt);
+    if ((e = launch_p1d(pa, d_psum, d_pcnt, st)) != hipSuccess) break;
+    hipLaunchKernelGGL(k_label_row, dim3(1), dim3(64), 0, st, sa.out_fsum, sa.out_count, d_psum, d_pcnt, nk,
+                       y + i * (1 + nk));
+    if ((e = hipGetLastError()) != hipSuccess) break;
+  }
+  if (e != hipSuccess) {
+    snprintf(err, errlen, "label evaluation: %s", hipGetErrorString(e));
+    return LYA_EHIP;
+  }
+  return LYA_OK;
+}
+
+int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void* work, size_t work_bytes,
+                hipStream_t st, char* err, size_t errlen) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int nk = spec->p1d.n_kbins;
+  const TuneCarve c = carve_tune(spec->sk->n_sk, nk);
+  if (work_bytes < c.total) {
+    snprintf(err, errlen, "workspace too small for tuning");
+    return LYA_EWORKSPACE;
+  }
+  char* w = static_cast<char*>(work);
+  double h_stats[2 + 2 * kMaxKBins];
+  Evaluator ev{spec, w, c, st, nk, h_stats};
+  hipError_t e;
+  const double edges[2] = {-1e300, 1e300};
+  if ((e = hipMemcpyAsync(w + c.edges, edges, sizeof(edges), hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = launch_zchi_table(spec->cosmo.omega_m, reinterpret_cast<float*>(w + c.ztab), st)) != hipSuccess ||
+      (e = launch_twiddles(reinterpret_cast<float2*>(w + c.tw), kTw2048, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    snprintf(err, errlen, "tuning set-up: %s", hipGetErrorString(e));
+    return LYA_EHIP;
+  }
+  memset(res, 0, sizeof(*res));
+  for (int zi = 0; zi < spec->n_zt; ++zi) {
+    const double z = spec->z_t[zi], cc = spec->c_t[zi], fbt = spec->fbar_t[zi];
+    const double* pkt = spec->p1d_t + static_cast<size_t>(zi) * nk;
+    bool failed = false;
+    hipError_t last = hipSuccess;
+    double pk[kMaxKBins];
+    auto plain = [&](const double* t) -> double {
+      double fb;
+      last = ev.eval(exp(t[0]), exp(t[1]), cc, z, &fb, pk);
+      if (last != hipSuccess) { failed = true; return HUGE_VAL; }
+      return chi2_of(fb, pk, fbt, pkt, nk, spec->sigma_rel);
+    };
+    auto emul = [&](const double* t) -> double {
+      double fb;
+      last = emulator_predict(spec->emulator, exp(t[0]), exp(t[1]), cc, z, &fb, pk, nk,
+                              reinterpret_cast<char*>(w + c.emu), st);
+      if (last != hipSuccess) { failed = true; return HUGE_VAL; }
+      return chi2_of(fb, pk, fbt, pkt, nk, spec->sigma_rel);
+    };
+    double x[2] = {log(spec->a0), log(spec->b0)};
+    double fbest = 0.0;
+    int nev = 0;
+    if (mode == LYA_TUNE_EMULATOR) {
+      nelder_mead2(emul, x, 0.3, spec->xatol, spec->fatol, spec->max_evals, &fbest, &nev, &failed);
+    } else {
+      nelder_mead2(plain, x, 0.3, spec->xatol, spec->fatol, spec->max_evals, &fbest, &nev, &failed);
+    }
+    if (failed) {
+      snprintf(err, errlen, "tuning evaluation at z=%g: %s", z, hipGetErrorString(last));
+      return LYA_EHIP;
+    }
+    // statistics actually reached (one GPU evaluation)
+    double fb;
+    if ((e = ev.eval(exp(x[0]), exp(x[1]), cc, z, &fb, pk)) != hipSuccess) {
+      snprintf(err, errlen, "tuning evaluation: %s", hipGetErrorString(e));
+      return LYA_EHIP;
+    }
+    res->a[zi] = exp(x[0]);
+    res->b[zi] = exp(x[1]);
+    res->fbar[zi] = fb;
+    res->chi2[zi] = chi2_of(fb, pk, fbt, pkt, nk, spec->sigma_rel);
+    res->evals[zi] = nev;
+    for (int i = 0; i < nk; ++i) res->p1d[zi * kMaxKBins + i] = pk[i];
+  }
+  double xs[16], ys[3][16];
+  for (int zi = 0; zi < spec->n_zt; ++zi) {
+    xs[zi] = 1.0 + spec->z_t[zi];
+    ys[0][zi] = res->a[zi];
+    ys[1][zi] = res->b[zi];
+    ys[2][zi] = spec->c_t[zi];
+  }
+  for (int p = 0; p < 3; ++p) {
+    if (spec->n_zt >= 3) {
+      quad_fit(xs, ys[p], spec->n_zt, res->coef[p]);
+    } else {
+      res->coef[p][0] = spec->n_zt ? ys[p][0] : 0.0;
+      res->coef[p][1] = res->coef[p][2] = 0.0;
+    }
+  }
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return LYA_OK;
+}
+
+}  // namespace lya

@@ -16,8 +16,12 @@ LYA_F32, LYA_BF16 = 0, 1
 LYA_OP_BOX, LYA_OP_SKEWERS = 0, 1
 COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6}
 
-EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta", "lya_draw_skewers",
-           "lya_apply_fgpa", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
+EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta",
+           "lya_draw_skewers", "lya_apply_fgpa", "lya_p1d_workspace_size", "lya_p1d", "lya_tune_workspace_size",
+           "lya_tune_params", "lya_emulator_labels", "lya_emulator_bytes", "lya_emulator_param_offset",
+           "lya_emulator_param_count", "lya_emulator_init", "lya_emulator_train_workspace_size",
+           "lya_emulator_set_scaling", "lya_emulator_loss_grad", "lya_emulator_train", "lya_emulator_predict",
+           "lya_emulator_last_error", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
            "lya_last_error", "lya_version")
 
 
@@ -221,3 +225,151 @@ def timing_read():
         _check(lib.lya_timing_get(i, buf, 64, ctypes.byref(ms), ctypes.byref(cnt)))
         out[buf.value.decode()] = (ms.value, cnt.value)
     return out
+
+
+# ---------------------------------------------------------------- 1D power, tuning, emulator
+class P1dSpec(ctypes.Structure):
+    _fields_ = [("n_kbins", ctypes.c_int32), ("k_edges", ctypes.c_void_p), ("z_ref", ctypes.c_double),
+                ("dpix", ctypes.c_double)]
+
+
+TUNE_MAX_Z = 16
+LYA_TUNE_PLAIN, LYA_TUNE_EMULATOR = 0, 1
+
+
+class TuneSpec(ctypes.Structure):
+    _fields_ = [("sk", ctypes.POINTER(Skewers)), ("dens", ctypes.c_void_p), ("eta", ctypes.c_void_p),
+                ("cosmo", Cosmo), ("n_zt", ctypes.c_int32),
+                ("z_t", ctypes.c_double * TUNE_MAX_Z), ("c_t", ctypes.c_double * TUNE_MAX_Z),
+                ("fbar_t", ctypes.c_double * TUNE_MAX_Z), ("p1d_t", ctypes.c_void_p), ("p1d", P1dSpec),
+                ("a0", ctypes.c_double), ("b0", ctypes.c_double), ("sigma_rel", ctypes.c_double),
+                ("xatol", ctypes.c_double), ("fatol", ctypes.c_double), ("max_evals", ctypes.c_int32),
+                ("emulator", ctypes.c_void_p)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double * TUNE_MAX_Z), ("b", ctypes.c_double * TUNE_MAX_Z),
+                ("chi2", ctypes.c_double * TUNE_MAX_Z), ("fbar", ctypes.c_double * TUNE_MAX_Z),
+                ("p1d", ctypes.c_double * (TUNE_MAX_Z * 64)), ("evals", ctypes.c_int32 * TUNE_MAX_Z),
+                ("coef", (ctypes.c_double * 3) * 3), ("seconds", ctypes.c_double)]
+
+
+def _bind_more(lib):
+    P, VP = ctypes.POINTER, ctypes.c_void_p
+    lib.lya_p1d_workspace_size.restype = ctypes.c_size_t
+    lib.lya_p1d_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.lya_p1d.restype = ctypes.c_int
+    lib.lya_p1d.argtypes = [P(Skewers), P(Cosmo), VP, P(ZBins), P(P1dSpec), VP, VP, VP, ctypes.c_size_t, VP]
+    lib.lya_tune_workspace_size.restype = ctypes.c_size_t
+    lib.lya_tune_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.lya_tune_params.restype = ctypes.c_int
+    lib.lya_tune_params.argtypes = [P(TuneSpec), P(TuneResult), ctypes.c_int, VP, ctypes.c_size_t, VP]
+    lib.lya_emulator_labels.restype = ctypes.c_int
+    lib.lya_emulator_labels.argtypes = [P(TuneSpec), VP, ctypes.c_int64, VP, VP, ctypes.c_size_t, VP]
+    lib.lya_emulator_bytes.restype = ctypes.c_size_t
+    lib.lya_emulator_bytes.argtypes = [ctypes.c_int32]
+    lib.lya_emulator_param_offset.restype = ctypes.c_size_t
+    lib.lya_emulator_param_count.restype = ctypes.c_size_t
+    lib.lya_emulator_param_count.argtypes = [ctypes.c_int32]
+    lib.lya_emulator_init.restype = ctypes.c_int
+    lib.lya_emulator_init.argtypes = [VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, P(ctypes.c_double),
+                                      P(ctypes.c_double), VP]
+    lib.lya_emulator_train_workspace_size.restype = ctypes.c_size_t
+    lib.lya_emulator_train_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.lya_emulator_set_scaling.restype = ctypes.c_int
+    lib.lya_emulator_set_scaling.argtypes = [VP, VP, ctypes.c_int64, VP]
+    lib.lya_emulator_loss_grad.restype = ctypes.c_int
+    lib.lya_emulator_loss_grad.argtypes = [VP, VP, VP, ctypes.c_int32, ctypes.c_int32, VP, VP, VP, ctypes.c_size_t,
+                                           VP]
+    lib.lya_emulator_train.restype = ctypes.c_int
+    lib.lya_emulator_train.argtypes = [VP, VP, VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_int32, VP, VP, ctypes.c_size_t, VP]
+    lib.lya_emulator_predict.restype = ctypes.c_int
+    lib.lya_emulator_predict.argtypes = [VP, VP, ctypes.c_int64, VP, VP]
+    lib.lya_emulator_last_error.restype = ctypes.c_char_p
+
+
+def _lib2():
+    lib = load()
+    if not getattr(lib, "_bound_more", False):
+        _bind_more(lib)
+        lib._bound_more = True
+    return lib
+
+
+def _echeck(rc):
+    if rc != LYA_OK:
+        raise LyaError(rc, _lib2().lya_emulator_last_error().decode())
+
+
+def p1d_workspace_size(n_sk, n_kbins):
+    return int(_lib2().lya_p1d_workspace_size(int(n_sk), int(n_kbins)))
+
+
+def p1d(sk, cosmo, flux, fbar_zbins, spec, psum, pcount, work, stream=None):
+    """lya_p1d (see include/lyamock.h)."""
+    _check(_lib2().lya_p1d(ctypes.byref(sk), ctypes.byref(cosmo), _ptr(flux), ctypes.byref(fbar_zbins),
+                           ctypes.byref(spec), _ptr(psum), _ptr(pcount), _ptr(work),
+                           work.numel() * work.element_size(), _stream(stream)))
+
+
+def tune_workspace_size(n_sk, n_kbins):
+    return int(_lib2().lya_tune_workspace_size(int(n_sk), int(n_kbins)))
+
+
+def tune_params(spec, mode, work, stream=None):
+    """lya_tune_params: returns a TuneResult."""
+    res = TuneResult()
+    _check(_lib2().lya_tune_params(ctypes.byref(spec), ctypes.byref(res), int(mode), _ptr(work),
+                                   work.numel() * work.element_size(), _stream(stream)))
+    return res
+
+
+def emulator_labels(spec, draws_host, y, work, stream=None):
+    """lya_emulator_labels: draws_host is a C-contiguous float64 numpy array [n, 4]."""
+    import numpy as np
+    d = np.ascontiguousarray(draws_host, dtype=np.float64)
+    _check(_lib2().lya_emulator_labels(ctypes.byref(spec), d.ctypes.data, int(d.shape[0]), _ptr(y), _ptr(work),
+                                       work.numel() * work.element_size(), _stream(stream)))
+
+
+def emulator_bytes(n_out):
+    return int(_lib2().lya_emulator_bytes(int(n_out)))
+
+
+def emulator_param_offset():
+    return int(_lib2().lya_emulator_param_offset())
+
+
+def emulator_param_count(n_out):
+    return int(_lib2().lya_emulator_param_count(int(n_out)))
+
+
+def emulator_init(emu, n_out, log_from, seed, in_lo, in_hi, stream=None):
+    lo = (ctypes.c_double * 4)(*[float(v) for v in in_lo])
+    hi = (ctypes.c_double * 4)(*[float(v) for v in in_hi])
+    _echeck(_lib2().lya_emulator_init(_ptr(emu), int(n_out), int(log_from), int(seed), lo, hi, _stream(stream)))
+
+
+def emulator_train_workspace_size(batch, n_out):
+    return int(_lib2().lya_emulator_train_workspace_size(int(batch), int(n_out)))
+
+
+def emulator_set_scaling(emu, y, n, stream=None):
+    _echeck(_lib2().lya_emulator_set_scaling(_ptr(emu), _ptr(y), int(n), _stream(stream)))
+
+
+def emulator_loss_grad(emu, x0, t, batch, use_bf16, grad, loss, work, stream=None):
+    _echeck(_lib2().lya_emulator_loss_grad(_ptr(emu), _ptr(x0), _ptr(t), int(batch), int(bool(use_bf16)), _ptr(grad),
+                                           _ptr(loss), _ptr(work), work.numel() * work.element_size(),
+                                           _stream(stream)))
+
+
+def emulator_train(emu, x, y, n, steps, batch, lr, use_bf16, loss_hist, work, stream=None):
+    _echeck(_lib2().lya_emulator_train(_ptr(emu), _ptr(x), _ptr(y), int(n), int(steps), int(batch), float(lr),
+                                       int(bool(use_bf16)), _ptr(loss_hist), _ptr(work),
+                                       work.numel() * work.element_size(), _stream(stream)))
+
+
+def emulator_predict(emu, x, n, y, stream=None):
+    _echeck(_lib2().lya_emulator_predict(_ptr(emu), _ptr(x), int(n), _ptr(y), _stream(stream)))
