@@ -189,10 +189,14 @@ int lya_p1d(const lya_skewers* sk, const lya_cosmo* cosmo, const float* flux, co
  * saved forests in post-production.  Search: Nelder-Mead in (ln a, ln b) from
  * (a0, b0), initial steps 0.3, stopping when all vertices lie within xatol
  * (coordinates) and fatol (chi^2) of the best or after max_evals evaluations.
- * Mode LYA_TUNE_PLAIN evaluates every point on the GPU; LYA_TUNE_EMULATOR
- * searches on the emulator's predictions (see lya_emulator_*) and spends one
- * GPU evaluation per z_t to report the statistics reached.  a(z), b(z), c(z)
- * are then least-squares quadratics in (1+z).  Synchronous (reads back the
+ * Mode LYA_TUNE_PLAIN evaluates every point on the GPU.  LYA_TUNE_EMULATOR
+ * searches on the emulator's predictions (see lya_emulator_*), evaluates the
+ * optimum on the GPU, adds the measured defect (GPU minus prediction at that
+ * point) to every later prediction and searches again from there (initial
+ * steps 0.05), until the optimum moves by at most 10 xatol or emu_checks GPU
+ * evaluations are spent; the result holds the last GPU evaluation.  a(z), b(z), c(z)
+ * are then least-squares quadratics in (1+z) (n_zt >= 3; the line through
+ * two points, a constant for one).  Synchronous (reads back the
  * statistics of every evaluation); all GPU work runs on `stream`. */
 #define LYA_TUNE_MAX_Z 16
 enum { LYA_TUNE_PLAIN = 0, LYA_TUNE_EMULATOR = 1 };
@@ -211,12 +215,14 @@ typedef struct {
   double xatol, fatol;
   int32_t max_evals;         /* per z_t */
   const void* emulator;      /* emulator state (device) for LYA_TUNE_EMULATOR, else NULL */
+  int32_t emu_checks;        /* LYA_TUNE_EMULATOR: most GPU evaluations per z_t (<= 0: 1) */
 } lya_tune_spec;
 
 typedef struct {
   double a[LYA_TUNE_MAX_Z], b[LYA_TUNE_MAX_Z], chi2[LYA_TUNE_MAX_Z], fbar[LYA_TUNE_MAX_Z];
   double p1d[LYA_TUNE_MAX_Z * 64];   /* reached mean P1D, [z_t][bin] with row length 64 */
   int32_t evals[LYA_TUNE_MAX_Z];     /* search evaluations per z_t (GPU or emulator) */
+  int32_t gpu_evals[LYA_TUNE_MAX_Z]; /* GPU evaluations per z_t, the final one included */
   double coef[3][3];                 /* a, b, c = sum_i coef[p][i] (1+z)^i */
   double seconds;                    /* wall time of the call */
 } lya_tune_result;
@@ -224,6 +230,72 @@ typedef struct {
 size_t lya_tune_workspace_size(int64_t n_sk, int32_t n_kbins);
 int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void* work, size_t work_bytes,
                     void* stream);
+
+/* Tuning emulator (not in the paper: a surrogate for the evaluations of the
+ * tuning loop above).  A multilayer perceptron 4 -> 256 -> 256 -> 256 -> n_out
+ * with exact GELU hidden layers (x Phi(x)) and a linear output maps
+ * (a, b, c, z) to (Fbar, P_1, ..., P_nk), the statistics lya_tune_params
+ * matches.  Row-vector convention h = gelu(x W + b), W stored [in][out]
+ * row-major, parameters in the order W1 b1 W2 b2 W3 b3 W4 b4 (FP32).
+ * Inputs are scaled to [-1, 1] by the ranges given at init; outputs are
+ * standardised per column with statistics taken from the training labels
+ * (natural log first for columns >= log_from).  Training: mean squared error
+ * over batch and unmasked columns, Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected); the matrix products run on the matrix cores in bfloat16
+ * with FP32 accumulation (use_bf16 = 1) or in plain FP32.
+ *
+ * The emulator state is one device buffer of lya_emulator_bytes(n_out) bytes
+ * owned by the caller: a header, then the parameters at byte offset
+ * lya_emulator_param_offset(), then the two Adam moment arrays.  Errors of
+ * these calls are reported by lya_emulator_last_error(). */
+size_t lya_emulator_bytes(int32_t n_out);          /* 0 unless 1 <= n_out <= 64 */
+size_t lya_emulator_param_offset(void);
+size_t lya_emulator_param_count(int32_t n_out);    /* 0 unless 1 <= n_out <= 64 */
+
+/* Writes the header (input ranges in_lo < in_hi per input, identity output
+ * scaling, step 0) and He-normal weights (std sqrt(2/fan_in), Philox stream 3
+ * of `seed`), zero biases and zero moments.  Asynchronous on `stream` after a
+ * header upload that synchronises the stream. */
+int lya_emulator_init(void* emu, int32_t n_out, int32_t log_from, uint64_t seed, const double in_lo[4],
+                      const double in_hi[4], void* stream);
+
+/* Output standardisation from labels y (device, [n][n_out] row-major): per
+ * column FP64 mean and standard deviation (of ln y for columns >= log_from); a
+ * column with any non-finite value is masked out of the loss. */
+int lya_emulator_set_scaling(void* emu, const float* y, int64_t n, void* stream);
+
+/* Workspace of one training batch (activations, gradients): bytes. */
+size_t lya_emulator_train_workspace_size(int32_t batch, int32_t n_out);
+
+/* Loss and gradient of one batch of already standardised inputs x0
+ * ([batch][4]) and targets t ([batch][n_out]) (device): grad receives
+ * lya_emulator_param_count(n_out) floats in parameter order, loss (may be
+ * NULL) one float.  Parameters are not changed. */
+int lya_emulator_loss_grad(const void* emu, const float* x0, const float* t, int32_t batch, int32_t use_bf16,
+                           float* grad, float* loss, void* work, size_t work_bytes, void* stream);
+
+/* `steps` Adam steps with learning rate lr on the rows of x ([n][4], raw
+ * inputs) and y ([n][n_out], raw labels) (device); step s (counted from the
+ * emulator's own step counter) takes rows (s batch + i) mod n.  loss_hist
+ * (device, may be NULL) receives each step's loss.  Synchronises the stream at
+ * the end. */
+int lya_emulator_train(void* emu, const float* x, const float* y, int64_t n, int32_t steps, int32_t batch,
+                       double lr, int32_t use_bf16, float* loss_hist, void* work, size_t work_bytes, void* stream);
+
+/* FP32 prediction of raw outputs (exp applied for columns >= log_from) for n
+ * raw inputs x ([n][4]) into y ([n][n_out]) (device).  Asynchronous. */
+int lya_emulator_predict(const void* emu, const float* x, int64_t n, float* y, void* stream);
+
+/* Training labels for the emulator: for each host draw (a, b, c, z)
+ * (draws[4 i + 0..3], FP64) the statistics lya_tune_params evaluates at those
+ * constant parameters with velocity units at z, written to y[i][0] (Fbar) and
+ * y[i][1 + b] (mean P1D of k bin b) on the device (n_out = 1 + n_kbins).
+ * Uses the tuning workspace (lya_tune_workspace_size); errors are reported by
+ * lya_last_error(). */
+int lya_emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t n, float* y, void* work,
+                        size_t work_bytes, void* stream);
+
+const char* lya_emulator_last_error(void);
 
 /* Kernel timing for benchmarks.  lya_timing_enable(1) clears the records and
  * brackets every kernel the library launches afterwards with two HIP events on

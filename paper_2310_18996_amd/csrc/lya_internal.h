@@ -145,7 +145,15 @@ hipError_t launch_p1d(const P1dArgs& a, double* psum, int64_t* pcount, hipStream
 
 // Tuning (lya_tune.hip) and the emulator used by it (lya_mlp.hip).
 size_t emulator_eval_bytes();
-hipError_t emulator_predict(const void* emu, double a, double b, double c, double z, double* fbar, double* pk,
-                            int nk, char* scratch, hipStream_t st);
+// Device-side Nelder-Mead over (ln a, ln b) on the emulator plus offsets;
+// x holds the start on entry and the optimum on return (synchronous).
+struct EmuSearchSpec {
+  double fbar_t, off_f, c, z, step, xatol, fatol, sigma;
+  int nk, max_evals;
+  const double* pk_t;
+  const double* off_p;
+};
+hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2], double* fbest, int* nev,
+                           double* pred_fbar, double* pred_pk, char* scratch, hipStream_t st);
 
 }  // namespace lya

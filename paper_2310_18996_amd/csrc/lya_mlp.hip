@@ -13,6 +13,7 @@
 
 #include "../../include/lyamock.h"
 #include "lya_internal.h"
+#include "lya_nm.h"
 
 namespace lya {
 
@@ -431,25 +432,128 @@ static const float* emu_params(const void* emu) {
   return reinterpret_cast<const float*>(static_cast<const char*>(emu) + kHeaderBytes);
 }
 
-size_t emulator_eval_bytes() { return 256 + 64 * sizeof(float) * 2; }
+size_t emulator_eval_bytes() { return 1024; }
 
-// one prediction for the tuning search: (a, b, c, z) -> Fbar, P1D[nk]
-hipError_t emulator_predict(const void* emu, double a, double b, double c, double z, double* fbar, double* pk, int nk,
-                            char* scratch, hipStream_t st) {
-  if (!emu) return hipErrorInvalidValue;
-  float hx[4] = {static_cast<float>(a), static_cast<float>(b), static_cast<float>(c), static_cast<float>(z)};
-  float* dx = reinterpret_cast<float*>(scratch);
-  float* dy = dx + 64;
-  hipError_t e;
-  if ((e = hipMemcpyAsync(dx, hx, sizeof(hx), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emu_predict, dim3(1), dim3(256), 0, st, static_cast<const EmuHeader*>(emu), emu_params(emu),
-                     dx, int64_t(1), dy);
-  float hy[kMaxOut];
-  if ((e = hipMemcpyAsync(hy, dy, sizeof(float) * (nk + 1), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+// ---------------------------------------------------------------- device-side tuning search
+struct SearchArgs {
+  const EmuHeader* h;
+  const float* params;
+  double fbar_t, off_f, c, z, x0[2], step, xatol, fatol, sigma;
+  int nk, max_evals;
+  double pk_t[kMaxOut], off_p[kMaxOut];
+  double* out;  // x[2], best objective, evaluations, raw prediction [1 + nk] at x
+};
+
+// One forward pass of a single input by the whole block (256 threads, one
+// hidden unit each); raw outputs (exp for columns >= log_from) into outv.
+__device__ void forward_one(const EmuHeader* __restrict__ h, const float* __restrict__ params, const Offs& o,
+                            const float xin[4], float (*hs)[kHid], float* part, float* outv) {
+  const int t = threadIdx.x, n_out = h->n_out;
+  float a = params[o.b[0] + t];
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) {
+    const float u = 2.0f * (xin[i] - h->in_lo[i]) / (h->in_hi[i] - h->in_lo[i]) - 1.0f;
+    a = fmaf(u, params[o.W[0] + i * kHid + t], a);
+  }
+  hs[0][t] = gelu(a);
+  __syncthreads();
+  int cur = 0;
+  for (int l = 1; l < 3; ++l) {
+    float acc = params[o.b[l] + t];
+    const float* W = params + o.W[l] + t;
+#pragma unroll 8
+    for (int k = 0; k < kHid; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * kHid], acc);
+    hs[cur ^ 1][t] = gelu(acc);
+    __syncthreads();
+    cur ^= 1;
+  }
+  // output layer: four threads per column, each a quarter of the sum
+  const int oc = t & 63, q = t >> 6;
+  float acc = 0.0f;
+  if (oc < n_out) {
+    const float* W = params + o.W[3] + oc;
+    for (int k = 64 * q; k < 64 * q + 64; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * n_out], acc);
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (t < n_out) {
+    float v = params[o.b[3] + t] + ((part[t] + part[t + 64]) + (part[t + 128] + part[t + 192]));
+    v = v * h->out_std[t] + h->out_mean[t];
+    if (t >= h->log_from) v = expf(v);
+    outv[t] = v;
+  }
+  __syncthreads();
+}
+
+// Nelder-Mead over (ln a, ln b) on the emulator's predictions plus the given
+// offsets, entirely on the device: one block, every thread runs the same
+// search on the same (block-broadcast) objective values.
+__global__ void __launch_bounds__(256) k_emu_search(SearchArgs a) {
+  __shared__ float hs[2][kHid];
+  __shared__ float part[256];
+  __shared__ float outv[kMaxOut];
+  const Offs o = param_offsets(a.h->n_out);
+  const int nk = a.nk;
+  auto f = [&](const double* th) -> double {
+    const float xin[4] = {static_cast<float>(exp(th[0])), static_cast<float>(exp(th[1])), static_cast<float>(a.c),
+                          static_cast<float>(a.z)};
+    forward_one(a.h, a.params, o, xin, hs, part, outv);
+    double pk[kMaxOut];
+    for (int i = 0; i < nk; ++i) pk[i] = static_cast<double>(outv[1 + i]) + a.off_p[i];
+    return tune_chi2(static_cast<double>(outv[0]) + a.off_f, pk, a.fbar_t, a.pk_t, nk, a.sigma);
+  };
+  double x[2] = {a.x0[0], a.x0[1]}, fbest = 0.0;
+  int nev = 0;
+  bool failed = false;
+  nelder_mead2(f, x, a.step, a.xatol, a.fatol, a.max_evals, &fbest, &nev, &failed);
+  f(x);
+  const int t = threadIdx.x;
+  if (t == 0) {
+    a.out[0] = x[0];
+    a.out[1] = x[1];
+    a.out[2] = fbest;
+    a.out[3] = static_cast<double>(nev);
+  }
+  if (t <= nk) a.out[4 + t] = static_cast<double>(outv[t]);
+}
+
+hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2], double* fbest, int* nev,
+                           double* pred_fbar, double* pred_pk, char* scratch, hipStream_t st) {
+  if (!emu || sp.nk < 0 || sp.nk + 1 > kMaxOut) return hipErrorInvalidValue;
+  SearchArgs a{};
+  a.h = static_cast<const EmuHeader*>(emu);
+  a.params = emu_params(emu);
+  a.fbar_t = sp.fbar_t;
+  a.off_f = sp.off_f;
+  a.c = sp.c;
+  a.z = sp.z;
+  a.x0[0] = x[0];
+  a.x0[1] = x[1];
+  a.step = sp.step;
+  a.xatol = sp.xatol;
+  a.fatol = sp.fatol;
+  a.sigma = sp.sigma;
+  a.nk = sp.nk;
+  a.max_evals = sp.max_evals;
+  for (int i = 0; i < sp.nk; ++i) {
+    a.pk_t[i] = sp.pk_t[i];
+    a.off_p[i] = sp.off_p[i];
+  }
+  a.out = reinterpret_cast<double*>(scratch);
+  hipLaunchKernelGGL(k_emu_search, dim3(1), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double hout[4 + kMaxOut];
+  if ((e = hipMemcpyAsync(hout, a.out, sizeof(double) * (5 + sp.nk), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  *fbar = hy[0];
-  for (int i = 0; i < nk; ++i) pk[i] = hy[1 + i];
-  return hipGetLastError();
+  x[0] = hout[0];
+  x[1] = hout[1];
+  *fbest = hout[2];
+  *nev = static_cast<int>(hout[3]);
+  *pred_fbar = hout[4];
+  for (int i = 0; i < sp.nk; ++i) pred_pk[i] = hout[5 + i];
+  return hipSuccess;
 }
 
 }  // namespace lya

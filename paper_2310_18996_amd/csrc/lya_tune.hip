@@ -3,8 +3,9 @@
 // driving GPU evaluations of the mean flux and the 1D power of the stored
 // pre-FGPA pixels under constant (a, b, c) (the paper's post-production reuse
 // of saved forests), then least-squares quadratics in (1+z).  The emulator
-// mode runs the same search on the MLP's predictions and spends one GPU
-// evaluation per redshift to report the statistics actually reached.
+// mode runs the same search on the MLP's predictions, checks the optimum on the
+// GPU and corrects the prediction by the measured defect before searching
+// again (a few GPU evaluations per redshift instead of one per search step).
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -13,6 +14,7 @@
 
 #include "../../include/lyamock.h"
 #include "lya_internal.h"
+#include "lya_nm.h"
 
 namespace lya {
 
@@ -126,87 +128,6 @@ struct Evaluator {
   }
 };
 
-double chi2_of(double fbar, const double* pk, double fbar_t, const double* pk_t, int nk, double s) {
-  double r = (fbar - fbar_t) / (s * fbar_t);
-  r *= r;
-  for (int i = 0; i < nk; ++i) {
-    if (!isfinite(pk_t[i]) || !isfinite(pk[i])) continue;
-    const double d = (pk[i] - pk_t[i]) / (s * pk_t[i]);
-    r += d * d;
-  }
-  return r;
-}
-
-// Nelder-Mead (reflection 1, expansion 2, contraction 1/2, shrink 1/2), 2D;
-// stops when every vertex is within xatol of the best one in each coordinate
-// and within fatol in value, or after max_evals evaluations.
-template <typename F>
-int nelder_mead2(F&& f, double x[2], double step, double xatol, double fatol, int max_evals, double* fbest,
-                 int* nev, bool* failed) {
-  double s[3][2] = {{x[0], x[1]}, {x[0] + step, x[1]}, {x[0], x[1] + step}};
-  double fv[3];
-  int n = 0;
-  for (int i = 0; i < 3; ++i) {
-    fv[i] = f(s[i]);
-    ++n;
-    if (*failed) return n;
-  }
-  while (n < max_evals) {
-    // order
-    for (int i = 0; i < 2; ++i)
-      for (int j = i + 1; j < 3; ++j)
-        if (fv[j] < fv[i]) {
-          double t = fv[i]; fv[i] = fv[j]; fv[j] = t;
-          for (int d = 0; d < 2; ++d) { t = s[i][d]; s[i][d] = s[j][d]; s[j][d] = t; }
-        }
-    double dx = 0.0, df = 0.0;
-    for (int i = 1; i < 3; ++i) {
-      for (int d = 0; d < 2; ++d) dx = fmax(dx, fabs(s[i][d] - s[0][d]));
-      df = fmax(df, fabs(fv[i] - fv[0]));
-    }
-    if (dx <= xatol && df <= fatol) break;
-    const double cx[2] = {0.5 * (s[0][0] + s[1][0]), 0.5 * (s[0][1] + s[1][1])};
-    double xr[2] = {2.0 * cx[0] - s[2][0], 2.0 * cx[1] - s[2][1]};
-    const double fr = f(xr);
-    ++n;
-    if (*failed) return n;
-    if (fr < fv[0]) {
-      double xe[2] = {3.0 * cx[0] - 2.0 * s[2][0], 3.0 * cx[1] - 2.0 * s[2][1]};
-      const double fe = f(xe);
-      ++n;
-      if (*failed) return n;
-      if (fe < fr) { s[2][0] = xe[0]; s[2][1] = xe[1]; fv[2] = fe; }
-      else { s[2][0] = xr[0]; s[2][1] = xr[1]; fv[2] = fr; }
-    } else if (fr < fv[1]) {
-      s[2][0] = xr[0]; s[2][1] = xr[1]; fv[2] = fr;
-    } else {
-      const bool outside = fr < fv[2];
-      double xc[2];
-      if (outside) { xc[0] = 1.5 * cx[0] - 0.5 * s[2][0]; xc[1] = 1.5 * cx[1] - 0.5 * s[2][1]; }
-      else { xc[0] = 0.5 * (cx[0] + s[2][0]); xc[1] = 0.5 * (cx[1] + s[2][1]); }
-      const double fc = f(xc);
-      ++n;
-      if (*failed) return n;
-      if (fc < (outside ? fr : fv[2])) {
-        s[2][0] = xc[0]; s[2][1] = xc[1]; fv[2] = fc;
-      } else {
-        for (int i = 1; i < 3; ++i) {
-          for (int d = 0; d < 2; ++d) s[i][d] = s[0][d] + 0.5 * (s[i][d] - s[0][d]);
-          fv[i] = f(s[i]);
-          ++n;
-          if (*failed) return n;
-        }
-      }
-    }
-  }
-  int best = 0;
-  for (int i = 1; i < 3; ++i) if (fv[i] < fv[best]) best = i;
-  x[0] = s[best][0];
-  x[1] = s[best][1];
-  *fbest = fv[best];
-  *nev = n;
-  return n;
-}
 
 // least squares y = p0 + p1 x + p2 x^2 through (x_i, y_i), normal equations in FP64
 void quad_fit(const double* x, const double* y, int n, double out[3]) {
@@ -350,6 +271,18 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
     snprintf(err, errlen, "tuning set-up: %s", hipGetErrorString(e));
     return LYA_EHIP;
   }
+  if (mode == LYA_TUNE_EMULATOR) {  // the emulator must predict (Fbar, P_1..P_nk)
+    int32_t n_out = 0;
+    if ((e = hipMemcpyAsync(&n_out, spec->emulator, sizeof(n_out), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      snprintf(err, errlen, "reading the emulator header: %s", hipGetErrorString(e));
+      return LYA_EHIP;
+    }
+    if (n_out != 1 + nk) {
+      snprintf(err, errlen, "emulator has %d outputs, tuning needs 1 + n_kbins = %d", n_out, 1 + nk);
+      return LYA_EINVAL;
+    }
+  }
   memset(res, 0, sizeof(*res));
   for (int zi = 0; zi < spec->n_zt; ++zi) {
     const double z = spec->z_t[zi], cc = spec->c_t[zi], fbt = spec->fbar_t[zi];
@@ -361,38 +294,64 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
       double fb;
       last = ev.eval(exp(t[0]), exp(t[1]), cc, z, &fb, pk);
       if (last != hipSuccess) { failed = true; return HUGE_VAL; }
-      return chi2_of(fb, pk, fbt, pkt, nk, spec->sigma_rel);
+      return tune_chi2(fb, pk, fbt, pkt, nk, spec->sigma_rel);
     };
-    auto emul = [&](const double* t) -> double {
-      double fb;
-      last = emulator_predict(spec->emulator, exp(t[0]), exp(t[1]), cc, z, &fb, pk, nk,
-                              reinterpret_cast<char*>(w + c.emu), st);
-      if (last != hipSuccess) { failed = true; return HUGE_VAL; }
-      return chi2_of(fb, pk, fbt, pkt, nk, spec->sigma_rel);
-    };
+    double off_f = 0.0, off_p[kMaxKBins] = {0.0};
     double x[2] = {log(spec->a0), log(spec->b0)};
-    double fbest = 0.0;
-    int nev = 0;
+    double fbest = 0.0, fb = 0.0;
+    int nev = 0, gpu_ev = 0;
     if (mode == LYA_TUNE_EMULATOR) {
-      nelder_mead2(emul, x, 0.3, spec->xatol, spec->fatol, spec->max_evals, &fbest, &nev, &failed);
+      // search on the emulator, check the point on the GPU, move the emulator's
+      // prediction onto the measured statistics there (defect correction) and
+      // search again from that point; stop when the checked point no longer
+      // moves or after `emu_checks` GPU evaluations
+      const int checks = spec->emu_checks > 0 ? spec->emu_checks : 1;
+      double step = 0.3;
+      for (int it = 0; it < checks; ++it) {
+        int n1 = 0;
+        const double xprev[2] = {x[0], x[1]};
+        EmuSearchSpec ss{fbt, off_f, cc, z, step, spec->xatol, spec->fatol, spec->sigma_rel, nk, spec->max_evals,
+                         pkt, off_p};
+        double pe[kMaxKBins], fe;
+        if ((last = emulator_search(spec->emulator, ss, x, &fbest, &n1, &fe, pe, reinterpret_cast<char*>(w + c.emu),
+                                    st)) != hipSuccess) {
+          failed = true;
+          break;
+        }
+        nev += n1;
+        if ((last = ev.eval(exp(x[0]), exp(x[1]), cc, z, &fb, pk)) != hipSuccess) {
+          failed = true;
+          break;
+        }
+        ++gpu_ev;
+        off_f = fb - fe;
+        for (int i = 0; i < nk; ++i) off_p[i] = pk[i] - pe[i];
+        const double moved = fmax(fabs(x[0] - xprev[0]), fabs(x[1] - xprev[1]));
+        if (it > 0 && moved <= 10.0 * spec->xatol) break;
+        step = 0.05;
+      }
     } else {
       nelder_mead2(plain, x, 0.3, spec->xatol, spec->fatol, spec->max_evals, &fbest, &nev, &failed);
+      gpu_ev = nev;
     }
     if (failed) {
       snprintf(err, errlen, "tuning evaluation at z=%g: %s", z, hipGetErrorString(last));
       return LYA_EHIP;
     }
-    // statistics actually reached (one GPU evaluation)
-    double fb;
-    if ((e = ev.eval(exp(x[0]), exp(x[1]), cc, z, &fb, pk)) != hipSuccess) {
-      snprintf(err, errlen, "tuning evaluation: %s", hipGetErrorString(e));
-      return LYA_EHIP;
+    if (mode != LYA_TUNE_EMULATOR) {
+      // statistics actually reached (one GPU evaluation)
+      if ((e = ev.eval(exp(x[0]), exp(x[1]), cc, z, &fb, pk)) != hipSuccess) {
+        snprintf(err, errlen, "tuning evaluation: %s", hipGetErrorString(e));
+        return LYA_EHIP;
+      }
+      ++gpu_ev;
     }
     res->a[zi] = exp(x[0]);
     res->b[zi] = exp(x[1]);
     res->fbar[zi] = fb;
-    res->chi2[zi] = chi2_of(fb, pk, fbt, pkt, nk, spec->sigma_rel);
+    res->chi2[zi] = tune_chi2(fb, pk, fbt, pkt, nk, spec->sigma_rel);
     res->evals[zi] = nev;
+    res->gpu_evals[zi] = gpu_ev;
     for (int i = 0; i < nk; ++i) res->p1d[zi * kMaxKBins + i] = pk[i];
   }
   double xs[16], ys[3][16];
@@ -405,8 +364,12 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
   for (int p = 0; p < 3; ++p) {
     if (spec->n_zt >= 3) {
       quad_fit(xs, ys[p], spec->n_zt, res->coef[p]);
+    } else if (spec->n_zt == 2) {  // the line through both points
+      res->coef[p][1] = (ys[p][1] - ys[p][0]) / (xs[1] - xs[0]);
+      res->coef[p][0] = ys[p][0] - res->coef[p][1] * xs[0];
+      res->coef[p][2] = 0.0;
     } else {
-      res->coef[p][0] = spec->n_zt ? ys[p][0] : 0.0;
+      res->coef[p][0] = ys[p][0];
       res->coef[p][1] = res->coef[p][2] = 0.0;
     }
   }

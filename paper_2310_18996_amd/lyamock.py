@@ -244,13 +244,14 @@ class TuneSpec(ctypes.Structure):
                 ("fbar_t", ctypes.c_double * TUNE_MAX_Z), ("p1d_t", ctypes.c_void_p), ("p1d", P1dSpec),
                 ("a0", ctypes.c_double), ("b0", ctypes.c_double), ("sigma_rel", ctypes.c_double),
                 ("xatol", ctypes.c_double), ("fatol", ctypes.c_double), ("max_evals", ctypes.c_int32),
-                ("emulator", ctypes.c_void_p)]
+                ("emulator", ctypes.c_void_p), ("emu_checks", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double * TUNE_MAX_Z), ("b", ctypes.c_double * TUNE_MAX_Z),
                 ("chi2", ctypes.c_double * TUNE_MAX_Z), ("fbar", ctypes.c_double * TUNE_MAX_Z),
                 ("p1d", ctypes.c_double * (TUNE_MAX_Z * 64)), ("evals", ctypes.c_int32 * TUNE_MAX_Z),
+                ("gpu_evals", ctypes.c_int32 * TUNE_MAX_Z),
                 ("coef", (ctypes.c_double * 3) * 3), ("seconds", ctypes.c_double)]
 
 

@@ -1,0 +1,81 @@
+"""The C-ABI library: every function declared in include/lyamock.h is
+exported, the ctypes structures of the binding match the C layout, and the
+pure host-side size queries answer without a GPU (no kernel is launched)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2310_18996_amd import lyamock as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lyamock.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(lya_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_binding_exports():
+    names = declared_functions()
+    assert len(names) >= 20
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_library_exports_every_declared_function():
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+STRUCTS = {
+    "lya_box": L.Box, "lya_pk": L.Pk, "lya_skewers": L.Skewers, "lya_ps1d": L.Ps1d, "lya_fgpa": L.Fgpa,
+    "lya_cosmo": L.Cosmo, "lya_zbins": L.ZBins, "lya_p1d_spec": L.P1dSpec, "lya_tune_spec": L.TuneSpec,
+    "lya_tune_result": L.TuneResult,
+}
+
+
+def test_ctypes_structures_match_the_c_layout():
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lyamock.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, py in STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_host_size_queries():
+    b = L.Box(n=64, dx=2.0, storage=L.LYA_F32)
+    pitch = L.plane_pitch(b)
+    assert pitch == 64 * 64 + 32
+    assert L.field_elems(b) == 64 * pitch
+    assert L.p1d_workspace_size(1000, 16) > 1000 * 16 * 12
+    assert L.p1d_workspace_size(10, 0) == 0 and L.p1d_workspace_size(10, 65) == 0
+    assert L.tune_workspace_size(100, 16) > 0 and L.tune_workspace_size(-1, 16) == 0
+    n_out = 33
+    assert L.emulator_param_count(n_out) == 4 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * n_out + n_out
+    assert L.emulator_param_count(0) == 0 and L.emulator_param_count(65) == 0
+    assert L.emulator_bytes(n_out) >= L.emulator_param_offset() + 3 * 4 * L.emulator_param_count(n_out)
+    assert L.emulator_train_workspace_size(256, n_out) > 256 * 256 * 4 * 9
+    assert L.emulator_train_workspace_size(0, n_out) == 0

@@ -1,0 +1,296 @@
+"""GPU tuning (lya_tune_params, plain and emulator-driven) and the emulator
+kernels (lya_emulator_*) against the FP64 oracle: gradients, the first Adam
+step, predictions, training labels, and emulator-driven against plain
+tuning on the same stored pixels."""
+import ctypes
+import time
+
+import numpy as np
+import pytest
+
+import mockinputs
+from oracle import field, mlp, p1d, power, skewers, tune
+from tests.lyahelp import rel_rms
+
+pytestmark = pytest.mark.gpu
+N_OUT = 17          # mean flux + 16 P1D bins in these tests
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_18996_amd import lyamock
+    lyamock.load()
+    return lyamock
+
+
+@pytest.fixture(scope="module")
+def mock():
+    """Stored pre-FGPA pixels of a small oracle mock (32^3 box, 60 skewers of
+    200-1200 pixels)."""
+    cfg = mockinputs.config("mid", n=32, n_sk=60)
+    tab = power.amplitude_table(power.PowerSpectrum(**cfg["pk"]), 32, cfg["dx"])
+    box = field.make_box(32, 5, tab, ("delta", "zz"))
+    sk = mockinputs.skewer_table(cfg)
+    dens, eta = skewers.draw_skewers(box.real, box.imag, sk, 5, 0.5, 1.5, 0.2)
+    return sk, dens.astype(np.float32), eta.astype(np.float32)
+
+
+class Spec:
+    """lya_tune_spec with its device buffers kept alive."""
+
+    def __init__(self, L, sk, dens, eta, k_edges, z_t, c_t, fbar_t, pk_t, a0=0.25, b0=1.0, emulator=None,
+                 checks=4, max_evals=400):
+        import torch
+        from tests.lyahelp import skewer_tensors
+        self.s, self.keep = skewer_tensors(L, sk)
+        self.dens = torch.from_numpy(np.ascontiguousarray(dens, np.float32)).cuda()
+        self.eta = torch.from_numpy(np.ascontiguousarray(eta, np.float32)).cuda()
+        self.ke = torch.from_numpy(np.asarray(k_edges, np.float64)).cuda()
+        nk = len(k_edges) - 1
+        self.pk_t = np.ascontiguousarray(np.asarray(pk_t, np.float64).reshape(len(z_t), nk))
+        sp = L.TuneSpec()
+        sp.sk = ctypes.pointer(self.s)
+        sp.dens = self.dens.data_ptr()
+        sp.eta = self.eta.data_ptr()
+        sp.cosmo = L.Cosmo(0.3147)
+        sp.n_zt = len(z_t)
+        for i in range(len(z_t)):
+            sp.z_t[i], sp.c_t[i], sp.fbar_t[i] = z_t[i], c_t[i], fbar_t[i]
+        sp.p1d_t = self.pk_t.ctypes.data
+        sp.p1d = L.P1dSpec(nk, self.ke.data_ptr(), 0.0, 0.2)
+        sp.a0, sp.b0 = a0, b0
+        sp.sigma_rel = tune.SIGMA_REL
+        sp.xatol, sp.fatol = 1e-6, 1e-8
+        sp.max_evals = max_evals
+        sp.emulator = None if emulator is None else emulator.data_ptr()
+        sp.emu_checks = checks
+        self.spec = sp
+        self.work = torch.empty(L.tune_workspace_size(len(sk["npix"]), nk), dtype=torch.uint8, device="cuda")
+
+
+K_EDGES = p1d.log_k_edges(N_OUT - 1, 0.002, 0.05)
+
+
+def test_plain_tuning_recovers_known_parameters(L, mock):
+    sk, dens, eta = mock
+    z_t = [2.1, 2.6, 3.1]
+    c_t = [1.1, 1.2, 1.3]
+    truth = [(0.2, 1.5), (0.35, 1.4), (0.6, 1.3)]
+    tg = [tune.evaluate(dens, eta, sk, a, b, c, z, K_EDGES, 0.2) for (a, b), c, z in zip(truth, c_t, z_t)]
+    sp = Spec(L, sk, dens, eta, K_EDGES, z_t, c_t, [t[0] for t in tg], np.stack([t[1] for t in tg]))
+    print("plain tuning, 3 redshifts", flush=True)
+    res = L.tune_params(sp.spec, L.LYA_TUNE_PLAIN, sp.work)
+    for i, (a, b) in enumerate(truth):
+        print("z=%.1f a=%.6f (%.6f) b=%.6f (%.6f) chi2=%.3g evals=%d" % (z_t[i], res.a[i], a, res.b[i], b,
+                                                                        res.chi2[i], res.evals[i]))
+        assert abs(res.a[i] / a - 1) < 2e-3 and abs(res.b[i] / b - 1) < 2e-3
+        assert res.gpu_evals[i] == res.evals[i] + 1
+        # the statistics reported are the oracle's at the parameters found
+        fb, pk = tune.evaluate(dens, eta, sk, res.a[i], res.b[i], c_t[i], z_t[i], K_EDGES, 0.2)
+        assert abs(res.fbar[i] / fb - 1) < 1e-5
+        assert rel_rms(np.array(res.p1d[i * 64:i * 64 + N_OUT - 1]), pk) < 1e-5
+    coef = tune.fit_quadratics(z_t, [res.a[i] for i in range(3)], [res.b[i] for i in range(3)], c_t)
+    np.testing.assert_allclose(np.array(res.coef), np.array(coef), rtol=1e-9, atol=1e-12)
+    assert res.seconds > 0
+
+
+def _upload_params(L, emu, params):
+    import torch
+    off = L.emulator_param_offset()
+    flat = np.concatenate([p.reshape(-1) for p in params]).astype(np.float32)
+    view = emu[off:off + 4 * flat.size].view(torch.float32)
+    view.copy_(torch.from_numpy(flat))
+    torch.cuda.synchronize()
+    return flat
+
+
+def _new_emulator(L, n_out, log_from, seed=7, lo=(-1, -1, -1, -1), hi=(1, 1, 1, 1)):
+    import torch
+    emu = torch.zeros(L.emulator_bytes(n_out), dtype=torch.uint8, device="cuda")
+    L.emulator_init(emu, n_out, log_from, seed, lo, hi)
+    torch.cuda.synchronize()
+    return emu
+
+
+def _oracle_params(seed, n_out):
+    params = mlp.init_params(seed, (4, 256, 256, 256, n_out))
+    rng = np.random.default_rng(seed + 100)
+    for i in range(1, len(params), 2):
+        params[i] += rng.normal(0, 0.1, params[i].shape)
+    return [p.astype(np.float32).astype(np.float64) for p in params]
+
+
+@pytest.mark.parametrize("batch", [64, 50, 200])
+def test_gradients_match_oracle(L, batch):
+    import torch
+    print("emulator gradient batch %d" % batch, flush=True)
+    params = _oracle_params(1, N_OUT)
+    emu = _new_emulator(L, N_OUT, N_OUT)
+    _upload_params(L, emu, params)
+    rng = np.random.default_rng(batch)
+    x0 = rng.uniform(-1, 1, (batch, 4)).astype(np.float32)
+    t = rng.normal(size=(batch, N_OUT)).astype(np.float32)
+    loss_r, grads_r = mlp.backward(params, x0.astype(np.float64), t.astype(np.float64))
+    work = torch.empty(L.emulator_train_workspace_size(batch, N_OUT), dtype=torch.uint8, device="cuda")
+    npar = L.emulator_param_count(N_OUT)
+    for bf16, tol in ((False, 1e-5), (True, 2e-2)):
+        g = torch.full((npar,), float("nan"), dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        L.emulator_loss_grad(emu, torch.from_numpy(x0).cuda(), torch.from_numpy(t).cuda(), batch, bf16, g, loss,
+                             work)
+        torch.cuda.synchronize()
+        g = g.cpu().numpy().astype(np.float64)
+        o = 0
+        errs = []
+        for gr in grads_r:
+            errs.append(rel_rms(g[o:o + gr.size], gr.reshape(-1)))
+            o += gr.size
+        print("bf16" if bf16 else "fp32", "loss %.8g vs %.8g, grad rel rms per tensor" % (loss.item(), loss_r),
+              ["%.2e" % e for e in errs])
+        assert abs(loss.item() / loss_r - 1) < tol
+        assert max(errs) < tol
+
+
+def test_first_adam_step_is_lr_sign(L):
+    import torch
+    params = _oracle_params(2, N_OUT)
+    emu = _new_emulator(L, N_OUT, N_OUT)
+    p0 = _upload_params(L, emu, params)
+    rng = np.random.default_rng(3)
+    B = 128
+    x = rng.uniform(-1, 1, (B, 4)).astype(np.float32)
+    y = rng.normal(size=(B, N_OUT)).astype(np.float32)
+    _, grads = mlp.backward(params, x.astype(np.float64), y.astype(np.float64))
+    g = np.concatenate([gr.reshape(-1) for gr in grads])
+    work = torch.empty(L.emulator_train_workspace_size(B, N_OUT), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lr = 1e-3
+    L.emulator_train(emu, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), B, 1, B, lr, False, hist, work)
+    off = L.emulator_param_offset()
+    p1 = emu[off:off + 4 * p0.size].view(torch.float32).cpu().numpy()
+    big = np.abs(g) > 1e-4
+    assert big.sum() > 0.5 * g.size
+    np.testing.assert_allclose((p1 - p0)[big], -lr * np.sign(g[big]), rtol=2e-3, atol=0)
+    assert abs(hist.item() / mlp.loss(params, x, y) - 1) < 1e-5
+
+
+def test_predict_and_scaling_match_oracle(L):
+    import torch
+    params = _oracle_params(4, N_OUT)
+    lo, hi = (0.1, 1.0, 0.5, 1.8), (2.0, 2.2, 2.0, 3.6)
+    emu = _new_emulator(L, N_OUT, 1, lo=lo, hi=hi)
+    _upload_params(L, emu, params)
+    rng = np.random.default_rng(5)
+    lab = np.exp(rng.normal(size=(300, N_OUT)) * 0.3 + 1.0).astype(np.float32)
+    lab[:, 0] = rng.uniform(0.3, 0.8, 300)
+    L.emulator_set_scaling(emu, torch.from_numpy(lab).cuda(), 300)
+    torch.cuda.synchronize()
+    hdr = emu[:2048].cpu().numpy()
+    fl = hdr.view(np.float32)
+    mean, std = fl[12:12 + 64][:N_OUT], fl[12 + 64:12 + 128][:N_OUT]
+    col = np.concatenate([lab[:, :1].astype(np.float64), np.log(lab[:, 1:].astype(np.float32)).astype(np.float64)],
+                         axis=1)
+    np.testing.assert_allclose(mean, col.mean(0), rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(std, col.std(0), rtol=1e-4)
+    x = np.stack([rng.uniform(a, b, 37) for a, b in zip(lo, hi)], axis=1).astype(np.float32)
+    yg = torch.zeros((37, N_OUT), dtype=torch.float32, device="cuda")
+    L.emulator_predict(emu, torch.from_numpy(x).cuda(), 37, yg)
+    torch.cuda.synchronize()
+    x0 = 2 * (x.astype(np.float64) - np.array(lo)) / (np.array(hi) - np.array(lo)) - 1
+    f, _ = mlp.forward(params, x0)
+    ref = f * std.astype(np.float64) + mean.astype(np.float64)
+    ref[:, 1:] = np.exp(ref[:, 1:])
+    assert rel_rms(yg.cpu().numpy(), ref) < 1e-5
+
+
+def test_bf16_training_fits_a_smooth_map(L):
+    import torch
+    emu = _new_emulator(L, 3, 3, seed=11)
+    rng = np.random.default_rng(6)
+    n = 4096
+    x = rng.uniform(-1, 1, (n, 4)).astype(np.float32)
+    y = np.stack([np.sin(2 * x[:, 0]) + x[:, 1] * x[:, 2], np.cos(x[:, 3]) * x[:, 0], x[:, 1] ** 2], 1)
+    y = y.astype(np.float32)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    L.emulator_set_scaling(emu, yd, n)
+    B, steps = 256, 1500
+    work = torch.empty(L.emulator_train_workspace_size(B, 3), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    L.emulator_train(emu, xd, yd, n, steps, B, 1e-3, True, hist, work)
+    h = hist.cpu().numpy()
+    print("bf16 training loss first %.4g last-50 mean %.4g" % (h[:10].mean(), h[-50:].mean()))
+    assert np.all(np.isfinite(h))
+    assert h[-50:].mean() < 0.02 * h[:10].mean()
+
+
+def test_labels_match_oracle(L, mock):
+    import torch
+    sk, dens, eta = mock
+    draws = mockinputs.emulator_draws(6, seed=9)
+    sp = Spec(L, sk, dens, eta, K_EDGES, [2.5], [1.0], [0.5], np.ones((1, N_OUT - 1)))
+    y = torch.full((6, N_OUT), float("nan"), dtype=torch.float32, device="cuda")
+    L.emulator_labels(sp.spec, draws, y, sp.work)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    for i, (a, b, c, z) in enumerate(draws):
+        fb, pk = tune.evaluate(dens, eta, sk, a, b, c, z, K_EDGES, 0.2)
+        assert abs(y[i, 0] / fb - 1) < 1e-5
+        ok = np.isfinite(pk)
+        np.testing.assert_array_equal(np.isfinite(y[i, 1:]), ok)
+        assert rel_rms(y[i, 1:][ok], pk[ok]) < 1e-5
+
+
+def test_emulator_tuning_matches_plain_with_fewer_gpu_evaluations(L, mock):
+    """The learned part's gain: tuning driven by a GPU-trained emulator reaches
+    the plain loop's statistics within 0.5% with a few GPU evaluations per
+    redshift instead of one per search step."""
+    import torch
+    sk, dens, eta = mock
+    n_lab = 3000
+    draws = mockinputs.emulator_draws(n_lab, seed=21)
+    z_t = [2.0, 2.4, 2.8, 3.2]
+    c_t = [1.0, 1.1, 1.2, 1.3]
+    fbar_t = list(tune.fbar_target(z_t))
+    pk_t = np.stack([tune.evaluate(dens, eta, sk, 0.3 * (1 + z) / 3.4, 1.5, c, z, K_EDGES, 0.2)[1]
+                     for z, c in zip(z_t, c_t)])
+    pk_t = np.where(np.isfinite(pk_t), pk_t, np.nan)
+    sp = Spec(L, sk, dens, eta, K_EDGES, z_t, c_t, fbar_t, pk_t)
+    y = torch.empty((n_lab, N_OUT), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    L.emulator_labels(sp.spec, draws, y, sp.work)
+    torch.cuda.synchronize()
+    t_lab = time.perf_counter() - t0
+    emu = _new_emulator(L, N_OUT, 1, seed=3, lo=(0.1, 1.0, 0.5, 1.8), hi=(2.0, 2.2, 2.0, 3.6))
+    xd = torch.from_numpy(draws.astype(np.float32)).cuda()
+    L.emulator_set_scaling(emu, y, n_lab)
+    B, steps = 256, 4000
+    work = torch.empty(L.emulator_train_workspace_size(B, N_OUT), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    L.emulator_train(emu, xd, y, n_lab, steps, B, 1e-3, True, hist, work)
+    t_train = time.perf_counter() - t0
+    h = hist.cpu().numpy()
+    print("labels %.2f s, training %.2f s, loss %.3g -> %.3g" % (t_lab, t_train, h[:10].mean(), h[-100:].mean()))
+    rp = L.tune_params(sp.spec, L.LYA_TUNE_PLAIN, sp.work)
+    sp_e = Spec(L, sk, dens, eta, K_EDGES, z_t, c_t, fbar_t, pk_t, emulator=emu, checks=6)
+    re_ = L.tune_params(sp_e.spec, L.LYA_TUNE_EMULATOR, sp_e.work)
+    nk = N_OUT - 1
+    for i in range(len(z_t)):
+        pp = np.array(rp.p1d[i * 64:i * 64 + nk])
+        pe = np.array(re_.p1d[i * 64:i * 64 + nk])
+        ok = np.isfinite(pk_t[i])
+        df = abs(re_.fbar[i] / rp.fbar[i] - 1)
+        dp = np.max(np.abs(pe[ok] / pp[ok] - 1))
+        print("z=%.1f plain a=%.4f b=%.4f gpu evals %d | emulator a=%.4f b=%.4f gpu evals %d; dFbar %.2e dP %.2e"
+              % (z_t[i], rp.a[i], rp.b[i], rp.gpu_evals[i], re_.a[i], re_.b[i], re_.gpu_evals[i], df, dp))
+        assert df < 5e-3 and dp < 5e-3
+        assert re_.gpu_evals[i] * 10 <= rp.gpu_evals[i]
+    print("tuning wall time: plain %.3f s, emulator %.3f s" % (rp.seconds, re_.seconds))
+    assert re_.seconds < rp.seconds
+    # an emulator whose outputs do not match the k bins is refused
+    sp_bad = Spec(L, sk, dens, eta, K_EDGES[:-1], z_t, c_t, fbar_t, pk_t[:, :-1], emulator=emu)
+    with pytest.raises(L.LyaError):
+        L.tune_params(sp_bad.spec, L.LYA_TUNE_EMULATOR, sp_bad.work)
