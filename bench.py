@@ -11,6 +11,14 @@ events on the launch stream).  `roofline` reports the dominant kernel's
 algorithmic bytes per launch over its mean launch time against 8 TB/s.
 `cpu_baseline` times the FP64 oracle on the host on a bounded sample of the
 same workload (same cells-to-pixels ratio), scaled to cells per second.
+
+`tune` (after the timed steps, not part of them): FGPA tuning at five
+redshifts against a target mean flux (0.75 -> 0.35) and the P1D of a truth
+512^3 mock made with another seed, on the stored pixels of the 512^3 mid mock;
+the plain loop (every search point evaluated on the GPU) against the
+emulator-driven search (MLP trained on the GPU on labels of one 256^3 mock
+with 20,000 skewers), with wall times, the label and training cost, and the
+relative difference of the statistics both reach.
 """
 import argparse
 import json
@@ -93,6 +101,161 @@ def cpu_baseline(cfg, pixels_per_cell, budget_n=256):
                            budget_n, cells, ns, pix, t1 - t0, t2 - t1))
 
 
+# ---------------------------------------------------------------- tuning leg
+def stored_pixels(L, torch, cfg, seed, sk_seed):
+    """Pre-FGPA pixels (delta_L + delta_S, eta_par) of a mock made by the
+    library: box of cfg, skewer table drawn with sk_seed."""
+    import mockinputs
+    sk = mockinputs.skewer_table(cfg, seed=sk_seed)
+    box = L.box_struct(cfg["n"], cfg["dx"])
+    field = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    L.make_box(box, L.pk_struct(**cfg["pk"]), seed, cfg["f"], True, field, work)
+    del work
+    dev = {k: torch.from_numpy(np.ascontiguousarray(sk[k])).cuda()
+           for k in ("origin_fx", "step_fx", "npix", "offset", "chi0")}
+    s = L.skewers_struct(len(sk["npix"]), dev["origin_fx"], dev["step_fx"], dev["npix"], dev["offset"], dev["chi0"],
+                         sk["dchi"])
+    dens = torch.empty(sk["total"], dtype=torch.float32, device="cuda")
+    eta = torch.empty_like(dens)
+    work = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    L.draw_skewers(box, field, s, L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0), seed,
+                   L.Cosmo(cfg["omega_m"]), None, dens, eta, None, None, work)
+    torch.cuda.synchronize()
+    del field, work
+    return dict(s=s, dev=dev, dens=dens, eta=eta, n_sk=len(sk["npix"]), pixels=sk["total"])
+
+
+def truth_targets(L, torch, mock, cosmo, z_t, b_t, c_t, fbar_t, k_edges, dpix):
+    """Targets measured on the truth mock: at each z_t its a is set (bisection
+    in ln a, b and c held at the hidden values) so that the mean flux of all
+    stored pixels is fbar_t; the P1D target is the truth mock's P1D there."""
+    s = mock["s"]
+    flux = torch.empty_like(mock["dens"])
+    edges = torch.tensor([-1e30, 1e30], dtype=torch.float64, device="cuda")
+    fsum = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    zb = L.zbins_struct(edges, fsum, cnt)
+    work = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS), dtype=torch.uint8, device="cuda")
+    nk = k_edges.numel() - 1
+    pwork = torch.empty(L.p1d_workspace_size(mock["n_sk"], nk), dtype=torch.uint8, device="cuda")
+    psum = torch.zeros(nk, dtype=torch.float64, device="cuda")
+    pcnt = torch.zeros(nk, dtype=torch.int64, device="cuda")
+    a_t, pk_t = [], []
+    for z, b, c, ft in zip(z_t, b_t, c_t, fbar_t):
+        def fbar(a, want_flux=False):
+            L.apply_fgpa(s, cosmo, mock["dens"], mock["eta"], L.fgpa_struct([[a, 0, 0], [b, 0, 0], [c, 0, 0]]),
+                         flux if want_flux else None, zb, work)
+            return float(fsum.item()) / float(cnt.item())
+        lo, hi = np.log(1e-4), np.log(1e2)
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            if fbar(np.exp(mid)) > ft:
+                lo = mid
+            else:
+                hi = mid
+        a = float(np.exp(0.5 * (lo + hi)))
+        fbar(a, True)
+        spec = L.P1dSpec(nk, k_edges.data_ptr(), float(z), float(dpix))
+        L.p1d(s, cosmo, flux, zb, spec, psum, pcnt, pwork)
+        pc = pcnt.cpu().numpy()
+        pk_t.append(np.where(pc > 0, psum.cpu().numpy() / np.maximum(pc, 1), np.nan))
+        a_t.append(a)
+    return np.array(a_t), np.stack(pk_t)
+
+
+def tune_leg(L, torch, n_labels, train_steps):
+    """Plain against emulator-driven tuning; returns the `tune` record."""
+    import mockinputs
+    z_t = mockinputs.TUNE_Z
+    c_t = mockinputs.tune_c(z_t)
+    b_true = mockinputs.tune_b_truth(z_t)
+    fbar_t = mockinputs.fbar_target(z_t)
+    k_edges = torch.from_numpy(mockinputs.tune_k_edges()).cuda()
+    nk = k_edges.numel() - 1
+    mid = mockinputs.config("mid")
+    cosmo = L.Cosmo(mid["omega_m"])
+    t0 = time.perf_counter()
+    truth = stored_pixels(L, torch, mid, 4321, 4321)
+    a_true, pk_t = truth_targets(L, torch, truth, cosmo, z_t, b_true, c_t, fbar_t, k_edges, mid["dpix"])
+    del truth
+    mock = stored_pixels(L, torch, mid, mid["seed"], mid["seed"])
+    t_mocks = time.perf_counter() - t0
+    print("bench: tuning targets and mocks ready (%.1f s)" % t_mocks, file=sys.stderr, flush=True)
+    spec, keep = L.tune_spec(mock["s"], mock["dens"], mock["eta"], cosmo, z_t, c_t, fbar_t, pk_t, k_edges,
+                             mid["dpix"], a0=0.3, b0=1.5)
+    work = torch.empty(L.tune_workspace_size(mock["n_sk"], nk), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp = L.tune_params(spec, L.LYA_TUNE_PLAIN, work)
+    t_plain = time.perf_counter() - t0
+    print("bench: plain tuning %.2f s" % t_plain, file=sys.stderr, flush=True)
+    # emulator: labels from one 256^3 mock with 20,000 skewers, then training
+    ecfg = mockinputs.config("emulator")
+    emock = stored_pixels(L, torch, ecfg, ecfg["seed"], ecfg["seed"])
+    espec, ekeep = L.tune_spec(emock["s"], emock["dens"], emock["eta"], cosmo, [2.5], [1.0], [0.5],
+                               np.ones((1, nk)), k_edges, ecfg["dpix"])
+    ework = torch.empty(L.tune_workspace_size(emock["n_sk"], nk), dtype=torch.uint8, device="cuda")
+    draws = mockinputs.emulator_draws(n_labels, seed=ecfg["seed"])
+    y = torch.empty((n_labels, 1 + nk), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.emulator_labels(espec, draws, y, ework)
+    torch.cuda.synchronize()
+    t_labels = time.perf_counter() - t0
+    print("bench: %d labels %.1f s" % (n_labels, t_labels), file=sys.stderr, flush=True)
+    del emock, ework
+    emu = torch.zeros(L.emulator_bytes(1 + nk), dtype=torch.uint8, device="cuda")
+    L.emulator_init(emu, 1 + nk, 1, ecfg["seed"], (0.1, 1.0, 0.5, 1.8), (2.0, 2.2, 2.0, 3.6))
+    x = torch.from_numpy(draws.astype(np.float32)).cuda()
+    L.emulator_set_scaling(emu, y, n_labels)
+    B = 512
+    twork = torch.empty(L.emulator_train_workspace_size(B, 1 + nk), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(train_steps, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n1 = (3 * train_steps) // 4
+    L.emulator_train(emu, x, y, n_labels, n1, B, 1e-3, True, hist, twork)
+    L.emulator_train(emu, x, y, n_labels, train_steps - n1, B, 2e-4, True, hist[n1:], twork)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    h = hist.cpu().numpy()
+    print("bench: training %d steps %.1f s, loss %.3g -> %.3g" % (train_steps, t_train, h[:20].mean(),
+                                                                  h[-200:].mean()), file=sys.stderr, flush=True)
+    spec_e, keep_e = L.tune_spec(mock["s"], mock["dens"], mock["eta"], cosmo, z_t, c_t, fbar_t, pk_t, k_edges,
+                                 mid["dpix"], a0=0.3, b0=1.5, emulator=emu, emu_checks=6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    re_ = L.tune_params(spec_e, L.LYA_TUNE_EMULATOR, work)
+    t_emu = time.perf_counter() - t0
+    print("bench: emulator tuning %.3f s" % t_emu, file=sys.stderr, flush=True)
+    n = len(z_t)
+    dfb = [abs(re_.fbar[i] / rp.fbar[i] - 1) for i in range(n)]
+    dpk = []
+    for i in range(n):
+        pp = np.array(rp.p1d[i * 64:i * 64 + nk])
+        pe = np.array(re_.p1d[i * 64:i * 64 + nk])
+        ok = np.isfinite(pp) & np.isfinite(pe)
+        dpk.append(float(np.max(np.abs(pe[ok] / pp[ok] - 1))) if ok.any() else float("nan"))
+    return dict(
+        workload="tune a(z), b(z) at z_t=%s with c(z_t) fixed, targets: mean flux 0.75->0.35 and the P1D of a "
+                 "truth 512^3 mock (other seed); tuned on the 512^3 mid mock (%d skewers, %d pixels); emulator "
+                 "trained on %d labels of one 256^3 mock with 20,000 skewers" % (
+                     list(z_t), mock["n_sk"], mock["pixels"], n_labels),
+        plain_s=t_plain, emulator_s=t_emu, speedup=t_plain / t_emu,
+        labels_s=t_labels, train_s=t_train, train_steps=train_steps, batch=B,
+        speedup_incl_labels_training=t_plain / (t_emu + t_labels + t_train),
+        train_loss_final=float(h[-200:].mean()),
+        gpu_evals_plain=[int(rp.gpu_evals[i]) for i in range(n)],
+        gpu_evals_emulator=[int(re_.gpu_evals[i]) for i in range(n)],
+        emulator_search_evals=[int(re_.evals[i]) for i in range(n)],
+        a_plain=[rp.a[i] for i in range(n)], b_plain=[rp.b[i] for i in range(n)],
+        a_emulator=[re_.a[i] for i in range(n)], b_emulator=[re_.b[i] for i in range(n)],
+        a_truth=list(a_true), chi2_plain=[rp.chi2[i] for i in range(n)], chi2_emulator=[re_.chi2[i] for i in range(n)],
+        max_rel_dfbar=float(max(dfb)), max_rel_dp1d=float(np.nanmax(dpk)),
+        coef_plain=[list(r) for r in rp.coef], coef_emulator=[list(r) for r in re_.coef])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +264,9 @@ def main():
     ap.add_argument("--config", default="big", choices=["tiny", "mid", "big", "precision", "emulator"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=192)
+    ap.add_argument("--no-tune", action="store_true", help="skip the tuning leg")
+    ap.add_argument("--tune-labels", type=int, default=100_000)
+    ap.add_argument("--tune-steps", type=int, default=20_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 4 GiB device copy first (reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -111,7 +277,6 @@ def main():
 
     import torch
     import mockinputs
-    from oracle import fgpa as ofgpa
     from paper_2310_18996_amd import lyamock as L
 
     L.load()
@@ -133,9 +298,8 @@ def main():
     dens = torch.empty(pixels, dtype=torch.float32, device="cuda")
     eta = torch.empty_like(dens)
     flux = torch.empty_like(dens)
-    # redshift-bin edges in comoving distance: the library's own host-side
-    # conversion is not exposed, the FP64 oracle's table of 23 numbers is used
-    edges = torch.from_numpy(ofgpa.chi_edges_for_z(cfg["z_edges"])).cuda()
+    # redshift-bin edges in comoving distance (the library's host conversion)
+    edges = torch.from_numpy(L.chi_of_z(cfg["z_edges"], cfg["omega_m"])).cuda()
     fsum = torch.zeros(len(cfg["z_edges"]) - 1, dtype=torch.float64, device="cuda")
     cnt = torch.zeros(len(cfg["z_edges"]) - 1, dtype=torch.int64, device="cuda")
     zb = L.zbins_struct(edges, fsum, cnt)
@@ -203,6 +367,13 @@ def main():
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
     else:
         out["cpu_baseline"] = None
+    if not args.no_tune:
+        del field, bwork, swork, dens, eta, flux, dev
+        torch.cuda.empty_cache()
+        print("bench: tuning leg", file=sys.stderr, flush=True)
+        out["tune"] = tune_leg(L, torch, args.tune_labels, args.tune_steps)
+    else:
+        out["tune"] = None
     print(json.dumps(out), flush=True)
 
 

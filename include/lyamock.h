@@ -307,6 +307,13 @@ int lya_timing_enable(int on);
 int lya_timing_collect(void);
 int lya_timing_get(int i, char* name, int name_len, double* total_ms, int64_t* launches);
 
+/* Comoving distance chi(z) = (c/H0) int_0^z dz'/E(z') in Mpc/h, E^2 =
+ * Omega_m (1+z)^3 + 1 - Omega_m (the flat background of the mocks, section
+ * "Mock generation"), for n host redshifts in [0, 1100] into host chi; FP64 Simpson
+ * rule with 4096 intervals.  Host-only (no GPU call): converts redshift-bin
+ * edges into the distance edges lya_zbins takes. */
+int lya_chi_of_z(const lya_cosmo* cosmo, int32_t n, const double* z, double* chi);
+
 /* Last error message of the calling thread ("" if none). */
 const char* lya_last_error(void);
 

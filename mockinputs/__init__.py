@@ -160,3 +160,35 @@ def emulator_draws(n, seed=1234):
     rng = np.random.default_rng([seed, 3])
     return np.stack([rng.uniform(0.1, 2.0, n), rng.uniform(1.0, 2.2, n),
                      rng.uniform(0.5, 2.0, n), rng.uniform(1.8, 3.6, n)], axis=1)
+
+
+# ---------------------------------------------------------------- tuning workload
+TUNE_Z = [1.8, 2.2, 2.6, 3.0, 3.6]
+TUNE_K_BINS = (32, 0.001, 0.05)      # 32 log-spaced P1D bins over [0.001, 0.05] s/km
+
+
+def fbar_target(z, f_lo=0.75, f_hi=0.35, z_lo=1.8, z_hi=3.6):
+    """Target mean transmission of the tuning workload: log-linear in z from
+    f_lo at z_lo to f_hi at z_hi."""
+    t = (np.asarray(z, dtype=np.float64) - z_lo) / (z_hi - z_lo)
+    return np.exp(np.log(f_lo) + t * (np.log(f_hi) - np.log(f_lo)))
+
+
+def tune_c(z):
+    """c(z_t) held fixed while tuning: the mid workload's c(z) quadratic."""
+    x = 1.0 + np.asarray(z, dtype=np.float64)
+    c = FGPA_MID[2]
+    return c[0] + c[1] * x + c[2] * x * x
+
+
+def tune_k_edges():
+    n, lo, hi = TUNE_K_BINS
+    return lo * (hi / lo) ** (np.arange(n + 1) / n)
+
+
+def tune_b_truth(z):
+    """b(z_t) of the hidden parameters of the truth mock: the mid workload's
+    b(z) quadratic."""
+    x = 1.0 + np.asarray(z, dtype=np.float64)
+    b = FGPA_MID[1]
+    return b[0] + b[1] * x + b[2] * x * x

@@ -70,9 +70,3 @@ def fit_quadratics(z_t, a_t, b_t, c_t):
         p = np.polyfit(x, np.asarray(vals, dtype=np.float64), 2)   # highest power first
         out.append([p[2], p[1], p[0]])
     return out
-
-
-def fbar_target(z, f_lo=0.75, f_hi=0.35, z_lo=1.8, z_hi=3.6):
-    """Log-linear target mean transmission of the tuning workload."""
-    t = (np.asarray(z, dtype=np.float64) - z_lo) / (z_hi - z_lo)
-    return np.exp(np.log(f_lo) + t * (np.log(f_hi) - np.log(f_lo)))

@@ -293,6 +293,27 @@ int lya_p1d(const lya_skewers* sk, const lya_cosmo* cosmo, const float* flux, co
   return LYA_OK;
 }
 
+int lya_chi_of_z(const lya_cosmo* cosmo, int32_t n, const double* z, double* chi) {
+  g_err[0] = 0;
+  if (!cosmo || !(cosmo->omega_m >= 0.0 && cosmo->omega_m <= 1.0)) return fail(LYA_EINVAL, "invalid cosmo%s");
+  if (n < 0 || (n > 0 && (!z || !chi))) return fail(LYA_EINVAL, "invalid redshift arrays%s");
+  const double om = cosmo->omega_m;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!(z[i] >= 0.0 && z[i] <= 1100.0)) return fail(LYA_EINVAL, "redshift outside [0, 1100]%s");
+    // composite Simpson rule over [0, z] with 4096 intervals, FP64
+    constexpr int kN = 4096;
+    const double h = z[i] / kN;
+    double acc = 0.0;
+    for (int k = 0; k <= kN; ++k) {
+      const double x = 1.0 + k * h;
+      const double inv_e = 1.0 / sqrt(om * (x * x * x) + (1.0 - om));
+      acc += (k == 0 || k == kN ? 1.0 : (k & 1 ? 4.0 : 2.0)) * inv_e;
+    }
+    chi[i] = lya::kCOverH0 * acc * h / 3.0;
+  }
+  return LYA_OK;
+}
+
 const char* lya_last_error(void) { return g_err; }
 
 const char* lya_version(void) { return "lyamock 0.1 gfx950"; }

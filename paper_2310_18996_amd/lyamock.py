@@ -21,7 +21,7 @@ EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make
            "lya_tune_params", "lya_emulator_labels", "lya_emulator_bytes", "lya_emulator_param_offset",
            "lya_emulator_param_count", "lya_emulator_init", "lya_emulator_train_workspace_size",
            "lya_emulator_set_scaling", "lya_emulator_loss_grad", "lya_emulator_train", "lya_emulator_predict",
-           "lya_emulator_last_error", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
+           "lya_emulator_last_error", "lya_chi_of_z", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
            "lya_last_error", "lya_version")
 
 
@@ -288,6 +288,8 @@ def _bind_more(lib):
     lib.lya_emulator_predict.restype = ctypes.c_int
     lib.lya_emulator_predict.argtypes = [VP, VP, ctypes.c_int64, VP, VP]
     lib.lya_emulator_last_error.restype = ctypes.c_char_p
+    lib.lya_chi_of_z.restype = ctypes.c_int
+    lib.lya_chi_of_z.argtypes = [P(Cosmo), ctypes.c_int32, VP, VP]
 
 
 def _lib2():
@@ -374,3 +376,47 @@ def emulator_train(emu, x, y, n, steps, batch, lr, use_bf16, loss_hist, work, st
 
 def emulator_predict(emu, x, n, y, stream=None):
     _echeck(_lib2().lya_emulator_predict(_ptr(emu), _ptr(x), int(n), _ptr(y), _stream(stream)))
+
+
+def chi_of_z(z, omega_m=0.3147):
+    """lya_chi_of_z on the host: comoving distance (Mpc/h) of redshifts z."""
+    import numpy as np
+    zz = np.ascontiguousarray(np.atleast_1d(z), dtype=np.float64)
+    out = np.empty_like(zz)
+    _check(_lib2().lya_chi_of_z(ctypes.byref(Cosmo(float(omega_m))), int(zz.size), zz.ctypes.data,
+                                out.ctypes.data))
+    return out
+
+
+def tune_spec(sk, dens, eta, cosmo, z_t, c_t, fbar_t, p1d_t, k_edges, dpix, a0=0.3, b0=1.5, sigma_rel=0.002,
+              xatol=1e-6, fatol=1e-8, max_evals=400, emulator=None, emu_checks=4):
+    """Build a TuneSpec.  sk is a Skewers structure, dens/eta/k_edges/emulator
+    device tensors, p1d_t a host array [n_zt][n_kbins].  Returns (spec, keep):
+    keep holds the host arrays the spec points to and must outlive its use."""
+    import numpy as np
+    z_t = np.atleast_1d(np.asarray(z_t, dtype=np.float64))
+    n = len(z_t)
+    if n < 1 or n > TUNE_MAX_Z:
+        raise ValueError("1..%d tuning redshifts" % TUNE_MAX_Z)
+    nk = int(k_edges.numel()) - 1
+    pt = np.ascontiguousarray(np.asarray(p1d_t, dtype=np.float64).reshape(n, nk))
+    sp = TuneSpec()
+    skp = ctypes.pointer(sk)
+    sp.sk = skp
+    sp.dens = dens.data_ptr()
+    sp.eta = eta.data_ptr()
+    sp.cosmo = cosmo
+    sp.n_zt = n
+    for i in range(n):
+        sp.z_t[i] = float(z_t[i])
+        sp.c_t[i] = float(np.atleast_1d(c_t)[i])
+        sp.fbar_t[i] = float(np.atleast_1d(fbar_t)[i])
+    sp.p1d_t = pt.ctypes.data
+    sp.p1d = P1dSpec(nk, k_edges.data_ptr(), 0.0, float(dpix))
+    sp.a0, sp.b0 = float(a0), float(b0)
+    sp.sigma_rel = float(sigma_rel)
+    sp.xatol, sp.fatol = float(xatol), float(fatol)
+    sp.max_evals = int(max_evals)
+    sp.emulator = None if emulator is None else emulator.data_ptr()
+    sp.emu_checks = int(emu_checks)
+    return sp, (skp, pt, sk)

@@ -7,6 +7,7 @@ import re
 import subprocess
 import tempfile
 
+import numpy as np
 import pytest
 
 from paper_2310_18996_amd import lyamock as L
@@ -79,3 +80,13 @@ def test_host_size_queries():
     assert L.emulator_bytes(n_out) >= L.emulator_param_offset() + 3 * 4 * L.emulator_param_count(n_out)
     assert L.emulator_train_workspace_size(256, n_out) > 256 * 256 * 4 * 9
     assert L.emulator_train_workspace_size(0, n_out) == 0
+
+
+def test_chi_of_z_on_the_host_matches_the_oracle():
+    from oracle import cosmology
+    z = np.array([0.0, 0.5, 1.6, 2.5, 3.8, 6.0])
+    np.testing.assert_allclose(L.chi_of_z(z), cosmology.chi_of_z(z), rtol=1e-12, atol=1e-9)
+    with pytest.raises(L.LyaError):
+        L.chi_of_z([-1.0])
+    with pytest.raises(L.LyaError):
+        L.chi_of_z([1.0], omega_m=1.5)

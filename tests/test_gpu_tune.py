@@ -253,7 +253,7 @@ def test_emulator_tuning_matches_plain_with_fewer_gpu_evaluations(L, mock):
     draws = mockinputs.emulator_draws(n_lab, seed=21)
     z_t = [2.0, 2.4, 2.8, 3.2]
     c_t = [1.0, 1.1, 1.2, 1.3]
-    fbar_t = list(tune.fbar_target(z_t))
+    fbar_t = list(mockinputs.fbar_target(z_t))
     pk_t = np.stack([tune.evaluate(dens, eta, sk, 0.3 * (1 + z) / 3.4, 1.5, c, z, K_EDGES, 0.2)[1]
                      for z, c in zip(z_t, c_t)])
     pk_t = np.where(np.isfinite(pk_t), pk_t, np.nan)

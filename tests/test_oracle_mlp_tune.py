@@ -93,4 +93,4 @@ def test_fit_quadratics_exact_for_quadratic_data():
 
 
 def test_fbar_target_endpoints():
-    assert abs(tune.fbar_target(1.8) - 0.75) < 1e-15 and abs(tune.fbar_target(3.6) - 0.35) < 1e-15
+    assert abs(mockinputs.fbar_target(1.8) - 0.75) < 1e-15 and abs(mockinputs.fbar_target(3.6) - 0.35) < 1e-15
