@@ -196,7 +196,8 @@ def tune_leg(L, torch, n_labels, train_steps):
     espec, ekeep = L.tune_spec(emock["s"], emock["dens"], emock["eta"], cosmo, [2.5], [1.0], [0.5],
                                np.ones((1, nk)), k_edges, ecfg["dpix"])
     ework = torch.empty(L.tune_workspace_size(emock["n_sk"], nk), dtype=torch.uint8, device="cuda")
-    draws = mockinputs.emulator_draws(n_labels, seed=ecfg["seed"])
+    rng = mockinputs.TUNE_EMULATOR_RANGES
+    draws = mockinputs.emulator_draws(n_labels, seed=ecfg["seed"], ranges=rng, log_a=True)
     y = torch.empty((n_labels, 1 + nk), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -206,7 +207,7 @@ def tune_leg(L, torch, n_labels, train_steps):
     print("bench: %d labels %.1f s" % (n_labels, t_labels), file=sys.stderr, flush=True)
     del emock, ework
     emu = torch.zeros(L.emulator_bytes(1 + nk), dtype=torch.uint8, device="cuda")
-    L.emulator_init(emu, 1 + nk, 1, ecfg["seed"], (0.1, 1.0, 0.5, 1.8), (2.0, 2.2, 2.0, 3.6))
+    L.emulator_init(emu, 1 + nk, 1, ecfg["seed"], [r[0] for r in rng], [r[1] for r in rng], log_inputs=0b0001)
     x = torch.from_numpy(draws.astype(np.float32)).cuda()
     L.emulator_set_scaling(emu, y, n_labels)
     B = 512

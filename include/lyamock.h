@@ -190,11 +190,15 @@ int lya_p1d(const lya_skewers* sk, const lya_cosmo* cosmo, const float* flux, co
  * (a0, b0), initial steps 0.3, stopping when all vertices lie within xatol
  * (coordinates) and fatol (chi^2) of the best or after max_evals evaluations.
  * Mode LYA_TUNE_PLAIN evaluates every point on the GPU.  LYA_TUNE_EMULATOR
- * searches on the emulator's predictions (see lya_emulator_*), evaluates the
- * optimum on the GPU, adds the measured defect (GPU minus prediction at that
- * point) to every later prediction and searches again from there (initial
- * steps 0.05), until the optimum moves by at most 10 xatol or emu_checks GPU
- * evaluations are spent; the result holds the last GPU evaluation.  a(z), b(z), c(z)
+ * runs the same search on the device against a model of the statistics, the
+ * emulator's prediction (see lya_emulator_*) plus an offset plus a linear
+ * correction in (ln a, ln b); each search is followed by one GPU evaluation at
+ * its optimum, after which the offset is set so that the model equals the GPU
+ * there and the linear correction takes a Broyden update so that it also
+ * reproduces the previous GPU evaluation; the next search starts there with
+ * steps 0.05.  Points outside the emulator's (a, b) input range are rejected.
+ * It stops when a search moves the point by at most max(10 xatol, 1e-4) or
+ * after emu_checks GPU evaluations; the result holds the last GPU evaluation.  a(z), b(z), c(z)
  * are then least-squares quadratics in (1+z) (n_zt >= 3; the line through
  * two points, a constant for one).  Synchronous (reads back the
  * statistics of every evaluation); all GPU work runs on `stream`. */
@@ -237,9 +241,9 @@ int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, v
  * (a, b, c, z) to (Fbar, P_1, ..., P_nk), the statistics lya_tune_params
  * matches.  Row-vector convention h = gelu(x W + b), W stored [in][out]
  * row-major, parameters in the order W1 b1 W2 b2 W3 b3 W4 b4 (FP32).
- * Inputs are scaled to [-1, 1] by the ranges given at init; outputs are
- * standardised per column with statistics taken from the training labels
- * (natural log first for columns >= log_from).  Training: mean squared error
+ * Inputs are scaled to [-1, 1] by the ranges given at init (optionally in
+ * ln x); outputs are standardised per column with statistics taken from the
+ * training labels (natural log first for columns >= log_from).  Training: mean squared error
  * over batch and unmasked columns, Adam (beta1 0.9, beta2 0.999, eps 1e-8,
  * bias-corrected); the matrix products run on the matrix cores in bfloat16
  * with FP32 accumulation (use_bf16 = 1) or in plain FP32.
@@ -252,12 +256,14 @@ size_t lya_emulator_bytes(int32_t n_out);          /* 0 unless 1 <= n_out <= 64 
 size_t lya_emulator_param_offset(void);
 size_t lya_emulator_param_count(int32_t n_out);    /* 0 unless 1 <= n_out <= 64 */
 
-/* Writes the header (input ranges in_lo < in_hi per input, identity output
+/* Writes the header (input ranges in_lo < in_hi per input; bit i of
+ * log_inputs (0..15) makes input i enter as ln x, which needs in_lo > 0; each
+ * input is mapped affinely onto [-1, 1] over its range; identity output
  * scaling, step 0) and He-normal weights (std sqrt(2/fan_in), Philox stream 3
  * of `seed`), zero biases and zero moments.  Asynchronous on `stream` after a
  * header upload that synchronises the stream. */
 int lya_emulator_init(void* emu, int32_t n_out, int32_t log_from, uint64_t seed, const double in_lo[4],
-                      const double in_hi[4], void* stream);
+                      const double in_hi[4], int32_t log_inputs, void* stream);
 
 /* Output standardisation from labels y (device, [n][n_out] row-major): per
  * column FP64 mean and standard deviation (of ln y for columns >= log_from); a

@@ -155,11 +155,18 @@ def skewer_table(cfg, n_sk=None, seed=None, sort_by_length=True):
                 id_base=0, total=int(npix.astype(np.int64).sum()))
 
 
-def emulator_draws(n, seed=1234):
-    """(a, b, c, z) uniform in the emulator's training ranges."""
+EMULATOR_RANGES = ((0.1, 2.0), (1.0, 2.2), (0.5, 2.0), (1.8, 3.6))
+# Ranges that cover the tuning workload's solutions (a from ~0.008 at z=1.8 to
+# ~2.7 at z=3.6 and c(1.8)=2.48 on these z=0 boxes), a drawn log-uniform
+TUNE_EMULATOR_RANGES = ((1e-3, 5.0), (1.0, 2.2), (0.5, 2.6), (1.8, 3.6))
+
+
+def emulator_draws(n, seed=1234, ranges=EMULATOR_RANGES, log_a=False):
+    """(a, b, c, z) uniform in the given ranges (a log-uniform if log_a)."""
     rng = np.random.default_rng([seed, 3])
-    return np.stack([rng.uniform(0.1, 2.0, n), rng.uniform(1.0, 2.2, n),
-                     rng.uniform(0.5, 2.0, n), rng.uniform(1.8, 3.6, n)], axis=1)
+    (a0, a1), (b0, b1), (c0, c1), (z0, z1) = ranges
+    a = np.exp(rng.uniform(np.log(a0), np.log(a1), n)) if log_a else rng.uniform(a0, a1, n)
+    return np.stack([a, rng.uniform(b0, b1, n), rng.uniform(c0, c1, n), rng.uniform(z0, z1, n)], axis=1)
 
 
 # ---------------------------------------------------------------- tuning workload

@@ -50,12 +50,14 @@ __global__ void __launch_bounds__(kPdNT) k_p1d(P1dArgs a) {
     const int64_t q1 = q0 + a.chunk < a.n_sk ? q0 + a.chunk : a.n_sk;
     for (int64_t q = q0; q < q1; ++q) {
       const int np = a.npix[q];
-      double* psum = a.part_sum + q * nk;
-      int* pcnt = a.part_cnt + q * nk;
+      // per-skewer partial sums, bin-major: [b][q]
+      double* psum = a.part_sum + q;
+      int* pcnt = a.part_cnt + q;
+      const int64_t ld = a.n_sk;
       if (np < 2) {
         for (int b = lane; b < nk; b += 64) {
-          psum[b] = 0.0;
-          pcnt[b] = 0;
+          psum[b * ld] = 0.0;
+          pcnt[b * ld] = 0;
         }
         continue;
       }
@@ -111,16 +113,16 @@ __global__ void __launch_bounds__(kPdNT) k_p1d(P1dArgs a) {
       for (int b = lane; b < nk; b += 64) {
         double s = 0.0;
         for (int m = mlo[b]; m < mlo[b + 1]; ++m) s += pw[m];
-        psum[b] = s;
-        pcnt[b] = mlo[b + 1] - mlo[b];
+        psum[b * ld] = s;
+        pcnt[b * ld] = mlo[b + 1] - mlo[b];
       }
       wave_sync();
     }
   }
 }
 
-// per k bin: sum over skewers in a fixed order (strided partial sums, then a
-// fixed tree), FP64 sum and int64 count
+// per k bin: sum over skewers in a fixed order (strided partial sums over the
+// bin's contiguous row, then a fixed tree), FP64 sum and int64 count
 __global__ void __launch_bounds__(256) k_p1d_reduce(int64_t n_sk, int nk, const double* __restrict__ part_sum,
                                                    const int* __restrict__ part_cnt, double* psum, int64_t* pcount) {
   __shared__ double ss[256];
@@ -128,9 +130,11 @@ __global__ void __launch_bounds__(256) k_p1d_reduce(int64_t n_sk, int nk, const 
   const int b = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
   long long c = 0;
+  const double* ps = part_sum + static_cast<int64_t>(b) * n_sk;
+  const int* pc = part_cnt + static_cast<int64_t>(b) * n_sk;
   for (int64_t q = t; q < n_sk; q += 256) {
-    s += part_sum[q * nk + b];
-    c += part_cnt[q * nk + b];
+    s += ps[q];
+    c += pc[q];
   }
   ss[t] = s;
   sc[t] = c;

@@ -145,15 +145,19 @@ hipError_t launch_p1d(const P1dArgs& a, double* psum, int64_t* pcount, hipStream
 
 // Tuning (lya_tune.hip) and the emulator used by it (lya_mlp.hip).
 size_t emulator_eval_bytes();
-// Device-side Nelder-Mead over (ln a, ln b) on the emulator plus offsets;
-// x holds the start on entry and the optimum on return (synchronous).
+// Device-side Nelder-Mead over th = (ln a, ln b) on the model
+// emulator(th) + off + jac (th - xk) (statistics: Fbar, then the P1D bins);
+// x holds the start on entry and the optimum on return, pred the raw emulator
+// prediction [1 + nk] there (synchronous).
 struct EmuSearchSpec {
-  double fbar_t, off_f, c, z, step, xatol, fatol, sigma;
+  double fbar_t, c, z, step, xatol, fatol, sigma;
   int nk, max_evals;
-  const double* pk_t;
-  const double* off_p;
+  const double* pk_t;   // [nk]
+  const double* off;    // [1 + nk]
+  const double* jac;    // [1 + nk][2]
+  double xk[2];
 };
 hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2], double* fbest, int* nev,
-                           double* pred_fbar, double* pred_pk, char* scratch, hipStream_t st);
+                           double* pred, char* scratch, hipStream_t st);
 
 }  // namespace lya

@@ -21,12 +21,18 @@ constexpr int kIn = 4, kHid = 256, kMaxOut = 64;
 
 struct EmuHeader {
   int32_t n_out;
-  int32_t step;  // Adam steps taken
+  int32_t step;    // Adam steps taken
   int32_t log_from;
-  int32_t pad0;
+  int32_t in_log;  // bit i: input i enters as ln x
   float in_lo[4], in_hi[4];
+  float in_mul[4], in_add[4];  // scaled input = in_mul (x or ln x) + in_add, in [-1, 1] over the range
   float out_mean[kMaxOut], out_std[kMaxOut], out_mask[kMaxOut];
 };
+
+__device__ __forceinline__ float scale_input(const EmuHeader* __restrict__ h, int i, float x) {
+  const float v = ((h->in_log >> i) & 1) ? logf(x) : x;
+  return fmaf(h->in_mul[i], v, h->in_add[i]);
+}
 constexpr size_t kHeaderBytes = 2048;
 static_assert(sizeof(EmuHeader) <= kHeaderBytes, "header");
 
@@ -125,7 +131,7 @@ __global__ void __launch_bounds__(256) k_emu_gather(const float* __restrict__ x,
     const int i = k / (kIn + n_out), c = k % (kIn + n_out);
     const int64_t r = (s * B + i) % n;
     if (c < kIn) {
-      x0[i * kIn + c] = 2.0f * (x[r * kIn + c] - h->in_lo[c]) / (h->in_hi[c] - h->in_lo[c]) - 1.0f;
+      x0[i * kIn + c] = scale_input(h, c, x[r * kIn + c]);
     } else {
       const int o = c - kIn;
       float v = y[r * n_out + o];
@@ -173,6 +179,37 @@ __global__ void __launch_bounds__(256) k_gemm_f32(int M, int N, int K, const flo
   C[static_cast<size_t>(m) * ldc + n] = epilogue(epi, acc, m, n, bias, aux, ldaux, dummy);
 }
 
+// FP32 product for few outputs and a long inner dimension (the first
+// layer's weight gradient): sixteen outputs per block, sixteen threads per
+// output each summing every sixteenth k in order, then a fixed tree
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_f32_ks(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                     const float* __restrict__ B, int ldb, float* C, int ldc,
+                                                     const float* bias, int epi, float* aux, int ldaux) {
+  __shared__ float sp[16][17];
+  const int oi = threadIdx.x & 15, j = threadIdx.x >> 4;
+  const int64_t id = static_cast<int64_t>(blockIdx.x) * 16 + oi;
+  const bool valid = id < static_cast<int64_t>(M) * N;
+  const int m = valid ? static_cast<int>(id / N) : 0, n = valid ? static_cast<int>(id % N) : 0;
+  float acc = 0.0f;
+  if (valid)
+    for (int k = j; k < K; k += 16) {
+      const float a = TA ? A[static_cast<size_t>(k) * lda + m] : A[static_cast<size_t>(m) * lda + k];
+      const float b = TB ? B[static_cast<size_t>(n) * ldb + k] : B[static_cast<size_t>(k) * ldb + n];
+      acc = fmaf(a, b, acc);
+    }
+  sp[j][oi] = acc;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (j < w) sp[j][oi] += sp[j + w][oi];
+    __syncthreads();
+  }
+  if (j == 0 && valid) {
+    float dummy;
+    C[static_cast<size_t>(m) * ldc + n] = epilogue(epi, sp[0][oi], m, n, bias, aux, ldaux, dummy);
+  }
+}
+
 typedef short v4i16 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
 
@@ -204,16 +241,16 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const fl
   for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int idx = tid + 256 * e;  // 0..1023
+      const int idx = tid + 256 * e;  // 0..1023; consecutive threads read consecutive addresses
       {
-        const int mm = idx / 16, kk = idx % 16;
+        const int mm = TA ? idx % 64 : idx / 16, kk = TA ? idx / 64 : idx % 16;
         const int m = m0 + mm, k = k0 + kk;
         float v = 0.0f;
         if (m < M && k < K) v = TA ? A[static_cast<size_t>(k) * lda + m] : A[static_cast<size_t>(m) * lda + k];
         As[mm][kk] = to_bf16(v);
       }
       {
-        const int kk = idx / 64, nn = idx % 64;
+        const int kk = TB ? idx % 16 : idx / 64, nn = TB ? idx / 16 : idx % 64;
         const int k = k0 + kk, n = n0 + nn;
         float v = 0.0f;
         if (n < N && k < K) v = TB ? B[static_cast<size_t>(n) * ldb + k] : B[static_cast<size_t>(k) * ldb + n];
@@ -261,8 +298,13 @@ hipError_t gemm(bool bf16, int M, int N, int K, const float* A, int lda, const f
                        B, ldb, C, ldc, bias, epi, aux, ldaux);
   } else {
     const int64_t tot = static_cast<int64_t>(M) * N;
-    hipLaunchKernelGGL((k_gemm_f32<TA, TB>), dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, M, N,
-                       K, A, lda, B, ldb, C, ldc, bias, epi, aux, ldaux);
+    if (tot <= 65536 && K >= 64) {
+      hipLaunchKernelGGL((k_gemm_f32_ks<TA, TB>), dim3(static_cast<unsigned>((tot + 15) / 16)), dim3(256), 0, st, M,
+                         N, K, A, lda, B, ldb, C, ldc, bias, epi, aux, ldaux);
+    } else {
+      hipLaunchKernelGGL((k_gemm_f32<TA, TB>), dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, M,
+                         N, K, A, lda, B, ldb, C, ldc, bias, epi, aux, ldaux);
+    }
   }
   return hipGetLastError();
 }
@@ -292,13 +334,22 @@ __global__ void __launch_bounds__(256) k_emu_dloss(const float* __restrict__ y, 
   if (threadIdx.x == 0 && loss) loss[0] = static_cast<float>(sl[0] / (static_cast<double>(B) * (neff > 0 ? neff : 1)));
 }
 
-// db[n] = sum over rows of d[m][n] (fixed order per column)
-__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ d, int M, int N, float* db) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= N) return;
+// db[n] = sum over rows of d[m][n]: 64 columns per block, sixteen row groups
+// (rows g, g + 16, ...) summed in order, then the groups in a fixed tree
+__global__ void __launch_bounds__(1024) k_colsum(const float* __restrict__ d, int M, int N, float* db) {
+  __shared__ float sp[16][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   float s = 0.0f;
-  for (int m = 0; m < M; ++m) s += d[static_cast<size_t>(m) * N + n];
-  db[n] = s;
+  if (n < N)
+    for (int m = g; m < M; m += 16) s += d[static_cast<size_t>(m) * N + n];
+  sp[g][c] = s;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (g < w) sp[g][c] += sp[g + w][c];
+    __syncthreads();
+  }
+  if (g == 0 && n < N) db[n] = sp[0][c];
 }
 
 __global__ void __launch_bounds__(256) k_adam(float* p, float* m, float* v, const float* __restrict__ g, size_t np,
@@ -329,7 +380,7 @@ __global__ void __launch_bounds__(256) k_emu_predict(const EmuHeader* __restrict
   for (int s = 0; s < ns; ++s) {
     float a = params[o.b[0] + t];
     for (int i = 0; i < kIn; ++i) {
-      const float u = 2.0f * (x[(s0 + s) * kIn + i] - h->in_lo[i]) / (h->in_hi[i] - h->in_lo[i]) - 1.0f;
+      const float u = scale_input(h, i, x[(s0 + s) * kIn + i]);
       a = fmaf(u, params[o.W[0] + i * kHid + t], a);
     }
     hs[0][s][t] = gelu(a);
@@ -409,20 +460,20 @@ static hipError_t emu_fwd_bwd(const EmuHeader* h_dev, const float* params, int n
   // backward: output layer
   if ((e = gemm<true, false>(bf16, kHid, n_out, B, t.hh[2], kHid, t.dy, n_out, t.grad + o.W[3], n_out, nullptr,
                              EPI_STORE, nullptr, 0, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3((n_out + 255) / 256), dim3(256), 0, st, t.dy, B, n_out, t.grad + o.b[3]);
+  hipLaunchKernelGGL(k_colsum, dim3((n_out + 63) / 64), dim3(1024), 0, st, t.dy, B, n_out, t.grad + o.b[3]);
   // dZ3 = (dY W4^T) * gelu'(Z3)
   if ((e = gemm<false, true>(bf16, B, kHid, n_out, t.dy, n_out, params + o.W[3], n_out, t.dz[2], kHid, nullptr,
                              EPI_GELU_GRAD, t.z[2], kHid, st)) != hipSuccess) return e;
   for (int l = 2; l >= 1; --l) {
     if ((e = gemm<true, false>(bf16, kHid, kHid, B, t.hh[l - 1], kHid, t.dz[l], kHid, t.grad + o.W[l], kHid, nullptr,
                                EPI_STORE, nullptr, 0, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, t.dz[l], B, kHid, t.grad + o.b[l]);
+    hipLaunchKernelGGL(k_colsum, dim3(kHid / 64), dim3(1024), 0, st, t.dz[l], B, kHid, t.grad + o.b[l]);
     if ((e = gemm<false, true>(bf16, B, kHid, kHid, t.dz[l], kHid, params + o.W[l], kHid, t.dz[l - 1], kHid, nullptr,
                                EPI_GELU_GRAD, t.z[l - 1], kHid, st)) != hipSuccess) return e;
   }
   if ((e = gemm<true, false>(false, kIn, kHid, B, t.x0, kIn, t.dz[0], kHid, t.grad + o.W[0], kHid, nullptr,
                              EPI_STORE, nullptr, 0, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, t.dz[0], B, kHid, t.grad + o.b[0]);
+  hipLaunchKernelGGL(k_colsum, dim3(kHid / 64), dim3(1024), 0, st, t.dz[0], B, kHid, t.grad + o.b[0]);
   return hipGetLastError();
 }
 
@@ -435,80 +486,141 @@ static const float* emu_params(const void* emu) {
 size_t emulator_eval_bytes() { return 1024; }
 
 // ---------------------------------------------------------------- device-side tuning search
+constexpr int kSearchNT = 1024;
+
 struct SearchArgs {
   const EmuHeader* h;
   const float* params;
-  double fbar_t, off_f, c, z, x0[2], step, xatol, fatol, sigma;
+  double fbar_t, c, z, x0[2], xk[2], step, xatol, fatol, sigma;
   int nk, max_evals;
-  double pk_t[kMaxOut], off_p[kMaxOut];
-  double* out;  // x[2], best objective, evaluations, raw prediction [1 + nk] at x
+  double pk_t[kMaxOut];
+  double off[kMaxOut];       // model offset per statistic (Fbar first)
+  double jac[kMaxOut][2];    // model slope per statistic in (ln a, ln b) about xk
+  double* out;               // x[2], best objective, evaluations, raw prediction [1 + nk] at x
 };
 
-// One forward pass of a single input by the whole block (256 threads, one
-// hidden unit each); raw outputs (exp for columns >= log_from) into outv.
+// One forward pass of a single input by a block of kSearchNT threads: four
+// threads per hidden unit (a quarter of the inner sum each), sixteen per
+// output column; raw outputs (exp for columns >= log_from) into outv.
 __device__ void forward_one(const EmuHeader* __restrict__ h, const float* __restrict__ params, const Offs& o,
                             const float xin[4], float (*hs)[kHid], float* part, float* outv) {
   const int t = threadIdx.x, n_out = h->n_out;
-  float a = params[o.b[0] + t];
+  if (t < kHid) {
+    float a = params[o.b[0] + t];
 #pragma unroll
-  for (int i = 0; i < kIn; ++i) {
-    const float u = 2.0f * (xin[i] - h->in_lo[i]) / (h->in_hi[i] - h->in_lo[i]) - 1.0f;
-    a = fmaf(u, params[o.W[0] + i * kHid + t], a);
+    for (int i = 0; i < kIn; ++i) a = fmaf(scale_input(h, i, xin[i]), params[o.W[0] + i * kHid + t], a);
+    hs[0][t] = gelu(a);
   }
-  hs[0][t] = gelu(a);
   __syncthreads();
   int cur = 0;
+  const int u = t & (kHid - 1), q = t >> 8;
   for (int l = 1; l < 3; ++l) {
-    float acc = params[o.b[l] + t];
-    const float* W = params + o.W[l] + t;
-#pragma unroll 8
-    for (int k = 0; k < kHid; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * kHid], acc);
-    hs[cur ^ 1][t] = gelu(acc);
+    float acc = 0.0f;
+    const float* W = params + o.W[l] + u;
+#pragma unroll 16
+    for (int k = 64 * q; k < 64 * q + 64; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * kHid], acc);
+    part[q * kHid + u] = acc;
+    __syncthreads();
+    if (t < kHid) {
+      const float v = params[o.b[l] + t] + ((part[t] + part[kHid + t]) + (part[2 * kHid + t] + part[3 * kHid + t]));
+      hs[cur ^ 1][t] = gelu(v);
+    }
     __syncthreads();
     cur ^= 1;
   }
-  // output layer: four threads per column, each a quarter of the sum
-  const int oc = t & 63, q = t >> 6;
+  const int oc = t & 63, r = t >> 6;  // column, sixteenth of the sum
   float acc = 0.0f;
   if (oc < n_out) {
     const float* W = params + o.W[3] + oc;
-    for (int k = 64 * q; k < 64 * q + 64; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * n_out], acc);
+#pragma unroll
+    for (int k = 16 * r; k < 16 * r + 16; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * n_out], acc);
   }
-  part[t] = acc;
+  part[r * 64 + oc] = acc;
   __syncthreads();
   if (t < n_out) {
-    float v = params[o.b[3] + t] + ((part[t] + part[t + 64]) + (part[t + 128] + part[t + 192]));
-    v = v * h->out_std[t] + h->out_mean[t];
+    float v = 0.0f;
+    for (int i = 0; i < 16; ++i) v += part[i * 64 + t];
+    v = (params[o.b[3] + t] + v) * h->out_std[t] + h->out_mean[t];
     if (t >= h->log_from) v = expf(v);
     outv[t] = v;
   }
   __syncthreads();
 }
 
-// Nelder-Mead over (ln a, ln b) on the emulator's predictions plus the given
-// offsets, entirely on the device: one block, every thread runs the same
-// search on the same (block-broadcast) objective values.
-__global__ void __launch_bounds__(256) k_emu_search(SearchArgs a) {
+// Nelder-Mead over th = (ln a, ln b) on the model
+//   stat(th) = emulator(th) + off + jac (th - xk),
+// on the device in one block: the whole block runs each forward pass, wave 0
+// forms the objective (one statistic per lane, fixed-order shuffle sum) and
+// lane 0 steps the search and broadcasts the next point through LDS.  Points
+// outside the emulator's input range in a or b get an infinite objective.
+__global__ void __launch_bounds__(kSearchNT) k_emu_search(SearchArgs a) {
   __shared__ float hs[2][kHid];
-  __shared__ float part[256];
+  __shared__ float part[4 * kHid];
   __shared__ float outv[kMaxOut];
+  __shared__ double spt[2];
+  __shared__ int slast;
   const Offs o = param_offsets(a.h->n_out);
-  const int nk = a.nk;
-  auto f = [&](const double* th) -> double {
-    const float xin[4] = {static_cast<float>(exp(th[0])), static_cast<float>(exp(th[1])), static_cast<float>(a.c),
+  const int nk = a.nk, t = threadIdx.x;
+  const double alo = log(static_cast<double>(a.h->in_lo[0])), ahi = log(static_cast<double>(a.h->in_hi[0]));
+  const double blo = log(static_cast<double>(a.h->in_lo[1])), bhi = log(static_cast<double>(a.h->in_hi[1]));
+  Nm2 nm;  // used by lane 0 only
+  double x[2] = {a.x0[0], a.x0[1]}, fbest = HUGE_VAL;
+  int nev = 0;
+  if (t == 0) {
+    nm.init(a.x0, a.step, a.xatol, a.fatol, a.max_evals);
+    double p[2];
+    const bool more = nm.ask(p);
+    if (!more) {
+      nm.result(x, &fbest, &nev);
+      p[0] = x[0];
+      p[1] = x[1];
+    }
+    spt[0] = p[0];
+    spt[1] = p[1];
+    slast = more ? 0 : 1;
+  }
+  __syncthreads();
+  // at most max_evals + 2 search values, then one pass at the best vertex
+  for (int it = 0; it < a.max_evals + 4; ++it) {
+    const double th0 = spt[0], th1 = spt[1];
+    const int last = slast;
+    const float xin[4] = {static_cast<float>(exp(th0)), static_cast<float>(exp(th1)), static_cast<float>(a.c),
                           static_cast<float>(a.z)};
     forward_one(a.h, a.params, o, xin, hs, part, outv);
-    double pk[kMaxOut];
-    for (int i = 0; i < nk; ++i) pk[i] = static_cast<double>(outv[1 + i]) + a.off_p[i];
-    return tune_chi2(static_cast<double>(outv[0]) + a.off_f, pk, a.fbar_t, a.pk_t, nk, a.sigma);
-  };
-  double x[2] = {a.x0[0], a.x0[1]}, fbest = 0.0;
-  int nev = 0;
-  bool failed = false;
-  nelder_mead2(f, x, a.step, a.xatol, a.fatol, a.max_evals, &fbest, &nev, &failed);
-  f(x);
-  const int t = threadIdx.x;
+    if (last) break;
+    if (t < 64) {
+      const bool inside = th0 >= alo && th0 <= ahi && th1 >= blo && th1 <= bhi;
+      const double d0 = th0 - a.xk[0], d1 = th1 - a.xk[1];
+      double r = 0.0;
+      for (int i = t; i <= nk; i += 64) {
+        const double m = static_cast<double>(outv[i]) + a.off[i] + a.jac[i][0] * d0 + a.jac[i][1] * d1;
+        if (i == 0) {
+          const double fr = (m - a.fbar_t) / (a.sigma * a.fbar_t);
+          r += fr * fr;
+        } else {
+          r += chi2_term(m, a.pk_t[i - 1], a.sigma);
+        }
+      }
+#pragma unroll
+      for (int w = 32; w >= 1; w >>= 1) r += __shfl_xor(r, w);
+      if (t == 0) {
+        nm.tell(inside ? r : HUGE_VAL);
+        double p[2];
+        const bool more = nm.ask(p);
+        if (!more) {
+          nm.result(x, &fbest, &nev);
+          p[0] = x[0];
+          p[1] = x[1];
+        }
+        spt[0] = p[0];
+        spt[1] = p[1];
+        slast = more ? 0 : 1;
+      }
+    }
+    __syncthreads();
+  }
   if (t == 0) {
+    if (!slast) nm.result(x, &fbest, &nev);  // bound reached (not expected)
     a.out[0] = x[0];
     a.out[1] = x[1];
     a.out[2] = fbest;
@@ -518,29 +630,32 @@ __global__ void __launch_bounds__(256) k_emu_search(SearchArgs a) {
 }
 
 hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2], double* fbest, int* nev,
-                           double* pred_fbar, double* pred_pk, char* scratch, hipStream_t st) {
+                           double* pred, char* scratch, hipStream_t st) {
   if (!emu || sp.nk < 0 || sp.nk + 1 > kMaxOut) return hipErrorInvalidValue;
   SearchArgs a{};
   a.h = static_cast<const EmuHeader*>(emu);
   a.params = emu_params(emu);
   a.fbar_t = sp.fbar_t;
-  a.off_f = sp.off_f;
   a.c = sp.c;
   a.z = sp.z;
   a.x0[0] = x[0];
   a.x0[1] = x[1];
+  a.xk[0] = sp.xk[0];
+  a.xk[1] = sp.xk[1];
   a.step = sp.step;
   a.xatol = sp.xatol;
   a.fatol = sp.fatol;
   a.sigma = sp.sigma;
   a.nk = sp.nk;
   a.max_evals = sp.max_evals;
-  for (int i = 0; i < sp.nk; ++i) {
-    a.pk_t[i] = sp.pk_t[i];
-    a.off_p[i] = sp.off_p[i];
+  for (int i = 0; i <= sp.nk; ++i) {
+    if (i < sp.nk) a.pk_t[i] = sp.pk_t[i];
+    a.off[i] = sp.off[i];
+    a.jac[i][0] = sp.jac[2 * i];
+    a.jac[i][1] = sp.jac[2 * i + 1];
   }
   a.out = reinterpret_cast<double*>(scratch);
-  hipLaunchKernelGGL(k_emu_search, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_emu_search, dim3(1), dim3(kSearchNT), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double hout[4 + kMaxOut];
@@ -551,8 +666,7 @@ hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2]
   x[1] = hout[1];
   *fbest = hout[2];
   *nev = static_cast<int>(hout[3]);
-  *pred_fbar = hout[4];
-  for (int i = 0; i < sp.nk; ++i) pred_pk[i] = hout[5 + i];
+  for (int i = 0; i <= sp.nk; ++i) pred[i] = hout[4 + i];
   return hipSuccess;
 }
 
@@ -582,18 +696,26 @@ size_t lya_emulator_param_count(int32_t n_out) {
 }
 
 int lya_emulator_init(void* emu, int32_t n_out, int32_t log_from, uint64_t seed, const double in_lo[4],
-                      const double in_hi[4], void* stream) {
-  if (!emu || n_out < 1 || n_out > lya::kMaxOut || !in_lo || !in_hi || log_from < 0)
+                      const double in_hi[4], int32_t log_inputs, void* stream) {
+  if (!emu || n_out < 1 || n_out > lya::kMaxOut || !in_lo || !in_hi || log_from < 0 || log_inputs < 0 ||
+      log_inputs > 15)
     return efail(LYA_EINVAL, "invalid emulator arguments");
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i) {
     if (!(in_hi[i] > in_lo[i])) return efail(LYA_EINVAL, "input ranges must be increasing");
+    if (((log_inputs >> i) & 1) && !(in_lo[i] > 0.0)) return efail(LYA_EINVAL, "log-scaled inputs need lo > 0");
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   lya::EmuHeader h{};
   h.n_out = n_out;
   h.log_from = log_from;
+  h.in_log = log_inputs;
   for (int i = 0; i < 4; ++i) {
     h.in_lo[i] = static_cast<float>(in_lo[i]);
     h.in_hi[i] = static_cast<float>(in_hi[i]);
+    const bool lg = (log_inputs >> i) & 1;
+    const double lo = lg ? log(in_lo[i]) : in_lo[i], hi = lg ? log(in_hi[i]) : in_hi[i];
+    h.in_mul[i] = static_cast<float>(2.0 / (hi - lo));
+    h.in_add[i] = static_cast<float>(-(hi + lo) / (hi - lo));
   }
   for (int o = 0; o < lya::kMaxOut; ++o) {
     h.out_mean[o] = 0.0f;

@@ -296,24 +296,30 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
       if (last != hipSuccess) { failed = true; return HUGE_VAL; }
       return tune_chi2(fb, pk, fbt, pkt, nk, spec->sigma_rel);
     };
-    double off_f = 0.0, off_p[kMaxKBins] = {0.0};
     double x[2] = {log(spec->a0), log(spec->b0)};
     double fbest = 0.0, fb = 0.0;
     int nev = 0, gpu_ev = 0;
     if (mode == LYA_TUNE_EMULATOR) {
-      // search on the emulator, check the point on the GPU, move the emulator's
-      // prediction onto the measured statistics there (defect correction) and
-      // search again from that point; stop when the checked point no longer
-      // moves or after `emu_checks` GPU evaluations
+      // Search on the model emulator + offset + slope correction, check the
+      // optimum on the GPU, then (i) move the model onto the measured
+      // statistics there (offset = GPU - emulator) and (ii) correct its slope
+      // along the last step by a Broyden update, so that the model also
+      // reproduces the previous check; search again from the new point.  Stops
+      // when a check moves the point by at most max(10 xatol, 1e-4) or after
+      // emu_checks GPU evaluations.
       const int checks = spec->emu_checks > 0 ? spec->emu_checks : 1;
+      const int ns = 1 + nk;
+      const double xtol = fmax(10.0 * spec->xatol, 1e-4);
+      double off[kMaxKBins + 1] = {0.0}, jac[2 * (kMaxKBins + 1)] = {0.0}, dprev[kMaxKBins + 1];
+      double xk[2] = {x[0], x[1]};
       double step = 0.3;
       for (int it = 0; it < checks; ++it) {
         int n1 = 0;
-        const double xprev[2] = {x[0], x[1]};
-        EmuSearchSpec ss{fbt, off_f, cc, z, step, spec->xatol, spec->fatol, spec->sigma_rel, nk, spec->max_evals,
-                         pkt, off_p};
-        double pe[kMaxKBins], fe;
-        if ((last = emulator_search(spec->emulator, ss, x, &fbest, &n1, &fe, pe, reinterpret_cast<char*>(w + c.emu),
+        // the search stops on position alone, ten times finer than the check tolerance
+        EmuSearchSpec ss{fbt, cc, z, step, 0.1 * xtol, HUGE_VAL, spec->sigma_rel, nk, spec->max_evals, pkt,
+                         off, jac, {xk[0], xk[1]}};
+        double pe[kMaxKBins + 1];
+        if ((last = emulator_search(spec->emulator, ss, x, &fbest, &n1, pe, reinterpret_cast<char*>(w + c.emu),
                                     st)) != hipSuccess) {
           failed = true;
           break;
@@ -324,14 +330,34 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
           break;
         }
         ++gpu_ev;
-        off_f = fb - fe;
-        for (int i = 0; i < nk; ++i) off_p[i] = pk[i] - pe[i];
-        const double moved = fmax(fabs(x[0] - xprev[0]), fabs(x[1] - xprev[1]));
-        if (it > 0 && moved <= 10.0 * spec->xatol) break;
+        double d[kMaxKBins + 1];
+        d[0] = fb - pe[0];
+        for (int i = 0; i < nk; ++i) d[1 + i] = pk[i] - pe[1 + i];
+        const double s0 = xk[0] - x[0], s1 = xk[1] - x[1], s2 = s0 * s0 + s1 * s1;
+        if (it > 0 && s2 > 1e-24) {
+          for (int j = 0; j < ns; ++j) {
+            if (!isfinite(d[j]) || !isfinite(dprev[j])) {
+              jac[2 * j] = jac[2 * j + 1] = 0.0;
+              continue;
+            }
+            const double r = (dprev[j] - d[j]) - (jac[2 * j] * s0 + jac[2 * j + 1] * s1);
+            jac[2 * j] += r * s0 / s2;
+            jac[2 * j + 1] += r * s1 / s2;
+          }
+        }
+        const double moved = fmax(fabs(s0), fabs(s1));
+        for (int j = 0; j < ns; ++j) off[j] = dprev[j] = d[j];
+        xk[0] = x[0];
+        xk[1] = x[1];
+        if (it > 0 && moved <= xtol) break;
         step = 0.05;
       }
     } else {
-      nelder_mead2(plain, x, 0.3, spec->xatol, spec->fatol, spec->max_evals, &fbest, &nev, &failed);
+      Nm2 nm;
+      nm.init(x, 0.3, spec->xatol, spec->fatol, spec->max_evals);
+      double p[2];
+      while (!failed && nm.ask(p)) nm.tell(plain(p));
+      nm.result(x, &fbest, &nev);
       gpu_ev = nev;
     }
     if (failed) {

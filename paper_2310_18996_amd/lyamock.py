@@ -274,7 +274,7 @@ def _bind_more(lib):
     lib.lya_emulator_param_count.argtypes = [ctypes.c_int32]
     lib.lya_emulator_init.restype = ctypes.c_int
     lib.lya_emulator_init.argtypes = [VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, P(ctypes.c_double),
-                                      P(ctypes.c_double), VP]
+                                      P(ctypes.c_double), ctypes.c_int32, VP]
     lib.lya_emulator_train_workspace_size.restype = ctypes.c_size_t
     lib.lya_emulator_train_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.lya_emulator_set_scaling.restype = ctypes.c_int
@@ -348,10 +348,11 @@ def emulator_param_count(n_out):
     return int(_lib2().lya_emulator_param_count(int(n_out)))
 
 
-def emulator_init(emu, n_out, log_from, seed, in_lo, in_hi, stream=None):
+def emulator_init(emu, n_out, log_from, seed, in_lo, in_hi, log_inputs=0, stream=None):
     lo = (ctypes.c_double * 4)(*[float(v) for v in in_lo])
     hi = (ctypes.c_double * 4)(*[float(v) for v in in_hi])
-    _echeck(_lib2().lya_emulator_init(_ptr(emu), int(n_out), int(log_from), int(seed), lo, hi, _stream(stream)))
+    _echeck(_lib2().lya_emulator_init(_ptr(emu), int(n_out), int(log_from), int(seed), lo, hi, int(log_inputs),
+                                      _stream(stream)))
 
 
 def emulator_train_workspace_size(batch, n_out):

@@ -107,10 +107,10 @@ def _upload_params(L, emu, params):
     return flat
 
 
-def _new_emulator(L, n_out, log_from, seed=7, lo=(-1, -1, -1, -1), hi=(1, 1, 1, 1)):
+def _new_emulator(L, n_out, log_from, seed=7, lo=(-1, -1, -1, -1), hi=(1, 1, 1, 1), log_inputs=0):
     import torch
     emu = torch.zeros(L.emulator_bytes(n_out), dtype=torch.uint8, device="cuda")
-    L.emulator_init(emu, n_out, log_from, seed, lo, hi)
+    L.emulator_init(emu, n_out, log_from, seed, lo, hi, log_inputs)
     torch.cuda.synchronize()
     return emu
 
@@ -181,7 +181,7 @@ def test_predict_and_scaling_match_oracle(L):
     import torch
     params = _oracle_params(4, N_OUT)
     lo, hi = (0.1, 1.0, 0.5, 1.8), (2.0, 2.2, 2.0, 3.6)
-    emu = _new_emulator(L, N_OUT, 1, lo=lo, hi=hi)
+    emu = _new_emulator(L, N_OUT, 1, lo=lo, hi=hi, log_inputs=0b0001)
     _upload_params(L, emu, params)
     rng = np.random.default_rng(5)
     lab = np.exp(rng.normal(size=(300, N_OUT)) * 0.3 + 1.0).astype(np.float32)
@@ -190,7 +190,7 @@ def test_predict_and_scaling_match_oracle(L):
     torch.cuda.synchronize()
     hdr = emu[:2048].cpu().numpy()
     fl = hdr.view(np.float32)
-    mean, std = fl[12:12 + 64][:N_OUT], fl[12 + 64:12 + 128][:N_OUT]
+    mean, std = fl[20:20 + 64][:N_OUT], fl[20 + 64:20 + 128][:N_OUT]
     col = np.concatenate([lab[:, :1].astype(np.float64), np.log(lab[:, 1:].astype(np.float32)).astype(np.float64)],
                          axis=1)
     np.testing.assert_allclose(mean, col.mean(0), rtol=1e-5, atol=1e-6)
@@ -200,6 +200,8 @@ def test_predict_and_scaling_match_oracle(L):
     L.emulator_predict(emu, torch.from_numpy(x).cuda(), 37, yg)
     torch.cuda.synchronize()
     x0 = 2 * (x.astype(np.float64) - np.array(lo)) / (np.array(hi) - np.array(lo)) - 1
+    # input a enters as ln a
+    x0[:, 0] = 2 * (np.log(x[:, 0].astype(np.float64)) - np.log(lo[0])) / (np.log(hi[0]) - np.log(lo[0])) - 1
     f, _ = mlp.forward(params, x0)
     ref = f * std.astype(np.float64) + mean.astype(np.float64)
     ref[:, 1:] = np.exp(ref[:, 1:])
@@ -250,7 +252,7 @@ def test_emulator_tuning_matches_plain_with_fewer_gpu_evaluations(L, mock):
     import torch
     sk, dens, eta = mock
     n_lab = 3000
-    draws = mockinputs.emulator_draws(n_lab, seed=21)
+    draws = mockinputs.emulator_draws(n_lab, seed=21, log_a=True)
     z_t = [2.0, 2.4, 2.8, 3.2]
     c_t = [1.0, 1.1, 1.2, 1.3]
     fbar_t = list(mockinputs.fbar_target(z_t))
@@ -263,7 +265,7 @@ def test_emulator_tuning_matches_plain_with_fewer_gpu_evaluations(L, mock):
     L.emulator_labels(sp.spec, draws, y, sp.work)
     torch.cuda.synchronize()
     t_lab = time.perf_counter() - t0
-    emu = _new_emulator(L, N_OUT, 1, seed=3, lo=(0.1, 1.0, 0.5, 1.8), hi=(2.0, 2.2, 2.0, 3.6))
+    emu = _new_emulator(L, N_OUT, 1, seed=3, lo=(0.1, 1.0, 0.5, 1.8), hi=(2.0, 2.2, 2.0, 3.6), log_inputs=1)
     xd = torch.from_numpy(draws.astype(np.float32)).cuda()
     L.emulator_set_scaling(emu, y, n_lab)
     B, steps = 256, 4000
