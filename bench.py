@@ -34,9 +34,14 @@ sys.path.insert(0, ROOT)
 METRIC = "box cells/s (GRF+FFT), skewer pixels/s (interp+FGPA), %HBM roofline, tune time"
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the plain copy kernel against rocprofv3 counters, and the
-# counter-based traffic of the dominant kernel (see profiles/); None until taken
-TRAFFIC = {}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) on the 2048^3 + 1M-skewer workload, scaled by what the same
+# counters read for a plain 4 GiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1);
+# profiles/box2048_skewers1M_hbm_traffic.md.  Valid only for the kernels as
+# they were when the counters were taken (a changed kernel must drop its
+# entry) and reported only for that workload.
+TRAFFIC = {"fft_x": 137534552117, "fft_y": 140341231014, "fft_z_gen": 96074136017, "skewers": 14565410985}
+TRAFFIC_CONFIG = "big"
 
 
 def algorithmic_bytes(name, n, pixels, n_sk, voxel_bytes):
@@ -46,7 +51,7 @@ def algorithmic_bytes(name, n, pixels, n_sk, voxel_bytes):
     if name in ("fft_y", "fft_x"):
         return 16.0 * cells                  # reads and writes it
     if name == "skewers":
-        return 12.0 * pixels + voxel_bytes + 44.0 * n_sk
+        return 12.0 * pixels + voxel_bytes + 68.0 * n_sk   # table: 2 x int64[3], int32, int64, f64
     return None
 
 
@@ -346,7 +351,8 @@ def main():
     ab = algorithmic_bytes(dom, n, pixels, n_sk, vox_bytes)
     achieved = ab / (avg_ms * 1e-3) / 1e9 if ab else None
     roof = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=TRAFFIC.get(dom),
+                frac=(achieved / HBM_PEAK_GBS) if achieved else None,
+                traffic=TRAFFIC.get(dom) if args.config == TRAFFIC_CONFIG else None,
                 algorithmic_bytes_per_launch=ab, mean_launch_ms=avg_ms)
     kernels = {k: dict(mean_ms=v[0] / v[1], launches=v[1]) for k, v in sorted(kt.items())}
     for k in kernels:
