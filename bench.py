@@ -106,6 +106,69 @@ def cpu_baseline(cfg, pixels_per_cell, budget_n=256):
                            budget_n, cells, ns, pix, t1 - t0, t2 - t1))
 
 
+# ---------------------------------------------------------------- precision leg
+def precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, edges, stream, reps=3):
+    """BF16 against FP32 storage of {delta, eta_par} on the same workload:
+    times of both and the BF16 error relative to the FP32 results over the
+    whole box and every pixel (the FP32 path's own error against the FP64
+    oracle is measured by the parity tests)."""
+    import mockinputs
+    n, seed = cfg["n"], cfg["seed"]
+    b16 = L.box_struct(n, cfg["dx"], L.LYA_BF16)
+    f16 = torch.empty((L.field_elems(b16),), dtype=torch.int32, device="cuda")
+    w16 = torch.empty(L.workspace_size(L.LYA_OP_BOX, b16), dtype=torch.uint8, device="cuda")
+    pk = L.pk_struct(**cfg["pk"])
+    d16, e16, fl16 = (torch.empty_like(flux) for _ in range(3))
+    fs16, cn16 = torch.zeros_like(fsum), torch.zeros_like(cnt)
+    zb16 = L.zbins_struct(edges, fs16, cn16)
+    swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, b16), dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    box_ms = timed(lambda: L.make_box(b16, pk, seed, cfg["f"], True, f16, w16, stream))
+    sk_ms = timed(lambda: L.draw_skewers(b16, f16, s, ps, seed, cosmo, fg, d16, e16, fl16, zb16, swork, stream))
+    # the FP32 box of the same seed (the timed steps left it in `field`)
+    v32 = L.box_view(field, n)
+    w = L.box_view(f16, n)
+    num = [0.0, 0.0]
+    den = [0.0, 0.0]
+    for x in range(0, n, 64):   # in slabs, FP64 sums
+        a = v32[x:x + 64].double()
+        ws = w[x:x + 64]
+        lo = (ws << 16).view(torch.float32).double()
+        hi = (ws & -65536).view(torch.float32).double()
+        num[0] += float(((lo - a[..., 0]) ** 2).sum())
+        num[1] += float(((hi - a[..., 1]) ** 2).sum())
+        den[0] += float((a[..., 0] ** 2).sum())
+        den[1] += float((a[..., 1] ** 2).sum())
+    fl = flux.double()
+    rel_flux = float(torch.sqrt(((fl16.double() - fl) ** 2).sum() / (fl ** 2).sum()))
+    ok = cnt > 0
+    fbar_rel = float(((fs16[ok] / fsum[ok]) - 1).abs().max())
+    k_edges = torch.from_numpy(mockinputs.tune_k_edges()).cuda()
+    nk = k_edges.numel() - 1
+    pw = torch.empty(L.p1d_workspace_size(s.n_sk, nk), dtype=torch.uint8, device="cuda")
+    res = []
+    for fx, zb_ in ((flux, L.zbins_struct(edges, fsum, cnt)), (fl16, zb16)):
+        pss = torch.zeros(nk, dtype=torch.float64, device="cuda")
+        pcc = torch.zeros(nk, dtype=torch.int64, device="cuda")
+        L.p1d(s, cosmo, fx, zb_, L.P1dSpec(nk, k_edges.data_ptr(), 2.6, cfg["dpix"]), pss, pcc, pw, stream)
+        res.append(pss)
+    torch.cuda.synchronize()
+    good = res[0] != 0
+    p1d_rel = float(((res[1][good] / res[0][good]) - 1).abs().max())
+    return dict(bf16_box_ms=box_ms, bf16_skewer_ms=sk_ms,
+                bf16_vs_fp32=dict(delta_rel_rms=(num[0] / den[0]) ** 0.5, eta_rel_rms=(num[1] / den[1]) ** 0.5,
+                                  flux_rel_rms=rel_flux, fbar_max_rel=fbar_rel, p1d_max_rel=p1d_rel))
+
+
 # ---------------------------------------------------------------- tuning leg
 def stored_pixels(L, torch, cfg, seed, sk_seed):
     """Pre-FGPA pixels (delta_L + delta_S, eta_par) of a mock made by the
@@ -271,6 +334,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=192)
     ap.add_argument("--no-tune", action="store_true", help="skip the tuning leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured replay")
     ap.add_argument("--tune-labels", type=int, default=100_000)
     ap.add_argument("--tune-steps", type=int, default=20_000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -312,7 +377,10 @@ def main():
     ps = L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0)
     cosmo = L.Cosmo(cfg["omega_m"])
     fg = L.fgpa_struct(cfg["fgpa"])
-    stream = torch.cuda.current_stream()
+    # a created stream (graph capture is not possible on the default stream); torch's own
+    # work in this process runs on it too, so everything stays in stream order
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
     if args.calibrate_copy:
         # a plain copy of known size: 4 GiB read, 4 GiB written
         src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
@@ -325,6 +393,24 @@ def main():
     def step():
         L.make_box(box, pk, seed, cfg["f"], True, field, bwork, stream)
         L.draw_skewers(box, field, s, ps, seed, cosmo, fg, dens, eta, flux, zb, swork, stream)
+
+    autotune = None
+    if not args.no_autotune:
+        # launch shapes for this box size (untimed; clobbers the buffers, which
+        # the warm-up steps then rewrite)
+        t0 = time.perf_counter()
+        tf, ms_fft = L.autotune_fft(box, field, bwork, reps=2, stream=stream)
+        L.make_box(box, pk, seed, cfg["f"], True, field, bwork, stream)
+        ts, ms_sk = L.autotune_skewers(box, field, s, ps, seed, cosmo, fg, dens, eta, flux, zb, swork, reps=1,
+                                       stream=stream)
+        torch.cuda.synchronize()
+        autotune = dict(fft_y=tf.fft_y, fft_x=tf.fft_x, sk_chunk=ts.sk_chunk, sk_blocks_per_cu=ts.sk_blocks_per_cu,
+                        fft_ms={"y": ms_fft[0], "x": ms_fft[1]},
+                        skewer_ms={"chunks": list(L.SK_CHUNKS), "blocks_per_cu": list(L.SK_BLOCKS_PER_CU),
+                                   "ms": ms_sk},
+                        seconds=time.perf_counter() - t0)
+        print("bench: autotuned fft y=%d x=%d, skewer chunk %d blocks/CU %d (%.1f s)" % (
+            tf.fft_y, tf.fft_x, ts.sk_chunk, ts.sk_blocks_per_cu, autotune["seconds"]), file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         step()
@@ -340,6 +426,25 @@ def main():
     kt = L.timing_read()
     L.timing_enable(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
+    graph = None
+    if not args.no_graph:
+        # the same step as one captured HIP graph, replayed; its output must
+        # equal the eager step's bit for bit
+        ref = flux.clone()
+        g = L.Graph(stream)
+        with g:
+            step()
+        flux.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(flux, ref))
+        del ref
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            g.launch()
+        torch.cuda.synchronize()
+        graph = dict(ms_per_step=(time.perf_counter() - t2) * 1e3 / args.steps, matches_eager=same)
+        g.close()
     box_names = ("pk_sigma8", "pk_finalize", "pk_table", "fft_z_gen", "fft_y", "fft_x")
     sk_names = ("zchi_table", "twiddles", "skewer_reset", "skewers", "skewer_finalize")
     box_ms = sum(kt[k][0] for k in box_names if k in kt) / args.steps
@@ -367,7 +472,13 @@ def main():
                    n=n, dx=dx, n_skewers=n_sk, pixels=pixels, seed=seed),
                box_cells_per_s=cells / (box_ms * 1e-3), box_ms=box_ms,
                skewer_pixels_per_s=pixels / (sk_ms * 1e-3), skewer_ms=sk_ms,
-               distinct_voxels_per_pixel=vox_per_pix, roofline=roof, kernels=kernels)
+               distinct_voxels_per_pixel=vox_per_pix, roofline=roof, kernels=kernels, autotune=autotune,
+               graph=graph)
+    if args.config == "precision":
+        print("bench: BF16 storage leg", file=sys.stderr, flush=True)
+        out["precision"] = precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, edges, stream)
+        out["precision"]["fp32_box_ms"] = box_ms
+        out["precision"]["fp32_skewer_ms"] = sk_ms
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, pixels / cells, args.cpu_n)

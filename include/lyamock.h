@@ -303,6 +303,63 @@ int lya_emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t 
 
 const char* lya_emulator_last_error(void);
 
+/* Launch-shape tuning (the batching and autotuning row of the hot path).
+ * Per box size n the library keeps:
+ *   fft_y, fft_x      variant of the strided FFT passes, 0..LYA_FFT_VARIANTS-1:
+ *                     0/1 one tile of the full pencil count per block, tile
+ *                     order 0/1; 2/3 half the pencils per tile (half the LDS,
+ *                     two blocks per CU), order 0/1; 4/5 half tiles in the
+ *                     persistent software-pipelined kernel (next tile's loads
+ *                     issued before the current tile's FFT), order 0/1; 6/7
+ *                     full tiles with half the elements per thread (twice the
+ *                     waves), order 0/1; 8/9 those in the pipelined kernel.
+ *                     Boxes below 1024 have variants 0 and 1 only.  Defaults:
+ *                     y 0, x 1.
+ *   sk_chunk          skewers taken per pull from the skewer work queue (default 8);
+ *   sk_blocks_per_cu  persistent skewer blocks per CU, 1..4 (default 4).
+ * The table is process-wide and applies to every later call for that n. */
+#define LYA_FFT_VARIANTS 10
+typedef struct {
+  int32_t fft_y, fft_x, sk_chunk, sk_blocks_per_cu;
+} lya_tuning;
+
+int lya_get_tuning(int32_t n, lya_tuning* t);
+int lya_set_tuning(int32_t n, const lya_tuning* t);
+
+/* Times both strided FFT passes in every variant on `field` (an FP32 box of
+ * size box->n, whose contents are overwritten), `reps` runs each after one
+ * untimed run, with HIP events on `stream`; stores the fastest variant of
+ * each pass in the table.  ms (may be NULL) receives the mean milliseconds,
+ * [pass][variant] with 2 x LYA_FFT_VARIANTS entries (-1 for variants not
+ * available at this n).  work: at least 8 n bytes (twiddles).  Synchronous. */
+int lya_autotune_fft(const lya_box* box, void* field, void* work, size_t work_bytes, int32_t reps, double* ms,
+                     lya_tuning* out, void* stream);
+
+/* Times lya_draw_skewers (same arguments; outputs overwritten) for skewer
+ * chunks {1, 2, 4, 8, 16, 32, 64} x blocks per CU {1, 2, 3, 4}, `reps` runs
+ * each; stores the fastest in the table for box->n.  ms (may be NULL)
+ * receives 7 x 4 mean milliseconds, [chunk][blocks].  Synchronous. */
+int lya_autotune_skewers(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                         uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                         float* flux, const lya_zbins* zb, void* work, size_t work_bytes, int32_t reps, double* ms,
+                         lya_tuning* out, void* stream);
+
+/* HIP-graph capture of a sequence of library calls on one stream:
+ * lya_graph_begin(stream), then the calls (lya_make_box, lya_make_eta,
+ * lya_draw_skewers, lya_apply_fgpa, lya_p1d: none of them synchronises the
+ * host or records memset nodes; kernel timing must be off), then
+ * lya_graph_end(stream, &g) instantiates the graph; lya_graph_launch replays
+ * it with the same pointers and arguments; lya_graph_destroy frees it (host
+ * memory only). */
+typedef struct lya_graph_s* lya_graph;
+int lya_graph_begin(void* stream);
+int lya_graph_end(void* stream, lya_graph* out);
+int lya_graph_launch(lya_graph g, void* stream);
+int lya_graph_destroy(lya_graph g);
+
+/* Last error message of the tuning and graph calls (thread-local). */
+const char* lya_autotune_last_error(void);
+
 /* Kernel timing for benchmarks.  lya_timing_enable(1) clears the records and
  * brackets every kernel the library launches afterwards with two HIP events on
  * the launch stream; lya_timing_enable(0) clears and stops.

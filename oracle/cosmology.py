@@ -7,7 +7,8 @@ Distances are in Mpc/h, so h cancels and c/H0 = 2997.92458 Mpc/h.
 
 chi(z) = (c/H0) * int_0^z dz'/E(z') is evaluated with 64-node Gauss-Legendre
 quadrature on [0, z] (numpy.polynomial.legendre.leggauss); z(chi) inverts it by
-Newton iteration, d chi/dz = (c/H0)/E(z).
+Newton iteration, d chi/dz = (c/H0)/E(z), started from a linear interpolation
+in a table of chi(z).
 
 Pins: the Einstein-de Sitter closed form (Om = 1), the pure-Lambda closed form
 (Om = 0), scipy.integrate.quad at sample redshifts, and z(chi(z)) = z.
@@ -35,16 +36,30 @@ def chi_of_z(z, omega_m=OMEGA_M):
     return C_OVER_H0 * half[..., 0] * np.sum(_GL_W * integrand, axis=-1)
 
 
-def z_of_chi(chi, omega_m=OMEGA_M, iters=60):
-    """Inverse of chi_of_z by Newton iteration (vectorised)."""
+def z_of_chi(chi, omega_m=OMEGA_M, iters=60, chunk=1 << 15):
+    """Inverse of chi_of_z by Newton iteration (vectorised).  Each value stops
+    at its first step below 1e-15 (1 + z); values are processed in chunks so
+    that the quadrature arrays stay small."""
     chi = np.asarray(chi, dtype=np.float64)
-    z = chi / C_OVER_H0  # low-z start, chi ~ (c/H0) z
-    for _ in range(iters):
-        dz = (chi_of_z(z, omega_m) - chi) * hubble_e(z, omega_m) / C_OVER_H0
-        z = z - dz
-        if np.all(np.abs(dz) < 1e-15 * (1.0 + np.abs(z))):
-            break
-    return z
+    flat = chi.reshape(-1)
+    out = np.empty_like(flat)
+    # starting values: linear interpolation in a table of chi_of_z itself
+    z_tab = np.linspace(0.0, 12.0, 4801)
+    chi_tab = chi_of_z(z_tab, omega_m)
+    for s in range(0, flat.size, chunk):
+        c = flat[s:s + chunk]
+        z = np.interp(c, chi_tab, z_tab, right=z_tab[-1])
+        active = np.arange(c.size)
+        for _ in range(iters):
+            za = z[active]
+            dz = (chi_of_z(za, omega_m) - c[active]) * hubble_e(za, omega_m) / C_OVER_H0
+            zn = za - dz
+            z[active] = zn
+            active = active[np.abs(dz) >= 1e-15 * (1.0 + np.abs(zn))]
+            if active.size == 0:
+                break
+        out[s:s + chunk] = z
+    return out.reshape(chi.shape)
 
 
 def dv_per_dchi(z, omega_m=OMEGA_M):

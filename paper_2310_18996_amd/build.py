@@ -1,15 +1,18 @@
-"""Build liblyamock.so (HIP, gfx950) in-tree with hipcc."""
+"""Build liblyamock.so (HIP, gfx950) in-tree with hipcc: every source is
+compiled to its own object in parallel (under _build/), then linked."""
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "liblyamock.so")
 SOURCES = ["lya_abi.hip", "lya_timing.hip", "k_tables.hip", "k_fft.hip", "k_skewers.hip", "k_p1d.hip",
-           "lya_tune.hip", "lya_mlp.hip"]
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+           "lya_tune.hip", "lya_mlp.hip", "lya_autotune.hip"]
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 
@@ -18,10 +21,33 @@ def hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose=False):
-    """Compile every HIP source into liblyamock.so (always recompiles)."""
+def _compile(src, verbose):
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+    return obj, r.returncode, msg
+
+
+def build(verbose=False, jobs=None):
+    """Compile every HIP source and link liblyamock.so (always recompiles)."""
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        res = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    failed = False
+    for (obj, rc, msg), src in zip(res, SOURCES):
+        if msg.strip():
+            print(msg, file=sys.stderr)
+        if rc != 0:
+            print("hipcc failed on %s" % src, file=sys.stderr)
+            failed = True
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc")
     tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [r[0] for r in res]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -30,5 +56,5 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose="-v" in sys.argv)
     sys.exit(0)

@@ -183,6 +183,40 @@ struct Pass {
     }
   }
 
+  // stage-0 registers of a strided tile straight from global memory
+  __device__ static __forceinline__ void load_global0(float2 (&v)[E], const float2* __restrict__ data, int outer,
+                                                      int t0, int tid) {
+    constexpr int R = radix_of(N, 0), B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      int p, j;
+      coords<R>(tid + b * NT, p, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b * R + r] = data[gidx(outer, t0, j + r * (N / R), p)];
+    }
+  }
+
+  // stages 0.. of the tile held in v, ending with the natural-order global store
+  __device__ static __forceinline__ void transform_store(float2 (&v)[E], float2* lds, float2* data,
+                                                         uint32_t* out_bf16, const float2* __restrict__ tw,
+                                                         bool zero_b, int outer, int t0, bool paired, int tid) {
+    butterflies<0>(v, tw, tid);
+    store_lds<0>(v, lds, tid);
+    __syncthreads();
+    load_lds<1>(v, lds, tid);
+    butterflies<1>(v, tw, tid);
+    if constexpr (NSTAGE == 2) {
+      store_global<1>(v, data, out_bf16, zero_b, outer, t0, paired, tid);
+    } else {
+      __syncthreads();
+      store_lds<1>(v, lds, tid);
+      __syncthreads();
+      load_lds<2>(v, lds, tid);
+      butterflies<2>(v, tw, tid);
+      store_global<2>(v, data, out_bf16, zero_b, outer, t0, paired, tid);
+    }
+  }
+
   template <int S>
   __device__ static __forceinline__ void load_lds(float2 (&v)[E], const float2* lds, int tid) {
     constexpr int R = radix_of(N, S), B = E / R;
@@ -323,39 +357,58 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
     __syncthreads();
     P::template load_lds<0>(v, lds, tid);
     __syncthreads();
-  } else {
+  } else if (KIND == KIND_GENZ) {
     constexpr int R = radix_of(N, 0), B = E / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       int p, j;
       P::template coords<R>(tid + b * NT, p, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = j + r * (N / R);
-        if (KIND == KIND_GENZ) {
-          v[b * R + r] = gen_mode<N>(g, outer, t0 + p, i);
-        } else {
-          v[b * R + r] = data[P::gidx(outer, t0, i, p)];
-        }
-      }
+      for (int r = 0; r < R; ++r) v[b * R + r] = gen_mode<N>(g, outer, t0 + p, j + r * (N / R));
     }
-  }
-  P::template butterflies<0>(v, tw, tid);
-  P::template store_lds<0>(v, lds, tid);
-  __syncthreads();
-  P::template load_lds<1>(v, lds, tid);
-  P::template butterflies<1>(v, tw, tid);
-  if constexpr (P::NSTAGE == 2) {
-    P::template store_global<1>(v, data, KIND == KIND_X ? out_bf16 : nullptr, KIND == KIND_X && g.comp_b < 0,
-                                 outer, t0, paired, tid);
   } else {
-    __syncthreads();
-    P::template store_lds<1>(v, lds, tid);
-    __syncthreads();
-    P::template load_lds<2>(v, lds, tid);
-    P::template butterflies<2>(v, tw, tid);
-    P::template store_global<2>(v, data, KIND == KIND_X ? out_bf16 : nullptr, KIND == KIND_X && g.comp_b < 0,
-                                 outer, t0, paired, tid);
+    P::load_global0(v, data, outer, t0, tid);
+  }
+  P::transform_store(v, lds, data, KIND == KIND_X ? out_bf16 : nullptr, tw, KIND == KIND_X && g.comp_b < 0, outer,
+                     t0, paired, tid);
+}
+
+// Persistent, software-pipelined strided pass: each block walks tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... (gridDim.x a multiple of 8, so a
+// block stays on one XCD's range of tiles) and issues the global loads of its
+// next tile before transforming the current one, so that their latency hides
+// behind the FFT and the stores.  Two register copies of a tile: the waves
+// are allowed the larger register budget of two waves per SIMD.
+template <int N, int T, int E, int KIND, int ORDER>
+__global__ void __launch_bounds__(N * T / E) __attribute__((amdgpu_waves_per_eu(1, 2)))
+k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const float2* __restrict__ tw, GenParams g) {
+  using P = Pass<N, T, E, KIND>;
+  constexpr int ntiles = N * (N / T);
+  __shared__ float2 lds[P::LDS_ELEMS];
+  float2 v[E], nv[E];
+  const int tid = threadIdx.x;
+  int b = blockIdx.x;
+  if (b >= ntiles) return;
+  int outer, t0;
+  strided_tile<N, T, ORDER>(b, outer, t0);
+  P::load_global0(v, data, outer, t0, tid);
+  for (;;) {
+    const int bn = b + static_cast<int>(gridDim.x);
+    const bool more = bn < ntiles;
+    int on = 0, tn = 0;
+    if (more) {
+      strided_tile<N, T, ORDER>(bn, on, tn);
+      P::load_global0(nv, data, on, tn, tid);
+    }
+    P::transform_store(v, lds, data, KIND == KIND_X ? out_bf16 : nullptr, tw, KIND == KIND_X && g.comp_b < 0,
+                       outer, t0, false, tid);
+    if (!more) break;
+    __syncthreads();  // every thread has read this tile's LDS before the next one is written
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = nv[e];
+    b = bn;
+    outer = on;
+    t0 = tn;
   }
 }
 
@@ -371,10 +424,88 @@ template <> struct Shape<512>  { static constexpr int TZ = 8,  EZ = 16, TS = 16,
 template <> struct Shape<1024> { static constexpr int TZ = 4,  EZ = 16, TS = 16, ES = 32; };
 template <> struct Shape<2048> { static constexpr int TZ = 2,  EZ = 16, TS = 8,  ES = 32; };
 
+// Variants of the strided passes (y and x), chosen per N by the autotuner:
+//   0/1: tile of the table's T pencils, one tile per block, tile order 0/1;
+//   2/3: half the pencils per tile (half the LDS: two blocks per CU), order 0/1;
+//   4/5: half tiles in the persistent pipelined kernel, order 0/1;
+//   6/7: full tiles with half the elements per thread (twice the waves), order 0/1;
+//   8/9: as 6/7 in the persistent pipelined kernel.
+// Boxes below 1024 have variants 0 and 1 only.
+namespace {
+int g_variant[2][12] = {};  // [pass y/x][log2 N]
+bool g_variant_init = false;
+void init_variants() {
+  if (g_variant_init) return;
+  for (int l = 0; l < 12; ++l) {
+    g_variant[0][l] = 0;  // y: one tile per block, order 0
+    g_variant[1][l] = 1;  // x: one tile per block, order 1
+  }
+  g_variant_init = true;
+}
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+}  // namespace
+
+int fft_variant(int n, int pass) {
+  init_variants();
+  return g_variant[pass][ilog2(n)];
+}
+
+int set_fft_variant(int n, int pass, int v) {
+  init_variants();
+  if (v < 0 || v >= kFftVariants || pass < 0 || pass > 1) return -1;
+  if (n < 1024 && v > 1) return -1;  // smaller boxes: one tile per block, order 0 or 1
+  g_variant[pass][ilog2(n)] = v;
+  return 0;
+}
+
+template <int N, int T, int E, int KIND, int ORDER, bool PIPE>
+hipError_t launch_strided_tile(float2* field, uint32_t* bf16, const float2* tw, const GenParams& g, hipStream_t st) {
+  const char* name = KIND == KIND_Y ? "fft_y" : "fft_x";
+  constexpr int ntiles = N * (N / T), nt = N * T / E;
+  if constexpr (PIPE) {
+    int blocks = (device_cus() + 7) / 8 * 8;
+    if (blocks > ntiles) blocks = ntiles;
+    LYA_TIMED(name, st,
+              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND, ORDER>), dim3(blocks), dim3(nt), 0, st, field, bf16, tw,
+                                 g));
+  } else {
+    LYA_TIMED(name, st,
+              hipLaunchKernelGGL((k_fft_pass<N, T, E, KIND, ORDER>), dim3(ntiles), dim3(nt), 0, st, field, bf16, tw,
+                                 g));
+  }
+  return hipGetLastError();
+}
+
+template <int N, int KIND>
+hipError_t launch_strided(int variant, float2* field, uint32_t* bf16, const float2* tw, const GenParams& g,
+                          hipStream_t st) {
+  using S = Shape<N>;
+  if constexpr (N >= 1024) {
+    constexpr int TH = S::TS / 2, EH = S::ES / 2;
+    switch (variant) {
+      case 2: return launch_strided_tile<N, TH, EH, KIND, 0, false>(field, bf16, tw, g, st);
+      case 3: return launch_strided_tile<N, TH, EH, KIND, 1, false>(field, bf16, tw, g, st);
+      case 4: return launch_strided_tile<N, TH, EH, KIND, 0, true>(field, bf16, tw, g, st);
+      case 5: return launch_strided_tile<N, TH, EH, KIND, 1, true>(field, bf16, tw, g, st);
+      case 6: return launch_strided_tile<N, S::TS, EH, KIND, 0, false>(field, bf16, tw, g, st);
+      case 7: return launch_strided_tile<N, S::TS, EH, KIND, 1, false>(field, bf16, tw, g, st);
+      case 8: return launch_strided_tile<N, S::TS, EH, KIND, 0, true>(field, bf16, tw, g, st);
+      case 9: return launch_strided_tile<N, S::TS, EH, KIND, 1, true>(field, bf16, tw, g, st);
+      default: break;
+    }
+  }
+  if (variant == 1) return launch_strided_tile<N, S::TS, S::ES, KIND, 1, false>(field, bf16, tw, g, st);
+  return launch_strided_tile<N, S::TS, S::ES, KIND, 0, false>(field, bf16, tw, g, st);
+}
+
 template <int N>
 hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16, hipStream_t st) {
   using S = Shape<N>;
-  const int tz = N * (N / S::TZ), ts = N * (N / S::TS);
+  const int tz = N * (N / S::TZ);
   const bool hooks = g.fixed_amp || g.only_n2 >= 0;
   const int gm = (!hooks && g.comp_a == 0 && g.comp_b == 3)    ? GEN_DELTA_ETAZ
                  : (!hooks && g.comp_a == 0 && g.comp_b == -1) ? GEN_DELTA
@@ -392,13 +523,25 @@ hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint
               hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_GENERIC>), dim3(tz),
                                  dim3(N * S::TZ / S::EZ), 0, st, field, nullptr, tw, g));
   }
-  LYA_TIMED("fft_y", st,
-            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_Y, 0>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
-                               field, nullptr, tw, g));
-  LYA_TIMED("fft_x", st,
-            hipLaunchKernelGGL((k_fft_pass<N, S::TS, S::ES, KIND_X, 1>), dim3(ts), dim3(N * S::TS / S::ES), 0, st,
-                               field, field_bf16, tw, g));
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_strided<N, KIND_Y>(fft_variant(N, 0), field, nullptr, tw, g, st)) != hipSuccess) return e;
+  return launch_strided<N, KIND_X>(fft_variant(N, 1), field, field_bf16, tw, g, st);
+}
+
+// One strided pass alone (autotuning): pass 0 = y, 1 = x, on the box in place.
+hipError_t launch_fft_strided_pass(int n, int pass, int variant, const float2* tw, float2* field, hipStream_t st) {
+  GenParams g{};
+  g.comp_b = 3;
+  switch (n) {
+#define LYA_CASE(NN)                                                                                        \
+  case NN:                                                                                                  \
+    return pass == 0 ? launch_strided<NN, KIND_Y>(variant, field, nullptr, tw, g, st)                       \
+                     : launch_strided<NN, KIND_X>(variant, field, nullptr, tw, g, st);
+    LYA_CASE(32) LYA_CASE(64) LYA_CASE(128) LYA_CASE(256) LYA_CASE(512) LYA_CASE(1024) LYA_CASE(2048)
+#undef LYA_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,

@@ -260,7 +260,7 @@ hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st) {
   LYA_TIMED("skewer_reset", st,
             hipLaunchKernelGGL(k_skewer_reset, dim3(1), dim3(256), 0, st, a.queue, a.bin_sum, a.bin_cnt));
   const int64_t nchunks = (a.n_sk + a.chunk - 1) / a.chunk;
-  int64_t blocks = static_cast<int64_t>(device_cus()) * 4;
+  int64_t blocks = static_cast<int64_t>(device_cus()) * (a.blocks_per_cu > 0 ? a.blocks_per_cu : 4);
   if (blocks * kSkWaves > nchunks) blocks = (nchunks + kSkWaves - 1) / kSkWaves;
   if (blocks < 1) blocks = 1;
   LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,

@@ -69,6 +69,16 @@ hipError_t launch_zchi_table(double omega_m, float* ztab, hipStream_t st);
 hipError_t launch_twiddles(float2* tw, int ntw, hipStream_t st);
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
                           hipStream_t st);
+// Strided-pass variants (0..kFftVariants-1) per box size and pass (0 = y, 1 = x).
+constexpr int kFftVariants = 10;
+int fft_variant(int n, int pass);
+int set_fft_variant(int n, int pass, int v);
+hipError_t launch_fft_strided_pass(int n, int pass, int variant, const float2* tw, float2* field, hipStream_t st);
+// Skewer-kernel launch shape per box size (autotuned): skewers per queue pull
+// and persistent blocks per CU.
+int sk_chunk(int n);
+int sk_blocks_per_cu(int n);
+void set_sk_shape(int n, int chunk, int bpc);
 
 // Skewer stage.
 struct SkewerArgs {
@@ -112,6 +122,7 @@ struct SkewerArgs {
   const float2* tw2048;
   unsigned int* queue;
   int chunk;
+  int blocks_per_cu;  // persistent blocks per CU (<= 0: 4)
 };
 
 hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st);
@@ -135,8 +146,8 @@ struct P1dArgs {
   int n_kbins;
   const double* k_edges;     // [n_kbins + 1], s/km
   double dv;                 // velocity pixel, km/s
-  double* part_sum;          // workspace [n_sk][n_kbins]
-  int* part_cnt;             // workspace [n_sk][n_kbins]
+  double* part_sum;          // workspace [n_kbins][n_sk]
+  int* part_cnt;             // workspace [n_kbins][n_sk]
   const float2* tw2048;
   unsigned int* queue;
   int chunk;

@@ -21,7 +21,9 @@ EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make
            "lya_tune_params", "lya_emulator_labels", "lya_emulator_bytes", "lya_emulator_param_offset",
            "lya_emulator_param_count", "lya_emulator_init", "lya_emulator_train_workspace_size",
            "lya_emulator_set_scaling", "lya_emulator_loss_grad", "lya_emulator_train", "lya_emulator_predict",
-           "lya_emulator_last_error", "lya_chi_of_z", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
+           "lya_emulator_last_error", "lya_chi_of_z", "lya_get_tuning", "lya_set_tuning",
+           "lya_autotune_fft", "lya_autotune_skewers", "lya_graph_begin", "lya_graph_end", "lya_graph_launch",
+           "lya_graph_destroy", "lya_autotune_last_error", "lya_timing_enable", "lya_timing_collect", "lya_timing_get",
            "lya_last_error", "lya_version")
 
 
@@ -255,6 +257,16 @@ class TuneResult(ctypes.Structure):
                 ("coef", (ctypes.c_double * 3) * 3), ("seconds", ctypes.c_double)]
 
 
+FFT_VARIANTS = 10
+SK_CHUNKS = (1, 2, 4, 8, 16, 32, 64)
+SK_BLOCKS_PER_CU = (1, 2, 3, 4)
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fft_y", ctypes.c_int32), ("fft_x", ctypes.c_int32), ("sk_chunk", ctypes.c_int32),
+                ("sk_blocks_per_cu", ctypes.c_int32)]
+
+
 def _bind_more(lib):
     P, VP = ctypes.POINTER, ctypes.c_void_p
     lib.lya_p1d_workspace_size.restype = ctypes.c_size_t
@@ -289,6 +301,24 @@ def _bind_more(lib):
     lib.lya_emulator_predict.argtypes = [VP, VP, ctypes.c_int64, VP, VP]
     lib.lya_emulator_last_error.restype = ctypes.c_char_p
     lib.lya_chi_of_z.restype = ctypes.c_int
+    lib.lya_get_tuning.restype = ctypes.c_int
+    lib.lya_get_tuning.argtypes = [ctypes.c_int32, P(Tuning)]
+    lib.lya_set_tuning.restype = ctypes.c_int
+    lib.lya_set_tuning.argtypes = [ctypes.c_int32, P(Tuning)]
+    lib.lya_autotune_fft.restype = ctypes.c_int
+    lib.lya_autotune_fft.argtypes = [P(Box), VP, VP, ctypes.c_size_t, ctypes.c_int32, VP, P(Tuning), VP]
+    lib.lya_autotune_skewers.restype = ctypes.c_int
+    lib.lya_autotune_skewers.argtypes = [P(Box), VP, P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo), P(Fgpa), VP, VP,
+                                         VP, P(ZBins), VP, ctypes.c_size_t, ctypes.c_int32, VP, P(Tuning), VP]
+    lib.lya_graph_begin.restype = ctypes.c_int
+    lib.lya_graph_begin.argtypes = [VP]
+    lib.lya_graph_end.restype = ctypes.c_int
+    lib.lya_graph_end.argtypes = [VP, P(VP)]
+    lib.lya_graph_launch.restype = ctypes.c_int
+    lib.lya_graph_launch.argtypes = [VP, VP]
+    lib.lya_graph_destroy.restype = ctypes.c_int
+    lib.lya_graph_destroy.argtypes = [VP]
+    lib.lya_autotune_last_error.restype = ctypes.c_char_p
     lib.lya_chi_of_z.argtypes = [P(Cosmo), ctypes.c_int32, VP, VP]
 
 
@@ -421,3 +451,74 @@ def tune_spec(sk, dens, eta, cosmo, z_t, c_t, fbar_t, p1d_t, k_edges, dpix, a0=0
     sp.emulator = None if emulator is None else emulator.data_ptr()
     sp.emu_checks = int(emu_checks)
     return sp, (skp, pt, sk)
+
+
+def _acheck(rc):
+    if rc != LYA_OK:
+        raise LyaError(rc, _lib2().lya_autotune_last_error().decode())
+
+
+def get_tuning(n):
+    t = Tuning()
+    _acheck(_lib2().lya_get_tuning(int(n), ctypes.byref(t)))
+    return t
+
+
+def set_tuning(n, t):
+    _acheck(_lib2().lya_set_tuning(int(n), ctypes.byref(t)))
+
+
+def autotune_fft(box, field, work, reps=3, stream=None):
+    """lya_autotune_fft: returns (Tuning, ms[2][FFT_VARIANTS] as nested lists)."""
+    ms = (ctypes.c_double * (2 * FFT_VARIANTS))()
+    t = Tuning()
+    _acheck(_lib2().lya_autotune_fft(ctypes.byref(box), _ptr(field), _ptr(work), work.numel() * work.element_size(),
+                                     int(reps), ms, ctypes.byref(t), _stream(stream)))
+    return t, [[ms[p * FFT_VARIANTS + v] for v in range(FFT_VARIANTS)] for p in range(2)]
+
+
+def autotune_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, work, reps=2, stream=None):
+    """lya_autotune_skewers: returns (Tuning, ms[len(SK_CHUNKS)][len(SK_BLOCKS_PER_CU)])."""
+    nc, nb = len(SK_CHUNKS), len(SK_BLOCKS_PER_CU)
+    ms = (ctypes.c_double * (nc * nb))()
+    t = Tuning()
+    _acheck(_lib2().lya_autotune_skewers(ctypes.byref(box), _ptr(field), ctypes.byref(sk), ctypes.byref(ps),
+                                         int(seed), ctypes.byref(cosmo), ctypes.byref(fgpa) if fgpa else None,
+                                         _ptr(dens), _ptr(eta), _ptr(flux),
+                                         ctypes.byref(zbins) if zbins is not None else None, _ptr(work),
+                                         work.numel() * work.element_size(), int(reps), ms, ctypes.byref(t),
+                                         _stream(stream)))
+    return t, [[ms[i * nb + j] for j in range(nb)] for i in range(nc)]
+
+
+class Graph:
+    """A captured sequence of library calls (lya_graph_*): use as
+    `with L.Graph(stream) as g: <library calls on stream>`, then g.launch()."""
+
+    def __init__(self, stream=None):
+        self.stream = stream
+        self.handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        _acheck(_lib2().lya_graph_begin(_stream(self.stream)))
+        return self
+
+    def __exit__(self, et, ev, tb):
+        rc = _lib2().lya_graph_end(_stream(self.stream), ctypes.byref(self.handle))
+        if et is None:
+            _acheck(rc)
+        return False
+
+    def launch(self, stream=None):
+        _acheck(_lib2().lya_graph_launch(self.handle, _stream(stream if stream is not None else self.stream)))
+
+    def close(self):
+        if self.handle:
+            _acheck(_lib2().lya_graph_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

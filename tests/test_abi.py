@@ -38,7 +38,7 @@ def test_library_exports_every_declared_function():
 STRUCTS = {
     "lya_box": L.Box, "lya_pk": L.Pk, "lya_skewers": L.Skewers, "lya_ps1d": L.Ps1d, "lya_fgpa": L.Fgpa,
     "lya_cosmo": L.Cosmo, "lya_zbins": L.ZBins, "lya_p1d_spec": L.P1dSpec, "lya_tune_spec": L.TuneSpec,
-    "lya_tune_result": L.TuneResult,
+    "lya_tune_result": L.TuneResult, "lya_tuning": L.Tuning,
 }
 
 
@@ -90,3 +90,18 @@ def test_chi_of_z_on_the_host_matches_the_oracle():
         L.chi_of_z([-1.0])
     with pytest.raises(L.LyaError):
         L.chi_of_z([1.0], omega_m=1.5)
+
+
+def test_tuning_table_on_the_host():
+    t = L.get_tuning(2048)
+    assert (t.fft_y, t.fft_x, t.sk_chunk, t.sk_blocks_per_cu) == (0, 1, 8, 4)
+    L.set_tuning(2048, L.Tuning(4, 5, 16, 2))
+    u = L.get_tuning(2048)
+    assert (u.fft_y, u.fft_x, u.sk_chunk, u.sk_blocks_per_cu) == (4, 5, 16, 2)
+    with pytest.raises(L.LyaError):
+        L.set_tuning(512, L.Tuning(2, 1, 8, 4))      # half tiles exist from 1024 up
+    with pytest.raises(L.LyaError):
+        L.set_tuning(2048, L.Tuning(0, 1, 8, 5))
+    L.set_tuning(2048, t)
+    v = L.get_tuning(512)
+    assert (v.fft_y, v.fft_x) == (0, 1)

@@ -1,0 +1,158 @@
+"""Launch-shape variants, the autotuners and HIP-graph capture (C-ABI).
+
+Every strided-FFT variant runs the same butterflies on the same pencils, and
+every skewer launch shape computes each skewer in one wavefront with exact
+fixed-point bin sums, so all of them must give bit-identical outputs; a
+captured graph replayed several times (with eager work in between) must
+reproduce the eager outputs exactly."""
+import numpy as np
+import pytest
+
+import mockinputs
+from tests.lyahelp import skewer_tensors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_18996_amd import lyamock
+    lyamock.load()
+    return lyamock
+
+
+def _box(L, torch, n):
+    box = L.box_struct(n, 2.19)
+    field = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    return box, field, work
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_fft_variants_are_bit_identical(L, n):
+    import torch
+    print("fft variants n=%d" % n, flush=True)
+    box, field, work = _box(L, torch, n)
+    pk = L.pk_struct()
+    saved = L.get_tuning(n)
+    try:
+        L.set_tuning(n, L.Tuning(0, 1, saved.sk_chunk, saved.sk_blocks_per_cu))
+        L.make_box(box, pk, 1234, 1.0, True, field, work)
+        ref = L.box_view(field, n).clone()      # the plane padding is never written
+        for vy, vx in [(1, 0), (2, 3), (3, 2), (4, 5), (5, 4), (6, 7), (7, 6), (8, 9), (9, 8)]:
+            field.fill_(float("nan"))
+            L.set_tuning(n, L.Tuning(vy, vx, saved.sk_chunk, saved.sk_blocks_per_cu))
+            L.make_box(box, pk, 1234, 1.0, True, field, work)
+            torch.cuda.synchronize()
+            assert torch.equal(L.box_view(field, n), ref), (vy, vx)
+    finally:
+        L.set_tuning(n, saved)
+    del ref, field, work
+    torch.cuda.empty_cache()
+
+
+def test_autotune_fft_keeps_results(L):
+    import torch
+    n = 1024
+    box, field, work = _box(L, torch, n)
+    pk = L.pk_struct()
+    saved = L.get_tuning(n)
+    try:
+        L.make_box(box, pk, 77, 1.0, True, field, work)
+        ref = L.box_view(field, n).clone()
+        t, ms = L.autotune_fft(box, field, work, reps=2)
+        print("autotune fft n=%d: y %d x %d; ms %s" % (n, t.fft_y, t.fft_x, ms))
+        assert 0 <= t.fft_y < L.FFT_VARIANTS and 0 <= t.fft_x < L.FFT_VARIANTS
+        assert all(v > 0 for row in ms for v in row)
+        assert ms[0][t.fft_y] == min(ms[0]) and ms[1][t.fft_x] == min(ms[1])
+        L.make_box(box, pk, 77, 1.0, True, field, work)
+        torch.cuda.synchronize()
+        assert torch.equal(L.box_view(field, n), ref)
+        small = L.box_struct(256, 2.19)
+        f2 = torch.empty((L.field_elems(small), 2), dtype=torch.float32, device="cuda")
+        t2, ms2 = L.autotune_fft(small, f2, work, reps=1)
+        assert t2.fft_y in (0, 1) and t2.fft_x in (0, 1)
+        assert all(ms2[p][v] == -1.0 for p in range(2) for v in range(2, L.FFT_VARIANTS))
+    finally:
+        L.set_tuning(n, saved)
+        L.set_tuning(256, L.Tuning(0, 1, 8, 4))
+
+
+def _mid_skewers(L, torch, n=256, n_sk=3000):
+    cfg = mockinputs.config("mid", n=n, n_sk=n_sk)
+    sk = mockinputs.skewer_table(cfg)
+    s, keep = skewer_tensors(L, sk)
+    tot = sk["total"]
+    bufs = [torch.empty(tot, dtype=torch.float32, device="cuda") for _ in range(3)]
+    edges = torch.from_numpy(L.chi_of_z(cfg["z_edges"])).cuda()
+    fsum = torch.zeros(len(cfg["z_edges"]) - 1, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros_like(fsum, dtype=torch.int64)
+    zb = L.zbins_struct(edges, fsum, cnt)
+    return cfg, s, keep, bufs, (edges, fsum, cnt), zb
+
+
+def test_autotune_skewers_keeps_results(L):
+    import torch
+    n = 256
+    box, field, work = _box(L, torch, n)
+    cfg, s, keep, (d, e, f), zkeep, zb = _mid_skewers(L, torch, n)
+    L.make_box(box, L.pk_struct(**cfg["pk"]), 5, 1.0, True, field, work)
+    swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    ps = L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0)
+    cosmo, fg = L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"])
+    saved = L.get_tuning(n)
+    try:
+        L.draw_skewers(box, field, s, ps, 5, cosmo, fg, d, e, f, zb, swork)
+        torch.cuda.synchronize()
+        ref = [x.clone() for x in (d, e, f, zkeep[1], zkeep[2])]
+        t, ms = L.autotune_skewers(box, field, s, ps, 5, cosmo, fg, d, e, f, zb, swork, reps=1)
+        print("autotune skewers: chunk %d blocks/CU %d" % (t.sk_chunk, t.sk_blocks_per_cu))
+        assert t.sk_chunk in L.SK_CHUNKS and t.sk_blocks_per_cu in L.SK_BLOCKS_PER_CU
+        for c in (1, 64):
+            for b in (1, 4):
+                L.set_tuning(n, L.Tuning(saved.fft_y, saved.fft_x, c, b))
+                for x in (d, e, f):
+                    x.fill_(float("nan"))
+                L.draw_skewers(box, field, s, ps, 5, cosmo, fg, d, e, f, zb, swork)
+                torch.cuda.synchronize()
+                for x, r in zip((d, e, f, zkeep[1], zkeep[2]), ref):
+                    assert torch.equal(x, r), (c, b)
+    finally:
+        L.set_tuning(n, saved)
+
+
+def test_graph_replays_match_eager(L):
+    import torch
+    n = 256
+    box, field, work = _box(L, torch, n)
+    cfg, s, keep, (d, e, f), zkeep, zb = _mid_skewers(L, torch, n)
+    swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    pk = L.pk_struct(**cfg["pk"])
+    ps = L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0)
+    cosmo, fg = L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        L.make_box(box, pk, 9, 1.0, True, field, work, stream)
+        L.draw_skewers(box, field, s, ps, 9, cosmo, fg, d, e, f, zb, swork, stream)
+    stream.synchronize()
+    ref = [x.clone() for x in (L.box_view(field, n), d, e, f, zkeep[1], zkeep[2])]
+    g = L.Graph(stream)
+    with g:
+        L.make_box(box, pk, 9, 1.0, True, field, work, stream)
+        L.draw_skewers(box, field, s, ps, 9, cosmo, fg, d, e, f, zb, swork, stream)
+    try:
+        for rep in range(3):
+            for x in (field, d, e, f, zkeep[1], zkeep[2]):
+                x.zero_()
+            torch.cuda.synchronize()
+            g.launch()
+            stream.synchronize()
+            for x, r in zip((L.box_view(field, n), d, e, f, zkeep[1], zkeep[2]), ref):
+                assert torch.equal(x, r), rep
+            junk = torch.randn(1 << 20, device="cuda").sum().item()  # eager work between replays
+            assert np.isfinite(junk)
+    finally:
+        g.close()

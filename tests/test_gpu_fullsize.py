@@ -1,0 +1,206 @@
+"""Parity at the full sizes of the benchmark configurations.
+
+* 2048^3 box (the benchmark workload): whole z-lines against the exact FP64
+  C oracle (O(N^3) per batch of lines), then the skewer stage on a
+  10,000-skewer subset of the 1M-skewer table, with the oracle interpolating
+  the GPU field (already checked line by line) in FP64.
+* 1024^3 precision configuration: FP32 against BF16 storage of {delta,
+  eta_par}, each against the FP64 oracle: z-lines, pixels, flux, mean flux per
+  redshift bin and P1D on a 20,000-skewer subset of the 200,000-skewer table.
+"""
+import numpy as np
+import pytest
+
+import mockinputs
+from oracle import fgpa, lines, p1d, skewers
+from tests.lyahelp import oracle_table, rel_rms, skewer_tensors
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_18996_amd import lyamock
+    lyamock.load()
+    return lyamock
+
+
+class DeviceGrid:
+    """[n, n, n] complex view of a device box for the oracle's trilinear
+    gathers: indexing copies the requested voxels to the host (data movement
+    only; every arithmetic step stays in the FP64 oracle)."""
+
+    def __init__(self, L, field, n, bf16=False):
+        import torch
+        self.torch = torch
+        self.n = n
+        self.shape = (n, n, n)
+        self.bf16 = bf16
+        self.v = L.box_view(field, n)
+
+    def __getitem__(self, idx):
+        t = self.torch
+        a, b, c = (t.from_numpy(np.ascontiguousarray(i, dtype=np.int64)).cuda() for i in idx)
+        vals = self.v[a, b, c]
+        if self.bf16:  # packed bf16x2 words: low half delta, high half eta
+            w = vals.cpu().numpy().view(np.uint32)
+            re = (w << 16).view(np.float32).astype(np.float64)
+            im = (w & 0xFFFF0000).view(np.float32).astype(np.float64)
+        else:
+            h = vals.cpu().numpy().astype(np.float64)
+            re, im = h[..., 0], h[..., 1]
+        return re + 1j * im
+
+
+def subset(sk, count, seed):
+    """count skewers of the table sk (random, in table order), re-packed."""
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(sk["npix"]), size=count, replace=False))
+    npix = sk["npix"][idx]
+    off = np.zeros(count, dtype=np.int64)
+    off[1:] = np.cumsum(npix[:-1].astype(np.int64))
+    return dict(origin_fx=sk["origin_fx"][idx], step_fx=sk["step_fx"][idx], npix=npix, offset=off,
+                chi0=sk["chi0"][idx], dchi=sk["dchi"], id_base=0, total=int(npix.sum()))
+
+
+def oracle_pixels(grid, sk, seed, cfg):
+    """The oracle's pre-FGPA pixels: trilinear on grid (FP64) + delta_S."""
+    pos = np.concatenate([skewers.pixel_positions(sk["origin_fx"][q], sk["step_fx"][q], int(sk["npix"][q]))
+                          for q in range(len(sk["npix"]))])
+    v = skewers.trilinear(grid, pos)
+    dens = v.real.copy()
+    for q in range(len(sk["npix"])):
+        o, nq = int(sk["offset"][q]), int(sk["npix"][q])
+        dens[o:o + nq] += skewers.delta_s(seed, q, nq, cfg["dpix"], cfg["ps_amp"], cfg["ps_kcut"])
+    return dens, v.imag.copy()
+
+
+def gpu_pixels(L, torch, box, field, sk, seed, cfg, edges):
+    s, keep = skewer_tensors(L, sk)
+    tot = sk["total"]
+    d, e, f = (torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(3))
+    ed = torch.from_numpy(edges).cuda()
+    fs = torch.zeros(len(edges) - 1, dtype=torch.float64, device="cuda")
+    cn = torch.zeros(len(edges) - 1, dtype=torch.int64, device="cuda")
+    work = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    L.draw_skewers(box, field, s, L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0), seed,
+                   L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"]), d, e, f, L.zbins_struct(ed, fs, cn), work)
+    torch.cuda.synchronize()
+    out = dict(dens=d.cpu().numpy(), eta=e.cpu().numpy(), flux=f.cpu().numpy(), fsum=fs.cpu().numpy(),
+               count=cn.cpu().numpy())
+    return out, (s, keep, f, ed, fs, cn)
+
+
+def gpu_p1d(L, torch, sk_handles, k_edges, z_ref, cfg, n_sk):
+    s, keep, f, ed, fs, cn = sk_handles
+    ke = torch.from_numpy(k_edges).cuda()
+    ps = torch.zeros(len(k_edges) - 1, dtype=torch.float64, device="cuda")
+    pc = torch.zeros(len(k_edges) - 1, dtype=torch.int64, device="cuda")
+    work = torch.empty(L.p1d_workspace_size(n_sk, len(k_edges) - 1), dtype=torch.uint8, device="cuda")
+    L.p1d(s, L.Cosmo(cfg["omega_m"]), f, L.zbins_struct(ed, fs, cn), L.P1dSpec(len(k_edges) - 1, ke.data_ptr(),
+          float(z_ref), float(cfg["dpix"])), ps, pc, work)
+    torch.cuda.synchronize()
+    return ps.cpu().numpy(), pc.cpu().numpy()
+
+
+def _make(L, torch, cfg, storage):
+    n = cfg["n"]
+    box = L.box_struct(n, cfg["dx"], storage)
+    elems = L.field_elems(box)
+    field = (torch.empty((elems, 2), dtype=torch.float32, device="cuda") if storage == L.LYA_F32
+             else torch.empty((elems,), dtype=torch.int32, device="cuda"))
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    L.make_box(box, L.pk_struct(**cfg["pk"]), cfg["seed"], cfg["f"], True, field, work)
+    torch.cuda.synchronize()
+    del work
+    return box, field
+
+
+@pytest.mark.timeout(600)
+def test_big_box_lines_and_skewer_subset(L):
+    import torch
+    cfg = mockinputs.config("big")
+    n = cfg["n"]
+    print("2048^3 box: lines against the C oracle", flush=True)
+    box, field = _make(L, torch, cfg, L.LYA_F32)
+    view = L.box_view(field, n)
+    cols = [(0, 0), (1, n - 1), (n // 2, 3), (1234, 777)]
+    re, im = lines.field_lines(n, cfg["seed"], oracle_table(cfg["pk"], n, cfg["dx"]), cols)
+    for l, (mx, my) in enumerate(cols):
+        line = view[mx, my].cpu().numpy().astype(np.float64)
+        e = (rel_rms(line[:, 0], re[l]), rel_rms(line[:, 1], im[l]))
+        print("line", (mx, my), "rel rms delta %.2e eta %.2e" % e, flush=True)
+        assert max(e) < TOL, (mx, my, e)
+    print("skewer subset", flush=True)
+    sk = subset(mockinputs.skewer_table(cfg), 10_000, 7)
+    edges = fgpa.chi_edges_for_z(cfg["z_edges"])
+    out, _ = gpu_pixels(L, torch, box, field, sk, cfg["seed"], cfg, edges)
+    print("oracle pixels (%d)" % sk["total"], flush=True)
+    rd, re_ = oracle_pixels(DeviceGrid(L, field, n), sk, cfg["seed"], cfg)
+    print("oracle FGPA", flush=True)
+    rf, _ = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
+    e = dict(dens=rel_rms(out["dens"], rd), eta=rel_rms(out["eta"], re_), flux=rel_rms(out["flux"], rf))
+    print("10k skewers (%d pixels): rel rms" % sk["total"], e, flush=True)
+    assert all(v < TOL for v in e.values()), e
+    fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
+    np.testing.assert_array_equal(out["count"], cnt)
+    ok = cnt > 0
+    assert np.max(np.abs(out["fsum"][ok] / fs[ok] - 1)) < 1e-5
+    del view, field
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_precision_fp32_and_bf16_storage(L):
+    import torch
+    cfg = mockinputs.config("precision")
+    n = cfg["n"]
+    print("1024^3 precision configuration", flush=True)
+    box32, f32 = _make(L, torch, cfg, L.LYA_F32)
+    box16, f16 = _make(L, torch, cfg, L.LYA_BF16)
+    cols = [(0, 0), (3, n - 1), (n // 2, 17), (700, 300)]
+    print("C oracle lines", flush=True)
+    re, im = lines.field_lines(n, cfg["seed"], oracle_table(cfg["pk"], n, cfg["dx"]), cols)
+    g32, g16 = DeviceGrid(L, f32, n), DeviceGrid(L, f16, n, bf16=True)
+    report = {}
+    for name, g in (("fp32", g32), ("bf16", g16)):
+        d = [rel_rms(g[(np.full(n, mx), np.full(n, my), np.arange(n))].real, re[l]) for l, (mx, my) in enumerate(cols)]
+        h = [rel_rms(g[(np.full(n, mx), np.full(n, my), np.arange(n))].imag, im[l]) for l, (mx, my) in enumerate(cols)]
+        report[name] = dict(delta=max(d), eta=max(h))
+    sk = subset(mockinputs.skewer_table(cfg), 20_000, 11)
+    edges = fgpa.chi_edges_for_z(cfg["z_edges"])
+    # oracle pixels interpolate the FP32 GPU field, itself checked line by line above
+    print("oracle pixels (%d)" % sk["total"], flush=True)
+    rd, re_ = oracle_pixels(g32, sk, cfg["seed"], cfg)
+    print("oracle FGPA", flush=True)
+    rf, _ = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
+    print("oracle P1D", flush=True)
+    fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
+    ok = cnt > 0
+    fmean = np.where(ok, fs / np.maximum(cnt, 1), 1.0)
+    k_edges = mockinputs.tune_k_edges()
+    ps_r, pc_r = p1d.p1d(rf, sk, edges, fmean, k_edges, 2.6, cfg["dpix"])
+    good = pc_r > 0
+    for name, box, field in (("fp32", box32, f32), ("bf16", box16, f16)):
+        print("GPU skewers and P1D,", name, flush=True)
+        out, hd = gpu_pixels(L, torch, box, field, sk, cfg["seed"], cfg, edges)
+        ps_g, pc_g = gpu_p1d(L, torch, hd, k_edges, 2.6, cfg, len(sk["npix"]))
+        np.testing.assert_array_equal(pc_g, pc_r)
+        report[name].update(dens=rel_rms(out["dens"], rd), eta_pix=rel_rms(out["eta"], re_),
+                            flux=rel_rms(out["flux"], rf),
+                            fbar_max_rel=float(np.max(np.abs(out["fsum"][ok] / fs[ok] - 1))),
+                            p1d_max_rel=float(np.max(np.abs(ps_g[good] / ps_r[good] - 1))))
+    for name, r in report.items():
+        print(name, {k: "%.2e" % v for k, v in r.items()}, flush=True)
+    f = report["fp32"]
+    assert max(f["delta"], f["eta"], f["dens"], f["eta_pix"], f["flux"], f["fbar_max_rel"]) < TOL, f
+    assert f["p1d_max_rel"] < 1e-4, f
+    b = report["bf16"]
+    assert max(b["delta"], b["eta"], b["dens"], b["eta_pix"], b["flux"]) < 1e-2, b
+    assert b["fbar_max_rel"] < 1e-3 and b["p1d_max_rel"] < 5e-2, b
+    del f32, f16
+    torch.cuda.empty_cache()
