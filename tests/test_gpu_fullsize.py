@@ -148,8 +148,8 @@ def test_big_box_lines_and_skewer_subset(L):
     assert all(v < TOL for v in e.values()), e
     fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
     np.testing.assert_array_equal(out["count"], cnt)
-    ok = cnt > 0
-    assert np.max(np.abs(out["fsum"][ok] / fs[ok] - 1)) < 1e-5
+    # the GPU sums round(F 2^32) exactly: each pixel carries at most half a quantum
+    assert np.all(np.abs(out["fsum"] - fs) <= 1e-5 * np.abs(fs) + cnt * 2.0 ** -32)
     del view, field
     torch.cuda.empty_cache()
 
@@ -190,9 +190,12 @@ def test_precision_fp32_and_bf16_storage(L):
         out, hd = gpu_pixels(L, torch, box, field, sk, cfg["seed"], cfg, edges)
         ps_g, pc_g = gpu_p1d(L, torch, hd, k_edges, 2.6, cfg, len(sk["npix"]))
         np.testing.assert_array_equal(pc_g, pc_r)
+        # mean-flux error in units of each bin's own scale: relative, plus the
+        # fixed-point quantum 2^-32 per pixel of the GPU's exact sums
+        fb_err = np.abs(out["fsum"] - fs) / (np.abs(fs) + cnt * 2.0 ** -32 / 1e-5)
         report[name].update(dens=rel_rms(out["dens"], rd), eta_pix=rel_rms(out["eta"], re_),
                             flux=rel_rms(out["flux"], rf),
-                            fbar_max_rel=float(np.max(np.abs(out["fsum"][ok] / fs[ok] - 1))),
+                            fbar_max_rel=float(np.max(fb_err[ok])),
                             p1d_max_rel=float(np.max(np.abs(ps_g[good] / ps_r[good] - 1))))
     for name, r in report.items():
         print(name, {k: "%.2e" % v for k, v in r.items()}, flush=True)
