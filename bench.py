@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/box2048_skewers1M_hbm_traffic.md.  Valid only for the kernels as
 # they were when the counters were taken (a changed kernel must drop its
 # entry) and reported only for that workload.
-TRAFFIC = {"fft_x": 137534552117, "fft_y": 140341231014, "fft_z_gen": 96074136017, "skewers": 14565410985}
+TRAFFIC = {"fft_x": 137534552117, "fft_y": 140341231014, "fft_z_gen": 96074136017}
 TRAFFIC_CONFIG = "big"
 
 

@@ -189,16 +189,18 @@ int lya_p1d(const lya_skewers* sk, const lya_cosmo* cosmo, const float* flux, co
  * saved forests in post-production.  Search: Nelder-Mead in (ln a, ln b) from
  * (a0, b0), initial steps 0.3, stopping when all vertices lie within xatol
  * (coordinates) and fatol (chi^2) of the best or after max_evals evaluations.
- * Mode LYA_TUNE_PLAIN evaluates every point on the GPU.  LYA_TUNE_EMULATOR
- * runs the same search on the device against a model of the statistics, the
- * emulator's prediction (see lya_emulator_*) plus an offset plus a linear
- * correction in (ln a, ln b); each search is followed by one GPU evaluation at
- * its optimum, after which the offset is set so that the model equals the GPU
- * there and the linear correction takes a Broyden update so that it also
- * reproduces the previous GPU evaluation; the next search starts there with
- * steps 0.05.  Points outside the emulator's (a, b) input range are rejected.
- * It stops when a search moves the point by at most max(10 xatol, 1e-4) or
- * after emu_checks GPU evaluations; the result holds the last GPU evaluation.  a(z), b(z), c(z)
+ * Mode LYA_TUNE_PLAIN evaluates every Nelder-Mead point on the GPU.
+ * LYA_TUNE_EMULATOR searches on the device against a model of the
+ * statistics, the emulator's prediction (see lya_emulator_*) plus an offset
+ * plus a linear correction in (ln a, ln b), by Levenberg-Marquardt on the
+ * residuals above (Jacobian by forward differences of the model, h = 1e-3);
+ * each search is followed by one GPU evaluation at its optimum, after which
+ * the offset is set so that the model equals the GPU there and the linear
+ * correction takes a Broyden update so that it also reproduces the previous
+ * GPU evaluation; the next search starts there.  Points outside the
+ * emulator's (a, b) input range are rejected.  It stops when a search moves
+ * the point by at most max(10 xatol, 5e-4) or after emu_checks GPU
+ * evaluations; the result holds the last GPU evaluation.  a(z), b(z), c(z)
  * are then least-squares quadratics in (1+z) (n_zt >= 3; the line through
  * two points, a constant for one).  Synchronous (reads back the
  * statistics of every evaluation); all GPU work runs on `stream`. */

@@ -30,7 +30,9 @@ __global__ void __launch_bounds__(kPdNT) k_p1d(P1dArgs a) {
   __shared__ int sjb[kPdWaves][kMaxZBins + 1];
   __shared__ int smlo[kPdWaves][kMaxKBins + 1];
   __shared__ float sfm[kMaxZBins];
+  __shared__ float2 stw[kTw2048];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  load_twiddles(stw, a.tw2048, tid, kPdNT);
   for (int b = tid; b < a.n_fbins; b += kPdNT) {
     const double c = static_cast<double>(a.fcount[b]);
     sfm[b] = c > 0.0 ? static_cast<float>(a.fsum[b] / c) : 1.0f;
@@ -87,7 +89,7 @@ __global__ void __launch_bounds__(kPdNT) k_p1d(P1dArgs a) {
         buf[pidx(n)] = make_float2(d[0], d[1]);
       }
       wave_sync();
-      wave_ifft(buf, M, a.tw2048, lane);
+      wave_ifft(buf, M, stw, lane);
       const int twstep = kTw2048 / n_p;
       const float scale = static_cast<float>(a.dv / n_p);
       for (int m = lane + 1; m <= M; m += 64) {
@@ -95,7 +97,7 @@ __global__ void __launch_bounds__(kPdNT) k_p1d(P1dArgs a) {
         const float2 zc = buf[pidx(M - m)];
         const float2 E = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
         const float2 O = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
-        const float2 X = cadd(E, cmul(a.tw2048[m * twstep], O));
+        const float2 X = cadd(E, cmul(stw[m * twstep], O));
         pw[m] = scale * (X.x * X.x + X.y * X.y);
       }
       // first mode of each k bin: smallest m >= 1 with k_m >= edge (M+1 if none)

@@ -70,7 +70,7 @@ __device__ __forceinline__ float2 ps_mode(const SkewerArgs& a, uint64_t qid, int
 
 // delta_S of one skewer by one wavefront into buf (pixel 2n in .x and pixel
 // 2n+1 in .y of element pidx(n)); ns = next_pow2(npix) >= 2.
-__device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, float2* buf, int lane) {
+__device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, float2* buf, const float2* tw, int lane) {
   const int M = ns / 2;
   const float amp_scale = static_cast<float>(a.ps_amp / (ns * a.dpix));
   const double dk = 2.0 * M_PI / (ns * a.dpix) / a.ps_kcut;
@@ -88,18 +88,18 @@ __device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, floa
     {
       const float2 s = make_float2(yk.x + ymk.x, yk.y - ymk.y);   // Y_k + conj(Y_{M-k})
       const float2 d = make_float2(yk.x - ymk.x, yk.y + ymk.y);   // Y_k - conj(Y_{M-k})
-      const float2 t = cmul(d, a.tw2048[k * twstep]);
+      const float2 t = cmul(d, tw[k * twstep]);
       buf[pidx(k)] = make_float2(s.x - t.y, s.y + t.x);
     }
     if (M - k != k) {
       const float2 s = make_float2(ymk.x + yk.x, ymk.y - yk.y);
       const float2 d = make_float2(ymk.x - yk.x, ymk.y + yk.y);
-      const float2 t = cmul(d, a.tw2048[(M - k) * twstep]);
+      const float2 t = cmul(d, tw[(M - k) * twstep]);
       buf[pidx(M - k)] = make_float2(s.x - t.y, s.y + t.x);
     }
   }
   wave_sync();
-  wave_ifft(buf, M, a.tw2048, lane);
+  wave_ifft(buf, M, tw, lane);
 }
 
 __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c000, float c001, float c010, float c011,
@@ -144,7 +144,8 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
       while (ns < np) ns <<= 1;
       // delta_S needs next_pow2(npix) <= 2048 (the wave's LDS line); longer skewers get none
       const bool with_ds = gather && a.ps_amp > 0.0 && ns >= 2 && ns <= 2 * kHalfMax;
-      if (with_ds) small_scale_wave(a, a.id_base + q, ns, buf, lane);
+      // twiddles from global memory: a copy in LDS would cost this kernel its fourth block per CU
+      if (with_ds) small_scale_wave(a, a.id_base + q, ns, buf, a.tw2048, lane);
       // bin boundaries: jb[b] = first pixel with chi_j < edges[b] (chi_j decreases with j)
       if (want_bins) {
         bin_bounds(a.chi_edges, a.n_bins, chi0, a.dchi, np, jb, lane);

@@ -154,6 +154,32 @@ struct P1dArgs {
 };
 hipError_t launch_p1d(const P1dArgs& a, double* psum, int64_t* pcount, hipStream_t st);
 
+// Batched tuning statistics (Fbar and binned P1D) of stored pixels for up to
+// kTuneEvalMaxG constant-parameter draws in one pass.
+constexpr int kTuneEvalMaxG = 8;
+struct TuneEvalArgs {
+  int64_t n_sk;
+  const int32_t* npix;
+  const int64_t* offset;
+  const float* dens;
+  const float* eta;
+  int G;                          // draws in this launch
+  float draw[kTuneEvalMaxG][3];   // a, b, c of each draw
+  double dv[kTuneEvalMaxG];       // velocity pixel (km/s) at each draw's z
+  int nk;
+  const double* k_edges;          // device [nk + 1]
+  double* fs;                     // workspace [G][n_sk]: sum of F per skewer
+  double* ps;                     // workspace [G][nk][n_sk]: sum |X_m|^2 / N_P
+  int* pc;                        // workspace [G][nk][n_sk]: modes
+  const float2* tw2048;
+  unsigned int* queue;
+  int chunk;
+};
+// sums/counts: [G][nk + 1] (bins, then flux and pixels); rows (FP64) and rows32
+// (FP32, may be NULL): [G][1 + nk] = Fbar, P_1..P_nk.
+hipError_t launch_tune_eval(const TuneEvalArgs& a, double* sums, int64_t* counts, double* rows, float* rows32,
+                            hipStream_t st);
+
 // Tuning (lya_tune.hip) and the emulator used by it (lya_mlp.hip).
 size_t emulator_eval_bytes();
 // Device-side Nelder-Mead over th = (ln a, ln b) on the model

@@ -487,6 +487,7 @@ size_t emulator_eval_bytes() { return 1024; }
 
 // ---------------------------------------------------------------- device-side tuning search
 constexpr int kSearchNT = 1024;
+constexpr int kLmS = 3;  // samples per batched forward pass: a point and two difference steps
 
 struct SearchArgs {
   const EmuHeader* h;
@@ -499,134 +500,207 @@ struct SearchArgs {
   double* out;               // x[2], best objective, evaluations, raw prediction [1 + nk] at x
 };
 
-// One forward pass of a single input by a block of kSearchNT threads: four
-// threads per hidden unit (a quarter of the inner sum each), sixteen per
-// output column; raw outputs (exp for columns >= log_from) into outv.
-__device__ void forward_one(const EmuHeader* __restrict__ h, const float* __restrict__ params, const Offs& o,
-                            const float xin[4], float (*hs)[kHid], float* part, float* outv) {
+// Forward passes of ns <= kLmS inputs by a block of kSearchNT threads sharing
+// every weight load (hidden layers: float4 loads of four units, sixteen
+// threads per unit group; output layer: sixteen threads per column); raw
+// outputs (exp for columns >= log_from) into outv[s].
+__device__ void forward_batch(const EmuHeader* __restrict__ h, const float* __restrict__ params, const Offs& o,
+                              const float (*xin)[4], int ns, float (*hs)[kLmS][kHid], float* part,
+                              float (*outv)[kMaxOut]) {
   const int t = threadIdx.x, n_out = h->n_out;
   if (t < kHid) {
-    float a = params[o.b[0] + t];
+    const float b0 = params[o.b[0] + t];
+    for (int s = 0; s < ns; ++s) {
+      float a = b0;
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) a = fmaf(scale_input(h, i, xin[i]), params[o.W[0] + i * kHid + t], a);
-    hs[0][t] = gelu(a);
+      for (int i = 0; i < kIn; ++i) a = fmaf(scale_input(h, i, xin[s][i]), params[o.W[0] + i * kHid + t], a);
+      hs[0][s][t] = gelu(a);
+    }
   }
   __syncthreads();
   int cur = 0;
-  const int u = t & (kHid - 1), q = t >> 8;
+  // hidden layers: thread = four consecutive units (one float4 weight load per
+  // k) x a sixteenth of the inner sum; the sixteen partial sums are added in
+  // a fixed order
+  const int ug = t & 63, kg = t >> 6;
   for (int l = 1; l < 3; ++l) {
-    float acc = 0.0f;
-    const float* W = params + o.W[l] + u;
-#pragma unroll 16
-    for (int k = 64 * q; k < 64 * q + 64; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * kHid], acc);
-    part[q * kHid + u] = acc;
+    float acc[kLmS][4] = {};
+    const float4* W = reinterpret_cast<const float4*>(params + o.W[l]) + ug;
+#pragma unroll 8
+    for (int k = 16 * kg; k < 16 * kg + 16; ++k) {
+      const float4 w = W[static_cast<size_t>(k) * (kHid / 4)];
+#pragma unroll
+      for (int s = 0; s < kLmS; ++s) {
+        if (s < ns) {
+          const float hv = hs[cur][s][k];
+          acc[s][0] = fmaf(hv, w.x, acc[s][0]);
+          acc[s][1] = fmaf(hv, w.y, acc[s][1]);
+          acc[s][2] = fmaf(hv, w.z, acc[s][2]);
+          acc[s][3] = fmaf(hv, w.w, acc[s][3]);
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kLmS; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[(kg * kLmS + s) * kHid + 4 * ug + j] = acc[s][j];
     __syncthreads();
     if (t < kHid) {
-      const float v = params[o.b[l] + t] + ((part[t] + part[kHid + t]) + (part[2 * kHid + t] + part[3 * kHid + t]));
-      hs[cur ^ 1][t] = gelu(v);
+      const float bl = params[o.b[l] + t];
+      for (int s = 0; s < ns; ++s) {
+        float v = 0.0f;
+        for (int i = 0; i < 16; ++i) v += part[(i * kLmS + s) * kHid + t];
+        hs[cur ^ 1][s][t] = gelu(bl + v);
+      }
     }
     __syncthreads();
     cur ^= 1;
   }
   const int oc = t & 63, r = t >> 6;  // column, sixteenth of the sum
-  float acc = 0.0f;
+  float acc[kLmS] = {0.0f, 0.0f, 0.0f};
   if (oc < n_out) {
     const float* W = params + o.W[3] + oc;
 #pragma unroll
-    for (int k = 16 * r; k < 16 * r + 16; ++k) acc = fmaf(hs[cur][k], W[static_cast<size_t>(k) * n_out], acc);
+    for (int k = 16 * r; k < 16 * r + 16; ++k) {
+      const float w = W[static_cast<size_t>(k) * n_out];
+#pragma unroll
+      for (int s = 0; s < kLmS; ++s)
+        if (s < ns) acc[s] = fmaf(hs[cur][s][k], w, acc[s]);
+    }
   }
-  part[r * 64 + oc] = acc;
+#pragma unroll
+  for (int s = 0; s < kLmS; ++s) part[(r * kLmS + s) * 64 + oc] = acc[s];
   __syncthreads();
   if (t < n_out) {
-    float v = 0.0f;
-    for (int i = 0; i < 16; ++i) v += part[i * 64 + t];
-    v = (params[o.b[3] + t] + v) * h->out_std[t] + h->out_mean[t];
-    if (t >= h->log_from) v = expf(v);
-    outv[t] = v;
+    for (int s = 0; s < ns; ++s) {
+      float v = 0.0f;
+      for (int i = 0; i < 16; ++i) v += part[(i * kLmS + s) * 64 + t];
+      v = (params[o.b[3] + t] + v) * h->out_std[t] + h->out_mean[t];
+      if (t >= h->log_from) v = expf(v);
+      outv[s][t] = v;
+    }
   }
   __syncthreads();
 }
 
-// Nelder-Mead over th = (ln a, ln b) on the model
+// Levenberg-Marquardt over th = (ln a, ln b) on the residuals of the model
 //   stat(th) = emulator(th) + off + jac (th - xk),
-// on the device in one block: the whole block runs each forward pass, wave 0
-// forms the objective (one statistic per lane, fixed-order shuffle sum) and
-// lane 0 steps the search and broadcasts the next point through LDS.  Points
-// outside the emulator's input range in a or b get an infinite objective.
+//   r_0 = (stat_0 - Fbar_t)/(s Fbar_t), r_{1+b} = (stat_{1+b} - P_t,b)/(s P_t,b)
+// (0 where the target or the value is not finite; chi^2 = sum r^2), entirely
+// on the device in one block.  Each iteration runs one batched forward pass at
+// the trial point and its two forward-difference steps (h = 1e-3), so the
+// Jacobian of an accepted point comes with it.  Wave 0 forms the residuals
+// (one statistic per lane) and the 2x2 normal equations (fixed-order shuffle
+// sums); lane 0 steps the search and broadcasts through LDS.  Trial points
+// outside the emulator's (a, b) input range are rejected like uphill steps.
+// Stops when an accepted step is below xatol in both coordinates, when the
+// damping exceeds 1e10, or after max_evals forward samples.
 __global__ void __launch_bounds__(kSearchNT) k_emu_search(SearchArgs a) {
-  __shared__ float hs[2][kHid];
-  __shared__ float part[4 * kHid];
-  __shared__ float outv[kMaxOut];
-  __shared__ double spt[2];
-  __shared__ int slast;
+  __shared__ float hs[2][kLmS][kHid];
+  __shared__ float part[16 * kLmS * kHid];
+  __shared__ float outv[kLmS][kMaxOut];
+  __shared__ double strial[2];
+  __shared__ int sstate;  // 0 evaluate strial, 1 done
   const Offs o = param_offsets(a.h->n_out);
   const int nk = a.nk, t = threadIdx.x;
   const double alo = log(static_cast<double>(a.h->in_lo[0])), ahi = log(static_cast<double>(a.h->in_hi[0]));
   const double blo = log(static_cast<double>(a.h->in_lo[1])), bhi = log(static_cast<double>(a.h->in_hi[1]));
-  Nm2 nm;  // used by lane 0 only
-  double x[2] = {a.x0[0], a.x0[1]}, fbest = HUGE_VAL;
+  constexpr double kH = 1e-3;
+  // lane-0 state
+  double th[2] = {a.x0[0], a.x0[1]}, chi2 = HUGE_VAL, lam = 1e-3, A00 = 0, A01 = 0, A11 = 0, g0 = 0, g1 = 0;
+  bool have = false;
   int nev = 0;
   if (t == 0) {
-    nm.init(a.x0, a.step, a.xatol, a.fatol, a.max_evals);
-    double p[2];
-    const bool more = nm.ask(p);
-    if (!more) {
-      nm.result(x, &fbest, &nev);
-      p[0] = x[0];
-      p[1] = x[1];
-    }
-    spt[0] = p[0];
-    spt[1] = p[1];
-    slast = more ? 0 : 1;
+    strial[0] = th[0];
+    strial[1] = th[1];
+    sstate = 0;
   }
   __syncthreads();
-  // at most max_evals + 2 search values, then one pass at the best vertex
-  for (int it = 0; it < a.max_evals + 4; ++it) {
-    const double th0 = spt[0], th1 = spt[1];
-    const int last = slast;
-    const float xin[4] = {static_cast<float>(exp(th0)), static_cast<float>(exp(th1)), static_cast<float>(a.c),
-                          static_cast<float>(a.z)};
-    forward_one(a.h, a.params, o, xin, hs, part, outv);
-    if (last) break;
+  const int max_iter = a.max_evals / kLmS + 1;
+  for (int it = 0; it < max_iter + 1; ++it) {
+    const double p0 = strial[0], p1 = strial[1];
+    const int state = sstate;
+    const float fc = static_cast<float>(a.c), fz = static_cast<float>(a.z);
+    const float xin[kLmS][4] = {{static_cast<float>(exp(p0)), static_cast<float>(exp(p1)), fc, fz},
+                                {static_cast<float>(exp(p0 + kH)), static_cast<float>(exp(p1)), fc, fz},
+                                {static_cast<float>(exp(p0)), static_cast<float>(exp(p1 + kH)), fc, fz}};
+    forward_batch(a.h, a.params, o, xin, state ? 1 : kLmS, hs, part, outv);
+    if (state) break;  // the last pass: the raw prediction at the optimum
     if (t < 64) {
-      const bool inside = th0 >= alo && th0 <= ahi && th1 >= blo && th1 <= bhi;
-      const double d0 = th0 - a.xk[0], d1 = th1 - a.xk[1];
-      double r = 0.0;
-      for (int i = t; i <= nk; i += 64) {
-        const double m = static_cast<double>(outv[i]) + a.off[i] + a.jac[i][0] * d0 + a.jac[i][1] * d1;
-        if (i == 0) {
-          const double fr = (m - a.fbar_t) / (a.sigma * a.fbar_t);
-          r += fr * fr;
-        } else {
-          r += chi2_term(m, a.pk_t[i - 1], a.sigma);
+      double r = 0.0, j0 = 0.0, j1 = 0.0;
+      const int i = t;
+      if (i <= nk) {
+        const double tgt = i == 0 ? a.fbar_t : a.pk_t[i - 1];
+        const double inv = 1.0 / (a.sigma * tgt);
+        const double d0 = p0 - a.xk[0], d1 = p1 - a.xk[1];
+        const double lin = a.off[i] + a.jac[i][0] * d0 + a.jac[i][1] * d1;
+        const double m = static_cast<double>(outv[0][i]) + lin;
+        const double ma = static_cast<double>(outv[1][i]) + lin + a.jac[i][0] * kH;
+        const double mb = static_cast<double>(outv[2][i]) + lin + a.jac[i][1] * kH;
+        if (isfinite(tgt) && isfinite(m) && isfinite(ma) && isfinite(mb)) {
+          r = (m - tgt) * inv;
+          j0 = (ma - m) * inv / kH;
+          j1 = (mb - m) * inv / kH;
         }
       }
+      double c2 = r * r, s00 = j0 * j0, s01 = j0 * j1, s11 = j1 * j1, q0 = j0 * r, q1 = j1 * r;
 #pragma unroll
-      for (int w = 32; w >= 1; w >>= 1) r += __shfl_xor(r, w);
+      for (int w = 32; w >= 1; w >>= 1) {
+        c2 += __shfl_xor(c2, w);
+        s00 += __shfl_xor(s00, w);
+        s01 += __shfl_xor(s01, w);
+        s11 += __shfl_xor(s11, w);
+        q0 += __shfl_xor(q0, w);
+        q1 += __shfl_xor(q1, w);
+      }
       if (t == 0) {
-        nm.tell(inside ? r : HUGE_VAL);
-        double p[2];
-        const bool more = nm.ask(p);
-        if (!more) {
-          nm.result(x, &fbest, &nev);
-          p[0] = x[0];
-          p[1] = x[1];
+        nev += kLmS;
+        const bool inside = p0 >= alo && p0 <= ahi && p1 >= blo && p1 <= bhi;
+        bool done = false;
+        if (inside && c2 < chi2) {  // accept the point (and its Jacobian)
+          const double step = have ? fmax(fabs(p0 - th[0]), fabs(p1 - th[1])) : HUGE_VAL;
+          th[0] = p0;
+          th[1] = p1;
+          chi2 = c2;
+          A00 = s00;
+          A01 = s01;
+          A11 = s11;
+          g0 = q0;
+          g1 = q1;
+          lam = fmax(lam / 3.0, 1e-12);
+          have = true;
+          if (step <= a.xatol) done = true;
+        } else {
+          lam *= 4.0;
+          if (lam > 1e10) done = true;
         }
-        spt[0] = p[0];
-        spt[1] = p[1];
-        slast = more ? 0 : 1;
+        if (!have) done = true;  // the start itself is unusable
+        if (nev + kLmS > a.max_evals) done = true;
+        double n0 = th[0], n1 = th[1];
+        if (!done) {  // (A + lam diag A) delta = -g
+          const double m00 = A00 * (1.0 + lam) + 1e-300, m11 = A11 * (1.0 + lam) + 1e-300, m01 = A01;
+          const double det = m00 * m11 - m01 * m01;
+          if (!(det > 0.0) || !isfinite(det)) {
+            done = true;
+          } else {
+            n0 = th[0] + (-g0 * m11 + g1 * m01) / det;
+            n1 = th[1] + (-g1 * m00 + g0 * m01) / det;
+          }
+        }
+        strial[0] = done ? th[0] : n0;
+        strial[1] = done ? th[1] : n1;
+        sstate = done ? 1 : 0;
       }
     }
     __syncthreads();
   }
   if (t == 0) {
-    if (!slast) nm.result(x, &fbest, &nev);  // bound reached (not expected)
-    a.out[0] = x[0];
-    a.out[1] = x[1];
-    a.out[2] = fbest;
+    a.out[0] = th[0];
+    a.out[1] = th[1];
+    a.out[2] = chi2;
     a.out[3] = static_cast<double>(nev);
   }
-  if (t <= nk) a.out[4 + t] = static_cast<double>(outv[t]);
+  if (t <= nk) a.out[4 + t] = static_cast<double>(outv[0][t]);
 }
 
 hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2], double* fbest, int* nev,

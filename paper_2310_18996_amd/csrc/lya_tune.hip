@@ -1,8 +1,9 @@
 // FGPA parameter tuning (section "Adjusting mock parameters"): host-side FP64
 // Nelder-Mead over (ln a, ln b) at each tuning redshift z_t with c fixed,
-// driving GPU evaluations of the mean flux and the 1D power of the stored
-// pre-FGPA pixels under constant (a, b, c) (the paper's post-production reuse
-// of saved forests), then least-squares quadratics in (1+z).  The emulator
+// driving GPU evaluations (k_tune_eval.hip) of the mean flux and the 1D power
+// of the stored pre-FGPA pixels under constant (a, b, c) (the paper's
+// post-production reuse of saved forests), then least-squares quadratics in
+// (1+z).  The emulator
 // mode runs the same search on the MLP's predictions, checks the optimum on the
 // GPU and corrects the prediction by the measured defect before searching
 // again (a few GPU evaluations per redshift instead of one per search step).
@@ -23,27 +24,51 @@ namespace {
 size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct TuneCarve {
-  size_t edges, fsum, fcnt, psum, pcnt, ztab, tw, queue, bsum, bcnt, part_sum, part_cnt, emu, total;
+  size_t tw, queue, fs, ps, pc, sums, counts, rows, emu, total;
 };
 
+// workspace of the batched evaluation: per-skewer partials for up to
+// kTuneEvalMaxG draws, the reductions, the statistics rows
 TuneCarve carve_tune(int64_t n_sk, int nk) {
   TuneCarve c{};
+  const size_t G = kTuneEvalMaxG, S = static_cast<size_t>(n_sk > 0 ? n_sk : 1);
   size_t o = 0;
-  c.edges = o;    o += 256;
-  c.fsum = o;     o += 256;
-  c.fcnt = o;     o += 256;
-  c.psum = o;     o += al256(sizeof(double) * kMaxKBins);
-  c.pcnt = o;     o += al256(sizeof(int64_t) * kMaxKBins);
-  c.ztab = o;     o += al256(sizeof(float) * kZTabN);
-  c.tw = o;       o += al256(sizeof(float2) * kTw2048);
-  c.queue = o;    o += 256;
-  c.bsum = o;     o += al256(sizeof(unsigned long long) * kMaxZBins);
-  c.bcnt = o;     o += al256(sizeof(unsigned long long) * kMaxZBins);
-  c.part_sum = o; o += al256(sizeof(double) * static_cast<size_t>(n_sk) * nk);
-  c.part_cnt = o; o += al256(sizeof(int) * static_cast<size_t>(n_sk) * nk);
-  c.emu = o;      o += al256(emulator_eval_bytes());
+  c.tw = o;     o += al256(sizeof(float2) * kTw2048);
+  c.queue = o;  o += 256;
+  c.fs = o;     o += al256(sizeof(double) * G * S);
+  c.ps = o;     o += al256(sizeof(double) * G * nk * S);
+  c.pc = o;     o += al256(sizeof(int) * G * nk * S);
+  c.sums = o;   o += al256(sizeof(double) * G * (nk + 1));
+  c.counts = o; o += al256(sizeof(int64_t) * G * (nk + 1));
+  c.rows = o;   o += al256(sizeof(double) * G * (nk + 1));
+  c.emu = o;    o += al256(emulator_eval_bytes());
   c.total = o;
   return c;
+}
+
+TuneEvalArgs eval_args(const lya_tune_spec* spec, char* w, const TuneCarve& c) {
+  TuneEvalArgs a{};
+  const lya_skewers* sk = spec->sk;
+  a.n_sk = sk->n_sk;
+  a.npix = sk->npix;
+  a.offset = sk->offset;
+  a.dens = spec->dens;
+  a.eta = spec->eta;
+  a.nk = spec->p1d.n_kbins;
+  a.k_edges = spec->p1d.k_edges;
+  a.fs = reinterpret_cast<double*>(w + c.fs);
+  a.ps = reinterpret_cast<double*>(w + c.ps);
+  a.pc = reinterpret_cast<int*>(w + c.pc);
+  a.tw2048 = reinterpret_cast<const float2*>(w + c.tw);
+  a.queue = reinterpret_cast<unsigned int*>(w + c.queue);
+  a.chunk = 4;
+  return a;
+}
+
+// velocity pixel in km/s at redshift z: dpix 100 E(z)/(1+z)
+double velocity_pixel_at(const lya_tune_spec* spec, double z) {
+  const double x = 1.0 + z, om = spec->cosmo.omega_m;
+  return spec->p1d.dpix * (100.0 * sqrt(om * (x * x * x) + (1.0 - om)) / x);
 }
 
 struct Evaluator {
@@ -52,82 +77,27 @@ struct Evaluator {
   TuneCarve c;
   hipStream_t st;
   int nk;
-  double* h_stats;  // pinned-free host staging: fsum, fcnt, psum[nk], pcnt[nk]
 
   // Mean flux and mean P1D per bin of the stored pixels under constant (a, b, c).
   hipError_t eval(double a, double b, double cc, double z, double* fbar, double* pk) {
-    const lya_skewers* sk = spec->sk;
-    SkewerArgs sa{};
-    sa.n_sk = sk->n_sk;
-    sa.npix = sk->npix;
-    sa.offset = sk->offset;
-    sa.chi0 = sk->chi0;
-    sa.dchi = sk->dchi;
-    sa.n = 32;
-    sa.in_dens = spec->dens;
-    sa.in_eta = spec->eta;
-    sa.do_flux = 1;
-    sa.cf[0][0] = static_cast<float>(a);
-    sa.cf[1][0] = static_cast<float>(b);
-    sa.cf[2][0] = static_cast<float>(cc);
-    sa.n_bins = 1;
-    sa.chi_edges = reinterpret_cast<const double*>(w + c.edges);
-    sa.bin_sum = reinterpret_cast<unsigned long long*>(w + c.bsum);
-    sa.bin_cnt = reinterpret_cast<unsigned long long*>(w + c.bcnt);
-    sa.out_fsum = reinterpret_cast<double*>(w + c.fsum);
-    sa.out_count = reinterpret_cast<int64_t*>(w + c.fcnt);
-    sa.ztab = reinterpret_cast<const float*>(w + c.ztab);
-    sa.tw2048 = reinterpret_cast<const float2*>(w + c.tw);
-    sa.queue = reinterpret_cast<unsigned int*>(w + c.queue);
-    sa.chunk = 8;
-    hipError_t e = launch_skewers(sa, st);
+    TuneEvalArgs ea = eval_args(spec, w, c);
+    ea.G = 1;
+    ea.draw[0][0] = static_cast<float>(a);
+    ea.draw[0][1] = static_cast<float>(b);
+    ea.draw[0][2] = static_cast<float>(cc);
+    ea.dv[0] = velocity_pixel_at(spec, z);
+    hipError_t e = launch_tune_eval(ea, reinterpret_cast<double*>(w + c.sums), reinterpret_cast<int64_t*>(w + c.counts),
+                                    reinterpret_cast<double*>(w + c.rows), nullptr, st);
     if (e != hipSuccess) return e;
-    P1dArgs pa{};
-    pa.n_sk = sk->n_sk;
-    pa.npix = sk->npix;
-    pa.offset = sk->offset;
-    pa.chi0 = sk->chi0;
-    pa.dchi = sk->dchi;
-    pa.dens = spec->dens;
-    pa.eta = spec->eta;
-    pa.fa = sa.cf[0][0];
-    pa.fb = sa.cf[1][0];
-    pa.fc = sa.cf[2][0];
-    pa.n_fbins = 1;
-    pa.chi_edges = sa.chi_edges;
-    pa.fsum = sa.out_fsum;
-    pa.fcount = sa.out_count;
-    pa.n_kbins = nk;
-    pa.k_edges = spec->p1d.k_edges;
-    const double x = 1.0 + z, om = spec->cosmo.omega_m;
-    pa.dv = spec->p1d.dpix * (100.0 * sqrt(om * (x * x * x) + (1.0 - om)) / x);
-    pa.part_sum = reinterpret_cast<double*>(w + c.part_sum);
-    pa.part_cnt = reinterpret_cast<int*>(w + c.part_cnt);
-    pa.tw2048 = sa.tw2048;
-    pa.queue = sa.queue;
-    pa.chunk = 4;
-    double* d_psum = reinterpret_cast<double*>(w + c.psum);
-    int64_t* d_pcnt = reinterpret_cast<int64_t*>(w + c.pcnt);
-    if ((e = launch_p1d(pa, d_psum, d_pcnt, st)) != hipSuccess) return e;
-    double* h = h_stats;
-    if ((e = hipMemcpyAsync(h, w + c.fsum, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(h + 1, w + c.fcnt, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(h + 2, d_psum, sizeof(double) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(h + 2 + nk, d_pcnt, sizeof(int64_t) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess)
+    double h[kMaxKBins + 1];
+    if ((e = hipMemcpyAsync(h, w + c.rows, sizeof(double) * (nk + 1), hipMemcpyDeviceToHost, st)) != hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    int64_t fc;
-    memcpy(&fc, h + 1, sizeof(fc));
-    *fbar = fc > 0 ? h[0] / static_cast<double>(fc) : NAN;
-    for (int i = 0; i < nk; ++i) {
-      int64_t pc;
-      memcpy(&pc, h + 2 + nk + i, sizeof(pc));
-      pk[i] = pc > 0 ? h[2 + i] / static_cast<double>(pc) : NAN;
-    }
+    *fbar = h[0];
+    for (int i = 0; i < nk; ++i) pk[i] = h[1 + i];
     return hipSuccess;
   }
 };
-
 
 // least squares y = p0 + p1 x + p2 x^2 through (x_i, y_i), normal equations in FP64
 void quad_fit(const double* x, const double* y, int n, double out[3]) {
@@ -153,12 +123,6 @@ void quad_fit(const double* x, const double* y, int n, double out[3]) {
   for (int r = 0; r < 3; ++r) out[r] = A[r][3] / A[r][r];
 }
 
-__global__ void __launch_bounds__(64) k_label_row(const double* fsum, const int64_t* fcnt, const double* psum,
-                                                  const int64_t* pcnt, int nk, float* row) {
-  const int t = threadIdx.x;
-  if (t == 0) row[0] = fcnt[0] > 0 ? static_cast<float>(fsum[0] / static_cast<double>(fcnt[0])) : NAN;
-  if (t < nk) row[1 + t] = pcnt[t] > 0 ? static_cast<float>(psum[t] / static_cast<double>(pcnt[t])) : NAN;
-}
 
 }  // namespace
 
@@ -166,7 +130,8 @@ size_t tune_workspace_bytes(int64_t n_sk, int nk) { return carve_tune(n_sk, nk).
 
 // Emulator training labels: for each host draw (a, b, c, z) the mean flux and
 // mean P1D per bin (velocity units at z) of the stored pixels, written to
-// y[i][0] and y[i][1 + b] on the device; no host synchronisation per draw.
+// y[i][0] and y[i][1 + b] on the device, kTuneEvalMaxG draws per pass over
+// the pixels; no host synchronisation per draw.
 int emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t n, float* y, void* work, size_t work_bytes,
                     hipStream_t st, char* err, size_t errlen) {
   const int nk = spec->p1d.n_kbins;
@@ -176,72 +141,19 @@ int emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t n, f
     return LYA_EWORKSPACE;
   }
   char* w = static_cast<char*>(work);
-  const double edges[2] = {-1e300, 1e300};
-  hipError_t e;
-  if ((e = hipMemcpyAsync(w + c.edges, edges, sizeof(edges), hipMemcpyHostToDevice, st)) != hipSuccess ||
-      (e = hipStreamSynchronize(st)) != hipSuccess ||
-      (e = launch_zchi_table(spec->cosmo.omega_m, reinterpret_cast<float*>(w + c.ztab), st)) != hipSuccess ||
-      (e = launch_twiddles(reinterpret_cast<float2*>(w + c.tw), kTw2048, st)) != hipSuccess) {
-    snprintf(err, errlen, "label set-up: %s", hipGetErrorString(e));
-    return LYA_EHIP;
-  }
-  const lya_skewers* sk = spec->sk;
-  for (int64_t i = 0; i < n; ++i) {
-    const double a = draws[4 * i], b = draws[4 * i + 1], cc = draws[4 * i + 2], z = draws[4 * i + 3];
-    SkewerArgs sa{};
-    sa.n_sk = sk->n_sk;
-    sa.npix = sk->npix;
-    sa.offset = sk->offset;
-    sa.chi0 = sk->chi0;
-    sa.dchi = sk->dchi;
-    sa.n = 32;
-    sa.in_dens = spec->dens;
-    sa.in_eta = spec->eta;
-    sa.do_flux = 1;
-    sa.cf[0][0] = static_cast<float>(a);
-    sa.cf[1][0] = static_cast<float>(b);
-    sa.cf[2][0] = static_cast<float>(cc);
-    sa.n_bins = 1;
-    sa.chi_edges = reinterpret_cast<const double*>(w + c.edges);
-    sa.bin_sum = reinterpret_cast<unsigned long long*>(w + c.bsum);
-    sa.bin_cnt = reinterpret_cast<unsigned long long*>(w + c.bcnt);
-    sa.out_fsum = reinterpret_cast<double*>(w + c.fsum);
-    sa.out_count = reinterpret_cast<int64_t*>(w + c.fcnt);
-    sa.ztab = reinterpret_cast<const float*>(w + c.ztab);
-    sa.tw2048 = reinterpret_cast<const float2*>(w + c.tw);
-    sa.queue = reinterpret_cast<unsigned int*>(w + c.queue);
-    sa.chunk = 8;
-    if ((e = launch_skewers(sa, st)) != hipSuccess) break;
-    P1dArgs pa{};
-    pa.n_sk = sk->n_sk;
-    pa.npix = sk->npix;
-    pa.offset = sk->offset;
-    pa.chi0 = sk->chi0;
-    pa.dchi = sk->dchi;
-    pa.dens = spec->dens;
-    pa.eta = spec->eta;
-    pa.fa = sa.cf[0][0];
-    pa.fb = sa.cf[1][0];
-    pa.fc = sa.cf[2][0];
-    pa.n_fbins = 1;
-    pa.chi_edges = sa.chi_edges;
-    pa.fsum = sa.out_fsum;
-    pa.fcount = sa.out_count;
-    pa.n_kbins = nk;
-    pa.k_edges = spec->p1d.k_edges;
-    const double x = 1.0 + z, om = spec->cosmo.omega_m;
-    pa.dv = spec->p1d.dpix * (100.0 * sqrt(om * (x * x * x) + (1.0 - om)) / x);
-    pa.part_sum = reinterpret_cast<double*>(w + c.part_sum);
-    pa.part_cnt = reinterpret_cast<int*>(w + c.part_cnt);
-    pa.tw2048 = sa.tw2048;
-    pa.queue = sa.queue;
-    pa.chunk = 4;
-    double* d_psum = reinterpret_cast<double*>(w + c.psum);
-    int64_t* d_pcnt = reinterpret_cast<int64_t*>(w + c.pcnt);
-    if ((e = launch_p1d(pa, d_psum, d_pcnt, st)) != hipSuccess) break;
-    hipLaunchKernelGGL(k_label_row, dim3(1), dim3(64), 0, st, sa.out_fsum, sa.out_count, d_psum, d_pcnt, nk,
-                       y + i * (1 + nk));
-    if ((e = hipGetLastError()) != hipSuccess) break;
+  hipError_t e = launch_twiddles(reinterpret_cast<float2*>(w + c.tw), kTw2048, st);
+  for (int64_t i0 = 0; i0 < n && e == hipSuccess; i0 += kTuneEvalMaxG) {
+    TuneEvalArgs ea = eval_args(spec, w, c);
+    ea.G = static_cast<int>(n - i0 < kTuneEvalMaxG ? n - i0 : kTuneEvalMaxG);
+    for (int g = 0; g < ea.G; ++g) {
+      const double* d = draws + 4 * (i0 + g);
+      ea.draw[g][0] = static_cast<float>(d[0]);
+      ea.draw[g][1] = static_cast<float>(d[1]);
+      ea.draw[g][2] = static_cast<float>(d[2]);
+      ea.dv[g] = velocity_pixel_at(spec, d[3]);
+    }
+    e = launch_tune_eval(ea, reinterpret_cast<double*>(w + c.sums), reinterpret_cast<int64_t*>(w + c.counts),
+                         nullptr, y + i0 * (1 + nk), st);
   }
   if (e != hipSuccess) {
     snprintf(err, errlen, "label evaluation: %s", hipGetErrorString(e));
@@ -260,13 +172,9 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
     return LYA_EWORKSPACE;
   }
   char* w = static_cast<char*>(work);
-  double h_stats[2 + 2 * kMaxKBins];
-  Evaluator ev{spec, w, c, st, nk, h_stats};
+  Evaluator ev{spec, w, c, st, nk};
   hipError_t e;
-  const double edges[2] = {-1e300, 1e300};
-  if ((e = hipMemcpyAsync(w + c.edges, edges, sizeof(edges), hipMemcpyHostToDevice, st)) != hipSuccess ||
-      (e = launch_zchi_table(spec->cosmo.omega_m, reinterpret_cast<float*>(w + c.ztab), st)) != hipSuccess ||
-      (e = launch_twiddles(reinterpret_cast<float2*>(w + c.tw), kTw2048, st)) != hipSuccess ||
+  if ((e = launch_twiddles(reinterpret_cast<float2*>(w + c.tw), kTw2048, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     snprintf(err, errlen, "tuning set-up: %s", hipGetErrorString(e));
     return LYA_EHIP;
@@ -300,23 +208,23 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
     double fbest = 0.0, fb = 0.0;
     int nev = 0, gpu_ev = 0;
     if (mode == LYA_TUNE_EMULATOR) {
-      // Search on the model emulator + offset + slope correction, check the
-      // optimum on the GPU, then (i) move the model onto the measured
-      // statistics there (offset = GPU - emulator) and (ii) correct its slope
-      // along the last step by a Broyden update, so that the model also
-      // reproduces the previous check; search again from the new point.  Stops
-      // when a check moves the point by at most max(10 xatol, 1e-4) or after
-      // emu_checks GPU evaluations.
+      // Search on the model emulator + offset + slope correction (device
+      // Levenberg-Marquardt), check the optimum on the GPU, then (i) move the
+      // model onto the measured statistics there (offset = GPU - emulator) and
+      // (ii) correct its slope along the last step by a Broyden update, so that
+      // the model also reproduces the previous check; search again from the
+      // new point.  Stops when a check moves the point by at most
+      // max(10 xatol, 5e-4) or after emu_checks GPU evaluations.
       const int checks = spec->emu_checks > 0 ? spec->emu_checks : 1;
       const int ns = 1 + nk;
-      const double xtol = fmax(10.0 * spec->xatol, 1e-4);
+      const double xtol = fmax(10.0 * spec->xatol, 5e-4);
       double off[kMaxKBins + 1] = {0.0}, jac[2 * (kMaxKBins + 1)] = {0.0}, dprev[kMaxKBins + 1];
       double xk[2] = {x[0], x[1]};
       double step = 0.3;
       for (int it = 0; it < checks; ++it) {
         int n1 = 0;
-        // the search stops on position alone, ten times finer than the check tolerance
-        EmuSearchSpec ss{fbt, cc, z, step, 0.1 * xtol, HUGE_VAL, spec->sigma_rel, nk, spec->max_evals, pkt,
+        // the search stops on position alone, a hundred times finer than the check tolerance
+        EmuSearchSpec ss{fbt, cc, z, step, 0.01 * xtol, HUGE_VAL, spec->sigma_rel, nk, 3 * spec->max_evals, pkt,
                          off, jac, {xk[0], xk[1]}};
         double pe[kMaxKBins + 1];
         if ((last = emulator_search(spec->emulator, ss, x, &fbest, &n1, pe, reinterpret_cast<char*>(w + c.emu),

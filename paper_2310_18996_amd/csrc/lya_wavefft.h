@@ -41,11 +41,17 @@ __device__ __forceinline__ void bin_bounds(const double* __restrict__ edges, int
   }
 }
 
+// The block's copy of the twiddle table tw2048 in LDS (read by every stage of
+// every wavefront FFT; global reads would put an L2 round trip in each stage).
+__device__ __forceinline__ void load_twiddles(float2* stw, const float2* __restrict__ tw2048, int tid, int nt) {
+  for (int i = tid; i < kTw2048; i += nt) stw[i] = tw2048[i];
+}
+
 // Unnormalised inverse DFT (exp(+2 pi i k n / M)) of buf[pidx(0..M-1)], M a
 // power of two <= kHalfMax, by an in-place Stockham radix-4/2 FFT: every stage
 // first reads all of the lane's inputs, then writes (the wave runs in lockstep).
 // tw2048[k] = exp(2 pi i k / 2048).
-__device__ __forceinline__ void wave_ifft(float2* buf, int M, const float2* __restrict__ tw2048, int lane) {
+__device__ __forceinline__ void wave_ifft(float2* buf, int M, const float2* tw2048, int lane) {
   for (int s = 1; s < M;) {
     const int R = (M / s >= 4) ? 4 : 2;
     const int nb = M / R;
