@@ -332,7 +332,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="big", choices=["tiny", "mid", "big", "precision", "emulator"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=192)
+    ap.add_argument("--cpu-n", type=int, default=384)
     ap.add_argument("--no-tune", action="store_true", help="skip the tuning leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured replay")

@@ -220,16 +220,19 @@ __device__ __forceinline__ unsigned short to_bf16(float f) {
 }
 
 // 64x64 output tile per block of 4 waves (2x2, 32x32 each = 2x2 MFMA 16x16
-// tiles); K in steps of 16 through LDS in bfloat16.  MFMA 16x16x16 operand
+// tiles); K in tiles of 64 staged through LDS in bfloat16, the next tile's
+// global loads issued before the current tile's MFMAs.  MFMA 16x16x16 operand
 // layout: lane l supplies A rows (l % 16), k = 4 (l / 16) .. +3, and B columns
 // (l % 16), k = 4 (l / 16) .. +3; result element r of lane l is row
 // 4 (l / 16) + r, column l % 16.
+constexpr int kGemmBK = 64;
+
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const float* __restrict__ A, int lda,
                                                    const float* __restrict__ B, int ldb, float* C, int ldc,
                                                    const float* bias, int epi, float* aux, int ldaux) {
-  __shared__ unsigned short As[64][16 + 4];
-  __shared__ unsigned short Bs[16][64 + 4];
+  __shared__ unsigned short As[64][kGemmBK + 8];
+  __shared__ unsigned short Bs[kGemmBK][64 + 8];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
@@ -238,39 +241,63 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(int M, int N, int K, const fl
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f32{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  // element e of this thread in a 64 x 64 tile: consecutive threads read
+  // consecutive addresses of the operand's own layout
+  auto a_coord = [&](int e, int& mm, int& kk) {
+    const int idx = tid + 256 * e;
+    mm = TA ? idx % 64 : idx / 64;
+    kk = TA ? idx / 64 : idx % 64;
+  };
+  auto b_coord = [&](int e, int& kk, int& nn) {
+    const int idx = tid + 256 * e;
+    kk = TB ? idx % 64 : idx / 64;
+    nn = TB ? idx / 64 : idx % 64;
+  };
+  float ra[16], rb[16];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid + 256 * e;  // 0..1023; consecutive threads read consecutive addresses
-      {
-        const int mm = TA ? idx % 64 : idx / 16, kk = TA ? idx / 64 : idx % 16;
-        const int m = m0 + mm, k = k0 + kk;
-        float v = 0.0f;
-        if (m < M && k < K) v = TA ? A[static_cast<size_t>(k) * lda + m] : A[static_cast<size_t>(m) * lda + k];
-        As[mm][kk] = to_bf16(v);
-      }
-      {
-        const int kk = TB ? idx % 16 : idx / 64, nn = TB ? idx / 16 : idx % 64;
-        const int k = k0 + kk, n = n0 + nn;
-        float v = 0.0f;
-        if (n < N && k < K) v = TB ? B[static_cast<size_t>(n) * ldb + k] : B[static_cast<size_t>(k) * ldb + n];
-        Bs[kk][nn] = to_bf16(v);
-      }
+    for (int e = 0; e < 16; ++e) {
+      int mm, kk;
+      a_coord(e, mm, kk);
+      const int m = m0 + mm, k = k0 + kk;
+      ra[e] = (m < M && k < K) ? (TA ? A[static_cast<size_t>(k) * lda + m] : A[static_cast<size_t>(m) * lda + k])
+                               : 0.0f;
+      int kb, nn;
+      b_coord(e, kb, nn);
+      const int kg = k0 + kb, n = n0 + nn;
+      rb[e] = (n < N && kg < K) ? (TB ? B[static_cast<size_t>(n) * ldb + kg] : B[static_cast<size_t>(kg) * ldb + n])
+                                : 0.0f;
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += kGemmBK) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      int mm, kk, kb, nn;
+      a_coord(e, mm, kk);
+      b_coord(e, kb, nn);
+      As[mm][kk] = to_bf16(ra[e]);
+      Bs[kb][nn] = to_bf16(rb[e]);
     }
     __syncthreads();
+    if (k0 + kGemmBK < K) gload(k0 + kGemmBK);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      v4i16 af;
-      const int r = wm + 16 * i + (lane & 15), kb = 4 * (lane >> 4);
+    for (int ks = 0; ks < kGemmBK; ks += 16) {
+      const int kb = ks + 4 * (lane >> 4);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) af[q] = static_cast<short>(As[r][kb + q]);
+      for (int i = 0; i < 2; ++i) {
+        v4i16 af;
+        const int r = wm + 16 * i + (lane & 15);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        v4i16 bfr;
-        const int cidx = wn + 16 * j + (lane & 15);
+        for (int q = 0; q < 4; ++q) af[q] = static_cast<short>(As[r][kb + q]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bfr[q] = static_cast<short>(Bs[kb + q][cidx]);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bfr, acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {
+          v4i16 bfr;
+          const int cidx = wn + 16 * j + (lane & 15);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bfr[q] = static_cast<short>(Bs[kb + q][cidx]);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bfr, acc[i][j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -310,20 +337,26 @@ hipError_t gemm(bool bf16, int M, int N, int K, const float* A, int lda, const f
 }
 
 // ---------------------------------------------------------------- loss, bias grads, Adam
-// dY = 2 (Y - T) mask / (B n_eff); loss partial sums (FP64, one block)
+// dY = 2 (Y - T) mask / (B n_eff), one element per thread; per-block FP64
+// partial sums of the squared misfit, then k_emu_loss sums the partials in a
+// fixed order (loss = sum / (B n_eff))
+__device__ __forceinline__ float emu_neff(const EmuHeader* __restrict__ h) {
+  float neff = 0.0f;
+  for (int o = 0; o < h->n_out; ++o) neff += h->out_mask[o];
+  return neff > 0.0f ? neff : 1.0f;
+}
+
 __global__ void __launch_bounds__(256) k_emu_dloss(const float* __restrict__ y, const float* __restrict__ t, int B,
-                                                   const EmuHeader* __restrict__ h, float* dy, float* loss) {
+                                                   const EmuHeader* __restrict__ h, float* dy, double* lpart) {
   __shared__ double sl[256];
   const int n_out = h->n_out;
-  float neff = 0.0f;
-  for (int o = 0; o < n_out; ++o) neff += h->out_mask[o];
-  const float scale = 2.0f / (static_cast<float>(B) * (neff > 0.0f ? neff : 1.0f));
+  const float scale = 2.0f / (static_cast<float>(B) * emu_neff(h));
+  const int k = blockIdx.x * 256 + threadIdx.x;
   double l = 0.0;
-  for (int k = threadIdx.x; k < B * n_out; k += 256) {
-    const int o = k % n_out;
-    const float d = (y[k] - t[k]) * h->out_mask[o];
+  if (k < B * n_out) {
+    const float d = (y[k] - t[k]) * h->out_mask[k % n_out];
     dy[k] = scale * d;
-    l += static_cast<double>(d) * d;
+    l = static_cast<double>(d) * d;
   }
   sl[threadIdx.x] = l;
   __syncthreads();
@@ -331,7 +364,21 @@ __global__ void __launch_bounds__(256) k_emu_dloss(const float* __restrict__ y, 
     if (threadIdx.x < w) sl[threadIdx.x] += sl[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && loss) loss[0] = static_cast<float>(sl[0] / (static_cast<double>(B) * (neff > 0 ? neff : 1)));
+  if (threadIdx.x == 0) lpart[blockIdx.x] = sl[0];
+}
+
+__global__ void __launch_bounds__(256) k_emu_loss(const double* __restrict__ lpart, int nparts, int B,
+                                                  const EmuHeader* __restrict__ h, float* loss) {
+  __shared__ double sl[256];
+  double l = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) l += lpart[i];
+  sl[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sl[threadIdx.x] += sl[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) loss[0] = static_cast<float>(sl[0] / (static_cast<double>(B) * emu_neff(h)));
 }
 
 // db[n] = sum over rows of d[m][n]: 64 columns per block, sixteen row groups
@@ -414,6 +461,7 @@ __global__ void __launch_bounds__(256) k_emu_predict(const EmuHeader* __restrict
 // ---------------------------------------------------------------- host side
 struct TrainBufs {
   float *x0, *tgt, *z[3], *hh[3], *y, *dy, *dz[3], *grad, *loss;
+  double* lpart;  // per-block loss partials
   size_t total;
 };
 
@@ -438,6 +486,7 @@ static TrainBufs carve_train(char* w, int B, int n_out) {
   t.dy = take(static_cast<size_t>(B) * n_out);
   t.grad = take(n_params(n_out));
   t.loss = take(1);
+  t.lpart = reinterpret_cast<double*>(take(2 * ((static_cast<size_t>(B) * n_out + 255) / 256)));
   t.total = o;
   return t;
 }
@@ -456,7 +505,11 @@ static hipError_t emu_fwd_bwd(const EmuHeader* h_dev, const float* params, int n
                                 params + o.b[l], EPI_BIAS_GELU, t.z[l], kHid, st)) != hipSuccess) return e;
   if ((e = gemm<false, false>(bf16, B, n_out, kHid, t.hh[2], kHid, params + o.W[3], n_out, t.y, n_out,
                               params + o.b[3], EPI_BIAS, nullptr, 0, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emu_dloss, dim3(1), dim3(256), 0, st, t.y, t.tgt, B, h_dev, t.dy, t.loss);
+  {
+    const int nparts = (B * n_out + 255) / 256;
+    hipLaunchKernelGGL(k_emu_dloss, dim3(nparts), dim3(256), 0, st, t.y, t.tgt, B, h_dev, t.dy, t.lpart);
+    hipLaunchKernelGGL(k_emu_loss, dim3(1), dim3(256), 0, st, t.lpart, nparts, B, h_dev, t.loss);
+  }
   // backward: output layer
   if ((e = gemm<true, false>(bf16, kHid, n_out, B, t.hh[2], kHid, t.dy, n_out, t.grad + o.W[3], n_out, nullptr,
                              EPI_STORE, nullptr, 0, st)) != hipSuccess) return e;
