@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/box2048_skewers1M_hbm_traffic.md.  Valid only for the kernels as
 # they were when the counters were taken (a changed kernel must drop its
 # entry) and reported only for that workload.
-TRAFFIC = {"fft_x": 137534552117, "fft_y": 140341231014, "fft_z_gen": 96074136017}
+TRAFFIC = {"fft_x": 137534552117, "fft_y": 140341231014}
 TRAFFIC_CONFIG = "big"
 
 
@@ -104,6 +104,25 @@ def cpu_baseline(cfg, pixels_per_cell, budget_n=256):
                 sample="%d^3 box (%d cells) + %d skewers (%d pixels, the workload's pixels per cell) on the host; "
                        "box %.2f s, skewers+FGPA %.2f s; numpy/scipy single-threaded" % (
                            budget_n, cells, ns, pix, t1 - t0, t2 - t1))
+
+
+def host_facts():
+    """CPU count, model and RAM of the host running the benchmark."""
+    model, ram = None, None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return dict(cpu_count=os.cpu_count(), cpu_model=model, ram_gib=ram)
 
 
 # ---------------------------------------------------------------- precision leg
@@ -473,7 +492,10 @@ def main():
                box_cells_per_s=cells / (box_ms * 1e-3), box_ms=box_ms,
                skewer_pixels_per_s=pixels / (sk_ms * 1e-3), skewer_ms=sk_ms,
                distinct_voxels_per_pixel=vox_per_pix, roofline=roof, kernels=kernels, autotune=autotune,
-               graph=graph)
+               graph=graph, host=host_facts(),
+               paper_context="the paper's make_box runs about 8.0e5 box cells/s per 64-thread CPU node "
+                             "(13 fields of a 2560x2560x1536 chunk, FFTW); other hardware and workload, "
+                             "so vs_baseline is null")
     if args.config == "precision":
         print("bench: BF16 storage leg", file=sys.stderr, flush=True)
         out["precision"] = precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, edges, stream)

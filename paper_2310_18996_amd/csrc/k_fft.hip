@@ -285,9 +285,17 @@ struct Pass {
 enum { GEN_GENERIC = 0, GEN_DELTA_ETAZ = 1, GEN_DELTA = 2 };
 
 template <int N, int T, int NT, int GM, typename LIDX>
-__device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, float2* lds, LIDX lidx) {
-  constexpr int H = T / 2;
+__device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, float2* lds, LIDX lidx, float* stab) {
+  constexpr int H = T / 2, NZ = N / 2 + 1;
   const int nx = ix;  // 0 < ix < N/2
+  // the amplitudes a pencil needs depend on |nz| only: gather them once, all
+  // at once, into LDS (the table is far larger than L2)
+  for (int w = threadIdx.x; w < H * NZ; w += NT) {
+    const int po = w / NZ, az = w % NZ;
+    const int ny = sfreq(iy0 + po, N);
+    stab[w] = g.table[nx * nx + ny * ny + az * az];
+  }
+  __syncthreads();
   for (int w = threadIdx.x; w < H * (N / 2); w += NT) {
     const int po = w / (N / 2), m = w % (N / 2);
     const int iy = iy0 + po;
@@ -300,7 +308,7 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
       const int iz = 2 * m + e;
       const int nz = sfreq(iz, N);
       const int n2 = nx * nx + ny * ny + nz * nz;
-      float s = g.table[n2];
+      float s = stab[po * NZ + (nz < 0 ? -nz : nz)];
       const float2 z = e ? box_muller(wd.z, wd.w) : box_muller(wd.x, wd.y);
       float2 wv = make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
       float ma, mb;
@@ -353,7 +361,8 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
 
   // stage 0: registers from global memory or from the synthesiser
   if (KIND == KIND_GENZ && paired) {
-    gen_paired<N, T, NT, GM>(g, outer, t0, lds, [](int i, int p) { return P::lidx(i, p); });
+    __shared__ float stab[KIND == KIND_GENZ ? (T / 2) * (N / 2 + 1) : 1];
+    gen_paired<N, T, NT, GM>(g, outer, t0, lds, [](int i, int p) { return P::lidx(i, p); }, stab);
     __syncthreads();
     P::template load_lds<0>(v, lds, tid);
     __syncthreads();
