@@ -424,12 +424,13 @@ def main():
                                        stream=stream)
         torch.cuda.synchronize()
         autotune = dict(fft_y=tf.fft_y, fft_x=tf.fft_x, sk_chunk=ts.sk_chunk, sk_blocks_per_cu=ts.sk_blocks_per_cu,
-                        fft_ms={"y": ms_fft[0], "x": ms_fft[1]},
+                        sk_unroll=ts.sk_unroll, fft_ms={"y": ms_fft[0], "x": ms_fft[1]},
                         skewer_ms={"chunks": list(L.SK_CHUNKS), "blocks_per_cu": list(L.SK_BLOCKS_PER_CU),
-                                   "ms": ms_sk},
+                                   "unroll": list(L.SK_UNROLL), "ms": ms_sk},
                         seconds=time.perf_counter() - t0)
-        print("bench: autotuned fft y=%d x=%d, skewer chunk %d blocks/CU %d (%.1f s)" % (
-            tf.fft_y, tf.fft_x, ts.sk_chunk, ts.sk_blocks_per_cu, autotune["seconds"]), file=sys.stderr, flush=True)
+        print("bench: autotuned fft y=%d x=%d, skewer chunk %d blocks/CU %d unroll %d (%.1f s)" % (
+            tf.fft_y, tf.fft_x, ts.sk_chunk, ts.sk_blocks_per_cu, ts.sk_unroll, autotune["seconds"]), file=sys.stderr,
+            flush=True)
 
     for _ in range(args.warmup):
         step()

@@ -318,11 +318,13 @@ const char* lya_emulator_last_error(void);
  *                     Boxes below 1024 have variants 0 and 1 only.  Defaults:
  *                     y 0, x 1.
  *   sk_chunk          skewers taken per pull from the skewer work queue (default 8);
- *   sk_blocks_per_cu  persistent skewer blocks per CU, 1..4 (default 4).
+ *   sk_blocks_per_cu  persistent skewer blocks per CU, 1..4 (default 4);
+ *   sk_unroll         pixels per lane whose gathers are issued together, 1, 2 or 4
+ *                     (default 2).
  * The table is process-wide and applies to every later call for that n. */
 #define LYA_FFT_VARIANTS 10
 typedef struct {
-  int32_t fft_y, fft_x, sk_chunk, sk_blocks_per_cu;
+  int32_t fft_y, fft_x, sk_chunk, sk_blocks_per_cu, sk_unroll;
 } lya_tuning;
 
 int lya_get_tuning(int32_t n, lya_tuning* t);
@@ -338,9 +340,10 @@ int lya_autotune_fft(const lya_box* box, void* field, void* work, size_t work_by
                      lya_tuning* out, void* stream);
 
 /* Times lya_draw_skewers (same arguments; outputs overwritten) for skewer
- * chunks {1, 2, 4, 8, 16, 32, 64} x blocks per CU {1, 2, 3, 4}, `reps` runs
- * each; stores the fastest in the table for box->n.  ms (may be NULL)
- * receives 7 x 4 mean milliseconds, [chunk][blocks].  Synchronous. */
+ * chunks {1, 2, 4, 8, 16, 32, 64} x blocks per CU {1, 2, 3, 4} x unroll
+ * {1, 2, 4}, `reps` runs each; stores the fastest in the table for box->n.
+ * ms (may be NULL) receives 7 x 4 x 3 mean milliseconds, [chunk][blocks][unroll].
+ * Synchronous. */
 int lya_autotune_skewers(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
                          uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
                          float* flux, const lya_zbins* zb, void* work, size_t work_bytes, int32_t reps, double* ms,

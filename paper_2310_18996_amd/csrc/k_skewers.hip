@@ -113,6 +113,7 @@ __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c00
   return c0 + tx * (c1 - c0);
 }
 
+template <int U>
 __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
   __shared__ float2 sbuf[kSkWaves][kHalfBuf];
   __shared__ int sjb[kSkWaves][kMaxZBins + 1];
@@ -161,68 +162,101 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
         sz = a.step_fx[3 * q + 2];
       }
       // pixel j is in bin b when jb[b+1] <= j < jb[b]; each lane walks j upward
-      // and therefore the bins downward, accumulating one bin at a time
+      // and therefore the bins downward, accumulating one bin at a time.  U
+      // pixels per lane per step: all their gathers are issued before any is used.
       int bin = a.n_bins - 1;
       int cur = -1;
       unsigned long long acc = 0ull, cnt = 0ull;
-      for (int j = lane; j < np; j += 64) {
-        float d, e;
+      for (int j0 = lane; j0 < np; j0 += 64 * U) {
+        float dd[U], ee[U];
         if (gather) {
-          const int64_t px = ox + j * sx, py = oy + j * sy, pz = oz + j * sz;
-          const int ix = static_cast<int>((px >> 32) & (N - 1));
-          const int iy = static_cast<int>((py >> 32) & (N - 1));
-          const int iz = static_cast<int>((pz >> 32) & (N - 1));
-          const int jx = (ix + 1) & (N - 1), jy = (iy + 1) & (N - 1), jz = (iz + 1) & (N - 1);
-          const float tx = static_cast<float>(static_cast<uint32_t>(px)) * 2.3283064365386963e-10f;
-          const float ty = static_cast<float>(static_cast<uint32_t>(py)) * 2.3283064365386963e-10f;
-          const float tz = static_cast<float>(static_cast<uint32_t>(pz)) * 2.3283064365386963e-10f;
-          const size_t r00 = ix * NN + static_cast<size_t>(iy) * N;
-          const size_t r01 = ix * NN + static_cast<size_t>(jy) * N;
-          const size_t r10 = jx * NN + static_cast<size_t>(iy) * N;
-          const size_t r11 = jx * NN + static_cast<size_t>(jy) * N;
-          const float2 c000 = ld_field(a, r00 + iz), c001 = ld_field(a, r00 + jz);
-          const float2 c010 = ld_field(a, r01 + iz), c011 = ld_field(a, r01 + jz);
-          const float2 c100 = ld_field(a, r10 + iz), c101 = ld_field(a, r10 + jz);
-          const float2 c110 = ld_field(a, r11 + iz), c111 = ld_field(a, r11 + jz);
-          d = trilerp(tx, ty, tz, c000.x, c001.x, c010.x, c011.x, c100.x, c101.x, c110.x, c111.x);
-          e = trilerp(tx, ty, tz, c000.y, c001.y, c010.y, c011.y, c100.y, c101.y, c110.y, c111.y);
-          if (with_ds) {
-            const float2 z2 = buf[pidx(j >> 1)];
-            d += (j & 1) ? z2.y : z2.x;
+          float2 c[U][8];
+          float t3[U][3];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = j0 + 64 * u;
+            const int jj = j < np ? j : j0;  // an in-range pixel (its result is dropped)
+            const int64_t px = ox + jj * sx, py = oy + jj * sy, pz = oz + jj * sz;
+            const int ix = static_cast<int>((px >> 32) & (N - 1));
+            const int iy = static_cast<int>((py >> 32) & (N - 1));
+            const int iz = static_cast<int>((pz >> 32) & (N - 1));
+            const int jx = (ix + 1) & (N - 1), jy = (iy + 1) & (N - 1), jz = (iz + 1) & (N - 1);
+            t3[u][0] = static_cast<float>(static_cast<uint32_t>(px)) * 2.3283064365386963e-10f;
+            t3[u][1] = static_cast<float>(static_cast<uint32_t>(py)) * 2.3283064365386963e-10f;
+            t3[u][2] = static_cast<float>(static_cast<uint32_t>(pz)) * 2.3283064365386963e-10f;
+            const size_t r00 = ix * NN + static_cast<size_t>(iy) * N;
+            const size_t r01 = ix * NN + static_cast<size_t>(jy) * N;
+            const size_t r10 = jx * NN + static_cast<size_t>(iy) * N;
+            const size_t r11 = jx * NN + static_cast<size_t>(jy) * N;
+            c[u][0] = ld_field(a, r00 + iz);
+            c[u][1] = ld_field(a, r00 + jz);
+            c[u][2] = ld_field(a, r01 + iz);
+            c[u][3] = ld_field(a, r01 + jz);
+            c[u][4] = ld_field(a, r10 + iz);
+            c[u][5] = ld_field(a, r10 + jz);
+            c[u][6] = ld_field(a, r11 + iz);
+            c[u][7] = ld_field(a, r11 + jz);
           }
-          if (a.dens) a.dens[off + j] = d;
-          if (a.eta) a.eta[off + j] = e;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = j0 + 64 * u;
+            const float tx = t3[u][0], ty = t3[u][1], tz = t3[u][2];
+            float d = trilerp(tx, ty, tz, c[u][0].x, c[u][1].x, c[u][2].x, c[u][3].x, c[u][4].x, c[u][5].x,
+                              c[u][6].x, c[u][7].x);
+            const float e = trilerp(tx, ty, tz, c[u][0].y, c[u][1].y, c[u][2].y, c[u][3].y, c[u][4].y, c[u][5].y,
+                                    c[u][6].y, c[u][7].y);
+            if (j < np) {
+              if (with_ds) {
+                const float2 z2 = buf[pidx(j >> 1)];
+                d += (j & 1) ? z2.y : z2.x;
+              }
+              if (a.dens) a.dens[off + j] = d;
+              if (a.eta) a.eta[off + j] = e;
+            }
+            dd[u] = d;
+            ee[u] = e;
+          }
         } else {
-          d = a.in_dens[off + j];
-          e = a.in_eta[off + j];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = j0 + 64 * u;
+            dd[u] = j < np ? a.in_dens[off + j] : 0.0f;
+            ee[u] = j < np ? a.in_eta[off + j] : 0.0f;
+          }
         }
         if (a.do_flux) {
-          const double u = pixel_chi(chi0, j, a.dchi) * (1.0 / kZTabH);
-          int iu = static_cast<int>(u);
-          iu = iu < 0 ? 0 : (iu > kZTabN - 2 ? kZTabN - 2 : iu);
-          const float t = static_cast<float>(u - iu);
-          const float zt0 = a.ztab[iu], zt1 = a.ztab[iu + 1];
-          const float x = (zt0 + t * (zt1 - zt0)) + (1.0f - kFgpaX0);   // (1+z) - x0
-          const float ca = a.cf[0][0] + x * (a.cf[0][1] + x * a.cf[0][2]);
-          const float cb = a.cf[1][0] + x * (a.cf[1][1] + x * a.cf[1][2]);
-          const float cc = a.cf[2][0] + x * (a.cf[2][1] + x * a.cf[2][2]);
-          const float F = __expf(-ca * __expf(cb * (d + cc * e)));
-          if (a.flux) a.flux[off + j] = F;
-          if (want_bins) {
-            while (bin >= 0 && j >= jb[bin]) --bin;  // pixel j lies below bin's upper edge
-            const int key = (bin >= 0 && j >= jb[bin + 1]) ? bin : -1;
-            if (key != cur) {
-              if (cnt) {
-                atomicAdd(&s_sum[cur], acc);
-                atomicAdd(&s_cnt[cur], cnt);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = j0 + 64 * u;
+            if (j >= np) break;
+            const float d = dd[u], e = ee[u];
+            const double uu = pixel_chi(chi0, j, a.dchi) * (1.0 / kZTabH);
+            int iu = static_cast<int>(uu);
+            iu = iu < 0 ? 0 : (iu > kZTabN - 2 ? kZTabN - 2 : iu);
+            const float t = static_cast<float>(uu - iu);
+            const float zt0 = a.ztab[iu], zt1 = a.ztab[iu + 1];
+            const float x = (zt0 + t * (zt1 - zt0)) + (1.0f - kFgpaX0);   // (1+z) - x0
+            const float ca = a.cf[0][0] + x * (a.cf[0][1] + x * a.cf[0][2]);
+            const float cb = a.cf[1][0] + x * (a.cf[1][1] + x * a.cf[1][2]);
+            const float cc = a.cf[2][0] + x * (a.cf[2][1] + x * a.cf[2][2]);
+            const float F = __expf(-ca * __expf(cb * (d + cc * e)));
+            if (a.flux) a.flux[off + j] = F;
+            if (want_bins) {
+              while (bin >= 0 && j >= jb[bin]) --bin;  // pixel j lies below bin's upper edge
+              const int key = (bin >= 0 && j >= jb[bin + 1]) ? bin : -1;
+              if (key != cur) {
+                if (cnt) {
+                  atomicAdd(&s_sum[cur], acc);
+                  atomicAdd(&s_cnt[cur], cnt);
+                }
+                acc = 0ull;
+                cnt = 0ull;
+                cur = key;
               }
-              acc = 0ull;
-              cnt = 0ull;
-              cur = key;
-            }
-            if (key >= 0) {
-              acc += __float2ull_rn(F * 4294967296.0f);
-              cnt += 1ull;
+              if (key >= 0) {
+                acc += __float2ull_rn(F * 4294967296.0f);
+                cnt += 1ull;
+              }
             }
           }
         }
@@ -264,8 +298,16 @@ hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st) {
   int64_t blocks = static_cast<int64_t>(device_cus()) * (a.blocks_per_cu > 0 ? a.blocks_per_cu : 4);
   if (blocks * kSkWaves > nchunks) blocks = (nchunks + kSkWaves - 1) / kSkWaves;
   if (blocks < 1) blocks = 1;
-  LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-            hipLaunchKernelGGL(k_skewers, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));
+  const int u = a.unroll == 1 || a.unroll == 4 ? a.unroll : 2;
+  if (u == 1)
+    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
+              hipLaunchKernelGGL(k_skewers<1>, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));
+  else if (u == 2)
+    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
+              hipLaunchKernelGGL(k_skewers<2>, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));
+  else
+    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
+              hipLaunchKernelGGL(k_skewers<4>, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));
   if (a.n_bins > 0 && a.do_flux)
     LYA_TIMED("skewer_finalize", st,
               hipLaunchKernelGGL(k_skewer_finalize, dim3(1), dim3(256), 0, st, a.n_bins, a.bin_sum, a.bin_cnt,

@@ -149,6 +149,7 @@ int run_skewers(lya::SkewerArgs& a, const lya_cosmo* cosmo, const lya_zbins* zb,
   // launch shape from the autotuned table of the box size (defaults for stored pixels)
   a.chunk = (a.field || a.field_bf16) ? lya::sk_chunk(a.n) : 8;
   a.blocks_per_cu = (a.field || a.field_bf16) ? lya::sk_blocks_per_cu(a.n) : 4;
+  a.unroll = (a.field || a.field_bf16) ? lya::sk_unroll(a.n) : 2;
   if (a.n_sk == 0) {
     if (a.n_bins > 0 && a.do_flux) {
       // still produce zero sums

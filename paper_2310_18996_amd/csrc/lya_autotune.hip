@@ -19,6 +19,7 @@ namespace {
 std::mutex g_mu;
 int g_chunk[12] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8};
 int g_bpc[12] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4};
+int g_unroll[12] = {2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
 int lg(int n) {
   int l = 0;
   while ((1 << l) < n && l < 11) ++l;
@@ -34,10 +35,15 @@ int sk_blocks_per_cu(int n) {
   std::lock_guard<std::mutex> lk(g_mu);
   return g_bpc[lg(n)];
 }
-void set_sk_shape(int n, int chunk, int bpc) {
+int sk_unroll(int n) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_unroll[lg(n)];
+}
+void set_sk_shape(int n, int chunk, int bpc, int unroll) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_chunk[lg(n)] = chunk;
   g_bpc[lg(n)] = bpc;
+  g_unroll[lg(n)] = unroll;
 }
 
 }  // namespace lya
@@ -59,8 +65,10 @@ bool box_ok(const lya_box* b) {
 
 constexpr int kChunks[] = {1, 2, 4, 8, 16, 32, 64};
 constexpr int kBpc[] = {1, 2, 3, 4};
+constexpr int kUnroll[] = {1, 2, 4};
 constexpr int kNChunks = sizeof(kChunks) / sizeof(kChunks[0]);
 constexpr int kNBpc = sizeof(kBpc) / sizeof(kBpc[0]);
+constexpr int kNUnroll = sizeof(kUnroll) / sizeof(kUnroll[0]);
 
 // mean milliseconds of `reps` runs of fn() on st, after one untimed run
 template <typename F>
@@ -102,20 +110,22 @@ int lya_get_tuning(int32_t n, lya_tuning* t) {
   t->fft_x = lya::fft_variant(n, 1);
   t->sk_chunk = lya::sk_chunk(n);
   t->sk_blocks_per_cu = lya::sk_blocks_per_cu(n);
+  t->sk_unroll = lya::sk_unroll(n);
   return LYA_OK;
 }
 
 int lya_set_tuning(int32_t n, const lya_tuning* t) {
   if (!t || n < 32 || n > 2048 || (n & (n - 1))) return afail(LYA_EINVAL, "invalid box size or NULL tuning");
-  if (t->sk_chunk < 1 || t->sk_chunk > 1024 || t->sk_blocks_per_cu < 1 || t->sk_blocks_per_cu > 4)
-    return afail(LYA_EINVAL, "skewer chunk must be in [1, 1024] and blocks per CU in [1, 4]");
+  if (t->sk_chunk < 1 || t->sk_chunk > 1024 || t->sk_blocks_per_cu < 1 || t->sk_blocks_per_cu > 4 ||
+      (t->sk_unroll != 1 && t->sk_unroll != 2 && t->sk_unroll != 4))
+    return afail(LYA_EINVAL, "skewer chunk must be in [1, 1024], blocks per CU in [1, 4], unroll 1, 2 or 4");
   const int oy = lya::fft_variant(n, 0), ox = lya::fft_variant(n, 1);
   if (lya::set_fft_variant(n, 0, t->fft_y) || lya::set_fft_variant(n, 1, t->fft_x)) {
     lya::set_fft_variant(n, 0, oy);
     lya::set_fft_variant(n, 1, ox);
     return afail(LYA_EINVAL, "FFT variant out of range (boxes below 1024 have only the default variants 0 and 1)");
   }
-  lya::set_sk_shape(n, t->sk_chunk, t->sk_blocks_per_cu);
+  lya::set_sk_shape(n, t->sk_chunk, t->sk_blocks_per_cu, t->sk_unroll);
   return LYA_OK;
 }
 
@@ -161,39 +171,42 @@ int lya_autotune_skewers(const lya_box* box, const void* field, const lya_skewer
   if (!box_ok(box)) return afail(LYA_EINVAL, "box must be FP32 with n a power of two in [32, 2048]");
   if (reps < 1) return afail(LYA_EINVAL, "reps must be >= 1");
   const int n = box->n;
-  const int c0 = lya::sk_chunk(n), b0 = lya::sk_blocks_per_cu(n);
+  const int c0 = lya::sk_chunk(n), b0 = lya::sk_blocks_per_cu(n), u0 = lya::sk_unroll(n);
   double bt = 1e300;
-  int bc = c0, bb = b0;
+  int bc = c0, bb = b0, bu = u0;
   for (int i = 0; i < kNChunks; ++i) {
     for (int j = 0; j < kNBpc; ++j) {
-      lya::set_sk_shape(n, kChunks[i], kBpc[j]);
-      int rc = LYA_OK;
-      double t = 0.0;
-      hipError_t e = time_ms(
-          [&] {
-            rc = lya_draw_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zb, work, work_bytes,
-                                  stream);
-            return rc == LYA_OK ? hipSuccess : hipErrorUnknown;
-          },
-          reps, static_cast<hipStream_t>(stream), &t);
-      if (rc != LYA_OK) {
-        lya::set_sk_shape(n, c0, b0);
-        snprintf(g_aerr, sizeof(g_aerr), "lya_draw_skewers: %s", lya_last_error());
-        return rc;
-      }
-      if (e != hipSuccess) {
-        lya::set_sk_shape(n, c0, b0);
-        return ahip(e, "timing a skewer launch shape");
-      }
-      if (ms) ms[i * kNBpc + j] = t;
-      if (t < bt) {
-        bt = t;
-        bc = kChunks[i];
-        bb = kBpc[j];
+      for (int k = 0; k < kNUnroll; ++k) {
+        lya::set_sk_shape(n, kChunks[i], kBpc[j], kUnroll[k]);
+        int rc = LYA_OK;
+        double t = 0.0;
+        hipError_t e = time_ms(
+            [&] {
+              rc = lya_draw_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zb, work, work_bytes,
+                                    stream);
+              return rc == LYA_OK ? hipSuccess : hipErrorUnknown;
+            },
+            reps, static_cast<hipStream_t>(stream), &t);
+        if (rc != LYA_OK) {
+          lya::set_sk_shape(n, c0, b0, u0);
+          snprintf(g_aerr, sizeof(g_aerr), "lya_draw_skewers: %s", lya_last_error());
+          return rc;
+        }
+        if (e != hipSuccess) {
+          lya::set_sk_shape(n, c0, b0, u0);
+          return ahip(e, "timing a skewer launch shape");
+        }
+        if (ms) ms[(i * kNBpc + j) * kNUnroll + k] = t;
+        if (t < bt) {
+          bt = t;
+          bc = kChunks[i];
+          bb = kBpc[j];
+          bu = kUnroll[k];
+        }
       }
     }
   }
-  lya::set_sk_shape(n, bc, bb);
+  lya::set_sk_shape(n, bc, bb, bu);
   if (out) return lya_get_tuning(n, out);
   return LYA_OK;
 }

@@ -74,11 +74,12 @@ constexpr int kFftVariants = 10;
 int fft_variant(int n, int pass);
 int set_fft_variant(int n, int pass, int v);
 hipError_t launch_fft_strided_pass(int n, int pass, int variant, const float2* tw, float2* field, hipStream_t st);
-// Skewer-kernel launch shape per box size (autotuned): skewers per queue pull
-// and persistent blocks per CU.
+// Skewer-kernel launch shape per box size (autotuned): skewers per queue pull,
+// persistent blocks per CU, pixels per lane per gather step.
 int sk_chunk(int n);
 int sk_blocks_per_cu(int n);
-void set_sk_shape(int n, int chunk, int bpc);
+int sk_unroll(int n);
+void set_sk_shape(int n, int chunk, int bpc, int unroll);
 
 // Skewer stage.
 struct SkewerArgs {
@@ -123,6 +124,7 @@ struct SkewerArgs {
   unsigned int* queue;
   int chunk;
   int blocks_per_cu;  // persistent blocks per CU (<= 0: 4)
+  int unroll;         // pixels per lane per step: 1, 2 or 4 (other values: 2)
 };
 
 hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st);

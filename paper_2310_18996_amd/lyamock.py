@@ -260,11 +260,12 @@ class TuneResult(ctypes.Structure):
 FFT_VARIANTS = 10
 SK_CHUNKS = (1, 2, 4, 8, 16, 32, 64)
 SK_BLOCKS_PER_CU = (1, 2, 3, 4)
+SK_UNROLL = (1, 2, 4)
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fft_y", ctypes.c_int32), ("fft_x", ctypes.c_int32), ("sk_chunk", ctypes.c_int32),
-                ("sk_blocks_per_cu", ctypes.c_int32)]
+                ("sk_blocks_per_cu", ctypes.c_int32), ("sk_unroll", ctypes.c_int32)]
 
 
 def _bind_more(lib):
@@ -478,9 +479,9 @@ def autotune_fft(box, field, work, reps=3, stream=None):
 
 
 def autotune_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, work, reps=2, stream=None):
-    """lya_autotune_skewers: returns (Tuning, ms[len(SK_CHUNKS)][len(SK_BLOCKS_PER_CU)])."""
-    nc, nb = len(SK_CHUNKS), len(SK_BLOCKS_PER_CU)
-    ms = (ctypes.c_double * (nc * nb))()
+    """lya_autotune_skewers: returns (Tuning, ms[len(SK_CHUNKS)][len(SK_BLOCKS_PER_CU)][len(SK_UNROLL)])."""
+    nc, nb, nu = len(SK_CHUNKS), len(SK_BLOCKS_PER_CU), len(SK_UNROLL)
+    ms = (ctypes.c_double * (nc * nb * nu))()
     t = Tuning()
     _acheck(_lib2().lya_autotune_skewers(ctypes.byref(box), _ptr(field), ctypes.byref(sk), ctypes.byref(ps),
                                          int(seed), ctypes.byref(cosmo), ctypes.byref(fgpa) if fgpa else None,
@@ -488,7 +489,7 @@ def autotune_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbi
                                          ctypes.byref(zbins) if zbins is not None else None, _ptr(work),
                                          work.numel() * work.element_size(), int(reps), ms, ctypes.byref(t),
                                          _stream(stream)))
-    return t, [[ms[i * nb + j] for j in range(nb)] for i in range(nc)]
+    return t, [[[ms[(i * nb + j) * nu + k] for k in range(nu)] for j in range(nb)] for i in range(nc)]
 
 
 class Graph:

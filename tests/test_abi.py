@@ -94,14 +94,16 @@ def test_chi_of_z_on_the_host_matches_the_oracle():
 
 def test_tuning_table_on_the_host():
     t = L.get_tuning(2048)
-    assert (t.fft_y, t.fft_x, t.sk_chunk, t.sk_blocks_per_cu) == (0, 1, 8, 4)
-    L.set_tuning(2048, L.Tuning(4, 5, 16, 2))
+    assert (t.fft_y, t.fft_x, t.sk_chunk, t.sk_blocks_per_cu, t.sk_unroll) == (0, 1, 8, 4, 2)
+    L.set_tuning(2048, L.Tuning(4, 5, 16, 2, 4))
     u = L.get_tuning(2048)
-    assert (u.fft_y, u.fft_x, u.sk_chunk, u.sk_blocks_per_cu) == (4, 5, 16, 2)
+    assert (u.fft_y, u.fft_x, u.sk_chunk, u.sk_blocks_per_cu, u.sk_unroll) == (4, 5, 16, 2, 4)
     with pytest.raises(L.LyaError):
-        L.set_tuning(512, L.Tuning(2, 1, 8, 4))      # half tiles exist from 1024 up
+        L.set_tuning(512, L.Tuning(2, 1, 8, 4, 2))      # half tiles exist from 1024 up
     with pytest.raises(L.LyaError):
-        L.set_tuning(2048, L.Tuning(0, 1, 8, 5))
+        L.set_tuning(2048, L.Tuning(0, 1, 8, 5, 2))
+    with pytest.raises(L.LyaError):
+        L.set_tuning(2048, L.Tuning(0, 1, 8, 4, 3))
     L.set_tuning(2048, t)
     v = L.get_tuning(512)
     assert (v.fft_y, v.fft_x) == (0, 1)

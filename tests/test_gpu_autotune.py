@@ -39,12 +39,12 @@ def test_fft_variants_are_bit_identical(L, n):
     pk = L.pk_struct()
     saved = L.get_tuning(n)
     try:
-        L.set_tuning(n, L.Tuning(0, 1, saved.sk_chunk, saved.sk_blocks_per_cu))
+        L.set_tuning(n, L.Tuning(0, 1, saved.sk_chunk, saved.sk_blocks_per_cu, saved.sk_unroll))
         L.make_box(box, pk, 1234, 1.0, True, field, work)
         ref = L.box_view(field, n).clone()      # the plane padding is never written
         for vy, vx in [(1, 0), (2, 3), (3, 2), (4, 5), (5, 4), (6, 7), (7, 6), (8, 9), (9, 8)]:
             field.fill_(float("nan"))
-            L.set_tuning(n, L.Tuning(vy, vx, saved.sk_chunk, saved.sk_blocks_per_cu))
+            L.set_tuning(n, L.Tuning(vy, vx, saved.sk_chunk, saved.sk_blocks_per_cu, saved.sk_unroll))
             L.make_box(box, pk, 1234, 1.0, True, field, work)
             torch.cuda.synchronize()
             assert torch.equal(L.box_view(field, n), ref), (vy, vx)
@@ -78,7 +78,7 @@ def test_autotune_fft_keeps_results(L):
         assert all(ms2[p][v] == -1.0 for p in range(2) for v in range(2, L.FFT_VARIANTS))
     finally:
         L.set_tuning(n, saved)
-        L.set_tuning(256, L.Tuning(0, 1, 8, 4))
+        L.set_tuning(256, L.Tuning(0, 1, 8, 4, 2))
 
 
 def _mid_skewers(L, torch, n=256, n_sk=3000):
@@ -109,17 +109,17 @@ def test_autotune_skewers_keeps_results(L):
         torch.cuda.synchronize()
         ref = [x.clone() for x in (d, e, f, zkeep[1], zkeep[2])]
         t, ms = L.autotune_skewers(box, field, s, ps, 5, cosmo, fg, d, e, f, zb, swork, reps=1)
-        print("autotune skewers: chunk %d blocks/CU %d" % (t.sk_chunk, t.sk_blocks_per_cu))
-        assert t.sk_chunk in L.SK_CHUNKS and t.sk_blocks_per_cu in L.SK_BLOCKS_PER_CU
-        for c in (1, 64):
-            for b in (1, 4):
-                L.set_tuning(n, L.Tuning(saved.fft_y, saved.fft_x, c, b))
+        print("autotune skewers: chunk %d blocks/CU %d unroll %d" % (t.sk_chunk, t.sk_blocks_per_cu, t.sk_unroll))
+        assert t.sk_chunk in L.SK_CHUNKS and t.sk_blocks_per_cu in L.SK_BLOCKS_PER_CU and t.sk_unroll in L.SK_UNROLL
+        for c, b, u in ((1, 1, 1), (64, 4, 4), (1, 4, 2), (64, 1, 1)):
+            if True:
+                L.set_tuning(n, L.Tuning(saved.fft_y, saved.fft_x, c, b, u))
                 for x in (d, e, f):
                     x.fill_(float("nan"))
                 L.draw_skewers(box, field, s, ps, 5, cosmo, fg, d, e, f, zb, swork)
                 torch.cuda.synchronize()
                 for x, r in zip((d, e, f, zkeep[1], zkeep[2]), ref):
-                    assert torch.equal(x, r), (c, b)
+                    assert torch.equal(x, r), (c, b, u)
     finally:
         L.set_tuning(n, saved)
 
