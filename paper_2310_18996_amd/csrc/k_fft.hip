@@ -21,6 +21,8 @@
 // global memory directly in natural order.  Tiles are mapped to blocks so that
 // each XCD walks a contiguous range of tiles (neighbouring z chunks share
 // cache lines).
+#include <atomic>
+
 #include "lya_internal.h"
 
 namespace lya {
@@ -438,36 +440,25 @@ template <> struct Shape<2048> { static constexpr int TZ = 2,  EZ = 16, TS = 8, 
 //   2/3: half the pencils per tile (half the LDS: two blocks per CU), order 0/1;
 //   4/5: half tiles in the persistent pipelined kernel, order 0/1;
 //   6/7: full tiles with half the elements per thread (twice the waves), order 0/1;
-//   8/9: as 6/7 in the persistent pipelined kernel.
+//   8/9: as 6/7 in the persistent pipelined kernel;
+//   10/11: full tiles, one per block, tile order 2 (plain) / 3 (outer index fastest).
 // Boxes below 1024 have variants 0 and 1 only.
 namespace {
-int g_variant[2][12] = {};  // [pass y/x][log2 N]
-bool g_variant_init = false;
-void init_variants() {
-  if (g_variant_init) return;
-  for (int l = 0; l < 12; ++l) {
-    g_variant[0][l] = 0;  // y: one tile per block, order 0
-    g_variant[1][l] = 1;  // x: one tile per block, order 1
-  }
-  g_variant_init = true;
-}
+// [pass y/x][log2 N]; defaults: y one tile per block with order 0, x with order 1
+std::atomic<int> g_variant[2][12] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1}};
 int ilog2(int n) {
   int l = 0;
-  while ((1 << l) < n) ++l;
+  while ((1 << l) < n && l < 11) ++l;
   return l;
 }
 }  // namespace
 
-int fft_variant(int n, int pass) {
-  init_variants();
-  return g_variant[pass][ilog2(n)];
-}
+int fft_variant(int n, int pass) { return g_variant[pass][ilog2(n)].load(std::memory_order_relaxed); }
 
 int set_fft_variant(int n, int pass, int v) {
-  init_variants();
   if (v < 0 || v >= kFftVariants || pass < 0 || pass > 1) return -1;
   if (n < 1024 && v > 1) return -1;  // smaller boxes: one tile per block, order 0 or 1
-  g_variant[pass][ilog2(n)] = v;
+  g_variant[pass][ilog2(n)].store(v, std::memory_order_relaxed);
   return 0;
 }
 
@@ -504,6 +495,8 @@ hipError_t launch_strided(int variant, float2* field, uint32_t* bf16, const floa
       case 7: return launch_strided_tile<N, S::TS, EH, KIND, 1, false>(field, bf16, tw, g, st);
       case 8: return launch_strided_tile<N, S::TS, EH, KIND, 0, true>(field, bf16, tw, g, st);
       case 9: return launch_strided_tile<N, S::TS, EH, KIND, 1, true>(field, bf16, tw, g, st);
+      case 10: return launch_strided_tile<N, S::TS, S::ES, KIND, 2, false>(field, bf16, tw, g, st);
+      case 11: return launch_strided_tile<N, S::TS, S::ES, KIND, 3, false>(field, bf16, tw, g, st);
       default: break;
     }
   }

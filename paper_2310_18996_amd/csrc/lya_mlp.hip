@@ -656,8 +656,11 @@ __global__ void __launch_bounds__(kSearchNT) k_emu_search(SearchArgs a) {
   __shared__ int sstate;  // 0 evaluate strial, 1 done
   const Offs o = param_offsets(a.h->n_out);
   const int nk = a.nk, t = threadIdx.x;
-  const double alo = log(static_cast<double>(a.h->in_lo[0])), ahi = log(static_cast<double>(a.h->in_hi[0]));
-  const double blo = log(static_cast<double>(a.h->in_lo[1])), bhi = log(static_cast<double>(a.h->in_hi[1]));
+  // the emulator's (a, b) input range in (ln a, ln b); a non-positive lower
+  // limit leaves that side open
+  auto lnlim = [](float v) { return v > 0.0f ? log(static_cast<double>(v)) : -HUGE_VAL; };
+  const double alo = lnlim(a.h->in_lo[0]), ahi = log(static_cast<double>(a.h->in_hi[0]));
+  const double blo = lnlim(a.h->in_lo[1]), bhi = log(static_cast<double>(a.h->in_hi[1]));
   constexpr double kH = 1e-3;
   // lane-0 state
   double th[2] = {a.x0[0], a.x0[1]}, chi2 = HUGE_VAL, lam = 1e-3, A00 = 0, A01 = 0, A11 = 0, g0 = 0, g1 = 0;
