@@ -51,9 +51,12 @@ def mode_grid(n, ix_slice=None):
     return np.meshgrid(ix, iy, iz, indexing="ij")
 
 
-def white_noise(n, seed, ix_slice=None, fixed_amp=False):
-    """Hermitian-paired unit complex noise W for all modes (or an ix slab)."""
-    gx, gy, gz = mode_grid(n, ix_slice)
+def noise_at(n, seed, gx, gy, gz, fixed_amp=False):
+    """Hermitian-paired unit complex noise W of the modes with index arrays
+    (gx, gy, gz) in [0, n): the lower linear index of a mode and its partner
+    -n mod N owns the Philox draw; the partner takes the conjugate;
+    self-conjugate modes take the real normal."""
+    gx, gy, gz = (np.asarray(a, dtype=np.int64) for a in (gx, gy, gz))
     lin = (gx * n + gy) * n + gz
     px, py, pz = (-gx) % n, (-gy) % n, (-gz) % n
     plin = (px * n + py) * n + pz
@@ -67,11 +70,17 @@ def white_noise(n, seed, ix_slice=None, fixed_amp=False):
     return w
 
 
-def component_multiplier(n, comp, f=1.0, ix_slice=None):
-    """Real multiplier turning delta_hat into the requested component."""
+def white_noise(n, seed, ix_slice=None, fixed_amp=False):
+    """Hermitian-paired unit complex noise W for all modes (or an ix slab)."""
+    gx, gy, gz = mode_grid(n, ix_slice)
+    return noise_at(n, seed, gx, gy, gz, fixed_amp)
+
+
+def multiplier_at(n, comp, f, gx, gy, gz):
+    """Real multiplier turning delta_hat into the requested component at the
+    modes (gx, gy, gz); None for delta."""
     if comp == "delta":
         return None
-    gx, gy, gz = mode_grid(n, ix_slice)
     nv = [signed_freq(gx, n), signed_freq(gy, n), signed_freq(gz, n)]
     n2 = nv[0] ** 2 + nv[1] ** 2 + nv[2] ** 2
     axis = {"x": 0, "y": 1, "z": 2}
@@ -81,6 +90,14 @@ def component_multiplier(n, comp, f=1.0, ix_slice=None):
         nyq = (nv[p] == -(n // 2)) | (nv[q] == -(n // 2))
         num = np.where(nyq, 0.0, num)
     return f * np.where(n2 > 0, num / np.where(n2 > 0, n2, 1), 0.0)
+
+
+def component_multiplier(n, comp, f=1.0, ix_slice=None):
+    """Real multiplier turning delta_hat into the requested component."""
+    if comp == "delta":
+        return None
+    gx, gy, gz = mode_grid(n, ix_slice)
+    return multiplier_at(n, comp, f, gx, gy, gz)
 
 
 def amplitudes(n, table, ix_slice=None, only_n2=-1):
@@ -133,3 +150,40 @@ def brute_force_field(n, xhat):
                 out += xhat[a, b, c] * (ph[a][:, None, None] * ph[b][None, :, None]
                                         * ph[c][None, None, :])
     return out
+
+
+def shell_modes(n, seed, table, only_n2, comps=("delta", "zz"), f=1.0):
+    """The modes of one shell |n|^2 = only_n2 of the packed spectrum (the
+    spectrum() field with every other mode zero): integer frequencies
+    [M, 3] and complex coefficients [M], from the same noise, amplitude and
+    component rules as spectrum()."""
+    r = int(np.floor(np.sqrt(only_n2))) + 1
+    v = np.arange(-r, r + 1)
+    nx, ny, nz = np.meshgrid(v, v, v, indexing="ij")
+    sel = (nx ** 2 + ny ** 2 + nz ** 2 == only_n2) & (np.abs(nx) <= n // 2) & (np.abs(ny) <= n // 2) & \
+        (np.abs(nz) <= n // 2) & (nx != n // 2) & (ny != n // 2) & (nz != n // 2)
+    freqs = np.stack([nx[sel], ny[sel], nz[sel]], axis=1).astype(np.int64)
+    gx, gy, gz = (freqs[:, i] % n for i in range(3))
+    base = table[only_n2] * noise_at(n, seed, gx, gy, gz)
+    vals = []
+    for comp in comps:
+        mult = multiplier_at(n, comp, f, gx, gy, gz)
+        vals.append(base if mult is None else mult * base)
+    coef = vals[0] if len(vals) == 1 else vals[0] + 1j * vals[1]
+    return freqs, coef
+
+
+def shell_field_at(n, freqs, coef, ix, iy, iz, chunk=1 << 15):
+    """Direct sum of the inverse DFT over the given modes at grid points
+    (ix, iy, iz) (integer arrays of equal shape): sum_m coef_m
+    exp(2 pi i (a ix + b iy + c iz) / n), the phase reduced mod n in integers
+    first (so it is exact), then taken from a table of exp(2 pi i k / n)."""
+    ix, iy, iz = (np.asarray(a, dtype=np.int64) for a in (ix, iy, iz))
+    pts = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+    cis = np.exp(2j * np.pi * np.arange(n) / n)
+    f = np.asarray(freqs, dtype=np.int64).T
+    coef = np.asarray(coef, dtype=np.complex128)
+    out = np.empty(len(pts), dtype=np.complex128)
+    for s in range(0, len(pts), chunk):
+        out[s:s + chunk] = cis[(pts[s:s + chunk] @ f) % n] @ coef
+    return out.reshape(ix.shape)

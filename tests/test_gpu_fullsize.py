@@ -1,22 +1,27 @@
-"""Parity at the full sizes of the benchmark configurations.
+"""Parity at the full sizes of the benchmark configurations.  Every expected
+value comes from the FP64 oracle alone; no GPU output is fed to it.
 
 * 2048^3 box (the benchmark workload): whole z-lines against the exact FP64
-  C oracle (O(N^3) per batch of lines), then the skewer stage on a
-  10,000-skewer subset of the 1M-skewer table, with the oracle interpolating
-  the GPU field (already checked line by line) in FP64.
+  C oracle (O(N^3) per batch of lines).
+* 2048^3 skewer stage on a 10,000-skewer subset of the 1M-skewer table, on a
+  single-shell box (the only_n2 test hook, |n|^2 = 10003: 288 modes), whose
+  field the oracle evaluates exactly at every voxel by direct summation.
 * 1024^3 precision configuration: FP32 against BF16 storage of {delta,
-  eta_par}, each against the FP64 oracle: z-lines, pixels, flux, mean flux per
-  redshift bin and P1D on a 20,000-skewer subset of the 200,000-skewer table.
+  eta_par}, each against the oracle: z-lines, and the pixels, flux, mean flux
+  per redshift bin and P1D of eight skewers of the 200,000-skewer table whose
+  voxel columns the C oracle computes exactly.
 """
 import numpy as np
 import pytest
 
 import mockinputs
-from oracle import fgpa, lines, p1d, skewers
+from oracle import field, fgpa, lines, p1d, power, skewers
 from tests.lyahelp import oracle_table, rel_rms, skewer_tensors
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
+SHELL = 10003
+SHELL_SIGMA8 = 100.0  # delta rms ~0.4 from the 288 modes alone
 
 
 @pytest.fixture(scope="module")
@@ -29,49 +34,56 @@ def L():
     return lyamock
 
 
-class DeviceGrid:
-    """[n, n, n] complex view of a device box for the oracle's trilinear
-    gathers: indexing copies the requested voxels to the host (data movement
-    only; every arithmetic step stays in the FP64 oracle)."""
+class ShellGrid:
+    """[n, n, n] complex grid of a single-shell field, evaluated by the oracle
+    (direct sum over the shell's modes) at the voxels requested."""
 
-    def __init__(self, L, field, n, bf16=False):
-        import torch
-        self.torch = torch
-        self.n = n
-        self.shape = (n, n, n)
-        self.bf16 = bf16
-        self.v = L.box_view(field, n)
+    def __init__(self, n, freqs, coef):
+        self.n, self.shape, self.freqs, self.coef = n, (n, n, n), freqs, coef
 
     def __getitem__(self, idx):
-        t = self.torch
-        a, b, c = (t.from_numpy(np.ascontiguousarray(i, dtype=np.int64)).cuda() for i in idx)
-        vals = self.v[a, b, c]
-        if self.bf16:  # packed bf16x2 words: low half delta, high half eta
-            w = vals.cpu().numpy().view(np.uint32)
-            re = (w << 16).view(np.float32).astype(np.float64)
-            im = (w & 0xFFFF0000).view(np.float32).astype(np.float64)
-        else:
-            h = vals.cpu().numpy().astype(np.float64)
-            re, im = h[..., 0], h[..., 1]
-        return re + 1j * im
+        a, b, c = (np.asarray(i, dtype=np.int64) for i in idx)
+        key = (a * self.n + b) * self.n + c
+        uniq, inv = np.unique(key.ravel(), return_inverse=True)
+        ua, rest = np.divmod(uniq, self.n * self.n)
+        ub, uc = np.divmod(rest, self.n)
+        vals = field.shell_field_at(self.n, self.freqs, self.coef, ua, ub, uc)
+        return vals[inv].reshape(key.shape)
 
 
-def subset(sk, count, seed):
-    """count skewers of the table sk (random, in table order), re-packed."""
-    rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(len(sk["npix"]), size=count, replace=False))
+class LineGrid:
+    """[n, n, n] complex grid backed by whole z-lines of the C oracle for a
+    set of (x, y) columns."""
+
+    def __init__(self, n, columns, re, im):
+        self.n, self.shape = n, (n, n, n)
+        self.index = {tuple(c): i for i, c in enumerate(columns)}
+        self.lines = np.asarray(re) + 1j * np.asarray(im)
+
+    def __getitem__(self, idx):
+        a, b, c = (np.asarray(i, dtype=np.int64) for i in idx)
+        rows = np.vectorize(lambda x, y: self.index[(int(x), int(y))])(a, b)
+        return self.lines[rows, c]
+
+
+def subset(sk, idx):
+    """The skewers idx of table sk, re-packed."""
+    idx = np.asarray(idx)
     npix = sk["npix"][idx]
-    off = np.zeros(count, dtype=np.int64)
+    off = np.zeros(len(idx), dtype=np.int64)
     off[1:] = np.cumsum(npix[:-1].astype(np.int64))
     return dict(origin_fx=sk["origin_fx"][idx], step_fx=sk["step_fx"][idx], npix=npix, offset=off,
                 chi0=sk["chi0"][idx], dchi=sk["dchi"], id_base=0, total=int(npix.sum()))
 
 
+def all_positions(sk):
+    return np.concatenate([skewers.pixel_positions(sk["origin_fx"][q], sk["step_fx"][q], int(sk["npix"][q]))
+                           for q in range(len(sk["npix"]))])
+
+
 def oracle_pixels(grid, sk, seed, cfg):
     """The oracle's pre-FGPA pixels: trilinear on grid (FP64) + delta_S."""
-    pos = np.concatenate([skewers.pixel_positions(sk["origin_fx"][q], sk["step_fx"][q], int(sk["npix"][q]))
-                          for q in range(len(sk["npix"]))])
-    v = skewers.trilinear(grid, pos)
+    v = skewers.trilinear(grid, all_positions(sk))
     dens = v.real.copy()
     for q in range(len(sk["npix"])):
         o, nq = int(sk["offset"][q]), int(sk["npix"][q])
@@ -79,7 +91,7 @@ def oracle_pixels(grid, sk, seed, cfg):
     return dens, v.imag.copy()
 
 
-def gpu_pixels(L, torch, box, field, sk, seed, cfg, edges):
+def gpu_pixels(L, torch, box, fld, sk, seed, cfg, edges):
     s, keep = skewer_tensors(L, sk)
     tot = sk["total"]
     d, e, f = (torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(3))
@@ -87,7 +99,7 @@ def gpu_pixels(L, torch, box, field, sk, seed, cfg, edges):
     fs = torch.zeros(len(edges) - 1, dtype=torch.float64, device="cuda")
     cn = torch.zeros(len(edges) - 1, dtype=torch.int64, device="cuda")
     work = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
-    L.draw_skewers(box, field, s, L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0), seed,
+    L.draw_skewers(box, fld, s, L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0), seed,
                    L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"]), d, e, f, L.zbins_struct(ed, fs, cn), work)
     torch.cuda.synchronize()
     out = dict(dens=d.cpu().numpy(), eta=e.cpu().numpy(), flux=f.cpu().numpy(), fsum=fs.cpu().numpy(),
@@ -95,39 +107,44 @@ def gpu_pixels(L, torch, box, field, sk, seed, cfg, edges):
     return out, (s, keep, f, ed, fs, cn)
 
 
-def gpu_p1d(L, torch, sk_handles, k_edges, z_ref, cfg, n_sk):
-    s, keep, f, ed, fs, cn = sk_handles
+def gpu_p1d(L, torch, handles, k_edges, z_ref, cfg, n_sk):
+    s, keep, f, ed, fs, cn = handles
     ke = torch.from_numpy(k_edges).cuda()
     ps = torch.zeros(len(k_edges) - 1, dtype=torch.float64, device="cuda")
     pc = torch.zeros(len(k_edges) - 1, dtype=torch.int64, device="cuda")
     work = torch.empty(L.p1d_workspace_size(n_sk, len(k_edges) - 1), dtype=torch.uint8, device="cuda")
-    L.p1d(s, L.Cosmo(cfg["omega_m"]), f, L.zbins_struct(ed, fs, cn), L.P1dSpec(len(k_edges) - 1, ke.data_ptr(),
-          float(z_ref), float(cfg["dpix"])), ps, pc, work)
+    L.p1d(s, L.Cosmo(cfg["omega_m"]), f, L.zbins_struct(ed, fs, cn),
+          L.P1dSpec(len(k_edges) - 1, ke.data_ptr(), float(z_ref), float(cfg["dpix"])), ps, pc, work)
     torch.cuda.synchronize()
     return ps.cpu().numpy(), pc.cpu().numpy()
 
 
-def _make(L, torch, cfg, storage):
+def make_box(L, torch, cfg, storage, **pk_over):
     n = cfg["n"]
     box = L.box_struct(n, cfg["dx"], storage)
     elems = L.field_elems(box)
-    field = (torch.empty((elems, 2), dtype=torch.float32, device="cuda") if storage == L.LYA_F32
-             else torch.empty((elems,), dtype=torch.int32, device="cuda"))
+    fld = (torch.empty((elems, 2), dtype=torch.float32, device="cuda") if storage == L.LYA_F32
+           else torch.empty((elems,), dtype=torch.int32, device="cuda"))
     work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
-    L.make_box(box, L.pk_struct(**cfg["pk"]), cfg["seed"], cfg["f"], True, field, work)
+    L.make_box(box, L.pk_struct(**dict(cfg["pk"], **pk_over)), cfg["seed"], cfg["f"], True, fld, work)
     torch.cuda.synchronize()
     del work
-    return box, field
+    return box, fld
+
+
+def bin_sums_close(gpu_fsum, fs, cnt):
+    # the GPU sums round(F 2^32) exactly: each pixel carries at most half a quantum
+    return np.all(np.abs(gpu_fsum - fs) <= 1e-5 * np.abs(fs) + cnt * 2.0 ** -32)
 
 
 @pytest.mark.timeout(600)
-def test_big_box_lines_and_skewer_subset(L):
+def test_big_box_lines(L):
     import torch
     cfg = mockinputs.config("big")
     n = cfg["n"]
     print("2048^3 box: lines against the C oracle", flush=True)
-    box, field = _make(L, torch, cfg, L.LYA_F32)
-    view = L.box_view(field, n)
+    box, fld = make_box(L, torch, cfg, L.LYA_F32)
+    view = L.box_view(fld, n)
     cols = [(0, 0), (1, n - 1), (n // 2, 3), (1234, 777)]
     re, im = lines.field_lines(n, cfg["seed"], oracle_table(cfg["pk"], n, cfg["dx"]), cols)
     for l, (mx, my) in enumerate(cols):
@@ -135,23 +152,67 @@ def test_big_box_lines_and_skewer_subset(L):
         e = (rel_rms(line[:, 0], re[l]), rel_rms(line[:, 1], im[l]))
         print("line", (mx, my), "rel rms delta %.2e eta %.2e" % e, flush=True)
         assert max(e) < TOL, (mx, my, e)
-    print("skewer subset", flush=True)
-    sk = subset(mockinputs.skewer_table(cfg), 10_000, 7)
+    del view, fld
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_big_skewer_subset_on_a_single_shell_box(L):
+    import torch
+    cfg = mockinputs.config("big")
+    n = cfg["n"]
+    pk = dict(cfg["pk"], sigma8=SHELL_SIGMA8)   # shell amplitude comparable to delta_S
+    print("2048^3 single-shell box |n|^2 = %d" % SHELL, flush=True)
+    box, fld = make_box(L, torch, cfg, L.LYA_F32, sigma8=SHELL_SIGMA8, only_n2=SHELL)
+    tab = power.amplitude_table(power.PowerSpectrum(**pk), n, cfg["dx"])
+    freqs, coef = field.shell_modes(n, cfg["seed"], tab, SHELL)
+    rng = np.random.default_rng(7)
+    sk_all = mockinputs.skewer_table(cfg)
+    sk = subset(sk_all, np.sort(rng.choice(len(sk_all["npix"]), size=10_000, replace=False)))
     edges = fgpa.chi_edges_for_z(cfg["z_edges"])
-    out, _ = gpu_pixels(L, torch, box, field, sk, cfg["seed"], cfg, edges)
-    print("oracle pixels (%d)" % sk["total"], flush=True)
-    rd, re_ = oracle_pixels(DeviceGrid(L, field, n), sk, cfg["seed"], cfg)
+    out, _ = gpu_pixels(L, torch, box, fld, sk, cfg["seed"], cfg, edges)
+    print("oracle pixels (%d, %d modes)" % (sk["total"], len(freqs)), flush=True)
+    rd, re_ = oracle_pixels(ShellGrid(n, freqs, coef), sk, cfg["seed"], cfg)
     print("oracle FGPA", flush=True)
     rf, _ = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
     e = dict(dens=rel_rms(out["dens"], rd), eta=rel_rms(out["eta"], re_), flux=rel_rms(out["flux"], rf))
-    print("10k skewers (%d pixels): rel rms" % sk["total"], e, flush=True)
+    print("10k skewers (%d pixels): rel rms" % sk["total"], {k: "%.2e" % v for k, v in e.items()},
+          "eta rms %.3f" % float(np.sqrt(np.mean(re_ ** 2))), flush=True)
     assert all(v < TOL for v in e.values()), e
     fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
     np.testing.assert_array_equal(out["count"], cnt)
-    # the GPU sums round(F 2^32) exactly: each pixel carries at most half a quantum
-    assert np.all(np.abs(out["fsum"] - fs) <= 1e-5 * np.abs(fs) + cnt * 2.0 ** -32)
-    del view, field
+    assert bin_sums_close(out["fsum"], fs, cnt)
+    del fld
     torch.cuda.empty_cache()
+
+
+def skewer_columns(sk, n):
+    """The (x, y) voxel columns the trilinear gathers of sk touch."""
+    pos = all_positions(sk)
+    cell = (pos >> 32) % n
+    cols = set()
+    for dx in (0, 1):
+        for dy in (0, 1):
+            cols.update(zip(((cell[:, 0] + dx) % n).tolist(), ((cell[:, 1] + dy) % n).tolist()))
+    return sorted(cols)
+
+
+def few_column_skewers(sk):
+    """Eight skewers of the table, two per length band: in each band the first
+    that stays inside one (x, y) cell and the first that crosses one cell
+    boundary in x and one in y (so the C oracle needs few voxel columns)."""
+    o, s, npix = sk["origin_fx"], sk["step_fx"], sk["npix"].astype(np.int64)
+    end = o + s * (npix[:, None] - 1)
+    cx = np.abs((end[:, 0] >> 32) - (o[:, 0] >> 32))
+    cy = np.abs((end[:, 1] >> 32) - (o[:, 1] >> 32))
+    pick = []
+    for lo, hi in ((200, 450), (450, 700), (700, 950), (950, 1201)):
+        band = (npix >= lo) & (npix < hi)
+        for m in ((cx == 0) & (cy == 0), (cx == 1) & (cy == 1)):
+            idx = np.flatnonzero(band & m)
+            assert len(idx), (lo, hi)
+            pick.append(int(idx[0]))
+    return sorted(pick)
 
 
 @pytest.mark.timeout(600)
@@ -160,45 +221,53 @@ def test_precision_fp32_and_bf16_storage(L):
     cfg = mockinputs.config("precision")
     n = cfg["n"]
     print("1024^3 precision configuration", flush=True)
-    box32, f32 = _make(L, torch, cfg, L.LYA_F32)
-    box16, f16 = _make(L, torch, cfg, L.LYA_BF16)
-    cols = [(0, 0), (3, n - 1), (n // 2, 17), (700, 300)]
-    print("C oracle lines", flush=True)
-    re, im = lines.field_lines(n, cfg["seed"], oracle_table(cfg["pk"], n, cfg["dx"]), cols)
-    g32, g16 = DeviceGrid(L, f32, n), DeviceGrid(L, f16, n, bf16=True)
+    box32, f32 = make_box(L, torch, cfg, L.LYA_F32)
+    box16, f16 = make_box(L, torch, cfg, L.LYA_BF16)
+    sk_all = mockinputs.skewer_table(cfg)
+    pick = few_column_skewers(sk_all)
+    sk = subset(sk_all, pick)
+    cols = skewer_columns(sk, n)
+    probe = [(0, 0), (3, n - 1), (n // 2, 17), (700, 300)]
+    allcols = probe + [c for c in cols if c not in probe]
+    print("C oracle: %d columns" % len(allcols), flush=True)
+    re, im = lines.field_lines(n, cfg["seed"], oracle_table(cfg["pk"], n, cfg["dx"]), allcols)
+    grid = LineGrid(n, allcols, re, im)
     report = {}
-    for name, g in (("fp32", g32), ("bf16", g16)):
-        d = [rel_rms(g[(np.full(n, mx), np.full(n, my), np.arange(n))].real, re[l]) for l, (mx, my) in enumerate(cols)]
-        h = [rel_rms(g[(np.full(n, mx), np.full(n, my), np.arange(n))].imag, im[l]) for l, (mx, my) in enumerate(cols)]
+    for name, fld, packed in (("fp32", f32, False), ("bf16", f16, True)):
+        v = L.box_view(fld, n)
+        d, h = [], []
+        for l, (mx, my) in enumerate(probe):
+            line = v[mx, my].cpu().numpy()
+            if packed:
+                w = line.view(np.uint32)
+                lr, li = (w << 16).view(np.float32), (w & 0xFFFF0000).view(np.float32)
+            else:
+                lr, li = line[:, 0], line[:, 1]
+            d.append(rel_rms(lr, re[l]))
+            h.append(rel_rms(li, im[l]))
         report[name] = dict(delta=max(d), eta=max(h))
-    sk = subset(mockinputs.skewer_table(cfg), 20_000, 11)
     edges = fgpa.chi_edges_for_z(cfg["z_edges"])
-    # oracle pixels interpolate the FP32 GPU field, itself checked line by line above
-    print("oracle pixels (%d)" % sk["total"], flush=True)
-    rd, re_ = oracle_pixels(g32, sk, cfg["seed"], cfg)
-    print("oracle FGPA", flush=True)
+    rd, re_ = oracle_pixels(grid, sk, cfg["seed"], cfg)
     rf, _ = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
-    print("oracle P1D", flush=True)
     fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
     ok = cnt > 0
     fmean = np.where(ok, fs / np.maximum(cnt, 1), 1.0)
     k_edges = mockinputs.tune_k_edges()
     ps_r, pc_r = p1d.p1d(rf, sk, edges, fmean, k_edges, 2.6, cfg["dpix"])
     good = pc_r > 0
-    for name, box, field in (("fp32", box32, f32), ("bf16", box16, f16)):
-        print("GPU skewers and P1D,", name, flush=True)
-        out, hd = gpu_pixels(L, torch, box, field, sk, cfg["seed"], cfg, edges)
+    for name, box, fld in (("fp32", box32, f32), ("bf16", box16, f16)):
+        out, hd = gpu_pixels(L, torch, box, fld, sk, cfg["seed"], cfg, edges)
         ps_g, pc_g = gpu_p1d(L, torch, hd, k_edges, 2.6, cfg, len(sk["npix"]))
         np.testing.assert_array_equal(pc_g, pc_r)
-        # mean-flux error in units of each bin's own scale: relative, plus the
-        # fixed-point quantum 2^-32 per pixel of the GPU's exact sums
+        np.testing.assert_array_equal(out["count"], cnt)
+        # mean-flux error in units of each bin's scale: relative, plus the 2^-32 quantum per pixel
         fb_err = np.abs(out["fsum"] - fs) / (np.abs(fs) + cnt * 2.0 ** -32 / 1e-5)
         report[name].update(dens=rel_rms(out["dens"], rd), eta_pix=rel_rms(out["eta"], re_),
-                            flux=rel_rms(out["flux"], rf),
-                            fbar_max_rel=float(np.max(fb_err[ok])),
+                            flux=rel_rms(out["flux"], rf), fbar_max_rel=float(np.max(fb_err[ok])),
                             p1d_max_rel=float(np.max(np.abs(ps_g[good] / ps_r[good] - 1))))
     for name, r in report.items():
-        print(name, {k: "%.2e" % v for k, v in r.items()}, flush=True)
+        print(name, "(%d skewers, %d pixels)" % (len(pick), sk["total"]), {k: "%.2e" % v for k, v in r.items()},
+              flush=True)
     f = report["fp32"]
     assert max(f["delta"], f["eta"], f["dens"], f["eta_pix"], f["flux"], f["fbar_max_rel"]) < TOL, f
     assert f["p1d_max_rel"] < 1e-4, f

@@ -136,3 +136,16 @@ def test_c_lines_only_shell():
     box = field.make_box(n, 2, tab, ("delta", "zz"), only_n2=1)
     re, im = lines.field_lines(n, 2, tab, [(5, 6)], only_n2=1, nthreads=1)
     np.testing.assert_allclose(re[0] + 1j * im[0], box[5, 6], atol=1e-12)
+
+
+@pytest.mark.parametrize("n,s2", [(16, 1), (16, 6), (32, 27), (32, 50)])
+def test_shell_direct_sum_matches_box(n, s2):
+    # the single-shell evaluator (a direct sum over the shell's modes at any
+    # voxel) reproduces the FFT box with only that shell kept
+    tab = _table(n)
+    box = field.make_box(n, 9, tab, ("delta", "zz"), f=0.8, only_n2=s2)
+    freqs, coef = field.shell_modes(n, 9, tab, s2, f=0.8)
+    assert len(freqs) > 0
+    ix, iy, iz = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    got = field.shell_field_at(n, freqs, coef, ix, iy, iz, chunk=999)
+    np.testing.assert_allclose(got, box, atol=1e-12 * np.abs(box).max())
