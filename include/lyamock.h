@@ -316,14 +316,16 @@ const char* lya_emulator_last_error(void);
  *                     full tiles with half the elements per thread (twice the
  *                     waves), order 0/1; 8/9 those in the pipelined kernel;
  *                     10/11 full tiles with tile order 2 (plain block order) /
- *                     3 (outer index fastest within an XCD).  Boxes below 1024
- *                     have variants 0 and 1 only.  Defaults: y 0, x 1.
+ *                     3 (outer index fastest within an XCD); 12/13 full tiles
+ *                     in the pipelined kernel, order 0/1.  Boxes below 1024
+ *                     have variants 0 and 1 only.  Defaults: y 8, x 9 from
+ *                     1024 up, y 0, x 1 below.
  *   sk_chunk          skewers taken per pull from the skewer work queue (default 8);
  *   sk_blocks_per_cu  persistent skewer blocks per CU, 1..4 (default 4);
  *   sk_unroll         pixels per lane whose gathers are issued together, 1, 2 or 4
  *                     (default 2).
  * The table is process-wide and applies to every later call for that n. */
-#define LYA_FFT_VARIANTS 12
+#define LYA_FFT_VARIANTS 14
 typedef struct {
   int32_t fft_y, fft_x, sk_chunk, sk_blocks_per_cu, sk_unroll;
 } lya_tuning;

@@ -396,14 +396,23 @@ k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const flo
   using P = Pass<N, T, E, KIND>;
   constexpr int ntiles = N * (N / T);
   __shared__ float2 lds[P::LDS_ELEMS];
+  // twiddles in LDS: a global twiddle load issued after the next tile's loads
+  // would wait for them (vector memory loads complete in order)
+  __shared__ float2 stw[N];
+  for (int i = threadIdx.x; i < N; i += P::NT) stw[i] = tw[i];
+  __syncthreads();
   float2 v[E], nv[E];
-  const int tid = threadIdx.x;
   int b = blockIdx.x;
   if (b >= ntiles) return;
   int outer, t0;
   strided_tile<N, T, ORDER>(b, outer, t0);
-  P::load_global0(v, data, outer, t0, tid);
+  P::load_global0(v, data, outer, t0, static_cast<int>(threadIdx.x));
   for (;;) {
+    // a thread index the compiler cannot prove loop-invariant: hoisted out of
+    // the loop, every LDS, twiddle and global address of the tile would stay
+    // live in registers for the whole kernel (and spill)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int bn = b + static_cast<int>(gridDim.x);
     const bool more = bn < ntiles;
     int on = 0, tn = 0;
@@ -411,7 +420,7 @@ k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const flo
       strided_tile<N, T, ORDER>(bn, on, tn);
       P::load_global0(nv, data, on, tn, tid);
     }
-    P::transform_store(v, lds, data, KIND == KIND_X ? out_bf16 : nullptr, tw, KIND == KIND_X && g.comp_b < 0,
+    P::transform_store(v, lds, data, KIND == KIND_X ? out_bf16 : nullptr, stw, KIND == KIND_X && g.comp_b < 0,
                        outer, t0, false, tid);
     if (!more) break;
     __syncthreads();  // every thread has read this tile's LDS before the next one is written
@@ -441,11 +450,14 @@ template <> struct Shape<2048> { static constexpr int TZ = 2,  EZ = 16, TS = 8, 
 //   4/5: half tiles in the persistent pipelined kernel, order 0/1;
 //   6/7: full tiles with half the elements per thread (twice the waves), order 0/1;
 //   8/9: as 6/7 in the persistent pipelined kernel;
-//   10/11: full tiles, one per block, tile order 2 (plain) / 3 (outer index fastest).
+//   10/11: full tiles, one per block, tile order 2 (plain) / 3 (outer index fastest);
+//   12/13: full tiles in the persistent pipelined kernel, order 0/1.
 // Boxes below 1024 have variants 0 and 1 only.
 namespace {
-// [pass y/x][log2 N]; defaults: y one tile per block with order 0, x with order 1
-std::atomic<int> g_variant[2][12] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1}};
+// [pass y/x][log2 N]; defaults: below 1024 one tile per block, y with tile
+// order 0 and x with order 1; from 1024 up the pipelined kernel with full
+// tiles of half the elements per thread, y order 0 (variant 8), x order 1 (9)
+std::atomic<int> g_variant[2][12] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 8, 8}, {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 9, 9}};
 int ilog2(int n) {
   int l = 0;
   while ((1 << l) < n && l < 11) ++l;
@@ -497,6 +509,8 @@ hipError_t launch_strided(int variant, float2* field, uint32_t* bf16, const floa
       case 9: return launch_strided_tile<N, S::TS, EH, KIND, 1, true>(field, bf16, tw, g, st);
       case 10: return launch_strided_tile<N, S::TS, S::ES, KIND, 2, false>(field, bf16, tw, g, st);
       case 11: return launch_strided_tile<N, S::TS, S::ES, KIND, 3, false>(field, bf16, tw, g, st);
+      case 12: return launch_strided_tile<N, S::TS, S::ES, KIND, 0, true>(field, bf16, tw, g, st);
+      case 13: return launch_strided_tile<N, S::TS, S::ES, KIND, 1, true>(field, bf16, tw, g, st);
       default: break;
     }
   }

@@ -257,7 +257,7 @@ class TuneResult(ctypes.Structure):
                 ("coef", (ctypes.c_double * 3) * 3), ("seconds", ctypes.c_double)]
 
 
-FFT_VARIANTS = 12
+FFT_VARIANTS = 14
 SK_CHUNKS = (1, 2, 4, 8, 16, 32, 64)
 SK_BLOCKS_PER_CU = (1, 2, 3, 4)
 SK_UNROLL = (1, 2, 4)
