@@ -37,11 +37,20 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) on the 2048^3 + 1M-skewer workload, scaled by what the same
 # counters read for a plain 4 GiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1);
-# profiles/box2048_skewers1M_hbm_traffic.md.  Valid only for the kernels as
-# they were when the counters were taken (a changed kernel must drop its
-# entry) and reported only for that workload.
-TRAFFIC = {"fft_x": 137534552117, "fft_y": 140341231014}
+# profiles/box2048_skewers1M_hbm_traffic.md.  Keyed by (kernel, FFT variant)
+# for the strided passes; valid only for the kernels as they were when the
+# counters were taken (a changed kernel must drop its entry) and reported only
+# for that workload.
+TRAFFIC = {("fft_x", 9): 137475140296, ("fft_y", 8): 139264379197, ("fft_z_gen", None): 95698147393,
+           ("skewers", None): 14574181172}
 TRAFFIC_CONFIG = "big"
+
+
+def measured_traffic(L, name, n):
+    if name in ("fft_y", "fft_x"):
+        t = L.get_tuning(n)
+        return TRAFFIC.get((name, t.fft_y if name == "fft_y" else t.fft_x))
+    return TRAFFIC.get((name, None))
 
 
 def algorithmic_bytes(name, n, pixels, n_sk, voxel_bytes):
@@ -477,7 +486,7 @@ def main():
     achieved = ab / (avg_ms * 1e-3) / 1e9 if ab else None
     roof = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=(achieved / HBM_PEAK_GBS) if achieved else None,
-                traffic=TRAFFIC.get(dom) if args.config == TRAFFIC_CONFIG else None,
+                traffic=measured_traffic(L, dom, n) if args.config == TRAFFIC_CONFIG else None,
                 algorithmic_bytes_per_launch=ab, mean_launch_ms=avg_ms)
     kernels = {k: dict(mean_ms=v[0] / v[1], launches=v[1]) for k, v in sorted(kt.items())}
     for k in kernels:

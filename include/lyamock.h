@@ -338,7 +338,8 @@ int lya_set_tuning(int32_t n, const lya_tuning* t);
  * untimed run, with HIP events on `stream`; stores the fastest variant of
  * each pass in the table.  ms (may be NULL) receives the mean milliseconds,
  * [pass][variant] with 2 x LYA_FFT_VARIANTS entries (-1 for variants not
- * available at this n).  work: at least 8 n bytes (twiddles).  Synchronous. */
+ * available at this n).  A variant replaces the current one only if it is at
+ * least 2% faster.  work: at least 8 n bytes (twiddles).  Synchronous. */
 int lya_autotune_fft(const lya_box* box, void* field, void* work, size_t work_bytes, int32_t reps, double* ms,
                      lya_tuning* out, void* stream);
 

@@ -143,19 +143,26 @@ int lya_autotune_fft(const lya_box* box, void* field, void* work, size_t work_by
   const int nv = n >= 1024 ? lya::kFftVariants : 2;
   int best[2] = {lya::fft_variant(n, 0), lya::fft_variant(n, 1)};
   for (int pass = 0; pass < 2; ++pass) {
-    double bt = 1e300;
+    double t_all[lya::kFftVariants];
     for (int v = 0; v < lya::kFftVariants; ++v) {
       double t = -1.0;
       if (v < nv) {
         e = time_ms([&] { return lya::launch_fft_strided_pass(n, pass, v, tw, static_cast<float2*>(field), st); },
                     reps, st, &t);
         if (e != hipSuccess) return ahip(e, "timing an FFT variant");
-        if (t < bt) {
-          bt = t;
-          best[pass] = v;
-        }
       }
+      t_all[v] = t;
       if (ms) ms[pass * lya::kFftVariants + v] = t;
+    }
+    // the current variant stays unless another is at least 2% faster (timing
+    // noise alone should not flip the choice from run to run)
+    const int cur = best[pass];
+    double bt = t_all[cur] * 0.98;
+    for (int v = 0; v < nv; ++v) {
+      if (t_all[v] < bt) {
+        bt = t_all[v];
+        best[pass] = v;
+      }
     }
   }
   lya::set_fft_variant(n, 0, best[0]);

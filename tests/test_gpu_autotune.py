@@ -67,7 +67,10 @@ def test_autotune_fft_keeps_results(L):
         print("autotune fft n=%d: y %d x %d; ms %s" % (n, t.fft_y, t.fft_x, ms))
         assert 0 <= t.fft_y < L.FFT_VARIANTS and 0 <= t.fft_x < L.FFT_VARIANTS
         assert all(v > 0 for row in ms for v in row)
-        assert ms[0][t.fft_y] == min(ms[0]) and ms[1][t.fft_x] == min(ms[1])
+        # the previous variant stays unless another is at least 2% faster
+        for p, c, prev in ((0, t.fft_y, saved.fft_y), (1, t.fft_x, saved.fft_x)):
+            assert ms[p][c] <= min(ms[p]) / 0.98
+            assert c == prev or ms[p][c] == min(ms[p])
         L.make_box(box, pk, 77, 1.0, True, field, work)
         torch.cuda.synchronize()
         assert torch.equal(L.box_view(field, n), ref)
