@@ -303,16 +303,15 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
     const int iy = iy0 + po;
     const int ny = sfreq(iy, N);
     const uint64_t ctr = (static_cast<uint64_t>(ix) * N + iy) * (N / 2) + m;
-    const uint4 wd = philox10(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 0u, 0u),
-                              static_cast<uint32_t>(g.seed), static_cast<uint32_t>(g.seed >> 32));
+    const uint4 wd = philox10_x3(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 0u, 0u),
+                                 static_cast<uint32_t>(g.seed), static_cast<uint32_t>(g.seed >> 32));
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int iz = 2 * m + e;
       const int nz = sfreq(iz, N);
       const int n2 = nx * nx + ny * ny + nz * nz;
       float s = stab[po * NZ + (nz < 0 ? -nz : nz)];
-      const float2 z = e ? box_muller(wd.z, wd.w) : box_muller(wd.x, wd.y);
-      float2 wv = make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
+      float2 wv = e ? box_muller_half(wd.z, wd.w) : box_muller_half(wd.x, wd.y);
       float ma, mb;
       if (GM == GEN_GENERIC) {
         if (g.only_n2 >= 0 && n2 != g.only_n2) s = 0.0f;

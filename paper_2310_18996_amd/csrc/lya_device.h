@@ -33,8 +33,30 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
+// Philox4x32-10 as above with each 3-input xor in one v_bitop3_b32 (truth
+// table 0x96): the hot synthesis loop spends most of its integer work here.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint4 philox10_x3(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * c.x;
+    const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * c.z;
+    c = make_uint4(xor3(static_cast<uint32_t>(p1 >> 32), c.y, k0), static_cast<uint32_t>(p1),
+                   xor3(static_cast<uint32_t>(p0 >> 32), c.w, k1), static_cast<uint32_t>(p0));
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  return c;
+}
+
+// ((w >> 9) + 1/2) 2^-23 exactly: one fma on the converted 23-bit integer
+// (every intermediate is exact in FP32).
 __device__ __forceinline__ float u01(uint32_t w) {
-  return (static_cast<float>(w >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
+  return __builtin_fmaf(static_cast<float>(w >> 9), 1.1920928955078125e-07f, 5.9604644775390625e-08f);
 }
 
 // Box-Muller in FP32: (z1, z2) from the word pair (wa, wb), on the hardware
@@ -45,6 +67,15 @@ __device__ __forceinline__ float u01(uint32_t w) {
 __device__ __forceinline__ float2 box_muller(uint32_t wa, uint32_t wb) {
   constexpr float kMinus2Ln2 = -1.3862943611198906f;  // -2 ln 2
   const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u01(wa)));
+  const float t = u01(wb);
+  return make_float2(r * __builtin_amdgcn_cosf(t), r * __builtin_amdgcn_sinf(t));
+}
+
+// The Box-Muller pair scaled by sqrt(1/2) (the unit complex noise of a
+// Hermitian pair), the scale folded into the radius: sqrt(-ln2 log2 u).
+__device__ __forceinline__ float2 box_muller_half(uint32_t wa, uint32_t wb) {
+  constexpr float kMinusLn2 = -0.6931471805599453f;
+  const float r = __builtin_amdgcn_sqrtf(kMinusLn2 * __builtin_amdgcn_logf(u01(wa)));
   const float t = u01(wb);
   return make_float2(r * __builtin_amdgcn_cosf(t), r * __builtin_amdgcn_sinf(t));
 }
