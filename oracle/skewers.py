@@ -25,6 +25,10 @@ Readings (paper silent or superseded):
   delta_S(j) = sum over +-m of the modes exp(2 pi i m j / N_S), first n_q
   values.  P_s(k) = amp exp(-(k/kcut)^2) (the configuration's shape; the
   paper only says "proportional to").
+* Line of sight of eta_par: draw_skewers takes eta_par from a box built for
+  the z axis (the distant-observer reading, eta_zz); draw_skewers_wide forms
+  eta_par = u_p u_q eta^{pq} at each pixel from the six components, with u
+  the skewer's own direction (a straight radial line keeps one direction).
 """
 import numpy as np
 
@@ -111,4 +115,48 @@ def draw_skewers(delta, eta, sk, seed, ps_amp=0.0, ps_kcut=1.5, dpix=0.2,
         o = int(off[q])
         dens[o:o + nq] = d
         et[o:o + nq] = v.imag
+    return dens, et
+
+
+WIDE_COMPONENTS = ("xx", "yy", "zz", "xy", "xz", "yz")
+
+
+def los_unit(step_fx):
+    """Unit vector of a straight line of sight from its fixed-point step
+    (FP64; the sign is irrelevant to eta_par, which is quadratic in u)."""
+    u = np.asarray(step_fx, dtype=np.float64)
+    return u / np.sqrt(np.sum(u * u))
+
+
+def eta_par_from_components(eta6, u):
+    """eta_par = u_p u_q eta^{pq} (section "Mock generation", after eq:eta) from
+    the six components in the order xx, yy, zz, xy, xz, yz (arrays of any
+    common shape); the off-diagonal terms appear twice in the double sum."""
+    ux, uy, uz = u
+    xx, yy, zz, xy, xz, yz = eta6
+    return (ux * ux * xx + uy * uy * yy + uz * uz * zz
+            + 2.0 * (ux * uy * xy + ux * uz * xz + uy * uz * yz))
+
+
+def draw_skewers_wide(delta, eta6, sk, seed, ps_amp=0.0, ps_kcut=1.5, dpix=0.2, fixed_amp_s=False):
+    """Pre-FGPA pixels with the wide-angle line-of-sight velocity gradient:
+    as draw_skewers, but eta_par at each pixel is u_p u_q eta^{pq} with u the
+    skewer's own direction, from the six real grids eta6 (order xx, yy, zz,
+    xy, xz, yz), each interpolated trilinearly like delta."""
+    npix = np.asarray(sk["npix"])
+    off = np.asarray(sk["offset"])
+    total = int(np.max(off + npix)) if len(npix) else 0
+    dens = np.zeros(total)
+    et = np.zeros(total)
+    for q in range(len(npix)):
+        nq = int(npix[q])
+        pos = pixel_positions(sk["origin_fx"][q], sk["step_fx"][q], nq)
+        d = trilinear(delta, pos)
+        comps = [trilinear(g, pos) for g in eta6]
+        e = eta_par_from_components(comps, los_unit(sk["step_fx"][q]))
+        if ps_amp > 0.0:
+            d = d + delta_s(seed, int(sk["id_base"]) + q, nq, dpix, ps_amp, ps_kcut, fixed_amp_s)
+        o = int(off[q])
+        dens[o:o + nq] = d
+        et[o:o + nq] = e
     return dens, et
