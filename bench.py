@@ -197,6 +197,65 @@ def precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, 
                                   flux_rel_rms=rel_flux, fbar_max_rel=fbar_rel, p1d_max_rel=p1d_rel))
 
 
+# ---------------------------------------------------------- wide-angle leg
+def wide_leg(L, torch, stream, reps=3):
+    """The wide-angle line-of-sight velocity gradient (eta_par = u_p u_q
+    eta^pq, the six components of eq:eta) on the 1024^3 box with its 200,000
+    skewers: the four packed boxes, the skewer pass over them, and the same
+    skewers through the distant-observer pass (eta_zz) for comparison."""
+    import mockinputs
+    cfg = mockinputs.config("precision")
+    n, dx, seed, f = cfg["n"], cfg["dx"], cfg["seed"], cfg["f"]
+    box = L.box_struct(n, dx)
+    pk = L.pk_struct(**cfg["pk"])
+    bwork = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fields = [torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") for _ in range(4)]
+    comps = ((L.LYA_C_XX, L.LYA_C_YY), (L.LYA_C_XY, L.LYA_C_XZ), (L.LYA_C_YZ, L.LYA_C_NONE))
+    sk = mockinputs.skewer_table(cfg)
+    keep = {k: torch.from_numpy(np.ascontiguousarray(sk[k])).cuda()
+            for k in ("origin_fx", "step_fx", "npix", "offset", "chi0")}
+    s = L.skewers_struct(len(sk["npix"]), keep["origin_fx"], keep["step_fx"], keep["npix"], keep["offset"],
+                         keep["chi0"], sk["dchi"])
+    tot = int(sk["total"])
+    dens, eta, flux, eta_z = (torch.empty(tot, dtype=torch.float32, device="cuda") for _ in range(4))
+    edges = torch.from_numpy(L.chi_of_z(cfg["z_edges"], cfg["omega_m"])).cuda()
+    fsum = torch.zeros(edges.numel() - 1, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(edges.numel() - 1, dtype=torch.int64, device="cuda")
+    zb = L.zbins_struct(edges, fsum, cnt)
+    swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    ps = L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0)
+    cosmo, fg = L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"])
+
+    def boxes():
+        L.make_box(box, pk, seed, f, True, fields[0], bwork, stream)
+        for fl, (ca, cb) in zip(fields[1:], comps):
+            L.make_eta(box, pk, seed, f, ca, cb, fl, bwork, stream)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    boxes_ms = timed(boxes)
+    wide_ms = timed(lambda: L.draw_skewers_wide(box, fields, s, ps, seed, cosmo, fg, dens, eta, flux, zb, swork,
+                                                stream))
+    plain_ms = timed(lambda: L.draw_skewers(box, fields[0], s, ps, seed, cosmo, None, None, eta_z, None, None,
+                                            swork, stream))
+    d = eta.double() - eta_z.double()
+    rel = float(torch.sqrt((d ** 2).sum() / (eta_z.double() ** 2).sum()))
+    cells = float(n) ** 3
+    return dict(workload="%d^3 box at %.2f Mpc/h, %d skewers, %d pixels; four packed FP32 boxes "
+                         "{delta, eta_zz}, {eta_xx, eta_yy}, {eta_xy, eta_xz}, {eta_yz, 0}" % (n, dx, len(sk["npix"]), tot),
+                boxes_ms=boxes_ms, box_cells_per_s=cells / (boxes_ms * 1e-3),
+                skewers_wide_ms=wide_ms, skewer_pixels_per_s=tot / (wide_ms * 1e-3),
+                skewers_distant_observer_ms=plain_ms,
+                eta_par_wide_vs_eta_zz_rel_rms=rel)
+
+
 # ---------------------------------------------------------------- tuning leg
 def stored_pixels(L, torch, cfg, seed, sk_seed):
     """Pre-FGPA pixels (delta_L + delta_S, eta_par) of a mock made by the
@@ -364,6 +423,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the tuning leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured replay")
+    ap.add_argument("--no-wide", action="store_true", help="skip the wide-angle eta_par leg")
     ap.add_argument("--tune-labels", type=int, default=100_000)
     ap.add_argument("--tune-steps", type=int, default=20_000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -517,9 +577,16 @@ def main():
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
     else:
         out["cpu_baseline"] = None
-    if not args.no_tune:
+    if not args.no_tune or not args.no_wide:
         del field, bwork, swork, dens, eta, flux, dev
         torch.cuda.empty_cache()
+    if not args.no_wide:
+        print("bench: wide-angle leg", file=sys.stderr, flush=True)
+        out["wide_angle"] = wide_leg(L, torch, stream)
+        torch.cuda.empty_cache()
+    else:
+        out["wide_angle"] = None
+    if not args.no_tune:
         print("bench: tuning leg", file=sys.stderr, flush=True)
         out["tune"] = tune_leg(L, torch, args.tune_labels, args.tune_steps)
     else:

@@ -149,6 +149,25 @@ int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* s
                      uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
                      float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream);
 
+/* Wide-angle line-of-sight velocity gradient (section "Mock generation": the
+ * six boxes of eq:eta and eta_par = u_p u_q eta^pq).  As lya_draw_skewers, but
+ * eta_par at each pixel is
+ *   u_x^2 eta_xx + u_y^2 eta_yy + u_z^2 eta_zz
+ *     + 2 (u_x u_y eta_xy + u_x u_z eta_xz + u_y u_z eta_yz),
+ * u = step/|step| the skewer's own direction (a straight radial line keeps
+ * one), formed at the eight corner voxels and interpolated trilinearly like
+ * delta.  fields[4] (host array of device pointers), four boxes of the same
+ * lya_box made from the same pk, seed and f:
+ *   fields[0]  lya_make_box(with_eta = 1)           {delta, eta_zz}
+ *   fields[1]  lya_make_eta(LYA_C_XX, LYA_C_YY)     {eta_xx, eta_yy}
+ *   fields[2]  lya_make_eta(LYA_C_XY, LYA_C_XZ)     {eta_xy, eta_xz}
+ *   fields[3]  lya_make_eta(LYA_C_YZ, LYA_C_NONE)   {eta_yz, 0}
+ * Everything else (delta_S, FGPA, bins, outputs, workspace, errors) is as for
+ * lya_draw_skewers; a NULL entry in fields is LYA_EINVAL. */
+int lya_draw_skewers_wide(const lya_box* box, const void* const* fields, const lya_skewers* sk, const lya_ps1d* ps,
+                          uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                          float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream);
+
 /* FGPA on stored pre-FGPA pixels (eq:FGPA; the paper's post-production step):
  * flux = exp(-a(z) exp(b(z) (dens + c(z) eta))), z the redshift of chi_j.
  * Geometry fields of sk other than npix, offset, chi0 and dchi are unused.
@@ -355,8 +374,9 @@ int lya_autotune_skewers(const lya_box* box, const void* field, const lya_skewer
 
 /* HIP-graph capture of a sequence of library calls on one stream:
  * lya_graph_begin(stream), then the calls (lya_make_box, lya_make_eta,
- * lya_draw_skewers, lya_apply_fgpa, lya_p1d: none of them synchronises the
- * host or records memset nodes; kernel timing must be off), then
+ * lya_draw_skewers, lya_draw_skewers_wide, lya_apply_fgpa, lya_p1d: none of
+ * them synchronises the host or records memset nodes; kernel timing must be
+ * off), then
  * lya_graph_end(stream, &g) instantiates the graph; lya_graph_launch replays
  * it with the same pointers and arguments; lya_graph_destroy frees it (host
  * memory only). */

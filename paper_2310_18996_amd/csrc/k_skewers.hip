@@ -11,6 +11,9 @@
 //     inverse DFT, computed as one complex inverse FFT of length N_S/2 whose
 //     output holds the even pixels in its real part and the odd pixels in
 //     its imaginary part;
+//   * wide-angle variant: eta_par = u_p u_q eta^pq at each corner voxel from
+//     four packed boxes ({delta, eta_zz}, {eta_xx, eta_yy}, {eta_xy, eta_xz},
+//     {eta_yz, 0}), u the skewer's direction, then interpolated like delta;
 //   * g = delta_L + delta_S + c(z) eta_par, F = exp(-a(z) exp(b(z) g)), with
 //     a, b, c quadratics in (1+z) and z the unperturbed redshift of
 //     chi_j = chi0 - j*dchi (section "FGPA");
@@ -51,6 +54,11 @@ __global__ void __launch_bounds__(256) k_skewer_finalize(int n_bins, const unsig
 __device__ __forceinline__ float2 ld_field(const SkewerArgs& a, size_t i) {
   if (a.field) return a.field[i];
   return unpack_bf16x2(a.field_bf16[i]);
+}
+
+__device__ __forceinline__ float2 ld_wide(const SkewerArgs& a, int k, size_t i) {
+  if (a.field) return a.wide[k][i];
+  return unpack_bf16x2(a.wide_bf16[k][i]);
 }
 
 // Mode Y_m of the small-scale spectrum (0 < m <= ns/2).
@@ -113,7 +121,7 @@ __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c00
   return c0 + tx * (c1 - c0);
 }
 
-template <int U>
+template <int U, bool WIDE>
 __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
   __shared__ float2 sbuf[kSkWaves][kHalfBuf];
   __shared__ int sjb[kSkWaves][kMaxZBins + 1];
@@ -161,6 +169,19 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
         sy = a.step_fx[3 * q + 1];
         sz = a.step_fx[3 * q + 2];
       }
+      // wide-angle weights u_p u_q (off-diagonal ones doubled), u = step/|step|
+      float wxx = 0.0f, wyy = 0.0f, wzz = 0.0f, wxy = 0.0f, wxz = 0.0f, wyz = 0.0f;
+      if (WIDE) {
+        const double ux = static_cast<double>(sx), uy = static_cast<double>(sy), uz = static_cast<double>(sz);
+        const double r2 = ux * ux + uy * uy + uz * uz;
+        const double ir2 = r2 > 0.0 ? 1.0 / r2 : 0.0;
+        wxx = static_cast<float>(ux * ux * ir2);
+        wyy = static_cast<float>(uy * uy * ir2);
+        wzz = static_cast<float>(uz * uz * ir2);
+        wxy = static_cast<float>(2.0 * ux * uy * ir2);
+        wxz = static_cast<float>(2.0 * ux * uz * ir2);
+        wyz = static_cast<float>(2.0 * uy * uz * ir2);
+      }
       // pixel j is in bin b when jb[b+1] <= j < jb[b]; each lane walks j upward
       // and therefore the bins downward, accumulating one bin at a time.  U
       // pixels per lane per step: all their gathers are issued before any is used.
@@ -188,14 +209,27 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
             const size_t r01 = ix * NN + static_cast<size_t>(jy) * N;
             const size_t r10 = jx * NN + static_cast<size_t>(iy) * N;
             const size_t r11 = jx * NN + static_cast<size_t>(jy) * N;
-            c[u][0] = ld_field(a, r00 + iz);
-            c[u][1] = ld_field(a, r00 + jz);
-            c[u][2] = ld_field(a, r01 + iz);
-            c[u][3] = ld_field(a, r01 + jz);
-            c[u][4] = ld_field(a, r10 + iz);
-            c[u][5] = ld_field(a, r10 + jz);
-            c[u][6] = ld_field(a, r11 + iz);
-            c[u][7] = ld_field(a, r11 + jz);
+            const size_t ci[8] = {r00 + iz, r00 + jz, r01 + iz, r01 + jz, r10 + iz, r10 + jz, r11 + iz, r11 + jz};
+            if (WIDE) {
+              // all 32 gathers first, then eta_par = u_p u_q eta^pq per corner
+              float2 w0[8], w1[8], w2[8], w3[8];
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                w0[k] = ld_field(a, ci[k]);
+                w1[k] = ld_wide(a, 0, ci[k]);
+                w2[k] = ld_wide(a, 1, ci[k]);
+                w3[k] = ld_wide(a, 2, ci[k]);
+              }
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const float e = wzz * w0[k].y + wxx * w1[k].x + wyy * w1[k].y + wxy * w2[k].x + wxz * w2[k].y +
+                                wyz * w3[k].x;
+                c[u][k] = make_float2(w0[k].x, e);
+              }
+            } else {
+#pragma unroll
+              for (int k = 0; k < 8; ++k) c[u][k] = ld_field(a, ci[k]);
+            }
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
@@ -299,15 +333,23 @@ hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st) {
   if (blocks * kSkWaves > nchunks) blocks = (nchunks + kSkWaves - 1) / kSkWaves;
   if (blocks < 1) blocks = 1;
   const int u = a.unroll == 1 || a.unroll == 4 ? a.unroll : 2;
-  if (u == 1)
+  const dim3 grid(static_cast<unsigned>(blocks));
+  if (a.is_wide) {
+    // four boxes per pixel: at most two pixels per lane in flight
+    if (u == 1)
+      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<1, true>), grid, dim3(kSkNT), 0, st, a));
+    else
+      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<2, true>), grid, dim3(kSkNT), 0, st, a));
+  } else if (u == 1) {
     LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL(k_skewers<1>, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));
-  else if (u == 2)
+              hipLaunchKernelGGL((k_skewers<1, false>), grid, dim3(kSkNT), 0, st, a));
+  } else if (u == 2) {
     LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL(k_skewers<2>, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));
-  else
+              hipLaunchKernelGGL((k_skewers<2, false>), grid, dim3(kSkNT), 0, st, a));
+  } else {
     LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL(k_skewers<4>, dim3(static_cast<unsigned>(blocks)), dim3(kSkNT), 0, st, a));
+              hipLaunchKernelGGL((k_skewers<4, false>), grid, dim3(kSkNT), 0, st, a));
+  }
   if (a.n_bins > 0 && a.do_flux)
     LYA_TIMED("skewer_finalize", st,
               hipLaunchKernelGGL(k_skewer_finalize, dim3(1), dim3(256), 0, st, a.n_bins, a.bin_sum, a.bin_cnt,

@@ -388,6 +388,48 @@ int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* s
   return run_skewers(a, cosmo, fgpa ? zb : nullptr, work, work_bytes, stream);
 }
 
+int lya_draw_skewers_wide(const lya_box* box, const void* const* fields, const lya_skewers* sk, const lya_ps1d* ps,
+                          uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                          float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_box(box);
+  if (rc) return rc;
+  if (!fields || !fields[0] || !fields[1] || !fields[2] || !fields[3])
+    return fail(LYA_EINVAL, "fields must hold four non-NULL boxes%s");
+  if ((rc = check_skewers(sk, true))) return rc;
+  if ((rc = check_zbins(zb))) return rc;
+  if (ps && ps->amp > 0.0 && (!(ps->kcut > 0.0) || !(ps->dpix > 0.0)))
+    return fail(LYA_EINVAL, "invalid small-scale spectrum%s");
+  lya::SkewerArgs a{};
+  a.n_sk = sk->n_sk;
+  a.origin_fx = sk->origin_fx;
+  a.step_fx = sk->step_fx;
+  a.npix = sk->npix;
+  a.offset = sk->offset;
+  a.chi0 = sk->chi0;
+  a.dchi = sk->dchi;
+  a.id_base = sk->id_base;
+  a.n = box->n;
+  const bool f32 = box->storage == LYA_F32;
+  a.field = f32 ? static_cast<const float2*>(fields[0]) : nullptr;
+  a.field_bf16 = f32 ? nullptr : static_cast<const uint32_t*>(fields[0]);
+  for (int k = 0; k < 3; ++k) {
+    a.wide[k] = f32 ? static_cast<const float2*>(fields[k + 1]) : nullptr;
+    a.wide_bf16[k] = f32 ? nullptr : static_cast<const uint32_t*>(fields[k + 1]);
+  }
+  a.is_wide = true;
+  a.ps_amp = ps ? ps->amp : 0.0;
+  a.ps_kcut = ps ? ps->kcut : 1.0;
+  a.dpix = ps ? ps->dpix : 1.0;
+  a.ps_fixed_amp = ps ? ps->fixed_amp : 0;
+  a.seed = seed;
+  fill_fgpa(a, fgpa);
+  a.dens = dens;
+  a.eta = eta;
+  a.flux = fgpa ? flux : nullptr;
+  return run_skewers(a, cosmo, fgpa ? zb : nullptr, work, work_bytes, stream);
+}
+
 int lya_apply_fgpa(const lya_skewers* sk, const lya_cosmo* cosmo, const float* dens, const float* eta,
                    const lya_fgpa* fgpa, float* flux, const lya_zbins* zb, void* work, size_t work_bytes,
                    void* stream) {

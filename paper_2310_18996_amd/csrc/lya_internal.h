@@ -96,6 +96,11 @@ struct SkewerArgs {
   int n;
   const float2* field;         // FP32 {delta, eta} or null
   const uint32_t* field_bf16;  // BF16 {delta, eta} or null
+  // wide-angle eta_par (all null: eta_par is the box's second component): the
+  // boxes {eta_xx, eta_yy}, {eta_xy, eta_xz}, {eta_yz, 0} in the box's storage
+  const float2* wide[3];
+  const uint32_t* wide_bf16[3];
+  bool is_wide;
   // small-scale field
   double ps_amp, ps_kcut, dpix;
   int ps_fixed_amp;

@@ -14,10 +14,12 @@ LIB_PATH = os.path.join(HERE, "liblyamock.so")
 LYA_OK, LYA_EINVAL, LYA_EWORKSPACE, LYA_EUNSUPPORTED, LYA_EHIP = 0, -1, -2, -3, -4
 LYA_F32, LYA_BF16 = 0, 1
 LYA_OP_BOX, LYA_OP_SKEWERS = 0, 1
+LYA_C_NONE, LYA_C_DELTA, LYA_C_XX, LYA_C_YY, LYA_C_ZZ, LYA_C_XY, LYA_C_XZ, LYA_C_YZ = -1, 0, 1, 2, 3, 4, 5, 6
 COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6}
 
 EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta",
-           "lya_draw_skewers", "lya_apply_fgpa", "lya_p1d_workspace_size", "lya_p1d", "lya_tune_workspace_size",
+           "lya_draw_skewers", "lya_draw_skewers_wide", "lya_apply_fgpa", "lya_p1d_workspace_size", "lya_p1d",
+           "lya_tune_workspace_size",
            "lya_tune_params", "lya_emulator_labels", "lya_emulator_bytes", "lya_emulator_param_offset",
            "lya_emulator_param_count", "lya_emulator_init", "lya_emulator_train_workspace_size",
            "lya_emulator_set_scaling", "lya_emulator_loss_grad", "lya_emulator_train", "lya_emulator_predict",
@@ -94,6 +96,9 @@ def load():
     lib.lya_draw_skewers.restype = ctypes.c_int
     lib.lya_draw_skewers.argtypes = [P(Box), VP, P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo), P(Fgpa),
                                      VP, VP, VP, P(ZBins), VP, ctypes.c_size_t, VP]
+    lib.lya_draw_skewers_wide.restype = ctypes.c_int
+    lib.lya_draw_skewers_wide.argtypes = [P(Box), P(VP), P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo),
+                                          P(Fgpa), VP, VP, VP, P(ZBins), VP, ctypes.c_size_t, VP]
     lib.lya_apply_fgpa.restype = ctypes.c_int
     lib.lya_apply_fgpa.argtypes = [P(Skewers), P(Cosmo), VP, VP, P(Fgpa), VP, P(ZBins), VP, ctypes.c_size_t, VP]
     lib.lya_timing_enable.restype = ctypes.c_int
@@ -198,6 +203,21 @@ def draw_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, 
                                    _ptr(dens), _ptr(eta), _ptr(flux),
                                    ctypes.byref(zbins) if zbins is not None else None,
                                    _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def draw_skewers_wide(box, fields, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, work, stream=None):
+    """lya_draw_skewers_wide (see include/lyamock.h): fields = the four boxes
+    {delta, eta_zz}, {eta_xx, eta_yy}, {eta_xy, eta_xz}, {eta_yz, 0}."""
+    if len(fields) != 4:
+        raise ValueError("fields must hold four boxes")
+    arr = (ctypes.c_void_p * 4)(*[_ptr(f) for f in fields])
+    _check(load().lya_draw_skewers_wide(ctypes.byref(box), arr, ctypes.byref(sk),
+                                        ctypes.byref(ps) if ps is not None else None, int(seed),
+                                        ctypes.byref(cosmo) if cosmo is not None else None,
+                                        ctypes.byref(fgpa) if fgpa is not None else None,
+                                        _ptr(dens), _ptr(eta), _ptr(flux),
+                                        ctypes.byref(zbins) if zbins is not None else None,
+                                        _ptr(work), work.numel() * work.element_size(), _stream(stream)))
 
 
 def apply_fgpa(sk, cosmo, dens, eta, fgpa, flux, zbins, work, stream=None):

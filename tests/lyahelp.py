@@ -98,7 +98,10 @@ def gpu_skewers(L, field, n, dx, sk, seed, ps_amp, ps_kcut, dpix, coef=None, chi
     work = torch.empty(ws, dtype=torch.uint8, device="cuda")
     ps = L.Ps1d(float(ps_amp), float(ps_kcut), float(dpix), int(bool(ps_fixed)))
     fg = L.fgpa_struct(coef) if coef is not None else None
-    L.draw_skewers(box, field, s, ps, seed, L.Cosmo(omega_m), fg, dens, eta, flux, zb, work)
+    if isinstance(field, (list, tuple)):   # the four boxes of the wide-angle eta_par
+        L.draw_skewers_wide(box, field, s, ps, seed, L.Cosmo(omega_m), fg, dens, eta, flux, zb, work)
+    else:
+        L.draw_skewers(box, field, s, ps, seed, L.Cosmo(omega_m), fg, dens, eta, flux, zb, work)
     torch.cuda.synchronize()
     out = {}
     for k, v in (("dens", dens), ("eta", eta), ("flux", flux), ("fsum", fsum), ("count", cnt)):

@@ -276,3 +276,71 @@ def test_precision_fp32_and_bf16_storage(L):
     assert b["fbar_max_rel"] < 1e-3 and b["p1d_max_rel"] < 5e-2, b
     del f32, f16
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_wide_angle_on_the_precision_box(L):
+    """eta_par = u_p u_q eta^pq at 1024^3: four FP32 boxes against C-oracle
+    voxel columns of all seven components, on the eight few-column skewers."""
+    import torch
+    cfg = mockinputs.config("precision")
+    n, dx, seed, f = cfg["n"], cfg["dx"], cfg["seed"], cfg["f"]
+    print("1024^3 wide-angle: four boxes", flush=True)
+    box = L.box_struct(n, dx, L.LYA_F32)
+    pk = L.pk_struct(**cfg["pk"])
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fields = [torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") for _ in range(4)]
+    L.make_box(box, pk, seed, f, True, fields[0], work)
+    for fl, (ca, cb) in zip(fields[1:], ((L.LYA_C_XX, L.LYA_C_YY), (L.LYA_C_XY, L.LYA_C_XZ),
+                                         (L.LYA_C_YZ, L.LYA_C_NONE))):
+        L.make_eta(box, pk, seed, f, ca, cb, fl, work)
+    torch.cuda.synchronize()
+    del work
+    sk_all = mockinputs.skewer_table(cfg)
+    sk = subset(sk_all, few_column_skewers(sk_all))
+    cols = skewer_columns(sk, n)
+    tab = oracle_table(cfg["pk"], n, dx)
+    grids = []
+    for comps in (("delta", "zz"), ("xx", "yy"), ("xy", "xz"), ("yz",)):
+        print("C oracle %s: %d columns" % ("+".join(comps), len(cols)), flush=True)
+        re, im = lines.field_lines(n, seed, tab, cols, comps=comps, f=f)
+        grids.append(LineGrid(n, cols, re, im))
+
+    class Part:
+        def __init__(self, g, imag):
+            self.g, self.imag, self.shape = g, imag, g.shape
+
+        def __getitem__(self, idx):
+            v = self.g[idx]
+            return v.imag if self.imag else v.real
+
+    delta = Part(grids[0], False)
+    eta6 = [Part(grids[1], False), Part(grids[1], True), Part(grids[0], True), Part(grids[2], False),
+            Part(grids[2], True), Part(grids[3], False)]
+    rd, re_ = skewers.draw_skewers_wide(delta, eta6, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"])
+    rf, _ = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
+    edges = fgpa.chi_edges_for_z(cfg["z_edges"])
+    s, keep = skewer_tensors(L, sk)
+    tot = sk["total"]
+    d, e, fl = (torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(3))
+    ed = torch.from_numpy(edges).cuda()
+    fs = torch.zeros(len(edges) - 1, dtype=torch.float64, device="cuda")
+    cn = torch.zeros(len(edges) - 1, dtype=torch.int64, device="cuda")
+    sw = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    L.draw_skewers_wide(box, fields, s, L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0), seed,
+                        L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"]), d, e, fl, L.zbins_struct(ed, fs, cn), sw)
+    torch.cuda.synchronize()
+    out = dict(dens=d.cpu().numpy(), eta=e.cpu().numpy(), flux=fl.cpu().numpy())
+    err = {k: rel_rms(out[k], r) for k, r in (("dens", rd), ("eta", re_), ("flux", rf))}
+    # how far the wide-angle eta_par sits from the distant-observer eta_zz on these skewers
+    ez = np.concatenate([skewers.trilinear(eta6[2], skewers.pixel_positions(sk["origin_fx"][q], sk["step_fx"][q],
+                                                                             int(sk["npix"][q])))
+                         for q in range(len(sk["npix"]))])
+    print("wide 1024^3 (%d pixels): rel rms %s; eta_par vs eta_zz %.2e" % (
+        tot, {k: "%.2e" % v for k, v in err.items()}, rel_rms(re_, ez)), flush=True)
+    assert max(err.values()) < TOL, err
+    fsr, cnr = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
+    np.testing.assert_array_equal(cn.cpu().numpy(), cnr)
+    assert bin_sums_close(fs.cpu().numpy(), fsr, cnr)
+    del fields
+    torch.cuda.empty_cache()

@@ -1,0 +1,109 @@
+"""GPU parity of lya_draw_skewers_wide (eta_par = u_p u_q eta^pq from the six
+components, section "Mock generation") against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import mockinputs
+from oracle import fgpa, field, skewers
+from tests.lyahelp import gpu_box, gpu_skewers, oracle_table, rel_rms
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+T32 = 2 ** 32
+PAIRS = (("delta", "zz"), ("xx", "yy"), ("xy", "xz"), ("yz",))
+GPU_PAIRS = (None, (1, 2), (4, 5), (6, -1))
+
+
+@pytest.fixture(scope="module")
+def L():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_18996_amd import lyamock
+    lyamock.load()
+    return lyamock
+
+
+def iso_table(n, dx, S, seed, dpix=0.2, max_pix=300):
+    """S skewers with isotropic directions (the three axes among them),
+    random origins and lengths 1..max_pix."""
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=(S, 3))
+    u[:3] = np.eye(3)
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    npix = rng.integers(1, max_pix + 1, S).astype(np.int32)
+    npix[:3] = max_pix
+    off = np.zeros(S, np.int64)
+    off[1:] = np.cumsum(npix[:-1])
+    return dict(origin_fx=rng.integers(0, n * T32, (S, 3)).astype(np.int64),
+                step_fx=np.round(u * (dpix / dx) * T32).astype(np.int64), npix=npix, offset=off,
+                chi0=rng.uniform(3500.0, 4700.0, S), dchi=dpix, id_base=5, total=int(npix.sum()))
+
+
+@pytest.fixture(scope="module")
+def boxes(L):
+    cfg = mockinputs.config("tiny")
+    n, dx, seed, f = cfg["n"], cfg["dx"], cfg["seed"], 0.9
+    tab = oracle_table(cfg["pk"], n, dx)
+    ref = [field.make_box(n, seed, tab, c, f=f) for c in PAIRS]
+    delta = ref[0].real
+    eta6 = [ref[1].real, ref[1].imag, ref[0].imag, ref[2].real, ref[2].imag, ref[3].real]
+    gpu = {}
+    for storage in (0, 1):
+        gpu[storage] = [gpu_box(L, n, dx, seed, f, storage=storage, comps=c, **cfg["pk"]) for c in GPU_PAIRS]
+    return cfg, delta, eta6, gpu
+
+
+@pytest.mark.parametrize("which", ["table", "isotropic"])
+def test_wide_pipeline_matches_oracle(L, boxes, which):
+    cfg, delta, eta6, gpu = boxes
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    sk = mockinputs.skewer_table(cfg) if which == "table" else iso_table(n, dx, 400, 17)
+    print("wide-angle skewers (%s): %d skewers, %d pixels" % (which, len(sk["npix"]), sk["total"]), flush=True)
+    edges = fgpa.chi_edges_for_z(cfg["z_edges"])
+    out = gpu_skewers(L, gpu[0], n, dx, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], cfg["fgpa"], edges)
+    rd, re_ = skewers.draw_skewers_wide(delta, eta6, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"])
+    rf, _ = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
+    e = dict(dens=rel_rms(out["dens"], rd), eta=rel_rms(out["eta"], re_), flux=rel_rms(out["flux"], rf))
+    print("wide rel rms", {k: "%.2e" % v for k, v in e.items()}, flush=True)
+    assert all(v < TOL for v in e.values()), e
+    fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
+    np.testing.assert_array_equal(out["count"], cnt)
+    assert np.all(np.abs(out["fsum"] - fs) <= 1e-5 * np.abs(fs) + cnt * 2.0 ** -32)
+
+
+def test_wide_differs_from_the_distant_observer_where_it_should(L, boxes):
+    # along an axis the wide-angle eta_par is that axis' diagonal component;
+    # off axis it differs from eta_zz (checked against the oracle, not the GPU)
+    cfg, delta, eta6, gpu = boxes
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    sk = iso_table(n, dx, 3, 23)     # exactly the x, y and z axes
+    out = gpu_skewers(L, gpu[0], n, dx, sk, seed, 0.0, 1.5, 0.2, None, want=("eta",))
+    for q, comp in enumerate((0, 1, 2)):
+        o, m = int(sk["offset"][q]), int(sk["npix"][q])
+        pos = skewers.pixel_positions(sk["origin_fx"][q], sk["step_fx"][q], m)
+        ref = skewers.trilinear(eta6[comp], pos)
+        assert rel_rms(out["eta"][o:o + m], ref) < TOL, q
+
+
+def test_wide_bf16_storage(L, boxes):
+    cfg, delta, eta6, gpu = boxes
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    sk = iso_table(n, dx, 200, 29)
+    out = gpu_skewers(L, gpu[1], n, dx, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], cfg["fgpa"],
+                      storage=1)
+    rd, re_ = skewers.draw_skewers_wide(delta, eta6, sk, seed, cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"])
+    rf, _ = fgpa.apply_fgpa(rd, re_, sk, cfg["fgpa"])
+    e = dict(dens=rel_rms(out["dens"], rd), eta=rel_rms(out["eta"], re_), flux=rel_rms(out["flux"], rf))
+    print("wide bf16 rel rms", {k: "%.2e" % v for k, v in e.items()}, flush=True)
+    assert all(v < 1e-2 for v in e.values()), e
+
+
+def test_wide_rejects_missing_boxes(L, boxes):
+    cfg, delta, eta6, gpu = boxes
+    n, dx = cfg["n"], cfg["dx"]
+    sk = iso_table(n, dx, 4, 31)
+    with pytest.raises(L.LyaError):
+        gpu_skewers(L, [gpu[0][0], gpu[0][1], None, gpu[0][3]], n, dx, sk, 1, 0.0, 1.5, 0.2, None, want=("eta",))
+    with pytest.raises(ValueError):
+        gpu_skewers(L, gpu[0][:3], n, dx, sk, 1, 0.0, 1.5, 0.2, None, want=("eta",))
