@@ -12,7 +12,9 @@ Follows section "Gaussian fields along lines of sight":
 Readings (paper silent or superseded):
 
 * Interpolation: periodic trilinear interpolation of the grid values (grid
-  point m at x = m dx) replaces the paper's 7^3 Gaussian-kernel average.
+  point m at x = m dx) replaces the paper's 7^3 Gaussian-kernel average on
+  the hot path; gauss7 is that average (draw_skewers(interp=gauss7)), with
+  the pixel's voxel read as its nearest grid point.
 * Geometry: pixel j of a skewer sits at the fixed-point position
   p_j = origin + j step (integers, cell units times 2^32); the voxel index is
   floor(p_j / 2^32) mod N per axis, and the fractional offset is
@@ -69,6 +71,39 @@ def trilinear(grid, pos_fx):
     return out
 
 
+def gauss7(grid, pos_fx, sigma=1.0, reach=3):
+    """Gaussian-kernel average of grid [N,N,N] (real or complex) at fixed-point
+    positions pos_fx [..., 3] (section "Gaussian fields along lines of
+    sight": standard deviation one voxel side, three voxels each way of the
+    pixel's voxel, 7^3 = 343 voxels).  Reading: the pixel's voxel is its
+    nearest grid point c = floor(u + 1/2) per axis (u in cell units); voxel
+    c + o, o in [-reach, reach]^3, periodic, weighs exp(-|c + o - u|^2 /
+    (2 sigma^2)); the average divides by the sum of the 343 weights."""
+    n = grid.shape[0]
+    pos = np.asarray(pos_fx, dtype=np.int64)
+    cell = pos >> 32
+    frac = (pos & (TWO32 - 1)).astype(np.float64) / TWO32
+    up = frac >= 0.5                       # nearest grid point
+    c = cell + up
+    t = frac - up                          # u - c, in [-1/2, 1/2)
+    num = 0.0
+    den = 0.0
+    rng = range(-reach, reach + 1)
+    for ox in rng:
+        wx = np.exp(-((ox - t[..., 0]) ** 2) / (2.0 * sigma ** 2))
+        ix = (c[..., 0] + ox) % n
+        for oy in rng:
+            wy = np.exp(-((oy - t[..., 1]) ** 2) / (2.0 * sigma ** 2))
+            iy = (c[..., 1] + oy) % n
+            for oz in rng:
+                wz = np.exp(-((oz - t[..., 2]) ** 2) / (2.0 * sigma ** 2))
+                iz = (c[..., 2] + oz) % n
+                w = wx * wy * wz
+                num = num + w * grid[ix, iy, iz]
+                den = den + w
+    return num / den
+
+
 def ps_gauss(k, amp, kcut):
     return amp * np.exp(-(np.asarray(k) / kcut) ** 2)
 
@@ -92,7 +127,7 @@ def delta_s(seed, qid, npix, dpix, amp, kcut, fixed_amp=False):
 
 
 def draw_skewers(delta, eta, sk, seed, ps_amp=0.0, ps_kcut=1.5, dpix=0.2,
-                 fixed_amp_s=False):
+                 fixed_amp_s=False, interp=None):
     """Pre-FGPA pixels of every skewer.
 
     delta, eta: real grids [N,N,N] (FP64).  sk: dict with origin_fx [S,3],
@@ -107,7 +142,7 @@ def draw_skewers(delta, eta, sk, seed, ps_amp=0.0, ps_kcut=1.5, dpix=0.2,
     for q in range(len(npix)):
         nq = int(npix[q])
         pos = pixel_positions(sk["origin_fx"][q], sk["step_fx"][q], nq)
-        v = trilinear(grid, pos)
+        v = (interp or trilinear)(grid, pos)
         d = v.real.copy()
         if ps_amp > 0.0:
             d += delta_s(seed, int(sk["id_base"]) + q, nq, dpix, ps_amp,
