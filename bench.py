@@ -424,6 +424,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured replay")
     ap.add_argument("--no-wide", action="store_true", help="skip the wide-angle eta_par leg")
+    ap.add_argument("--no-gauss", action="store_true", help="skip the 7^3 Gaussian-kernel skewer pass")
     ap.add_argument("--tune-labels", type=int, default=100_000)
     ap.add_argument("--tune-steps", type=int, default=20_000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -534,6 +535,19 @@ def main():
         torch.cuda.synchronize()
         graph = dict(ms_per_step=(time.perf_counter() - t2) * 1e3 / args.steps, matches_eager=same)
         g.close()
+    gauss = None
+    if not args.no_gauss:
+        # the paper's 7^3 Gaussian-kernel average in place of trilinear, on the
+        # same box and skewers (outputs overwritten; not part of the step)
+        L.draw_skewers_gauss(box, field, s, ps, seed, cosmo, fg, dens, eta, flux, zb, swork, stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(2):
+            L.draw_skewers_gauss(box, field, s, ps, seed, cosmo, fg, dens, eta, flux, zb, swork, stream)
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - t2) * 1e3 / 2
+        gauss = dict(what="lya_draw_skewers_gauss: 7^3 Gaussian-kernel average (343 voxels per pixel) with "
+                          "delta_S, FGPA and bins, same box and skewers", ms=gms, pixels_per_s=pixels / (gms * 1e-3))
     box_names = ("pk_sigma8", "pk_finalize", "pk_table", "fft_z_gen", "fft_y", "fft_x")
     sk_names = ("zchi_table", "twiddles", "skewer_reset", "skewers", "skewer_finalize")
     box_ms = sum(kt[k][0] for k in box_names if k in kt) / args.steps
@@ -562,7 +576,7 @@ def main():
                box_cells_per_s=cells / (box_ms * 1e-3), box_ms=box_ms,
                skewer_pixels_per_s=pixels / (sk_ms * 1e-3), skewer_ms=sk_ms,
                distinct_voxels_per_pixel=vox_per_pix, roofline=roof, kernels=kernels, autotune=autotune,
-               graph=graph, host=host_facts(),
+               graph=graph, gauss_interpolation=gauss, host=host_facts(),
                paper_context="the paper's make_box runs about 8.0e5 box cells/s per 64-thread CPU node "
                              "(13 fields of a 2560x2560x1536 chunk, FFTW); other hardware and workload, "
                              "so vs_baseline is null")

@@ -149,6 +149,17 @@ int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* s
                      uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
                      float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream);
 
+/* The paper's interpolation (section "Gaussian fields along lines of sight"):
+ * as lya_draw_skewers, but delta_L and eta_par at a pixel are the Gaussian-
+ * kernel average of the 7^3 voxels around it, standard deviation one voxel
+ * side: with u the pixel position in cell units and c = floor(u + 1/2) its
+ * nearest grid point (per axis), voxel c + o, o in [-3, 3]^3 (periodic),
+ * weighs exp(-|c + o - u|^2 / 2), and the average divides by the sum of the
+ * 343 weights.  Same arguments, outputs and errors as lya_draw_skewers. */
+int lya_draw_skewers_gauss(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                           uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                           float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream);
+
 /* Wide-angle line-of-sight velocity gradient (section "Mock generation": the
  * six boxes of eq:eta and eta_par = u_p u_q eta^pq).  As lya_draw_skewers, but
  * eta_par at each pixel is
@@ -374,7 +385,8 @@ int lya_autotune_skewers(const lya_box* box, const void* field, const lya_skewer
 
 /* HIP-graph capture of a sequence of library calls on one stream:
  * lya_graph_begin(stream), then the calls (lya_make_box, lya_make_eta,
- * lya_draw_skewers, lya_draw_skewers_wide, lya_apply_fgpa, lya_p1d: none of
+ * lya_draw_skewers, lya_draw_skewers_gauss, lya_draw_skewers_wide,
+ * lya_apply_fgpa, lya_p1d: none of
  * them synchronises the host or records memset nodes; kernel timing must be
  * off), then
  * lya_graph_end(stream, &g) instantiates the graph; lya_graph_launch replays

@@ -14,6 +14,8 @@
 //   * wide-angle variant: eta_par = u_p u_q eta^pq at each corner voxel from
 //     four packed boxes ({delta, eta_zz}, {eta_xx, eta_yy}, {eta_xy, eta_xz},
 //     {eta_yz, 0}), u the skewer's direction, then interpolated like delta;
+//   * Gaussian-kernel variant: the paper's average over the 7^3 voxels around
+//     the pixel (standard deviation one voxel) in place of trilinear;
 //   * g = delta_L + delta_S + c(z) eta_par, F = exp(-a(z) exp(b(z) g)), with
 //     a, b, c quadratics in (1+z) and z the unperturbed redshift of
 //     chi_j = chi0 - j*dchi (section "FGPA");
@@ -110,6 +112,58 @@ __device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, floa
   wave_ifft(buf, M, tw, lane);
 }
 
+// Interpolation modes of the skewer kernel.
+enum { kSkTri = 0, kSkWide = 1, kSkGauss = 2 };
+
+// Gaussian-kernel average over the 7^3 voxels around the pixel's nearest grid
+// point c (standard deviation one voxel, section "Gaussian fields along lines
+// of sight"): the weights separate into 7 per axis, exp(-(o - t)^2/2) with
+// t = u - c in [-1/2, 1/2), and the average divides by their product sum.
+// Each z run of 7 voxels is contiguous in memory.
+__device__ __forceinline__ void gauss7_at(const SkewerArgs& a, int64_t px, int64_t py, int64_t pz, int N, size_t NN,
+                                          float& d, float& e) {
+  float g[3][7], s[3];
+  int c[3];
+  const int64_t p3[3] = {px, py, pz};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const uint32_t fr = static_cast<uint32_t>(p3[ax]);
+    const int up = static_cast<int>(fr >> 31);
+    c[ax] = static_cast<int>(((p3[ax] >> 32) + up) & (N - 1));
+    const float t = static_cast<float>(fr) * 2.3283064365386963e-10f - static_cast<float>(up);
+    s[ax] = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+      const float dd = static_cast<float>(o - 3) - t;
+      g[ax][o] = __expf(-0.5f * dd * dd);
+      s[ax] += g[ax][o];
+    }
+  }
+  float ax_ = 0.0f, ay_ = 0.0f;
+  for (int i = 0; i < 7; ++i) {
+    const size_t rx = static_cast<size_t>((c[0] + i - 3) & (N - 1)) * NN;
+    float bx = 0.0f, by = 0.0f;
+#pragma unroll
+    for (int jy = 0; jy < 7; ++jy) {
+      const size_t row = rx + static_cast<size_t>((c[1] + jy - 3) & (N - 1)) * N;
+      float rx_ = 0.0f, ry_ = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const float2 f = ld_field(a, row + ((c[2] + k - 3) & (N - 1)));
+        rx_ += g[2][k] * f.x;
+        ry_ += g[2][k] * f.y;
+      }
+      bx += g[1][jy] * rx_;
+      by += g[1][jy] * ry_;
+    }
+    ax_ += g[0][i] * bx;
+    ay_ += g[0][i] * by;
+  }
+  const float inv = 1.0f / (s[0] * s[1] * s[2]);
+  d = ax_ * inv;
+  e = ay_ * inv;
+}
+
 __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c000, float c001, float c010, float c011,
                                          float c100, float c101, float c110, float c111) {
   const float c00 = c000 + tz * (c001 - c000);
@@ -121,7 +175,7 @@ __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c00
   return c0 + tx * (c1 - c0);
 }
 
-template <int U, bool WIDE>
+template <int U, int MODE>
 __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
   __shared__ float2 sbuf[kSkWaves][kHalfBuf];
   __shared__ int sjb[kSkWaves][kMaxZBins + 1];
@@ -171,7 +225,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
       }
       // wide-angle weights u_p u_q (off-diagonal ones doubled), u = step/|step|
       float wxx = 0.0f, wyy = 0.0f, wzz = 0.0f, wxy = 0.0f, wxz = 0.0f, wyz = 0.0f;
-      if (WIDE) {
+      if (MODE == kSkWide) {
         const double ux = static_cast<double>(sx), uy = static_cast<double>(sy), uz = static_cast<double>(sz);
         const double r2 = ux * ux + uy * uy + uz * uz;
         const double ir2 = r2 > 0.0 ? 1.0 / r2 : 0.0;
@@ -191,6 +245,15 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
       for (int j0 = lane; j0 < np; j0 += 64 * U) {
         float dd[U], ee[U];
         if (gather) {
+          float dl[U], el[U];
+          if constexpr (MODE == kSkGauss) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int j = j0 + 64 * u;
+              const int jj = j < np ? j : j0;
+              gauss7_at(a, ox + jj * sx, oy + jj * sy, oz + jj * sz, N, NN, dl[u], el[u]);
+            }
+          } else {
           float2 c[U][8];
           float t3[U][3];
 #pragma unroll
@@ -210,7 +273,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
             const size_t r10 = jx * NN + static_cast<size_t>(iy) * N;
             const size_t r11 = jx * NN + static_cast<size_t>(jy) * N;
             const size_t ci[8] = {r00 + iz, r00 + jz, r01 + iz, r01 + jz, r10 + iz, r10 + jz, r11 + iz, r11 + jz};
-            if (WIDE) {
+            if (MODE == kSkWide) {
               // all 32 gathers first, then eta_par = u_p u_q eta^pq per corner
               float2 w0[8], w1[8], w2[8], w3[8];
 #pragma unroll
@@ -233,12 +296,18 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int j = j0 + 64 * u;
             const float tx = t3[u][0], ty = t3[u][1], tz = t3[u][2];
-            float d = trilerp(tx, ty, tz, c[u][0].x, c[u][1].x, c[u][2].x, c[u][3].x, c[u][4].x, c[u][5].x,
-                              c[u][6].x, c[u][7].x);
-            const float e = trilerp(tx, ty, tz, c[u][0].y, c[u][1].y, c[u][2].y, c[u][3].y, c[u][4].y, c[u][5].y,
-                                    c[u][6].y, c[u][7].y);
+            dl[u] = trilerp(tx, ty, tz, c[u][0].x, c[u][1].x, c[u][2].x, c[u][3].x, c[u][4].x, c[u][5].x,
+                            c[u][6].x, c[u][7].x);
+            el[u] = trilerp(tx, ty, tz, c[u][0].y, c[u][1].y, c[u][2].y, c[u][3].y, c[u][4].y, c[u][5].y,
+                            c[u][6].y, c[u][7].y);
+          }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = j0 + 64 * u;
+            float d = dl[u];
+            const float e = el[u];
             if (j < np) {
               if (with_ds) {
                 const float2 z2 = buf[pidx(j >> 1)];
@@ -334,21 +403,24 @@ hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st) {
   if (blocks < 1) blocks = 1;
   const int u = a.unroll == 1 || a.unroll == 4 ? a.unroll : 2;
   const dim3 grid(static_cast<unsigned>(blocks));
-  if (a.is_wide) {
+  if (a.is_gauss) {
+    // 343 gathers per pixel: one pixel per lane at a time
+    LYA_TIMED("skewers_gauss", st, hipLaunchKernelGGL((k_skewers<1, kSkGauss>), grid, dim3(kSkNT), 0, st, a));
+  } else if (a.is_wide) {
     // four boxes per pixel: at most two pixels per lane in flight
     if (u == 1)
-      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<1, true>), grid, dim3(kSkNT), 0, st, a));
+      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<1, kSkWide>), grid, dim3(kSkNT), 0, st, a));
     else
-      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<2, true>), grid, dim3(kSkNT), 0, st, a));
+      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<2, kSkWide>), grid, dim3(kSkNT), 0, st, a));
   } else if (u == 1) {
     LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL((k_skewers<1, false>), grid, dim3(kSkNT), 0, st, a));
+              hipLaunchKernelGGL((k_skewers<1, kSkTri>), grid, dim3(kSkNT), 0, st, a));
   } else if (u == 2) {
     LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL((k_skewers<2, false>), grid, dim3(kSkNT), 0, st, a));
+              hipLaunchKernelGGL((k_skewers<2, kSkTri>), grid, dim3(kSkNT), 0, st, a));
   } else {
     LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL((k_skewers<4, false>), grid, dim3(kSkNT), 0, st, a));
+              hipLaunchKernelGGL((k_skewers<4, kSkTri>), grid, dim3(kSkNT), 0, st, a));
   }
   if (a.n_bins > 0 && a.do_flux)
     LYA_TIMED("skewer_finalize", st,

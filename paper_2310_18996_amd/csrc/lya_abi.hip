@@ -353,9 +353,10 @@ int lya_make_eta(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, 
   return make_pair(box, pk, seed, f, comp_a, comp_b, field, work, work_bytes, stream);
 }
 
-int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
-                     uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
-                     float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream) {
+static int draw_skewers_impl(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                             uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                             float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream,
+                             bool gauss) {
   g_err[0] = 0;
   int rc = check_box(box);
   if (rc) return rc;
@@ -385,7 +386,22 @@ int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* s
   a.dens = dens;
   a.eta = eta;
   a.flux = fgpa ? flux : nullptr;
+  a.is_gauss = gauss;
   return run_skewers(a, cosmo, fgpa ? zb : nullptr, work, work_bytes, stream);
+}
+
+int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                     uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                     float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream) {
+  return draw_skewers_impl(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zb, work, work_bytes, stream,
+                           false);
+}
+
+int lya_draw_skewers_gauss(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                           uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                           float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream) {
+  return draw_skewers_impl(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zb, work, work_bytes, stream,
+                           true);
 }
 
 int lya_draw_skewers_wide(const lya_box* box, const void* const* fields, const lya_skewers* sk, const lya_ps1d* ps,

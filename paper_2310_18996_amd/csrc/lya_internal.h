@@ -101,6 +101,8 @@ struct SkewerArgs {
   const float2* wide[3];
   const uint32_t* wide_bf16[3];
   bool is_wide;
+  // the 7^3 Gaussian-kernel average in place of trilinear interpolation
+  bool is_gauss;
   // small-scale field
   double ps_amp, ps_kcut, dpix;
   int ps_fixed_amp;

@@ -18,7 +18,8 @@ LYA_C_NONE, LYA_C_DELTA, LYA_C_XX, LYA_C_YY, LYA_C_ZZ, LYA_C_XY, LYA_C_XZ, LYA_C
 COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6}
 
 EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta",
-           "lya_draw_skewers", "lya_draw_skewers_wide", "lya_apply_fgpa", "lya_p1d_workspace_size", "lya_p1d",
+           "lya_draw_skewers", "lya_draw_skewers_gauss", "lya_draw_skewers_wide", "lya_apply_fgpa",
+           "lya_p1d_workspace_size", "lya_p1d",
            "lya_tune_workspace_size",
            "lya_tune_params", "lya_emulator_labels", "lya_emulator_bytes", "lya_emulator_param_offset",
            "lya_emulator_param_count", "lya_emulator_init", "lya_emulator_train_workspace_size",
@@ -96,6 +97,8 @@ def load():
     lib.lya_draw_skewers.restype = ctypes.c_int
     lib.lya_draw_skewers.argtypes = [P(Box), VP, P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo), P(Fgpa),
                                      VP, VP, VP, P(ZBins), VP, ctypes.c_size_t, VP]
+    lib.lya_draw_skewers_gauss.restype = ctypes.c_int
+    lib.lya_draw_skewers_gauss.argtypes = lib.lya_draw_skewers.argtypes
     lib.lya_draw_skewers_wide.restype = ctypes.c_int
     lib.lya_draw_skewers_wide.argtypes = [P(Box), P(VP), P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo),
                                           P(Fgpa), VP, VP, VP, P(ZBins), VP, ctypes.c_size_t, VP]
@@ -203,6 +206,18 @@ def draw_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, 
                                    _ptr(dens), _ptr(eta), _ptr(flux),
                                    ctypes.byref(zbins) if zbins is not None else None,
                                    _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def draw_skewers_gauss(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, work, stream=None):
+    """lya_draw_skewers_gauss (see include/lyamock.h): the 7^3 Gaussian-kernel
+    average in place of trilinear interpolation."""
+    _check(load().lya_draw_skewers_gauss(ctypes.byref(box), _ptr(field), ctypes.byref(sk),
+                                         ctypes.byref(ps) if ps is not None else None, int(seed),
+                                         ctypes.byref(cosmo) if cosmo is not None else None,
+                                         ctypes.byref(fgpa) if fgpa is not None else None,
+                                         _ptr(dens), _ptr(eta), _ptr(flux),
+                                         ctypes.byref(zbins) if zbins is not None else None,
+                                         _ptr(work), work.numel() * work.element_size(), _stream(stream)))
 
 
 def draw_skewers_wide(box, fields, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, work, stream=None):

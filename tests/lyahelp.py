@@ -80,7 +80,7 @@ def total_pixels(sk):
 
 
 def gpu_skewers(L, field, n, dx, sk, seed, ps_amp, ps_kcut, dpix, coef=None, chi_edges=None, omega_m=0.3147,
-                storage=0, want=("dens", "eta", "flux"), ps_fixed=False):
+                storage=0, want=("dens", "eta", "flux"), ps_fixed=False, gauss=False):
     box = L.box_struct(n, dx, storage)
     s, keep = skewer_tensors(L, sk)
     tot = max(total_pixels(sk), 1)
@@ -100,6 +100,8 @@ def gpu_skewers(L, field, n, dx, sk, seed, ps_amp, ps_kcut, dpix, coef=None, chi
     fg = L.fgpa_struct(coef) if coef is not None else None
     if isinstance(field, (list, tuple)):   # the four boxes of the wide-angle eta_par
         L.draw_skewers_wide(box, field, s, ps, seed, L.Cosmo(omega_m), fg, dens, eta, flux, zb, work)
+    elif gauss:
+        L.draw_skewers_gauss(box, field, s, ps, seed, L.Cosmo(omega_m), fg, dens, eta, flux, zb, work)
     else:
         L.draw_skewers(box, field, s, ps, seed, L.Cosmo(omega_m), fg, dens, eta, flux, zb, work)
     torch.cuda.synchronize()
