@@ -164,6 +164,86 @@ __device__ __forceinline__ void gauss7_at(const SkewerArgs& a, int64_t px, int64
   e = ay_ * inv;
 }
 
+// Staged form for 64 consecutive pixels of one skewer (one per lane, valid
+// lanes only): their 7^3 neighbourhoods lie in a bounding box of cells that
+// the wave loads into its LDS slice once (z runs contiguous), then each lane
+// sums its 343 voxels from LDS.  Returns false (nothing done) when the box
+// holds more than kGaussCap cells; the caller then gathers from global memory.
+constexpr int kGaussCap = 1024;
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) v = min(v, __shfl_xor(v, w));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) v = max(v, __shfl_xor(v, w));
+  return v;
+}
+__device__ __forceinline__ bool gauss7_staged(const SkewerArgs& a, int64_t px, int64_t py, int64_t pz, bool valid,
+                                              int64_t base_x, int64_t base_y, int64_t base_z, int N, size_t NN,
+                                              float2* lds, int lane, float& d, float& e) {
+  const int64_t p3[3] = {px, py, pz};
+  const int64_t b3[3] = {base_x, base_y, base_z};
+  int c[3], lo[3], sz[3];
+  float g[3][7], s[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const uint32_t fr = static_cast<uint32_t>(p3[ax]);
+    const int up = static_cast<int>(fr >> 31);
+    // nearest grid point relative to the chunk's base cell (small integers)
+    c[ax] = static_cast<int>((p3[ax] >> 32) - b3[ax]) + up;
+    const float t = static_cast<float>(fr) * 2.3283064365386963e-10f - static_cast<float>(up);
+    s[ax] = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+      const float dd = static_cast<float>(o - 3) - t;
+      g[ax][o] = __expf(-0.5f * dd * dd);
+      s[ax] += g[ax][o];
+    }
+    lo[ax] = wave_min(valid ? c[ax] : INT_MAX) - 3;
+    sz[ax] = wave_max(valid ? c[ax] : INT_MIN) + 4 - lo[ax];
+  }
+  const int vol = sz[0] * sz[1] * sz[2];
+  if (vol > kGaussCap || sz[0] > 64 || sz[1] > 64 || sz[2] > 64) return false;
+  const int sxy = sz[1] * sz[2];
+  for (int v = lane; v < vol; v += 64) {
+    const int vx = v / sxy, r = v - vx * sxy, vy = r / sz[2], vz = r - vy * sz[2];
+    const int gx = static_cast<int>((base_x + lo[0] + vx) & (N - 1));
+    const int gy = static_cast<int>((base_y + lo[1] + vy) & (N - 1));
+    const int gz = static_cast<int>((base_z + lo[2] + vz) & (N - 1));
+    lds[v] = ld_field(a, gx * NN + static_cast<size_t>(gy) * N + gz);
+  }
+  wave_sync();
+  float ax_ = 0.0f, ay_ = 0.0f;
+  if (valid) {
+    const int o0 = ((c[0] - 3 - lo[0]) * sz[1] + (c[1] - 3 - lo[1])) * sz[2] + (c[2] - 3 - lo[2]);
+    for (int i = 0; i < 7; ++i) {
+      float bx = 0.0f, by = 0.0f;
+#pragma unroll
+      for (int jy = 0; jy < 7; ++jy) {
+        const float2* row = lds + o0 + i * sxy + jy * sz[2];
+        float rx_ = 0.0f, ry_ = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          const float2 f = row[k];
+          rx_ += g[2][k] * f.x;
+          ry_ += g[2][k] * f.y;
+        }
+        bx += g[1][jy] * rx_;
+        by += g[1][jy] * ry_;
+      }
+      ax_ += g[0][i] * bx;
+      ay_ += g[0][i] * by;
+    }
+  }
+  wave_sync();  // the slice is reloaded for the next 64 pixels
+  const float inv = 1.0f / (s[0] * s[1] * s[2]);
+  d = ax_ * inv;
+  e = ay_ * inv;
+  return true;
+}
+
 __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c000, float c001, float c010, float c011,
                                          float c100, float c101, float c110, float c111) {
   const float c00 = c000 + tz * (c001 - c000);
@@ -178,6 +258,7 @@ __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c00
 template <int U, int MODE>
 __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
   __shared__ float2 sbuf[kSkWaves][kHalfBuf];
+  __shared__ float2 sgauss[MODE == kSkGauss ? kSkWaves : 1][MODE == kSkGauss ? kGaussCap : 1];
   __shared__ int sjb[kSkWaves][kMaxZBins + 1];
   __shared__ unsigned long long s_sum[kMaxZBins], s_cnt[kMaxZBins];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -242,17 +323,24 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
       int bin = a.n_bins - 1;
       int cur = -1;
       unsigned long long acc = 0ull, cnt = 0ull;
-      for (int j0 = lane; j0 < np; j0 += 64 * U) {
+      // the Gaussian mode runs every lane through every 64-pixel chunk (its
+      // wave reductions need all lanes); lanes past the end are not stored
+      for (int it = (MODE == kSkGauss ? 0 : lane); it < np; it += 64 * U) {
+        const int j0 = MODE == kSkGauss ? it + lane : it;
         float dd[U], ee[U];
         if (gather) {
           float dl[U], el[U];
           if constexpr (MODE == kSkGauss) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int j = j0 + 64 * u;
-              const int jj = j < np ? j : j0;
-              gauss7_at(a, ox + jj * sx, oy + jj * sy, oz + jj * sz, N, NN, dl[u], el[u]);
-            }
+            static_assert(U == 1, "one pixel per lane");
+            const int j = j0;
+            const bool valid = j < np;
+            const int jj = valid ? j : j0 - lane;  // the chunk's first pixel (always valid)
+            const int64_t px = ox + jj * sx, py = oy + jj * sy, pz = oz + jj * sz;
+            // base cell: the chunk's first pixel, the same for every lane
+            const int j1 = j0 - lane;
+            const int64_t bx = (ox + j1 * sx) >> 32, by = (oy + j1 * sy) >> 32, bz = (oz + j1 * sz) >> 32;
+            if (!gauss7_staged(a, px, py, pz, valid, bx, by, bz, N, NN, sgauss[wv], lane, dl[0], el[0]))
+              gauss7_at(a, px, py, pz, N, NN, dl[0], el[0]);
           } else {
           float2 c[U][8];
           float t3[U][3];
