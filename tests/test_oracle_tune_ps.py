@@ -1,0 +1,93 @@
+"""Pins of the oracle's small-scale power iteration (section "Adjusting mock
+parameters")."""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import mockinputs
+from oracle import field, fgpa, p1d, skewers, tune_ps
+from tests.lyahelp import oracle_table
+
+
+@pytest.mark.parametrize("a,s", [(0.2, 0.5), (1.0, 1.2), (3.0, 0.3)])
+def test_gaussian_flux_moments_by_quadrature(a, s):
+    f1, sf = tune_ps.gauss_fbar_sigf(a, s)
+    pdf = lambda x: np.exp(-0.5 * x * x) / np.sqrt(2 * np.pi)
+    q1 = integrate.quad(lambda x: np.exp(-a * np.exp(s * x)) * pdf(x), -12, 12, epsabs=1e-14)[0]
+    q2 = integrate.quad(lambda x: np.exp(-2 * a * np.exp(s * x)) * pdf(x), -12, 12, epsabs=1e-14)[0]
+    np.testing.assert_allclose(f1, q1, rtol=1e-10)
+    np.testing.assert_allclose(sf, np.sqrt(q2 - q1 * q1), rtol=1e-8)
+
+
+def test_fit_recovers_a_and_s():
+    for a, s in ((0.25, 0.7), (1.3, 1.9), (0.05, 0.4)):
+        f1, sf = tune_ps.gauss_fbar_sigf(a, s)
+        ra, rs = tune_ps.fit_a_s(f1, sf)
+        np.testing.assert_allclose([ra, rs], [a, s], rtol=1e-8)
+
+
+def test_sigma_s2_matches_numerical_integral():
+    k_edges = p1d.log_k_edges()
+    edges_k = k_edges * tune_ps.dv_per_dchi(2.4)
+    ratio = 1.0 + 0.5 * np.sin(np.arange(len(k_edges) - 1))
+    dpix = 0.2
+    got = tune_ps.sigma_s2(1.3, 1.1, ratio, edges_k, dpix)
+    pts = np.concatenate([[0.0], edges_k, [np.pi / dpix]])
+    num = sum(integrate.quad(lambda k: tune_ps.ps_of_k(k, 1.3, 1.1, ratio, edges_k), lo, hi,
+                             epsabs=1e-14, limit=200)[0] for lo, hi in zip(pts[:-1], pts[1:]))
+    np.testing.assert_allclose(got, num / np.pi, rtol=1e-10)
+
+
+def test_unit_ratios_reproduce_delta_s():
+    k_edges = p1d.log_k_edges()
+    edges_k = k_edges * tune_ps.dv_per_dchi(2.0)
+    for q, n in ((3, 256), (9, 700), (12, 1)):
+        a = tune_ps.delta_s_tab(77, q, n, 0.2, 1.0, 1.5, np.ones(len(k_edges) - 1), edges_k)
+        b = skewers.delta_s(77, q, n, 0.2, 1.0, 1.5)
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+def test_ratios_scale_the_mode_amplitudes():
+    # a ratio r in one bin multiplies the modes inside it by sqrt(r)
+    k_edges = p1d.log_k_edges()
+    edges_k = k_edges * tune_ps.dv_per_dchi(2.0)
+    n, dpix = 1024, 0.2
+    r = np.ones(len(k_edges) - 1)
+    r[20] = 4.0
+    base = np.fft.rfft(tune_ps.delta_s_tab(5, 2, n, dpix, 1.0, 1.5, np.ones_like(r), edges_k))
+    mod = np.fft.rfft(tune_ps.delta_s_tab(5, 2, n, dpix, 1.0, 1.5, r, edges_k))
+    k = 2 * np.pi * np.arange(n // 2 + 1) / (n * dpix)
+    inside = (k >= edges_k[20]) & (k < edges_k[21])
+    assert inside.sum() > 0
+    np.testing.assert_allclose(mod[inside], 2.0 * base[inside], rtol=1e-12)
+    np.testing.assert_allclose(mod[~inside], base[~inside], rtol=1e-12, atol=1e-12)
+
+
+def test_iteration_converges_towards_a_target_from_another_small_scale_power():
+    cfg = mockinputs.config("tiny")
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    box = field.make_box(n, seed, oracle_table(cfg["pk"], n, dx), ("delta", "zz"), f=cfg["f"])
+    sk = mockinputs.skewer_table(cfg)
+    dl, eta = skewers.draw_skewers(box.real, box.imag, sk, seed)          # no delta_S
+    k_edges = p1d.log_k_edges()
+    z_t, c_t = 2.4, 1.2
+    # truth: delta_S of another amplitude and cut-off (and other draws), known FGPA
+    truth = np.array(dl, copy=True)
+    for q in range(len(sk["npix"])):
+        o, m = int(sk["offset"][q]), int(sk["npix"][q])
+        truth[o:o + m] += skewers.delta_s(seed + 1, q, m, cfg["dpix"], 1.8, 1.0)
+    F = np.exp(-0.35 * np.exp(1.4 * (truth + c_t * eta)))
+    fbar_t = float(F.mean())
+    ps, cnt = p1d.p1d(F, sk, [-1e30, 1e30], [fbar_t], k_edges, z_t, cfg["dpix"])
+    pk_t = np.where(cnt > 0, ps / np.maximum(cnt, 1), np.nan)
+    # the truth knows its flux dispersion; the binned P1D integral would miss
+    # the power outside the bins
+    res = tune_ps.iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, cfg["dpix"], 1.0, 1.5, n_iter=6,
+                          sigf_t=float(F.std()))
+    ok = np.isfinite(pk_t)
+    err = [np.sqrt(np.mean((h["p1d"][ok] / pk_t[ok] - 1) ** 2)) for h in res["hist"]]
+    print("P1D relative RMS error per iteration", ["%.3f" % e for e in err])
+    assert all(e1 < e0 for e0, e1 in zip(err, err[1:]))
+    assert err[-1] < 0.7 * err[0]
+    assert abs(res["hist"][-1]["fbar"] / fbar_t - 1) < 0.03
+    assert abs(res["b"] / 1.4 - 1) < 0.03
