@@ -22,7 +22,7 @@ Readings (the paper is silent or states these loosely):
   sigma_F,t^2 = Fbar_t^2 sum_b P_t,b (k_{b+1} - k_b) / pi (delta_F is
   F/Fbar - 1, and the 1D power of a real field integrates to its variance
   as (1/pi) int_0^inf P dk); bins with no target value add nothing;
-* the Gaussian averages use 64-node Gauss-Hermite quadrature;
+* the Gaussian averages use adaptive quadrature (scipy.integrate.quad);
 * P_s^n(k) = P_s^0(k) r_n(bin of k): P_s^0 the configuration's form
   amp exp(-(k/kcut)^2), r_0 = 1, the bins those of the P1D converted to
   h/Mpc at z_t (k = k_v dv/dchi, dv/dchi = 100 E(z_t)/(1+z_t)); wavenumbers
@@ -40,19 +40,23 @@ The outer loop of the paper (adjusting a and b against the bias of the
 correlation-function prediction) is not part of this reading.
 """
 import numpy as np
-from scipy import optimize, special
+from scipy import integrate, optimize, special
 
 from . import cosmology, philox
 from . import p1d as op1d
 from .skewers import next_pow2
 
 
-def gauss_fbar_sigf(a, s, nodes=64):
-    """(Fbar, sigma_F) of F = exp(-a exp(s x)), x a unit normal."""
-    x, w = np.polynomial.hermite.hermgauss(nodes)
-    u = np.sqrt(2.0) * s * x
-    f1 = np.sum(w * np.exp(-a * np.exp(u))) / np.sqrt(np.pi)
-    f2 = np.sum(w * np.exp(-2.0 * a * np.exp(u))) / np.sqrt(np.pi)
+def gauss_fbar_sigf(a, s):
+    """(Fbar, sigma_F) of F = exp(-a exp(s x)), x a unit normal: adaptive
+    quadrature over [-12, 12] with a break point where a exp(s x) = 1 (F
+    turns over there, steeply for large s)."""
+    pdf = lambda x: np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
+    x0 = float(np.clip(-np.log(a) / s, -11.0, 11.0)) if s > 0 else 0.0
+    f1 = integrate.quad(lambda x: np.exp(-a * np.exp(s * x)) * pdf(x), -12.0, 12.0, points=[x0],
+                        epsabs=1e-15, epsrel=1e-13, limit=400)[0]
+    f2 = integrate.quad(lambda x: np.exp(-2.0 * a * np.exp(s * x)) * pdf(x), -12.0, 12.0, points=[x0],
+                        epsabs=1e-15, epsrel=1e-13, limit=400)[0]
     return f1, np.sqrt(max(f2 - f1 * f1, 0.0))
 
 

@@ -10,13 +10,35 @@ from tests.lyahelp import oracle_table
 
 
 @pytest.mark.parametrize("a,s", [(0.2, 0.5), (1.0, 1.2), (3.0, 0.3)])
-def test_gaussian_flux_moments_by_quadrature(a, s):
+def test_gaussian_flux_moments_against_gauss_hermite(a, s):
+    # an independent rule where it is accurate (moderate s): 100-node Gauss-Hermite
     f1, sf = tune_ps.gauss_fbar_sigf(a, s)
-    pdf = lambda x: np.exp(-0.5 * x * x) / np.sqrt(2 * np.pi)
-    q1 = integrate.quad(lambda x: np.exp(-a * np.exp(s * x)) * pdf(x), -12, 12, epsabs=1e-14)[0]
-    q2 = integrate.quad(lambda x: np.exp(-2 * a * np.exp(s * x)) * pdf(x), -12, 12, epsabs=1e-14)[0]
-    np.testing.assert_allclose(f1, q1, rtol=1e-10)
-    np.testing.assert_allclose(sf, np.sqrt(q2 - q1 * q1), rtol=1e-8)
+    x, w = np.polynomial.hermite.hermgauss(100)
+    u = np.sqrt(2.0) * s * x
+    g1 = np.sum(w * np.exp(-a * np.exp(u))) / np.sqrt(np.pi)
+    g2 = np.sum(w * np.exp(-2 * a * np.exp(u))) / np.sqrt(np.pi)
+    np.testing.assert_allclose(f1, g1, rtol=1e-10)
+    np.testing.assert_allclose(sf, np.sqrt(g2 - g1 * g1), rtol=1e-8)
+
+
+@pytest.mark.parametrize("a,s", [(0.37, 3.96), (0.05, 6.0)])
+def test_gaussian_flux_moments_steep(a, s):
+    # steep F(x): a fine Riemann sum (Simpson on 200,001 nodes) as the check
+    f1, sf = tune_ps.gauss_fbar_sigf(a, s)
+    x = np.linspace(-12, 12, 200001)
+    pdf = np.exp(-0.5 * x * x) / np.sqrt(2 * np.pi)
+    F = np.exp(-a * np.exp(s * x))
+    g1 = integrate.simpson(F * pdf, x=x)
+    g2 = integrate.simpson(F * F * pdf, x=x)
+    np.testing.assert_allclose(f1, g1, rtol=1e-10)
+    np.testing.assert_allclose(sf, np.sqrt(g2 - g1 * g1), rtol=1e-9)
+
+
+def test_gaussian_flux_moments_limits():
+    # s -> 0: F is the constant exp(-a)
+    f1, sf = tune_ps.gauss_fbar_sigf(0.7, 1e-9)
+    np.testing.assert_allclose(f1, np.exp(-0.7), rtol=1e-12)
+    assert sf < 1e-8
 
 
 def test_fit_recovers_a_and_s():
