@@ -319,6 +319,81 @@ def truth_targets(L, torch, mock, cosmo, z_t, b_t, c_t, fbar_t, k_edges, dpix):
     return np.array(a_t), np.stack(pk_t)
 
 
+def tune_ps_leg(L, torch, n_iter=10):
+    """The small-scale power iteration (lya_tune_ps) on the 512^3 mock with
+    50,000 skewers: stored delta_L and eta_par without delta_S; the targets
+    (Fbar, sigma_F and P1D at the five z_t) come from a truth made of the
+    same large-scale pixels with delta_S of another spectrum (amplitude 1.6,
+    cut-off 1.1 h/Mpc, other Philox key) and hidden (a, b)."""
+    import ctypes
+    import mockinputs
+    z_t = mockinputs.TUNE_Z
+    c_t = mockinputs.tune_c(z_t)
+    b_true = mockinputs.tune_b_truth(z_t)
+    fbar_t = mockinputs.fbar_target(z_t)
+    k_edges = torch.from_numpy(mockinputs.tune_k_edges()).cuda()
+    nk = k_edges.numel() - 1
+    mid = dict(mockinputs.config("mid"), ps_amp=0.0)
+    seed = mid["seed"]
+    mock = stored_pixels(L, torch, mid, seed, 41)
+    cosmo = L.Cosmo(mid["omega_m"])
+    s = mock["s"]
+    flux = torch.empty_like(mock["dens"])
+    edges = torch.tensor([-1e30, 1e30], dtype=torch.float64, device="cuda")
+    fsum = torch.zeros(1, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    zb = L.zbins_struct(edges, fsum, cnt)
+    work = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS), dtype=torch.uint8, device="cuda")
+    pwork = torch.empty(L.p1d_workspace_size(mock["n_sk"], nk), dtype=torch.uint8, device="cuda")
+    psum = torch.zeros(nk, dtype=torch.float64, device="cuda")
+    pcnt = torch.zeros(nk, dtype=torch.int64, device="cuda")
+    ps_true = L.Ps1d(1.6, 1.1, mid["dpix"], 0)
+    a_true, sig_t, pk_t = [], [], []
+    for z, b, c, ft in zip(z_t, b_true, c_t, fbar_t):
+        def fbar(a):
+            L.apply_fgpa_ds(s, cosmo, mock["dens"], mock["eta"], ps_true, None, seed + 1,
+                            L.fgpa_struct([[a, 0, 0], [b, 0, 0], [c, 0, 0]]), flux, zb, work)
+            return float(fsum.item()) / float(cnt.item())
+        lo, hi = np.log(1e-4), np.log(1e2)
+        for _ in range(60):
+            m_ = 0.5 * (lo + hi)
+            if fbar(np.exp(m_)) > ft:
+                lo = m_
+            else:
+                hi = m_
+        a = float(np.exp(0.5 * (lo + hi)))
+        fb = fbar(a)
+        sig_t.append(float(torch.sqrt(((flux.double() - fb) ** 2).mean())))
+        L.p1d(s, cosmo, flux, zb, L.P1dSpec(nk, k_edges.data_ptr(), float(z), float(mid["dpix"])), psum, pcnt, pwork)
+        pc = pcnt.cpu().numpy()
+        pk_t.append(np.where(pc > 0, psum.cpu().numpy() / np.maximum(pc, 1), np.nan))
+        a_true.append(a)
+    pk_t = np.ascontiguousarray(np.stack(pk_t), dtype=np.float64)
+    spec = L.TunePsSpec()
+    spec.sk = ctypes.pointer(s)
+    spec.dens_l, spec.eta = mock["dens"].data_ptr(), mock["eta"].data_ptr()
+    spec.n_pixels = int(mock["pixels"])
+    spec.cosmo = cosmo
+    spec.seed = seed
+    spec.n_zt = len(z_t)
+    for i in range(len(z_t)):
+        spec.z_t[i], spec.c_t[i], spec.fbar_t[i], spec.sigf_t[i] = z_t[i], c_t[i], fbar_t[i], sig_t[i]
+    spec.p1d_t = pk_t.ctypes.data
+    spec.p1d = L.P1dSpec(nk, k_edges.data_ptr(), 0.0, float(mid["dpix"]))
+    spec.ps_amp, spec.ps_kcut, spec.n_iter = 1.0, 1.5, n_iter
+    tw = torch.empty(L.tune_ps_workspace_size(mock["n_sk"], mock["pixels"], nk), dtype=torch.uint8, device="cuda")
+    res = L.tune_ps(spec, tw)
+    M = L.TUNE_PS_MAX_ITER
+    return dict(workload="P_s iteration, %d iterations at z_t=%s on the 512^3 mock (%d skewers, %d pixels); truth: "
+                          "same delta_L and eta_par, delta_S with amplitude 1.6 and cut-off 1.1 h/Mpc (other key), "
+                          "P_s start amplitude 1.0, cut-off 1.5" % (n_iter, list(z_t), mock["n_sk"], mock["pixels"]),
+                seconds=res.seconds, a=list(res.a[:len(z_t)]), a_truth=a_true, b=list(res.b[:len(z_t)]),
+                b_truth=list(map(float, b_true)),
+                fbar_last=[res.fbar[i * M + n_iter - 1] for i in range(len(z_t))], fbar_target=list(map(float, fbar_t)),
+                p1d_rel_rms_first=[res.rms[i * M] for i in range(len(z_t))],
+                p1d_rel_rms_last=[res.rms[i * M + n_iter - 1] for i in range(len(z_t))])
+
+
 def tune_leg(L, torch, n_labels, train_steps):
     """Plain against emulator-driven tuning; returns the `tune` record."""
     import mockinputs
@@ -603,8 +678,12 @@ def main():
     if not args.no_tune:
         print("bench: tuning leg", file=sys.stderr, flush=True)
         out["tune"] = tune_leg(L, torch, args.tune_labels, args.tune_steps)
+        torch.cuda.empty_cache()
+        print("bench: small-scale power iteration", file=sys.stderr, flush=True)
+        out["tune_ps"] = tune_ps_leg(L, torch)
     else:
         out["tune"] = None
+        out["tune_ps"] = None
     print(json.dumps(out), flush=True)
 
 

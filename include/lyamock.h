@@ -187,6 +187,26 @@ int lya_apply_fgpa(const lya_skewers* sk, const lya_cosmo* cosmo, const float* d
                    const lya_fgpa* fgpa, float* flux, const lya_zbins* zb, void* work, size_t work_bytes,
                    void* stream);
 
+/* Post-production with a new small-scale spectrum (section "Adjusting mock
+ * parameters": the spectra are drawn again with the current P_s): draws
+ * delta_S for every skewer exactly as lya_draw_skewers does (Philox key seed,
+ * stream 1, lengths up to 2048 pixels) with
+ *   P_s(k) = ps->amp exp(-(k/ps->kcut)^2) r(k),
+ * r(k) = tab->ratio[b] for tab->k_edges[b] <= k < tab->k_edges[b+1] (k in
+ * h/Mpc; below the first edge the first ratio, from the last edge up the last
+ * one; tab NULL: r = 1), adds it to dens_l (stored delta_L without delta_S)
+ * and applies eq:FGPA as lya_apply_fgpa does.  tab->k_edges (n_bins + 1
+ * doubles, increasing) and tab->ratio (n_bins floats) are device arrays. */
+typedef struct {
+  int32_t n_bins;          /* 1..64 */
+  const double* k_edges;   /* device, h/Mpc */
+  const float* ratio;      /* device */
+} lya_ps_table;
+
+int lya_apply_fgpa_ds(const lya_skewers* sk, const lya_cosmo* cosmo, const float* dens_l, const float* eta,
+                      const lya_ps1d* ps, const lya_ps_table* tab, uint64_t seed, const lya_fgpa* fgpa, float* flux,
+                      const lya_zbins* zb, void* work, size_t work_bytes, void* stream);
+
 /* 1D flux power spectrum (the statistic the paper's tuning matches, section
  * "Adjusting mock parameters"; delta_F = F/Fbar - 1 of
  * equation::definition_delta).  Per skewer the first
@@ -266,6 +286,57 @@ typedef struct {
 size_t lya_tune_workspace_size(int64_t n_sk, int32_t n_kbins);
 int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void* work, size_t work_bytes,
                     void* stream);
+
+/* Small-scale power iteration of the tuning (section "Adjusting mock
+ * parameters").  dens_l and eta are stored pre-FGPA pixels WITHOUT delta_S.
+ * Their moments sigma_L^2, sigma_eta^2 and cov(delta_L, eta_par) are measured
+ * once (FP64).  At each z_t:
+ *   1. a and s = b sigma_g solve Fbar(a, s) = fbar_t and sigma_F(a, s) =
+ *      sigma_F,t for F = exp(-a exp(s x)), x a unit normal (host FP64);
+ *      sigma_F,t = sigf_t[z] if positive, else fbar_t (sum_b P_t,b dk_b /
+ *      pi)^(1/2) over the bins with a finite target;
+ *   2. iteration n (n_iter of them): P_s^n(k) = ps_amp exp(-(k/ps_kcut)^2)
+ *      r_n(bin of k), the P1D bins converted to h/Mpc at z_t (k = k_v 100
+ *      E(z_t)/(1+z_t)), r_0 = 1; sigma_s^2 = (1/pi) int_0^{pi/dpix} P_s^n dk;
+ *      b = s / (sigma_L^2 + sigma_s^2 + c_t^2 sigma_eta^2 + 2 c_t cov)^(1/2);
+ *      delta_S redrawn with P_s^n (lya_apply_fgpa_ds, key seed), F under
+ *      constant (a, b, c_t), Fbar = mean F and the P1D of F/Fbar - 1 at z_t
+ *      (lya_p1d); then r_{n+1} = r_n P_t / P1D in every bin where both are
+ *      finite and P1D > 0.
+ * The result holds a, b and the ratios of the last iteration, its P1D, and
+ * per iteration Fbar and the relative RMS P1D error over the bins with a
+ * target.  Synchronous; GPU work on `stream`; errors in
+ * lya_tune_ps_last_error().  (The paper's outer loop, which adjusts a and b
+ * against the correlation-function bias, is not part of this call.) */
+#define LYA_TUNE_PS_MAX_ITER 16
+typedef struct {
+  const lya_skewers* sk;     /* npix, offset, chi0, dchi, id_base used */
+  const float* dens_l;       /* device: delta_L per pixel (no delta_S) */
+  const float* eta;          /* device: eta_par per pixel */
+  int64_t n_pixels;          /* length of the pixel arrays (max offset + npix) */
+  lya_cosmo cosmo;
+  uint64_t seed;             /* Philox key of delta_S (stream 1) */
+  int32_t n_zt;              /* 1..16 */
+  double z_t[LYA_TUNE_MAX_Z], c_t[LYA_TUNE_MAX_Z], fbar_t[LYA_TUNE_MAX_Z], sigf_t[LYA_TUNE_MAX_Z];
+  const double* p1d_t;       /* host [n_zt][p1d.n_kbins] target mean P1D (NaN: bin unused) */
+  lya_p1d_spec p1d;          /* k bins (device edges, s/km) and dpix; z_ref is z_t */
+  double ps_amp, ps_kcut;    /* P_s^0 */
+  int32_t n_iter;            /* 1..16 (the paper uses 10) */
+} lya_tune_ps_spec;
+
+typedef struct {
+  double a[LYA_TUNE_MAX_Z], b[LYA_TUNE_MAX_Z], s[LYA_TUNE_MAX_Z];
+  double sigma2[3];                                    /* sigma_L^2, sigma_eta^2, cov */
+  double ratio[LYA_TUNE_MAX_Z * 64];                   /* r of the last iteration, [z_t][bin] */
+  double p1d[LYA_TUNE_MAX_Z * 64];                     /* its mean P1D, [z_t][bin] */
+  double fbar[LYA_TUNE_MAX_Z * LYA_TUNE_PS_MAX_ITER];  /* [z_t][iteration] */
+  double rms[LYA_TUNE_MAX_Z * LYA_TUNE_PS_MAX_ITER];   /* [z_t][iteration] */
+  double seconds;
+} lya_tune_ps_result;
+
+size_t lya_tune_ps_workspace_size(int64_t n_sk, int64_t n_pixels, int32_t n_kbins);
+int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* work, size_t work_bytes, void* stream);
+const char* lya_tune_ps_last_error(void);
 
 /* Tuning emulator (not in the paper: a surrogate for the evaluations of the
  * tuning loop above).  A multilayer perceptron 4 -> 256 -> 256 -> 256 -> n_out

@@ -67,7 +67,26 @@ __device__ __forceinline__ float2 ld_wide(const SkewerArgs& a, int k, size_t i) 
 __device__ __forceinline__ float2 ps_mode(const SkewerArgs& a, uint64_t qid, int m, int ns, float amp_scale,
                                           float dk2) {
   const float kk = static_cast<float>(m) * static_cast<float>(m) * dk2;   // (k/kcut)^2
-  const float amp = __builtin_amdgcn_sqrtf(amp_scale * __expf(-kk));
+  float ratio = 1.0f;
+  if (a.ps_ratio) {
+    // the mode's k bin (FP64, so the bin decision matches a double-precision
+    // reference): the largest b with edge_b <= k, clamped to the table
+    const double k = (2.0 * M_PI / (static_cast<double>(ns) * a.dpix)) * m;
+    const double* e = a.ps_edges_k;
+    int b = 0;
+    if (k >= e[a.ps_nb]) {
+      b = a.ps_nb - 1;
+    } else if (k >= e[0]) {
+      int lo = 0, hi = a.ps_nb;   // e[lo] <= k < e[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (e[mid] <= k) lo = mid; else hi = mid;
+      }
+      b = lo;
+    }
+    ratio = a.ps_ratio[b];
+  }
+  const float amp = __builtin_amdgcn_sqrtf(amp_scale * __expf(-kk) * ratio);
   const float2 z = normal_pair(a.seed, 1u, (qid << 33) + static_cast<uint64_t>(m));
   float2 w = (m == ns / 2) ? make_float2(z.x, 0.0f) : make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
   if (a.ps_fixed_amp) {
@@ -287,7 +306,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
       int ns = 1;
       while (ns < np) ns <<= 1;
       // delta_S needs next_pow2(npix) <= 2048 (the wave's LDS line); longer skewers get none
-      const bool with_ds = gather && a.ps_amp > 0.0 && ns >= 2 && ns <= 2 * kHalfMax;
+      const bool with_ds = (gather || a.ds_in_apply) && a.ps_amp > 0.0 && ns >= 2 && ns <= 2 * kHalfMax;
       // twiddles from global memory: a copy in LDS would cost this kernel its fourth block per CU
       if (with_ds) small_scale_wave(a, a.id_base + q, ns, buf, a.tw2048, lane);
       // bin boundaries: jb[b] = first pixel with chi_j < edges[b] (chi_j decreases with j)
@@ -413,6 +432,10 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
             const int j = j0 + 64 * u;
             dd[u] = j < np ? a.in_dens[off + j] : 0.0f;
             ee[u] = j < np ? a.in_eta[off + j] : 0.0f;
+            if (with_ds && j < np) {
+              const float2 z2 = buf[pidx(j >> 1)];
+              dd[u] += (j & 1) ? z2.y : z2.x;
+            }
           }
         }
         if (a.do_flux) {

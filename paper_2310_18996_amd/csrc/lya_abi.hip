@@ -163,7 +163,7 @@ int run_skewers(lya::SkewerArgs& a, const lya_cosmo* cosmo, const lya_zbins* zb,
     e = lya::launch_zchi_table(cosmo->omega_m, const_cast<float*>(a.ztab), st);
     if (e != hipSuccess) return hip_fail(e, "redshift table");
   }
-  if (a.field || a.field_bf16) {
+  if (a.field || a.field_bf16 || a.ds_in_apply) {
     e = lya::launch_twiddles(const_cast<float2*>(a.tw2048), lya::kTw2048, st);
     if (e != hipSuccess) return hip_fail(e, "twiddles");
   }
@@ -444,6 +444,45 @@ int lya_draw_skewers_wide(const lya_box* box, const void* const* fields, const l
   a.eta = eta;
   a.flux = fgpa ? flux : nullptr;
   return run_skewers(a, cosmo, fgpa ? zb : nullptr, work, work_bytes, stream);
+}
+
+int lya_apply_fgpa_ds(const lya_skewers* sk, const lya_cosmo* cosmo, const float* dens_l, const float* eta,
+                      const lya_ps1d* ps, const lya_ps_table* tab, uint64_t seed, const lya_fgpa* fgpa, float* flux,
+                      const lya_zbins* zb, void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_skewers(sk, false);
+  if (rc) return rc;
+  if ((rc = check_zbins(zb))) return rc;
+  if (!fgpa) return fail(LYA_EINVAL, "fgpa is NULL%s");
+  if (sk->n_sk > 0 && (!dens_l || !eta)) return fail(LYA_EINVAL, "dens_l/eta are NULL%s");
+  if (!ps || !(ps->amp >= 0.0) || !(ps->kcut > 0.0) || !(ps->dpix > 0.0))
+    return fail(LYA_EINVAL, "invalid small-scale spectrum%s");
+  if (tab && (tab->n_bins < 1 || tab->n_bins > lya::kMaxKBins || !tab->k_edges || !tab->ratio))
+    return fail(LYA_EINVAL, "invalid P_s table (1..64 bins with edges and ratios)%s");
+  lya::SkewerArgs a{};
+  a.n_sk = sk->n_sk;
+  a.npix = sk->npix;
+  a.offset = sk->offset;
+  a.chi0 = sk->chi0;
+  a.dchi = sk->dchi;
+  a.id_base = sk->id_base;
+  a.n = 32;
+  a.in_dens = dens_l;
+  a.in_eta = eta;
+  a.ds_in_apply = true;
+  a.ps_amp = ps->amp;
+  a.ps_kcut = ps->kcut;
+  a.dpix = ps->dpix;
+  a.ps_fixed_amp = ps->fixed_amp;
+  a.seed = seed;
+  if (tab) {
+    a.ps_nb = tab->n_bins;
+    a.ps_edges_k = tab->k_edges;
+    a.ps_ratio = tab->ratio;
+  }
+  fill_fgpa(a, fgpa);
+  a.flux = flux;
+  return run_skewers(a, cosmo, zb, work, work_bytes, stream);
 }
 
 int lya_apply_fgpa(const lya_skewers* sk, const lya_cosmo* cosmo, const float* dens, const float* eta,

@@ -103,6 +103,13 @@ struct SkewerArgs {
   bool is_wide;
   // the 7^3 Gaussian-kernel average in place of trilinear interpolation
   bool is_gauss;
+  // delta_S added to stored pixels in apply mode, and a tabulated factor of
+  // P_s per k bin (ps_ratio null: 1): bin b holds ps_edges_k[b] <= k <
+  // ps_edges_k[b+1] (h/Mpc), the ends clamped
+  bool ds_in_apply;
+  int ps_nb;
+  const double* ps_edges_k;
+  const float* ps_ratio;
   // small-scale field
   double ps_amp, ps_kcut, dpix;
   int ps_fixed_amp;

@@ -1,0 +1,362 @@
+// Small-scale power iteration of the tuning (section "Adjusting mock
+// parameters"): at each tuning redshift, a and s = b sigma_g from the target
+// mean flux and flux dispersion of a Gaussian g, sigma_g from the moments of
+// the stored pixels and the current P_s, then repeatedly: delta_S redrawn
+// with P_s (lya_apply_fgpa_ds), Fbar and P1D measured (lya_p1d), and P_s
+// multiplied per k bin by P_target / P1D.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <vector>
+
+#include "../../include/lyamock.h"
+#include "lya_internal.h"
+
+namespace lya {
+namespace {
+
+constexpr int kMomBlocks = 1024;
+constexpr int kMomNT = 256;
+
+// Per block, over skewers blockIdx.x, blockIdx.x + gridDim.x, ...: FP64 sums
+// of d, e, d^2, e^2, d e; fixed order within the block.
+__global__ void __launch_bounds__(kMomNT) k_moments(int64_t n_sk, const int32_t* __restrict__ npix,
+                                                    const int64_t* __restrict__ offset, const float* __restrict__ d,
+                                                    const float* __restrict__ e, double* __restrict__ part) {
+  __shared__ double s[5][kMomNT];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t q = blockIdx.x; q < n_sk; q += gridDim.x) {
+    const int np = npix[q];
+    const int64_t off = offset[q];
+    for (int j = threadIdx.x; j < np; j += kMomNT) {
+      const double x = d[off + j], y = e[off + j];
+      acc[0] += x;
+      acc[1] += y;
+      acc[2] += x * x;
+      acc[3] += y * y;
+      acc[4] += x * y;
+    }
+  }
+  for (int k = 0; k < 5; ++k) s[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = kMomNT / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w)
+      for (int k = 0; k < 5; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) part[threadIdx.x * kMomBlocks + blockIdx.x] = s[threadIdx.x][0];
+}
+
+// out[k] = sum over blocks of part[k][.], fixed tree order (one block per k).
+__global__ void __launch_bounds__(kMomBlocks) k_moments_reduce(const double* __restrict__ part, double* out) {
+  __shared__ double s[kMomBlocks];
+  s[threadIdx.x] = part[blockIdx.x * kMomBlocks + threadIdx.x];
+  __syncthreads();
+  for (int w = kMomBlocks / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+struct PsCarve {
+  size_t sk, p1d, flux, ratio, edges, zb, psum, pcnt, part, mom, total;
+};
+
+PsCarve carve_ps(int64_t n_sk, int64_t n_pix, int nk) {
+  PsCarve c{};
+  size_t o = 0;
+  c.sk = o;
+  o += al(lya_workspace_size(LYA_OP_SKEWERS, nullptr));
+  c.p1d = o;
+  o += al(lya_p1d_workspace_size(n_sk, nk));
+  c.flux = o;
+  o += al(sizeof(float) * static_cast<size_t>(n_pix > 0 ? n_pix : 1));
+  c.ratio = o;
+  o += al(sizeof(float) * kMaxKBins);
+  c.edges = o;
+  o += al(sizeof(double) * (kMaxKBins + 1));
+  c.zb = o;  // chi edges [2], fsum [1], count [1]
+  o += al(4 * sizeof(double));
+  c.psum = o;
+  o += al(sizeof(double) * kMaxKBins);
+  c.pcnt = o;
+  o += al(sizeof(int64_t) * kMaxKBins);
+  c.part = o;
+  o += al(sizeof(double) * 5 * kMomBlocks);
+  c.mom = o;
+  o += al(sizeof(double) * 5);
+  c.total = o;
+  return c;
+}
+
+// F = exp(-a exp(s x)), x a unit normal: mean and dispersion by the
+// trapezoid rule on [-12, 12] (the Gaussian weight makes it converge
+// geometrically; 4800 intervals leave ~1e-15).
+void gauss_flux(double a, double s, double* f1, double* sf) {
+  const int n = 4800;
+  const double h = 24.0 / n;
+  double m1 = 0.0, m2 = 0.0;
+  for (int i = 0; i <= n; ++i) {
+    const double x = -12.0 + i * h;
+    const double w = (i == 0 || i == n ? 0.5 : 1.0) * exp(-0.5 * x * x);
+    const double F = exp(-a * exp(s * x));
+    m1 += w * F;
+    m2 += w * F * F;
+  }
+  const double norm = h / sqrt(2.0 * M_PI);
+  m1 *= norm;
+  m2 *= norm;
+  *f1 = m1;
+  *sf = sqrt(m2 - m1 * m1 > 0.0 ? m2 - m1 * m1 : 0.0);
+}
+
+// (a, s) with gauss_flux = (fbar_t, sigf_t): damped Newton in (ln a, ln s).
+bool fit_a_s(double fbar_t, double sigf_t, double* a, double* s) {
+  double t[2] = {log(0.3), log(0.5)};
+  auto resid = [&](const double* u, double* r) {
+    double f1, sf;
+    gauss_flux(exp(u[0]), exp(u[1]), &f1, &sf);
+    if (!(f1 > 0.0) || !(sf > 0.0)) return false;
+    r[0] = log(f1 / fbar_t);
+    r[1] = log(sf / sigf_t);
+    return true;
+  };
+  double r[2];
+  if (!resid(t, r)) return false;
+  for (int it = 0; it < 200; ++it) {
+    const double nr = fabs(r[0]) + fabs(r[1]);
+    if (nr < 1e-13) break;
+    double J[2][2];
+    for (int k = 0; k < 2; ++k) {
+      double up[2] = {t[0], t[1]}, dn[2] = {t[0], t[1]}, rp[2], rm[2];
+      up[k] += 1e-6;
+      dn[k] -= 1e-6;
+      if (!resid(up, rp) || !resid(dn, rm)) return false;
+      J[0][k] = (rp[0] - rm[0]) / 2e-6;
+      J[1][k] = (rp[1] - rm[1]) / 2e-6;
+    }
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    if (!(fabs(det) > 1e-300)) return false;
+    const double d0 = -(J[1][1] * r[0] - J[0][1] * r[1]) / det;
+    const double d1 = -(-J[1][0] * r[0] + J[0][0] * r[1]) / det;
+    double lam = 1.0;
+    bool moved = false;
+    for (int ls = 0; ls < 40; ++ls, lam *= 0.5) {
+      double u[2] = {t[0] + lam * d0, t[1] + lam * d1}, ru[2];
+      if (resid(u, ru) && fabs(ru[0]) + fabs(ru[1]) < nr) {
+        t[0] = u[0];
+        t[1] = u[1];
+        r[0] = ru[0];
+        r[1] = ru[1];
+        moved = true;
+        break;
+      }
+    }
+    if (!moved) break;
+  }
+  if (!(fabs(r[0]) + fabs(r[1]) < 1e-9)) return false;
+  *a = exp(t[0]);
+  *s = exp(t[1]);
+  return true;
+}
+
+// (1/pi) int_0^{pi/dpix} amp exp(-(k/kcut)^2) r(k) dk, r piecewise constant
+// on the edges (h/Mpc), clamped at both ends.
+double sigma_s2(double amp, double kcut, const double* ratio, const double* edges, int nk, double dpix) {
+  const double kmax = M_PI / dpix;
+  auto prim = [&](double k) { return amp * kcut * sqrt(M_PI) * 0.5 * erf(k / kcut); };
+  double tot = 0.0, lo = 0.0;
+  for (int p = 0; p <= nk + 1; ++p) {
+    double hi = p <= nk ? edges[p] : kmax;
+    hi = hi < 0.0 ? 0.0 : (hi > kmax ? kmax : hi);
+    const double r = p == 0 ? ratio[0] : (p <= nk ? ratio[p - 1] : ratio[nk - 1]);
+    if (hi > lo) tot += r * (prim(hi) - prim(lo));
+    if (hi > lo) lo = hi;
+  }
+  return tot / M_PI;
+}
+
+}  // namespace
+}  // namespace lya
+
+namespace {
+thread_local char g_perr[256] = "";
+int pfail(int code, const char* msg) {
+  snprintf(g_perr, sizeof(g_perr), "%s", msg);
+  return code;
+}
+int phip(hipError_t e, const char* where) {
+  snprintf(g_perr, sizeof(g_perr), "%s: %s", where, hipGetErrorString(e));
+  return LYA_EHIP;
+}
+}  // namespace
+
+extern "C" {
+
+const char* lya_tune_ps_last_error(void) { return g_perr; }
+
+size_t lya_tune_ps_workspace_size(int64_t n_sk, int64_t n_pixels, int32_t n_kbins) {
+  if (n_sk < 0 || n_pixels < 0 || n_kbins < 1 || n_kbins > lya::kMaxKBins) return 0;
+  return lya::carve_ps(n_sk, n_pixels, n_kbins).total;
+}
+
+int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* work, size_t work_bytes,
+                void* stream) {
+  using namespace lya;
+  g_perr[0] = 0;
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!spec || !res || !spec->sk) return pfail(LYA_EINVAL, "spec, result or skewers is NULL");
+  const lya_skewers* sk = spec->sk;
+  const int nk = spec->p1d.n_kbins;
+  if (spec->n_zt < 1 || spec->n_zt > LYA_TUNE_MAX_Z) return pfail(LYA_EINVAL, "n_zt must be in [1, 16]");
+  if (nk < 1 || nk > kMaxKBins || !spec->p1d.k_edges || !spec->p1d_t)
+    return pfail(LYA_EINVAL, "P1D bins (1..64 with edges) and targets are required");
+  if (spec->n_iter < 1 || spec->n_iter > LYA_TUNE_PS_MAX_ITER) return pfail(LYA_EINVAL, "n_iter must be in [1, 16]");
+  if (!(spec->ps_amp > 0.0) || !(spec->ps_kcut > 0.0) || !(spec->p1d.dpix > 0.0))
+    return pfail(LYA_EINVAL, "P_s^0 amplitude, cut-off and dpix must be positive");
+  if (sk->n_sk < 1 || !sk->npix || !sk->offset || !sk->chi0 || !spec->dens_l || !spec->eta)
+    return pfail(LYA_EINVAL, "stored pixels and their skewer table are required");
+  if (!(spec->cosmo.omega_m >= 0.0 && spec->cosmo.omega_m <= 1.0)) return pfail(LYA_EINVAL, "omega_m out of [0,1]");
+  if (!work) return pfail(LYA_EINVAL, "work is NULL");
+  const PsCarve c = carve_ps(sk->n_sk, spec->n_pixels, nk);
+  if (spec->n_pixels < 1 || work_bytes < c.total) return pfail(LYA_EWORKSPACE, "workspace too small (or n_pixels < 1)");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(work);
+  float* flux = reinterpret_cast<float*>(w + c.flux);
+  float* d_ratio = reinterpret_cast<float*>(w + c.ratio);
+  double* d_edges = reinterpret_cast<double*>(w + c.edges);
+  double* d_zb = reinterpret_cast<double*>(w + c.zb);
+  double* d_psum = reinterpret_cast<double*>(w + c.psum);
+  int64_t* d_pcnt = reinterpret_cast<int64_t*>(w + c.pcnt);
+  double* d_part = reinterpret_cast<double*>(w + c.part);
+  double* d_mom = reinterpret_cast<double*>(w + c.mom);
+  memset(res, 0, sizeof(*res));
+
+  // moments of the stored pixels
+  hipLaunchKernelGGL(k_moments, dim3(kMomBlocks), dim3(kMomNT), 0, st, sk->n_sk, sk->npix, sk->offset, spec->dens_l,
+                     spec->eta, d_part);
+  hipLaunchKernelGGL(k_moments_reduce, dim3(5), dim3(kMomBlocks), 0, st, d_part, d_mom);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return phip(e, "moments");
+  double mom[5];
+  std::vector<int32_t> npix(sk->n_sk);
+  if ((e = hipMemcpyAsync(mom, d_mom, sizeof(mom), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(npix.data(), sk->npix, sizeof(int32_t) * sk->n_sk, hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return phip(e, "moments read-back");
+  double n_tot = 0.0;
+  for (int32_t v : npix) n_tot += v;
+  if (!(n_tot > 0.0)) return pfail(LYA_EINVAL, "no stored pixels");
+  const double ml = mom[0] / n_tot, me = mom[1] / n_tot;
+  const double sl2 = mom[2] / n_tot - ml * ml, se2 = mom[3] / n_tot - me * me, cov = mom[4] / n_tot - ml * me;
+  res->sigma2[0] = sl2;
+  res->sigma2[1] = se2;
+  res->sigma2[2] = cov;
+
+  std::vector<double> kv(nk + 1);
+  if ((e = hipMemcpyAsync(kv.data(), spec->p1d.k_edges, sizeof(double) * (nk + 1), hipMemcpyDeviceToHost, st)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return phip(e, "k edges read-back");
+  const double zb_edges[2] = {-1e30, 1e30};
+  lya_zbins zb{1, d_zb, d_zb + 2, reinterpret_cast<int64_t*>(d_zb + 3)};
+  lya_ps1d ps{spec->ps_amp, spec->ps_kcut, spec->p1d.dpix, 0};
+  lya_ps_table tab{nk, d_edges, d_ratio};
+
+  for (int z = 0; z < spec->n_zt; ++z) {
+    const double zt = spec->z_t[z], ct = spec->c_t[z], ft = spec->fbar_t[z];
+    const double* pt = spec->p1d_t + static_cast<size_t>(z) * nk;
+    if (!(ft > 0.0 && ft < 1.0)) return pfail(LYA_EINVAL, "target mean flux must lie in (0, 1)");
+    double sigf = spec->sigf_t[z];
+    if (!(sigf > 0.0)) {
+      double v = 0.0;
+      for (int b = 0; b < nk; ++b)
+        if (isfinite(pt[b])) v += pt[b] * (kv[b + 1] - kv[b]);
+      sigf = ft * sqrt(v / M_PI);
+    }
+    double a = 0.0, s = 0.0;
+    if (!(sigf > 0.0) || !fit_a_s(ft, sigf, &a, &s))
+      return pfail(LYA_EINVAL, "no (a, b sigma_g) reaches the target mean flux and dispersion");
+    const double opz = 1.0 + zt;
+    const double E = sqrt(spec->cosmo.omega_m * opz * opz * opz + 1.0 - spec->cosmo.omega_m);
+    const double dvdchi = 100.0 * E / opz;
+    std::vector<double> ek(nk + 1);
+    for (int b = 0; b <= nk; ++b) ek[b] = kv[b] * dvdchi;
+    std::vector<double> ratio(nk, 1.0);
+    std::vector<float> ratio32(nk);
+    std::vector<double> psum(nk);
+    std::vector<int64_t> pcnt(nk);
+    double fbar = 0.0, b_used = 0.0;
+    for (int it = 0; it < spec->n_iter; ++it) {
+      const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
+      const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
+      if (!(sg2 > 0.0)) return pfail(LYA_EINVAL, "sigma_g^2 is not positive");
+      b_used = s / sqrt(sg2);
+      for (int b = 0; b < nk; ++b) ratio32[b] = static_cast<float>(ratio[b]);
+      if ((e = hipMemcpyAsync(d_ratio, ratio32.data(), sizeof(float) * nk, hipMemcpyHostToDevice, st)) !=
+              hipSuccess ||
+          (e = hipMemcpyAsync(d_edges, ek.data(), sizeof(double) * (nk + 1), hipMemcpyHostToDevice, st)) !=
+              hipSuccess ||
+          (e = hipMemcpyAsync(d_zb, zb_edges, sizeof(zb_edges), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return phip(e, "table upload");
+      lya_fgpa fg{};
+      fg.coef[0][0] = a;
+      fg.coef[1][0] = b_used;
+      fg.coef[2][0] = ct;
+      int rc = lya_apply_fgpa_ds(sk, &spec->cosmo, spec->dens_l, spec->eta, &ps, &tab, spec->seed, &fg, flux, &zb,
+                                 w + c.sk, c.p1d - c.sk, stream);
+      if (rc != LYA_OK) {
+        snprintf(g_perr, sizeof(g_perr), "lya_apply_fgpa_ds: %s", lya_last_error());
+        return rc;
+      }
+      lya_p1d_spec pspec = spec->p1d;
+      pspec.z_ref = zt;
+      rc = lya_p1d(sk, &spec->cosmo, flux, &zb, &pspec, d_psum, d_pcnt, w + c.p1d, c.flux - c.p1d, stream);
+      if (rc != LYA_OK) {
+        snprintf(g_perr, sizeof(g_perr), "lya_p1d: %s", lya_last_error());
+        return rc;
+      }
+      double zsum[2];
+      if ((e = hipMemcpyAsync(zsum, d_zb + 2, sizeof(zsum), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (e = hipMemcpyAsync(psum.data(), d_psum, sizeof(double) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (e = hipMemcpyAsync(pcnt.data(), d_pcnt, sizeof(int64_t) * nk, hipMemcpyDeviceToHost, st)) !=
+              hipSuccess ||
+          (e = hipStreamSynchronize(st)) != hipSuccess)
+        return phip(e, "statistics read-back");
+      int64_t count;
+      memcpy(&count, &zsum[1], sizeof(count));
+      fbar = count > 0 ? zsum[0] / static_cast<double>(count) : NAN;
+      double se = 0.0;
+      int ne = 0;
+      for (int b = 0; b < nk; ++b) {
+        const double p = pcnt[b] > 0 ? psum[b] / static_cast<double>(pcnt[b]) : NAN;
+        res->p1d[z * 64 + b] = p;
+        res->ratio[z * 64 + b] = ratio[b];
+        if (isfinite(pt[b]) && isfinite(p) && pt[b] != 0.0) {
+          se += (p / pt[b] - 1.0) * (p / pt[b] - 1.0);
+          ++ne;
+        }
+      }
+      res->fbar[z * LYA_TUNE_PS_MAX_ITER + it] = fbar;
+      res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = ne ? sqrt(se / ne) : NAN;
+      // P_s^{n+1} = P_s^n P_target / P1D in every bin with both values
+      for (int b = 0; b < nk; ++b) {
+        const double p = res->p1d[z * 64 + b];
+        if (isfinite(pt[b]) && isfinite(p) && p > 0.0) ratio[b] *= pt[b] / p;
+      }
+    }
+    res->a[z] = a;
+    res->b[z] = b_used;
+    res->s[z] = s;
+  }
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return LYA_OK;
+}
+
+}  // extern "C"

@@ -19,6 +19,7 @@ COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 
 
 EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta",
            "lya_draw_skewers", "lya_draw_skewers_gauss", "lya_draw_skewers_wide", "lya_apply_fgpa",
+           "lya_apply_fgpa_ds", "lya_tune_ps_workspace_size", "lya_tune_ps", "lya_tune_ps_last_error",
            "lya_p1d_workspace_size", "lya_p1d",
            "lya_tune_workspace_size",
            "lya_tune_params", "lya_emulator_labels", "lya_emulator_bytes", "lya_emulator_param_offset",
@@ -292,6 +293,30 @@ class TuneResult(ctypes.Structure):
                 ("coef", (ctypes.c_double * 3) * 3), ("seconds", ctypes.c_double)]
 
 
+TUNE_PS_MAX_ITER = 16
+
+
+class PsTable(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("k_edges", ctypes.c_void_p), ("ratio", ctypes.c_void_p)]
+
+
+class TunePsSpec(ctypes.Structure):
+    _fields_ = [("sk", ctypes.POINTER(Skewers)), ("dens_l", ctypes.c_void_p), ("eta", ctypes.c_void_p),
+                ("n_pixels", ctypes.c_int64), ("cosmo", Cosmo), ("seed", ctypes.c_uint64), ("n_zt", ctypes.c_int32),
+                ("z_t", ctypes.c_double * TUNE_MAX_Z), ("c_t", ctypes.c_double * TUNE_MAX_Z),
+                ("fbar_t", ctypes.c_double * TUNE_MAX_Z), ("sigf_t", ctypes.c_double * TUNE_MAX_Z),
+                ("p1d_t", ctypes.c_void_p), ("p1d", P1dSpec), ("ps_amp", ctypes.c_double),
+                ("ps_kcut", ctypes.c_double), ("n_iter", ctypes.c_int32)]
+
+
+class TunePsResult(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double * TUNE_MAX_Z), ("b", ctypes.c_double * TUNE_MAX_Z),
+                ("s", ctypes.c_double * TUNE_MAX_Z), ("sigma2", ctypes.c_double * 3),
+                ("ratio", ctypes.c_double * (TUNE_MAX_Z * 64)), ("p1d", ctypes.c_double * (TUNE_MAX_Z * 64)),
+                ("fbar", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)),
+                ("rms", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)), ("seconds", ctypes.c_double)]
+
+
 FFT_VARIANTS = 14
 SK_CHUNKS = (1, 2, 4, 8, 16, 32, 64)
 SK_BLOCKS_PER_CU = (1, 2, 3, 4)
@@ -356,6 +381,14 @@ def _bind_more(lib):
     lib.lya_graph_destroy.argtypes = [VP]
     lib.lya_autotune_last_error.restype = ctypes.c_char_p
     lib.lya_chi_of_z.argtypes = [P(Cosmo), ctypes.c_int32, VP, VP]
+    lib.lya_apply_fgpa_ds.restype = ctypes.c_int
+    lib.lya_apply_fgpa_ds.argtypes = [P(Skewers), P(Cosmo), VP, VP, P(Ps1d), P(PsTable), ctypes.c_uint64, P(Fgpa),
+                                      VP, P(ZBins), VP, ctypes.c_size_t, VP]
+    lib.lya_tune_ps_workspace_size.restype = ctypes.c_size_t
+    lib.lya_tune_ps_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+    lib.lya_tune_ps.restype = ctypes.c_int
+    lib.lya_tune_ps.argtypes = [P(TunePsSpec), P(TunePsResult), VP, ctypes.c_size_t, VP]
+    lib.lya_tune_ps_last_error.restype = ctypes.c_char_p
 
 
 def _lib2():
@@ -380,6 +413,28 @@ def p1d(sk, cosmo, flux, fbar_zbins, spec, psum, pcount, work, stream=None):
     _check(_lib2().lya_p1d(ctypes.byref(sk), ctypes.byref(cosmo), _ptr(flux), ctypes.byref(fbar_zbins),
                            ctypes.byref(spec), _ptr(psum), _ptr(pcount), _ptr(work),
                            work.numel() * work.element_size(), _stream(stream)))
+
+
+def apply_fgpa_ds(sk, cosmo, dens_l, eta, ps, table, seed, fgpa, flux, zbins, work, stream=None):
+    """lya_apply_fgpa_ds (see include/lyamock.h); table: PsTable or None."""
+    _check(_lib2().lya_apply_fgpa_ds(ctypes.byref(sk), ctypes.byref(cosmo), _ptr(dens_l), _ptr(eta),
+                                     ctypes.byref(ps), ctypes.byref(table) if table is not None else None, int(seed),
+                                     ctypes.byref(fgpa), _ptr(flux), ctypes.byref(zbins) if zbins is not None else None,
+                                     _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def tune_ps_workspace_size(n_sk, n_pixels, n_kbins):
+    return int(_lib2().lya_tune_ps_workspace_size(int(n_sk), int(n_pixels), int(n_kbins)))
+
+
+def tune_ps(spec, work, stream=None):
+    """lya_tune_ps: returns a TunePsResult."""
+    res = TunePsResult()
+    rc = _lib2().lya_tune_ps(ctypes.byref(spec), ctypes.byref(res), _ptr(work), work.numel() * work.element_size(),
+                             _stream(stream))
+    if rc != LYA_OK:
+        raise LyaError(rc, _lib2().lya_tune_ps_last_error().decode())
+    return res
 
 
 def tune_workspace_size(n_sk, n_kbins):
