@@ -55,15 +55,23 @@ typedef struct {
   int32_t storage;  /* LYA_F32 or LYA_BF16 element type of the output box */
 } lya_box;
 
-/* Linear power spectrum, stand-in for the paper's CAMB P_m(k) (eq:deltaL):
+/* Linear power spectrum (eq:deltaL).  Either the analytic stand-in for the
+ * paper's CAMB P_m(k):
  *   P(k) = A k^ns T_BBKS(k/gamma)^2 (1 + wig_amp sin(k wig_r) exp(-(k/wig_kd)^2)),
- * A set so that sigma_8 = sigma8.  k in h/Mpc, P in (Mpc/h)^3. */
+ * A set so that sigma_8 = sigma8; or, when k_tab is not NULL, a table such as
+ * CAMB's: ln P linear in ln k between the nodes (k_tab increasing, k_tab > 0,
+ * p_tab > 0; device arrays of n_tab >= 2 doubles), the end intervals' power
+ * laws continued outside, used as given (sigma8 and the shape parameters are
+ * then ignored).  k in h/Mpc, P in (Mpc/h)^3. */
 typedef struct {
   double sigma8, ns, gamma, wig_amp, wig_r, wig_kd;
   double smooth;     /* Gaussian window sigma in Mpc/h on the mode amplitude, 0 = off
                         (the paper's smoothing, Appendix B, W^2 = exp(-dx^2 k^2), is smooth = dx) */
   int32_t fixed_amp; /* 1: |W(k)| = 1 (fixed-amplitude test hook) */
   int32_t only_n2;   /* >= 0: keep only the modes with |n|^2 == only_n2 (test hook); -1: all */
+  const double* k_tab;  /* NULL: analytic form */
+  const double* p_tab;
+  int32_t n_tab;
 } lya_pk;
 
 /* Quasar lines of sight.  Pixel j (0 <= j < npix[q]) of skewer q sits at the

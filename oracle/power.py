@@ -88,6 +88,21 @@ class PowerSpectrum:
         return self.amp * pk_shape(k, **self.params)
 
 
+class TabulatedPower:
+    """P(k) from a table (the paper's CAMB spectrum is one): ln P linear in
+    ln k between the nodes, the end intervals' power laws continued outside."""
+
+    def __init__(self, k_tab, p_tab):
+        self.lk = np.log(np.asarray(k_tab, dtype=np.float64))
+        self.lp = np.log(np.asarray(p_tab, dtype=np.float64))
+
+    def __call__(self, k):
+        x = np.log(np.asarray(k, dtype=np.float64))
+        i = np.clip(np.searchsorted(self.lk, x, side="right") - 1, 0, len(self.lk) - 2)
+        t = (x - self.lk[i]) / (self.lk[i + 1] - self.lk[i])
+        return np.exp(self.lp[i] + t * (self.lp[i + 1] - self.lp[i]))
+
+
 def amplitude_table(pk, n, dx, smooth=0.0):
     """s(n^2) for every integer n^2 in [0, 3 (n/2)^2] (index = n^2)."""
     L = n * dx

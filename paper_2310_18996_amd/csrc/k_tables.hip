@@ -9,6 +9,8 @@
 //   A from sigma8: sigma_8^2 = 1/(2 pi^2) int k^3 P W_TH(8k)^2 dln k with the
 //   sphere window W_TH(x) = 3 (sin x - x cos x)/x^3, composite Simpson in
 //   ln k over [1e-5, 1e3] h/Mpc with 2^16+1 nodes.
+// A tabulated P(k) (the paper's CAMB table) replaces the analytic form and its
+// sigma8 normalisation when given.
 // Amplitude per mode (eq:deltaL with unit-variance complex noise):
 //   s(n^2) = sqrt(P(2 pi |n| / L) / L^3) * exp(-k^2 smooth^2 / 2), s(0) = 0.
 // Pixel redshift (section "FGPA": unperturbed cosmological redshift), flat
@@ -81,6 +83,29 @@ __global__ void __launch_bounds__(256) k_pk_finalize(PkParams p, const double* p
   }
 }
 
+// Tabulated P(k): ln P linear in ln k between the nodes; below the first and
+// above the last node the end intervals' power laws continue.
+__device__ __forceinline__ double pk_tabulated(double k, const PkParams& p) {
+  const double* kt = p.k_tab;
+  const int n = p.n_tab;
+  int i;   // interval [kt[i], kt[i+1]]
+  if (k <= kt[0]) {
+    i = 0;
+  } else if (k >= kt[n - 1]) {
+    i = n - 2;
+  } else {
+    int lo = 0, hi = n - 1;   // kt[lo] <= k < kt[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (kt[mid] <= k) lo = mid; else hi = mid;
+    }
+    i = lo;
+  }
+  const double x0 = log(kt[i]), x1 = log(kt[i + 1]);
+  const double y0 = log(p.p_tab[i]), y1 = log(p.p_tab[i + 1]);
+  return exp(y0 + (y1 - y0) * (log(k) - x0) / (x1 - x0));
+}
+
 __global__ void __launch_bounds__(256) k_amp_table(const double* amp, PkParams p, double L, int nentries, float* table) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nentries) return;
@@ -89,7 +114,8 @@ __global__ void __launch_bounds__(256) k_amp_table(const double* amp, PkParams p
     return;
   }
   const double k = 2.0 * M_PI * sqrt(static_cast<double>(e)) / L;
-  double s = sqrt(amp[0] * pk_shape(k, p) / (L * L * L));
+  const double P = p.k_tab ? pk_tabulated(k, p) : amp[0] * pk_shape(k, p);
+  double s = sqrt(P / (L * L * L));
   if (p.smooth > 0.0) s *= exp(-0.5 * (k * p.smooth) * (k * p.smooth));
   table[e] = static_cast<float>(s);
 }

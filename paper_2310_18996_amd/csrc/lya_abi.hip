@@ -76,15 +76,20 @@ int make_pair(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int
   if (!work) return fail(LYA_EINVAL, "work is NULL%s");
   if (ca < LYA_C_DELTA || ca > LYA_C_YZ || cb < LYA_C_NONE || cb > LYA_C_YZ)
     return fail(LYA_EINVAL, "unknown field component%s");
-  if (!(pk->sigma8 > 0.0) || !(pk->gamma > 0.0) || !(pk->wig_kd > 0.0) || pk->smooth < 0.0)
+  if (pk->k_tab) {
+    if (!pk->p_tab || pk->n_tab < 2 || pk->smooth < 0.0)
+      return fail(LYA_EINVAL, "tabulated P(k) needs p_tab and n_tab >= 2%s");
+  } else if (!(pk->sigma8 > 0.0) || !(pk->gamma > 0.0) || !(pk->wig_kd > 0.0) || pk->smooth < 0.0) {
     return fail(LYA_EINVAL, "invalid power-spectrum parameters%s");
+  }
   const BoxCarve c = carve_box(box);
   if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the box%s");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(work);
   lya::TableWork tw{reinterpret_cast<double*>(w + c.partial), reinterpret_cast<double*>(w + c.amp),
                     reinterpret_cast<float2*>(w + c.tw), reinterpret_cast<float*>(w + c.table)};
-  lya::PkParams p{pk->sigma8, pk->ns, pk->gamma, pk->wig_amp, pk->wig_r, pk->wig_kd, pk->smooth};
+  lya::PkParams p{pk->sigma8, pk->ns, pk->gamma, pk->wig_amp, pk->wig_r, pk->wig_kd, pk->smooth,
+                  pk->k_tab, pk->p_tab, pk->n_tab};
   hipError_t e = lya::launch_pk_table(p, box->n, box->dx, tw, st);
   if (e != hipSuccess) return hip_fail(e, "power-spectrum table");
   lya::GenParams g{tw.table, seed, static_cast<float>(f), ca, cb, pk->fixed_amp ? 1 : 0, pk->only_n2};

@@ -19,6 +19,11 @@ constexpr float kFgpaX0 = 3.5f;           // centre (in 1+z) of the FGPA quadrat
 
 struct PkParams {
   double sigma8, ns, gamma, wig_amp, wig_r, wig_kd, smooth;
+  // tabulated P(k) (device, n_tab >= 2, k increasing): used instead of the
+  // analytic form when k_tab is not null
+  const double* k_tab;
+  const double* p_tab;
+  int n_tab;
 };
 
 inline int amp_table_entries(int n) { return 3 * (n / 2) * (n / 2) + 1; }

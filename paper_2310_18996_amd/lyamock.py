@@ -44,7 +44,8 @@ class Box(ctypes.Structure):
 class Pk(ctypes.Structure):
     _fields_ = [("sigma8", ctypes.c_double), ("ns", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("wig_amp", ctypes.c_double), ("wig_r", ctypes.c_double), ("wig_kd", ctypes.c_double),
-                ("smooth", ctypes.c_double), ("fixed_amp", ctypes.c_int32), ("only_n2", ctypes.c_int32)]
+                ("smooth", ctypes.c_double), ("fixed_amp", ctypes.c_int32), ("only_n2", ctypes.c_int32),
+                ("k_tab", ctypes.c_void_p), ("p_tab", ctypes.c_void_p), ("n_tab", ctypes.c_int32)]
 
 
 class Skewers(ctypes.Structure):
@@ -142,8 +143,13 @@ def box_struct(n, dx, storage=LYA_F32):
 
 
 def pk_struct(sigma8=0.8, ns=0.96, gamma=0.21, wig_amp=0.05, wig_r=105.0, wig_kd=0.2, smooth=0.0,
-              fixed_amp=False, only_n2=-1):
-    return Pk(sigma8, ns, gamma, wig_amp, wig_r, wig_kd, smooth, int(bool(fixed_amp)), int(only_n2))
+              fixed_amp=False, only_n2=-1, k_tab=None, p_tab=None):
+    """lya_pk; k_tab/p_tab: device float64 tensors of a tabulated P(k) (both or neither)."""
+    if (k_tab is None) != (p_tab is None):
+        raise ValueError("k_tab and p_tab go together")
+    n_tab = 0 if k_tab is None else int(k_tab.numel())
+    return Pk(sigma8, ns, gamma, wig_amp, wig_r, wig_kd, smooth, int(bool(fixed_amp)), int(only_n2),
+              None if k_tab is None else k_tab.data_ptr(), None if p_tab is None else p_tab.data_ptr(), n_tab)
 
 
 def field_elems(box):

@@ -112,3 +112,24 @@ def test_box_lines_against_c_oracle(L, n):
         line = gt[mx, my].cpu().numpy().astype(np.float64)
         assert rel_rms(line[:, 0], re[l]) < TOL, (mx, my)
         assert rel_rms(line[:, 1], im[l]) < TOL, (mx, my)
+
+
+def test_tabulated_power_spectrum(L):
+    # a table unlike the analytic form (a log-periodic modulation) through
+    # lya_pk.k_tab / p_tab against the oracle's box from the same table
+    import torch
+    from oracle import power
+    n, dx, seed = 64, 2.19, 21
+    k = np.geomspace(1e-3, 20.0, 400)
+    p = power.PowerSpectrum()(k) * (1.0 + 0.3 * np.sin(3.0 * np.log(k)))
+    kt = torch.from_numpy(k).cuda()
+    pt = torch.from_numpy(p).cuda()
+    got = gpu_box(L, n, dx, seed, 1.0, k_tab=kt, p_tab=pt).cpu().numpy()
+    ref = field.make_box(n, seed, power.amplitude_table(power.TabulatedPower(k, p), n, dx), ("delta", "zz"))
+    e = (rel_rms(got[..., 0], ref.real), rel_rms(got[..., 1], ref.imag))
+    print("tabulated P(k) rel rms delta %.2e eta %.2e" % e)
+    assert max(e) < 1e-5
+    with pytest.raises(ValueError):
+        L.pk_struct(k_tab=kt)
+    with pytest.raises(L.LyaError):
+        gpu_box(L, n, dx, seed, 1.0, k_tab=kt[:1], p_tab=pt[:1])

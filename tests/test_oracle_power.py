@@ -66,3 +66,24 @@ def test_amplitude_table():
     assert abs(tab[5] - np.sqrt(pk(k) / L ** 3)) < 1e-15 * tab[5] * 10
     sm = power.amplitude_table(pk, n, dx, smooth=dx)
     assert abs(sm[5] / tab[5] - np.exp(-0.5 * (k * dx) ** 2)) < 1e-14
+
+
+def test_tabulated_power_nodes_and_power_laws():
+    k = np.geomspace(1e-3, 10.0, 40)
+    pk = power.PowerSpectrum()
+    tab = power.TabulatedPower(k, pk(k))
+    np.testing.assert_allclose(tab(k), pk(k), rtol=1e-13)           # exact at the nodes
+    # a pure power law is a straight line in log-log: reproduced everywhere,
+    # extrapolation included
+    law = power.TabulatedPower(k, 3.0 * k ** -1.7)
+    kk = np.geomspace(1e-5, 1e3, 101)
+    np.testing.assert_allclose(law(kk), 3.0 * kk ** -1.7, rtol=1e-12)
+
+
+def test_dense_table_reproduces_the_analytic_amplitudes():
+    pk = power.PowerSpectrum()
+    k = np.geomspace(1e-4, 1e2, 20000)
+    tab = power.TabulatedPower(k, pk(k))
+    a = power.amplitude_table(pk, 64, 2.19)
+    b = power.amplitude_table(tab, 64, 2.19)
+    np.testing.assert_allclose(b[1:], a[1:], rtol=2e-6)
