@@ -28,7 +28,7 @@ def test_inverse_roundtrip():
     np.testing.assert_allclose(cz.z_of_chi(cz.chi_of_z(z)), z, rtol=1e-12, atol=1e-13)
 
 
-def test_survey_scale_values():
+def test_forest_distance_scale():
     # order-of-magnitude anchors for the workload geometry (Mpc/h)
     assert 3300 < cz.chi_of_z(1.8) < 3450
     assert 4650 < cz.chi_of_z(3.6) < 4850
