@@ -172,3 +172,27 @@ def test_error_paths(L):
     with pytest.raises(L.LyaError) as ei:
         L.make_box(box, L.pk_struct(), 1, 1.0, True, f, torch.empty(16, dtype=torch.uint8, device="cuda"))
     assert ei.value.code == L.LYA_EWORKSPACE
+
+
+@pytest.mark.parametrize("mode", ["gauss", "wide"])
+def test_empty_and_degenerate_variants(L, mode):
+    # no skewers, and zero-length skewers among others, through the Gaussian-
+    # kernel and wide-angle passes; a zero box gives F = exp(-a) exactly
+    import torch
+    n, dx = 32, 2.19
+    zero = padded_box(L, np.zeros((n, n, n, 2), np.float32))
+    fld = [zero, zero, zero, zero] if mode == "wide" else zero
+    kw = dict(gauss=True) if mode == "gauss" else {}
+    sk = dict(origin_fx=np.zeros((0, 3), np.int64), step_fx=np.zeros((0, 3), np.int64),
+              npix=np.zeros(0, np.int32), offset=np.zeros(0, np.int64), chi0=np.zeros(0), dchi=0.2, id_base=0)
+    out = gpu_skewers(L, fld, n, dx, sk, 1, 1.0, 1.5, 0.2, mockinputs.FGPA_MID, np.array([1000.0, 3000.0]), **kw)
+    np.testing.assert_array_equal(out["count"], [0])
+    sk = dict(origin_fx=np.array([[0, 0, 0], [5 * 2 ** 32, 7 * 2 ** 31, 3], [0, 0, 0]], np.int64),
+              step_fx=np.array([[0, 0, 2 ** 28], [2 ** 27, -2 ** 27, 2 ** 28], [0, 0, 0]], np.int64),
+              npix=np.array([0, 70, 0], np.int32), offset=np.array([0, 0, 70], np.int64),
+              chi0=np.full(3, 2500.0), dchi=0.2, id_base=0)
+    out = gpu_skewers(L, fld, n, dx, sk, 1, 0.0, 1.5, 0.2, [[0.5, 0, 0], [1.6, 0, 0], [1.0, 0, 0]],
+                      np.array([2000.0, 3000.0]), **kw)
+    np.testing.assert_array_equal(out["count"], [70])
+    np.testing.assert_allclose(out["flux"][:70], np.exp(-0.5), rtol=1e-6)
+    np.testing.assert_array_equal(out["dens"][:70], 0.0)
