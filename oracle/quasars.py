@@ -21,16 +21,33 @@ Readings (the paper is silent on these):
   length, normally the voxel side, the paper's window W^2 = exp(-dx^2 k^2));
   without a cut-off the transform of a CDM-like P diverges at r -> 0;
 * G is the growing mode of flat LCDM, D(a) proportional to
-  E(a) int_0^a da' / (a' E(a'))^3, normalised to G(0) = 1;
+  E(a) int_0^a da' / (a' E(a'))^3, normalised to G(0) = 1.  Appendix A
+  equates a(z) = sqrt(xi_mod / xi_0) with b_q(z) (1 + z_0) / (b_q(z_0) (1 + z)),
+  which holds when G is proportional to 1/(1+z) (matter domination, true to
+  about 1% over 1.9 < z < 3.6); the quasar fields therefore use
+  G_q(z) = G(z_ref) (1 + z_ref) / (1 + z), z_ref the middle box (or the only
+  one), and the box of redshift z_i takes b_0 = b_q(z_i) G_q(z_i).  With the
+  exact LCDM growth instead, the three-box combination misses the model by
+  about 1e-3 rather than the paper's 5e-4;
 * the probability of voxel m (grid point, x = m dx) is
-  p = nbar(z) dx^3 exp(alpha delta_q - alpha^2 sigma_q^2 / 2), capped at 1, with
-  z = z(|x - O|) for the observer O, nbar a tabulated comoving density
-  (linear in z, zero outside the table) and sigma_q^2 the grid variance of
-  delta_q (so the mean of the exponential factor is one);
-* Philox4x32-10 stream 2, counter = the voxel's linear index m_x N^2 +
-  m_y N + m_z: word 0 as the uniform u = ((w >> 9) + 1/2) 2^-23 decides
-  (u < p); words 1-3 give the position in cell units times 2^32,
-  (m << 32) - 2^31 + w, uniform over the voxel [m - 1/2, m + 1/2).
+  p = nbar(z) dx^3 sum_i c_i(z) exp(a_i(z) delta_i - a_i(z)^2 sigma_i^2 / 2),
+  clipped to [0, 1], with z = z(|x - O|) for the observer O, nbar a tabulated
+  comoving density (linear in z, zero outside the table), sigma_i^2 the
+  variance of box i (the mean of each exponential factor is then one) and
+  a_i(z) = b_q(z) (1 + z_i) / (b_q(z_i) (1 + z)) (Appendix A);
+* one box: c_1 = 1.  Three boxes (Appendix A): p_12 interpolates p_1, p_2
+  linearly in z, p_23 extrapolates p_2, p_3 linearly in z, and
+  p = w p_12 + (1 - w) p_23 with w fixed at r = 5 Mpc/h by
+  w xi_12 + (1 - w) xi_23 = xi_mod, where xi_i = (1 + xi_0i)^(a_i^2) - 1,
+  xi_0i = b_0i^2 xi_m(5), xi_mod = (b_q(z) G_q(z))^2 xi_m(5) and xi_12, xi_23
+  the same linear combinations of the xi_i; w = 1/2 where xi_12 = xi_23
+  (then p_12 = p_23); w is clipped to [0, 1];
+* random numbers: the decision of voxel m uses Philox4x32-10 stream 2,
+  counter m >> 2, word m & 3 (one call serves four consecutive voxels), as
+  the uniform u = ((w >> 9) + 1/2) 2^-23, and selects when u < p; the
+  position of a selected voxel uses stream 4, counter m, words 0-2: per axis
+  (m_axis << 32) - 2^31 + w in cell units times 2^32, uniform over the voxel
+  [m - 1/2, m + 1/2).
 """
 import numpy as np
 from scipy import integrate
@@ -90,24 +107,70 @@ def lognormal_pk(pk, b0, smooth, k, rmax=2000.0, nr=4001):
     return pq_of_k(spl, k, rmax)
 
 
-def draw(delta_q, dx, observer, z0, nbar_z, nbar, seed, omega_m=cosmology.OMEGA_M):
-    """Selected voxels and quasar positions.  Returns (lin index sorted,
-    positions fx [M, 3] int64, probability p and uniform u of every voxel)."""
-    n = delta_q.shape[0]
+def growth_q(z, z_ref, omega_m=cosmology.OMEGA_M):
+    """G_q(z) = G(z_ref) (1 + z_ref) / (1 + z)."""
+    return growth(z_ref, omega_m) * (1.0 + z_ref) / (1.0 + np.asarray(z, dtype=np.float64))
+
+
+def box_bias2(z_box, z_ref, omega_m=cosmology.OMEGA_M):
+    """b_0^2 of the box at z_box: (b_q(z_box) G_q(z_box))^2."""
+    return float((bias_qso(z_box) * growth_q(z_box, z_ref, omega_m)) ** 2)
+
+
+def mix_coeffs(z, z_box, xi5, omega_m=cosmology.OMEGA_M):
+    """(c_1, c_2, c_3) of the three-box combination at redshift z (scalar)."""
+    z1, z2, z3 = (float(v) for v in z_box)
+    a = [float(alpha_of_z(z, zi)) for zi in (z1, z2, z3)]
+    xi = [(1.0 + box_bias2(zi, z2, omega_m) * xi5) ** (ai * ai) - 1.0 for zi, ai in zip((z1, z2, z3), a)]
+    xi_mod = float(bias_qso(z) * growth_q(z, z2, omega_m)) ** 2 * xi5
+    t12 = (z - z1) / (z2 - z1)
+    t23 = (z - z2) / (z3 - z2)
+    xi12 = (1.0 - t12) * xi[0] + t12 * xi[1]
+    xi23 = (1.0 - t23) * xi[1] + t23 * xi[2]
+    den = xi12 - xi23
+    w = 0.5 if abs(den) <= 1e-12 * abs(xi[1]) else min(max((xi_mod - xi23) / den, 0.0), 1.0)
+    return np.array([w * (1.0 - t12), w * t12 + (1.0 - w) * (1.0 - t23), (1.0 - w) * t23])
+
+
+def probability(fields, dx, observer, z_box, sigma2, nbar_z, nbar, xi5=None, omega_m=cosmology.OMEGA_M):
+    """p of every voxel (flat, linear index order) and its redshift."""
+    n = fields[0].shape[0]
     m = np.arange(n)
     gx, gy, gz = np.meshgrid(m, m, m, indexing="ij")
     pos = np.stack([gx, gy, gz], axis=-1).astype(np.float64) * dx
-    chi = np.sqrt(np.sum((pos - np.asarray(observer, dtype=np.float64)) ** 2, axis=-1))
-    z = cosmology.z_of_chi(chi.ravel(), omega_m).reshape(chi.shape)
-    al = alpha_of_z(z, z0)
-    s2 = float(np.mean(delta_q ** 2))
+    chi = np.sqrt(np.sum((pos - np.asarray(observer, dtype=np.float64)) ** 2, axis=-1)).ravel()
+    z = cosmology.z_of_chi(chi, omega_m)
     nb = np.interp(z, nbar_z, nbar, left=0.0, right=0.0)
-    p = np.minimum(nb * dx ** 3 * np.exp(al * delta_q - 0.5 * al * al * s2), 1.0)
-    lin = ((gx.astype(np.int64) * n + gy) * n + gz).ravel()
-    w = philox.words(seed, 2, lin)          # [V, 4], 32-bit values
-    u = ((w[:, 0] >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
-    sel = u < p.ravel()
-    idx = lin[sel]
-    cells = np.stack([gx.ravel()[sel], gy.ravel()[sel], gz.ravel()[sel]], axis=1).astype(np.int64)
-    fx = (cells << 32) - (1 << 31) + w[sel][:, 1:4].astype(np.int64)
-    return idx, fx, p.ravel(), u, s2
+    if len(fields) == 1:
+        coef = np.ones((len(z), 1))
+    else:
+        coef = np.array([mix_coeffs(zz, z_box, xi5, omega_m) for zz in z])
+    acc = np.zeros(len(z))
+    for i, (f, zi, s2) in enumerate(zip(fields, z_box, sigma2)):
+        al = alpha_of_z(z, zi)
+        acc += coef[:, i] * np.exp(al * np.asarray(f, dtype=np.float64).ravel() - 0.5 * al * al * s2)
+    return np.clip(nb * dx ** 3 * acc, 0.0, 1.0), z
+
+
+def decision_uniforms(seed, n_vox):
+    lin = np.arange(n_vox, dtype=np.uint64)
+    w = philox.words(seed, 2, lin >> np.uint64(2))
+    wd = np.take_along_axis(w, (lin & np.uint64(3)).astype(np.int64)[:, None], axis=1)[:, 0]
+    return ((wd >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+
+
+def positions(seed, idx, n):
+    """Fixed-point positions of the selected voxels idx (linear indices)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    w = philox.words(seed, 4, idx.astype(np.uint64))
+    cells = np.stack([idx // (n * n), (idx // n) % n, idx % n], axis=1).astype(np.int64)
+    return (cells << 32) - (1 << 31) + w[:, 0:3].astype(np.int64)
+
+
+def draw(fields, dx, observer, z_box, sigma2, nbar_z, nbar, seed, xi5=None, omega_m=cosmology.OMEGA_M):
+    """Selected voxels (linear indices, increasing), their fixed-point
+    positions [M, 3], and p, u of every voxel."""
+    p, _ = probability(fields, dx, observer, z_box, sigma2, nbar_z, nbar, xi5, omega_m)
+    u = decision_uniforms(seed, p.size)
+    idx = np.flatnonzero(u < p)
+    return idx, positions(seed, idx, fields[0].shape[0]), p, u

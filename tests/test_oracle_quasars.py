@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 from scipy import integrate
 
-from oracle import cosmology, power, quasars
+from oracle import cosmology, philox, power, quasars
 
 pytestmark = pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
 
@@ -46,15 +46,58 @@ def test_lognormal_spectrum_linear_limit():
     np.testing.assert_allclose(pq, b0 * b0 * pk(k) * np.exp(-(k * s) ** 2), rtol=2e-3)
 
 
+def test_single_box_deviation_quoted_in_appendix_a():
+    # one box at z0 = 2.33 used at z = 3.6: (1 + xi0)^(a^2) - 1 exceeds a^2 xi0
+    # by about 18% at r = 10 Mpc/h (the paper's CAMB spectrum; the analytic
+    # stand-in gives about 17%)
+    xi_m = quasars.xi_of_r(power.PowerSpectrum(), [10.0], 0.5)[0]
+    xi0 = quasars.box_bias2(2.33, 2.33) * xi_m
+    a = quasars.alpha_of_z(3.6, 2.33)
+    dev = ((1.0 + xi0) ** (a * a) - 1.0) / (a * a * xi0) - 1.0
+    assert 0.14 < dev < 0.22
+
+
+def test_three_box_coefficients():
+    zb = (1.9, 2.75, 3.6)
+    xi5 = 0.82
+    for zi, want in zip(zb, np.eye(3)):
+        np.testing.assert_allclose(quasars.mix_coeffs(zi, zb, xi5), want, atol=1e-12)
+    for z in np.linspace(1.2, 4.2, 25):
+        np.testing.assert_allclose(np.sum(quasars.mix_coeffs(z, zb, xi5)), 1.0, rtol=1e-12)
+
+
+def test_three_box_model_within_the_quoted_bound():
+    # Appendix A: the combination reproduces b_q^2 G^2 xi_m to better than
+    # 5e-4 down to r = 5 Mpc/h; the correlation of each p_i is
+    # (1 + xi_0i)^(a_i^2) - 1 and the combination mixes them with the c_i
+    r = np.array([5.0, 7.0, 10.0, 15.0, 20.0, 30.0, 50.0])
+    xi = quasars.xi_of_r(power.PowerSpectrum(), r, 2.19)
+    zb = (1.9, 2.75, 3.6)
+    worst = 0.0
+    for z in np.linspace(1.95, 3.55, 17):
+        c = quasars.mix_coeffs(z, zb, xi[0])
+        comb = 0.0
+        for ci, zi in zip(c, zb):
+            a = quasars.alpha_of_z(z, zi)
+            comb = comb + ci * ((1.0 + quasars.box_bias2(zi, 2.75) * xi) ** (a * a) - 1.0)
+        model = (quasars.bias_qso(z) * quasars.growth(2.75) * 3.75 / (1.0 + z)) ** 2 * xi
+        worst = max(worst, np.max(np.abs(comb / model - 1.0)))
+    assert worst < 5e-4
+
+
+def _observer(n, dx, z):
+    return np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(z)])
+
+
 def test_draw_decisions_and_positions():
     rng = np.random.default_rng(4)
     n, dx, z0 = 8, 40.0, 2.5
     dq = rng.normal(scale=0.5, size=(n, n, n))
-    obs = np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(2.4)])
+    obs = _observer(n, dx, 2.4)
     zt = np.array([1.5, 2.5, 4.0])
     nb = np.array([2e-6, 5e-6, 1e-6])
-    idx, fx, p, u, s2 = quasars.draw(dq, dx, obs, z0, zt, nb, 11)
-    np.testing.assert_allclose(s2, np.mean(dq ** 2))
+    s2 = float(np.var(dq))
+    idx, fx, p, u = quasars.draw([dq], dx, obs, [z0], [s2], zt, nb, 11)
     # brute force on a few voxels, written out
     for lin in (0, 77, 300, 511):
         ix, iy, iz = lin // (n * n), (lin // n) % n, lin % n
@@ -63,24 +106,48 @@ def test_draw_decisions_and_positions():
         al = quasars.bias_qso(z) * (1 + z0) / (quasars.bias_qso(z0) * (1 + z))
         want = min(np.interp(z, zt, nb) * dx ** 3 * np.exp(al * dq[ix, iy, iz] - al * al * s2 / 2), 1.0)
         np.testing.assert_allclose(p[lin], want, rtol=1e-12)
+        # decision uniform: word lin % 4 of the call for counter lin // 4
+        w = philox.words(11, 2, np.array([lin // 4]))[0, lin % 4]
+        assert u[lin] == ((int(w) >> 9) + 0.5) * 2.0 ** -23
     np.testing.assert_array_equal(idx, np.flatnonzero(u < p))
-    cells = fx >> 32
-    frac = fx - (cells << 32)
-    # positions inside their voxel [m - 1/2, m + 1/2)
+    # positions inside their voxel [m - 1/2, m + 1/2), from stream 4
     centre = np.stack([idx // (n * n), (idx // n) % n, idx % n], axis=1)
     off = (fx - (centre << 32)).astype(np.float64) / 2 ** 32
     assert np.all(off >= -0.5) and np.all(off < 0.5)
-    assert np.all((frac >= 0) & (frac < 2 ** 32))
+    w4 = philox.words(11, 4, idx.astype(np.uint64))
+    np.testing.assert_array_equal(fx - (centre << 32) + (1 << 31), w4[:, :3].astype(np.int64))
+
+
+def test_draw_three_boxes_reduce_to_one():
+    # identical boxes at z1 = z2 = z3 spacing collapse: with the same field in
+    # each slot and z inside [z1, z3], sum c_i = 1 gives the one-box p when
+    # the alphas agree, i.e. for voxels at z = z_i; check at the middle box
+    rng = np.random.default_rng(8)
+    n, dx = 8, 10.0
+    dq = rng.normal(scale=0.4, size=(n, n, n))
+    s2 = float(np.var(dq))
+    zb = (1.9, 2.75, 3.6)
+    obs = _observer(n, dx, 2.75)
+    zt, nb = np.array([0.0, 9.0]), np.array([1e-3, 1e-3])
+    p3, z = quasars.probability([dq, dq, dq], dx, obs, zb, [s2] * 3, zt, nb, xi5=0.8)
+    p1, _ = quasars.probability([dq], dx, obs, [2.75], [s2], zt, nb)
+    near = np.abs(z - 2.75) < 2e-3
+    assert near.sum() > 0
+    np.testing.assert_allclose(p3[near], p1[near], rtol=2e-3)
 
 
 def test_draw_mean_count():
-    # with alpha delta_q normalised, the expected count is sum nbar dx^3
+    # each exponential factor has mean one, so the expected count is
+    # sum nbar dx^3 (here a constant 0.02 per voxel)
     rng = np.random.default_rng(5)
     n, dx, z0 = 16, 20.0, 2.5
     dq = rng.normal(scale=0.3, size=(n, n, n))
-    obs = np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(2.49)])
+    dq -= dq.mean()
+    s2 = float(np.var(dq))
+    obs = _observer(n, dx, 2.49)
     zt, nb = np.array([0.0, 10.0]), np.array([0.02 / dx ** 3, 0.02 / dx ** 3])
-    counts = [len(quasars.draw(dq, dx, obs, z0, zt, nb, s)[0]) for s in range(6)]
-    mean = np.mean(counts)
-    expect = 0.02 * n ** 3 * np.mean(np.exp(quasars.alpha_of_z(2.5, z0) * dq - 0.5 * np.mean(dq ** 2)))
-    assert abs(mean - expect) < 4 * np.sqrt(expect / 6) + 3
+    counts = [len(quasars.draw([dq], dx, obs, [z0], [s2], zt, nb, s)[0]) for s in range(6)]
+    p, _ = quasars.probability([dq], dx, obs, [z0], [s2], zt, nb)
+    expect = p.sum()
+    assert abs(np.mean(counts) - expect) < 4 * np.sqrt(expect / 6) + 3
+    assert abs(expect / (0.02 * n ** 3) - 1.0) < 0.05
