@@ -46,7 +46,7 @@ enum { LYA_C_NONE = -1, LYA_C_DELTA = 0, LYA_C_XX = 1, LYA_C_YY = 2, LYA_C_ZZ = 
        LYA_C_XY = 4, LYA_C_XZ = 5, LYA_C_YZ = 6 };
 
 /* Workspace kinds for lya_workspace_size. */
-enum { LYA_OP_BOX = 0, LYA_OP_SKEWERS = 1 };
+enum { LYA_OP_BOX = 0, LYA_OP_SKEWERS = 1, LYA_OP_QUASARS = 2 };
 
 /* Periodic box (section "Mock generation"). */
 typedef struct {
@@ -122,10 +122,11 @@ typedef struct {
 size_t lya_field_elems(const lya_box* box);
 size_t lya_plane_pitch(const lya_box* box);
 
-/* Bytes of device workspace a call needs.  op = LYA_OP_BOX for lya_make_box and
- * lya_make_eta (for LYA_BF16 storage this includes an n^3 complex64 staging box),
- * LYA_OP_SKEWERS for lya_draw_skewers and lya_apply_fgpa.  Returns 0 for
- * invalid arguments. */
+/* Bytes of device workspace a call needs.  op = LYA_OP_BOX for lya_make_box,
+ * lya_make_eta and lya_make_box_pair (for LYA_BF16 storage this includes an
+ * n^3 complex64 staging box), LYA_OP_SKEWERS for lya_draw_skewers and
+ * lya_apply_fgpa, LYA_OP_QUASARS for lya_box_moments and lya_draw_quasars.
+ * Returns 0 for invalid arguments. */
 size_t lya_workspace_size(int op, const lya_box* box);
 
 /* Gaussian box and line-of-sight velocity gradient (section "Mock generation",
@@ -144,6 +145,16 @@ int lya_make_box(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, 
  * lya_make_box. */
 int lya_make_eta(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int comp_a, int comp_b,
                  void* field, void* work, size_t work_bytes, void* stream);
+
+/* Two Gaussian fields of the same modes with different spectra (section
+ * "Quasar generation": the quasar-density field takes the original
+ * delta_hat(k) with the amplitudes sqrt(P_q/V)): writes {delta_a, delta_b},
+ * delta_a from pk_a in the real part and delta_b from pk_b in the imaginary
+ * part, each exactly what lya_make_box with that spectrum and seed writes as
+ * delta.  The test hooks fixed_amp and only_n2 of pk_a apply to both.  Same
+ * layout and workspace as lya_make_box. */
+int lya_make_box_pair(const lya_box* box, const lya_pk* pk_a, const lya_pk* pk_b, uint64_t seed, void* field,
+                      void* work, size_t work_bytes, void* stream);
 
 /* Ray-march every skewer through the box {delta, eta_par} (section "Gaussian
  * fields along lines of sight"): periodic trilinear interpolation at each
@@ -413,6 +424,72 @@ int lya_emulator_labels(const lya_tune_spec* spec, const double* draws, int64_t 
                         size_t work_bytes, void* stream);
 
 const char* lya_emulator_last_error(void);
+
+/* Lognormal quasar field (section "Quasar generation", Appendix A).
+ *
+ * lya_lognormal_pk: the quasar-density spectrum
+ *   P_q(k) = 4 pi int_0^rmax G(r) r^2 sin(kr)/(kr) dr,  G = ln(1 + b_0^2 xi_m(r)),
+ * xi_m(r) = 1/(2 pi^2) int P(k) exp(-k^2 s^2) k^2 sin(kr)/(kr) dk the
+ * correlation function of the matter spectrum pk smoothed by s = pk->smooth
+ * (> 0; the box's own window, so P_q needs no further smoothing), and
+ * b_0 = b_q(z_box) G(z_ref) (1 + z_ref)/(1 + z_box), b_q(z) = 3.7 ((1+z)/3.33)^1.7,
+ * G the linear growth of flat LCDM with G(0) = 1: the growth between boxes is
+ * taken as 1/(1+z), which the appendix's a(z) presumes.  z_ref: the middle box
+ * of three, or the only box.  Quadrature, FP64: xi_m by composite Simpson on
+ * [0, 12/s] with spacing <= 0.1/rmax; P_q by composite Simpson on the n_r
+ * (odd) nodes r_i = i rmax/(n_r - 1).  k: device [n_k] (h/Mpc, k = 0 gives
+ * the limit); pq: device [n_k], values below 1e-12 of the largest raised to
+ * that floor (so the result serves as lya_pk's p_tab); xi: device [n_r] or
+ * NULL, xi_m at r_i.  work >= lya_lognormal_workspace_size(pk->smooth, rmax,
+ * n_r) bytes (0: invalid arguments). */
+size_t lya_lognormal_workspace_size(double smooth, double rmax, int32_t n_r);
+int lya_lognormal_pk(const lya_pk* pk, double z_box, double z_ref, const lya_cosmo* cosmo, double rmax, int32_t n_r,
+                     int32_t n_k, const double* k, double* pq, double* xi, void* work, size_t work_bytes,
+                     void* stream);
+
+/* Mean and variance over the n^3 grid points of both parts of an LYA_F32
+ * box: out (device [4]) = {mean re, var re, mean im, var im}, FP64 sums.
+ * work >= lya_workspace_size(LYA_OP_QUASARS, box). */
+int lya_box_moments(const lya_box* box, const void* field, double* out, void* work, size_t work_bytes,
+                    void* stream);
+
+typedef struct {
+  int32_t n_box;          /* 1 or 3 */
+  const void* box_a;      /* LYA_F32 box: delta_q of box 1 in the real part; with three boxes
+                             delta_q of box 2 in the imaginary part (lya_make_box_pair) */
+  const void* box_b;      /* three boxes: LYA_F32 box with delta_q of box 3 in the real part */
+  double z_box[3];        /* box redshifts, increasing (the paper: 1.9, 2.75, 3.6) */
+  const double* var[3];   /* device scalars: the variance of each delta_q (lya_box_moments:
+                             out + 1 for a real part, out + 3 for an imaginary part) */
+  double xi5;             /* three boxes: xi_m(5 Mpc/h) of the smoothed matter spectrum */
+  double observer[3];     /* Mpc/h, in the frame where grid point m sits at m dx */
+  int32_t n_nbar;         /* 2..256 */
+  const double* nbar_z;   /* device [n_nbar], increasing */
+  const double* nbar;     /* device [n_nbar]: comoving quasar density, (h/Mpc)^3 */
+  uint64_t seed;
+} lya_qso_spec;
+
+/* Draws quasars voxel by voxel: grid point m (at x = m dx, z its redshift at
+ * comoving distance |x - observer|) is selected with probability
+ *   p = nbar(z) dx^3 sum_i c_i(z) exp(a_i delta_i(m) - a_i^2 var_i / 2), clipped to [0, 1],
+ * a_i = b_q(z)(1 + z_i)/(b_q(z_i)(1 + z)), nbar linear between its nodes and 0
+ * outside them; one box: c_1 = 1; three boxes: p = w p_12 + (1 - w) p_23 with
+ * p_12 the linear interpolation in z of boxes 1 and 2, p_23 the linear
+ * extrapolation of boxes 2 and 3, and w in [0, 1] such that
+ * w xi_12 + (1 - w) xi_23 = (b_q(z) G(z))^2 xi5 at r = 5 Mpc/h, where
+ * xi_i = (1 + b_0i^2 xi5)^(a_i^2) - 1 (Appendix A).  Random numbers:
+ * Philox4x32-10, key = seed; the decision of voxel m (linear index
+ * (m_x n + m_y) n + m_z) takes word m & 3 of counter (m >> 2, 0, 2, 0) as
+ * u = ((w >> 9) + 1/2) 2^-23 and selects when u < p; the selected voxel's
+ * position takes words 0-2 of counter (m, 0, 4, 0): per axis
+ * (m_axis << 32) - 2^31 + word, cell units times 2^32 (uniform in
+ * [m - 1/2, m + 1/2)).  Outputs: *count (device) = number selected; pos_fx
+ * (device [cap][3]) holds min(count, cap) positions in an unspecified order
+ * (a count above cap asks for a larger buffer).  Every grid point must lie
+ * within 10000 Mpc/h of the observer.  work >= lya_workspace_size(
+ * LYA_OP_QUASARS, box). */
+int lya_draw_quasars(const lya_box* box, const lya_qso_spec* spec, const lya_cosmo* cosmo, int64_t* pos_fx,
+                     int64_t cap, int64_t* count, void* work, size_t work_bytes, void* stream);
 
 /* Launch-shape tuning (the batching and autotuning row of the hot path).
  * Per box size n the library keeps:

@@ -118,18 +118,22 @@ def box_bias2(z_box, z_ref, omega_m=cosmology.OMEGA_M):
 
 
 def mix_coeffs(z, z_box, xi5, omega_m=cosmology.OMEGA_M):
-    """(c_1, c_2, c_3) of the three-box combination at redshift z (scalar)."""
+    """(c_1, c_2, c_3) of the three-box combination at redshift z (scalar or
+    array; the coefficients go along the last axis)."""
+    z = np.asarray(z, dtype=np.float64)
     z1, z2, z3 = (float(v) for v in z_box)
-    a = [float(alpha_of_z(z, zi)) for zi in (z1, z2, z3)]
-    xi = [(1.0 + box_bias2(zi, z2, omega_m) * xi5) ** (ai * ai) - 1.0 for zi, ai in zip((z1, z2, z3), a)]
-    xi_mod = float(bias_qso(z) * growth_q(z, z2, omega_m)) ** 2 * xi5
+    g2 = growth(z2, omega_m)
+    xi = [(1.0 + box_bias2(zi, z2, omega_m) * xi5) ** (alpha_of_z(z, zi) ** 2) - 1.0 for zi in (z1, z2, z3)]
+    xi_mod = (bias_qso(z) * g2 * (1.0 + z2) / (1.0 + z)) ** 2 * xi5
     t12 = (z - z1) / (z2 - z1)
     t23 = (z - z2) / (z3 - z2)
     xi12 = (1.0 - t12) * xi[0] + t12 * xi[1]
     xi23 = (1.0 - t23) * xi[1] + t23 * xi[2]
     den = xi12 - xi23
-    w = 0.5 if abs(den) <= 1e-12 * abs(xi[1]) else min(max((xi_mod - xi23) / den, 0.0), 1.0)
-    return np.array([w * (1.0 - t12), w * t12 + (1.0 - w) * (1.0 - t23), (1.0 - w) * t23])
+    flat = np.abs(den) <= 1e-12 * np.abs(xi[1])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        w = np.where(flat, 0.5, np.clip((xi_mod - xi23) / np.where(flat, 1.0, den), 0.0, 1.0))
+    return np.stack([w * (1.0 - t12), w * t12 + (1.0 - w) * (1.0 - t23), (1.0 - w) * t23], axis=-1)
 
 
 def probability(fields, dx, observer, z_box, sigma2, nbar_z, nbar, xi5=None, omega_m=cosmology.OMEGA_M):
@@ -144,7 +148,7 @@ def probability(fields, dx, observer, z_box, sigma2, nbar_z, nbar, xi5=None, ome
     if len(fields) == 1:
         coef = np.ones((len(z), 1))
     else:
-        coef = np.array([mix_coeffs(zz, z_box, xi5, omega_m) for zz in z])
+        coef = mix_coeffs(z, z_box, xi5, omega_m)
     acc = np.zeros(len(z))
     for i, (f, zi, s2) in enumerate(zip(fields, z_box, sigma2)):
         al = alpha_of_z(z, zi)

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "liblyamock.so")
 SOURCES = ["lya_abi.hip", "lya_timing.hip", "k_tables.hip", "k_fft.hip", "k_skewers.hip", "k_p1d.hip",
-           "lya_tune.hip", "lya_mlp.hip", "lya_autotune.hip", "k_tune_eval.hip", "lya_tune_ps.hip"]
+           "lya_tune.hip", "lya_mlp.hip", "lya_autotune.hip", "k_tune_eval.hip", "lya_tune_ps.hip",
+           "lya_qso.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

@@ -102,8 +102,9 @@ __device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, i
   const int nx = sfreq(ix, N), ny = sfreq(iy, N), nz = sfreq(iz, N);
   const int n2 = nx * nx + ny * ny + nz * nz;
   float s = g.table[n2];
-  if (g.only_n2 >= 0 && n2 != g.only_n2) s = 0.0f;
-  if (s == 0.0f) return make_float2(0.0f, 0.0f);
+  float sb = g.table_b ? g.table_b[n2] : s;
+  if (g.only_n2 >= 0 && n2 != g.only_n2) s = sb = 0.0f;
+  if (s == 0.0f && sb == 0.0f) return make_float2(0.0f, 0.0f);
   const uint64_t lin = (static_cast<uint64_t>(ix) * N + iy) * N + iz;
   const uint64_t plin = (static_cast<uint64_t>((N - ix) & (N - 1)) * N + ((N - iy) & (N - 1))) * N + ((N - iz) & (N - 1));
   const uint64_t own = lin < plin ? lin : plin;
@@ -121,6 +122,10 @@ __device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, i
   }
   const float ma = comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
   const float mb = comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
+  if (g.table_b) {
+    const float pa = s * ma, pb = sb * mb;
+    return make_float2(w.x * pa - w.y * pb, w.y * pa + w.x * pb);
+  }
   return make_float2(s * (w.x * ma - w.y * mb), s * (w.y * ma + w.x * mb));
 }
 
@@ -287,7 +292,8 @@ struct Pass {
 enum { GEN_GENERIC = 0, GEN_DELTA_ETAZ = 1, GEN_DELTA = 2 };
 
 template <int N, int T, int NT, int GM, typename LIDX>
-__device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, float2* lds, LIDX lidx, float* stab) {
+__device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, float2* lds, LIDX lidx, float* stab,
+                                           float* stab_b) {
   constexpr int H = T / 2, NZ = N / 2 + 1;
   const int nx = ix;  // 0 < ix < N/2
   // the amplitudes a pencil needs depend on |nz| only: gather them once, all
@@ -296,6 +302,7 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
     const int po = w / NZ, az = w % NZ;
     const int ny = sfreq(iy0 + po, N);
     stab[w] = g.table[nx * nx + ny * ny + az * az];
+    if (GM == GEN_GENERIC && g.table_b) stab_b[w] = g.table_b[nx * nx + ny * ny + az * az];
   }
   __syncthreads();
   for (int w = threadIdx.x; w < H * (N / 2); w += NT) {
@@ -314,14 +321,15 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
       float2 wv = e ? box_muller_half(wd.z, wd.w) : box_muller_half(wd.x, wd.y);
       float ma, mb;
       if (GM == GEN_GENERIC) {
-        if (g.only_n2 >= 0 && n2 != g.only_n2) s = 0.0f;
+        float sb = g.table_b ? stab_b[po * NZ + (nz < 0 ? -nz : nz)] : s;
+        if (g.only_n2 >= 0 && n2 != g.only_n2) s = sb = 0.0f;
         if (g.fixed_amp) {
           const float r = rsqrtf(wv.x * wv.x + wv.y * wv.y);
           wv.x *= r;
           wv.y *= r;
         }
         ma = s * comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
-        mb = s * comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
+        mb = sb * comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
       } else {
         ma = s;  // n2 > 0 here (ix > 0)
         mb = GM == GEN_DELTA_ETAZ ? s * g.f * static_cast<float>(nz * nz) * __builtin_amdgcn_rcpf(static_cast<float>(n2))
@@ -363,7 +371,9 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
   // stage 0: registers from global memory or from the synthesiser
   if (KIND == KIND_GENZ && paired) {
     __shared__ float stab[KIND == KIND_GENZ ? (T / 2) * (N / 2 + 1) : 1];
-    gen_paired<N, T, NT, GM>(g, outer, t0, lds, [](int i, int p) { return P::lidx(i, p); }, stab);
+    // second amplitude table: only the generic synthesiser serves two spectra
+    __shared__ float stab_b[KIND == KIND_GENZ && GM == GEN_GENERIC ? (T / 2) * (N / 2 + 1) : 1];
+    gen_paired<N, T, NT, GM>(g, outer, t0, lds, [](int i, int p) { return P::lidx(i, p); }, stab, stab_b);
     __syncthreads();
     P::template load_lds<0>(v, lds, tid);
     __syncthreads();
@@ -521,7 +531,7 @@ template <int N>
 hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16, hipStream_t st) {
   using S = Shape<N>;
   const int tz = N * (N / S::TZ);
-  const bool hooks = g.fixed_amp || g.only_n2 >= 0;
+  const bool hooks = g.fixed_amp || g.only_n2 >= 0 || g.table_b;
   const int gm = (!hooks && g.comp_a == 0 && g.comp_b == 3)    ? GEN_DELTA_ETAZ
                  : (!hooks && g.comp_a == 0 && g.comp_b == -1) ? GEN_DELTA
                                                                : GEN_GENERIC;

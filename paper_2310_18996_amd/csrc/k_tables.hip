@@ -120,6 +120,25 @@ __global__ void __launch_bounds__(256) k_amp_table(const double* amp, PkParams p
   table[e] = static_cast<float>(s);
 }
 
+// Integrand of the matter correlation function of the smoothed spectrum
+// (section "Quasar generation"): xi(r) = 1/(2 pi^2 r) int_0^kmax P(k)
+// exp(-k^2 s^2) k sin(k r) dk, composite Simpson on k_j = j h, j = 0..m
+// (m even).  f_j holds the Simpson weight times P(k_j) exp(-k_j^2 s^2) k_j;
+// k = 0 carries nothing.
+__global__ void __launch_bounds__(256) k_xi_weights(const double* amp, PkParams p, double s, double h, int m,
+                                                    double* f) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j > m) return;
+  if (j == 0) {
+    f[0] = 0.0;
+    return;
+  }
+  const double k = h * j;
+  const double P = p.k_tab ? pk_tabulated(k, p) : amp[0] * pk_shape(k, p);
+  const double w = (j == m) ? 1.0 : ((j & 1) ? 4.0 : 2.0);
+  f[j] = w * h / 3.0 * P * exp(-(k * s) * (k * s)) * k;
+}
+
 // ---- pixel redshift table: z at chi = i * h_chi, i = 0..n-1 ----
 __device__ __forceinline__ double inv_e(double z, double om) {
   const double zp = 1.0 + z;
@@ -157,6 +176,19 @@ hipError_t launch_pk_table(const PkParams& p, int n, double dx, TableWork& w, hi
   const int ne = amp_table_entries(n);
   LYA_TIMED("pk_table", st,
             hipLaunchKernelGGL(k_amp_table, dim3((ne + 255) / 256), dim3(256), 0, st, w.amp, p, L, ne, w.table));
+  return hipGetLastError();
+}
+
+hipError_t launch_xi_weights(const PkParams& p, double s, double h, int m, double* partial, double* amp,
+                             double* f, hipStream_t st) {
+  if (!p.k_tab) {
+    LYA_TIMED("pk_sigma8", st, hipLaunchKernelGGL(k_sigma8_partial, dim3(kSigmaBlocks), dim3(256), 0, st, p, partial));
+    LYA_TIMED("pk_finalize", st,
+              hipLaunchKernelGGL(k_pk_finalize, dim3(1), dim3(256), 0, st, p, partial, kSigmaBlocks, amp,
+                                 static_cast<float2*>(nullptr), 0));
+  }
+  LYA_TIMED("xi_weights", st,
+            hipLaunchKernelGGL(k_xi_weights, dim3((m + 256) / 256), dim3(256), 0, st, amp, p, s, h, m, f));
   return hipGetLastError();
 }
 

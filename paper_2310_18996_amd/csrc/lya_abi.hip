@@ -26,7 +26,7 @@ bool pow2_in_range(int n) { return n >= 32 && n <= 2048 && (n & (n - 1)) == 0; }
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct BoxCarve {
-  size_t partial, amp, tw, table, staging, total;
+  size_t partial, amp, tw, table, table_b, staging, total;
 };
 
 BoxCarve carve_box(const lya_box* b) {
@@ -36,6 +36,7 @@ BoxCarve carve_box(const lya_box* b) {
   c.amp = o;     o += align256(sizeof(double));
   c.tw = o;      o += align256(sizeof(float2) * b->n);
   c.table = o;   o += align256(sizeof(float) * lya::amp_table_entries(b->n));
+  c.table_b = o; o += align256(sizeof(float) * lya::amp_table_entries(b->n));
   c.staging = o;
   if (b->storage == LYA_BF16) o += align256(sizeof(float2) * lya::box_elems(b->n));
   c.total = o;
@@ -58,6 +59,72 @@ SkCarve carve_sk() {
   return c;
 }
 
+struct QsoCarve {
+  size_t ztab, tab, part, total;
+};
+
+QsoCarve carve_qso() {
+  QsoCarve c{};
+  size_t o = 0;
+  c.ztab = o; o += align256(sizeof(float) * lya::kZTabN);
+  c.tab = o;  o += align256(sizeof(float4) * lya::kZTabN);
+  c.part = o; o += align256(sizeof(double) * 4 * lya::kQsoMomBlocks);
+  c.total = o;
+  return c;
+}
+
+// xi quadrature of lya_lognormal_pk: Simpson on [0, 12/s] with spacing at
+// most 0.1/rmax (a tenth of a radian per node at the largest r), m even.
+constexpr int64_t kMaxXiNodes = int64_t(1) << 26;
+int64_t xi_nodes(double smooth, double rmax) {
+  const double kmax = 12.0 / smooth;
+  const double h = fmin(0.1 / rmax, kmax / 64.0);
+  const double m = 2.0 * ceil(kmax / (2.0 * h));
+  return m > static_cast<double>(kMaxXiNodes) ? -1 : static_cast<int64_t>(m);
+}
+
+struct LnCarve {
+  size_t partial, amp, f, xi, g, total;
+};
+
+LnCarve carve_lognormal(int64_t m, int32_t n_r) {
+  LnCarve c{};
+  size_t o = 0;
+  c.partial = o; o += align256(sizeof(double) * lya::kSigmaBlocks);
+  c.amp = o;     o += align256(sizeof(double));
+  c.f = o;       o += align256(sizeof(double) * static_cast<size_t>(m + 1));
+  c.xi = o;      o += align256(sizeof(double) * static_cast<size_t>(n_r));
+  c.g = o;       o += align256(sizeof(double) * static_cast<size_t>(n_r));
+  c.total = o;
+  return c;
+}
+
+// Linear growth of flat LCDM normalised to G(0) = 1: D(a) proportional to
+// E(a) int_0^a da' / (a' E(a'))^3, with a' = t^2 (a smooth integrand near 0)
+// and composite Simpson over t in [0, sqrt(a)], 4096 intervals, FP64.
+double growth_lcdm(double z, double om) {
+  auto d = [om](double a) {
+    constexpr int kN = 4096;
+    const double tmax = sqrt(a), h = tmax / kN;
+    double acc = 0.0;
+    for (int i = 1; i <= kN; ++i) {
+      const double t = h * i, ap = t * t;
+      const double ae2 = om / ap + (1.0 - om) * ap * ap;  // (a E)^2
+      acc += (i == kN ? 1.0 : (i & 1 ? 4.0 : 2.0)) * 2.0 * t / (ae2 * sqrt(ae2));
+    }
+    return sqrt(om / (a * a * a) + 1.0 - om) * acc * h / 3.0;
+  };
+  return d(1.0 / (1.0 + z)) / d(1.0);
+}
+
+double bias_qso(double z) { return 3.7 * pow((1.0 + z) / 3.33, 1.7); }
+
+// b_0^2 of the quasar box at z_box: (b_q(z_box) G(z_ref) (1 + z_ref)/(1 + z_box))^2.
+double qso_b2(double z_box, double z_ref, double g_ref) {
+  const double b = bias_qso(z_box) * g_ref * (1.0 + z_ref) / (1.0 + z_box);
+  return b * b;
+}
+
 int check_box(const lya_box* box) {
   if (!box) return fail(LYA_EINVAL, "box is NULL%s");
   if (box->n < 32 || box->n > 2048) return fail(LYA_EINVAL, "box n must be in [32, 2048]%s");
@@ -67,32 +134,51 @@ int check_box(const lya_box* box) {
   return LYA_OK;
 }
 
-int make_pair(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int ca, int cb, void* field,
-              void* work, size_t work_bytes, void* stream) {
-  int rc = check_box(box);
-  if (rc) return rc;
+int check_pk(const lya_pk* pk) {
   if (!pk) return fail(LYA_EINVAL, "pk is NULL%s");
-  if (!field) return fail(LYA_EINVAL, "field is NULL%s");
-  if (!work) return fail(LYA_EINVAL, "work is NULL%s");
-  if (ca < LYA_C_DELTA || ca > LYA_C_YZ || cb < LYA_C_NONE || cb > LYA_C_YZ)
-    return fail(LYA_EINVAL, "unknown field component%s");
   if (pk->k_tab) {
     if (!pk->p_tab || pk->n_tab < 2 || pk->smooth < 0.0)
       return fail(LYA_EINVAL, "tabulated P(k) needs p_tab and n_tab >= 2%s");
   } else if (!(pk->sigma8 > 0.0) || !(pk->gamma > 0.0) || !(pk->wig_kd > 0.0) || pk->smooth < 0.0) {
     return fail(LYA_EINVAL, "invalid power-spectrum parameters%s");
   }
+  return LYA_OK;
+}
+
+lya::PkParams pk_params(const lya_pk* pk) {
+  return lya::PkParams{pk->sigma8, pk->ns, pk->gamma, pk->wig_amp, pk->wig_r, pk->wig_kd, pk->smooth,
+                       pk->k_tab, pk->p_tab, pk->n_tab};
+}
+
+// Components (ca, cb) of the modes of pk; with pk_b, component b takes the
+// amplitudes of pk_b instead.
+int make_pair(const lya_box* box, const lya_pk* pk, const lya_pk* pk_b, uint64_t seed, double f, int ca, int cb,
+              void* field, void* work, size_t work_bytes, void* stream) {
+  int rc = check_box(box);
+  if (rc) return rc;
+  if ((rc = check_pk(pk))) return rc;
+  if (pk_b && (rc = check_pk(pk_b))) return rc;
+  if (!field) return fail(LYA_EINVAL, "field is NULL%s");
+  if (!work) return fail(LYA_EINVAL, "work is NULL%s");
+  if (ca < LYA_C_DELTA || ca > LYA_C_YZ || cb < LYA_C_NONE || cb > LYA_C_YZ)
+    return fail(LYA_EINVAL, "unknown field component%s");
   const BoxCarve c = carve_box(box);
   if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the box%s");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(work);
   lya::TableWork tw{reinterpret_cast<double*>(w + c.partial), reinterpret_cast<double*>(w + c.amp),
                     reinterpret_cast<float2*>(w + c.tw), reinterpret_cast<float*>(w + c.table)};
-  lya::PkParams p{pk->sigma8, pk->ns, pk->gamma, pk->wig_amp, pk->wig_r, pk->wig_kd, pk->smooth,
-                  pk->k_tab, pk->p_tab, pk->n_tab};
-  hipError_t e = lya::launch_pk_table(p, box->n, box->dx, tw, st);
+  hipError_t e = lya::launch_pk_table(pk_params(pk), box->n, box->dx, tw, st);
   if (e != hipSuccess) return hip_fail(e, "power-spectrum table");
-  lya::GenParams g{tw.table, seed, static_cast<float>(f), ca, cb, pk->fixed_amp ? 1 : 0, pk->only_n2};
+  const float* table_b = nullptr;
+  if (pk_b) {
+    lya::TableWork twb = tw;
+    twb.table = reinterpret_cast<float*>(w + c.table_b);
+    e = lya::launch_pk_table(pk_params(pk_b), box->n, box->dx, twb, st);
+    if (e != hipSuccess) return hip_fail(e, "second power-spectrum table");
+    table_b = twb.table;
+  }
+  lya::GenParams g{tw.table, table_b, seed, static_cast<float>(f), ca, cb, pk->fixed_amp ? 1 : 0, pk->only_n2};
   float2* f32 = box->storage == LYA_F32 ? static_cast<float2*>(field) : reinterpret_cast<float2*>(w + c.staging);
   uint32_t* b16 = box->storage == LYA_BF16 ? static_cast<uint32_t*>(field) : nullptr;
   e = lya::launch_box_fft(box->n, g, tw.tw, f32, b16, st);
@@ -342,20 +428,28 @@ size_t lya_workspace_size(int op, const lya_box* box) {
     return carve_box(box).total;
   }
   if (op == LYA_OP_SKEWERS) return carve_sk().total;
+  if (op == LYA_OP_QUASARS) return carve_qso().total;
   return 0;
 }
 
 int lya_make_box(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int with_eta, void* field,
                  void* work, size_t work_bytes, void* stream) {
   g_err[0] = 0;
-  return make_pair(box, pk, seed, f, LYA_C_DELTA, with_eta ? LYA_C_ZZ : LYA_C_NONE, field, work, work_bytes,
-                   stream);
+  return make_pair(box, pk, nullptr, seed, f, LYA_C_DELTA, with_eta ? LYA_C_ZZ : LYA_C_NONE, field, work,
+                   work_bytes, stream);
 }
 
 int lya_make_eta(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int comp_a, int comp_b,
                  void* field, void* work, size_t work_bytes, void* stream) {
   g_err[0] = 0;
-  return make_pair(box, pk, seed, f, comp_a, comp_b, field, work, work_bytes, stream);
+  return make_pair(box, pk, nullptr, seed, f, comp_a, comp_b, field, work, work_bytes, stream);
+}
+
+int lya_make_box_pair(const lya_box* box, const lya_pk* pk_a, const lya_pk* pk_b, uint64_t seed, void* field,
+                      void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!pk_b) return fail(LYA_EINVAL, "pk_b is NULL%s");
+  return make_pair(box, pk_a, pk_b, seed, 1.0, LYA_C_DELTA, LYA_C_DELTA, field, work, work_bytes, stream);
 }
 
 static int draw_skewers_impl(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
@@ -512,6 +606,144 @@ int lya_apply_fgpa(const lya_skewers* sk, const lya_cosmo* cosmo, const float* d
   fill_fgpa(a, fgpa);
   a.flux = flux;
   return run_skewers(a, cosmo, zb, work, work_bytes, stream);
+}
+
+size_t lya_lognormal_workspace_size(double smooth, double rmax, int32_t n_r) {
+  if (!(smooth > 0.0) || !(rmax > 0.0) || n_r < 3 || n_r > (1 << 22) || !(n_r & 1)) return 0;
+  const int64_t m = xi_nodes(smooth, rmax);
+  return m < 0 ? 0 : carve_lognormal(m, n_r).total;
+}
+
+int lya_lognormal_pk(const lya_pk* pk, double z_box, double z_ref, const lya_cosmo* cosmo, double rmax, int32_t n_r,
+                     int32_t n_k, const double* k, double* pq, double* xi, void* work, size_t work_bytes,
+                     void* stream) {
+  g_err[0] = 0;
+  int rc = check_pk(pk);
+  if (rc) return rc;
+  if (!(pk->smooth > 0.0)) return fail(LYA_EINVAL, "the matter spectrum needs smooth > 0%s");
+  if (!cosmo || !(cosmo->omega_m > 0.0 && cosmo->omega_m <= 1.0)) return fail(LYA_EINVAL, "invalid cosmo%s");
+  if (!(z_box > -1.0 && z_box < 20.0) || !(z_ref > -1.0 && z_ref < 20.0))
+    return fail(LYA_EINVAL, "redshifts must lie in (-1, 20)%s");
+  if (!(rmax > 0.0) || n_r < 3 || n_r > (1 << 22) || !(n_r & 1))
+    return fail(LYA_EINVAL, "need rmax > 0 and an odd n_r in [3, 2^22]%s");
+  if (n_k < 0 || n_k > (1 << 20) || (n_k > 0 && (!k || !pq))) return fail(LYA_EINVAL, "invalid k/pq arrays%s");
+  if (!work) return fail(LYA_EINVAL, "work is NULL%s");
+  const int64_t m = xi_nodes(pk->smooth, rmax);
+  if (m < 0) return fail(LYA_EUNSUPPORTED, "rmax / smooth too large for the xi quadrature%s");
+  const LnCarve c = carve_lognormal(m, n_r);
+  if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the lognormal spectrum%s");
+  char* w = static_cast<char*>(work);
+  lya::LognormalArgs a{};
+  a.smooth = pk->smooth;
+  a.m = static_cast<int>(m);
+  a.h = (12.0 / pk->smooth) / static_cast<double>(m);
+  a.n_r = n_r;
+  a.dr = rmax / (n_r - 1);
+  a.b2 = qso_b2(z_box, z_ref, growth_lcdm(z_ref, cosmo->omega_m));
+  a.n_k = n_k;
+  a.k = k;
+  a.pq = pq;
+  a.xi = xi ? xi : reinterpret_cast<double*>(w + c.xi);
+  a.f = reinterpret_cast<double*>(w + c.f);
+  a.g = reinterpret_cast<double*>(w + c.g);
+  a.partial = reinterpret_cast<double*>(w + c.partial);
+  a.amp = reinterpret_cast<double*>(w + c.amp);
+  hipError_t e = lya::launch_lognormal(pk_params(pk), a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lognormal spectrum");
+  return LYA_OK;
+}
+
+int lya_box_moments(const lya_box* box, const void* field, double* out, void* work, size_t work_bytes,
+                    void* stream) {
+  g_err[0] = 0;
+  int rc = check_box(box);
+  if (rc) return rc;
+  if (box->storage != LYA_F32) return fail(LYA_EUNSUPPORTED, "box moments need LYA_F32 storage%s");
+  if (!field || !out || !work) return fail(LYA_EINVAL, "field/out/work is NULL%s");
+  const QsoCarve c = carve_qso();
+  if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small%s");
+  hipError_t e = lya::launch_box_moments(static_cast<const float2*>(field), box->n,
+                                         reinterpret_cast<double*>(static_cast<char*>(work) + c.part), out,
+                                         static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "box moments");
+  return LYA_OK;
+}
+
+int lya_draw_quasars(const lya_box* box, const lya_qso_spec* spec, const lya_cosmo* cosmo, int64_t* pos_fx,
+                     int64_t cap, int64_t* count, void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_box(box);
+  if (rc) return rc;
+  if (box->storage != LYA_F32) return fail(LYA_EUNSUPPORTED, "the quasar draw needs LYA_F32 boxes%s");
+  if (!spec) return fail(LYA_EINVAL, "spec is NULL%s");
+  if (!cosmo || !(cosmo->omega_m > 0.0 && cosmo->omega_m <= 1.0)) return fail(LYA_EINVAL, "invalid cosmo%s");
+  const int nb = spec->n_box;
+  if (nb != 1 && nb != 3) return fail(LYA_EINVAL, "n_box must be 1 or 3%s");
+  if (!spec->box_a || (nb == 3 && !spec->box_b)) return fail(LYA_EINVAL, "quasar boxes are NULL%s");
+  for (int i = 0; i < nb; ++i) {
+    if (!spec->var[i]) return fail(LYA_EINVAL, "variance pointer is NULL%s");
+    if (!(spec->z_box[i] > -1.0 && spec->z_box[i] < 20.0)) return fail(LYA_EINVAL, "box redshift out of range%s");
+  }
+  if (nb == 3 && !(spec->z_box[0] < spec->z_box[1] && spec->z_box[1] < spec->z_box[2]))
+    return fail(LYA_EINVAL, "box redshifts must increase%s");
+  if (nb == 3 && !(spec->xi5 > 0.0)) return fail(LYA_EINVAL, "xi5 must be > 0%s");
+  if (spec->n_nbar < 2 || spec->n_nbar > lya::kQsoMaxNbar || !spec->nbar_z || !spec->nbar)
+    return fail(LYA_EINVAL, "nbar table needs 2..256 nodes%s");
+  if (cap < 0 || (cap > 0 && !pos_fx) || !count) return fail(LYA_EINVAL, "invalid output arrays%s");
+  if (!work) return fail(LYA_EINVAL, "work is NULL%s");
+  const QsoCarve c = carve_qso();
+  if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small%s");
+  // every grid point must lie inside the distance table
+  const double span = (box->n - 1) * box->dx;
+  double far = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const double o = spec->observer[ax];
+    if (!(fabs(o) < 1e6)) return fail(LYA_EINVAL, "observer out of range%s");
+    const double d = fmax(fabs(o), fabs(span - o));
+    far += d * d;
+  }
+  if (!(sqrt(far) < (lya::kZTabN - 2) * lya::kZTabH))
+    return fail(LYA_EUNSUPPORTED, "box reaches beyond 10000 Mpc/h from the observer%s");
+
+  char* w = static_cast<char*>(work);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* ztab = reinterpret_cast<float*>(w + c.ztab);
+  hipError_t e = lya::launch_zchi_table(cosmo->omega_m, ztab, st);
+  if (e != hipSuccess) return hip_fail(e, "redshift table");
+  const double z_ref = nb == 3 ? spec->z_box[1] : spec->z_box[0];
+  lya::QsoCoef cf{};
+  cf.nb = nb;
+  cf.z_ref = z_ref;
+  cf.g_ref = growth_lcdm(z_ref, cosmo->omega_m);
+  cf.xi5 = spec->xi5;
+  lya::QsoDrawArgs a{};
+  a.n = box->n;
+  a.pitch = lya::plane_pitch(box->n);
+  a.nb = nb;
+  a.box_a = static_cast<const float2*>(spec->box_a);
+  a.box_b = nb == 3 ? static_cast<const float2*>(spec->box_b) : nullptr;
+  for (int i = 0; i < nb; ++i) {
+    cf.z[i] = spec->z_box[i];
+    cf.b2[i] = qso_b2(spec->z_box[i], z_ref, cf.g_ref);
+    a.var[i] = spec->var[i];
+    a.l2z[i] = static_cast<float>(log2(1.0 + spec->z_box[i]));
+  }
+  a.dx = static_cast<float>(box->dx);
+  a.dx_d = box->dx;
+  a.dx3 = static_cast<float>(box->dx * box->dx * box->dx);
+  for (int ax = 0; ax < 3; ++ax) a.o[ax] = spec->observer[ax];
+  a.oz = static_cast<float>(spec->observer[2]);
+  a.tab = reinterpret_cast<const float4*>(w + c.tab);
+  a.n_nbar = spec->n_nbar;
+  a.nbar_z = spec->nbar_z;
+  a.nbar = spec->nbar;
+  a.seed = spec->seed;
+  a.pos = pos_fx;
+  a.cap = cap;
+  a.count = reinterpret_cast<unsigned long long*>(count);
+  e = lya::launch_qso_draw(cf, a, ztab, reinterpret_cast<float4*>(w + c.tab), st);
+  if (e != hipSuccess) return hip_fail(e, "quasar draw");
+  return LYA_OK;
 }
 
 }  // extern "C"

@@ -49,6 +49,7 @@ struct TableWork {
 // What the first FFT pass synthesises for each mode.
 struct GenParams {
   const float* table;
+  const float* table_b;  // non-null: component b takes its own amplitudes (two spectra, one set of modes)
   uint64_t seed;
   float f;
   int comp_a, comp_b;  // 0 delta, 1 xx, 2 yy, 3 zz, 4 xy, 5 xz, 6 yz; -1 none
@@ -71,6 +72,10 @@ int device_cus();
 
 hipError_t launch_pk_table(const PkParams& p, int n, double dx, TableWork& w, hipStream_t st);
 hipError_t launch_zchi_table(double omega_m, float* ztab, hipStream_t st);
+// Simpson-weighted integrand of xi_m (k_j = j h, j = 0..m): sigma8
+// normalisation first for the analytic form (partial: kSigmaBlocks, amp: 1).
+hipError_t launch_xi_weights(const PkParams& p, double s, double h, int m, double* partial, double* amp,
+                             double* f, hipStream_t st);
 hipError_t launch_twiddles(float2* tw, int ntw, hipStream_t st);
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
                           hipStream_t st);
@@ -200,6 +205,59 @@ struct TuneEvalArgs {
 // (FP32, may be NULL): [G][1 + nk] = Fbar, P_1..P_nk.
 hipError_t launch_tune_eval(const TuneEvalArgs& a, double* sums, int64_t* counts, double* rows, float* rows32,
                             hipStream_t st);
+
+// Lognormal quasar field (lya_qso.hip).
+struct LognormalArgs {
+  double smooth;   // Gaussian smoothing length of the matter spectrum, Mpc/h
+  double h;        // k spacing of the xi quadrature; nodes j = 0..m (m even)
+  int m;
+  double dr;       // r spacing; nodes i = 0..n_r-1 (n_r odd)
+  int n_r;
+  double b2;       // b_0^2
+  int n_k;
+  const double* k;   // device [n_k]
+  double* pq;        // device [n_k]
+  double* xi;        // device [n_r]
+  double* f;         // workspace [m + 1]
+  double* g;         // workspace [n_r]
+  double* partial;   // workspace [kSigmaBlocks]
+  double* amp;       // workspace [1]
+};
+hipError_t launch_lognormal(const PkParams& p, const LognormalArgs& a, hipStream_t st);
+
+constexpr int kQsoMomBlocks = 1024;
+// box: FP32 {re, im} box; part: workspace [kQsoMomBlocks][4]; out: device [4]
+// = {mean re, var re, mean im, var im}.
+hipError_t launch_box_moments(const float2* box, int n, double* part, double* out, hipStream_t st);
+
+constexpr int kQsoMaxNbar = 256;
+struct QsoCoef {
+  int nb;
+  double z[3];
+  double b2[3];
+  double g_ref, z_ref;
+  double xi5;
+};
+struct QsoDrawArgs {
+  int n;
+  size_t pitch;
+  int nb;
+  const float2* box_a;    // delta_1 (re) and, for three boxes, delta_2 (im)
+  const float2* box_b;    // delta_3 (re)
+  const double* var[3];   // device scalars
+  float dx, oz, dx3;
+  double dx_d, o[3];
+  float l2z[3];           // log2(1 + z_i)
+  const float4* tab;      // {z, c_1, c_2, c_3} per kZTabH of comoving distance
+  int n_nbar;
+  const double* nbar_z;
+  const double* nbar;
+  uint64_t seed;
+  int64_t* pos;
+  int64_t cap;
+  unsigned long long* count;
+};
+hipError_t launch_qso_draw(const QsoCoef& c, const QsoDrawArgs& a, const float* ztab, float4* tab, hipStream_t st);
 
 // Tuning (lya_tune.hip) and the emulator used by it (lya_mlp.hip).
 size_t emulator_eval_bytes();

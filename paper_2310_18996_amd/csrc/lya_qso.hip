@@ -1,0 +1,344 @@
+// Lognormal quasar field (gfx950), section "Quasar generation" and Appendix A:
+//   * xi_m(r) of the smoothed matter spectrum and the lognormal spectrum
+//     P_q(k) = FT of ln(1 + b_0^2 xi_m), both in FP64;
+//   * the variance of a box (a reduction over the grid);
+//   * per comoving distance: z and the three-box coefficients c_i(z);
+//   * the draw: every voxel is selected with probability
+//     p = nbar(z) dx^3 sum_i c_i(z) exp(a_i(z) delta_i - a_i(z)^2 var_i / 2),
+//     a_i(z) = b_q(z) (1 + z_i) / (b_q(z_i) (1 + z)) = ((1 + z)/(1 + z_i))^0.7
+//     for b_q proportional to (1 + z)^1.7, and a selected voxel gets a
+//     uniform position inside it.
+#include "lya_internal.h"
+
+namespace lya {
+
+namespace {
+
+// Sum over a 256-thread block; the result is valid in thread 0.
+__device__ double block_sum256(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return threadIdx.x == 0 ? red[0] + red[1] + red[2] + red[3] : 0.0;
+}
+
+// Nodes a thread takes between exact sines: the rest come from rotating by
+// the angle of 256 nodes (rounding grows by about an ulp per rotation).
+constexpr int kRotSteps = 32;
+
+}  // namespace
+
+// xi_m at r_b = b dr (one block per r): sum_j f_j sin(k_j r) / (2 pi^2 r),
+// f from launch_xi_weights; r = 0 takes the limit sum_j f_j k_j / (2 pi^2).
+__global__ void __launch_bounds__(256) k_xi_r(const double* __restrict__ f, int m, double h, double dr,
+                                              double* __restrict__ xi) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const double r = dr * b;
+  double acc = 0.0;
+  if (b == 0) {
+    for (int j = threadIdx.x; j <= m; j += 256) acc += f[j] * (h * j);
+  } else {
+    double sd, cd;
+    sincos(256.0 * h * r, &sd, &cd);
+    for (int j0 = threadIdx.x; j0 <= m; j0 += 256 * kRotSteps) {
+      double sn, cs;
+      sincos(h * j0 * r, &sn, &cs);
+      const int jend = min(j0 + 256 * kRotSteps, m + 1);
+      for (int j = j0; j < jend; j += 256) {
+        acc += f[j] * sn;
+        const double t = sn * cd + cs * sd;
+        cs = cs * cd - sn * sd;
+        sn = t;
+      }
+    }
+  }
+  const double tot = block_sum256(acc, red);
+  if (threadIdx.x == 0) xi[b] = (b == 0 ? tot : tot / r) / (2.0 * M_PI * M_PI);
+}
+
+// g_i = Simpson weight (dr/3) ln(1 + b2 xi_i) r_i on r_i = i dr (n_r odd).
+__global__ void __launch_bounds__(256) k_lognormal_g(const double* __restrict__ xi, int n_r, double dr, double b2,
+                                                     double* __restrict__ g) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_r) return;
+  const double w = (i == 0 || i == n_r - 1) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+  g[i] = w * dr / 3.0 * log1p(b2 * xi[i]) * (dr * i);
+}
+
+// P_q(k) = 4 pi / k sum_i g_i sin(k r_i), one block per k; k = 0: 4 pi sum g_i r_i.
+__global__ void __launch_bounds__(256) k_lognormal_pq(const double* __restrict__ g, int n_r, double dr,
+                                                      const double* __restrict__ kv, double* __restrict__ pq) {
+  __shared__ double red[4];
+  const double k = kv[blockIdx.x];
+  double acc = 0.0;
+  if (k <= 0.0) {
+    for (int i = threadIdx.x; i < n_r; i += 256) acc += g[i] * (dr * i);
+  } else {
+    double sd, cd;
+    sincos(256.0 * dr * k, &sd, &cd);
+    for (int i0 = threadIdx.x; i0 < n_r; i0 += 256 * kRotSteps) {
+      double sn, cs;
+      sincos(dr * i0 * k, &sn, &cs);
+      const int iend = min(i0 + 256 * kRotSteps, n_r);
+      for (int i = i0; i < iend; i += 256) {
+        acc += g[i] * sn;
+        const double t = sn * cd + cs * sd;
+        cs = cs * cd - sn * sd;
+        sn = t;
+      }
+    }
+  }
+  const double tot = block_sum256(acc, red);
+  if (threadIdx.x == 0) pq[blockIdx.x] = 4.0 * M_PI * (k <= 0.0 ? tot : tot / k);
+}
+
+// Values below 1e-12 of the largest are raised to that floor (one block), so
+// that the result can serve as a tabulated spectrum (ln P interpolation).
+__global__ void __launch_bounds__(256) k_lognormal_floor(double* pq, int n_k) {
+  __shared__ double red[4];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n_k; i += 256) mx = fmax(mx, pq[i]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  const double fl = 1e-12 * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (fl <= 0.0) return;
+  for (int i = threadIdx.x; i < n_k; i += 256) pq[i] = fmax(pq[i], fl);
+}
+
+hipError_t launch_lognormal(const PkParams& p, const LognormalArgs& a, hipStream_t st) {
+  hipError_t e = launch_xi_weights(p, a.smooth, a.h, a.m, a.partial, a.amp, a.f, st);
+  if (e != hipSuccess) return e;
+  LYA_TIMED("xi_r", st, hipLaunchKernelGGL(k_xi_r, dim3(a.n_r), dim3(256), 0, st, a.f, a.m, a.h, a.dr, a.xi));
+  LYA_TIMED("lognormal_g", st,
+            hipLaunchKernelGGL(k_lognormal_g, dim3((a.n_r + 255) / 256), dim3(256), 0, st, a.xi, a.n_r, a.dr, a.b2,
+                               a.g));
+  if (a.n_k > 0) {
+    LYA_TIMED("lognormal_pq", st,
+              hipLaunchKernelGGL(k_lognormal_pq, dim3(a.n_k), dim3(256), 0, st, a.g, a.n_r, a.dr, a.k, a.pq));
+    LYA_TIMED("lognormal_floor", st, hipLaunchKernelGGL(k_lognormal_floor, dim3(1), dim3(256), 0, st, a.pq, a.n_k));
+  }
+  return hipGetLastError();
+}
+
+// ---- box moments ----
+// Per block: sums of re, re^2, im, im^2 over rows (x, y) of the box.
+__global__ void __launch_bounds__(256) k_box_moments(const float2* __restrict__ box, int n, size_t pitch,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t rows = static_cast<int64_t>(n) * n;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const float2* q = box + static_cast<size_t>(row / n) * pitch + static_cast<size_t>(row % n) * n;
+    for (int iz = threadIdx.x; iz < n; iz += 256) {
+      const float2 v = q[iz];
+      s[0] += v.x;
+      s[1] += static_cast<double>(v.x) * v.x;
+      s[2] += v.y;
+      s[3] += static_cast<double>(v.y) * v.y;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double t = block_sum256(s[c], red);
+    if (threadIdx.x == 0) part[blockIdx.x * 4 + c] = t;
+    __syncthreads();
+  }
+}
+
+// out = {mean re, var re, mean im, var im} over the n^3 grid points.
+__global__ void __launch_bounds__(256) k_box_moments_final(const double* __restrict__ part, int nblocks,
+                                                           double inv_count, double* __restrict__ out) {
+  __shared__ double red[4];
+  double t[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += part[b * 4 + c];
+    t[c] = block_sum256(s, red);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m0 = t[0] * inv_count, m1 = t[2] * inv_count;
+    out[0] = m0;
+    out[1] = t[1] * inv_count - m0 * m0;
+    out[2] = m1;
+    out[3] = t[3] * inv_count - m1 * m1;
+  }
+}
+
+hipError_t launch_box_moments(const float2* box, int n, double* part, double* out, hipStream_t st) {
+  LYA_TIMED("box_moments", st,
+            hipLaunchKernelGGL(k_box_moments, dim3(kQsoMomBlocks), dim3(256), 0, st, box, n, plane_pitch(n), part));
+  const double inv = 1.0 / (static_cast<double>(n) * n * n);
+  LYA_TIMED("box_moments_final", st,
+            hipLaunchKernelGGL(k_box_moments_final, dim3(1), dim3(256), 0, st, part, kQsoMomBlocks, inv, out));
+  return hipGetLastError();
+}
+
+// ---- per-distance table: {z, c_1, c_2, c_3} at chi = i kZTabH ----
+__device__ __forceinline__ double bias_qso(double z) { return 3.7 * pow((1.0 + z) / 3.33, 1.7); }
+
+__global__ void __launch_bounds__(256) k_qso_coef(const float* __restrict__ ztab, QsoCoef c, float4* __restrict__ tab) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= kZTabN) return;
+  const double z = ztab[i];
+  double cf[3] = {1.0, 0.0, 0.0};
+  if (c.nb == 3) {
+    double xi[3];
+    for (int j = 0; j < 3; ++j) {
+      const double al = pow((1.0 + z) / (1.0 + c.z[j]), 0.7);
+      xi[j] = pow(1.0 + c.b2[j] * c.xi5, al * al) - 1.0;
+    }
+    const double gq = c.g_ref * (1.0 + c.z_ref) / (1.0 + z);
+    const double bz = bias_qso(z) * gq;
+    const double xi_mod = bz * bz * c.xi5;
+    const double t12 = (z - c.z[0]) / (c.z[1] - c.z[0]);
+    const double t23 = (z - c.z[1]) / (c.z[2] - c.z[1]);
+    const double xi12 = (1.0 - t12) * xi[0] + t12 * xi[1];
+    const double xi23 = (1.0 - t23) * xi[1] + t23 * xi[2];
+    const double den = xi12 - xi23;
+    const double w = fabs(den) <= 1e-12 * fabs(xi[1]) ? 0.5 : fmin(fmax((xi_mod - xi23) / den, 0.0), 1.0);
+    cf[0] = w * (1.0 - t12);
+    cf[1] = w * t12 + (1.0 - w) * (1.0 - t23);
+    cf[2] = (1.0 - w) * t23;
+  }
+  tab[i] = make_float4(static_cast<float>(z), static_cast<float>(cf[0]), static_cast<float>(cf[1]),
+                       static_cast<float>(cf[2]));
+}
+
+// ---- the draw ----
+// One thread per four consecutive voxels along z (one Philox call gives their
+// four decision uniforms).  Selected voxels are appended with one atomic per
+// wave; a slot at or beyond cap is counted but not written.
+template <int NB>
+__global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
+  __shared__ float snz[kQsoMaxNbar], snb[kQsoMaxNbar];
+  for (int i = threadIdx.x; i < a.n_nbar; i += 256) {
+    snz[i] = static_cast<float>(a.nbar_z[i]);
+    snb[i] = static_cast<float>(a.nbar[i]);
+  }
+  __syncthreads();
+  float hv[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) hv[i] = 0.5f * static_cast<float>(*a.var[i]);
+
+  const int n = a.n;
+  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * 256u + threadIdx.x;
+  const int q = n >> 2;
+  const uint64_t row = g / q;
+  const int iz0 = static_cast<int>(g % q) * 4;
+  const int ix = static_cast<int>(row / n), iy = static_cast<int>(row % n);
+  const size_t e0 = static_cast<size_t>(ix) * a.pitch + static_cast<size_t>(iy) * n + iz0;
+
+  float d[NB][4];
+  {
+    const float4 v0 = *reinterpret_cast<const float4*>(a.box_a + e0);
+    const float4 v1 = *reinterpret_cast<const float4*>(a.box_a + e0 + 2);
+    d[0][0] = v0.x; d[0][1] = v0.z; d[0][2] = v1.x; d[0][3] = v1.z;
+    if (NB == 3) {
+      const float4 w0 = *reinterpret_cast<const float4*>(a.box_b + e0);
+      const float4 w1 = *reinterpret_cast<const float4*>(a.box_b + e0 + 2);
+      d[1 % NB][0] = v0.y; d[1 % NB][1] = v0.w; d[1 % NB][2] = v1.y; d[1 % NB][3] = v1.w;
+      d[2 % NB][0] = w0.x; d[2 % NB][1] = w0.z; d[2 % NB][2] = w1.x; d[2 % NB][3] = w1.z;
+    }
+  }
+  const uint4 wd = philox10_x3(make_uint4(static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), 2u, 0u),
+                               static_cast<uint32_t>(a.seed), static_cast<uint32_t>(a.seed >> 32));
+  const uint32_t words[4] = {wd.x, wd.y, wd.z, wd.w};
+  const float rx = static_cast<float>(ix * a.dx_d - a.o[0]);
+  const float ry = static_cast<float>(iy * a.dx_d - a.o[1]);
+  const float r2xy = rx * rx + ry * ry;
+  bool sel[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float rz = static_cast<float>(iz0 + e) * a.dx - a.oz;
+    const float chi = __builtin_sqrtf(r2xy + rz * rz);
+    const float t = chi * (1.0f / static_cast<float>(kZTabH));
+    const int i0 = min(static_cast<int>(t), kZTabN - 2);
+    const float fr = t - static_cast<float>(i0);
+    const float4 c0 = a.tab[i0], c1 = a.tab[i0 + 1];
+    const float z = c0.x + fr * (c1.x - c0.x);
+    // nbar(z): linear between the nodes, zero outside
+    float nb = 0.0f;
+    if (z >= snz[0] && z <= snz[a.n_nbar - 1]) {
+      int lo = 0, hi = a.n_nbar - 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (snz[mid] <= z) lo = mid; else hi = mid;
+      }
+      const float span = snz[hi] - snz[lo];
+      nb = span > 0.0f ? snb[lo] + (snb[hi] - snb[lo]) * ((z - snz[lo]) / span) : snb[lo];
+    }
+    const float lz = __log2f(1.0f + z);
+    float acc;
+    if (NB == 1) {
+      const float al = exp2f(0.7f * (lz - a.l2z[0]));
+      acc = expf(al * d[0][e] - al * al * hv[0]);
+    } else {
+      const float cf[3] = {c0.y + fr * (c1.y - c0.y), c0.z + fr * (c1.z - c0.z), c0.w + fr * (c1.w - c0.w)};
+      acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const float al = exp2f(0.7f * (lz - a.l2z[i]));
+        acc += cf[i] * expf(al * d[i][e] - al * al * hv[i]);
+      }
+    }
+    const float p = fminf(nb * a.dx3 * acc, 1.0f);
+    sel[e] = u01(words[e]) < p;
+  }
+
+  uint64_t b[4];
+  int tot = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    b[e] = __ballot(sel[e]);
+    tot += __popcll(b[e]);
+  }
+  if (tot == 0) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(a.count, static_cast<unsigned long long>(tot));
+  const uint32_t blo = __shfl(static_cast<uint32_t>(base), 0, 64);
+  const uint32_t bhi = __shfl(static_cast<uint32_t>(base >> 32), 0, 64);
+  base = (static_cast<unsigned long long>(bhi) << 32) | blo;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long before = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (sel[e]) {
+      const unsigned long long slot = base + before + __popcll(b[e] & below);
+      if (slot < static_cast<unsigned long long>(a.cap)) {
+        const uint64_t m = (static_cast<uint64_t>(ix) * n + iy) * n + iz0 + e;
+        const uint4 pw = philox10_x3(make_uint4(static_cast<uint32_t>(m), static_cast<uint32_t>(m >> 32), 4u, 0u),
+                                     static_cast<uint32_t>(a.seed), static_cast<uint32_t>(a.seed >> 32));
+        int64_t* o = a.pos + 3 * slot;
+        o[0] = (static_cast<int64_t>(ix) << 32) - (int64_t(1) << 31) + pw.x;
+        o[1] = (static_cast<int64_t>(iy) << 32) - (int64_t(1) << 31) + pw.y;
+        o[2] = (static_cast<int64_t>(iz0 + e) << 32) - (int64_t(1) << 31) + pw.z;
+      }
+    }
+    before += __popcll(b[e]);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+hipError_t launch_qso_draw(const QsoCoef& c, const QsoDrawArgs& a, const float* ztab, float4* tab, hipStream_t st) {
+  LYA_TIMED("qso_coef", st,
+            hipLaunchKernelGGL(k_qso_coef, dim3((kZTabN + 255) / 256), dim3(256), 0, st, ztab, c, tab));
+  LYA_TIMED("qso_zero", st, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, a.count));
+  // n^3 / 4 threads: a multiple of 256 for every supported n (n >= 32)
+  const uint64_t blocks = static_cast<uint64_t>(a.n) * a.n * a.n / 4 / 256;
+  if (a.nb == 3) {
+    LYA_TIMED("qso_draw", st, hipLaunchKernelGGL(k_qso_draw<3>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                                                 st, a));
+  } else {
+    LYA_TIMED("qso_draw", st, hipLaunchKernelGGL(k_qso_draw<1>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                                                 st, a));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lya

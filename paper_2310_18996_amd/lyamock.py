@@ -13,11 +13,13 @@ LIB_PATH = os.path.join(HERE, "liblyamock.so")
 
 LYA_OK, LYA_EINVAL, LYA_EWORKSPACE, LYA_EUNSUPPORTED, LYA_EHIP = 0, -1, -2, -3, -4
 LYA_F32, LYA_BF16 = 0, 1
-LYA_OP_BOX, LYA_OP_SKEWERS = 0, 1
+LYA_OP_BOX, LYA_OP_SKEWERS, LYA_OP_QUASARS = 0, 1, 2
 LYA_C_NONE, LYA_C_DELTA, LYA_C_XX, LYA_C_YY, LYA_C_ZZ, LYA_C_XY, LYA_C_XZ, LYA_C_YZ = -1, 0, 1, 2, 3, 4, 5, 6
 COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6}
 
 EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta",
+           "lya_make_box_pair", "lya_lognormal_workspace_size", "lya_lognormal_pk", "lya_box_moments",
+           "lya_draw_quasars",
            "lya_draw_skewers", "lya_draw_skewers_gauss", "lya_draw_skewers_wide", "lya_apply_fgpa",
            "lya_apply_fgpa_ds", "lya_tune_ps_workspace_size", "lya_tune_ps", "lya_tune_ps_last_error",
            "lya_p1d_workspace_size", "lya_p1d",
@@ -334,6 +336,35 @@ class Tuning(ctypes.Structure):
                 ("sk_blocks_per_cu", ctypes.c_int32), ("sk_unroll", ctypes.c_int32)]
 
 
+class QsoSpec(ctypes.Structure):
+    _fields_ = [("n_box", ctypes.c_int32), ("box_a", ctypes.c_void_p), ("box_b", ctypes.c_void_p),
+                ("z_box", ctypes.c_double * 3), ("var", ctypes.c_void_p * 3), ("xi5", ctypes.c_double),
+                ("observer", ctypes.c_double * 3), ("n_nbar", ctypes.c_int32), ("nbar_z", ctypes.c_void_p),
+                ("nbar", ctypes.c_void_p), ("seed", ctypes.c_uint64)]
+
+
+def qso_spec(boxes, z_box, var_ptrs, observer, nbar_z, nbar, seed, xi5=0.0):
+    """lya_qso_spec.  boxes: [box_a] or [box_a, box_b] device tensors; var_ptrs:
+    device addresses (ints) of the variances; nbar_z, nbar: device float64.
+    The spec holds references to the tensors it points to."""
+    sp = QsoSpec()
+    sp.n_box = len(z_box)
+    sp.box_a = boxes[0].data_ptr()
+    sp.box_b = boxes[1].data_ptr() if len(boxes) > 1 else None
+    for i, z in enumerate(z_box):
+        sp.z_box[i] = float(z)
+        sp.var[i] = int(var_ptrs[i])
+    sp.xi5 = float(xi5)
+    for i in range(3):
+        sp.observer[i] = float(observer[i])
+    sp.n_nbar = int(nbar_z.numel())
+    sp.nbar_z = nbar_z.data_ptr()
+    sp.nbar = nbar.data_ptr()
+    sp.seed = int(seed)
+    sp._refs = (boxes, nbar_z, nbar)   # the device arrays must outlive the spec
+    return sp
+
+
 def _bind_more(lib):
     P, VP = ctypes.POINTER, ctypes.c_void_p
     lib.lya_p1d_workspace_size.restype = ctypes.c_size_t
@@ -395,6 +426,17 @@ def _bind_more(lib):
     lib.lya_tune_ps.restype = ctypes.c_int
     lib.lya_tune_ps.argtypes = [P(TunePsSpec), P(TunePsResult), VP, ctypes.c_size_t, VP]
     lib.lya_tune_ps_last_error.restype = ctypes.c_char_p
+    lib.lya_make_box_pair.restype = ctypes.c_int
+    lib.lya_make_box_pair.argtypes = [P(Box), P(Pk), P(Pk), ctypes.c_uint64, VP, VP, ctypes.c_size_t, VP]
+    lib.lya_lognormal_workspace_size.restype = ctypes.c_size_t
+    lib.lya_lognormal_workspace_size.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32]
+    lib.lya_lognormal_pk.restype = ctypes.c_int
+    lib.lya_lognormal_pk.argtypes = [P(Pk), ctypes.c_double, ctypes.c_double, P(Cosmo), ctypes.c_double,
+                                     ctypes.c_int32, ctypes.c_int32, VP, VP, VP, VP, ctypes.c_size_t, VP]
+    lib.lya_box_moments.restype = ctypes.c_int
+    lib.lya_box_moments.argtypes = [P(Box), VP, VP, VP, ctypes.c_size_t, VP]
+    lib.lya_draw_quasars.restype = ctypes.c_int
+    lib.lya_draw_quasars.argtypes = [P(Box), P(QsoSpec), P(Cosmo), VP, ctypes.c_int64, VP, VP, ctypes.c_size_t, VP]
 
 
 def _lib2():
@@ -619,3 +661,33 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def make_box_pair(box, pk_a, pk_b, seed, field, work, stream=None):
+    """lya_make_box_pair: {delta_a, delta_b} of one set of modes, two spectra."""
+    _check(_lib2().lya_make_box_pair(ctypes.byref(box), ctypes.byref(pk_a), ctypes.byref(pk_b), int(seed),
+                                     _ptr(field), _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def lognormal_workspace_size(smooth, rmax, n_r):
+    return int(_lib2().lya_lognormal_workspace_size(float(smooth), float(rmax), int(n_r)))
+
+
+def lognormal_pk(pk, z_box, z_ref, cosmo, rmax, n_r, k, pq, xi, work, stream=None):
+    """lya_lognormal_pk: P_q at k (device float64) into pq; xi_m at the r nodes into xi (or None)."""
+    _check(_lib2().lya_lognormal_pk(ctypes.byref(pk), float(z_box), float(z_ref), ctypes.byref(cosmo), float(rmax),
+                                    int(n_r), int(k.numel()), _ptr(k), _ptr(pq), _ptr(xi), _ptr(work),
+                                    work.numel() * work.element_size(), _stream(stream)))
+
+
+def box_moments(box, field, out, work, stream=None):
+    """lya_box_moments: out (device float64 [4]) = mean/var of the real and imaginary parts."""
+    _check(_lib2().lya_box_moments(ctypes.byref(box), _ptr(field), _ptr(out), _ptr(work),
+                                   work.numel() * work.element_size(), _stream(stream)))
+
+
+def draw_quasars(box, spec, cosmo, pos_fx, count, work, stream=None):
+    """lya_draw_quasars: pos_fx (device int64 [cap, 3] or None), count (device int64 [1])."""
+    cap = 0 if pos_fx is None else int(pos_fx.shape[0])
+    _check(_lib2().lya_draw_quasars(ctypes.byref(box), ctypes.byref(spec), ctypes.byref(cosmo), _ptr(pos_fx), cap,
+                                    _ptr(count), _ptr(work), work.numel() * work.element_size(), _stream(stream)))

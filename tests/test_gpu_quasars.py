@@ -1,0 +1,255 @@
+"""GPU parity of the lognormal quasar field (section "Quasar generation",
+Appendix A) through the C-ABI: lya_lognormal_pk, lya_make_box_pair,
+lya_box_moments and lya_draw_quasars against oracle.quasars."""
+import numpy as np
+import pytest
+
+from lyahelp import rel_rms
+from oracle import cosmology, field, power, quasars
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")]
+
+torch = pytest.importorskip("torch")
+
+ZB3 = (1.9, 2.75, 3.6)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_18996_amd import lyamock
+    lyamock.load()
+    return lyamock
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.asarray(a), dtype=dtype).cuda()
+
+
+def gpu_lognormal(L, z_box, z_ref, rmax, n_r, k, smooth=2.19, **pkkw):
+    pk = L.pk_struct(smooth=smooth, **pkkw)
+    kt = _dev(k)
+    pq = torch.empty_like(kt)
+    xi = torch.empty(n_r, dtype=torch.float64, device="cuda")
+    work = torch.empty(L.lognormal_workspace_size(smooth, rmax, n_r), dtype=torch.uint8, device="cuda")
+    L.lognormal_pk(pk, z_box, z_ref, L.Cosmo(cosmology.OMEGA_M), rmax, n_r, kt, pq, xi, work)
+    torch.cuda.synchronize()
+    return pq.cpu().numpy(), xi.cpu().numpy()
+
+
+def test_lognormal_spectrum(L):
+    # P_q of the box at z = 2.75 against the oracle's adaptive quadratures
+    rmax, s = 300.0, 2.19
+    k = np.geomspace(0.004, 1.5, 24)
+    pq, xi = gpu_lognormal(L, 2.75, 2.75, rmax, 12001, k, smooth=s)
+    r = np.array([0.0, 5.0, 50.0, 120.0, 300.0])
+    xi_ref = quasars.xi_of_r(power.PowerSpectrum(), r, s)
+    got = xi[np.rint(r / (rmax / 12000)).astype(int)]
+    print("xi", got, xi_ref)
+    np.testing.assert_allclose(got, xi_ref, rtol=1e-6, atol=1e-10)
+    b0 = np.sqrt(quasars.box_bias2(2.75, 2.75))
+    with np.errstate(all="ignore"):
+        ref = quasars.lognormal_pk(power.PowerSpectrum(), b0, s, k, rmax=rmax, nr=1201)
+    big = ref > 1e-6 * ref.max()
+    err = np.abs(pq - ref) / ref
+    print("P_q rel err max %.2e over %d k" % (err[big].max(), big.sum()))
+    assert big.sum() >= 18
+    assert err[big].max() < 2e-5
+
+
+def test_lognormal_bias_scaling(L):
+    # the box redshift enters only through b_0 = b_q(z) G(z_ref)(1+z_ref)/(1+z):
+    # xi is the same, and at small b_0^2 xi the spectrum scales with b_0^2
+    k = np.geomspace(0.01, 0.5, 8)
+    pq1, xi1 = gpu_lognormal(L, 1.9, 2.75, 400.0, 4001, k)
+    pq3, xi3 = gpu_lognormal(L, 3.6, 2.75, 400.0, 4001, k)
+    np.testing.assert_array_equal(xi1, xi3)
+    b1, b3 = quasars.box_bias2(1.9, 2.75), quasars.box_bias2(3.6, 2.75)
+    # on large scales P_q follows b_0^2 P up to the lognormal correction
+    ratio = (pq3 / pq1)[:3]
+    print("P_q ratio", ratio, "b0^2 ratio", b3 / b1)
+    assert np.all(ratio > 1.0) and np.all(np.abs(ratio / (b3 / b1) - 1.0) < 0.3)
+
+
+def _pair_box(L, n, dx, seed, pk_a, pk_b):
+    box = L.box_struct(n, dx)
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fld = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
+    L.make_box_pair(box, pk_a, pk_b, seed, fld, work)
+    torch.cuda.synchronize()
+    return box, fld
+
+
+def test_box_pair_two_spectra(L):
+    # delta_a from the analytic spectrum, delta_b from a table, one set of modes
+    n, dx, seed = 64, 5.0, 31
+    k = np.geomspace(1e-3, 20.0, 300)
+    p = 0.3 * power.PowerSpectrum()(k) * np.exp(-(k * 3.0) ** 2) + 1e-3
+    pa = L.pk_struct(smooth=dx)
+    kt, pt = _dev(k), _dev(p)
+    pb = L.pk_struct(k_tab=kt, p_tab=pt)
+    box, fld = _pair_box(L, n, dx, seed, pa, pb)
+    got = L.box_view(fld, n).cpu().numpy()
+    ra = field.make_box(n, seed, power.amplitude_table(power.PowerSpectrum(), n, dx, dx), ("delta", "zz")).real
+    rb = field.make_box(n, seed, power.amplitude_table(power.TabulatedPower(k, p), n, dx), ("delta", "zz")).real
+    e = (rel_rms(got[..., 0], ra), rel_rms(got[..., 1], rb))
+    print("pair box rel rms %.2e %.2e" % e)
+    assert max(e) < 1e-5
+    # box moments of the same box against the oracle's boxes
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    qw = torch.empty(L.workspace_size(L.LYA_OP_QUASARS, box), dtype=torch.uint8, device="cuda")
+    L.box_moments(box, fld, out, qw)
+    m = out.cpu().numpy()
+    want = np.array([ra.mean(), ra.var(), rb.mean(), rb.var()])
+    print("moments", m, want)
+    np.testing.assert_allclose(m[[1, 3]], want[[1, 3]], rtol=2e-5)
+    assert abs(m[0]) < 1e-6 * np.sqrt(want[1]) and abs(m[2]) < 1e-6 * np.sqrt(want[3])
+    with pytest.raises(L.LyaError):
+        L.make_box_pair(box, pa, pb, seed, fld, qw[:16])
+
+
+def _draw(L, fields, dx, obs, z_box, var, nbar_z, nbar, seed, xi5=0.0, cap=None):
+    """Upload oracle-side fields into library boxes and draw on the GPU."""
+    n = fields[0].shape[0]
+    box = L.box_struct(n, dx)
+    arr_a = np.zeros((n, n, n, 2), dtype=np.float32)
+    arr_a[..., 0] = fields[0]
+    boxes = []
+    if len(fields) == 3:
+        arr_a[..., 1] = fields[1]
+        arr_b = np.zeros((n, n, n, 2), dtype=np.float32)
+        arr_b[..., 0] = fields[2]
+    for arr in ([arr_a] if len(fields) == 1 else [arr_a, arr_b]):
+        f = torch.zeros((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
+        L.box_view(f, n).copy_(torch.from_numpy(arr))
+        boxes.append(f)
+    vt = _dev(var)
+    ptrs = [vt.data_ptr() + 8 * i for i in range(len(var))]
+    spec = L.qso_spec(boxes, z_box, ptrs, obs, _dev(nbar_z), _dev(nbar), seed, xi5)
+    work = torch.empty(L.workspace_size(L.LYA_OP_QUASARS, box), dtype=torch.uint8, device="cuda")
+    cap = n ** 3 if cap is None else cap
+    pos = torch.full((cap, 3), -1, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    L.draw_quasars(box, spec, L.Cosmo(cosmology.OMEGA_M), pos, cnt, work)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    return c, pos[:min(c, cap)].cpu().numpy()
+
+
+def _voxel_ids(pos, n):
+    cells = (pos + (1 << 31)) >> 32
+    return (cells[:, 0] * n + cells[:, 1]) * n + cells[:, 2]
+
+
+def _compare(n, c, pos, idx, fx, p, u, band=1e-5):
+    """Selections agree except where u and p are within the band; positions of
+    common voxels are bit-exact."""
+    gid = _voxel_ids(pos, n)
+    order = np.argsort(gid)
+    gid, pos = gid[order], pos[order]
+    assert len(np.unique(gid)) == len(gid)
+    near = np.abs(u - p) <= band * p + 1e-9
+    only_gpu = np.setdiff1d(gid, idx)
+    only_ref = np.setdiff1d(idx, gid)
+    print("selected gpu %d oracle %d, differing %d/%d (near threshold %d)"
+          % (c, len(idx), len(only_gpu), len(only_ref), near.sum()))
+    assert np.all(near[only_gpu]) and np.all(near[only_ref])
+    common, ig, ir = np.intersect1d(gid, idx, return_indices=True)
+    np.testing.assert_array_equal(pos[ig], fx[ir])
+    assert c == len(gid)
+
+
+def _nbar_table():
+    return np.array([1.6, 2.0, 2.4, 2.9, 3.8]), np.array([2e-5, 5e-5, 6e-5, 3e-5, 1e-5])
+
+
+def test_draw_one_box(L):
+    rng = np.random.default_rng(12)
+    n, dx = 64, 12.0
+    dq = rng.normal(scale=0.6, size=(n, n, n))
+    var = [float(np.var(dq))]
+    obs = np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(2.05)])
+    nz, nb = _nbar_table()
+    c, pos = _draw(L, [dq.astype(np.float32)], dx, obs, [2.33], var, nz, nb, 77)
+    idx, fx, p, u = quasars.draw([dq.astype(np.float32).astype(np.float64)], dx, obs, [2.33], var, nz, nb, 77)
+    assert len(idx) > 5000
+    _compare(n, c, pos, idx, fx, p, u)
+
+
+def test_draw_three_boxes(L):
+    rng = np.random.default_rng(13)
+    n, dx = 64, 20.0
+    f3 = [rng.normal(scale=s, size=(n, n, n)).astype(np.float32) for s in (0.7, 0.55, 0.45)]
+    var = [float(np.var(f.astype(np.float64))) for f in f3]
+    obs = np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(1.95)])
+    nz, nb = _nbar_table()
+    xi5 = 0.82
+    c, pos = _draw(L, f3, dx, obs, ZB3, var, nz, nb, 78, xi5=xi5)
+    idx, fx, p, u = quasars.draw([f.astype(np.float64) for f in f3], dx, obs, ZB3, var, nz, nb, 78, xi5=xi5)
+    assert len(idx) > 5000
+    _compare(n, c, pos, idx, fx, p, u)
+
+
+def test_draw_cap_and_errors(L):
+    rng = np.random.default_rng(14)
+    n, dx = 32, 15.0
+    dq = rng.normal(scale=0.5, size=(n, n, n)).astype(np.float32)
+    var = [float(np.var(dq.astype(np.float64)))]
+    obs = np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(2.2)])
+    nz, nb = _nbar_table()
+    idx, fx, p, u = quasars.draw([dq.astype(np.float64)], dx, obs, [2.5], var, nz, nb, 5)
+    full, _ = _draw(L, [dq], dx, obs, [2.5], var, nz, nb, 5)
+    c, pos = _draw(L, [dq], dx, obs, [2.5], var, nz, nb, 5, cap=100)
+    assert c == full and len(pos) == 100
+    gid = _voxel_ids(pos, n)
+    assert len(np.unique(gid)) == 100
+    near = np.abs(u - p) <= 1e-5 * p + 1e-9
+    assert np.all(np.isin(gid, idx) | near[gid])
+    # zero density: nothing drawn
+    c0, _ = _draw(L, [dq], dx, obs, [2.5], var, nz, 0.0 * nb, 5)
+    assert c0 == 0
+    with pytest.raises(L.LyaError):
+        _draw(L, [dq], dx, np.array([0.0, 0.0, -20000.0]), [2.5], var, nz, nb, 5)
+    with pytest.raises(L.LyaError):
+        _draw(L, [dq, dq, dq], dx, obs, (2.0, 1.9, 3.0), var * 3, nz, nb, 5, xi5=0.8)
+
+
+def test_chain_one_box(L):
+    # P_q, the delta_q box, its variance and the draw, each side on its own
+    n, dx, seed = 64, 10.0, 41
+    z0, rmax = 2.5, 400.0
+    kk = np.geomspace(2e-3, 2.0, 48)
+    pq_gpu, _ = gpu_lognormal(L, z0, z0, rmax, 16001, kk, smooth=dx)
+    kt = _dev(kk)
+    pt = _dev(pq_gpu)
+    box = L.box_struct(n, dx)
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fld = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
+    L.make_box(box, L.pk_struct(k_tab=kt, p_tab=pt), seed, 1.0, 0, fld, work)
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    qw = torch.empty(L.workspace_size(L.LYA_OP_QUASARS, box), dtype=torch.uint8, device="cuda")
+    L.box_moments(box, fld, out, qw)
+    obs = np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(2.3)])
+    nz, nb = _nbar_table()
+    spec = L.qso_spec([fld], [z0], [out.data_ptr() + 8], obs, _dev(nz), _dev(nb), 9)
+    pos = torch.empty((n ** 3, 3), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    L.draw_quasars(box, spec, L.Cosmo(cosmology.OMEGA_M), pos, cnt, qw)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    pos = pos[:c].cpu().numpy()
+
+    b0 = np.sqrt(quasars.box_bias2(z0, z0))
+    with np.errstate(all="ignore"):
+        pq = quasars.lognormal_pk(power.PowerSpectrum(), b0, dx, kk, rmax=rmax, nr=1601)
+    pq = np.maximum(pq, 1e-12 * pq.max())
+    dq = field.make_box(n, seed, power.amplitude_table(power.TabulatedPower(kk, pq), n, dx), ("delta",)).real
+    var = [float(np.var(dq))]
+    got_var = out.cpu().numpy()[1]
+    print("variance gpu %.6e oracle %.6e" % (got_var, var[0]))
+    assert abs(got_var / var[0] - 1.0) < 1e-3
+    idx, fx, p, u = quasars.draw([dq], dx, obs, [z0], var, nz, nb, 9)
+    assert len(idx) > 3000
+    # the two spectra agree to ~1e-4, so p agrees to ~1e-3
+    _compare(n, c, pos, idx, fx, p, u, band=3e-3)
