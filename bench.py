@@ -257,6 +257,92 @@ def wide_leg(L, torch, stream, reps=3):
 
 
 # ---------------------------------------------------------------- tuning leg
+def quasar_leg(L, torch, stream, cfg, reps=2):
+    """The lognormal quasar field on the workload's box (section "Quasar
+    generation", Appendix A): P_q of the three boxes at z = 1.9, 2.75, 3.6
+    from the smoothed matter spectrum, the pair box {delta_q1, delta_q2} and
+    the box {delta_q3, 0} from the step's modes, their variances, and the
+    three-box draw of every voxel against a quasar density peaking at
+    1e-5 (h/Mpc)^3."""
+    import mockinputs
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    box = L.box_struct(n, dx)
+    cosmo = L.Cosmo(cfg["omega_m"])
+    zb = mockinputs.QSO_Z_BOXES
+    rmax, n_r = mockinputs.QSO_RMAX, mockinputs.QSO_NR
+    kk = torch.from_numpy(mockinputs.qso_k_nodes(n, dx)).cuda()
+    pkm = L.pk_struct(smooth=dx, **cfg["pk"])
+    lw = torch.empty(L.lognormal_workspace_size(dx, rmax, n_r), dtype=torch.uint8, device="cuda")
+    pqs = [torch.empty_like(kk) for _ in range(3)]
+    xi = torch.empty(n_r, dtype=torch.float64, device="cuda")
+    bwork = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fa, fb = (torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") for _ in range(2))
+    qw = torch.empty(L.workspace_size(L.LYA_OP_QUASARS, box), dtype=torch.uint8, device="cuda")
+    mom = torch.zeros(8, dtype=torch.float64, device="cuda")
+    nz, nb = mockinputs.qso_nbar()
+    nzt, nbt = torch.from_numpy(nz).cuda(), torch.from_numpy(nb).cuda()
+    cap = 1 << 23
+    pos = torch.empty((cap, 3), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pks = [L.pk_struct(k_tab=kk, p_tab=pq) for pq in pqs]
+
+    def spectra():
+        for z, pq in zip(zb, pqs):
+            L.lognormal_pk(pkm, z, zb[1], cosmo, rmax, n_r, kk, pq, xi, lw, stream)
+
+    def boxes():
+        L.make_box_pair(box, pks[0], pks[1], seed, fa, bwork, stream)
+        L.make_box(box, pks[2], seed, 1.0, False, fb, bwork, stream)
+
+    def moments():
+        L.box_moments(box, fa, mom[:4], qw, stream)
+        L.box_moments(box, fb, mom[4:], qw, stream)
+
+    def timed(fn, r=reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(r):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / r
+
+    pq_ms = timed(spectra, 1)
+    xi5 = float(xi[int(round(5.0 / (rmax / (n_r - 1))))])
+    boxes_ms = timed(boxes)
+    mom_ms = timed(moments)
+    base = mom.data_ptr()
+    spec = L.qso_spec([fa, fb], zb, [base + 8, base + 24, base + 40], mockinputs.qso_observer(n, dx), nzt, nbt,
+                      seed, xi5)
+    draw = lambda: L.draw_quasars(box, spec, cosmo, pos, cnt, qw, stream)
+    draw()
+    torch.cuda.synchronize()
+    L.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        draw()
+    torch.cuda.synchronize()
+    draw_ms = (time.perf_counter() - t0) * 1e3 / reps
+    kt = L.timing_read()
+    L.timing_enable(False)
+    count = int(cnt.item())
+    kern = kt["qso_draw"][0] / kt["qso_draw"][1]
+    cells = float(n) ** 3
+    ab = 16.0 * cells + 24.0 * min(count, cap)
+    achieved = ab / (kern * 1e-3) / 1e9
+    m = mom.cpu().numpy()
+    return dict(workload="%d^3 box at %.2f Mpc/h, boxes at z = %s, observer at (L/2, L/2, -chi(%.1f)), "
+                         "P_q on %d k nodes (rmax %.0f Mpc/h, %d r nodes)" % (
+                             n, dx, ",".join("%.2f" % z for z in zb), mockinputs.QSO_Z_OBS, kk.numel(), rmax, n_r),
+                lognormal_pk_ms_3_boxes=pq_ms, boxes_ms=boxes_ms, box_cells_per_s=2 * cells / (boxes_ms * 1e-3),
+                moments_ms=mom_ms, draw_ms=draw_ms, draw_kernel_ms=kern, voxels_per_s=cells / (kern * 1e-3),
+                quasars=count, xi5=xi5, variances=[float(m[1]), float(m[3]), float(m[5])],
+                roofline=dict(kernel="qso_draw", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=achieved / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=ab,
+                              mean_launch_ms=kern))
+
+
 def stored_pixels(L, torch, cfg, seed, sk_seed):
     """Pre-FGPA pixels (delta_L + delta_S, eta_par) of a mock made by the
     library: box of cfg, skewer table drawn with sk_seed."""
@@ -500,6 +586,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured replay")
     ap.add_argument("--no-wide", action="store_true", help="skip the wide-angle eta_par leg")
     ap.add_argument("--no-gauss", action="store_true", help="skip the 7^3 Gaussian-kernel skewer pass")
+    ap.add_argument("--no-quasars", action="store_true", help="skip the lognormal quasar leg")
     ap.add_argument("--tune-labels", type=int, default=100_000)
     ap.add_argument("--tune-steps", type=int, default=20_000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -666,9 +753,15 @@ def main():
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
     else:
         out["cpu_baseline"] = None
-    if not args.no_tune or not args.no_wide:
+    if not args.no_tune or not args.no_wide or not args.no_quasars:
         del field, bwork, swork, dens, eta, flux, dev
         torch.cuda.empty_cache()
+    if not args.no_quasars:
+        print("bench: lognormal quasar leg", file=sys.stderr, flush=True)
+        out["quasars"] = quasar_leg(L, torch, stream, cfg)
+        torch.cuda.empty_cache()
+    else:
+        out["quasars"] = None
     if not args.no_wide:
         print("bench: wide-angle leg", file=sys.stderr, flush=True)
         out["wide_angle"] = wide_leg(L, torch, stream)

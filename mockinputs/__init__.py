@@ -70,6 +70,33 @@ CONFIGS = {
 }
 
 
+# Lognormal quasar field: the paper's three box redshifts, the r range and
+# nodes of the P_q transform (5 Mpc/h is node 100), a quasar density in
+# (h/Mpc)^3 with the shape of the skewer n(z) peaking at 1e-5, and the
+# observer of the quasar draw at (L/2, L/2, -chi(1.8)).
+QSO_Z_BOXES = (1.9, 2.75, 3.6)
+QSO_RMAX = 2000.0
+QSO_NR = 40001
+QSO_Z_OBS = 1.8
+
+
+def qso_nbar():
+    z = np.round(np.linspace(1.7, 4.0, 24), 10)
+    shape = (1 + z) ** 2 * np.exp(-((z - 2.3) / 0.6) ** 2)
+    return z, 1e-5 * shape / shape.max()
+
+
+def qso_k_nodes(n, dx, count=512):
+    """k nodes (h/Mpc) of the tabulated P_q: from half the fundamental mode to
+    just past the box's largest |k|."""
+    L = n * dx
+    return np.geomspace(np.pi / L, 1.05 * np.sqrt(3.0) * np.pi / dx, count)
+
+
+def qso_observer(n, dx):
+    return np.array([n * dx / 2, n * dx / 2, -_Distance().chi_of(QSO_Z_OBS)])
+
+
 def config(name, **over):
     c = dict(CONFIGS[name])
     c.update(over)

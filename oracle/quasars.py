@@ -136,31 +136,39 @@ def mix_coeffs(z, z_box, xi5, omega_m=cosmology.OMEGA_M):
     return np.stack([w * (1.0 - t12), w * t12 + (1.0 - w) * (1.0 - t23), (1.0 - w) * t23], axis=-1)
 
 
-def probability(fields, dx, observer, z_box, sigma2, nbar_z, nbar, xi5=None, omega_m=cosmology.OMEGA_M):
-    """p of every voxel (flat, linear index order) and its redshift."""
-    n = fields[0].shape[0]
-    m = np.arange(n)
-    gx, gy, gz = np.meshgrid(m, m, m, indexing="ij")
-    pos = np.stack([gx, gy, gz], axis=-1).astype(np.float64) * dx
-    chi = np.sqrt(np.sum((pos - np.asarray(observer, dtype=np.float64)) ** 2, axis=-1)).ravel()
+def probability_at(lin, values, n, dx, observer, z_box, sigma2, nbar_z, nbar, xi5=None,
+                   omega_m=cosmology.OMEGA_M):
+    """p and z of the voxels with linear indices lin (grid point m at m dx),
+    values[i] holding delta_i at those voxels."""
+    lin = np.asarray(lin, dtype=np.int64)
+    pos = np.stack([lin // (n * n), (lin // n) % n, lin % n], axis=-1).astype(np.float64) * dx
+    chi = np.sqrt(np.sum((pos - np.asarray(observer, dtype=np.float64)) ** 2, axis=-1))
     z = cosmology.z_of_chi(chi, omega_m)
     nb = np.interp(z, nbar_z, nbar, left=0.0, right=0.0)
-    if len(fields) == 1:
-        coef = np.ones((len(z), 1))
-    else:
-        coef = mix_coeffs(z, z_box, xi5, omega_m)
+    coef = np.ones((len(z), 1)) if len(values) == 1 else mix_coeffs(z, z_box, xi5, omega_m)
     acc = np.zeros(len(z))
-    for i, (f, zi, s2) in enumerate(zip(fields, z_box, sigma2)):
+    for i, (v, zi, s2) in enumerate(zip(values, z_box, sigma2)):
         al = alpha_of_z(z, zi)
-        acc += coef[:, i] * np.exp(al * np.asarray(f, dtype=np.float64).ravel() - 0.5 * al * al * s2)
+        acc += coef[:, i] * np.exp(al * np.asarray(v, dtype=np.float64) - 0.5 * al * al * s2)
     return np.clip(nb * dx ** 3 * acc, 0.0, 1.0), z
 
 
-def decision_uniforms(seed, n_vox):
-    lin = np.arange(n_vox, dtype=np.uint64)
+def probability(fields, dx, observer, z_box, sigma2, nbar_z, nbar, xi5=None, omega_m=cosmology.OMEGA_M):
+    """p of every voxel (flat, linear index order) and its redshift."""
+    n = fields[0].shape[0]
+    return probability_at(np.arange(n ** 3), [np.asarray(f).ravel() for f in fields], n, dx, observer, z_box,
+                          sigma2, nbar_z, nbar, xi5, omega_m)
+
+
+def decision_uniforms_at(seed, lin):
+    lin = np.asarray(lin, dtype=np.uint64)
     w = philox.words(seed, 2, lin >> np.uint64(2))
     wd = np.take_along_axis(w, (lin & np.uint64(3)).astype(np.int64)[:, None], axis=1)[:, 0]
     return ((wd >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+
+
+def decision_uniforms(seed, n_vox):
+    return decision_uniforms_at(seed, np.arange(n_vox))
 
 
 def positions(seed, idx, n):

@@ -96,13 +96,14 @@ __device__ __forceinline__ float comp_mult(int comp, int nx, int ny, int nz, int
   return f * static_cast<float>(a * b) * __builtin_amdgcn_rcpf(static_cast<float>(n2));
 }
 
-// Mode (ix, iy, iz) of the packed spectrum.
-template <int N>
+// Mode (ix, iy, iz) of the packed spectrum (a second amplitude table only in
+// the generic synthesiser).
+template <int N, bool TWO_TABLES>
 __device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, int iz) {
   const int nx = sfreq(ix, N), ny = sfreq(iy, N), nz = sfreq(iz, N);
   const int n2 = nx * nx + ny * ny + nz * nz;
   float s = g.table[n2];
-  float sb = g.table_b ? g.table_b[n2] : s;
+  float sb = (TWO_TABLES && g.table_b) ? g.table_b[n2] : s;
   if (g.only_n2 >= 0 && n2 != g.only_n2) s = sb = 0.0f;
   if (s == 0.0f && sb == 0.0f) return make_float2(0.0f, 0.0f);
   const uint64_t lin = (static_cast<uint64_t>(ix) * N + iy) * N + iz;
@@ -122,7 +123,7 @@ __device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, i
   }
   const float ma = comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
   const float mb = comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
-  if (g.table_b) {
+  if (TWO_TABLES && g.table_b) {
     const float pa = s * ma, pb = sb * mb;
     return make_float2(w.x * pa - w.y * pb, w.y * pa + w.x * pb);
   }
@@ -384,7 +385,7 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
       int p, j;
       P::template coords<R>(tid + b * NT, p, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b * R + r] = gen_mode<N>(g, outer, t0 + p, j + r * (N / R));
+      for (int r = 0; r < R; ++r) v[b * R + r] = gen_mode<N, GM == GEN_GENERIC>(g, outer, t0 + p, j + r * (N / R));
     }
   } else {
     P::load_global0(v, data, outer, t0, tid);

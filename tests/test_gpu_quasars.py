@@ -253,3 +253,87 @@ def test_chain_one_box(L):
     assert len(idx) > 3000
     # the two spectra agree to ~1e-4, so p agrees to ~1e-3
     _compare(n, c, pos, idx, fx, p, u, band=3e-3)
+
+
+SHELL = 10003
+SHELL_SIGMA8 = 100.0  # field rms ~0.4 from the shell's 288 modes
+
+
+def test_full_size_draw_on_a_single_shell_box(L):
+    # the 2048^3 box of the benchmark's quasar leg: a single-shell field (the
+    # only_n2 hook) in both parts of a pair box, drawn as one box and as three
+    # (delta_1 = delta_2 = delta_3); the oracle evaluates the field by direct
+    # summation, p and the uniforms at sampled voxels, and the exact variance
+    import mockinputs
+    cfg = mockinputs.config("big")
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    print("2048^3 pair box, shell |n|^2 = %d" % SHELL, flush=True)
+    box = L.box_struct(n, dx)
+    pk = L.pk_struct(sigma8=SHELL_SIGMA8, only_n2=SHELL)
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fld = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
+    L.make_box_pair(box, pk, pk, seed, fld, work)
+    del work
+    qw = torch.empty(L.workspace_size(L.LYA_OP_QUASARS, box), dtype=torch.uint8, device="cuda")
+    mom = torch.zeros(4, dtype=torch.float64, device="cuda")
+    L.box_moments(box, fld, mom, qw)
+    tab = power.amplitude_table(power.PowerSpectrum(**dict(cfg["pk"], sigma8=SHELL_SIGMA8)), n, dx)
+    freqs, coef = field.shell_modes(n, seed, tab, SHELL, comps=("delta",))
+    var = float(np.sum(np.abs(coef) ** 2))   # Parseval for the unnormalised inverse DFT
+    m = mom.cpu().numpy()
+    print("variance gpu %.8e %.8e exact %.8e" % (m[1], m[3], var), flush=True)
+    assert abs(m[1] / var - 1.0) < 1e-5 and abs(m[3] / var - 1.0) < 1e-5
+
+    nz, nb = mockinputs.qso_nbar()
+    nb = 100.0 * nb                # p up to 1e-2: many selections per sample
+    obs = mockinputs.qso_observer(n, dx)
+    nzt, nbt = _dev(nz), _dev(nb)
+    cap = 1 << 26
+    pos = torch.empty((cap, 3), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rng = np.random.default_rng(3)
+    sample = np.unique(rng.integers(0, n ** 3, 200_000))
+    def shell_at(lin):
+        a, rest = np.divmod(lin, n * n)
+        b, c = np.divmod(rest, n)
+        return field.shell_field_at(n, freqs, coef, a, b, c).real
+    vals = shell_at(sample)
+    base = mom.data_ptr()
+    band = 2e-5
+    for nbox, zb, ptrs in ((1, [2.75], [base + 8]), (3, list(ZB3), [base + 8, base + 24, base + 8])):
+        spec = L.qso_spec([fld] if nbox == 1 else [fld, fld], zb, ptrs, obs, nzt, nbt, 99, xi5=0.82)
+        L.draw_quasars(box, spec, L.Cosmo(cfg["omega_m"]), pos, cnt, qw)
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        assert 0 < c < cap
+        got = pos[:c].cpu().numpy()
+        gid = _voxel_ids(got, n)
+        order = np.argsort(gid)
+        gid, got = gid[order], got[order]
+        assert np.all(np.diff(gid) > 0)
+        p, _ = quasars.probability_at(sample, [vals] * nbox, n, dx, obs, zb, [var] * nbox, nz, nb, xi5=0.82)
+        u = quasars.decision_uniforms_at(99, sample)
+        inside = np.isin(sample, gid)
+        sure_in = u < p * (1.0 - band)
+        sure_out = u > p * (1.0 + band) + 1e-12
+        print("%d box(es): %d quasars; sample %d voxels, %d surely in, %d in the band"
+              % (nbox, c, len(sample), sure_in.sum(), (~sure_in & ~sure_out).sum()), flush=True)
+        assert sure_in.sum() > 150
+        assert np.all(inside[sure_in]) and not np.any(inside[sure_out])
+        # positions of the sampled selected voxels, bit for bit
+        hit = sample[inside]
+        rows = np.searchsorted(gid, hit)
+        np.testing.assert_array_equal(got[rows], quasars.positions(99, hit, n))
+        # 2000 selected voxels anywhere in the box are selections of the oracle too
+        pick = np.sort(rng.choice(c, size=2000, replace=False))
+        p2, _ = quasars.probability_at(gid[pick], [shell_at(gid[pick])] * nbox, n, dx, obs, zb, [var] * nbox,
+                                       nz, nb, xi5=0.82)
+        u2 = quasars.decision_uniforms_at(99, gid[pick])
+        assert np.all(u2 <= p2 * (1.0 + band) + 1e-12)
+        np.testing.assert_array_equal(got[pick], quasars.positions(99, gid[pick], n))
+        # the count against the sample's estimate of sum p
+        est = p.mean() * float(n) ** 3
+        print("count %d, sampled estimate %.4g" % (c, est), flush=True)
+        assert abs(c / est - 1.0) < 0.05
+    del fld, pos
+    torch.cuda.empty_cache()
