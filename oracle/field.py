@@ -34,7 +34,7 @@ import numpy as np
 
 from . import philox
 
-COMPONENTS = ("delta", "xx", "yy", "zz", "xy", "xz", "yz")
+COMPONENTS = ("delta", "xx", "yy", "zz", "xy", "xz", "yz", "vx", "vy", "vz")
 
 
 def signed_freq(i, n):
@@ -76,14 +76,21 @@ def white_noise(n, seed, ix_slice=None, fixed_amp=False):
     return noise_at(n, seed, gx, gy, gz, fixed_amp)
 
 
-def multiplier_at(n, comp, f, gx, gy, gz):
-    """Real multiplier turning delta_hat into the requested component at the
-    modes (gx, gy, gz); None for delta."""
+def multiplier_at(n, comp, f, gx, gy, gz, box_len=None):
+    """Multiplier turning delta_hat into the requested component at the
+    modes (gx, gy, gz); None for delta.  Real for eta_pq; for the velocity
+    v_j (eq:velocity, at z = 0 with aH = 100 km/s per Mpc/h) it is
+    i f 100 k_j / k^2 (km/s), k_j = 2 pi n_j / box_len, zero on the Nyquist
+    plane of j (odd in k: such a mode is its own partner)."""
     if comp == "delta":
         return None
     nv = [signed_freq(gx, n), signed_freq(gy, n), signed_freq(gz, n)]
     n2 = nv[0] ** 2 + nv[1] ** 2 + nv[2] ** 2
     axis = {"x": 0, "y": 1, "z": 2}
+    if comp[0] == "v":
+        j = nv[axis[comp[1]]]
+        kj_over_k2 = np.where((n2 > 0) & (j != -(n // 2)), j / np.where(n2 > 0, n2, 1), 0.0) * box_len / (2 * np.pi)
+        return 1j * f * 100.0 * kj_over_k2
     p, q = axis[comp[0]], axis[comp[1]]
     num = (nv[p] * nv[q]).astype(np.float64)
     if p != q:
@@ -92,12 +99,12 @@ def multiplier_at(n, comp, f, gx, gy, gz):
     return f * np.where(n2 > 0, num / np.where(n2 > 0, n2, 1), 0.0)
 
 
-def component_multiplier(n, comp, f=1.0, ix_slice=None):
-    """Real multiplier turning delta_hat into the requested component."""
+def component_multiplier(n, comp, f=1.0, ix_slice=None, box_len=None):
+    """Multiplier turning delta_hat into the requested component."""
     if comp == "delta":
         return None
     gx, gy, gz = mode_grid(n, ix_slice)
-    return multiplier_at(n, comp, f, gx, gy, gz)
+    return multiplier_at(n, comp, f, gx, gy, gz, box_len)
 
 
 def amplitudes(n, table, ix_slice=None, only_n2=-1):
@@ -110,14 +117,15 @@ def amplitudes(n, table, ix_slice=None, only_n2=-1):
 
 
 def spectrum(n, seed, table, comps=("delta", "zz"), f=1.0, fixed_amp=False,
-             only_n2=-1, ix_slice=None):
-    """Packed k-space field X = C_a + i C_b for the component pair comps."""
+             only_n2=-1, ix_slice=None, box_len=None):
+    """Packed k-space field X = C_a + i C_b for the component pair comps
+    (box_len, the box side in Mpc/h, is needed by the velocities)."""
     w = white_noise(n, seed, ix_slice, fixed_amp)
     s = amplitudes(n, table, ix_slice, only_n2)
     base = s * w
     out = []
     for c in comps:
-        m = component_multiplier(n, c, f, ix_slice)
+        m = component_multiplier(n, c, f, ix_slice, box_len)
         out.append(base if m is None else m * base)
     if len(out) == 1:
         return out[0]
@@ -131,10 +139,10 @@ def inverse_dft3(x):
 
 
 def make_box(n, seed, table, comps=("delta", "zz"), f=1.0, fixed_amp=False,
-             only_n2=-1):
+             only_n2=-1, box_len=None):
     """Complex field C_a + i C_b on the grid (for comps=("delta","zz"),
     real part = delta, imaginary part = eta_par along z)."""
-    x = spectrum(n, seed, table, comps, f, fixed_amp, only_n2)
+    x = spectrum(n, seed, table, comps, f, fixed_amp, only_n2, box_len=box_len)
     return inverse_dft3(x)
 
 

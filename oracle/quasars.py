@@ -48,11 +48,30 @@ Readings (the paper is silent on these):
   position of a selected voxel uses stream 4, counter m, words 0-2: per axis
   (m_axis << 32) - 2^31 + w in cell units times 2^32, uniform over the voxel
   [m - 1/2, m + 1/2).
+
+Catalogue and lines of sight (section "Quasar generation": the quasar
+velocity from eq:velocity; readings, the paper giving no formulas):
+
+* the velocity boxes are made at z = 0 with f = 1 and aH = 100 km/s per
+  Mpc/h, v_hat_j = i 100 k_j / k^2 delta_hat; at redshift z the velocity is
+  that times G(z) f(z) E(z) / (1 + z) (the faH of eq:velocity with the
+  growth of the z = 0 box), f = dln G / dln a of flat LCDM;
+* a quasar at x (its fixed-point position times dx) has the comoving
+  distance chi = |x - O|, the cosmological redshift z_c = z(chi), the
+  line-of-sight velocity v_par = v(x) . (x - O) / chi with v trilinear from
+  the boxes (as the pixels), and the redshift z_q = z_c + (1 + z_c) v_par / c;
+* its forest runs from the red end z_hi = (1 + z_q) r_hi - 1 towards the
+  observer down to z_lo = max((1 + z_q) r_lo - 1, z_min), r = lambda /
+  lambda_Lya for the rest-frame window (1040-1200 A in the paper's P1D
+  selection); pixel j at chi(z_hi) - j dchi, npix = floor((chi(z_hi) -
+  chi(z_lo)) / dchi) capped at 2048 (0 when z_hi <= z_lo); the origin
+  O + u chi(z_hi) and the step -u dchi, u = (x - O) / chi, in cell units
+  times 2^32 rounded to the nearest integer.
 """
 import numpy as np
 from scipy import integrate
 
-from . import cosmology, philox
+from . import cosmology, philox, skewers
 
 
 def bias_qso(z):
@@ -186,3 +205,55 @@ def draw(fields, dx, observer, z_box, sigma2, nbar_z, nbar, seed, xi5=None, omeg
     u = decision_uniforms(seed, p.size)
     idx = np.flatnonzero(u < p)
     return idx, positions(seed, idx, fields[0].shape[0]), p, u
+
+
+C_KMS = 299792.458
+MAX_PIX = 2048
+
+
+def growth_rate(z, omega_m=cosmology.OMEGA_M):
+    """f = dln D / dln a of flat LCDM with D = E(a) I(a), I = int_0^a
+    da' / (a' E(a'))^3: f = a E'/E + a / (I (a E)^3), a E'/E = -3 Om / (2 a^3 E^2)."""
+    a = 1.0 / (1.0 + float(z))
+    e2 = omega_m / a ** 3 + 1.0 - omega_m
+    integ = integrate.quad(lambda x: (omega_m / x + (1.0 - omega_m) * x * x) ** -1.5, 0.0, a,
+                           epsabs=0, epsrel=1e-13)[0]
+    return -1.5 * omega_m / (a ** 3 * e2) + a / (integ * (a * a * e2) ** 1.5)
+
+
+def velocity_factor(z, omega_m=cosmology.OMEGA_M):
+    """G(z) f(z) E(z) / (1 + z): the z = 0, f = 1 velocity boxes to redshift z."""
+    return growth(z, omega_m) * growth_rate(z, omega_m) * float(cosmology.hubble_e(z, omega_m)) / (1.0 + z)
+
+
+def lines_of_sight(pos_fx, vx, vy, vz, dx, observer, r_lo, r_hi, z_min, dchi, omega_m=cosmology.OMEGA_M):
+    """Redshift-space catalogue and its skewer table, quasar by quasar.
+    vx, vy, vz: velocity grids (z = 0, f = 1).  Returns a dict with z_c, z_q,
+    origin_fx, step_fx, npix, offset, chi0, total."""
+    pos = np.asarray(pos_fx, dtype=np.int64)
+    o = np.asarray(observer, dtype=np.float64)
+    nq = len(pos)
+    out = dict(z_c=np.zeros(nq), z_q=np.zeros(nq), origin_fx=np.zeros((nq, 3), np.int64),
+               step_fx=np.zeros((nq, 3), np.int64), npix=np.zeros(nq, np.int32), chi0=np.zeros(nq))
+    for q in range(nq):
+        x = pos[q].astype(np.float64) / 2.0 ** 32 * dx
+        d = x - o
+        chi = np.sqrt(np.sum(d * d))
+        u = d / chi
+        zc = float(cosmology.z_of_chi(np.array([chi]), omega_m)[0])
+        v = np.array([skewers.trilinear(g, pos[q][None, :])[0] for g in (vx, vy, vz)])
+        vpar = float(v @ u) * velocity_factor(zc, omega_m)
+        zq = zc + (1.0 + zc) * vpar / C_KMS
+        z_hi = (1.0 + zq) * r_hi - 1.0
+        z_lo = max((1.0 + zq) * r_lo - 1.0, z_min)
+        c_hi = float(cosmology.chi_of_z(z_hi, omega_m))
+        npix = 0
+        if z_hi > z_lo:
+            c_lo = float(cosmology.chi_of_z(z_lo, omega_m))
+            npix = min(int(np.floor((c_hi - c_lo) / dchi)), MAX_PIX)
+        out["z_c"][q], out["z_q"][q], out["chi0"][q], out["npix"][q] = zc, zq, c_hi, npix
+        out["origin_fx"][q] = np.rint((o + u * c_hi) / dx * 2.0 ** 32).astype(np.int64)
+        out["step_fx"][q] = np.rint(-u * dchi / dx * 2.0 ** 32).astype(np.int64)
+    out["offset"] = np.concatenate([[0], np.cumsum(out["npix"].astype(np.int64))[:-1]]) if nq else np.zeros(0, np.int64)
+    out["total"] = int(out["npix"].astype(np.int64).sum())
+    return out

@@ -40,7 +40,7 @@ def test_fields_are_real():
     n = 16
     tab = _table(n)
     for comp in field.COMPONENTS:
-        x = field.spectrum(n, 9, tab, (comp,))
+        x = field.spectrum(n, 9, tab, (comp,), box_len=40.0)
         v = field.inverse_dft3(x)
         assert np.max(np.abs(v.imag)) <= 1e-12 * max(np.max(np.abs(v.real)), 1e-300)
 
@@ -149,3 +149,25 @@ def test_shell_direct_sum_matches_box(n, s2):
     ix, iy, iz = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
     got = field.shell_field_at(n, freqs, coef, ix, iy, iz, chunk=999)
     np.testing.assert_allclose(got, box, atol=1e-12 * np.abs(box).max())
+
+
+def test_velocity_continuity_and_reality():
+    # eq:velocity: v_hat = i f aH k / k^2 delta_hat, so i k . v_hat = -f aH delta_hat
+    # (linear continuity), checked on the forward FFT of the real-space boxes
+    n, dx, f = 16, 5.0, 0.7
+    L = n * dx
+    tab = power.amplitude_table(power.PowerSpectrum(), n, dx)
+    vxy = field.make_box(n, 3, tab, ("vx", "vy"), f=f, box_len=L)
+    vz = field.make_box(n, 3, tab, ("vz",), f=f, box_len=L)
+    delta = field.make_box(n, 3, tab, ("delta",)).real
+    assert np.max(np.abs(vz.imag)) < 1e-9 * np.max(np.abs(vz.real))   # a real field
+    k1 = 2 * np.pi * np.fft.fftfreq(n, d=dx)
+    kx, ky, kz = np.meshgrid(k1, k1, k1, indexing="ij")
+    div = 1j * (kx * np.fft.fftn(vxy.real) + ky * np.fft.fftn(vxy.imag) + kz * np.fft.fftn(vz.real))
+    want = -f * 100.0 * np.fft.fftn(delta)
+    nyq = (np.abs(np.fft.fftfreq(n) * n) == n // 2)
+    off = ~(nyq[:, None, None] | nyq[None, :, None] | nyq[None, None, :])
+    np.testing.assert_allclose(div[off], want[off], rtol=0, atol=1e-9 * np.abs(want).max())
+    # the Nyquist plane of v_j carries nothing
+    vx_hat = np.fft.fftn(vxy.real)
+    assert np.max(np.abs(vx_hat[n // 2])) < 1e-9 * np.abs(vx_hat).max()

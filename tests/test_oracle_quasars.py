@@ -151,3 +151,56 @@ def test_draw_mean_count():
     expect = p.sum()
     assert abs(np.mean(counts) - expect) < 4 * np.sqrt(expect / 6) + 3
     assert abs(expect / (0.02 * n ** 3) - 1.0) < 0.05
+
+
+def test_growth_rate():
+    # Einstein-de Sitter: f = 1; flat LCDM: the logarithmic derivative of G
+    np.testing.assert_allclose(quasars.growth_rate(2.0, omega_m=1.0), 1.0, rtol=1e-10)
+    for z in (0.0, 1.0, 2.5):
+        # f = dln G / dln a = -(1 + z) dln G / dz, by central differences
+        h = 1e-4
+        fd = -(1.0 + z) * (np.log(quasars.growth(z + h)) - np.log(quasars.growth(z - h))) / (2.0 * h)
+        np.testing.assert_allclose(quasars.growth_rate(z), fd, rtol=1e-6)
+    # Linder's approximation Omega_m(z)^0.55 holds to about 0.5%
+    assert abs(quasars.growth_rate(0.0) / cosmology.OMEGA_M ** 0.55 - 1.0) < 0.01
+
+
+def test_lines_of_sight_geometry():
+    n, dx = 16, 10.0
+    obs = np.array([80.0, 80.0, -cosmology.chi_of_z(2.3)])
+    zero = np.zeros((n, n, n))
+    # a quasar straight above the observer (along +z), another off axis
+    pos = np.array([[8 << 32, 8 << 32, 5 << 32], [(3 << 32) + 12345, (11 << 32) - 999, (14 << 32) + 7]],
+                   dtype=np.int64)
+    r_lo, r_hi = 1040.0 / 1215.67, 1200.0 / 1215.67
+    los = quasars.lines_of_sight(pos, zero, zero, zero, dx, obs, r_lo, r_hi, 1.8, 0.2)
+    x0 = pos[0] / 2.0 ** 32 * dx
+    chi = x0[2] - obs[2]
+    np.testing.assert_allclose(los["z_q"][0], cosmology.z_of_chi(np.array([chi]))[0], rtol=1e-13)
+    z_hi = (1 + los["z_q"][0]) * r_hi - 1
+    c_hi = cosmology.chi_of_z(z_hi)
+    np.testing.assert_array_equal(los["origin_fx"][0], np.rint(np.array([80.0 / dx, 80.0 / dx,
+                                                                         (obs[2] + c_hi) / dx]) * 2.0 ** 32))
+    np.testing.assert_array_equal(los["step_fx"][0], [0, 0, -round(0.2 / dx * 2.0 ** 32)])
+    assert los["npix"][0] == min(int((c_hi - cosmology.chi_of_z(max((1 + los["z_q"][0]) * r_lo - 1, 1.8))) / 0.2),
+                                 2048)
+    # every pixel's distance to the observer is chi0 - j dchi
+    for q in range(2):
+        j = np.array([0, 100, int(los["npix"][q]) - 1])
+        p = (los["origin_fx"][q][None, :] + j[:, None] * los["step_fx"][q][None, :]) / 2.0 ** 32 * dx
+        np.testing.assert_allclose(np.sqrt(np.sum((p - obs) ** 2, axis=1)), los["chi0"][q] - 0.2 * j, atol=1e-6)
+    np.testing.assert_array_equal(los["offset"], [0, los["npix"][0]])
+
+
+def test_lines_of_sight_velocity_shift():
+    # a uniform velocity V along +z: a quasar on the z axis moves to
+    # z_q = z_c + (1 + z_c) V G f E / (1 + z_c) / c
+    n, dx, V = 16, 10.0, 300.0
+    obs = np.array([80.0, 80.0, -cosmology.chi_of_z(2.3)])
+    zero, vz = np.zeros((n, n, n)), np.full((n, n, n), V)
+    pos = np.array([[8 << 32, 8 << 32, 5 << 32]], dtype=np.int64)
+    los = quasars.lines_of_sight(pos, zero, zero, vz, dx, obs, 0.85, 0.99, 1.8, 0.2)
+    zc = los["z_c"][0]
+    want = zc + (1 + zc) * V * quasars.velocity_factor(zc) / quasars.C_KMS
+    np.testing.assert_allclose(los["z_q"][0], want, rtol=1e-14)
+    assert los["z_q"][0] - zc > 1e-4
