@@ -41,9 +41,11 @@ typedef enum {
 
 enum { LYA_F32 = 0, LYA_BF16 = 1 };
 
-/* Field components (eq:deltaL and eq:eta): delta, then eta_pq = f k_p k_q / k^2 delta. */
+/* Field components (eq:deltaL, eq:eta, eq:velocity): delta, then
+ * eta_pq = f k_p k_q / k^2 delta, then the velocity v_j = i f (aH)_0 k_j / k^2 delta
+ * in km/s with (aH)_0 = 100 km/s per Mpc/h (the box's redshift is 0). */
 enum { LYA_C_NONE = -1, LYA_C_DELTA = 0, LYA_C_XX = 1, LYA_C_YY = 2, LYA_C_ZZ = 3,
-       LYA_C_XY = 4, LYA_C_XZ = 5, LYA_C_YZ = 6 };
+       LYA_C_XY = 4, LYA_C_XZ = 5, LYA_C_YZ = 6, LYA_C_VX = 7, LYA_C_VY = 8, LYA_C_VZ = 9 };
 
 /* Workspace kinds for lya_workspace_size. */
 enum { LYA_OP_BOX = 0, LYA_OP_SKEWERS = 1, LYA_OP_QUASARS = 2 };
@@ -125,7 +127,8 @@ size_t lya_plane_pitch(const lya_box* box);
 /* Bytes of device workspace a call needs.  op = LYA_OP_BOX for lya_make_box,
  * lya_make_eta and lya_make_box_pair (for LYA_BF16 storage this includes an
  * n^3 complex64 staging box), LYA_OP_SKEWERS for lya_draw_skewers and
- * lya_apply_fgpa, LYA_OP_QUASARS for lya_box_moments and lya_draw_quasars.
+ * lya_apply_fgpa, LYA_OP_QUASARS for lya_box_moments, lya_draw_quasars and
+ * lya_quasar_skewers.
  * Returns 0 for invalid arguments. */
 size_t lya_workspace_size(int op, const lya_box* box);
 
@@ -140,7 +143,8 @@ int lya_make_box(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, 
                  void* field, void* work, size_t work_bytes, void* stream);
 
 /* Any pair of components of the same modes (eq:eta: eta_pq = f k_p k_q/k^2
- * delta_hat; cross terms vanish on the Nyquist plane of p or q): writes
+ * delta_hat; cross terms vanish on the Nyquist plane of p or q; eq:velocity:
+ * v_j = i f (aH)_0 k_j/k^2 delta_hat, zero on the Nyquist plane of j): writes
  * {comp_a, comp_b} (comp_b may be LYA_C_NONE).  Same layout and workspace as
  * lya_make_box. */
 int lya_make_eta(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int comp_a, int comp_b,
@@ -490,6 +494,38 @@ typedef struct {
  * LYA_OP_QUASARS, box). */
 int lya_draw_quasars(const lya_box* box, const lya_qso_spec* spec, const lya_cosmo* cosmo, int64_t* pos_fx,
                      int64_t cap, int64_t* count, void* work, size_t work_bytes, void* stream);
+
+typedef struct {
+  int64_t n_q;            /* quasars */
+  const int64_t* pos_fx;  /* device [n_q][3]: positions, cell units times 2^32 (lya_draw_quasars) */
+  const void* vel_xy;     /* LYA_F32 box {v_x, v_y}: lya_make_eta(LYA_C_VX, LYA_C_VY) with f = 1, or NULL */
+  const void* vel_z;      /* LYA_F32 box {v_z, 0}: lya_make_eta(LYA_C_VZ, LYA_C_NONE) with f = 1, or NULL */
+  double observer[3];     /* Mpc/h, as in lya_qso_spec */
+  double lam_lo, lam_hi;  /* rest-frame forest window over the Lya wavelength (e.g. 1040/1215.67, 1200/1215.67) */
+  double z_min;           /* lowest pixel redshift */
+  double dchi;            /* pixel length, Mpc/h (the paper: 0.2) */
+} lya_qso_los_spec;
+
+/* The catalogue and its skewer table (section "Quasar generation": the
+ * quasar velocity of eq:velocity; section "Gaussian fields along lines of
+ * sight": pixels along the line to the observer).  Quasar q at
+ * x = pos_fx[q] 2^-32 dx has chi = |x - O| and z_c = z(chi) (Newton on the
+ * Simpson chi(z) below, FP64); with velocity
+ * boxes, v_par = v(x) . (x - O)/chi (periodic trilinear, FP64 weights) times
+ * G(z_c) f(z_c) E(z_c)/(1 + z_c) (the boxes are at z = 0 with f = 1; G and
+ * f = dln G/dln a of flat LCDM), and z_q = z_c + (1 + z_c) v_par / c (without
+ * velocity boxes z_q = z_c).  Its row of the skewer table (lya_skewers, with
+ * dchi): the forest from z_hi = (1 + z_q) lam_hi - 1 towards the observer
+ * down to z_lo = max((1 + z_q) lam_lo - 1, z_min); chi0 = chi(z_hi) (FP64
+ * Simpson, 1024 intervals); npix = floor((chi(z_hi) - chi(z_lo))/dchi), at
+ * most 2048, 0 when z_hi <= z_lo; origin_fx = (O + u chi0)/dx and step_fx =
+ * -u dchi/dx in cell units times 2^32, rounded to nearest, u = (x - O)/chi;
+ * offset = exclusive prefix sum of npix, *total (device) = the sum.
+ * Outputs: device arrays of n_q rows (origin_fx, step_fx: [n_q][3]).
+ * work >= lya_workspace_size(LYA_OP_QUASARS, box). */
+int lya_quasar_skewers(const lya_box* box, const lya_qso_los_spec* spec, const lya_cosmo* cosmo, double* z_q,
+                       int64_t* origin_fx, int64_t* step_fx, int32_t* npix, int64_t* offset, double* chi0,
+                       int64_t* total, void* work, size_t work_bytes, void* stream);
 
 /* Launch-shape tuning (the batching and autotuning row of the hot path).
  * Per box size n the library keeps:

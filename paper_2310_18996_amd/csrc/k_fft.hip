@@ -96,14 +96,27 @@ __device__ __forceinline__ float comp_mult(int comp, int nx, int ny, int nz, int
   return f * static_cast<float>(a * b) * __builtin_amdgcn_rcpf(static_cast<float>(n2));
 }
 
-// Mode (ix, iy, iz) of the packed spectrum (a second amplitude table only in
-// the generic synthesiser).
-template <int N, bool TWO_TABLES>
+// Complex multiplier (re, im) of a component: delta and eta_pq real (above);
+// the velocity v_j = i f (aH)_0 k_j / k^2 delta_hat (eq:velocity, (aH)_0 =
+// 100 km/s per Mpc/h) is i vscale n_j / |n|^2 with vscale = f 100 L / (2 pi).
+// It is odd in k, so it vanishes on the Nyquist plane of j, where a mode is
+// its own partner.
+__device__ __forceinline__ float2 comp_mult2(int comp, int nx, int ny, int nz, int n2, int n, float f,
+                                             float vscale) {
+  if (comp < 7) return make_float2(comp_mult(comp, nx, ny, nz, n2, n, f), 0.0f);
+  const int a = comp == 7 ? nx : (comp == 8 ? ny : nz);
+  if (n2 == 0 || a == -(n / 2)) return make_float2(0.0f, 0.0f);
+  return make_float2(0.0f, vscale * static_cast<float>(a) * __builtin_amdgcn_rcpf(static_cast<float>(n2)));
+}
+
+// Mode (ix, iy, iz) of the packed spectrum (a second amplitude table and the
+// complex multipliers only in the generic synthesiser).
+template <int N, bool GENERIC>
 __device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, int iz) {
   const int nx = sfreq(ix, N), ny = sfreq(iy, N), nz = sfreq(iz, N);
   const int n2 = nx * nx + ny * ny + nz * nz;
   float s = g.table[n2];
-  float sb = (TWO_TABLES && g.table_b) ? g.table_b[n2] : s;
+  float sb = (GENERIC && g.table_b) ? g.table_b[n2] : s;
   if (g.only_n2 >= 0 && n2 != g.only_n2) s = sb = 0.0f;
   if (s == 0.0f && sb == 0.0f) return make_float2(0.0f, 0.0f);
   const uint64_t lin = (static_cast<uint64_t>(ix) * N + iy) * N + iz;
@@ -121,12 +134,15 @@ __device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, i
     w.x *= m;
     w.y *= m;
   }
+  if (GENERIC) {
+    // X = W (s c_a + i sb c_b)
+    const float2 ca = comp_mult2(g.comp_a, nx, ny, nz, n2, N, g.f, g.vscale);
+    const float2 cb = comp_mult2(g.comp_b, nx, ny, nz, n2, N, g.f, g.vscale);
+    const float pr = s * ca.x - sb * cb.y, pi = s * ca.y + sb * cb.x;
+    return make_float2(w.x * pr - w.y * pi, w.y * pr + w.x * pi);
+  }
   const float ma = comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
   const float mb = comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
-  if (TWO_TABLES && g.table_b) {
-    const float pa = s * ma, pb = sb * mb;
-    return make_float2(w.x * pa - w.y * pb, w.y * pa + w.x * pb);
-  }
   return make_float2(s * (w.x * ma - w.y * mb), s * (w.y * ma + w.x * mb));
 }
 
@@ -329,8 +345,19 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
           wv.x *= r;
           wv.y *= r;
         }
-        ma = s * comp_mult(g.comp_a, nx, ny, nz, n2, N, g.f);
-        mb = sb * comp_mult(g.comp_b, nx, ny, nz, n2, N, g.f);
+        // X = W P, X' = conj(W) P' with P = s c_a + i sb c_b at the mode and P'
+        // the same at its partner (-nx, -ny, -nz): P' = P for the even
+        // components, P' = -P for the velocities
+        const int pny = sfreq((N - iy) & (N - 1), N), pnz = sfreq((N - iz) & (N - 1), N);
+        const float2 ca = comp_mult2(g.comp_a, nx, ny, nz, n2, N, g.f, g.vscale);
+        const float2 cb = comp_mult2(g.comp_b, nx, ny, nz, n2, N, g.f, g.vscale);
+        const float2 da = comp_mult2(g.comp_a, -nx, pny, pnz, n2, N, g.f, g.vscale);
+        const float2 db = comp_mult2(g.comp_b, -nx, pny, pnz, n2, N, g.f, g.vscale);
+        const float pr = s * ca.x - sb * cb.y, pi = s * ca.y + sb * cb.x;
+        const float qr = s * da.x - sb * db.y, qi = s * da.y + sb * db.x;
+        lds[lidx(iz, po)] = make_float2(wv.x * pr - wv.y * pi, wv.y * pr + wv.x * pi);
+        lds[lidx((N - iz) & (N - 1), H + po)] = make_float2(wv.x * qr + wv.y * qi, wv.x * qi - wv.y * qr);
+        continue;
       } else {
         ma = s;  // n2 > 0 here (ix > 0)
         mb = GM == GEN_DELTA_ETAZ ? s * g.f * static_cast<float>(nz * nz) * __builtin_amdgcn_rcpf(static_cast<float>(n2))

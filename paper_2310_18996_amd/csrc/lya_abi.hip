@@ -60,7 +60,7 @@ SkCarve carve_sk() {
 }
 
 struct QsoCarve {
-  size_t ztab, tab, part, total;
+  size_t ztab, tab, vtab, part, total;
 };
 
 QsoCarve carve_qso() {
@@ -68,6 +68,7 @@ QsoCarve carve_qso() {
   size_t o = 0;
   c.ztab = o; o += align256(sizeof(float) * lya::kZTabN);
   c.tab = o;  o += align256(sizeof(float4) * lya::kZTabN);
+  c.vtab = o; o += align256(sizeof(float) * lya::kZTabN);
   c.part = o; o += align256(sizeof(double) * 4 * lya::kQsoMomBlocks);
   c.total = o;
   return c;
@@ -160,7 +161,7 @@ int make_pair(const lya_box* box, const lya_pk* pk, const lya_pk* pk_b, uint64_t
   if (pk_b && (rc = check_pk(pk_b))) return rc;
   if (!field) return fail(LYA_EINVAL, "field is NULL%s");
   if (!work) return fail(LYA_EINVAL, "work is NULL%s");
-  if (ca < LYA_C_DELTA || ca > LYA_C_YZ || cb < LYA_C_NONE || cb > LYA_C_YZ)
+  if (ca < LYA_C_DELTA || ca > LYA_C_VZ || cb < LYA_C_NONE || cb > LYA_C_VZ)
     return fail(LYA_EINVAL, "unknown field component%s");
   const BoxCarve c = carve_box(box);
   if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the box%s");
@@ -178,7 +179,9 @@ int make_pair(const lya_box* box, const lya_pk* pk, const lya_pk* pk_b, uint64_t
     if (e != hipSuccess) return hip_fail(e, "second power-spectrum table");
     table_b = twb.table;
   }
-  lya::GenParams g{tw.table, table_b, seed, static_cast<float>(f), ca, cb, pk->fixed_amp ? 1 : 0, pk->only_n2};
+  const double vscale = f * 100.0 * box->n * box->dx / (2.0 * M_PI);
+  lya::GenParams g{tw.table, table_b, seed, static_cast<float>(f), ca, cb, pk->fixed_amp ? 1 : 0, pk->only_n2,
+                   static_cast<float>(vscale)};
   float2* f32 = box->storage == LYA_F32 ? static_cast<float2*>(field) : reinterpret_cast<float2*>(w + c.staging);
   uint32_t* b16 = box->storage == LYA_BF16 ? static_cast<uint32_t*>(field) : nullptr;
   e = lya::launch_box_fft(box->n, g, tw.tw, f32, b16, st);
@@ -743,6 +746,57 @@ int lya_draw_quasars(const lya_box* box, const lya_qso_spec* spec, const lya_cos
   a.count = reinterpret_cast<unsigned long long*>(count);
   e = lya::launch_qso_draw(cf, a, ztab, reinterpret_cast<float4*>(w + c.tab), st);
   if (e != hipSuccess) return hip_fail(e, "quasar draw");
+  return LYA_OK;
+}
+
+int lya_quasar_skewers(const lya_box* box, const lya_qso_los_spec* spec, const lya_cosmo* cosmo, double* z_q,
+                       int64_t* origin_fx, int64_t* step_fx, int32_t* npix, int64_t* offset, double* chi0,
+                       int64_t* total, void* work, size_t work_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_box(box);
+  if (rc) return rc;
+  if (!spec) return fail(LYA_EINVAL, "spec is NULL%s");
+  if (!cosmo || !(cosmo->omega_m > 0.0 && cosmo->omega_m <= 1.0)) return fail(LYA_EINVAL, "invalid cosmo%s");
+  if (spec->n_q < 0 || spec->n_q > (int64_t(1) << 36)) return fail(LYA_EINVAL, "n_q out of range%s");
+  if (spec->n_q > 0 && (!spec->pos_fx || !z_q || !origin_fx || !step_fx || !npix || !offset || !chi0))
+    return fail(LYA_EINVAL, "catalogue arrays are NULL%s");
+  if (!total || !work) return fail(LYA_EINVAL, "total/work is NULL%s");
+  if ((spec->vel_xy == nullptr) != (spec->vel_z == nullptr))
+    return fail(LYA_EINVAL, "give both velocity boxes or neither%s");
+  if (spec->vel_xy && box->storage != LYA_F32) return fail(LYA_EUNSUPPORTED, "velocity boxes need LYA_F32%s");
+  if (!(spec->lam_lo > 0.0 && spec->lam_lo < spec->lam_hi) || !(spec->dchi > 0.0) || !(spec->z_min >= 0.0))
+    return fail(LYA_EINVAL, "need 0 < lam_lo < lam_hi, dchi > 0, z_min >= 0%s");
+  for (int ax = 0; ax < 3; ++ax)
+    if (!(fabs(spec->observer[ax]) < 1e6)) return fail(LYA_EINVAL, "observer out of range%s");
+  const QsoCarve c = carve_qso();
+  if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small%s");
+  char* w = static_cast<char*>(work);
+  lya::QsoLosArgs a{};
+  a.n_q = spec->n_q;
+  a.pos = spec->pos_fx;
+  a.vxy = static_cast<const float2*>(spec->vel_xy);
+  a.vz = static_cast<const float2*>(spec->vel_z);
+  a.n = box->n;
+  a.pitch = lya::plane_pitch(box->n);
+  a.dx = box->dx;
+  for (int ax = 0; ax < 3; ++ax) a.o[ax] = spec->observer[ax];
+  a.om = cosmo->omega_m;
+  a.r_lo = spec->lam_lo;
+  a.r_hi = spec->lam_hi;
+  a.z_min = spec->z_min;
+  a.dchi = spec->dchi;
+  a.ztab = reinterpret_cast<const float*>(w + c.ztab);
+  a.vtab = reinterpret_cast<const float*>(w + c.vtab);
+  a.z_q = z_q;
+  a.origin = origin_fx;
+  a.step = step_fx;
+  a.npix = npix;
+  a.offset = offset;
+  a.chi0 = chi0;
+  a.total = total;
+  hipError_t e = lya::launch_qso_los(a, reinterpret_cast<float*>(w + c.ztab), reinterpret_cast<float*>(w + c.vtab),
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "quasar lines of sight");
   return LYA_OK;
 }
 

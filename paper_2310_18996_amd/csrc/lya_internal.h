@@ -52,9 +52,10 @@ struct GenParams {
   const float* table_b;  // non-null: component b takes its own amplitudes (two spectra, one set of modes)
   uint64_t seed;
   float f;
-  int comp_a, comp_b;  // 0 delta, 1 xx, 2 yy, 3 zz, 4 xy, 5 xz, 6 yz; -1 none
+  int comp_a, comp_b;  // 0 delta, 1 xx, 2 yy, 3 zz, 4 xy, 5 xz, 6 yz, 7-9 v_x, v_y, v_z; -1 none
   int fixed_amp;
   int only_n2;
+  float vscale;        // velocities: f 100 L / (2 pi), km/s
 };
 
 // Optional event timing around each launch (see lya_timing_enable).
@@ -258,6 +259,28 @@ struct QsoDrawArgs {
   unsigned long long* count;
 };
 hipError_t launch_qso_draw(const QsoCoef& c, const QsoDrawArgs& a, const float* ztab, float4* tab, hipStream_t st);
+
+struct QsoLosArgs {
+  int64_t n_q;
+  const int64_t* pos;     // [n_q][3] fixed point
+  const float2* vxy;      // {v_x, v_y} box or null (no velocities)
+  const float2* vz;       // {v_z, .} box
+  int n;
+  size_t pitch;
+  double dx, o[3], om;
+  double r_lo, r_hi, z_min, dchi;
+  const float* ztab;      // z at chi = i kZTabH
+  const float* vtab;      // G f E / (1 + z) at the same nodes
+  double* z_q;
+  int64_t* origin;
+  int64_t* step;
+  int32_t* npix;
+  int64_t* offset;
+  double* chi0;
+  int64_t* total;
+};
+// Fills ztab_w and vtab_w (kZTabN floats each), then the catalogue.
+hipError_t launch_qso_los(const QsoLosArgs& a, float* ztab_w, float* vtab_w, hipStream_t st);
 
 // Tuning (lya_tune.hip) and the emulator used by it (lya_mlp.hip).
 size_t emulator_eval_bytes();

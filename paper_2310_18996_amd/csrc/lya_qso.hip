@@ -7,7 +7,11 @@
 //     p = nbar(z) dx^3 sum_i c_i(z) exp(a_i(z) delta_i - a_i(z)^2 var_i / 2),
 //     a_i(z) = b_q(z) (1 + z_i) / (b_q(z_i) (1 + z)) = ((1 + z)/(1 + z_i))^0.7
 //     for b_q proportional to (1 + z)^1.7, and a selected voxel gets a
-//     uniform position inside it.
+//     uniform position inside it;
+//   * the catalogue: each quasar's redshift with its line-of-sight velocity
+//     (eq:velocity) and its line of sight as a skewer-table row.
+#include <algorithm>
+
 #include "lya_internal.h"
 
 namespace lya {
@@ -338,6 +342,158 @@ hipError_t launch_qso_draw(const QsoCoef& c, const QsoDrawArgs& a, const float* 
     LYA_TIMED("qso_draw", st, hipLaunchKernelGGL(k_qso_draw<1>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
                                                  st, a));
   }
+  return hipGetLastError();
+}
+
+// ---- catalogue: redshift-space quasar redshifts and their lines of sight ----
+// Flat LCDM in FP64.  I(a) = int_0^a da' / (a' E(a'))^3 by composite Simpson
+// in t = sqrt(a') (a smooth integrand near 0), 512 intervals.
+__device__ double growth_integral(double a, double om) {
+  constexpr int kN = 512;
+  const double tmax = sqrt(a), h = tmax / kN;
+  double acc = 0.0;
+  for (int i = 1; i <= kN; ++i) {
+    const double t = h * i, ap = t * t;
+    const double ae2 = om / ap + (1.0 - om) * ap * ap;  // (a E)^2
+    acc += (i == kN ? 1.0 : (i & 1 ? 4.0 : 2.0)) * 2.0 * t / (ae2 * sqrt(ae2));
+  }
+  return acc * h / 3.0;
+}
+
+// chi(z) = c/H0 int_0^z dz' / E(z'), composite Simpson with 1024 intervals.
+__device__ double chi_of_z_fine(double z, double om) {
+  constexpr int kN = 1024;
+  const double h = z / kN;
+  double acc = 0.0;
+  for (int i = 0; i <= kN; ++i) {
+    const double x = 1.0 + h * i;
+    acc += (i == 0 || i == kN ? 1.0 : (i & 1 ? 4.0 : 2.0)) / sqrt(om * x * x * x + (1.0 - om));
+  }
+  return kCOverH0 * acc * h / 3.0;
+}
+
+// Velocity factor G(z) f(z) E(z) / (1 + z) at chi = i kZTabH (z from ztab):
+// the velocity boxes (z = 0, f = 1) to redshift z.  f = dln D / dln a =
+// -3 Om / (2 a^3 E^2) + a / (I (a E)^3) for D = E I.
+__global__ void __launch_bounds__(256) k_qso_vtab(const float* __restrict__ ztab, double om, float* __restrict__ vtab) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= kZTabN) return;
+  const double z = ztab[i];
+  const double a = 1.0 / (1.0 + z);
+  const double e2 = om / (a * a * a) + 1.0 - om;
+  const double I = growth_integral(a, om), I1 = growth_integral(1.0, om);
+  const double g = sqrt(e2) * I / I1;
+  const double ae2 = a * a * e2;
+  const double f = -1.5 * om / (a * a * a * e2) + a / (I * ae2 * sqrt(ae2));
+  vtab[i] = static_cast<float>(g * f * sqrt(e2) / (1.0 + z));
+}
+
+__device__ __forceinline__ double lerp_tab(const float* tab, double chi) {
+  const double t = chi / kZTabH;
+  const int i0 = min(static_cast<int>(t), kZTabN - 2);
+  const double fr = t - i0;
+  return tab[i0] + fr * (static_cast<double>(tab[i0 + 1]) - tab[i0]);
+}
+
+// One thread per quasar.
+__global__ void __launch_bounds__(256) k_qso_los(QsoLosArgs a) {
+  constexpr double kTwo32 = 4294967296.0;
+  constexpr double kCKms = 299792.458;
+  for (int64_t q = blockIdx.x * 256ll + threadIdx.x; q < a.n_q; q += static_cast<int64_t>(gridDim.x) * 256) {
+    const int64_t p[3] = {a.pos[3 * q], a.pos[3 * q + 1], a.pos[3 * q + 2]};
+    double d[3], chi2 = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+      d[ax] = static_cast<double>(p[ax]) / kTwo32 * a.dx - a.o[ax];
+      chi2 += d[ax] * d[ax];
+    }
+    const double chi = sqrt(chi2);
+    double u[3] = {d[0] / chi, d[1] / chi, d[2] / chi};
+    // z(chi): the table's value refined by Newton steps on chi(z) (FP64)
+    double zc = lerp_tab(a.ztab, chi);
+    for (int it = 0; it < 3; ++it) {
+      const double x = 1.0 + zc;
+      zc -= (chi_of_z_fine(zc, a.om) - chi) * sqrt(a.om * x * x * x + 1.0 - a.om) / kCOverH0;
+    }
+    double vpar = 0.0;
+    if (a.vxy) {
+      // periodic trilinear of {v_x, v_y} and v_z at the quasar
+      int c0[3], c1[3];
+      double w1[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        const int64_t cell = p[ax] >> 32;
+        c0[ax] = static_cast<int>(((cell % a.n) + a.n) % a.n);
+        c1[ax] = c0[ax] + 1 == a.n ? 0 : c0[ax] + 1;
+        w1[ax] = static_cast<double>(p[ax] & 0xffffffffll) / kTwo32;
+      }
+      double v[3] = {0.0, 0.0, 0.0};
+      for (int cx = 0; cx < 2; ++cx)
+        for (int cy = 0; cy < 2; ++cy)
+          for (int cz = 0; cz < 2; ++cz) {
+            const double w = (cx ? w1[0] : 1.0 - w1[0]) * (cy ? w1[1] : 1.0 - w1[1]) * (cz ? w1[2] : 1.0 - w1[2]);
+            const size_t e = static_cast<size_t>(cx ? c1[0] : c0[0]) * a.pitch +
+                             static_cast<size_t>(cy ? c1[1] : c0[1]) * a.n + (cz ? c1[2] : c0[2]);
+            const float2 xy = a.vxy[e];
+            v[0] += w * xy.x;
+            v[1] += w * xy.y;
+            v[2] += w * a.vz[e].x;
+          }
+      vpar = (v[0] * u[0] + v[1] * u[1] + v[2] * u[2]) * lerp_tab(a.vtab, chi);
+    }
+    const double zq = zc + (1.0 + zc) * vpar / kCKms;
+    const double z_hi = (1.0 + zq) * a.r_hi - 1.0;
+    const double z_lo = fmax((1.0 + zq) * a.r_lo - 1.0, a.z_min);
+    const double c_hi = chi_of_z_fine(z_hi, a.om);
+    int np = 0;
+    if (z_hi > z_lo) np = static_cast<int>(fmin(floor((c_hi - chi_of_z_fine(z_lo, a.om)) / a.dchi), 2048.0));
+    a.z_q[q] = zq;
+    a.chi0[q] = c_hi;
+    a.npix[q] = np;
+    for (int ax = 0; ax < 3; ++ax) {
+      a.origin[3 * q + ax] = llrint((a.o[ax] + u[ax] * c_hi) / a.dx * kTwo32);
+      a.step[3 * q + ax] = llrint(-u[ax] * a.dchi / a.dx * kTwo32);
+    }
+  }
+}
+
+// Exclusive prefix sum of npix into offset, and the total (one block).
+__global__ void __launch_bounds__(1024) k_qso_offsets(const int32_t* __restrict__ npix, int64_t n_q,
+                                                      int64_t* __restrict__ offset, int64_t* __restrict__ total) {
+  __shared__ int wsum[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long long run = 0;
+  for (int64_t base = 0; base < n_q; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int v = i < n_q ? npix[i] : 0;
+    int x = v;  // inclusive scan in the wave (a chunk sums to at most 2^21)
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int before = 0, chunk = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wv) before += wsum[k];
+      chunk += wsum[k];
+    }
+    if (i < n_q) offset[i] = run + before + x - v;
+    run += chunk;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = run;
+}
+
+hipError_t launch_qso_los(const QsoLosArgs& a, float* ztab_w, float* vtab_w, hipStream_t st) {
+  hipError_t e = launch_zchi_table(a.om, ztab_w, st);
+  if (e != hipSuccess) return e;
+  LYA_TIMED("qso_vtab", st, hipLaunchKernelGGL(k_qso_vtab, dim3((kZTabN + 255) / 256), dim3(256), 0, st, ztab_w,
+                                               a.om, vtab_w));
+  if (a.n_q > 0) {
+    const int64_t blocks = std::min<int64_t>((a.n_q + 255) / 256, static_cast<int64_t>(device_cus()) * 16);
+    LYA_TIMED("qso_los", st, hipLaunchKernelGGL(k_qso_los, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a));
+  }
+  LYA_TIMED("qso_offsets", st,
+            hipLaunchKernelGGL(k_qso_offsets, dim3(1), dim3(1024), 0, st, a.npix, a.n_q, a.offset, a.total));
   return hipGetLastError();
 }
 

@@ -15,11 +15,13 @@ LYA_OK, LYA_EINVAL, LYA_EWORKSPACE, LYA_EUNSUPPORTED, LYA_EHIP = 0, -1, -2, -3, 
 LYA_F32, LYA_BF16 = 0, 1
 LYA_OP_BOX, LYA_OP_SKEWERS, LYA_OP_QUASARS = 0, 1, 2
 LYA_C_NONE, LYA_C_DELTA, LYA_C_XX, LYA_C_YY, LYA_C_ZZ, LYA_C_XY, LYA_C_XZ, LYA_C_YZ = -1, 0, 1, 2, 3, 4, 5, 6
-COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6}
+LYA_C_VX, LYA_C_VY, LYA_C_VZ = 7, 8, 9
+COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6, "vx": 7, "vy": 8,
+              "vz": 9}
 
 EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta",
            "lya_make_box_pair", "lya_lognormal_workspace_size", "lya_lognormal_pk", "lya_box_moments",
-           "lya_draw_quasars",
+           "lya_draw_quasars", "lya_quasar_skewers",
            "lya_draw_skewers", "lya_draw_skewers_gauss", "lya_draw_skewers_wide", "lya_apply_fgpa",
            "lya_apply_fgpa_ds", "lya_tune_ps_workspace_size", "lya_tune_ps", "lya_tune_ps_last_error",
            "lya_p1d_workspace_size", "lya_p1d",
@@ -365,6 +367,12 @@ def qso_spec(boxes, z_box, var_ptrs, observer, nbar_z, nbar, seed, xi5=0.0):
     return sp
 
 
+class QsoLosSpec(ctypes.Structure):
+    _fields_ = [("n_q", ctypes.c_int64), ("pos_fx", ctypes.c_void_p), ("vel_xy", ctypes.c_void_p),
+                ("vel_z", ctypes.c_void_p), ("observer", ctypes.c_double * 3), ("lam_lo", ctypes.c_double),
+                ("lam_hi", ctypes.c_double), ("z_min", ctypes.c_double), ("dchi", ctypes.c_double)]
+
+
 def _bind_more(lib):
     P, VP = ctypes.POINTER, ctypes.c_void_p
     lib.lya_p1d_workspace_size.restype = ctypes.c_size_t
@@ -435,6 +443,9 @@ def _bind_more(lib):
                                      ctypes.c_int32, ctypes.c_int32, VP, VP, VP, VP, ctypes.c_size_t, VP]
     lib.lya_box_moments.restype = ctypes.c_int
     lib.lya_box_moments.argtypes = [P(Box), VP, VP, VP, ctypes.c_size_t, VP]
+    lib.lya_quasar_skewers.restype = ctypes.c_int
+    lib.lya_quasar_skewers.argtypes = [P(Box), P(QsoLosSpec), P(Cosmo), VP, VP, VP, VP, VP, VP, VP, VP,
+                                       ctypes.c_size_t, VP]
     lib.lya_draw_quasars.restype = ctypes.c_int
     lib.lya_draw_quasars.argtypes = [P(Box), P(QsoSpec), P(Cosmo), VP, ctypes.c_int64, VP, VP, ctypes.c_size_t, VP]
 
@@ -691,3 +702,28 @@ def draw_quasars(box, spec, cosmo, pos_fx, count, work, stream=None):
     cap = 0 if pos_fx is None else int(pos_fx.shape[0])
     _check(_lib2().lya_draw_quasars(ctypes.byref(box), ctypes.byref(spec), ctypes.byref(cosmo), _ptr(pos_fx), cap,
                                     _ptr(count), _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def quasar_skewers(box, pos_fx, vel_xy, vel_z, observer, lam_lo, lam_hi, z_min, dchi, cosmo, work, stream=None):
+    """lya_quasar_skewers: returns dict of device tensors z_q, origin_fx,
+    step_fx, npix, offset, chi0 and the total pixel count (synchronises)."""
+    import torch
+    nq = 0 if pos_fx is None else int(pos_fx.shape[0])
+    dev = pos_fx.device if pos_fx is not None else torch.device("cuda")
+    out = dict(z_q=torch.empty(nq, dtype=torch.float64, device=dev),
+               origin_fx=torch.empty((nq, 3), dtype=torch.int64, device=dev),
+               step_fx=torch.empty((nq, 3), dtype=torch.int64, device=dev),
+               npix=torch.empty(nq, dtype=torch.int32, device=dev),
+               offset=torch.empty(nq, dtype=torch.int64, device=dev),
+               chi0=torch.empty(nq, dtype=torch.float64, device=dev))
+    total = torch.zeros(1, dtype=torch.int64, device=dev)
+    sp = QsoLosSpec(nq, None if pos_fx is None else pos_fx.data_ptr(),
+                    None if vel_xy is None else vel_xy.data_ptr(), None if vel_z is None else vel_z.data_ptr(),
+                    (ctypes.c_double * 3)(*[float(v) for v in observer]), float(lam_lo), float(lam_hi),
+                    float(z_min), float(dchi))
+    _check(_lib2().lya_quasar_skewers(ctypes.byref(box), ctypes.byref(sp), ctypes.byref(cosmo),
+                                      *[_ptr(out[k]) for k in ("z_q", "origin_fx", "step_fx", "npix", "offset",
+                                                               "chi0")],
+                                      _ptr(total), _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+    out["total"] = int(total.item())
+    return out

@@ -337,3 +337,93 @@ def test_full_size_draw_on_a_single_shell_box(L):
         assert abs(c / est - 1.0) < 0.05
     del fld, pos
     torch.cuda.empty_cache()
+
+
+def test_velocity_boxes(L):
+    # eq:velocity through lya_make_eta: {v_x, v_y} and {v_z, 0} at z = 0, f = 1
+    n, dx, seed = 64, 5.0, 23
+    box = L.box_struct(n, dx)
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fxy, fz = (torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") for _ in range(2))
+    pk = L.pk_struct()
+    L.make_eta(box, pk, seed, 1.0, "vx", "vy", fxy, work)
+    L.make_eta(box, pk, seed, 1.0, "vz", "none", fz, work)
+    torch.cuda.synchronize()
+    gxy, gz = L.box_view(fxy, n).cpu().numpy(), L.box_view(fz, n).cpu().numpy()
+    tab = power.amplitude_table(power.PowerSpectrum(), n, dx)
+    rxy = field.make_box(n, seed, tab, ("vx", "vy"), f=1.0, box_len=n * dx)
+    rz = field.make_box(n, seed, tab, ("vz",), f=1.0, box_len=n * dx)
+    e = (rel_rms(gxy[..., 0], rxy.real), rel_rms(gxy[..., 1], rxy.imag), rel_rms(gz[..., 0], rz.real))
+    print("velocity boxes rel rms %.2e %.2e %.2e, v_z rms %.1f km/s" % (e + (float(np.std(rz.real)),)))
+    assert max(e) < 1e-5
+    assert not np.any(gz[..., 1])
+
+
+def _catalogue_inputs(n, dx, seed):
+    # quasar positions from the oracle's draw on a seeded Gaussian field
+    rng = np.random.default_rng(seed)
+    dq = rng.normal(scale=0.5, size=(n, n, n))
+    obs = np.array([n * dx / 2, n * dx / 2, -cosmology.chi_of_z(2.0)])
+    nz, nb = _nbar_table()
+    idx, fx, _, _ = quasars.draw([dq], dx, obs, [2.5], [float(np.var(dq))], nz, 0.05 * nb, seed)
+    return fx, obs
+
+
+def test_quasar_lines_of_sight(L):
+    n, dx, seed = 64, 10.0, 29
+    r_lo, r_hi = 1040.0 / 1215.67, 1200.0 / 1215.67
+    fx, obs = _catalogue_inputs(n, dx, seed)
+    assert 500 < len(fx) < 4000
+    box = L.box_struct(n, dx)
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fxy, fz = (torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") for _ in range(2))
+    L.make_eta(box, L.pk_struct(), seed, 1.0, "vx", "vy", fxy, work)
+    L.make_eta(box, L.pk_struct(), seed, 1.0, "vz", "none", fz, work)
+    tab = power.amplitude_table(power.PowerSpectrum(), n, dx)
+    rxy = field.make_box(n, seed, tab, ("vx", "vy"), f=1.0, box_len=n * dx)
+    rz = field.make_box(n, seed, tab, ("vz",), f=1.0, box_len=n * dx)
+    qw = torch.empty(L.workspace_size(L.LYA_OP_QUASARS, box), dtype=torch.uint8, device="cuda")
+    pos = torch.from_numpy(fx).cuda()
+    cosmo = L.Cosmo(cosmology.OMEGA_M)
+    for vel in (False, True):
+        got = L.quasar_skewers(box, pos, fxy if vel else None, fz if vel else None, obs, r_lo, r_hi, 1.8, 0.2,
+                               cosmo, qw)
+        got = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in got.items()}
+        zero = np.zeros((n, n, n))
+        ref = quasars.lines_of_sight(fx, rxy.real if vel else zero, rxy.imag if vel else zero,
+                                     rz.real if vel else zero, dx, obs, r_lo, r_hi, 1.8, 0.2)
+        dz = np.abs(got["z_q"] - ref["z_q"])
+        shift = np.abs(ref["z_q"] - ref["z_c"])
+        print("velocities %s: %d quasars, max |dz_q| %.2e (RSD shift up to %.2e), total pixels %d / %d"
+              % (vel, len(fx), dz.max(), shift.max(), got["total"], ref["total"]))
+        assert dz.max() < (1e-8 if vel else 1e-11)
+        if vel:
+            assert shift.max() > 1e-4
+        np.testing.assert_allclose(got["chi0"], ref["chi0"], rtol=0, atol=1e-4 if vel else 1e-8)
+        # npix is a floor: it may differ by one only where the oracle's length
+        # in pixels lies within 1e-3 of an integer
+        c_lo = cosmology.chi_of_z(np.maximum((1 + ref["z_q"]) * r_lo - 1, 1.8))
+        frac = (ref["chi0"] - c_lo) / 0.2
+        edge = np.abs(frac - np.rint(frac)) < 1e-3
+        diff = got["npix"] != ref["npix"]
+        assert np.all(edge[diff]) and np.all(np.abs(got["npix"] - ref["npix"]) <= 1)
+        if not diff.any():
+            np.testing.assert_array_equal(got["offset"], ref["offset"])
+            assert got["total"] == ref["total"]
+        tol = (1 << 14) if vel else 8
+        assert np.abs(got["origin_fx"] - ref["origin_fx"]).max() <= tol
+        assert np.abs(got["step_fx"] - ref["step_fx"]).max() <= 2
+    # the table feeds the skewer pass as it is
+    fld = fxy
+    L.make_box(box, L.pk_struct(), seed, 1.0, True, fld, work)
+    s = L.skewers_struct(len(fx), torch.from_numpy(got["origin_fx"]).cuda(),
+                         torch.from_numpy(got["step_fx"]).cuda(), torch.from_numpy(got["npix"]).cuda(),
+                         torch.from_numpy(got["offset"]).cuda(), torch.from_numpy(got["chi0"]).cuda(), 0.2)
+    tot = int(got["total"])
+    dens, eta = (torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(2))
+    sw = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    L.draw_skewers(box, fld, s, L.Ps1d(0.0, 1.0, 0.2, 0), seed, cosmo, None, dens, eta, None, None, sw)
+    torch.cuda.synchronize()
+    assert torch.isfinite(dens).all() and torch.isfinite(eta).all()
+    # the skewers' first pixels sit at the forests' red ends, the quasars beyond them
+    assert np.all(got["chi0"] < np.sqrt(np.sum((fx / 2.0 ** 32 * dx - obs) ** 2, axis=1)))
