@@ -19,6 +19,12 @@ the plain loop (every search point evaluated on the GPU) against the
 emulator-driven search (MLP trained on the GPU on labels of one 256^3 mock
 with 20,000 skewers), with wall times, the label and training cost, and the
 relative difference of the statistics both reach.
+
+`quasars` (after the timed steps): the lognormal quasar field on the 2048^3
+box -- P_q of the three boxes, the quasar-density boxes from the step's
+modes, their variances, the three-box draw (with its own roofline line) --
+then the catalogue: velocity boxes, redshift-space quasar redshifts and the
+skewer table, and the skewer pass with FGPA over those lines of sight.
 """
 import argparse
 import json
@@ -332,12 +338,54 @@ def quasar_leg(L, torch, stream, cfg, reps=2):
     ab = 16.0 * cells + 24.0 * min(count, cap)
     achieved = ab / (kern * 1e-3) / 1e9
     m = mom.cpu().numpy()
+
+    # the catalogue: velocity boxes (z = 0, f = 1) in place of the quasar
+    # boxes, redshift-space redshifts and the skewer table; then the matter
+    # box and the skewer pass with FGPA over the catalogue's lines of sight
+    nq = min(count, cap)
+    qpos = pos[:nq].contiguous()
+    del spec
+
+    def velocities():
+        L.make_eta(box, pkm0, seed, 1.0, "vx", "vy", fa, bwork, stream)
+        L.make_eta(box, pkm0, seed, 1.0, "vz", "none", fb, bwork, stream)
+
+    pkm0 = L.pk_struct(**cfg["pk"])
+    vel_ms = timed(velocities, 1)
+    r_lo, r_hi = 1040.0 / mockinputs.LYA_A, 1200.0 / mockinputs.LYA_A
+    L.quasar_skewers(box, qpos, fa, fb, mockinputs.qso_observer(n, dx), r_lo, r_hi, 1.8, cfg["dpix"], cosmo, qw,
+                     stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cat = L.quasar_skewers(box, qpos, fa, fb, mockinputs.qso_observer(n, dx), r_lo, r_hi, 1.8, cfg["dpix"], cosmo,
+                           qw, stream)
+    cat_ms = (time.perf_counter() - t0) * 1e3
+    del fb
+    torch.cuda.empty_cache()
+    L.make_box(box, pkm0, seed, cfg["f"], True, fa, bwork, stream)
+    s = L.skewers_struct(nq, cat["origin_fx"], cat["step_fx"], cat["npix"], cat["offset"], cat["chi0"], cfg["dpix"])
+    tot = cat["total"]
+    dens, eta, flux = (torch.empty(max(tot, 1), dtype=torch.float32, device="cuda") for _ in range(3))
+    edges = torch.from_numpy(L.chi_of_z(cfg["z_edges"], cfg["omega_m"])).cuda()
+    fsum = torch.zeros(edges.numel() - 1, dtype=torch.float64, device="cuda")
+    fcnt = torch.zeros(edges.numel() - 1, dtype=torch.int64, device="cuda")
+    zbins = L.zbins_struct(edges, fsum, fcnt)
+    swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    ps = L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0)
+    sk_ms = timed(lambda: L.draw_skewers(box, fa, s, ps, seed, cosmo, L.fgpa_struct(cfg["fgpa"]), dens, eta, flux,
+                                         zbins, swork, stream))
+    fbar = float(fsum.sum() / max(int(fcnt.sum()), 1))
+    zq = cat["z_q"]
+    catalogue = dict(velocity_boxes_ms=vel_ms, lines_of_sight_ms=cat_ms, quasars=nq, pixels=tot,
+                     z_q_range=[float(zq.min()), float(zq.max())] if nq else None,
+                     skewer_pass_ms=sk_ms, skewer_pixels_per_s=tot / (sk_ms * 1e-3), mean_flux=fbar,
+                     finite=bool(torch.isfinite(flux[:tot]).all()))
     return dict(workload="%d^3 box at %.2f Mpc/h, boxes at z = %s, observer at (L/2, L/2, -chi(%.1f)), "
                          "P_q on %d k nodes (rmax %.0f Mpc/h, %d r nodes)" % (
                              n, dx, ",".join("%.2f" % z for z in zb), mockinputs.QSO_Z_OBS, kk.numel(), rmax, n_r),
                 lognormal_pk_ms_3_boxes=pq_ms, boxes_ms=boxes_ms, box_cells_per_s=2 * cells / (boxes_ms * 1e-3),
                 moments_ms=mom_ms, draw_ms=draw_ms, draw_kernel_ms=kern, voxels_per_s=cells / (kern * 1e-3),
-                quasars=count, xi5=xi5, variances=[float(m[1]), float(m[3]), float(m[5])],
+                quasars=count, xi5=xi5, variances=[float(m[1]), float(m[3]), float(m[5])], catalogue=catalogue,
                 roofline=dict(kernel="qso_draw", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                               frac=achieved / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=ab,
                               mean_launch_ms=kern))
