@@ -134,13 +134,17 @@ __global__ void __launch_bounds__(256) k_box_moments(const float2* __restrict__ 
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t rows = static_cast<int64_t>(n) * n;
   for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-    const float2* q = box + static_cast<size_t>(row / n) * pitch + static_cast<size_t>(row % n) * n;
-    for (int iz = threadIdx.x; iz < n; iz += 256) {
-      const float2 v = q[iz];
-      s[0] += v.x;
-      s[1] += static_cast<double>(v.x) * v.x;
-      s[2] += v.y;
-      s[3] += static_cast<double>(v.y) * v.y;
+    // two cells per 16-byte load (rows start 16-byte aligned: n and the
+    // plane pitch are multiples of 4)
+    const float4* q = reinterpret_cast<const float4*>(box + static_cast<size_t>(row / n) * pitch +
+                                                      static_cast<size_t>(row % n) * n);
+#pragma unroll 2
+    for (int i = threadIdx.x; i < n / 2; i += 256) {
+      const float4 v = q[i];
+      s[0] += static_cast<double>(v.x) + v.z;
+      s[1] += static_cast<double>(v.x) * v.x + static_cast<double>(v.z) * v.z;
+      s[2] += static_cast<double>(v.y) + v.w;
+      s[3] += static_cast<double>(v.y) * v.y + static_cast<double>(v.w) * v.w;
     }
   }
 #pragma unroll
@@ -214,7 +218,7 @@ __global__ void __launch_bounds__(256) k_qso_coef(const float* __restrict__ ztab
 
 // ---- the draw ----
 // One thread per four consecutive voxels along z (one Philox call gives their
-// four decision uniforms).  Selected voxels are appended with one atomic per
+// four decision uniforms), persistent blocks walking tiles of 1,024 voxels.  Selected voxels are appended with one atomic per
 // wave; a slot at or beyond cap is counted but not written.
 template <int NB>
 __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
@@ -224,12 +228,21 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
     snb[i] = static_cast<float>(a.nbar[i]);
   }
   __syncthreads();
+  // the largest density, raised by a margin over the rounding of the
+  // interpolation between two nodes
+  float nb_top = 0.0f;
+  for (int i = 0; i < a.n_nbar; ++i) nb_top = fmaxf(nb_top, snb[i]);
+  nb_top *= 1.0f + 1.0e-6f;
   float hv[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) hv[i] = 0.5f * static_cast<float>(*a.var[i]);
 
   const int n = a.n;
-  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * 256u + threadIdx.x;
+  // persistent blocks over tiles of 256 groups: every thread of a block runs
+  // the same number of tiles, so the wave-wide ballots see full waves
+  const uint64_t ntiles = static_cast<uint64_t>(n) * n * n / 1024u;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const uint64_t g = tile * 256u + threadIdx.x;
   const int q = n >> 2;
   const uint64_t row = g / q;
   const int iz0 = static_cast<int>(g % q) * 4;
@@ -264,17 +277,6 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
     const float fr = t - static_cast<float>(i0);
     const float4 c0 = a.tab[i0], c1 = a.tab[i0 + 1];
     const float z = c0.x + fr * (c1.x - c0.x);
-    // nbar(z): linear between the nodes, zero outside
-    float nb = 0.0f;
-    if (z >= snz[0] && z <= snz[a.n_nbar - 1]) {
-      int lo = 0, hi = a.n_nbar - 1;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (snz[mid] <= z) lo = mid; else hi = mid;
-      }
-      const float span = snz[hi] - snz[lo];
-      nb = span > 0.0f ? snb[lo] + (snb[hi] - snb[lo]) * ((z - snz[lo]) / span) : snb[lo];
-    }
     const float lz = __log2f(1.0f + z);
     float acc;
     if (NB == 1) {
@@ -289,8 +291,24 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
         acc += cf[i] * expf(al * d[i][e] - al * al * hv[i]);
       }
     }
-    const float p = fminf(nb * a.dx3 * acc, 1.0f);
-    sel[e] = u01(words[e]) < p;
+    // p <= nb_top dx^3 acc (rounding is monotone): most voxels are rejected
+    // on that bound before nbar(z) is looked up
+    const float u = u01(words[e]);
+    sel[e] = false;
+    if (u < fminf(nb_top * a.dx3 * acc, 1.0f)) {
+      // nbar(z): linear between the nodes, zero outside
+      float nb = 0.0f;
+      if (z >= snz[0] && z <= snz[a.n_nbar - 1]) {
+        int lo = 0, hi = a.n_nbar - 1;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (snz[mid] <= z) lo = mid; else hi = mid;
+        }
+        const float span = snz[hi] - snz[lo];
+        nb = span > 0.0f ? snb[lo] + (snb[hi] - snb[lo]) * ((z - snz[lo]) / span) : snb[lo];
+      }
+      sel[e] = u < fminf(nb * a.dx3 * acc, 1.0f);
+    }
   }
 
   uint64_t b[4];
@@ -300,7 +318,7 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
     b[e] = __ballot(sel[e]);
     tot += __popcll(b[e]);
   }
-  if (tot == 0) return;  // uniform over the wave
+  if (tot == 0) continue;  // uniform over the wave
   const int lane = threadIdx.x & 63;
   unsigned long long base = 0;
   if (lane == 0) base = atomicAdd(a.count, static_cast<unsigned long long>(tot));
@@ -325,6 +343,7 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
     }
     before += __popcll(b[e]);
   }
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
@@ -333,8 +352,10 @@ hipError_t launch_qso_draw(const QsoCoef& c, const QsoDrawArgs& a, const float* 
   LYA_TIMED("qso_coef", st,
             hipLaunchKernelGGL(k_qso_coef, dim3((kZTabN + 255) / 256), dim3(256), 0, st, ztab, c, tab));
   LYA_TIMED("qso_zero", st, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, a.count));
-  // n^3 / 4 threads: a multiple of 256 for every supported n (n >= 32)
-  const uint64_t blocks = static_cast<uint64_t>(a.n) * a.n * a.n / 4 / 256;
+  // tiles of 256 threads x 4 voxels: n^3 / 1024 of them for every supported n
+  // (n >= 32); eight persistent blocks per CU at most
+  const uint64_t tiles = static_cast<uint64_t>(a.n) * a.n * a.n / 1024;
+  const uint64_t blocks = std::min<uint64_t>(tiles, static_cast<uint64_t>(device_cus()) * 8);
   if (a.nb == 3) {
     LYA_TIMED("qso_draw", st, hipLaunchKernelGGL(k_qso_draw<3>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
                                                  st, a));
