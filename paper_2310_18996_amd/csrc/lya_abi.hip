@@ -721,6 +721,7 @@ int lya_draw_quasars(const lya_box* box, const lya_qso_spec* spec, const lya_cos
   cf.xi5 = spec->xi5;
   lya::QsoDrawArgs a{};
   a.n = box->n;
+  while ((1 << a.log2n) < box->n) ++a.log2n;
   a.pitch = lya::plane_pitch(box->n);
   a.nb = nb;
   a.box_a = static_cast<const float2*>(spec->box_a);

@@ -240,7 +240,7 @@ struct QsoCoef {
   double xi5;
 };
 struct QsoDrawArgs {
-  int n;
+  int n, log2n;
   size_t pitch;
   int nb;
   const float2* box_a;    // delta_1 (re) and, for three boxes, delta_2 (im)

@@ -217,15 +217,82 @@ __global__ void __launch_bounds__(256) k_qso_coef(const float* __restrict__ ztab
 }
 
 // ---- the draw ----
-// One thread per four consecutive voxels along z (one Philox call gives their
-// four decision uniforms), persistent blocks walking tiles of 1,024 voxels.  Selected voxels are appended with one atomic per
+// One thread per VPT consecutive voxels along z (one Philox call gives the
+// decision uniforms of four).  Selected voxels are appended with one atomic per
 // wave; a slot at or beyond cap is counted but not written.
-template <int NB>
+// The transcendentals run on the hardware units (v_sqrt_f32, v_log_f32,
+// v_exp_f32: about 1 ulp each); the exponent's own rounding, |x| 2^-24 for
+// |x| up to about 10, dominates the error of p (a few 1e-7 relative).
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr int kQsoVpt = 8;  // voxels per thread (consecutive along z)
+
+template <int NB, int VPT>
 __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
+  static_assert(VPT % 4 == 0, "whole Philox calls per thread");
   __shared__ float snz[kQsoMaxNbar], snb[kQsoMaxNbar];
+  const int n = a.n;
+  // thread t of block b takes voxels v0 .. v0 + VPT - 1 along z, v0 = VPT (256 b + t)
+  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * 256u + threadIdx.x;
+  const uint64_t v0 = g * VPT;
+  // n is a power of two: shifts and masks instead of 64-bit divisions
+  const uint64_t row = v0 >> a.log2n;
+  const int iz0 = static_cast<int>(v0 & static_cast<uint64_t>(n - 1));
+  const int ix = static_cast<int>(row >> a.log2n), iy = static_cast<int>(row & static_cast<uint64_t>(n - 1));
+  const size_t e0 = static_cast<size_t>(ix) * a.pitch + static_cast<size_t>(iy) * n + iz0;
+
+  // the field loads first, so that their latency overlaps the block's
+  // set-up (nbar into LDS, the variances) and the Philox rounds
+  float d[NB][VPT];
+#pragma unroll
+  for (int h = 0; h < VPT / 2; ++h) {
+    const float4 v = *reinterpret_cast<const float4*>(a.box_a + e0 + 2 * h);
+    d[0][2 * h] = v.x;
+    d[0][2 * h + 1] = v.z;
+    if (NB == 3) {
+      const float4 w = *reinterpret_cast<const float4*>(a.box_b + e0 + 2 * h);
+      d[1 % NB][2 * h] = v.y;
+      d[1 % NB][2 * h + 1] = v.w;
+      d[2 % NB][2 * h] = w.x;
+      d[2 % NB][2 * h + 1] = w.z;
+    }
+  }
   for (int i = threadIdx.x; i < a.n_nbar; i += 256) {
     snz[i] = static_cast<float>(a.nbar_z[i]);
     snb[i] = static_cast<float>(a.nbar[i]);
+  }
+  float hv[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) hv[i] = 0.5f * static_cast<float>(*a.var[i]);
+  // distance, z and the three-box coefficients of the voxels (table loads
+  // issued before the barrier as well)
+  const float rx = static_cast<float>(ix * a.dx_d - a.o[0]);
+  const float ry = static_cast<float>(iy * a.dx_d - a.o[1]);
+  const float r2xy = rx * rx + ry * ry;
+  float zv[VPT], cfv[VPT][3];
+#pragma unroll
+  for (int e = 0; e < VPT; ++e) {
+    const float rz = static_cast<float>(iz0 + e) * a.dx - a.oz;
+    const float chi = __builtin_amdgcn_sqrtf(r2xy + rz * rz);
+    const float t = chi * (1.0f / static_cast<float>(kZTabH));
+    const int i0 = min(static_cast<int>(t), kZTabN - 2);
+    const float fr = t - static_cast<float>(i0);
+    const float4 c0 = a.tab[i0], c1 = a.tab[i0 + 1];
+    zv[e] = c0.x + fr * (c1.x - c0.x);
+    cfv[e][0] = c0.y + fr * (c1.y - c0.y);
+    cfv[e][1] = c0.z + fr * (c1.z - c0.z);
+    cfv[e][2] = c0.w + fr * (c1.w - c0.w);
+  }
+  // decision words: voxel m takes word m & 3 of the call for counter m >> 2
+  uint32_t words[VPT];
+#pragma unroll
+  for (int c = 0; c < VPT / 4; ++c) {
+    const uint64_t ctr = (v0 >> 2) + c;
+    const uint4 wd = philox10_x3(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 2u, 0u),
+                                 static_cast<uint32_t>(a.seed), static_cast<uint32_t>(a.seed >> 32));
+    words[4 * c] = wd.x;
+    words[4 * c + 1] = wd.y;
+    words[4 * c + 2] = wd.z;
+    words[4 * c + 3] = wd.w;
   }
   __syncthreads();
   // the largest density, raised by a margin over the rounding of the
@@ -233,62 +300,22 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
   float nb_top = 0.0f;
   for (int i = 0; i < a.n_nbar; ++i) nb_top = fmaxf(nb_top, snb[i]);
   nb_top *= 1.0f + 1.0e-6f;
-  float hv[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) hv[i] = 0.5f * static_cast<float>(*a.var[i]);
 
-  const int n = a.n;
-  // persistent blocks over tiles of 256 groups: every thread of a block runs
-  // the same number of tiles, so the wave-wide ballots see full waves
-  const uint64_t ntiles = static_cast<uint64_t>(n) * n * n / 1024u;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-  const uint64_t g = tile * 256u + threadIdx.x;
-  const int q = n >> 2;
-  const uint64_t row = g / q;
-  const int iz0 = static_cast<int>(g % q) * 4;
-  const int ix = static_cast<int>(row / n), iy = static_cast<int>(row % n);
-  const size_t e0 = static_cast<size_t>(ix) * a.pitch + static_cast<size_t>(iy) * n + iz0;
-
-  float d[NB][4];
-  {
-    const float4 v0 = *reinterpret_cast<const float4*>(a.box_a + e0);
-    const float4 v1 = *reinterpret_cast<const float4*>(a.box_a + e0 + 2);
-    d[0][0] = v0.x; d[0][1] = v0.z; d[0][2] = v1.x; d[0][3] = v1.z;
-    if (NB == 3) {
-      const float4 w0 = *reinterpret_cast<const float4*>(a.box_b + e0);
-      const float4 w1 = *reinterpret_cast<const float4*>(a.box_b + e0 + 2);
-      d[1 % NB][0] = v0.y; d[1 % NB][1] = v0.w; d[1 % NB][2] = v1.y; d[1 % NB][3] = v1.w;
-      d[2 % NB][0] = w0.x; d[2 % NB][1] = w0.z; d[2 % NB][2] = w1.x; d[2 % NB][3] = w1.z;
-    }
-  }
-  const uint4 wd = philox10_x3(make_uint4(static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), 2u, 0u),
-                               static_cast<uint32_t>(a.seed), static_cast<uint32_t>(a.seed >> 32));
-  const uint32_t words[4] = {wd.x, wd.y, wd.z, wd.w};
-  const float rx = static_cast<float>(ix * a.dx_d - a.o[0]);
-  const float ry = static_cast<float>(iy * a.dx_d - a.o[1]);
-  const float r2xy = rx * rx + ry * ry;
-  bool sel[4];
+  bool sel[VPT];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const float rz = static_cast<float>(iz0 + e) * a.dx - a.oz;
-    const float chi = __builtin_sqrtf(r2xy + rz * rz);
-    const float t = chi * (1.0f / static_cast<float>(kZTabH));
-    const int i0 = min(static_cast<int>(t), kZTabN - 2);
-    const float fr = t - static_cast<float>(i0);
-    const float4 c0 = a.tab[i0], c1 = a.tab[i0 + 1];
-    const float z = c0.x + fr * (c1.x - c0.x);
+  for (int e = 0; e < VPT; ++e) {
+    const float z = zv[e];
     const float lz = __log2f(1.0f + z);
     float acc;
     if (NB == 1) {
-      const float al = exp2f(0.7f * (lz - a.l2z[0]));
-      acc = expf(al * d[0][e] - al * al * hv[0]);
+      const float al = __builtin_amdgcn_exp2f(0.7f * (lz - a.l2z[0]));
+      acc = __builtin_amdgcn_exp2f(kLog2e * (al * d[0][e] - al * al * hv[0]));
     } else {
-      const float cf[3] = {c0.y + fr * (c1.y - c0.y), c0.z + fr * (c1.z - c0.z), c0.w + fr * (c1.w - c0.w)};
       acc = 0.0f;
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const float al = exp2f(0.7f * (lz - a.l2z[i]));
-        acc += cf[i] * expf(al * d[i][e] - al * al * hv[i]);
+        const float al = __builtin_amdgcn_exp2f(0.7f * (lz - a.l2z[i]));
+        acc += cfv[e][i] * __builtin_amdgcn_exp2f(kLog2e * (al * d[i][e] - al * al * hv[i]));
       }
     }
     // p <= nb_top dx^3 acc (rounding is monotone): most voxels are rejected
@@ -311,14 +338,14 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
     }
   }
 
-  uint64_t b[4];
+  uint64_t b[VPT];
   int tot = 0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < VPT; ++e) {
     b[e] = __ballot(sel[e]);
     tot += __popcll(b[e]);
   }
-  if (tot == 0) continue;  // uniform over the wave
+  if (tot == 0) return;  // uniform over the wave
   const int lane = threadIdx.x & 63;
   unsigned long long base = 0;
   if (lane == 0) base = atomicAdd(a.count, static_cast<unsigned long long>(tot));
@@ -328,11 +355,11 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   unsigned long long before = 0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < VPT; ++e) {
     if (sel[e]) {
       const unsigned long long slot = base + before + __popcll(b[e] & below);
       if (slot < static_cast<unsigned long long>(a.cap)) {
-        const uint64_t m = (static_cast<uint64_t>(ix) * n + iy) * n + iz0 + e;
+        const uint64_t m = v0 + e;
         const uint4 pw = philox10_x3(make_uint4(static_cast<uint32_t>(m), static_cast<uint32_t>(m >> 32), 4u, 0u),
                                      static_cast<uint32_t>(a.seed), static_cast<uint32_t>(a.seed >> 32));
         int64_t* o = a.pos + 3 * slot;
@@ -343,7 +370,6 @@ __global__ void __launch_bounds__(256) k_qso_draw(QsoDrawArgs a) {
     }
     before += __popcll(b[e]);
   }
-  }
 }
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
@@ -352,16 +378,16 @@ hipError_t launch_qso_draw(const QsoCoef& c, const QsoDrawArgs& a, const float* 
   LYA_TIMED("qso_coef", st,
             hipLaunchKernelGGL(k_qso_coef, dim3((kZTabN + 255) / 256), dim3(256), 0, st, ztab, c, tab));
   LYA_TIMED("qso_zero", st, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, a.count));
-  // tiles of 256 threads x 4 voxels: n^3 / 1024 of them for every supported n
-  // (n >= 32); eight persistent blocks per CU at most
-  const uint64_t tiles = static_cast<uint64_t>(a.n) * a.n * a.n / 1024;
-  const uint64_t blocks = std::min<uint64_t>(tiles, static_cast<uint64_t>(device_cus()) * 8);
+  // 256 threads x kQsoVpt voxels per block: n^3 / (256 kQsoVpt) blocks, a
+  // whole number for every supported n (n >= 32), so every wave is full, as
+  // the wave-wide ballots need
+  const uint64_t blocks = static_cast<uint64_t>(a.n) * a.n * a.n / (256 * kQsoVpt);
   if (a.nb == 3) {
-    LYA_TIMED("qso_draw", st, hipLaunchKernelGGL(k_qso_draw<3>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
-                                                 st, a));
+    LYA_TIMED("qso_draw", st, hipLaunchKernelGGL((k_qso_draw<3, kQsoVpt>), dim3(static_cast<unsigned>(blocks)),
+                                                 dim3(256), 0, st, a));
   } else {
-    LYA_TIMED("qso_draw", st, hipLaunchKernelGGL(k_qso_draw<1>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
-                                                 st, a));
+    LYA_TIMED("qso_draw", st, hipLaunchKernelGGL((k_qso_draw<1, kQsoVpt>), dim3(static_cast<unsigned>(blocks)),
+                                                 dim3(256), 0, st, a));
   }
   return hipGetLastError();
 }
