@@ -43,12 +43,13 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) on the 2048^3 + 1M-skewer workload, scaled by what the same
 # counters read for a plain 4 GiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1);
-# profiles/box2048_skewers1M_hbm_traffic.md.  Keyed by (kernel, FFT variant)
+# profiles/box2048_skewers1M_hbm_traffic.md and, for the quasar draw of the
+# quasar leg, profiles/quasars2048_kernel_stats_hbm_traffic.md.  Keyed by (kernel, FFT variant)
 # for the strided passes; valid only for the kernels as they were when the
 # counters were taken (a changed kernel must drop its entry) and reported only
 # for that workload.
-TRAFFIC = {("fft_x", 9): 137507209985, ("fft_y", 8): 139297466605, ("fft_z_gen", None): 95735471957,
-           ("skewers", None): 14567472909}
+TRAFFIC = {("fft_x", 9): 137479106942, ("fft_y", 8): 140184875987, ("fft_z_gen", None): 95744906378,
+           ("skewers", None): 14569495777, ("qso_draw", None): 137557461001}
 TRAFFIC_CONFIG = "big"
 
 
@@ -263,7 +264,7 @@ def wide_leg(L, torch, stream, reps=3):
 
 
 # ---------------------------------------------------------------- tuning leg
-def quasar_leg(L, torch, stream, cfg, reps=2):
+def quasar_leg(L, torch, stream, cfg, reps=2, counted=False):
     """The lognormal quasar field on the workload's box (section "Quasar
     generation", Appendix A): P_q of the three boxes at z = 1.9, 2.75, 3.6
     from the smoothed matter spectrum, the pair box {delta_q1, delta_q2} and
@@ -387,7 +388,9 @@ def quasar_leg(L, torch, stream, cfg, reps=2):
                 moments_ms=mom_ms, draw_ms=draw_ms, draw_kernel_ms=kern, voxels_per_s=cells / (kern * 1e-3),
                 quasars=count, xi5=xi5, variances=[float(m[1]), float(m[3]), float(m[5])], catalogue=catalogue,
                 roofline=dict(kernel="qso_draw", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                              frac=achieved / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=ab,
+                              frac=achieved / HBM_PEAK_GBS,
+                              traffic=TRAFFIC.get(("qso_draw", None)) if counted else None,
+                              algorithmic_bytes_per_launch=ab,
                               mean_launch_ms=kern))
 
 
@@ -806,7 +809,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_quasars:
         print("bench: lognormal quasar leg", file=sys.stderr, flush=True)
-        out["quasars"] = quasar_leg(L, torch, stream, cfg)
+        out["quasars"] = quasar_leg(L, torch, stream, cfg, counted=args.config == TRAFFIC_CONFIG)
         torch.cuda.empty_cache()
     else:
         out["quasars"] = None
