@@ -160,7 +160,7 @@ def brute_force_field(n, xhat):
     return out
 
 
-def shell_modes(n, seed, table, only_n2, comps=("delta", "zz"), f=1.0):
+def shell_modes(n, seed, table, only_n2, comps=("delta", "zz"), f=1.0, box_len=None):
     """The modes of one shell |n|^2 = only_n2 of the packed spectrum (the
     spectrum() field with every other mode zero): integer frequencies
     [M, 3] and complex coefficients [M], from the same noise, amplitude and
@@ -175,7 +175,7 @@ def shell_modes(n, seed, table, only_n2, comps=("delta", "zz"), f=1.0):
     base = table[only_n2] * noise_at(n, seed, gx, gy, gz)
     vals = []
     for comp in comps:
-        mult = multiplier_at(n, comp, f, gx, gy, gz)
+        mult = multiplier_at(n, comp, f, gx, gy, gz, box_len)
         vals.append(base if mult is None else mult * base)
     coef = vals[0] if len(vals) == 1 else vals[0] + 1j * vals[1]
     return freqs, coef

@@ -427,3 +427,67 @@ def test_quasar_lines_of_sight(L):
     assert torch.isfinite(dens).all() and torch.isfinite(eta).all()
     # the skewers' first pixels sit at the forests' red ends, the quasars beyond them
     assert np.all(got["chi0"] < np.sqrt(np.sum((fx / 2.0 ** 32 * dx - obs) ** 2, axis=1)))
+
+
+class _ShellPart:
+    """[n, n, n] real grid: one part of a single-shell field, evaluated by the
+    oracle's direct sum at the voxels requested."""
+
+    def __init__(self, n, freqs, coef, imag=False):
+        self.n, self.shape, self.freqs, self.coef, self.imag = n, (n, n, n), freqs, coef, imag
+
+    def __getitem__(self, idx):
+        a, b, c = (np.asarray(i, dtype=np.int64) for i in idx)
+        v = field.shell_field_at(self.n, self.freqs, self.coef, a.ravel(), b.ravel(), c.ravel())
+        return (v.imag if self.imag else v.real).reshape(a.shape)
+
+
+def test_full_size_catalogue_on_single_shell_velocity_boxes(L):
+    # the 2048^3 velocity boxes of the benchmark's catalogue, single-shell (the
+    # only_n2 hook), and 2,000 quasars spread over the box below z = 4.5: redshifts and
+    # skewer rows against the oracle's direct-sum velocities
+    import mockinputs
+    cfg = mockinputs.config("big")
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    print("2048^3 velocity boxes, shell |n|^2 = %d" % SHELL, flush=True)
+    box = L.box_struct(n, dx)
+    pk = L.pk_struct(sigma8=SHELL_SIGMA8, only_n2=SHELL)
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fxy, fz = (torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") for _ in range(2))
+    L.make_eta(box, pk, seed, 1.0, "vx", "vy", fxy, work)
+    L.make_eta(box, pk, seed, 1.0, "vz", "none", fz, work)
+    del work
+    tab = power.amplitude_table(power.PowerSpectrum(**dict(cfg["pk"], sigma8=SHELL_SIGMA8)), n, dx)
+    fr_xy, c_xy = field.shell_modes(n, seed, tab, SHELL, comps=("vx", "vy"), f=1.0, box_len=n * dx)
+    fr_z, c_z = field.shell_modes(n, seed, tab, SHELL, comps=("vz",), f=1.0, box_len=n * dx)
+    rng = np.random.default_rng(17)
+    pos = rng.integers(0, n << 32, size=(8000, 3), dtype=np.int64) - (1 << 31)
+    obs = mockinputs.qso_observer(n, dx)
+    # quasars within the catalogue's redshifts (the far corners of the box lie
+    # beyond z = 40)
+    chi = np.sqrt(np.sum((pos / 2.0 ** 32 * dx - obs) ** 2, axis=1))
+    pos = pos[chi < cosmology.chi_of_z(4.5)][:2000]
+    assert len(pos) == 2000
+    r_lo, r_hi = 1040.0 / 1215.67, 1200.0 / 1215.67
+    qw = torch.empty(L.workspace_size(L.LYA_OP_QUASARS, box), dtype=torch.uint8, device="cuda")
+    got = L.quasar_skewers(box, torch.from_numpy(pos).cuda(), fxy, fz, obs, r_lo, r_hi, 1.8, 0.2,
+                           L.Cosmo(cosmology.OMEGA_M), qw)
+    got = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in got.items()}
+    print("oracle catalogue of %d quasars" % len(pos), flush=True)
+    ref = quasars.lines_of_sight(pos, _ShellPart(n, fr_xy, c_xy), _ShellPart(n, fr_xy, c_xy, imag=True),
+                                 _ShellPart(n, fr_z, c_z), dx, obs, r_lo, r_hi, 1.8, 0.2)
+    dz = np.abs(got["z_q"] - ref["z_q"])
+    shift = np.abs(ref["z_q"] - ref["z_c"])
+    print("max |dz_q| %.2e, RSD shifts up to %.2e; total pixels %d / %d"
+          % (dz.max(), shift.max(), got["total"], ref["total"]), flush=True)
+    assert shift.max() > 1e-4
+    assert dz.max() < 1e-8
+    np.testing.assert_allclose(got["chi0"], ref["chi0"], rtol=0, atol=1e-4)
+    c_lo = cosmology.chi_of_z(np.maximum((1 + ref["z_q"]) * r_lo - 1, 1.8))
+    frac = (ref["chi0"] - c_lo) / 0.2
+    diff = got["npix"] != ref["npix"]
+    assert np.all(np.abs(frac - np.rint(frac))[diff] < 1e-3) and np.all(np.abs(got["npix"] - ref["npix"]) <= 1)
+    assert np.abs(got["origin_fx"] - ref["origin_fx"]).max() <= (1 << 14)
+    assert np.abs(got["step_fx"] - ref["step_fx"]).max() <= 2
+    del fxy, fz
+    torch.cuda.empty_cache()

@@ -171,3 +171,13 @@ def test_velocity_continuity_and_reality():
     # the Nyquist plane of v_j carries nothing
     vx_hat = np.fft.fftn(vxy.real)
     assert np.max(np.abs(vx_hat[n // 2])) < 1e-9 * np.abs(vx_hat).max()
+
+
+@pytest.mark.parametrize("n,s2", [(16, 6), (32, 27)])
+def test_shell_direct_sum_of_velocities(n, s2):
+    tab = _table(n)
+    box = field.make_box(n, 9, tab, ("vx", "vy"), f=1.0, only_n2=s2, box_len=40.0)
+    freqs, coef = field.shell_modes(n, 9, tab, s2, comps=("vx", "vy"), f=1.0, box_len=40.0)
+    ix, iy, iz = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    got = field.shell_field_at(n, freqs, coef, ix, iy, iz, chunk=999)
+    np.testing.assert_allclose(got, box, atol=1e-12 * np.abs(box).max())
