@@ -491,3 +491,30 @@ def test_full_size_catalogue_on_single_shell_velocity_boxes(L):
     assert np.abs(got["step_fx"] - ref["step_fx"]).max() <= 2
     del fxy, fz
     torch.cuda.empty_cache()
+
+
+def test_pair_and_velocity_boxes_in_bf16_storage(L):
+    # the two-spectrum box and the velocity pair in BF16 storage (8
+    # significant bits) against the oracle's boxes
+    from lyahelp import bf16_to_f32
+    n, dx, seed = 64, 5.0, 37
+    box = L.box_struct(n, dx, L.LYA_BF16)
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    fld = torch.empty((L.field_elems(box),), dtype=torch.int32, device="cuda")
+    k = np.geomspace(1e-3, 20.0, 300)
+    p = 0.5 * power.PowerSpectrum()(k)
+    kt, pt = _dev(k), _dev(p)
+    L.make_box_pair(box, L.pk_struct(), L.pk_struct(k_tab=kt, p_tab=pt), seed, fld, work)
+    torch.cuda.synchronize()
+    got = bf16_to_f32(L.box_view(fld, n)).astype(np.float64)
+    ra = field.make_box(n, seed, power.amplitude_table(power.PowerSpectrum(), n, dx), ("delta",)).real
+    rb = field.make_box(n, seed, power.amplitude_table(power.TabulatedPower(k, p), n, dx), ("delta",)).real
+    e = (rel_rms(got[..., 0], ra), rel_rms(got[..., 1], rb))
+    L.make_eta(box, L.pk_struct(), seed, 1.0, "vx", "vy", fld, work)
+    torch.cuda.synchronize()
+    gv = bf16_to_f32(L.box_view(fld, n)).astype(np.float64)
+    rv = field.make_box(n, seed, power.amplitude_table(power.PowerSpectrum(), n, dx), ("vx", "vy"), f=1.0,
+                        box_len=n * dx)
+    e += (rel_rms(gv[..., 0], rv.real), rel_rms(gv[..., 1], rv.imag))
+    print("BF16 pair box and velocities: rel rms %s" % ["%.2e" % v for v in e])
+    assert max(e) < 4e-3
