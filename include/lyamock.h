@@ -480,8 +480,10 @@ typedef struct {
  * outside them; one box: c_1 = 1; three boxes: p = w p_12 + (1 - w) p_23 with
  * p_12 the linear interpolation in z of boxes 1 and 2, p_23 the linear
  * extrapolation of boxes 2 and 3, and w in [0, 1] such that
- * w xi_12 + (1 - w) xi_23 = (b_q(z) G(z))^2 xi5 at r = 5 Mpc/h, where
- * xi_i = (1 + b_0i^2 xi5)^(a_i^2) - 1 (Appendix A).  Random numbers:
+ * w xi_12 + (1 - w) xi_23 = (b_q(z) G_q(z))^2 xi5 at r = 5 Mpc/h, where
+ * xi_i = (1 + b_0i^2 xi5)^(a_i^2) - 1, G_q(z) = G(z_2)(1 + z_2)/(1 + z) and
+ * b_0i = b_q(z_i) G_q(z_i), as lya_lognormal_pk takes them with z_ref = z_2
+ * (Appendix A); w = 1/2 where xi_12 = xi_23.  Random numbers:
  * Philox4x32-10, key = seed; the decision of voxel m (linear index
  * (m_x n + m_y) n + m_z) takes word m & 3 of counter (m >> 2, 0, 2, 0) as
  * u = ((w >> 9) + 1/2) 2^-23 and selects when u < p; the selected voxel's
