@@ -36,8 +36,26 @@ Readings (the paper is silent or states these loosely):
 * delta_L and eta_par are the stored pixels without delta_S; delta_S is
   drawn per skewer exactly as oracle.skewers.delta_s (Philox stream 1,
   counter (q << 33) + m) with the amplitude sqrt(P_s^n(k_m) / (N_S dpix)).
-The outer loop of the paper (adjusting a and b against the bias of the
-correlation-function prediction) is not part of this reading.
+
+The outer loop (the paper adjusts a and b so that the bias its
+correlation-function prediction implies approaches the target while Fbar
+stays, then runs the P_s iteration again; five times), read as:
+
+* the large-scale flux bias with respect to delta_L is the first term of the
+  bivariate-Gaussian expansion of the flux correlation: b_F = E[dF/dg] /
+  Fbar = -(a s / sigma_g) E[e^{s x} F] / Fbar (Stein's identity; g =
+  delta_L + delta_S + c eta_par responds one to one to a long delta_L mode,
+  delta_S being uncorrelated), beta_F = f c (the paper's f c(z_t) = beta);
+  the target is the effective bias |b_F| (1 + 2 beta/3 + beta^2/5)^(1/2);
+* outer step o >= 1: sigma_g from the current P_s (the ratios after the last
+  update), (a, s) solve Fbar(a, s) = Fbar_t and b_eff(a, s; sigma_g) =
+  b_eff,t, and the P_s iteration runs again from the current ratios; outer
+  step 0 is the (Fbar, sigma_F) fit above;
+* at fixed Fbar the bias tends to phi(x_0) / (sigma_g Fbar), x_0 =
+  Phi^{-1}(Fbar), as s grows (F becomes a step), so a target beyond what the
+  current sigma_g allows has no solution: the outer loop then stops and keeps
+  the last step (a poor first step, e.g. sigma_F from a binned P1D that
+  misses most of the power, leads there).
 """
 import numpy as np
 from scipy import integrate, optimize, special
@@ -67,6 +85,38 @@ def fit_a_s(fbar_t, sigf_t, x0=(0.3, 0.5)):
         return [np.log(f / fbar_t), np.log(sf / sigf_t)]
 
     sol = optimize.root(resid, np.log(np.asarray(x0, dtype=np.float64)), method="hybr", tol=1e-14)
+    return float(np.exp(sol.x[0])), float(np.exp(sol.x[1]))
+
+
+def flux_bias(a, s, sigma_g):
+    """b_F = -(a s / sigma_g) E[e^{s x} F(x)] / Fbar, F = exp(-a exp(s x))."""
+    pdf = lambda x: np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
+    x0 = float(np.clip(-np.log(a) / s, -11.0, 11.0)) if s > 0 else 0.0
+    m = integrate.quad(lambda x: np.exp(s * x - a * np.exp(s * x)) * pdf(x), -12.0, 12.0, points=[x0],
+                       epsabs=1e-15, epsrel=1e-13, limit=400)[0]
+    fbar = gauss_fbar_sigf(a, s)[0]
+    return -(a * s / sigma_g) * m / fbar
+
+
+def kaiser_factor(beta):
+    """(1 + 2 beta/3 + beta^2/5)^(1/2): the monopole of (1 + beta mu^2)^2."""
+    return float(np.sqrt(1.0 + 2.0 * beta / 3.0 + beta * beta / 5.0))
+
+
+def effective_bias(a, s, sigma_g, beta):
+    return abs(flux_bias(a, s, sigma_g)) * kaiser_factor(beta)
+
+
+def fit_a_s_bias(fbar_t, beff_t, sigma_g, beta, x0=(0.3, 0.5)):
+    """(a, s) with Fbar(a, s) = fbar_t and b_eff(a, s; sigma_g) = beff_t, or
+    None when the solve fails."""
+    def resid(t):
+        a, s = np.exp(t[0]), np.exp(t[1])
+        return [np.log(gauss_fbar_sigf(a, s)[0] / fbar_t), np.log(effective_bias(a, s, sigma_g, beta) / beff_t)]
+
+    sol = optimize.root(resid, np.log(np.asarray(x0, dtype=np.float64)), method="hybr", tol=1e-14)
+    if not np.all(np.isfinite(sol.x)) or np.max(np.abs(resid(sol.x))) > 1e-9:
+        return None
     return float(np.exp(sol.x[0])), float(np.exp(sol.x[1]))
 
 
@@ -130,11 +180,14 @@ def moments(dl, eta):
 
 
 def iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, dpix, amp0, kcut0, n_iter=10,
-            omega_m=cosmology.OMEGA_M, sigf_t=None):
+            omega_m=cosmology.OMEGA_M, sigf_t=None, n_outer=1, beff_t=None, f=1.0):
     """The procedure above at one z_t.  Returns a, b of the last iteration, the
     ratios it used, and per iteration (Fbar, P1D, sigma_g).  sigf_t, when
     given, is the target flux dispersion itself (a synthetic truth knows it);
-    otherwise it comes from the target P1D over its bins."""
+    otherwise it comes from the target P1D over its bins.  n_outer > 1 adds
+    outer steps (target effective bias beff_t, beta = f c_t); "beff" holds
+    the predicted effective bias after each outer step run and "hist" the
+    iterations of the last one."""
     k_edges = np.asarray(k_edges, dtype=np.float64)
     nk = len(k_edges) - 1
     edges_k = k_edges * dv_per_dchi(z_t, omega_m)
@@ -145,6 +198,26 @@ def iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, dpix, amp0, kcut
     ratio = np.ones(nk)
     npix = np.asarray(sk["npix"])
     off = np.asarray(sk["offset"])
+    beta = f * c_t
+    sg_of = lambda r: np.sqrt(sl2 + sigma_s2(amp0, kcut0, r, edges_k, dpix) + c_t * c_t * se2 + 2.0 * c_t * cov)
+    beff = []
+    for o in range(n_outer):
+        if o > 0:
+            fit = fit_a_s_bias(fbar_t, beff_t, sg_of(ratio), beta, x0=(a, s))
+            if fit is None:
+                break
+            a, s = fit
+        hist, ratio = _inner(dl, eta, sk, seed, z_t, c_t, pk_t, k_edges, edges_k, dpix, amp0, kcut0, n_iter,
+                             omega_m, a, s, ratio, sl2, se2, cov, npix, off)
+        beff.append(effective_bias(a, s, hist[-1]["sigma_g"], beta))
+    return dict(a=a, s=s, b=hist[-1]["b"], ratio=hist[-1]["ratio"], hist=hist,
+                moments=(sl2, se2, cov), beff=beff)
+
+
+def _inner(dl, eta, sk, seed, z_t, c_t, pk_t, k_edges, edges_k, dpix, amp0, kcut0, n_iter, omega_m, a, s, ratio,
+           sl2, se2, cov, npix, off):
+    """n_iter P_s iterations from the given ratios; returns their history and
+    the ratios after the last update."""
     hist = []
     for it in range(n_iter):
         used = ratio.copy()
@@ -165,5 +238,4 @@ def iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, dpix, amp0, kcut
         upd = np.isfinite(pk_t) & np.isfinite(pk) & (pk > 0)
         ratio = used.copy()
         ratio[upd] = used[upd] * np.asarray(pk_t)[upd] / pk[upd]
-    return dict(a=a, s=s, b=hist[-1]["b"], ratio=hist[-1]["ratio"], hist=hist,
-                moments=(sl2, se2, cov))
+    return hist, ratio

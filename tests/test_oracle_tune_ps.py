@@ -113,3 +113,79 @@ def test_iteration_converges_towards_a_target_from_another_small_scale_power():
     assert err[-1] < 0.7 * err[0]
     assert abs(res["hist"][-1]["fbar"] / fbar_t - 1) < 0.03
     assert abs(res["b"] / 1.4 - 1) < 0.03
+
+
+@pytest.mark.parametrize("a,s,sg", [(0.3, 0.8, 2.0), (0.05, 2.5, 3.1), (1.2, 0.4, 1.0)])
+def test_flux_bias_is_the_mean_flux_response(a, s, sg):
+    # b_F = (1/Fbar) dFbar/dmu for a long mode shifting g by mu: with b = s/sg,
+    # F(g + mu) = exp(-a e^{b mu} e^{s x}), so Fbar(mu) = Fbar(a e^{b mu}, s)
+    b = s / sg
+    h = 1e-5
+    fp = tune_ps.gauss_fbar_sigf(a * np.exp(b * h), s)[0]
+    fm = tune_ps.gauss_fbar_sigf(a * np.exp(-b * h), s)[0]
+    f0 = tune_ps.gauss_fbar_sigf(a, s)[0]
+    np.testing.assert_allclose(tune_ps.flux_bias(a, s, sg), (fp - fm) / (2 * h) / f0, rtol=1e-7)
+    assert tune_ps.flux_bias(a, s, sg) < 0
+
+
+def test_flux_bias_step_limit():
+    # s -> infinity at fixed x_0 = -ln(a)/s: F -> 1{x < x_0}, |b_F| -> phi(x_0)/(sigma_g Phi(x_0))
+    from scipy import stats
+    x0, sg = 0.3, 2.0
+    lim = stats.norm.pdf(x0) / (sg * stats.norm.cdf(x0))
+    got = [abs(tune_ps.flux_bias(np.exp(-s * x0), s, sg)) for s in (10.0, 20.0, 80.0)]
+    assert abs(got[2] / lim - 1) < abs(got[1] / lim - 1) < abs(got[0] / lim - 1)
+    assert abs(got[2] / lim - 1) < 0.01
+    # a target far beyond any reachable bias has no solution
+    assert tune_ps.fit_a_s_bias(0.6, 10.0 * lim, sg, 0.0) is None
+
+
+def test_kaiser_monopole_factor():
+    for beta in (0.0, 0.8, 1.6):
+        mono = integrate.quad(lambda mu: (1 + beta * mu * mu) ** 2, 0.0, 1.0)[0]
+        np.testing.assert_allclose(tune_ps.kaiser_factor(beta) ** 2, mono, rtol=1e-13)
+
+
+def test_fit_with_the_bias_target_recovers_a_and_s():
+    a0, s0, sg, beta = 0.4, 1.1, 2.2, 1.3
+    fbar = tune_ps.gauss_fbar_sigf(a0, s0)[0]
+    beff = tune_ps.effective_bias(a0, s0, sg, beta)
+    a, s = tune_ps.fit_a_s_bias(fbar, beff, sg, beta)
+    np.testing.assert_allclose([a, s], [a0, s0], rtol=1e-8)
+
+
+def test_outer_steps_reach_the_bias_target():
+    # a truth of known (a, b) and its predicted effective bias as the target;
+    # from the (Fbar, sigma_F) start the outer steps bring the prediction to
+    # the target and keep improving the P1D
+    cfg = mockinputs.config("tiny")
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    box = field.make_box(n, seed, oracle_table(cfg["pk"], n, dx), ("delta", "zz"), f=cfg["f"])
+    sk = mockinputs.skewer_table(cfg)
+    dl, eta = skewers.draw_skewers(box.real, box.imag, sk, seed)
+    k_edges = p1d.log_k_edges()
+    z_t, c_t, a_true, b_true = 2.4, 1.2, 0.35, 1.4
+    truth = np.array(dl, copy=True)
+    for q in range(len(sk["npix"])):
+        o, m = int(sk["offset"][q]), int(sk["npix"][q])
+        truth[o:o + m] += skewers.delta_s(seed + 1, q, m, cfg["dpix"], 1.8, 1.0)
+    g = truth + c_t * eta
+    F = np.exp(-a_true * np.exp(b_true * g))
+    fbar_t = float(F.mean())
+    ps, cnt = p1d.p1d(F, sk, [-1e30, 1e30], [fbar_t], k_edges, z_t, cfg["dpix"])
+    pk_t = np.where(cnt > 0, ps / np.maximum(cnt, 1), np.nan)
+    sg = float(g.std())
+    beff_t = tune_ps.effective_bias(a_true, b_true * sg, sg, cfg["f"] * c_t)
+    ok = np.isfinite(pk_t)
+    runs = {}
+    for no in (1, 3):
+        r = tune_ps.iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, cfg["dpix"], 1.0, 1.5, n_iter=4,
+                            sigf_t=float(F.std()), n_outer=no, beff_t=beff_t, f=cfg["f"])
+        runs[no] = (r, np.sqrt(np.mean((r["hist"][-1]["p1d"][ok] / pk_t[ok] - 1) ** 2)))
+    print("b_eff / target per outer step", ["%.4f" % (v / beff_t) for v in runs[3][0]["beff"]],
+          "P1D error one / three steps %.3f %.3f" % (runs[1][1], runs[3][1]))
+    assert len(runs[3][0]["beff"]) == 3
+    assert abs(runs[3][0]["beff"][-1] / beff_t - 1) < 3e-3
+    assert abs(runs[3][0]["beff"][-1] / beff_t - 1) < abs(runs[1][0]["beff"][-1] / beff_t - 1)
+    assert runs[3][1] < runs[1][1]
+    assert abs(runs[3][0]["hist"][-1]["fbar"] / fbar_t - 1) < 0.03
