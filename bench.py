@@ -521,6 +521,36 @@ def tune_ps_leg(L, torch, n_iter=10):
     tw = torch.empty(L.tune_ps_workspace_size(mock["n_sk"], mock["pixels"], nk), dtype=torch.uint8, device="cuda")
     res = L.tune_ps(spec, tw)
     M = L.TUNE_PS_MAX_ITER
+    # the outer loop, five steps, against the truth's effective bias: |b_F| of
+    # its (a, b) at its sigma_g (moments of the stored pixels plus the truth's
+    # delta_S variance) with beta = f c
+    d, e = mock["dens"].double(), mock["eta"].double()
+    sl2, se2 = float(d.var(unbiased=False)), float(e.var(unbiased=False))
+    cov = float(((d - d.mean()) * (e - e.mean())).mean())
+    kmax = np.pi / mid["dpix"]
+    kk = np.linspace(0.0, kmax, 200001)
+    ss2_true = float(np.trapezoid(1.6 * np.exp(-(kk / 1.1) ** 2), kk) / np.pi)
+    x = np.linspace(-12.0, 12.0, 48001)
+    wx = np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
+    beff_t = []
+    for a, b, c in zip(a_true, b_true, c_t):
+        sg = np.sqrt(sl2 + ss2_true + c * c * se2 + 2.0 * c * cov)
+        sv = b * sg
+        F = np.exp(-a * np.exp(sv * x))
+        bF = (a * sv / sg) * np.trapezoid(np.exp(sv * x) * F * wx, x) / np.trapezoid(F * wx, x)
+        beta = mid["f"] * c
+        beff_t.append(float(bF * np.sqrt(1.0 + 2.0 * beta / 3.0 + beta * beta / 5.0)))
+    spec.n_outer, spec.f = 5, mid["f"]
+    for i in range(len(z_t)):
+        spec.beff_t[i] = beff_t[i]
+    res5 = L.tune_ps(spec, tw)
+    MO = L.TUNE_PS_MAX_OUTER
+    outer = dict(steps=[res5.n_outer_done[i] for i in range(len(z_t))], seconds=res5.seconds,
+                 beff_over_target=[[res5.beff[i * MO + o] / beff_t[i] for o in range(res5.n_outer_done[i])]
+                                   for i in range(len(z_t))],
+                 a=list(res5.a[:len(z_t)]), b=list(res5.b[:len(z_t)]),
+                 fbar_last=[res5.fbar[i * M + n_iter - 1] for i in range(len(z_t))],
+                 p1d_rel_rms_last=[res5.rms[i * M + n_iter - 1] for i in range(len(z_t))])
     return dict(workload="P_s iteration, %d iterations at z_t=%s on the 512^3 mock (%d skewers, %d pixels); truth: "
                           "same delta_L and eta_par, delta_S with amplitude 1.6 and cut-off 1.1 h/Mpc (other key), "
                           "P_s start amplitude 1.0, cut-off 1.5" % (n_iter, list(z_t), mock["n_sk"], mock["pixels"]),
@@ -528,7 +558,7 @@ def tune_ps_leg(L, torch, n_iter=10):
                 b_truth=list(map(float, b_true)),
                 fbar_last=[res.fbar[i * M + n_iter - 1] for i in range(len(z_t))], fbar_target=list(map(float, fbar_t)),
                 p1d_rel_rms_first=[res.rms[i * M] for i in range(len(z_t))],
-                p1d_rel_rms_last=[res.rms[i * M + n_iter - 1] for i in range(len(z_t))])
+                p1d_rel_rms_last=[res.rms[i * M + n_iter - 1] for i in range(len(z_t))], outer_loop=outer)
 
 
 def tune_leg(L, torch, n_labels, train_steps):

@@ -328,10 +328,23 @@ int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, v
  *      finite and P1D > 0.
  * The result holds a, b and the ratios of the last iteration, its P1D, and
  * per iteration Fbar and the relative RMS P1D error over the bins with a
- * target.  Synchronous; GPU work on `stream`; errors in
- * lya_tune_ps_last_error().  (The paper's outer loop, which adjusts a and b
- * against the correlation-function bias, is not part of this call.) */
+ * target.
+ * The outer loop (n_outer >= 2; the paper adjusts a and b so that the bias
+ * its correlation-function prediction implies meets the target while Fbar
+ * stays, then iterates P_s again, five times): the prediction's flux bias is
+ * b_F = E[dF/dg]/Fbar = -(a s/sigma_g) E[e^{s x} F]/Fbar (the first term of
+ * the bivariate-Gaussian expansion of the flux correlation), beta = f c_t,
+ * and the effective bias |b_F| (1 + 2 beta/3 + beta^2/5)^(1/2); each outer
+ * step after the first takes sigma_g from the current ratios, solves (a, s)
+ * for Fbar = fbar_t and the effective bias = beff_t[z], and runs the n_iter
+ * iterations again from the current ratios.  A target the current sigma_g
+ * cannot reach (at fixed Fbar the bias tends to phi(x_0)/(sigma_g Fbar) as s
+ * grows) ends the outer loop early; n_outer_done[z] counts the steps run and
+ * beff[z][o] is the effective bias after step o (sigma_g of its last
+ * iteration).  fbar and rms then describe the last step's iterations.
+ * Synchronous; GPU work on `stream`; errors in lya_tune_ps_last_error(). */
 #define LYA_TUNE_PS_MAX_ITER 16
+#define LYA_TUNE_PS_MAX_OUTER 8
 typedef struct {
   const lya_skewers* sk;     /* npix, offset, chi0, dchi, id_base used */
   const float* dens_l;       /* device: delta_L per pixel (no delta_S) */
@@ -345,6 +358,9 @@ typedef struct {
   lya_p1d_spec p1d;          /* k bins (device edges, s/km) and dpix; z_ref is z_t */
   double ps_amp, ps_kcut;    /* P_s^0 */
   int32_t n_iter;            /* 1..16 (the paper uses 10) */
+  int32_t n_outer;           /* 0 or 1: no outer loop; up to 8 (the paper uses 5) */
+  double beff_t[LYA_TUNE_MAX_Z];  /* outer loop: target effective bias per z_t (> 0) */
+  double f;                  /* outer loop: growth rate of the boxes' eta_par (beta = f c_t) */
 } lya_tune_ps_spec;
 
 typedef struct {
@@ -355,6 +371,8 @@ typedef struct {
   double fbar[LYA_TUNE_MAX_Z * LYA_TUNE_PS_MAX_ITER];  /* [z_t][iteration] */
   double rms[LYA_TUNE_MAX_Z * LYA_TUNE_PS_MAX_ITER];   /* [z_t][iteration] */
   double seconds;
+  double beff[LYA_TUNE_MAX_Z * LYA_TUNE_PS_MAX_OUTER]; /* [z_t][outer step] */
+  int32_t n_outer_done[LYA_TUNE_MAX_Z];
 } lya_tune_ps_result;
 
 size_t lya_tune_ps_workspace_size(int64_t n_sk, int64_t n_pixels, int32_t n_kbins);

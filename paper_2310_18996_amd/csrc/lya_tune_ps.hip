@@ -3,7 +3,9 @@
 // mean flux and flux dispersion of a Gaussian g, sigma_g from the moments of
 // the stored pixels and the current P_s, then repeatedly: delta_S redrawn
 // with P_s (lya_apply_fgpa_ds), Fbar and P1D measured (lya_p1d), and P_s
-// multiplied per k bin by P_target / P1D.
+// multiplied per k bin by P_target / P1D.  The outer loop re-solves (a, s)
+// for Fbar and the target effective bias of the correlation-function
+// prediction, then runs the iteration again.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -94,38 +96,45 @@ PsCarve carve_ps(int64_t n_sk, int64_t n_pix, int nk) {
   return c;
 }
 
-// F = exp(-a exp(s x)), x a unit normal: mean and dispersion by the
-// trapezoid rule on [-12, 12] (the Gaussian weight makes it converge
-// geometrically; 4800 intervals leave ~1e-15).
-void gauss_flux(double a, double s, double* f1, double* sf) {
+// F = exp(-a exp(s x)), x a unit normal: mean and dispersion, and
+// E[e^{s x} F] (the flux bias), by the trapezoid rule on [-12, 12] (the
+// Gaussian weight makes it converge geometrically; 4800 intervals leave
+// ~1e-15).
+void gauss_flux(double a, double s, double* f1, double* sf, double* mb = nullptr) {
   const int n = 4800;
   const double h = 24.0 / n;
-  double m1 = 0.0, m2 = 0.0;
+  double m1 = 0.0, m2 = 0.0, m3 = 0.0;
   for (int i = 0; i <= n; ++i) {
     const double x = -12.0 + i * h;
     const double w = (i == 0 || i == n ? 0.5 : 1.0) * exp(-0.5 * x * x);
-    const double F = exp(-a * exp(s * x));
+    const double e = exp(s * x);
+    const double F = exp(-a * e);
     m1 += w * F;
     m2 += w * F * F;
+    m3 += w * exp(s * x - a * e);
   }
   const double norm = h / sqrt(2.0 * M_PI);
   m1 *= norm;
   m2 *= norm;
   *f1 = m1;
   *sf = sqrt(m2 - m1 * m1 > 0.0 ? m2 - m1 * m1 : 0.0);
+  if (mb) *mb = m3 * norm;
 }
 
-// (a, s) with gauss_flux = (fbar_t, sigf_t): damped Newton in (ln a, ln s).
-bool fit_a_s(double fbar_t, double sigf_t, double* a, double* s) {
-  double t[2] = {log(0.3), log(0.5)};
-  auto resid = [&](const double* u, double* r) {
-    double f1, sf;
-    gauss_flux(exp(u[0]), exp(u[1]), &f1, &sf);
-    if (!(f1 > 0.0) || !(sf > 0.0)) return false;
-    r[0] = log(f1 / fbar_t);
-    r[1] = log(sf / sigf_t);
-    return true;
-  };
+// Effective bias of the correlation-function prediction: |b_F| (1 + 2 beta/3
+// + beta^2/5)^(1/2), b_F = E[dF/dg] / Fbar = -(a s / sigma_g) E[e^{s x} F] / Fbar.
+double effective_bias(double a, double s, double sigma_g, double beta, double* fbar) {
+  double f1, sf, mb;
+  gauss_flux(a, s, &f1, &sf, &mb);
+  if (fbar) *fbar = f1;
+  return (a * s / sigma_g) * mb / f1 * sqrt(1.0 + 2.0 * beta / 3.0 + beta * beta / 5.0);
+}
+
+// Damped Newton in t = (ln a, ln s) on two residuals; true when both end
+// below 1e-9.
+template <typename R>
+bool newton2(R resid, double* a, double* s) {
+  double t[2] = {log(*a), log(*s)};
   double r[2];
   if (!resid(t, r)) return false;
   for (int it = 0; it < 200; ++it) {
@@ -163,6 +172,38 @@ bool fit_a_s(double fbar_t, double sigf_t, double* a, double* s) {
   *a = exp(t[0]);
   *s = exp(t[1]);
   return true;
+}
+
+// (a, s) with gauss_flux = (fbar_t, sigf_t), from (0.3, 0.5).
+bool fit_a_s(double fbar_t, double sigf_t, double* a, double* s) {
+  *a = 0.3;
+  *s = 0.5;
+  return newton2(
+      [&](const double* u, double* r) {
+        double f1, sf;
+        gauss_flux(exp(u[0]), exp(u[1]), &f1, &sf);
+        if (!(f1 > 0.0) || !(sf > 0.0)) return false;
+        r[0] = log(f1 / fbar_t);
+        r[1] = log(sf / sigf_t);
+        return true;
+      },
+      a, s);
+}
+
+// (a, s) with Fbar = fbar_t and the effective bias = beff_t at sigma_g, from
+// the given (a, s); false when no solution is found (a target beyond the
+// bias the step limit allows).
+bool fit_a_s_bias(double fbar_t, double beff_t, double sigma_g, double beta, double* a, double* s) {
+  return newton2(
+      [&](const double* u, double* r) {
+        double f1;
+        const double be = effective_bias(exp(u[0]), exp(u[1]), sigma_g, beta, &f1);
+        if (!(f1 > 0.0) || !(be > 0.0) || !isfinite(be)) return false;
+        r[0] = log(f1 / fbar_t);
+        r[1] = log(be / beff_t);
+        return true;
+      },
+      a, s);
 }
 
 // (1/pi) int_0^{pi/dpix} amp exp(-(k/kcut)^2) r(k) dk, r piecewise constant
@@ -217,6 +258,13 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
   if (nk < 1 || nk > kMaxKBins || !spec->p1d.k_edges || !spec->p1d_t)
     return pfail(LYA_EINVAL, "P1D bins (1..64 with edges) and targets are required");
   if (spec->n_iter < 1 || spec->n_iter > LYA_TUNE_PS_MAX_ITER) return pfail(LYA_EINVAL, "n_iter must be in [1, 16]");
+  if (spec->n_outer < 0 || spec->n_outer > LYA_TUNE_PS_MAX_OUTER) return pfail(LYA_EINVAL, "n_outer must be in [0, 8]");
+  const int n_outer = spec->n_outer < 1 ? 1 : spec->n_outer;
+  if (n_outer > 1) {
+    if (!(spec->f > 0.0)) return pfail(LYA_EINVAL, "the outer loop needs f > 0");
+    for (int z = 0; z < spec->n_zt; ++z)
+      if (!(spec->beff_t[z] > 0.0)) return pfail(LYA_EINVAL, "the outer loop needs beff_t > 0 at every z_t");
+  }
   if (!(spec->ps_amp > 0.0) || !(spec->ps_kcut > 0.0) || !(spec->p1d.dpix > 0.0))
     return pfail(LYA_EINVAL, "P_s^0 amplitude, cut-off and dpix must be positive");
   if (sk->n_sk < 1 || !sk->npix || !sk->offset || !sk->chi0 || !spec->dens_l || !spec->eta)
@@ -293,6 +341,19 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
     std::vector<double> psum(nk);
     std::vector<int64_t> pcnt(nk);
     double fbar = 0.0, b_used = 0.0;
+    const double beta = spec->f * ct;
+    int done = 0;
+    for (int o = 0; o < n_outer; ++o) {
+    if (o > 0) {
+      // re-solve (a, s) for Fbar and the target effective bias at the
+      // sigma_g of the current ratios
+      const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
+      const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
+      double a2 = a, s2 = s;
+      if (!(sg2 > 0.0) || !fit_a_s_bias(ft, spec->beff_t[z], sqrt(sg2), beta, &a2, &s2)) break;
+      a = a2;
+      s = s2;
+    }
     for (int it = 0; it < spec->n_iter; ++it) {
       const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
       const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
@@ -351,6 +412,10 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
         if (isfinite(pt[b]) && isfinite(p) && p > 0.0) ratio[b] *= pt[b] / p;
       }
     }
+    res->beff[z * LYA_TUNE_PS_MAX_OUTER + o] = effective_bias(a, s, s / b_used, beta, nullptr);
+    done = o + 1;
+    }
+    res->n_outer_done[z] = done;
     res->a[z] = a;
     res->b[z] = b_used;
     res->s[z] = s;

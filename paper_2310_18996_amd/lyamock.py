@@ -304,6 +304,7 @@ class TuneResult(ctypes.Structure):
 
 
 TUNE_PS_MAX_ITER = 16
+TUNE_PS_MAX_OUTER = 8
 
 
 class PsTable(ctypes.Structure):
@@ -316,7 +317,8 @@ class TunePsSpec(ctypes.Structure):
                 ("z_t", ctypes.c_double * TUNE_MAX_Z), ("c_t", ctypes.c_double * TUNE_MAX_Z),
                 ("fbar_t", ctypes.c_double * TUNE_MAX_Z), ("sigf_t", ctypes.c_double * TUNE_MAX_Z),
                 ("p1d_t", ctypes.c_void_p), ("p1d", P1dSpec), ("ps_amp", ctypes.c_double),
-                ("ps_kcut", ctypes.c_double), ("n_iter", ctypes.c_int32)]
+                ("ps_kcut", ctypes.c_double), ("n_iter", ctypes.c_int32), ("n_outer", ctypes.c_int32),
+                ("beff_t", ctypes.c_double * TUNE_MAX_Z), ("f", ctypes.c_double)]
 
 
 class TunePsResult(ctypes.Structure):
@@ -324,7 +326,9 @@ class TunePsResult(ctypes.Structure):
                 ("s", ctypes.c_double * TUNE_MAX_Z), ("sigma2", ctypes.c_double * 3),
                 ("ratio", ctypes.c_double * (TUNE_MAX_Z * 64)), ("p1d", ctypes.c_double * (TUNE_MAX_Z * 64)),
                 ("fbar", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)),
-                ("rms", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)), ("seconds", ctypes.c_double)]
+                ("rms", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)), ("seconds", ctypes.c_double),
+                ("beff", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_OUTER)),
+                ("n_outer_done", ctypes.c_int32 * TUNE_MAX_Z)]
 
 
 FFT_VARIANTS = 14

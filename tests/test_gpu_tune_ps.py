@@ -41,8 +41,11 @@ def mock():
     fbar_t = float(F.mean())
     ps, cnt = p1d.p1d(F, sk, [-1e30, 1e30], [fbar_t], k_edges, z_t, cfg["dpix"])
     pk_t = np.where(cnt > 0, ps / np.maximum(cnt, 1), np.nan)
+    g = truth + c_t * eta
+    sg = float(g.std())
+    beff_t = tune_ps.effective_bias(0.35, 1.4 * sg, sg, cfg["f"] * c_t)
     return dict(cfg=cfg, sk=sk, dl=dl, eta=eta, k_edges=k_edges, z_t=z_t, c_t=c_t, fbar_t=fbar_t, pk_t=pk_t,
-                sigf_t=float(F.std()))
+                sigf_t=float(F.std()), beff_t=beff_t)
 
 
 def _dev(torch, x, dtype):
@@ -131,5 +134,54 @@ def test_tune_ps_rejects_bad_input(L, mock):
     import torch
     spec = L.TunePsSpec()
     work = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.LyaError):
+        L.tune_ps(spec, work)
+
+
+def test_tune_ps_outer_loop_matches_oracle(L, mock):
+    # three outer steps (the bias-matched re-solve of (a, s) between P_s runs)
+    import torch
+    cfg, sk = mock["cfg"], mock["sk"]
+    s, keep = skewer_tensors(L, sk)
+    k_edges = mock["k_edges"]
+    nk = len(k_edges) - 1
+    dl, eta = _dev(torch, mock["dl"], np.float32), _dev(torch, mock["eta"], np.float32)
+    ke = _dev(torch, k_edges, np.float64)
+    n_iter, n_outer = 3, 3
+    spec = L.TunePsSpec()
+    spec.sk = ctypes_pointer(L, s)
+    spec.dens_l, spec.eta = dl.data_ptr(), eta.data_ptr()
+    spec.n_pixels = int(sk["total"])
+    spec.cosmo = L.Cosmo(0.3147)
+    spec.seed = cfg["seed"]
+    spec.n_zt = 1
+    spec.z_t[0], spec.c_t[0], spec.fbar_t[0] = mock["z_t"], mock["c_t"], mock["fbar_t"]
+    spec.sigf_t[0] = mock["sigf_t"]
+    pk_t = np.ascontiguousarray(mock["pk_t"], dtype=np.float64)
+    spec.p1d_t = pk_t.ctypes.data
+    spec.p1d = L.P1dSpec(nk, ke.data_ptr(), mock["z_t"], cfg["dpix"])
+    spec.ps_amp, spec.ps_kcut, spec.n_iter = 1.0, 1.5, n_iter
+    spec.n_outer, spec.f = n_outer, cfg["f"]
+    spec.beff_t[0] = mock["beff_t"]
+    work = torch.empty(L.tune_ps_workspace_size(len(sk["npix"]), sk["total"], nk), dtype=torch.uint8, device="cuda")
+    res = L.tune_ps(spec, work)
+    ref = tune_ps.iterate(mock["dl"], mock["eta"], sk, cfg["seed"], mock["z_t"], mock["c_t"], mock["fbar_t"], pk_t,
+                          k_edges, cfg["dpix"], 1.0, 1.5, n_iter=n_iter, sigf_t=mock["sigf_t"], n_outer=n_outer,
+                          beff_t=mock["beff_t"], f=cfg["f"])
+    got_beff = [res.beff[o] for o in range(res.n_outer_done[0])]
+    print("outer loop: steps %d; b_eff / target %s (oracle %s); a %.6f b %.6f (oracle %.6f %.6f)"
+          % (res.n_outer_done[0], ["%.5f" % (v / mock["beff_t"]) for v in got_beff],
+             ["%.5f" % (v / mock["beff_t"]) for v in ref["beff"]], res.a[0], res.b[0], ref["a"], ref["b"]),
+          flush=True)
+    assert res.n_outer_done[0] == len(ref["beff"]) == n_outer
+    np.testing.assert_allclose(got_beff, ref["beff"], rtol=1e-5)
+    np.testing.assert_allclose([res.a[0], res.s[0], res.b[0]], [ref["a"], ref["s"], ref["b"]], rtol=1e-5)
+    fb = [res.fbar[i] for i in range(n_iter)]
+    np.testing.assert_allclose(fb, [h["fbar"] for h in ref["hist"]], rtol=TOL)
+    # an unreachable target ends the outer loop after the first step
+    spec.beff_t[0] = 10.0 * mock["beff_t"]
+    res2 = L.tune_ps(spec, work)
+    assert res2.n_outer_done[0] == 1
+    spec.beff_t[0] = 0.0
     with pytest.raises(L.LyaError):
         L.tune_ps(spec, work)
