@@ -344,76 +344,76 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
     const double beta = spec->f * ct;
     int done = 0;
     for (int o = 0; o < n_outer; ++o) {
-    if (o > 0) {
-      // re-solve (a, s) for Fbar and the target effective bias at the
-      // sigma_g of the current ratios
-      const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
-      const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
-      double a2 = a, s2 = s;
-      if (!(sg2 > 0.0) || !fit_a_s_bias(ft, spec->beff_t[z], sqrt(sg2), beta, &a2, &s2)) break;
-      a = a2;
-      s = s2;
-    }
-    for (int it = 0; it < spec->n_iter; ++it) {
-      const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
-      const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
-      if (!(sg2 > 0.0)) return pfail(LYA_EINVAL, "sigma_g^2 is not positive");
-      b_used = s / sqrt(sg2);
-      for (int b = 0; b < nk; ++b) ratio32[b] = static_cast<float>(ratio[b]);
-      if ((e = hipMemcpyAsync(d_ratio, ratio32.data(), sizeof(float) * nk, hipMemcpyHostToDevice, st)) !=
-              hipSuccess ||
-          (e = hipMemcpyAsync(d_edges, ek.data(), sizeof(double) * (nk + 1), hipMemcpyHostToDevice, st)) !=
-              hipSuccess ||
-          (e = hipMemcpyAsync(d_zb, zb_edges, sizeof(zb_edges), hipMemcpyHostToDevice, st)) != hipSuccess)
-        return phip(e, "table upload");
-      lya_fgpa fg{};
-      fg.coef[0][0] = a;
-      fg.coef[1][0] = b_used;
-      fg.coef[2][0] = ct;
-      int rc = lya_apply_fgpa_ds(sk, &spec->cosmo, spec->dens_l, spec->eta, &ps, &tab, spec->seed, &fg, flux, &zb,
-                                 w + c.sk, c.p1d - c.sk, stream);
-      if (rc != LYA_OK) {
-        snprintf(g_perr, sizeof(g_perr), "lya_apply_fgpa_ds: %s", lya_last_error());
-        return rc;
+      if (o > 0) {
+        // re-solve (a, s) for Fbar and the target effective bias at the
+        // sigma_g of the current ratios
+        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
+        const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
+        double a2 = a, s2 = s;
+        if (!(sg2 > 0.0) || !fit_a_s_bias(ft, spec->beff_t[z], sqrt(sg2), beta, &a2, &s2)) break;
+        a = a2;
+        s = s2;
       }
-      lya_p1d_spec pspec = spec->p1d;
-      pspec.z_ref = zt;
-      rc = lya_p1d(sk, &spec->cosmo, flux, &zb, &pspec, d_psum, d_pcnt, w + c.p1d, c.flux - c.p1d, stream);
-      if (rc != LYA_OK) {
-        snprintf(g_perr, sizeof(g_perr), "lya_p1d: %s", lya_last_error());
-        return rc;
-      }
-      double zsum[2];
-      if ((e = hipMemcpyAsync(zsum, d_zb + 2, sizeof(zsum), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-          (e = hipMemcpyAsync(psum.data(), d_psum, sizeof(double) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-          (e = hipMemcpyAsync(pcnt.data(), d_pcnt, sizeof(int64_t) * nk, hipMemcpyDeviceToHost, st)) !=
-              hipSuccess ||
-          (e = hipStreamSynchronize(st)) != hipSuccess)
-        return phip(e, "statistics read-back");
-      int64_t count;
-      memcpy(&count, &zsum[1], sizeof(count));
-      fbar = count > 0 ? zsum[0] / static_cast<double>(count) : NAN;
-      double se = 0.0;
-      int ne = 0;
-      for (int b = 0; b < nk; ++b) {
-        const double p = pcnt[b] > 0 ? psum[b] / static_cast<double>(pcnt[b]) : NAN;
-        res->p1d[z * 64 + b] = p;
-        res->ratio[z * 64 + b] = ratio[b];
-        if (isfinite(pt[b]) && isfinite(p) && pt[b] != 0.0) {
-          se += (p / pt[b] - 1.0) * (p / pt[b] - 1.0);
-          ++ne;
+      for (int it = 0; it < spec->n_iter; ++it) {
+        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
+        const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
+        if (!(sg2 > 0.0)) return pfail(LYA_EINVAL, "sigma_g^2 is not positive");
+        b_used = s / sqrt(sg2);
+        for (int b = 0; b < nk; ++b) ratio32[b] = static_cast<float>(ratio[b]);
+        if ((e = hipMemcpyAsync(d_ratio, ratio32.data(), sizeof(float) * nk, hipMemcpyHostToDevice, st)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(d_edges, ek.data(), sizeof(double) * (nk + 1), hipMemcpyHostToDevice, st)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(d_zb, zb_edges, sizeof(zb_edges), hipMemcpyHostToDevice, st)) != hipSuccess)
+          return phip(e, "table upload");
+        lya_fgpa fg{};
+        fg.coef[0][0] = a;
+        fg.coef[1][0] = b_used;
+        fg.coef[2][0] = ct;
+        int rc = lya_apply_fgpa_ds(sk, &spec->cosmo, spec->dens_l, spec->eta, &ps, &tab, spec->seed, &fg, flux, &zb,
+                                   w + c.sk, c.p1d - c.sk, stream);
+        if (rc != LYA_OK) {
+          snprintf(g_perr, sizeof(g_perr), "lya_apply_fgpa_ds: %s", lya_last_error());
+          return rc;
+        }
+        lya_p1d_spec pspec = spec->p1d;
+        pspec.z_ref = zt;
+        rc = lya_p1d(sk, &spec->cosmo, flux, &zb, &pspec, d_psum, d_pcnt, w + c.p1d, c.flux - c.p1d, stream);
+        if (rc != LYA_OK) {
+          snprintf(g_perr, sizeof(g_perr), "lya_p1d: %s", lya_last_error());
+          return rc;
+        }
+        double zsum[2];
+        if ((e = hipMemcpyAsync(zsum, d_zb + 2, sizeof(zsum), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(psum.data(), d_psum, sizeof(double) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(pcnt.data(), d_pcnt, sizeof(int64_t) * nk, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+          return phip(e, "statistics read-back");
+        int64_t count;
+        memcpy(&count, &zsum[1], sizeof(count));
+        fbar = count > 0 ? zsum[0] / static_cast<double>(count) : NAN;
+        double se = 0.0;
+        int ne = 0;
+        for (int b = 0; b < nk; ++b) {
+          const double p = pcnt[b] > 0 ? psum[b] / static_cast<double>(pcnt[b]) : NAN;
+          res->p1d[z * 64 + b] = p;
+          res->ratio[z * 64 + b] = ratio[b];
+          if (isfinite(pt[b]) && isfinite(p) && pt[b] != 0.0) {
+            se += (p / pt[b] - 1.0) * (p / pt[b] - 1.0);
+            ++ne;
+          }
+        }
+        res->fbar[z * LYA_TUNE_PS_MAX_ITER + it] = fbar;
+        res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = ne ? sqrt(se / ne) : NAN;
+        // P_s^{n+1} = P_s^n P_target / P1D in every bin with both values
+        for (int b = 0; b < nk; ++b) {
+          const double p = res->p1d[z * 64 + b];
+          if (isfinite(pt[b]) && isfinite(p) && p > 0.0) ratio[b] *= pt[b] / p;
         }
       }
-      res->fbar[z * LYA_TUNE_PS_MAX_ITER + it] = fbar;
-      res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = ne ? sqrt(se / ne) : NAN;
-      // P_s^{n+1} = P_s^n P_target / P1D in every bin with both values
-      for (int b = 0; b < nk; ++b) {
-        const double p = res->p1d[z * 64 + b];
-        if (isfinite(pt[b]) && isfinite(p) && p > 0.0) ratio[b] *= pt[b] / p;
-      }
-    }
-    res->beff[z * LYA_TUNE_PS_MAX_OUTER + o] = effective_bias(a, s, s / b_used, beta, nullptr);
-    done = o + 1;
+      res->beff[z * LYA_TUNE_PS_MAX_OUTER + o] = effective_bias(a, s, s / b_used, beta, nullptr);
+      done = o + 1;
     }
     res->n_outer_done[z] = done;
     res->a[z] = a;
