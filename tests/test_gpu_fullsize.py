@@ -6,6 +6,8 @@ value comes from the FP64 oracle alone; no GPU output is fed to it.
 * 2048^3 skewer stage on a 10,000-skewer subset of the 1M-skewer table, on a
   single-shell box (the only_n2 test hook, |n|^2 = 10003: 288 modes), whose
   field the oracle evaluates exactly at every voxel by direct summation.
+* The 7^3 Gaussian-kernel pass over the whole 1M-skewer table on that box,
+  150 sampled skewers against the oracle's kernel average.
 * 1024^3 precision configuration: FP32 against BF16 storage of {delta,
   eta_par}, each against the oracle: z-lines, and the pixels, flux, mean flux
   per redshift bin and P1D of eight skewers of the 200,000-skewer table whose
@@ -182,6 +184,88 @@ def test_big_skewer_subset_on_a_single_shell_box(L):
     fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
     np.testing.assert_array_equal(out["count"], cnt)
     assert bin_sums_close(out["fsum"], fs, cnt)
+    del fld
+    torch.cuda.empty_cache()
+
+
+class VoxelCache:
+    """Grid lookups from a table of voxel values: a first oracle pass with
+    record=True collects the voxels it asks for (answering zeros), then
+    fill() evaluates them once on the backing grid and later passes read the
+    table."""
+
+    def __init__(self, backing):
+        self.backing, self.n, self.shape = backing, backing.n, backing.shape
+        self.record, self.keys, self.seen = True, None, []
+
+    def __getitem__(self, idx):
+        a, b, c = (np.asarray(i, dtype=np.int64) for i in idx)
+        key = (a * self.n + b) * self.n + c
+        if self.record:
+            self.seen.append(np.unique(key))
+            return np.zeros(key.shape, dtype=np.complex128)
+        return self.vals[np.searchsorted(self.keys, key)]
+
+    def fill(self):
+        self.keys = np.unique(np.concatenate(self.seen))
+        ua, rest = np.divmod(self.keys, self.n * self.n)
+        ub, uc = np.divmod(rest, self.n)
+        self.vals = self.backing[ua, ub, uc]
+        self.record, self.seen = False, []
+
+
+@pytest.mark.timeout(600)
+def test_big_gauss_kernel_on_a_single_shell_box(L):
+    """lya_draw_skewers_gauss in the configuration the benchmark times (the
+    2048^3 box, the whole 1M-skewer table in one launch, FGPA and bins fused)
+    on a single-shell box; 150 sampled skewers against the oracle's 7^3
+    Gaussian-kernel average of the shell's direct sum, plus delta_S and FGPA."""
+    import torch
+    cfg = mockinputs.config("big")
+    n = cfg["n"]
+    pk = dict(cfg["pk"], sigma8=SHELL_SIGMA8)
+    print("2048^3 single-shell box, Gaussian-kernel pass over the 1M table", flush=True)
+    box, fld = make_box(L, torch, cfg, L.LYA_F32, sigma8=SHELL_SIGMA8, only_n2=SHELL)
+    sk = mockinputs.skewer_table(cfg)
+    s, keep = skewer_tensors(L, sk)
+    tot = sk["total"]
+    d, e, f = (torch.full((tot,), float("nan"), dtype=torch.float32, device="cuda") for _ in range(3))
+    edges = fgpa.chi_edges_for_z(cfg["z_edges"])
+    ed = torch.from_numpy(edges).cuda()
+    fs = torch.zeros(len(edges) - 1, dtype=torch.float64, device="cuda")
+    cn = torch.zeros(len(edges) - 1, dtype=torch.int64, device="cuda")
+    work = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+    L.draw_skewers_gauss(box, fld, s, L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0), cfg["seed"],
+                         L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"]), d, e, f, L.zbins_struct(ed, fs, cn),
+                         work)
+    torch.cuda.synchronize()
+    # every pixel written, bins count every pixel of the table in range
+    assert not bool(torch.isnan(d).any()) and not bool(torch.isnan(f).any())
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(len(sk["npix"]), size=150, replace=False))
+    sub = subset(sk, idx)
+    pix = np.concatenate([np.arange(int(sk["offset"][q]), int(sk["offset"][q]) + int(sk["npix"][q])) for q in idx])
+    pt = torch.from_numpy(pix).cuda()
+    got = {k: v.index_select(0, pt).cpu().numpy().astype(np.float64) for k, v in (("dens", d), ("eta", e), ("flux", f))}
+    del d, e, f, work
+    tab = power.amplitude_table(power.PowerSpectrum(**pk), n, cfg["dx"])
+    freqs, coef = field.shell_modes(n, cfg["seed"], tab, SHELL)
+    grid = VoxelCache(ShellGrid(n, freqs, coef))
+    pos = all_positions(sub)
+    skewers.gauss7(grid, pos)
+    grid.fill()
+    print("oracle: %d pixels, %d voxels, %d modes" % (len(pos), len(grid.keys), len(freqs)), flush=True)
+    v = skewers.gauss7(grid, pos)
+    rd, re_ = v.real.copy(), v.imag.copy()
+    for j, q in enumerate(idx):
+        o, nq = int(sub["offset"][j]), int(sub["npix"][j])
+        rd[o:o + nq] += skewers.delta_s(cfg["seed"], int(q), nq, cfg["dpix"], cfg["ps_amp"], cfg["ps_kcut"])
+    rf, _ = fgpa.apply_fgpa(rd, re_, sub, cfg["fgpa"])
+    err = dict(dens=rel_rms(got["dens"], rd), eta=rel_rms(got["eta"], re_), flux=rel_rms(got["flux"], rf))
+    print("150 skewers (%d pixels): rel rms" % len(pos), {k: "%.2e" % x for k, x in err.items()}, flush=True)
+    assert all(x < TOL for x in err.values()), err
+    _, all_cnt = fgpa.mean_flux_bins(np.zeros(tot), fgpa.pixel_chi(sk), edges)
+    np.testing.assert_array_equal(cn.cpu().numpy(), all_cnt)
     del fld
     torch.cuda.empty_cache()
 
