@@ -63,9 +63,8 @@ __device__ __forceinline__ float2 ld_wide(const SkewerArgs& a, int k, size_t i) 
   return unpack_bf16x2(a.wide_bf16[k][i]);
 }
 
-// Mode Y_m of the small-scale spectrum (0 < m <= ns/2).
-__device__ __forceinline__ float2 ps_mode(const SkewerArgs& a, uint64_t qid, int m, int ns, float amp_scale,
-                                          float dk2) {
+// Mode Y_m of the small-scale spectrum (0 < m <= ns/2) from its normal pair z.
+__device__ __forceinline__ float2 ps_mode(const SkewerArgs& a, int m, int ns, float amp_scale, float dk2, float2 z) {
   const float kk = static_cast<float>(m) * static_cast<float>(m) * dk2;   // (k/kcut)^2
   float ratio = 1.0f;
   if (a.ps_ratio) {
@@ -87,7 +86,6 @@ __device__ __forceinline__ float2 ps_mode(const SkewerArgs& a, uint64_t qid, int
     ratio = a.ps_ratio[b];
   }
   const float amp = __builtin_amdgcn_sqrtf(amp_scale * __expf(-kk) * ratio);
-  const float2 z = normal_pair(a.seed, 1u, (qid << 33) + static_cast<uint64_t>(m));
   float2 w = (m == ns / 2) ? make_float2(z.x, 0.0f) : make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
   if (a.ps_fixed_amp) {
     const float r = rsqrtf(w.x * w.x + w.y * w.y);
@@ -105,15 +103,28 @@ __device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, floa
   const double dk = 2.0 * M_PI / (ns * a.dpix) / a.ps_kcut;
   const float dk2 = static_cast<float>(dk * dk);
   const int twstep = kTw2048 / ns;  // w^k = exp(2 pi i k / ns)
-  // Z_k = (Y_k + Y_{k+M}) + i (Y_k - Y_{k+M}) w^k with Y_{k+M} = conj(Y_{M-k})
+  // the modes Y_1 .. Y_M into buf (Y_M in slot 0: the DC mode is zero).  Mode
+  // m is linear index (qid << 33) + m of stream 1, so the modes 2i and 2i + 1
+  // share one Philox call (counter = linear index >> 1, words 0-1 and 2-3).
+  for (int i = lane; i <= M / 2; i += 64) {
+    const uint64_t ctr = ((qid << 33) + 2 * static_cast<uint64_t>(i)) >> 1;
+    const uint4 wd = philox10_x3(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 1u, 0u),
+                                 static_cast<uint32_t>(a.seed), static_cast<uint32_t>(a.seed >> 32));
+    const int m0 = 2 * i, m1 = 2 * i + 1;
+    if (m0 >= 1 && m0 <= M) buf[pidx(m0 == M ? 0 : m0)] = ps_mode(a, m0, ns, amp_scale, dk2, box_muller(wd.x, wd.y));
+    if (m1 <= M) buf[pidx(m1 == M ? 0 : m1)] = ps_mode(a, m1, ns, amp_scale, dk2, box_muller(wd.z, wd.w));
+  }
+  wave_sync();
+  // Z_k = (Y_k + Y_{k+M}) + i (Y_k - Y_{k+M}) w^k with Y_{k+M} = conj(Y_{M-k});
+  // a lane reads both of its slots k and M - k before writing them
   for (int k = lane; k <= M / 2; k += 64) {
     if (k == 0) {
-      const float2 yM = ps_mode(a, qid, M, ns, amp_scale, dk2);  // real Nyquist mode
+      const float2 yM = buf[pidx(0)];  // real Nyquist mode
       buf[pidx(0)] = make_float2(yM.x, -yM.x);
       continue;
     }
-    const float2 yk = ps_mode(a, qid, k, ns, amp_scale, dk2);
-    const float2 ymk = (M - k == k) ? yk : ps_mode(a, qid, M - k, ns, amp_scale, dk2);
+    const float2 yk = buf[pidx(k)];
+    const float2 ymk = buf[pidx(M - k)];
     {
       const float2 s = make_float2(yk.x + ymk.x, yk.y - ymk.y);   // Y_k + conj(Y_{M-k})
       const float2 d = make_float2(yk.x - ymk.x, yk.y + ymk.y);   // Y_k - conj(Y_{M-k})
