@@ -299,7 +299,9 @@ __global__ void __launch_bounds__(kQsoBlock) k_qso_draw(QsoDrawArgs a) {
   // the largest density, raised by a margin over the rounding of the
   // interpolation between two nodes
   float nb_top = 0.0f;
-  for (int i = 0; i < a.n_nbar; ++i) nb_top = fmaxf(nb_top, snb[i]);
+  for (int i = static_cast<int>(threadIdx.x & 63); i < a.n_nbar; i += 64) nb_top = fmaxf(nb_top, snb[i]);
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) nb_top = fmaxf(nb_top, __shfl_xor(nb_top, w));  // over the wave
   nb_top *= 1.0f + 1.0e-6f;
 
   bool sel[VPT];
