@@ -85,11 +85,13 @@ typedef struct {
   int64_t n_sk;              /* number of skewers (>= 0) */
   const int64_t* origin_fx;  /* device [n_sk][3] */
   const int64_t* step_fx;    /* device [n_sk][3] */
-  const int32_t* npix;       /* device [n_sk], 0 <= npix <= 2048 */
+  const int32_t* npix;       /* device [n_sk], 0 <= npix <= 2048 (drawing delta_S on a longer
+                                skewer is an input error: NaN in its outputs, none in the bins) */
   const int64_t* offset;     /* device [n_sk] */
   const double* chi0;        /* device [n_sk], Mpc/h */
   double dchi;               /* pixel length in Mpc/h (the paper: 0.2) */
-  int64_t id_base;           /* quasar id of row 0: seeds its small-scale field */
+  int64_t id_base;           /* quasar id of row 0: seeds its small-scale field;
+                                0 <= id_base, n_sk + id_base <= 2^31 */
 } lya_skewers;
 
 /* Small-scale 1D spectrum of delta_S (section "Gaussian fields along lines of
@@ -272,8 +274,11 @@ int lya_p1d(const lya_skewers* sk, const lya_cosmo* cosmo, const float* flux, co
  * correction takes a Broyden update so that it also reproduces the previous
  * GPU evaluation; the next search starts there.  Points outside the
  * emulator's (a, b) input range are rejected.  It stops when a search moves
- * the point by at most max(10 xatol, 5e-4) or after emu_checks GPU
- * evaluations; the result holds the last GPU evaluation.  a(z), b(z), c(z)
+ * the point by at most max(10 xatol, 5e-4) from the previous GPU evaluation;
+ * the result then holds the last GPU evaluation.  When no search has settled
+ * after emu_checks GPU evaluations (an emulator trained poorly or used outside
+ * its range; always when emu_checks is 1), the plain loop takes over from the
+ * last point evaluated on the GPU and fallback[z_t] is set.  a(z), b(z), c(z)
  * are then least-squares quadratics in (1+z) (n_zt >= 3; the line through
  * two points, a constant for one).  Synchronous (reads back the
  * statistics of every evaluation); all GPU work runs on `stream`. */
@@ -304,6 +309,7 @@ typedef struct {
   int32_t gpu_evals[LYA_TUNE_MAX_Z]; /* GPU evaluations per z_t, the final one included */
   double coef[3][3];                 /* a, b, c = sum_i coef[p][i] (1+z)^i */
   double seconds;                    /* wall time of the call */
+  int32_t fallback[LYA_TUNE_MAX_Z];  /* LYA_TUNE_EMULATOR: 1 where the plain loop took over */
 } lya_tune_result;
 
 size_t lya_tune_workspace_size(int64_t n_sk, int32_t n_kbins);
@@ -337,11 +343,16 @@ int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, v
  * and the effective bias |b_F| (1 + 2 beta/3 + beta^2/5)^(1/2); each outer
  * step after the first takes sigma_g from the current ratios, solves (a, s)
  * for Fbar = fbar_t and the effective bias = beff_t[z], and runs the n_iter
- * iterations again from the current ratios.  A target the current sigma_g
+ * iterations again from the current ratios.  With beff_at_z set, beff_t[z]
+ * is a bias with respect to the matter field at z_t, as the paper's targets
+ * (fits to measured correlations) are: the pixels come from a z = 0 box, so
+ * the target becomes beff_t[z] G(z_t), G the linear growth of flat LCDM with
+ * G(0) = 1.  A target the current sigma_g
  * cannot reach (at fixed Fbar the bias tends to phi(x_0)/(sigma_g Fbar) as s
  * grows) ends the outer loop early; n_outer_done[z] counts the steps run and
- * beff[z][o] is the effective bias after step o (sigma_g of its last
- * iteration).  fbar and rms then describe the last step's iterations.
+ * beff[z][o] is the effective bias with respect to the box after step o
+ * (sigma_g of its last iteration).  fbar and rms then describe the last
+ * step's iterations.
  * Synchronous; GPU work on `stream`; errors in lya_tune_ps_last_error(). */
 #define LYA_TUNE_PS_MAX_ITER 16
 #define LYA_TUNE_PS_MAX_OUTER 8
@@ -361,6 +372,7 @@ typedef struct {
   int32_t n_outer;           /* 0 or 1: no outer loop; up to 8 (the paper uses 5) */
   double beff_t[LYA_TUNE_MAX_Z];  /* outer loop: target effective bias per z_t (> 0) */
   double f;                  /* outer loop: growth rate of the boxes' eta_par (beta = f c_t) */
+  int32_t beff_at_z;         /* outer loop: 1 = beff_t is with respect to the matter field at z_t */
 } lya_tune_ps_spec;
 
 typedef struct {
@@ -373,6 +385,7 @@ typedef struct {
   double seconds;
   double beff[LYA_TUNE_MAX_Z * LYA_TUNE_PS_MAX_OUTER]; /* [z_t][outer step] */
   int32_t n_outer_done[LYA_TUNE_MAX_Z];
+  double growth[LYA_TUNE_MAX_Z];                       /* G(z_t) if beff_at_z, else 1 */
 } lya_tune_ps_result;
 
 size_t lya_tune_ps_workspace_size(int64_t n_sk, int64_t n_pixels, int32_t n_kbins);

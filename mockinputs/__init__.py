@@ -215,6 +215,19 @@ def tune_c(z):
     return c[0] + c[1] * x + c[2] * x * x
 
 
+def paper_targets(z):
+    """The paper's tuning targets at redshift z (section "Adjusting mock
+    parameters"): the effective bias b_eff = 0.183 ((1+z)/3.3)^3.47 and the
+    distortion parameter beta = 1.76 ((1+z)/3.3)^-2.32 of its power-law fits to
+    the eBOSS DR16 forest, and the mean transmission exp(-0.0028 (1+z)^3.45)
+    of the Calura et al. parameterisation.  Returns (b_eff, beta, Fbar)."""
+    x = (1.0 + np.asarray(z, dtype=np.float64)) / 3.3
+    b_eff = 0.183 * x ** 3.47
+    beta = 1.76 * x ** -2.32
+    fbar = np.exp(-0.0028 * (1.0 + np.asarray(z, dtype=np.float64)) ** 3.45)
+    return b_eff, beta, fbar
+
+
 def tune_k_edges():
     n, lo, hi = TUNE_K_BINS
     return lo * (hi / lo) ** (np.arange(n + 1) / n)

@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
     int c = 0;
     if (lane == 0) c = static_cast<int>(atomicAdd(a.queue, 1u));
     c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));
-    const int64_t q0 = static_cast<int64_t>(c) * a.chunk;
+    const int64_t q0 = static_cast<int64_t>(static_cast<uint32_t>(c)) * a.chunk;  // pulls stay below 2^32
     if (q0 >= a.n_sk) break;
     const int64_t q1 = q0 + a.chunk < a.n_sk ? q0 + a.chunk : a.n_sk;
     for (int64_t q = q0; q < q1; ++q) {
@@ -316,8 +316,19 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
       const double chi0 = a.chi0[q];
       int ns = 1;
       while (ns < np) ns <<= 1;
-      // delta_S needs next_pow2(npix) <= 2048 (the wave's LDS line); longer skewers get none
-      const bool with_ds = (gather || a.ds_in_apply) && a.ps_amp > 0.0 && ns >= 2 && ns <= 2 * kHalfMax;
+      const bool with_ds = (gather || a.ds_in_apply) && a.ps_amp > 0.0 && ns >= 2;
+      // delta_S is drawn on lines of next_pow2(npix) <= 2048 pixels (the wave's
+      // LDS line): a longer skewer is an input error, marked by NaN in every
+      // output and left out of the bins
+      if (with_ds && ns > 2 * kHalfMax) {
+        const float qnan = __builtin_nanf("");
+        for (int j = lane; j < np; j += 64) {
+          if (a.dens) a.dens[off + j] = qnan;
+          if (a.eta) a.eta[off + j] = qnan;
+          if (a.flux) a.flux[off + j] = qnan;
+        }
+        continue;
+      }
       // twiddles from global memory: a copy in LDS would cost this kernel its fourth block per CU
       if (with_ds) small_scale_wave(a, a.id_base + q, ns, buf, a.tw2048, lane);
       // bin boundaries: jb[b] = first pixel with chi_j < edges[b] (chi_j decreases with j)

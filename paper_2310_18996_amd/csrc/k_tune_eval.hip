@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kTeNT) k_tune_eval(TuneEvalArgs a) {
     int c = 0;
     if (lane == 0) c = static_cast<int>(atomicAdd(a.queue, 1u));
     c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));
-    const int64_t q0 = static_cast<int64_t>(c) * a.chunk;
+    const int64_t q0 = static_cast<int64_t>(static_cast<uint32_t>(c)) * a.chunk;  // pulls stay below 2^32
     if (q0 >= a.n_sk) break;
     const int64_t q1 = q0 + a.chunk < a.n_sk ? q0 + a.chunk : a.n_sk;
     for (int64_t q = q0; q < q1; ++q) {

@@ -7,6 +7,28 @@
 #include "../../include/lyamock.h"
 #include "lya_internal.h"
 
+namespace lya {
+
+// Linear growth of flat LCDM normalised to G(0) = 1: D(a) proportional to
+// E(a) int_0^a da' / (a' E(a'))^3, with a' = t^2 (a smooth integrand near 0)
+// and composite Simpson over t in [0, sqrt(a)], 4096 intervals, FP64.
+double growth_lcdm(double z, double om) {
+  auto d = [om](double a) {
+    constexpr int kN = 4096;
+    const double tmax = sqrt(a), h = tmax / kN;
+    double acc = 0.0;
+    for (int i = 1; i <= kN; ++i) {
+      const double t = h * i, ap = t * t;
+      const double ae2 = om / ap + (1.0 - om) * ap * ap;  // (a E)^2
+      acc += (i == kN ? 1.0 : (i & 1 ? 4.0 : 2.0)) * 2.0 * t / (ae2 * sqrt(ae2));
+    }
+    return sqrt(om / (a * a * a) + 1.0 - om) * acc * h / 3.0;
+  };
+  return d(1.0 / (1.0 + z)) / d(1.0);
+}
+
+}  // namespace lya
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -100,24 +122,6 @@ LnCarve carve_lognormal(int64_t m, int32_t n_r) {
   return c;
 }
 
-// Linear growth of flat LCDM normalised to G(0) = 1: D(a) proportional to
-// E(a) int_0^a da' / (a' E(a'))^3, with a' = t^2 (a smooth integrand near 0)
-// and composite Simpson over t in [0, sqrt(a)], 4096 intervals, FP64.
-double growth_lcdm(double z, double om) {
-  auto d = [om](double a) {
-    constexpr int kN = 4096;
-    const double tmax = sqrt(a), h = tmax / kN;
-    double acc = 0.0;
-    for (int i = 1; i <= kN; ++i) {
-      const double t = h * i, ap = t * t;
-      const double ae2 = om / ap + (1.0 - om) * ap * ap;  // (a E)^2
-      acc += (i == kN ? 1.0 : (i & 1 ? 4.0 : 2.0)) * 2.0 * t / (ae2 * sqrt(ae2));
-    }
-    return sqrt(om / (a * a * a) + 1.0 - om) * acc * h / 3.0;
-  };
-  return d(1.0 / (1.0 + z)) / d(1.0);
-}
-
 double bias_qso(double z) { return 3.7 * pow((1.0 + z) / 3.33, 1.7); }
 
 // b_0^2 of the quasar box at z_box: (b_q(z_box) G(z_ref) (1 + z_ref)/(1 + z_box))^2.
@@ -192,12 +196,14 @@ int make_pair(const lya_box* box, const lya_pk* pk, const lya_pk* pk_b, uint64_t
 int check_skewers(const lya_skewers* sk, bool need_geometry) {
   if (!sk) return fail(LYA_EINVAL, "skewers is NULL%s");
   if (sk->n_sk < 0) return fail(LYA_EINVAL, "n_sk < 0%s");
-  if (sk->n_sk > (int64_t(1) << 40)) return fail(LYA_EINVAL, "n_sk too large%s");
+  if (sk->id_base < 0) return fail(LYA_EINVAL, "id_base < 0%s");
+  // quasar ids id_base + q stay below 2^31: the small-scale field's Philox
+  // counter is (id << 33) + mode, and the skewer work queue counts chunks in 32 bits
+  if (sk->n_sk > (int64_t(1) << 31) - sk->id_base) return fail(LYA_EINVAL, "n_sk + id_base above 2^31%s");
   if (sk->n_sk == 0) return LYA_OK;
   if (!sk->npix || !sk->offset || !sk->chi0) return fail(LYA_EINVAL, "skewer arrays are NULL%s");
   if (need_geometry && (!sk->origin_fx || !sk->step_fx)) return fail(LYA_EINVAL, "skewer geometry is NULL%s");
   if (!(sk->dchi >= 0.0)) return fail(LYA_EINVAL, "dchi must be >= 0%s");
-  if (sk->id_base < 0 || sk->id_base > (int64_t(1) << 30)) return fail(LYA_EINVAL, "id_base out of range%s");
   return LYA_OK;
 }
 
@@ -642,7 +648,7 @@ int lya_lognormal_pk(const lya_pk* pk, double z_box, double z_ref, const lya_cos
   a.h = (12.0 / pk->smooth) / static_cast<double>(m);
   a.n_r = n_r;
   a.dr = rmax / (n_r - 1);
-  a.b2 = qso_b2(z_box, z_ref, growth_lcdm(z_ref, cosmo->omega_m));
+  a.b2 = qso_b2(z_box, z_ref, lya::growth_lcdm(z_ref, cosmo->omega_m));
   a.n_k = n_k;
   a.k = k;
   a.pq = pq;
@@ -717,7 +723,7 @@ int lya_draw_quasars(const lya_box* box, const lya_qso_spec* spec, const lya_cos
   lya::QsoCoef cf{};
   cf.nb = nb;
   cf.z_ref = z_ref;
-  cf.g_ref = growth_lcdm(z_ref, cosmo->omega_m);
+  cf.g_ref = lya::growth_lcdm(z_ref, cosmo->omega_m);
   cf.xi5 = spec->xi5;
   lya::QsoDrawArgs a{};
   a.n = box->n;

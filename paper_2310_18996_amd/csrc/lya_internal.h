@@ -70,6 +70,8 @@ void timer_end(hipStream_t st);
 
 // Compute units of the current device (cached per device).
 int device_cus();
+// Linear growth of flat LCDM with G(0) = 1 (host, FP64).
+double growth_lcdm(double z, double om);
 
 hipError_t launch_pk_table(const PkParams& p, int n, double dx, TableWork& w, hipStream_t st);
 hipError_t launch_zchi_table(double omega_m, float* ztab, hipStream_t st);

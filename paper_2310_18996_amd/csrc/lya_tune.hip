@@ -207,6 +207,7 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
     double x[2] = {log(spec->a0), log(spec->b0)};
     double fbest = 0.0, fb = 0.0;
     int nev = 0, gpu_ev = 0;
+    bool fallback = false;
     if (mode == LYA_TUNE_EMULATOR) {
       // Search on the model emulator + offset + slope correction (device
       // Levenberg-Marquardt), check the optimum on the GPU, then (i) move the
@@ -221,6 +222,7 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
       double off[kMaxKBins + 1] = {0.0}, jac[2 * (kMaxKBins + 1)] = {0.0}, dprev[kMaxKBins + 1];
       double xk[2] = {x[0], x[1]};
       double step = 0.3;
+      bool converged = false;
       for (int it = 0; it < checks; ++it) {
         int n1 = 0;
         // the search stops on position alone, a hundred times finer than the check tolerance
@@ -257,22 +259,32 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
         for (int j = 0; j < ns; ++j) off[j] = dprev[j] = d[j];
         xk[0] = x[0];
         xk[1] = x[1];
-        if (it > 0 && moved <= xtol) break;
+        if (it > 0 && moved <= xtol) {
+          converged = true;
+          break;
+        }
         step = 0.05;
       }
-    } else {
+      // a search that has not settled after emu_checks GPU evaluations (an
+      // emulator trained poorly or used outside its range) hands over to the
+      // plain loop, which starts from the last point checked on the GPU
+      fallback = !failed && !converged;
+    }
+    if (mode != LYA_TUNE_EMULATOR || fallback) {
       Nm2 nm;
       nm.init(x, 0.3, spec->xatol, spec->fatol, spec->max_evals);
       double p[2];
       while (!failed && nm.ask(p)) nm.tell(plain(p));
-      nm.result(x, &fbest, &nev);
-      gpu_ev = nev;
+      int n_nm = 0;
+      nm.result(x, &fbest, &n_nm);
+      nev += n_nm;
+      gpu_ev += n_nm;
     }
     if (failed) {
       snprintf(err, errlen, "tuning evaluation at z=%g: %s", z, hipGetErrorString(last));
       return LYA_EHIP;
     }
-    if (mode != LYA_TUNE_EMULATOR) {
+    if (mode != LYA_TUNE_EMULATOR || fallback) {
       // statistics actually reached (one GPU evaluation)
       if ((e = ev.eval(exp(x[0]), exp(x[1]), cc, z, &fb, pk)) != hipSuccess) {
         snprintf(err, errlen, "tuning evaluation: %s", hipGetErrorString(e));
@@ -286,6 +298,7 @@ int tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, void*
     res->chi2[zi] = tune_chi2(fb, pk, fbt, pkt, nk, spec->sigma_rel);
     res->evals[zi] = nev;
     res->gpu_evals[zi] = gpu_ev;
+    res->fallback[zi] = fallback ? 1 : 0;
     for (int i = 0; i < nk; ++i) res->p1d[zi * kMaxKBins + i] = pk[i];
   }
   double xs[16], ys[3][16];

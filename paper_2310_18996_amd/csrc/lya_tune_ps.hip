@@ -342,6 +342,9 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
     std::vector<int64_t> pcnt(nk);
     double fbar = 0.0, b_used = 0.0;
     const double beta = spec->f * ct;
+    // the bias target with respect to the z = 0 box the pixels come from
+    res->growth[z] = spec->beff_at_z ? growth_lcdm(zt, spec->cosmo.omega_m) : 1.0;
+    const double beff_box = spec->beff_t[z] * res->growth[z];
     int done = 0;
     for (int o = 0; o < n_outer; ++o) {
       if (o > 0) {
@@ -350,7 +353,7 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
         const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
         const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
         double a2 = a, s2 = s;
-        if (!(sg2 > 0.0) || !fit_a_s_bias(ft, spec->beff_t[z], sqrt(sg2), beta, &a2, &s2)) break;
+        if (!(sg2 > 0.0) || !fit_a_s_bias(ft, beff_box, sqrt(sg2), beta, &a2, &s2)) break;
         a = a2;
         s = s2;
       }

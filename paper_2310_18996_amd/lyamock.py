@@ -300,7 +300,8 @@ class TuneResult(ctypes.Structure):
                 ("chi2", ctypes.c_double * TUNE_MAX_Z), ("fbar", ctypes.c_double * TUNE_MAX_Z),
                 ("p1d", ctypes.c_double * (TUNE_MAX_Z * 64)), ("evals", ctypes.c_int32 * TUNE_MAX_Z),
                 ("gpu_evals", ctypes.c_int32 * TUNE_MAX_Z),
-                ("coef", (ctypes.c_double * 3) * 3), ("seconds", ctypes.c_double)]
+                ("coef", (ctypes.c_double * 3) * 3), ("seconds", ctypes.c_double),
+                ("fallback", ctypes.c_int32 * TUNE_MAX_Z)]
 
 
 TUNE_PS_MAX_ITER = 16
@@ -318,7 +319,7 @@ class TunePsSpec(ctypes.Structure):
                 ("fbar_t", ctypes.c_double * TUNE_MAX_Z), ("sigf_t", ctypes.c_double * TUNE_MAX_Z),
                 ("p1d_t", ctypes.c_void_p), ("p1d", P1dSpec), ("ps_amp", ctypes.c_double),
                 ("ps_kcut", ctypes.c_double), ("n_iter", ctypes.c_int32), ("n_outer", ctypes.c_int32),
-                ("beff_t", ctypes.c_double * TUNE_MAX_Z), ("f", ctypes.c_double)]
+                ("beff_t", ctypes.c_double * TUNE_MAX_Z), ("f", ctypes.c_double), ("beff_at_z", ctypes.c_int32)]
 
 
 class TunePsResult(ctypes.Structure):
@@ -328,7 +329,7 @@ class TunePsResult(ctypes.Structure):
                 ("fbar", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)),
                 ("rms", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)), ("seconds", ctypes.c_double),
                 ("beff", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_OUTER)),
-                ("n_outer_done", ctypes.c_int32 * TUNE_MAX_Z)]
+                ("n_outer_done", ctypes.c_int32 * TUNE_MAX_Z), ("growth", ctypes.c_double * TUNE_MAX_Z)]
 
 
 FFT_VARIANTS = 14

@@ -18,6 +18,24 @@ def rel_rms(x, y):
     return float(np.sqrt(np.sum((x - y) ** 2)) / (den if den > 0 else 1.0))
 
 
+# Mean flux per redshift bin: relative error at most 1e-6.  The kernels add
+# round(F 2^32) as exact integers, so each pixel also carries at most half a
+# quantum (2^-33) of rounding; that part is allowed on top.
+FBAR_RTOL = 1e-6
+
+
+def fbar_bin_err(gpu_fsum, fs, cnt):
+    """Largest relative error of the per-bin flux sums beyond the fixed-point
+    quantum (0 when every bin is within it; inf for a bin whose exact sum is 0
+    and whose GPU sum is off by more than the quantum)."""
+    g = np.asarray(gpu_fsum, dtype=np.float64)
+    r = np.asarray(fs, dtype=np.float64)
+    excess = np.maximum(np.abs(g - r) - np.asarray(cnt, dtype=np.float64) * 2.0 ** -33, 0.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(excess > 0, excess / np.abs(r), 0.0)
+    return float(np.max(rel)) if rel.size else 0.0
+
+
 def oracle_table(cfg_pk, n, dx, smooth=0.0):
     pk = power.PowerSpectrum(**cfg_pk)
     return power.amplitude_table(pk, n, dx, smooth)

@@ -5,7 +5,7 @@ import pytest
 
 import mockinputs
 from oracle import fgpa, field, skewers
-from tests.lyahelp import gpu_box, gpu_skewers, oracle_table, rel_rms
+from tests.lyahelp import FBAR_RTOL, fbar_bin_err, gpu_box, gpu_skewers, oracle_table, rel_rms
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -68,7 +68,9 @@ def test_gauss_pipeline_matches_oracle(L, tiny, which):
     assert all(v < TOL for v in e.values()), e
     fs, cnt = fgpa.mean_flux_bins(rf, fgpa.pixel_chi(sk), edges)
     np.testing.assert_array_equal(out["count"], cnt)
-    assert np.all(np.abs(out["fsum"] - fs) <= 1e-5 * np.abs(fs) + cnt * 2.0 ** -32)
+    err = fbar_bin_err(out["fsum"], fs, cnt)
+    print("mean flux per bin: largest relative error %.2e" % err)
+    assert err <= FBAR_RTOL, err
 
 
 def test_gauss_smooths_relative_to_trilinear(L, tiny):

@@ -97,6 +97,32 @@ def test_plain_tuning_recovers_known_parameters(L, mock):
     assert res.seconds > 0
 
 
+def test_untrained_emulator_hands_over_to_the_plain_loop(L, mock):
+    """An emulator that cannot guide the search (untrained weights) must not
+    hand back untuned parameters: with a single GPU check no search can show
+    it has settled, so the plain loop takes over from the checked point,
+    reaches the known parameters as the plain loop does, and flags it."""
+    sk, dens, eta = mock
+    z_t = [2.1, 2.6]
+    c_t = [1.1, 1.2]
+    truth = [(0.2, 1.5), (0.35, 1.4)]
+    tg = [tune.evaluate(dens, eta, sk, a, b, c, z, K_EDGES, 0.2) for (a, b), c, z in zip(truth, c_t, z_t)]
+    fbar_t, pk_t = [t[0] for t in tg], np.stack([t[1] for t in tg])
+    emu = _new_emulator(L, N_OUT, 1, seed=11, lo=(0.05, 0.5, 0.5, 1.8), hi=(2.0, 2.5, 2.0, 3.6), log_inputs=1)
+    sp = Spec(L, sk, dens, eta, K_EDGES, z_t, c_t, fbar_t, pk_t, emulator=emu, checks=1)
+    print("emulator tuning with an untrained emulator, one check", flush=True)
+    res = L.tune_params(sp.spec, L.LYA_TUNE_EMULATOR, sp.work)
+    for i, (a, b) in enumerate(truth):
+        print("z=%.1f fallback=%d a=%.6f (%.6f) b=%.6f (%.6f) gpu evals %d" % (
+            z_t[i], res.fallback[i], res.a[i], a, res.b[i], b, res.gpu_evals[i]))
+        assert res.fallback[i] == 1
+        assert res.gpu_evals[i] > 2          # the check, the plain loop's points and its final evaluation
+        assert abs(res.a[i] / a - 1) < 2e-3 and abs(res.b[i] / b - 1) < 2e-3
+        fb, pk = tune.evaluate(dens, eta, sk, res.a[i], res.b[i], c_t[i], z_t[i], K_EDGES, 0.2)
+        assert abs(res.fbar[i] / fb - 1) < 1e-5
+        assert rel_rms(np.array(res.p1d[i * 64:i * 64 + N_OUT - 1]), pk) < 1e-5
+
+
 def _upload_params(L, emu, params):
     import torch
     off = L.emulator_param_offset()
@@ -289,6 +315,7 @@ def test_emulator_tuning_matches_plain_with_fewer_gpu_evaluations(L, mock):
         print("z=%.1f plain a=%.4f b=%.4f gpu evals %d | emulator a=%.4f b=%.4f gpu evals %d; dFbar %.2e dP %.2e"
               % (z_t[i], rp.a[i], rp.b[i], rp.gpu_evals[i], re_.a[i], re_.b[i], re_.gpu_evals[i], df, dp))
         assert df < 5e-3 and dp < 5e-3
+        assert re_.fallback[i] == 0 and rp.fallback[i] == 0
         assert re_.gpu_evals[i] * 10 <= rp.gpu_evals[i]
     print("tuning wall time: plain %.3f s, emulator %.3f s" % (rp.seconds, re_.seconds))
     assert re_.seconds < rp.seconds

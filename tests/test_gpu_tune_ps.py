@@ -185,3 +185,71 @@ def test_tune_ps_outer_loop_matches_oracle(L, mock):
     spec.beff_t[0] = 0.0
     with pytest.raises(L.LyaError):
         L.tune_ps(spec, work)
+
+
+def test_tune_ps_outer_loop_with_the_papers_targets(L, mock):
+    """The paper's own targets (section "Adjusting mock parameters"): Fbar(z)
+    of Calura et al., c_t = beta(z_t)/f and the effective bias
+    0.183 ((1+z)/3.3)^3.47 with respect to the matter field at z_t (the
+    library scales it by the linear growth, as the oracle does here).  The
+    P1D target and sigma_F come from a truth of the same pixels (delta_S of
+    another spectrum and key) whose a is set to hit that Fbar; three outer
+    steps at two redshifts against the oracle's."""
+    import torch
+    from oracle import quasars
+    cfg, sk = mock["cfg"], mock["sk"]
+    s, keep = skewer_tensors(L, sk)
+    k_edges = mock["k_edges"]
+    nk = len(k_edges) - 1
+    dl, eta = _dev(torch, mock["dl"], np.float32), _dev(torch, mock["eta"], np.float32)
+    ke = _dev(torch, k_edges, np.float64)
+    z_t = [1.8, 3.6]
+    beff_p, beta_p, fbar_p = mockinputs.paper_targets(z_t)
+    c_t = beta_p / cfg["f"]
+    truth = mock["dl"].copy()
+    for q in range(len(sk["npix"])):
+        o, m = int(sk["offset"][q]), int(sk["npix"][q])
+        truth[o:o + m] += skewers.delta_s(cfg["seed"] + 1, q, m, cfg["dpix"], 1.8, 1.0)
+    pk_t, sigf = [], []
+    for z, c, ft in zip(z_t, c_t, fbar_p):
+        lo, hi = np.log(1e-6), np.log(1e3)
+        for _ in range(80):              # the truth's a: bisection for its mean flux
+            mid = 0.5 * (lo + hi)
+            if np.exp(-np.exp(mid) * np.exp(0.6 * (truth + c * mock["eta"]))).mean() > ft:
+                lo = mid
+            else:
+                hi = mid
+        F = np.exp(-np.exp(0.5 * (lo + hi)) * np.exp(0.6 * (truth + c * mock["eta"])))
+        ps, cnt = p1d.p1d(F, sk, [-1e30, 1e30], [F.mean()], k_edges, z, cfg["dpix"])
+        pk_t.append(np.where(cnt > 0, ps / np.maximum(cnt, 1), np.nan))
+        sigf.append(float(F.std()))
+    pk_t = np.ascontiguousarray(np.stack(pk_t), dtype=np.float64)
+    n_iter, n_outer = 3, 3
+    spec = L.TunePsSpec()
+    spec.sk = ctypes_pointer(L, s)
+    spec.dens_l, spec.eta = dl.data_ptr(), eta.data_ptr()
+    spec.n_pixels = int(sk["total"])
+    spec.cosmo = L.Cosmo(0.3147)
+    spec.seed = cfg["seed"]
+    spec.n_zt = len(z_t)
+    for i in range(len(z_t)):
+        spec.z_t[i], spec.c_t[i], spec.fbar_t[i], spec.sigf_t[i] = z_t[i], c_t[i], fbar_p[i], sigf[i]
+        spec.beff_t[i] = beff_p[i]
+    spec.p1d_t = pk_t.ctypes.data
+    spec.p1d = L.P1dSpec(nk, ke.data_ptr(), 0.0, cfg["dpix"])
+    spec.ps_amp, spec.ps_kcut, spec.n_iter = 1.0, 1.5, n_iter
+    spec.n_outer, spec.f, spec.beff_at_z = n_outer, cfg["f"], 1
+    work = torch.empty(L.tune_ps_workspace_size(len(sk["npix"]), sk["total"], nk), dtype=torch.uint8, device="cuda")
+    res = L.tune_ps(spec, work)
+    for i, z in enumerate(z_t):
+        target = beff_p[i] * quasars.growth(z)
+        ref = tune_ps.iterate(mock["dl"], mock["eta"], sk, cfg["seed"], z, c_t[i], fbar_p[i], pk_t[i], k_edges,
+                              cfg["dpix"], 1.0, 1.5, n_iter=n_iter, sigf_t=sigf[i], n_outer=n_outer, beff_t=target,
+                              f=cfg["f"])
+        got = [res.beff[i * L.TUNE_PS_MAX_OUTER + o] for o in range(res.n_outer_done[i])]
+        print("z_t %.1f: paper b_eff %.4f (box %.4f), beta %.3f, Fbar %.4f; steps %d; b_eff/target %s (oracle %s)"
+              % (z, beff_p[i], target, beta_p[i], fbar_p[i], res.n_outer_done[i],
+                 ["%.4f" % (v / target) for v in got], ["%.4f" % (v / target) for v in ref["beff"]]), flush=True)
+        assert res.n_outer_done[i] == len(ref["beff"]) == n_outer
+        np.testing.assert_allclose(got, ref["beff"], rtol=1e-5)
+        np.testing.assert_allclose([res.a[i], res.s[i], res.b[i]], [ref["a"], ref["s"], ref["b"]], rtol=1e-5)
