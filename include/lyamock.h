@@ -174,6 +174,22 @@ int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* s
                      uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
                      float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream);
 
+/* Allocation-free variant of lya_draw_skewers, for callers that cannot
+ * allocate device memory (code under HIP-graph capture, tight serving loops,
+ * hosts that forbid hipMalloc): the same arguments, outputs and errors, without
+ * work and work_bytes.  Its workspace (the redshift table, the twiddles, the
+ * work-queue counter and the fixed-point sums of up to 64 bins, about 100 KB)
+ * is a static 128 KiB device array that each GPU the library runs on holds
+ * until the process ends; the first call on a device looks up its address.
+ * Every call on one GPU uses that GPU's array and leaves its contents behind,
+ * so calls that overlap on one GPU (other streams, other host threads) race;
+ * each call clears the counters it needs with kernels (no memset nodes).
+ * LYA_EWORKSPACE if the workspace would not fit the array (no valid input
+ * needs more: n_bins <= 64). */
+int lya_draw_skewers_static(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                            uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                            float* flux, const lya_zbins* zb, void* stream);
+
 /* The paper's interpolation (section "Gaussian fields along lines of sight"):
  * as lya_draw_skewers, but delta_L and eta_par at a pixel are the Gaussian-
  * kernel average of the 7^3 voxels around it, standard deviation one voxel

@@ -4,8 +4,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/lyamock.h"
 #include "lya_internal.h"
+
+constexpr size_t kStaticScratchBytes = size_t(1) << 17;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace lya {
 
@@ -79,6 +84,32 @@ SkCarve carve_sk() {
   c.bcnt = o;  o += align256(sizeof(unsigned long long) * lya::kMaxZBins);
   c.total = o;
   return c;
+}
+
+// Workspace of lya_draw_skewers_static: the file-scope device array
+// `scratch` (below), one copy in every GPU the library runs on, held until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy (on the host it only stands in for the symbol): the address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (LYA_OK) or an error code.
+int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LYA_EUNSUPPORTED, "device index above 63%s");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LYA_OK;
 }
 
 struct QsoCarve {
@@ -503,6 +534,21 @@ int lya_draw_skewers(const lya_box* box, const void* field, const lya_skewers* s
                      float* flux, const lya_zbins* zb, void* work, size_t work_bytes, void* stream) {
   return draw_skewers_impl(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zb, work, work_bytes, stream,
                            false);
+}
+
+int lya_draw_skewers_static(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,
+                            uint64_t seed, const lya_cosmo* cosmo, const lya_fgpa* fgpa, float* dens, float* eta,
+                            float* flux, const lya_zbins* zb, void* stream) {
+  g_err[0] = 0;
+  const size_t need = carve_sk().total;
+  if (need > kStaticScratchBytes)
+    return fail(LYA_EWORKSPACE, "the skewer workspace exceeds the static scratch array%s");
+  if (zb && zb->n_bins > lya::kMaxZBins) return fail(LYA_EINVAL, "n_bins must be in [0, 64]%s");
+  void* work = nullptr;
+  const int rc = scratch_address(&work);
+  if (rc) return rc;
+  return draw_skewers_impl(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zb, work, kStaticScratchBytes,
+                           stream, false);
 }
 
 int lya_draw_skewers_gauss(const lya_box* box, const void* field, const lya_skewers* sk, const lya_ps1d* ps,

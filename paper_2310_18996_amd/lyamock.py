@@ -22,7 +22,7 @@ COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 
 EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make_box", "lya_make_eta",
            "lya_make_box_pair", "lya_lognormal_workspace_size", "lya_lognormal_pk", "lya_box_moments",
            "lya_draw_quasars", "lya_quasar_skewers",
-           "lya_draw_skewers", "lya_draw_skewers_gauss", "lya_draw_skewers_wide", "lya_apply_fgpa",
+           "lya_draw_skewers", "lya_draw_skewers_static", "lya_draw_skewers_gauss", "lya_draw_skewers_wide", "lya_apply_fgpa",
            "lya_apply_fgpa_ds", "lya_tune_ps_workspace_size", "lya_tune_ps", "lya_tune_ps_last_error",
            "lya_p1d_workspace_size", "lya_p1d",
            "lya_tune_workspace_size",
@@ -103,6 +103,9 @@ def load():
     lib.lya_draw_skewers.restype = ctypes.c_int
     lib.lya_draw_skewers.argtypes = [P(Box), VP, P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo), P(Fgpa),
                                      VP, VP, VP, P(ZBins), VP, ctypes.c_size_t, VP]
+    lib.lya_draw_skewers_static.restype = ctypes.c_int
+    lib.lya_draw_skewers_static.argtypes = [P(Box), VP, P(Skewers), P(Ps1d), ctypes.c_uint64, P(Cosmo), P(Fgpa),
+                                            VP, VP, VP, P(ZBins), VP]
     lib.lya_draw_skewers_gauss.restype = ctypes.c_int
     lib.lya_draw_skewers_gauss.argtypes = lib.lya_draw_skewers.argtypes
     lib.lya_draw_skewers_wide.restype = ctypes.c_int
@@ -217,6 +220,17 @@ def draw_skewers(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, 
                                    _ptr(dens), _ptr(eta), _ptr(flux),
                                    ctypes.byref(zbins) if zbins is not None else None,
                                    _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+def draw_skewers_static(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, stream=None):
+    """lya_draw_skewers_static: lya_draw_skewers without a workspace argument
+    (the library's static device scratch; see include/lyamock.h)."""
+    _check(load().lya_draw_skewers_static(ctypes.byref(box), _ptr(field), ctypes.byref(sk),
+                                          ctypes.byref(ps) if ps is not None else None, int(seed),
+                                          ctypes.byref(cosmo) if cosmo is not None else None,
+                                          ctypes.byref(fgpa) if fgpa is not None else None,
+                                          _ptr(dens), _ptr(eta), _ptr(flux),
+                                          ctypes.byref(zbins) if zbins is not None else None, _stream(stream)))
 
 
 def draw_skewers_gauss(box, field, sk, ps, seed, cosmo, fgpa, dens, eta, flux, zbins, work, stream=None):
