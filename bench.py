@@ -9,8 +9,15 @@ Prints one JSON line.  `value` is box cells per second of the whole step;
 `box_cells_per_s` and `skewer_pixels_per_s` split it by stage (per-kernel HIP
 events on the launch stream).  `roofline` reports the dominant kernel's
 algorithmic bytes per launch over its mean launch time against 8 TB/s.
-`cpu_baseline` times the FP64 oracle on the host on a bounded sample of the
-same workload (same cells-to-pixels ratio), scaled to cells per second.
+`cpu_baseline` times the FP64 oracle on the host's cores (up to 16: the GPU
+box's share) on bounded samples of the same workload (same cells-to-pixels
+ratio), scaled to cells per second, with a labelled c N^3 log N / per-pixel
+extrapolation to the full workload.
+
+`precision` (after the timed steps): the 1024^3 precision configuration with
+200,000 skewers in FP32 and BF16 storage, times and BF16-vs-FP32 errors.
+`rocfft` (after the timed steps): the vendor FFT (torch.fft.ifftn, rocFFT)
+of the workload's box as a comparison line for the three box passes.
 
 `tune` (after the timed steps, not part of them): FGPA tuning at five
 redshifts against a target mean flux (0.75 -> 0.35) and the P1D of a truth
@@ -48,8 +55,7 @@ HBM_PEAK_GBS = 8000.0
 # for the strided passes; valid only for the kernels as they were when the
 # counters were taken (a changed kernel must drop its entry) and reported only
 # for that workload.
-TRAFFIC = {("fft_x", 9): 137479106942, ("fft_y", 8): 140184875987, ("fft_z_gen", None): 95744906378,
-           ("skewers", None): 14575779985, ("qso_draw", None): 137560151198}
+TRAFFIC = {("qso_draw", None): 137560151198}
 TRAFFIC_CONFIG = "big"
 
 
@@ -95,31 +101,122 @@ def distinct_voxel_bytes(sk, n, sample=2000, seed=0):
     return 8.0 * per_pix * float(np.sum(sk["npix"], dtype=np.int64)), per_pix
 
 
-def cpu_baseline(cfg, pixels_per_cell, budget_n=256):
-    """Time the oracle on a bounded sample of the workload: a budget_n^3 box and
-    the same number of pixels per box cell as the full workload."""
+CPU_WORKERS = 16   # the GPU machine's share of host cores
+
+
+def _cpu_spectrum_slab(args):
+    """One x slab of the oracle's k-space field, written into shared memory."""
+    from multiprocessing import shared_memory
+    from oracle import field
+    name, n, seed, tab, f, a, b = args
+    shm = shared_memory.SharedMemory(name=name)
+    try:
+        x = np.ndarray((n, n, n), dtype=np.complex128, buffer=shm.buf)
+        x[a:b] = field.spectrum(n, seed, tab, ("delta", "zz"), f=f, ix_slice=slice(a, b))
+    finally:
+        shm.close()
+    return b - a
+
+
+_CPU = {}
+
+
+def _cpu_skewer_rows(rows):
+    """The oracle's skewer pass, FGPA and bin sums on rows [a, b) of the table
+    (id_base a, so each row keeps its own small-scale field)."""
+    from oracle import fgpa, skewers
+    a, b = rows
+    box, sk, cfg = _CPU["box"], _CPU["sk"], _CPU["cfg"]
+    npix = sk["npix"][a:b]
+    off = np.zeros(b - a, dtype=np.int64)
+    off[1:] = np.cumsum(npix[:-1].astype(np.int64))
+    sub = dict(origin_fx=sk["origin_fx"][a:b], step_fx=sk["step_fx"][a:b], npix=npix, offset=off,
+               chi0=sk["chi0"][a:b], dchi=sk["dchi"], id_base=a)
+    dens, eta = skewers.draw_skewers(box.real, box.imag, sub, cfg["seed"], cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"])
+    F, _ = fgpa.apply_fgpa(dens, eta, sub, cfg["fgpa"])
+    fs, cnt = fgpa.mean_flux_bins(F, fgpa.pixel_chi(sub), fgpa.chi_edges_for_z(cfg["z_edges"]))
+    return fs, cnt
+
+
+def cpu_oracle_step(cfg, n, pixels_per_cell, workers):
+    """One step of the workload done by the oracle on the host at box size n
+    with the workload's pixels per box cell: the k-space field by x slabs over
+    `workers` processes, the inverse FFT (scipy, `workers` threads), then the
+    skewers, FGPA and bin sums by contiguous table rows over the processes.
+    Returns (box seconds, skewer seconds, skewers, pixels)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    import scipy.fft
     import mockinputs
-    from oracle import fgpa, field, power, skewers
-    cells = budget_n ** 3
+    from oracle import power
+    cells = n ** 3
     want_pix = pixels_per_cell * cells
-    sk_full = mockinputs.skewer_table(dict(cfg, n=budget_n), n_sk=max(64, int(want_pix / 700)))
-    # keep the workload's length mix, take just enough skewers
+    sk_full = mockinputs.skewer_table(dict(cfg, n=n), n_sk=max(64, int(want_pix / 700)))
     cum = np.cumsum(sk_full["npix"].astype(np.int64))
     ns = int(np.searchsorted(cum, want_pix)) + 1
     sk = {k: (v[:ns] if isinstance(v, np.ndarray) else v) for k, v in sk_full.items()}
     pix = int(np.sum(sk["npix"], dtype=np.int64))
+    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    tab = power.amplitude_table(power.PowerSpectrum(**cfg["pk"]), budget_n, cfg["dx"])
-    box = field.make_box(budget_n, cfg["seed"], tab, ("delta", "zz"), f=cfg["f"])
+    tab = power.amplitude_table(power.PowerSpectrum(**cfg["pk"]), n, cfg["dx"])
+    shm = shared_memory.SharedMemory(create=True, size=16 * cells)
+    try:
+        x = np.ndarray((n, n, n), dtype=np.complex128, buffer=shm.buf)
+        cuts = np.linspace(0, n, workers + 1).astype(int)
+        with ctx.Pool(workers) as pool:
+            pool.map(_cpu_spectrum_slab, [(shm.name, n, cfg["seed"], tab, cfg["f"], int(a), int(b))
+                                          for a, b in zip(cuts[:-1], cuts[1:]) if b > a])
+        box = scipy.fft.ifftn(x, workers=workers) * float(n) ** 3
+    finally:
+        shm.close()
+        shm.unlink()
     t1 = time.perf_counter()
-    dens, eta = skewers.draw_skewers(box.real, box.imag, sk, cfg["seed"], cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"])
-    F, _ = fgpa.apply_fgpa(dens, eta, sk, cfg["fgpa"])
-    fgpa.mean_flux_bins(F, fgpa.pixel_chi(sk), fgpa.chi_edges_for_z(cfg["z_edges"]))
+    _CPU.update(box=box, sk=sk, cfg=cfg)
+    rows = np.linspace(0, ns, 4 * workers + 1).astype(int)
+    with ctx.Pool(workers) as pool:
+        parts = pool.map(_cpu_skewer_rows, [(int(a), int(b)) for a, b in zip(rows[:-1], rows[1:]) if b > a])
+    fs = np.sum([p[0] for p in parts], axis=0)
     t2 = time.perf_counter()
-    return dict(value=cells / (t2 - t0), unit="box cells/s", cores=1, kind="oracle",
-                sample="%d^3 box (%d cells) + %d skewers (%d pixels, the workload's pixels per cell) on the host; "
-                       "box %.2f s, skewers+FGPA %.2f s; numpy/scipy single-threaded" % (
-                           budget_n, cells, ns, pix, t1 - t0, t2 - t1))
+    _CPU.clear()
+    assert np.all(np.isfinite(fs))
+    return t1 - t0, t2 - t1, ns, pix
+
+
+def cpu_baseline(cfg, pixels_per_cell, budget_n=384, full_n=None, full_pixels=None):
+    """Time the oracle on the host's cores on bounded samples of the workload
+    (box sizes up to budget_n, same pixels per cell), and extrapolate to the
+    full workload: box time c_b N^3 log2 N and skewer time c_p per pixel,
+    least squares over the samples."""
+    workers = max(1, min(CPU_WORKERS, os.cpu_count() or 1))
+    sizes = [n for n in (128, 192, 256, budget_n) if n <= budget_n]
+    runs = []
+    for n in sorted(set(sizes)):
+        tb, ts, ns, pix = cpu_oracle_step(cfg, n, pixels_per_cell, workers)
+        runs.append(dict(n=n, box_s=tb, skewer_s=ts, skewers=ns, pixels=pix))
+        print("bench: oracle on %d cores at %d^3: box %.2f s, %d skewers %.2f s" % (workers, n, tb, ns, ts),
+              file=sys.stderr, flush=True)
+    big = runs[-1]
+    cells = float(big["n"]) ** 3
+    out = dict(value=cells / (big["box_s"] + big["skewer_s"]), unit="box cells/s", cores=workers, kind="oracle",
+               sample="%d^3 box + %d skewers (%d pixels, the workload's pixels per cell): the oracle's k-space field "
+                      "by x slabs over %d processes, scipy.fft.ifftn on %d threads, the skewers, FGPA and bin sums "
+                      "by table rows over %d processes; box %.2f s, skewers %.2f s" % (
+                          big["n"], big["skewers"], big["pixels"], workers, workers, workers, big["box_s"],
+                          big["skewer_s"]),
+               samples=runs)
+    if full_n and full_pixels:
+        w = np.array([float(r["n"]) ** 3 * np.log2(r["n"]) for r in runs])
+        tb = np.array([r["box_s"] for r in runs])
+        c_b = float(np.dot(w, tb) / np.dot(w, w))
+        pp = np.array([float(r["pixels"]) for r in runs])
+        c_p = float(np.dot(pp, [r["skewer_s"] for r in runs]) / np.dot(pp, pp))
+        t_full = c_b * float(full_n) ** 3 * np.log2(full_n) + c_p * float(full_pixels)
+        out["extrapolated"] = dict(
+            label="EXTRAPOLATED, not measured: box time c_b N^3 log2 N and skewer time c_p per pixel fitted to the "
+                  "samples above, evaluated at the full workload",
+            n=int(full_n), pixels=int(full_pixels), c_box_s=c_b, c_pixel_s=c_p, seconds=t_full,
+            value=float(full_n) ** 3 / t_full, unit="box cells/s")
+    return out
 
 
 def host_facts():
@@ -142,21 +239,25 @@ def host_facts():
 
 
 # ---------------------------------------------------------------- precision leg
-def precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, edges, stream, reps=3):
-    """BF16 against FP32 storage of {delta, eta_par} on the same workload:
-    times of both and the BF16 error relative to the FP32 results over the
-    whole box and every pixel (the FP32 path's own error against the FP64
-    oracle is measured by the parity tests)."""
+def precision_leg(L, torch, stream, reps=3):
+    """The precision configuration (1024^3 box, 200,000 skewers): FP32 and
+    BF16 storage of {delta, eta_par}, each timed (box; skewer pass with
+    delta_S, FGPA and bins), and the BF16 results against the FP32 ones over
+    the whole box and every pixel (each storage type's own error against the
+    FP64 oracle is measured by the parity tests)."""
     import mockinputs
-    n, seed = cfg["n"], cfg["seed"]
-    b16 = L.box_struct(n, cfg["dx"], L.LYA_BF16)
-    f16 = torch.empty((L.field_elems(b16),), dtype=torch.int32, device="cuda")
-    w16 = torch.empty(L.workspace_size(L.LYA_OP_BOX, b16), dtype=torch.uint8, device="cuda")
+    cfg = mockinputs.config("precision")
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    sk = mockinputs.skewer_table(cfg)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(sk[k])).cuda()
+           for k in ("origin_fx", "step_fx", "npix", "offset", "chi0")}
+    s = L.skewers_struct(len(sk["npix"]), dev["origin_fx"], dev["step_fx"], dev["npix"], dev["offset"], dev["chi0"],
+                         sk["dchi"])
+    tot = int(sk["total"])
+    edges = torch.from_numpy(L.chi_of_z(cfg["z_edges"], cfg["omega_m"])).cuda()
+    ps = L.Ps1d(cfg["ps_amp"], cfg["ps_kcut"], cfg["dpix"], 0)
+    cosmo, fg = L.Cosmo(cfg["omega_m"]), L.fgpa_struct(cfg["fgpa"])
     pk = L.pk_struct(**cfg["pk"])
-    d16, e16, fl16 = (torch.empty_like(flux) for _ in range(3))
-    fs16, cn16 = torch.zeros_like(fsum), torch.zeros_like(cnt)
-    zb16 = L.zbins_struct(edges, fs16, cn16)
-    swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, b16), dtype=torch.uint8, device="cuda")
 
     def timed(fn):
         fn()
@@ -167,11 +268,24 @@ def precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, 
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / reps
 
-    box_ms = timed(lambda: L.make_box(b16, pk, seed, cfg["f"], True, f16, w16, stream))
-    sk_ms = timed(lambda: L.draw_skewers(b16, f16, s, ps, seed, cosmo, fg, d16, e16, fl16, zb16, swork, stream))
-    # the FP32 box of the same seed (the timed steps left it in `field`)
-    v32 = L.box_view(field, n)
-    w = L.box_view(f16, n)
+    runs = {}
+    for name, storage in (("fp32", L.LYA_F32), ("bf16", L.LYA_BF16)):
+        box = L.box_struct(n, dx, storage)
+        fld = (torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") if storage == L.LYA_F32
+               else torch.empty((L.field_elems(box),), dtype=torch.int32, device="cuda"))
+        bw = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+        sw = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
+        d, e, fl = (torch.empty(tot, dtype=torch.float32, device="cuda") for _ in range(3))
+        fs = torch.zeros(edges.numel() - 1, dtype=torch.float64, device="cuda")
+        cn = torch.zeros(edges.numel() - 1, dtype=torch.int64, device="cuda")
+        zb = L.zbins_struct(edges, fs, cn)
+        box_ms = timed(lambda: L.make_box(box, pk, seed, cfg["f"], True, fld, bw, stream))
+        sk_ms = timed(lambda: L.draw_skewers(box, fld, s, ps, seed, cosmo, fg, d, e, fl, zb, sw, stream))
+        del bw
+        runs[name] = dict(box=box, fld=fld, dens=d, eta=e, flux=fl, fsum=fs, cnt=cn, box_ms=box_ms, skewer_ms=sk_ms)
+    torch.cuda.empty_cache()
+    v32 = L.box_view(runs["fp32"]["fld"], n)
+    w = L.box_view(runs["bf16"]["fld"], n)
     num = [0.0, 0.0]
     den = [0.0, 0.0]
     for x in range(0, n, 64):   # in slabs, FP64 sums
@@ -183,25 +297,82 @@ def precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, 
         num[1] += float(((hi - a[..., 1]) ** 2).sum())
         den[0] += float((a[..., 0] ** 2).sum())
         den[1] += float((a[..., 1] ** 2).sum())
-    fl = flux.double()
-    rel_flux = float(torch.sqrt(((fl16.double() - fl) ** 2).sum() / (fl ** 2).sum()))
-    ok = cnt > 0
-    fbar_rel = float(((fs16[ok] / fsum[ok]) - 1).abs().max())
+
+    def rel(key):
+        x, y = runs["bf16"][key].double(), runs["fp32"][key].double()
+        return float(torch.sqrt(((x - y) ** 2).sum() / (y ** 2).sum()))
+    ok = runs["fp32"]["cnt"] > 0
+    fbar_rel = float(((runs["bf16"]["fsum"][ok] / runs["fp32"]["fsum"][ok]) - 1).abs().max())
     k_edges = torch.from_numpy(mockinputs.tune_k_edges()).cuda()
     nk = k_edges.numel() - 1
     pw = torch.empty(L.p1d_workspace_size(s.n_sk, nk), dtype=torch.uint8, device="cuda")
     res = []
-    for fx, zb_ in ((flux, L.zbins_struct(edges, fsum, cnt)), (fl16, zb16)):
+    for name in ("fp32", "bf16"):
+        r = runs[name]
         pss = torch.zeros(nk, dtype=torch.float64, device="cuda")
         pcc = torch.zeros(nk, dtype=torch.int64, device="cuda")
-        L.p1d(s, cosmo, fx, zb_, L.P1dSpec(nk, k_edges.data_ptr(), 2.6, cfg["dpix"]), pss, pcc, pw, stream)
+        L.p1d(s, cosmo, r["flux"], L.zbins_struct(edges, r["fsum"], r["cnt"]),
+              L.P1dSpec(nk, k_edges.data_ptr(), 2.6, cfg["dpix"]), pss, pcc, pw, stream)
         res.append(pss)
     torch.cuda.synchronize()
     good = res[0] != 0
     p1d_rel = float(((res[1][good] / res[0][good]) - 1).abs().max())
-    return dict(bf16_box_ms=box_ms, bf16_skewer_ms=sk_ms,
-                bf16_vs_fp32=dict(delta_rel_rms=(num[0] / den[0]) ** 0.5, eta_rel_rms=(num[1] / den[1]) ** 0.5,
-                                  flux_rel_rms=rel_flux, fbar_max_rel=fbar_rel, p1d_max_rel=p1d_rel))
+    cells = float(n) ** 3
+    out = dict(workload="%d^3 box at %.2f Mpc/h, %d skewers, %d pixels" % (n, dx, len(sk["npix"]), tot),
+               bf16_vs_fp32=dict(delta_rel_rms=(num[0] / den[0]) ** 0.5, eta_rel_rms=(num[1] / den[1]) ** 0.5,
+                                 pixel_dens_rel_rms=rel("dens"), pixel_eta_rel_rms=rel("eta"),
+                                 flux_rel_rms=rel("flux"), fbar_max_rel=fbar_rel, p1d_max_rel=p1d_rel),
+               parity_vs_oracle="tests/test_gpu_fullsize.py: z-lines, eight table skewers on C-oracle columns, and "
+                                "10,000 table skewers on a single-shell box, each storage type against the oracle")
+    for name in ("fp32", "bf16"):
+        r = runs[name]
+        out[name] = dict(box_ms=r["box_ms"], box_cells_per_s=cells / (r["box_ms"] * 1e-3), skewer_ms=r["skewer_ms"],
+                         skewer_pixels_per_s=tot / (r["skewer_ms"] * 1e-3))
+    del runs, v32, w
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------- rocFFT comparison
+def rocfft_leg(torch, n, ours_ms, reps=3):
+    """The vendor library as a comparison line (never part of the hot path):
+    torch.fft.ifftn (rocFFT) of an n^3 complex64 box, out of place into a
+    preallocated output, timed with events on the current stream, against the
+    library's three box passes (which also synthesise the modes)."""
+    try:
+        x = torch.empty((n, n, n), dtype=torch.complex64, device="cuda")
+        xr = torch.view_as_real(x)
+        for i in range(0, n, 256):
+            xr[i:i + 256].normal_()
+        torch.cuda.reset_peak_memory_stats()
+        # each call allocates its own output (an out= tensor only adds a
+        # temporary): free the previous one first, so input + output + the
+        # library's work area fit beside each other
+        y = torch.fft.ifftn(x, norm="forward")
+        torch.cuda.synchronize()
+        del y
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(reps):
+            a.record()
+            y = torch.fft.ifftn(x, norm="forward")
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+            del y
+        ms = float(np.mean(times))
+        peak = torch.cuda.max_memory_allocated() / 2 ** 30
+        del x, xr
+        torch.cuda.empty_cache()
+    except torch.OutOfMemoryError as e:
+        torch.cuda.empty_cache()
+        return dict(n=n, error="out of memory: %s" % str(e)[:160])
+    cells = float(n) ** 3
+    return dict(what="torch.fft.ifftn (rocFFT) of a %d^3 complex64 box, out of place, norm='forward' (unnormalised "
+                     "inverse), random input; mean of %d calls" % (n, reps),
+                n=n, rocfft_ms=ms, rocfft_cells_per_s=cells / (ms * 1e-3), ours_fft_passes_ms=ours_ms,
+                ours_over_rocfft_time=ours_ms / ms, rocfft_over_ours_speed=ms / ours_ms,
+                peak_allocated_gib=peak)
 
 
 # ---------------------------------------------------------- wide-angle leg
@@ -521,33 +692,68 @@ def tune_ps_leg(L, torch, n_iter=10):
     tw = torch.empty(L.tune_ps_workspace_size(mock["n_sk"], mock["pixels"], nk), dtype=torch.uint8, device="cuda")
     res = L.tune_ps(spec, tw)
     M = L.TUNE_PS_MAX_ITER
-    # the outer loop, five steps, against the truth's effective bias: |b_F| of
-    # its (a, b) at its sigma_g (moments of the stored pixels plus the truth's
-    # delta_S variance) with beta = f c
-    d, e = mock["dens"].double(), mock["eta"].double()
-    sl2, se2 = float(d.var(unbiased=False)), float(e.var(unbiased=False))
-    cov = float(((d - d.mean()) * (e - e.mean())).mean())
-    kmax = np.pi / mid["dpix"]
-    kk = np.linspace(0.0, kmax, 200001)
-    ss2_true = float(np.trapezoid(1.6 * np.exp(-(kk / 1.1) ** 2), kk) / np.pi)
-    x = np.linspace(-12.0, 12.0, 48001)
-    wx = np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
-    beff_t = []
-    for a, b, c in zip(a_true, b_true, c_t):
-        sg = np.sqrt(sl2 + ss2_true + c * c * se2 + 2.0 * c * cov)
-        sv = b * sg
-        F = np.exp(-a * np.exp(sv * x))
-        bF = (a * sv / sg) * np.trapezoid(np.exp(sv * x) * F * wx, x) / np.trapezoid(F * wx, x)
-        beta = mid["f"] * c
-        beff_t.append(float(bF * np.sqrt(1.0 + 2.0 * beta / 3.0 + beta * beta / 5.0)))
-    spec.n_outer, spec.f = 5, mid["f"]
-    for i in range(len(z_t)):
-        spec.beff_t[i] = beff_t[i]
-    res5 = L.tune_ps(spec, tw)
+    # the outer loop (five steps) against the paper's own targets: Fbar(z) of
+    # Calura et al., c_t = beta(z_t)/f and the effective bias of its power law,
+    # taken with respect to the matter field at z_t (the library scales it by
+    # the linear growth for the z = 0 box).  P1D and sigma_F targets: the same
+    # truth pixels with their a re-set to hit that Fbar and a b per z_t that
+    # puts the truth's own effective bias on the target (a first pass at
+    # b = 0.35 measures the bias its (Fbar, sigma_F) imply; b is then scaled
+    # by target/bias, to which the bias is close to proportional), so that the
+    # P1D and bias targets are consistent, as the paper's measured ones are.
+    beff_p, beta_p, fbar_p = mockinputs.paper_targets(z_t)
+    c_p = beta_p / mid["f"]
     MO = L.TUNE_PS_MAX_OUTER
-    outer = dict(steps=[res5.n_outer_done[i] for i in range(len(z_t))], seconds=res5.seconds,
-                 beff_over_target=[[res5.beff[i * MO + o] / beff_t[i] for o in range(res5.n_outer_done[i])]
-                                   for i in range(len(z_t))],
+
+    def paper_truth(bs):
+        pk_p, sig_p = [], []
+        for z, b, c, ft in zip(z_t, bs, c_p, fbar_p):
+            def fbar_p_of(a):
+                L.apply_fgpa_ds(s, cosmo, mock["dens"], mock["eta"], ps_true, None, seed + 1,
+                                L.fgpa_struct([[a, 0, 0], [b, 0, 0], [c, 0, 0]]), flux, zb, work)
+                return float(fsum.item()) / float(cnt.item())
+            lo, hi = np.log(1e-6), np.log(1e3)
+            for _ in range(60):
+                m_ = 0.5 * (lo + hi)
+                if fbar_p_of(np.exp(m_)) > ft:
+                    lo = m_
+                else:
+                    hi = m_
+            fb = fbar_p_of(float(np.exp(0.5 * (lo + hi))))
+            sig_p.append(float(torch.sqrt(((flux.double() - fb) ** 2).mean())))
+            L.p1d(s, cosmo, flux, zb, L.P1dSpec(nk, k_edges.data_ptr(), float(z), float(mid["dpix"])), psum, pcnt,
+                  pwork)
+            pc = pcnt.cpu().numpy()
+            pk_p.append(np.where(pc > 0, psum.cpu().numpy() / np.maximum(pc, 1), np.nan))
+        return np.ascontiguousarray(np.stack(pk_p), dtype=np.float64), sig_p
+
+    b_paper = np.full(len(z_t), 0.35)
+    for i in range(len(z_t)):
+        spec.c_t[i], spec.fbar_t[i], spec.beff_t[i] = c_p[i], fbar_p[i], beff_p[i]
+    spec.f, spec.beff_at_z = mid["f"], 1
+    pk_p, sig_p = paper_truth(b_paper)
+    for i in range(len(z_t)):
+        spec.sigf_t[i] = sig_p[i]
+    spec.p1d_t = pk_p.ctypes.data
+    spec.n_outer = 1
+    res0 = L.tune_ps(spec, tw)
+    b_paper = b_paper * np.array([beff_p[i] * res0.growth[i] / res0.beff[i * MO] for i in range(len(z_t))])
+    pk_p, sig_p = paper_truth(b_paper)
+    for i in range(len(z_t)):
+        spec.sigf_t[i] = sig_p[i]
+    spec.p1d_t = pk_p.ctypes.data
+    spec.n_outer = 5
+    res5 = L.tune_ps(spec, tw)
+    steps = [res5.n_outer_done[i] for i in range(len(z_t))]
+    ratio = [[res5.beff[i * MO + o] / (beff_p[i] * res5.growth[i]) for o in range(steps[i])] for i in range(len(z_t))]
+    outer = dict(targets="paper: b_eff = 0.183 ((1+z)/3.3)^3.47 with respect to the matter field at z_t, "
+                         "beta = 1.76 ((1+z)/3.3)^-2.32 (c_t = beta/f), Fbar = exp(-0.0028 (1+z)^3.45)",
+                 b_eff_paper=list(map(float, beff_p)), beta_paper=list(map(float, beta_p)),
+                 fbar_paper=list(map(float, fbar_p)), growth=[res5.growth[i] for i in range(len(z_t))],
+                 b_truth=list(map(float, b_paper)),
+                 steps=steps, seconds=res5.seconds, beff_over_target=ratio,
+                 reached=[bool(steps[i] == 5 and abs(ratio[i][-1] - 1.0) < 0.02) for i in range(len(z_t))],
+                 stopped_unreachable=[bool(steps[i] < 5) for i in range(len(z_t))],
                  a=list(res5.a[:len(z_t)]), b=list(res5.b[:len(z_t)]),
                  fbar_last=[res5.fbar[i * M + n_iter - 1] for i in range(len(z_t))],
                  p1d_rel_rms_last=[res5.rms[i * M + n_iter - 1] for i in range(len(z_t))])
@@ -621,7 +827,7 @@ def tune_leg(L, torch, n_labels, train_steps):
     print("bench: training %d steps %.1f s, loss %.3g -> %.3g" % (train_steps, t_train, h[:20].mean(),
                                                                   h[-200:].mean()), file=sys.stderr, flush=True)
     spec_e, keep_e = L.tune_spec(mock["s"], mock["dens"], mock["eta"], cosmo, z_t, c_t, fbar_t, pk_t, k_edges,
-                                 mid["dpix"], a0=0.3, b0=1.5, emulator=emu, emu_checks=6)
+                                 mid["dpix"], a0=0.3, b0=1.5, emulator=emu, emu_checks=10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     re_ = L.tune_params(spec_e, L.LYA_TUNE_EMULATOR, work)
@@ -646,6 +852,7 @@ def tune_leg(L, torch, n_labels, train_steps):
         train_loss_final=float(h[-200:].mean()),
         gpu_evals_plain=[int(rp.gpu_evals[i]) for i in range(n)],
         gpu_evals_emulator=[int(re_.gpu_evals[i]) for i in range(n)],
+        emulator_fell_back_to_plain=[int(re_.fallback[i]) for i in range(n)],
         emulator_search_evals=[int(re_.evals[i]) for i in range(n)],
         a_plain=[rp.a[i] for i in range(n)], b_plain=[rp.b[i] for i in range(n)],
         a_emulator=[re_.a[i] for i in range(n)], b_emulator=[re_.b[i] for i in range(n)],
@@ -668,6 +875,8 @@ def main():
     ap.add_argument("--no-wide", action="store_true", help="skip the wide-angle eta_par leg")
     ap.add_argument("--no-gauss", action="store_true", help="skip the 7^3 Gaussian-kernel skewer pass")
     ap.add_argument("--no-quasars", action="store_true", help="skip the lognormal quasar leg")
+    ap.add_argument("--no-rocfft", action="store_true", help="skip the rocFFT comparison line")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 1024^3 FP32/BF16 precision leg")
     ap.add_argument("--tune-labels", type=int, default=100_000)
     ap.add_argument("--tune-steps", type=int, default=20_000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -823,20 +1032,26 @@ def main():
                paper_context="the paper's make_box runs about 8.0e5 box cells/s per 64-thread CPU node "
                              "(13 fields of a 2560x2560x1536 chunk, FFTW); other hardware and workload, "
                              "so vs_baseline is null")
-    if args.config == "precision":
-        print("bench: BF16 storage leg", file=sys.stderr, flush=True)
-        out["precision"] = precision_leg(L, torch, cfg, box, field, s, ps, cosmo, fg, flux, fsum, cnt, edges, stream)
-        out["precision"]["fp32_box_ms"] = box_ms
-        out["precision"]["fp32_skewer_ms"] = sk_ms
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, pixels / cells, args.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(cfg, pixels / cells, args.cpu_n, full_n=n, full_pixels=pixels)
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
     else:
         out["cpu_baseline"] = None
-    if not args.no_tune or not args.no_wide or not args.no_quasars:
+    if not (args.no_tune and args.no_wide and args.no_quasars and args.no_rocfft and args.no_precision):
         del field, bwork, swork, dens, eta, flux, dev
         torch.cuda.empty_cache()
+    if not args.no_rocfft:
+        print("bench: rocFFT comparison line", file=sys.stderr, flush=True)
+        fft_ms = sum(kernels[k]["mean_ms"] for k in ("fft_z_gen", "fft_y", "fft_x") if k in kernels)
+        out["rocfft"] = rocfft_leg(torch, n, fft_ms)
+    else:
+        out["rocfft"] = None
+    if not args.no_precision:
+        print("bench: precision configuration (FP32 and BF16 storage)", file=sys.stderr, flush=True)
+        out["precision"] = precision_leg(L, torch, stream)
+    else:
+        out["precision"] = None
     if not args.no_quasars:
         print("bench: lognormal quasar leg", file=sys.stderr, flush=True)
         out["quasars"] = quasar_leg(L, torch, stream, cfg, counted=args.config == TRAFFIC_CONFIG)
