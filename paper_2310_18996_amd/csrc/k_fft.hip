@@ -312,23 +312,50 @@ template <int N, int T, int NT, int GM, typename LIDX>
 __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, float2* lds, LIDX lidx, float* stab,
                                            float* stab_b) {
   constexpr int H = T / 2, NZ = N / 2 + 1;
+  constexpr int NG = (H * NZ + NT - 1) / NT;  // amplitude gathers per thread
+  constexpr int NP = H * (N / 2) / NT;        // Philox calls per thread
+  static_assert(H * (N / 2) % NT == 0, "whole Philox calls per thread");
   const int nx = ix;  // 0 < ix < N/2
-  // the amplitudes a pencil needs depend on |nz| only: gather them once, all
-  // at once, into LDS (the table is far larger than L2)
-  for (int w = threadIdx.x; w < H * NZ; w += NT) {
-    const int po = w / NZ, az = w % NZ;
-    const int ny = sfreq(iy0 + po, N);
-    stab[w] = g.table[nx * nx + ny * ny + az * az];
-    if (GM == GEN_GENERIC && g.table_b) stab_b[w] = g.table_b[nx * nx + ny * ny + az * az];
+  // The amplitudes a pencil needs depend on |nz| only: gather them once into
+  // LDS (the table is far larger than L2).  All of a thread's gathers are
+  // issued first and stay in flight while it draws its Philox words; they are
+  // written to LDS only after that.
+  float ga[NG], gb[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int w = static_cast<int>(threadIdx.x) + i * NT;
+    if (w < H * NZ) {
+      const int po = w / NZ, az = w % NZ;
+      const int ny = sfreq(iy0 + po, N);
+      ga[i] = g.table[nx * nx + ny * ny + az * az];
+      if (GM == GEN_GENERIC && g.table_b) gb[i] = g.table_b[nx * nx + ny * ny + az * az];
+    }
+  }
+  uint4 wds[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int w = static_cast<int>(threadIdx.x) + p * NT;
+    const int po = w / (N / 2), m = w % (N / 2);
+    const uint64_t ctr = (static_cast<uint64_t>(ix) * N + iy0 + po) * (N / 2) + m;
+    wds[p] = philox10_x3(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 0u, 0u),
+                         static_cast<uint32_t>(g.seed), static_cast<uint32_t>(g.seed >> 32));
+  }
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int w = static_cast<int>(threadIdx.x) + i * NT;
+    if (w < H * NZ) {
+      stab[w] = ga[i];
+      if (GM == GEN_GENERIC && g.table_b) stab_b[w] = gb[i];
+    }
   }
   __syncthreads();
-  for (int w = threadIdx.x; w < H * (N / 2); w += NT) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int w = static_cast<int>(threadIdx.x) + p * NT;
     const int po = w / (N / 2), m = w % (N / 2);
     const int iy = iy0 + po;
     const int ny = sfreq(iy, N);
-    const uint64_t ctr = (static_cast<uint64_t>(ix) * N + iy) * (N / 2) + m;
-    const uint4 wd = philox10_x3(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 0u, 0u),
-                                 static_cast<uint32_t>(g.seed), static_cast<uint32_t>(g.seed >> 32));
+    const uint4 wd = wds[p];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int iz = 2 * m + e;

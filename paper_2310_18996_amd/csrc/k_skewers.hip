@@ -53,14 +53,19 @@ __global__ void __launch_bounds__(256) k_skewer_finalize(int n_bins, const unsig
   }
 }
 
+// Box element loads, the storage type fixed at compile time (a run-time test
+// per corner splits the gathers into separate blocks that each wait for their
+// load, instead of issuing all of a pixel's gathers together).
+template <bool B16>
 __device__ __forceinline__ float2 ld_field(const SkewerArgs& a, size_t i) {
-  if (a.field) return a.field[i];
-  return unpack_bf16x2(a.field_bf16[i]);
+  if constexpr (B16) return unpack_bf16x2(a.field_bf16[i]);
+  else return a.field[i];
 }
 
+template <bool B16>
 __device__ __forceinline__ float2 ld_wide(const SkewerArgs& a, int k, size_t i) {
-  if (a.field) return a.wide[k][i];
-  return unpack_bf16x2(a.wide_bf16[k][i]);
+  if constexpr (B16) return unpack_bf16x2(a.wide_bf16[k][i]);
+  else return a.wide[k][i];
 }
 
 // Mode Y_m of the small-scale spectrum (0 < m <= ns/2) from its normal pair z.
@@ -150,6 +155,7 @@ enum { kSkTri = 0, kSkWide = 1, kSkGauss = 2 };
 // of sight"): the weights separate into 7 per axis, exp(-(o - t)^2/2) with
 // t = u - c in [-1/2, 1/2), and the average divides by their product sum.
 // Each z run of 7 voxels is contiguous in memory.
+template <bool B16>
 __device__ __forceinline__ void gauss7_at(const SkewerArgs& a, int64_t px, int64_t py, int64_t pz, int N, size_t NN,
                                           float& d, float& e) {
   float g[3][7], s[3];
@@ -179,7 +185,7 @@ __device__ __forceinline__ void gauss7_at(const SkewerArgs& a, int64_t px, int64
       float rx_ = 0.0f, ry_ = 0.0f;
 #pragma unroll
       for (int k = 0; k < 7; ++k) {
-        const float2 f = ld_field(a, row + ((c[2] + k - 3) & (N - 1)));
+        const float2 f = ld_field<B16>(a, row + ((c[2] + k - 3) & (N - 1)));
         rx_ += g[2][k] * f.x;
         ry_ += g[2][k] * f.y;
       }
@@ -210,6 +216,7 @@ __device__ __forceinline__ int wave_max(int v) {
   for (int w = 32; w >= 1; w >>= 1) v = max(v, __shfl_xor(v, w));
   return v;
 }
+template <bool B16>
 __device__ __forceinline__ bool gauss7_staged(const SkewerArgs& a, int64_t px, int64_t py, int64_t pz, bool valid,
                                               int64_t base_x, int64_t base_y, int64_t base_z, int N, size_t NN,
                                               float2* lds, int lane, float& d, float& e) {
@@ -242,7 +249,7 @@ __device__ __forceinline__ bool gauss7_staged(const SkewerArgs& a, int64_t px, i
     const int gx = static_cast<int>((base_x + lo[0] + vx) & (N - 1));
     const int gy = static_cast<int>((base_y + lo[1] + vy) & (N - 1));
     const int gz = static_cast<int>((base_z + lo[2] + vz) & (N - 1));
-    lds[v] = ld_field(a, gx * NN + static_cast<size_t>(gy) * N + gz);
+    lds[v] = ld_field<B16>(a, gx * NN + static_cast<size_t>(gy) * N + gz);
   }
   wave_sync();
   float ax_ = 0.0f, ay_ = 0.0f;
@@ -285,7 +292,7 @@ __device__ __forceinline__ float trilerp(float tx, float ty, float tz, float c00
   return c0 + tx * (c1 - c0);
 }
 
-template <int U, int MODE>
+template <int U, int MODE, bool B16>
 __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
   __shared__ float2 sbuf[kSkWaves][kHalfBuf];
   __shared__ float2 sgauss[MODE == kSkGauss ? kSkWaves : 1][MODE == kSkGauss ? kGaussCap : 1];
@@ -358,6 +365,30 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
         wxz = static_cast<float>(2.0 * ux * uz * ir2);
         wyz = static_cast<float>(2.0 * uy * uz * ir2);
       }
+      // fixed-point positions of the lane's pixels j = lane + 64 u, advanced by
+      // one addition per step of 64 U pixels (pixels past the end wrap like any
+      // other and are dropped)
+      int64_t pos[U][3];
+      const int64_t adv[3] = {64 * U * sx, 64 * U * sy, 64 * U * sz};
+      // position of the lane's pixels in the z(chi) table, in table steps
+      // times 2^32 (chi_j / kZTabH = chi0 / kZTabH - j dchi / kZTabH, each term
+      // rounded to 2^-32 steps: at most 2^-22 Mpc/h off at j = 2048)
+      int64_t zpos[U];
+      const int64_t zstep = llrint(a.dchi * (4294967296.0 / kZTabH));
+      if (a.do_flux) {
+        const int64_t z0 = llrint(chi0 * (4294967296.0 / kZTabH));
+#pragma unroll
+        for (int u = 0; u < U; ++u) zpos[u] = z0 - (lane + 64 * u) * zstep;
+      }
+      if (MODE != kSkGauss) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t j = lane + 64 * u;
+          pos[u][0] = ox + j * sx;
+          pos[u][1] = oy + j * sy;
+          pos[u][2] = oz + j * sz;
+        }
+      }
       // pixel j is in bin b when jb[b+1] <= j < jb[b]; each lane walks j upward
       // and therefore the bins downward, accumulating one bin at a time.  U
       // pixels per lane per step: all their gathers are issued before any is used.
@@ -380,37 +411,39 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
             // base cell: the chunk's first pixel, the same for every lane
             const int j1 = j0 - lane;
             const int64_t bx = (ox + j1 * sx) >> 32, by = (oy + j1 * sy) >> 32, bz = (oz + j1 * sz) >> 32;
-            if (!gauss7_staged(a, px, py, pz, valid, bx, by, bz, N, NN, sgauss[wv], lane, dl[0], el[0]))
-              gauss7_at(a, px, py, pz, N, NN, dl[0], el[0]);
+            if (!gauss7_staged<B16>(a, px, py, pz, valid, bx, by, bz, N, NN, sgauss[wv], lane, dl[0], el[0]))
+              gauss7_at<B16>(a, px, py, pz, N, NN, dl[0], el[0]);
           } else {
           float2 c[U][8];
           float t3[U][3];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int j = j0 + 64 * u;
-            const int jj = j < np ? j : j0;  // an in-range pixel (its result is dropped)
-            const int64_t px = ox + jj * sx, py = oy + jj * sy, pz = oz + jj * sz;
-            const int ix = static_cast<int>((px >> 32) & (N - 1));
-            const int iy = static_cast<int>((py >> 32) & (N - 1));
-            const int iz = static_cast<int>((pz >> 32) & (N - 1));
-            const int jx = (ix + 1) & (N - 1), jy = (iy + 1) & (N - 1), jz = (iz + 1) & (N - 1);
+            const int64_t px = pos[u][0], py = pos[u][1], pz = pos[u][2];
+            pos[u][0] = px + adv[0];
+            pos[u][1] = py + adv[1];
+            pos[u][2] = pz + adv[2];
+            const uint32_t msk = static_cast<uint32_t>(N - 1);
+            const uint32_t ix = static_cast<uint32_t>(px >> 32) & msk;
+            const uint32_t iy = static_cast<uint32_t>(py >> 32) & msk;
+            const uint32_t iz = static_cast<uint32_t>(pz >> 32) & msk;
+            const uint32_t jx = (ix + 1) & msk, jy = (iy + 1) & msk, jz = (iz + 1) & msk;
             t3[u][0] = static_cast<float>(static_cast<uint32_t>(px)) * 2.3283064365386963e-10f;
             t3[u][1] = static_cast<float>(static_cast<uint32_t>(py)) * 2.3283064365386963e-10f;
             t3[u][2] = static_cast<float>(static_cast<uint32_t>(pz)) * 2.3283064365386963e-10f;
-            const size_t r00 = ix * NN + static_cast<size_t>(iy) * N;
-            const size_t r01 = ix * NN + static_cast<size_t>(jy) * N;
-            const size_t r10 = jx * NN + static_cast<size_t>(iy) * N;
-            const size_t r11 = jx * NN + static_cast<size_t>(jy) * N;
-            const size_t ci[8] = {r00 + iz, r00 + jz, r01 + iz, r01 + jz, r10 + iz, r10 + jz, r11 + iz, r11 + jz};
             if (MODE == kSkWide) {
+              // plane offsets in 64 bits, offsets within a plane (< n^2) in 32
+              const size_t x0 = static_cast<size_t>(ix) * NN, x1 = static_cast<size_t>(jx) * NN;
+              const uint32_t y0 = iy * static_cast<uint32_t>(N), y1 = jy * static_cast<uint32_t>(N);
+              const size_t ci[8] = {x0 + (y0 + iz), x0 + (y0 + jz), x0 + (y1 + iz), x0 + (y1 + jz),
+                                    x1 + (y0 + iz), x1 + (y0 + jz), x1 + (y1 + iz), x1 + (y1 + jz)};
               // all 32 gathers first, then eta_par = u_p u_q eta^pq per corner
               float2 w0[8], w1[8], w2[8], w3[8];
 #pragma unroll
               for (int k = 0; k < 8; ++k) {
-                w0[k] = ld_field(a, ci[k]);
-                w1[k] = ld_wide(a, 0, ci[k]);
-                w2[k] = ld_wide(a, 1, ci[k]);
-                w3[k] = ld_wide(a, 2, ci[k]);
+                w0[k] = ld_field<B16>(a, ci[k]);
+                w1[k] = ld_wide<B16>(a, 0, ci[k]);
+                w2[k] = ld_wide<B16>(a, 1, ci[k]);
+                w3[k] = ld_wide<B16>(a, 2, ci[k]);
               }
 #pragma unroll
               for (int k = 0; k < 8; ++k) {
@@ -419,8 +452,25 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
                 c[u][k] = make_float2(w0[k].x, e);
               }
             } else {
+              // byte addresses: each x plane's start as one 32 x 32 -> 64-bit
+              // multiply-add on the box pointer, the corner's offset within the
+              // plane (below 2^25 bytes) added to it
+              constexpr uint32_t ES = B16 ? 4u : 8u;
+              const char* fb = B16 ? reinterpret_cast<const char*>(a.field_bf16) : reinterpret_cast<const char*>(a.field);
+              const uint32_t pb = static_cast<uint32_t>(NN) * ES;  // plane pitch in bytes (< 2^32)
+              const char* p0 = fb + static_cast<uint64_t>(ix) * pb;
+              const char* p1 = fb + static_cast<uint64_t>(jx) * pb;
+              const uint32_t y0 = iy * (static_cast<uint32_t>(N) * ES), y1 = jy * (static_cast<uint32_t>(N) * ES);
+              const uint32_t z0 = iz * ES, z1 = jz * ES;
+              const uint32_t o[4] = {y0 + z0, y0 + z1, y1 + z0, y1 + z1};
 #pragma unroll
-              for (int k = 0; k < 8; ++k) c[u][k] = ld_field(a, ci[k]);
+              for (int k = 0; k < 8; ++k) {
+                const char* pk = (k < 4 ? p0 : p1) + o[k & 3];
+                if constexpr (B16)
+                  c[u][k] = unpack_bf16x2(*reinterpret_cast<const uint32_t*>(pk));
+                else
+                  c[u][k] = *reinterpret_cast<const float2*>(pk);
+              }
             }
           }
 #pragma unroll
@@ -466,10 +516,18 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
             const int j = j0 + 64 * u;
             if (j >= np) break;
             const float d = dd[u], e = ee[u];
-            const double uu = pixel_chi(chi0, j, a.dchi) * (1.0 / kZTabH);
-            int iu = static_cast<int>(uu);
-            iu = iu < 0 ? 0 : (iu > kZTabN - 2 ? kZTabN - 2 : iu);
-            const float t = static_cast<float>(uu - iu);
+            const int64_t zp = zpos[u];
+            const int64_t ip = zp >> 32;
+            int iu;
+            float t;
+            if (ip >= 0 && ip <= kZTabN - 2) {
+              iu = static_cast<int>(ip);
+              t = static_cast<float>(static_cast<uint32_t>(zp)) * 2.3283064365386963e-10f;
+            } else {  // beyond the table: the end interval continued linearly
+              iu = ip < 0 ? 0 : kZTabN - 2;
+              t = static_cast<float>(static_cast<double>(zp - (static_cast<int64_t>(iu) << 32)) *
+                                     2.3283064365386963e-10);
+            }
             const float zt0 = a.ztab[iu], zt1 = a.ztab[iu + 1];
             const float x = (zt0 + t * (zt1 - zt0)) + (1.0f - kFgpaX0);   // (1+z) - x0
             const float ca = a.cf[0][0] + x * (a.cf[0][1] + x * a.cf[0][2]);
@@ -495,6 +553,8 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
               }
             }
           }
+#pragma unroll
+          for (int u = 0; u < U; ++u) zpos[u] -= 64 * U * zstep;
         }
       }
       if (cnt) {
@@ -527,6 +587,29 @@ int device_cus() {
   return cached[dev];
 }
 
+template <bool B16>
+void launch_skewer_kernel(const SkewerArgs& a, int u, dim3 grid, hipStream_t st) {
+  if (a.is_gauss) {
+    // 343 gathers per pixel: one pixel per lane at a time
+    LYA_TIMED("skewers_gauss", st, hipLaunchKernelGGL((k_skewers<1, kSkGauss, B16>), grid, dim3(kSkNT), 0, st, a));
+  } else if (a.is_wide) {
+    // four boxes per pixel: at most two pixels per lane in flight
+    if (u == 1)
+      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<1, kSkWide, B16>), grid, dim3(kSkNT), 0, st, a));
+    else
+      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<2, kSkWide, B16>), grid, dim3(kSkNT), 0, st, a));
+  } else if (u == 1) {
+    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
+              hipLaunchKernelGGL((k_skewers<1, kSkTri, B16>), grid, dim3(kSkNT), 0, st, a));
+  } else if (u == 2) {
+    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
+              hipLaunchKernelGGL((k_skewers<2, kSkTri, B16>), grid, dim3(kSkNT), 0, st, a));
+  } else {
+    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
+              hipLaunchKernelGGL((k_skewers<4, kSkTri, B16>), grid, dim3(kSkNT), 0, st, a));
+  }
+}
+
 hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st) {
   LYA_TIMED("skewer_reset", st,
             hipLaunchKernelGGL(k_skewer_reset, dim3(1), dim3(256), 0, st, a.queue, a.bin_sum, a.bin_cnt));
@@ -536,25 +619,10 @@ hipError_t launch_skewers(const SkewerArgs& a, hipStream_t st) {
   if (blocks < 1) blocks = 1;
   const int u = a.unroll == 1 || a.unroll == 4 ? a.unroll : 2;
   const dim3 grid(static_cast<unsigned>(blocks));
-  if (a.is_gauss) {
-    // 343 gathers per pixel: one pixel per lane at a time
-    LYA_TIMED("skewers_gauss", st, hipLaunchKernelGGL((k_skewers<1, kSkGauss>), grid, dim3(kSkNT), 0, st, a));
-  } else if (a.is_wide) {
-    // four boxes per pixel: at most two pixels per lane in flight
-    if (u == 1)
-      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<1, kSkWide>), grid, dim3(kSkNT), 0, st, a));
-    else
-      LYA_TIMED("skewers_wide", st, hipLaunchKernelGGL((k_skewers<2, kSkWide>), grid, dim3(kSkNT), 0, st, a));
-  } else if (u == 1) {
-    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL((k_skewers<1, kSkTri>), grid, dim3(kSkNT), 0, st, a));
-  } else if (u == 2) {
-    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL((k_skewers<2, kSkTri>), grid, dim3(kSkNT), 0, st, a));
-  } else {
-    LYA_TIMED(a.in_dens ? "apply_fgpa" : "skewers", st,
-              hipLaunchKernelGGL((k_skewers<4, kSkTri>), grid, dim3(kSkNT), 0, st, a));
-  }
+  if (a.field_bf16)
+    launch_skewer_kernel<true>(a, u, grid, st);
+  else
+    launch_skewer_kernel<false>(a, u, grid, st);
   if (a.n_bins > 0 && a.do_flux)
     LYA_TIMED("skewer_finalize", st,
               hipLaunchKernelGGL(k_skewer_finalize, dim3(1), dim3(256), 0, st, a.n_bins, a.bin_sum, a.bin_cnt,
