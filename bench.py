@@ -52,17 +52,20 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 4 GiB device copy (FETCH_SIZE x 2, WRITE_SIZE x 1);
 # profiles/box2048_skewers1M_hbm_traffic.md and, for the quasar draw of the
 # quasar leg, profiles/quasars2048_kernel_stats_hbm_traffic.md.  Keyed by (kernel, FFT variant)
-# for the strided passes; valid only for the kernels as they were when the
-# counters were taken (a changed kernel must drop its entry) and reported only
-# for that workload.
-TRAFFIC = {("qso_draw", None): 137560151198}
+# for the strided passes and by (chunk, blocks per CU, unroll) for the skewer
+# kernel; valid only for the kernels as they were when the counters were taken
+# (a changed kernel must drop its entry) and reported only for that workload.
+TRAFFIC = {("fft_x", 9): 137505215170, ("fft_y", 8): 140257527650, ("fft_z_gen", None): 95813927866,
+           ("skewers", (4, 4, 1)): 14509553350, ("qso_draw", None): 137560151198}
 TRAFFIC_CONFIG = "big"
 
 
 def measured_traffic(L, name, n):
+    t = L.get_tuning(n)
     if name in ("fft_y", "fft_x"):
-        t = L.get_tuning(n)
         return TRAFFIC.get((name, t.fft_y if name == "fft_y" else t.fft_x))
+    if name == "skewers":
+        return TRAFFIC.get((name, (t.sk_chunk, t.sk_blocks_per_cu, t.sk_unroll)))
     return TRAFFIC.get((name, None))
 
 

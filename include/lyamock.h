@@ -591,10 +591,10 @@ int lya_quasar_skewers(const lya_box* box, const lya_qso_los_spec* spec, const l
  *                     in the pipelined kernel, order 0/1.  Boxes below 1024
  *                     have variants 0 and 1 only.  Defaults: y 8, x 9 from
  *                     1024 up, y 0, x 1 below.
- *   sk_chunk          skewers taken per pull from the skewer work queue (default 8);
+ *   sk_chunk          skewers taken per pull from the skewer work queue (default 4);
  *   sk_blocks_per_cu  persistent skewer blocks per CU, 1..4 (default 4);
  *   sk_unroll         pixels per lane whose gathers are issued together, 1, 2 or 4
- *                     (default 2).
+ *                     (default 1).
  * The table is process-wide and applies to every later call for that n. */
 #define LYA_FFT_VARIANTS 14
 typedef struct {

@@ -17,9 +17,9 @@ namespace lya {
 
 namespace {
 std::mutex g_mu;
-int g_chunk[12] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8};
+int g_chunk[12] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4};
 int g_bpc[12] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4};
-int g_unroll[12] = {2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+int g_unroll[12] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
 int lg(int n) {
   int l = 0;
   while ((1 << l) < n && l < 11) ++l;
