@@ -56,6 +56,15 @@ stays, then runs the P_s iteration again; five times), read as:
   current sigma_g allows has no solution: the outer loop then stops and keeps
   the last step (a poor first step, e.g. sigma_F from a binned P1D that
   misses most of the power, leads there).
+
+The emulator mode of the library (not in the paper) solves, at each z_t, the
+problem the iteration approaches: P_s keeps the configuration's form
+amp exp(-(k/kcut)^2) with (amp, kcut) free, (a, s) follow from (Fbar_t,
+sigma_F,t), or with the outer loop from (Fbar_t, b_eff,t) at the sigma_g of
+(amp, kcut), b = s / sigma_g, and (amp, kcut) minimise
+sum_b (P1D_b / P_t,b - 1)^2 over the bins with a target.  ps_fit_problem
+states that objective; statistics_ps is one evaluation of it (and one
+emulator training label).
 """
 import numpy as np
 from scipy import integrate, optimize, special
@@ -156,6 +165,12 @@ def sigma_s2(amp, kcut, ratio, edges_k, dpix):
     return tot / np.pi
 
 
+def sigma_s2_gauss(amp, kcut, dpix):
+    """(1/pi) int_0^{pi/dpix} amp exp(-(k/kcut)^2) dk in closed form:
+    amp kcut erf(pi / (dpix kcut)) / (2 sqrt(pi))."""
+    return float(amp * kcut * special.erf(np.pi / (dpix * kcut)) / (2.0 * np.sqrt(np.pi)))
+
+
 def delta_s_tab(seed, qid, npix, dpix, amp, kcut, ratio, edges_k):
     """delta_S of quasar qid with P_s = amp exp(-(k/kcut)^2) r(bin of k)."""
     ns = next_pow2(npix)
@@ -224,18 +239,70 @@ def _inner(dl, eta, sk, seed, z_t, c_t, pk_t, k_edges, edges_k, dpix, amp0, kcut
         ss2 = sigma_s2(amp0, kcut0, used, edges_k, dpix)
         sg = np.sqrt(sl2 + ss2 + c_t * c_t * se2 + 2.0 * c_t * cov)
         b = s / sg
-        dens = np.array(dl, dtype=np.float64, copy=True)
-        for q in range(len(npix)):
-            o, nq = int(off[q]), int(npix[q])
-            if nq > 0:
-                dens[o:o + nq] += delta_s_tab(seed, int(sk["id_base"]) + q, nq, dpix, amp0, kcut0, used, edges_k)
-        F = np.exp(-a * np.exp(b * (dens + c_t * np.asarray(eta, dtype=np.float64))))
-        fbar = float(np.mean(F))
-        ps, cnt = op1d.p1d(F, sk, [-1e30, 1e30], [fbar], k_edges, z_t, dpix, omega_m)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            pk = np.where(cnt > 0, ps / np.maximum(cnt, 1), np.nan)
+        fbar, pk = _statistics(dl, eta, sk, seed, z_t, c_t, a, b, amp0, kcut0, used, edges_k, k_edges, dpix, omega_m)
         hist.append(dict(fbar=fbar, p1d=pk, sigma_g=float(sg), b=float(b), ratio=used))
         upd = np.isfinite(pk_t) & np.isfinite(pk) & (pk > 0)
         ratio = used.copy()
         ratio[upd] = used[upd] * np.asarray(pk_t)[upd] / pk[upd]
     return hist, ratio
+
+
+def _statistics(dl, eta, sk, seed, z_t, c_t, a, b, amp, kcut, ratio, edges_k, k_edges, dpix, omega_m):
+    """Fbar and the P1D per bin of the stored pixels with delta_S of
+    P_s = amp exp(-(k/kcut)^2) r(bin of k) added, under constant (a, b, c_t)."""
+    npix = np.asarray(sk["npix"])
+    off = np.asarray(sk["offset"])
+    dens = np.array(dl, dtype=np.float64, copy=True)
+    for q in range(len(npix)):
+        o, nq = int(off[q]), int(npix[q])
+        if nq > 0:
+            dens[o:o + nq] += delta_s_tab(seed, int(sk["id_base"]) + q, nq, dpix, amp, kcut, ratio, edges_k)
+    F = np.exp(-a * np.exp(b * (dens + c_t * np.asarray(eta, dtype=np.float64))))
+    fbar = float(np.mean(F))
+    ps, cnt = op1d.p1d(F, sk, [-1e30, 1e30], [fbar], k_edges, z_t, dpix, omega_m)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        pk = np.where(cnt > 0, ps / np.maximum(cnt, 1), np.nan)
+    return fbar, pk
+
+
+def statistics_ps(dl, eta, sk, seed, z_t, c_t, a, b, amp, kcut, k_edges, dpix, omega_m=cosmology.OMEGA_M):
+    """(Fbar, P1D per bin) with delta_S of P_s = amp exp(-(k/kcut)^2) (no
+    table) redrawn on every skewer and constant (a, b, c_t) at z_t."""
+    k_edges = np.asarray(k_edges, dtype=np.float64)
+    one = np.ones(len(k_edges) - 1)
+    return _statistics(dl, eta, sk, seed, z_t, c_t, a, b, amp, kcut, one, k_edges * dv_per_dchi(z_t, omega_m),
+                       k_edges, dpix, omega_m)
+
+
+def ps_fit_problem(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, dpix, omega_m=cosmology.OMEGA_M,
+                   sigf_t=None, beff_t=None, f=1.0):
+    """The emulator mode's problem at one z_t as a function of
+    th = (ln amp, ln kcut): returns a callable giving (a, b, s, Fbar, P1D,
+    objective) at th, the objective sum_b (P1D_b / P_t,b - 1)^2 over the bins
+    with a finite target.  (a, s) from (fbar_t, sigma_F,t) when beff_t is
+    None, else from (fbar_t, beff_t) at sigma_g(th) (beta = f c_t)."""
+    k_edges = np.asarray(k_edges, dtype=np.float64)
+    pk_t = np.asarray(pk_t, dtype=np.float64)
+    if sigf_t is None:
+        sigf_t = fbar_t * np.sqrt(sigma_df2_target(pk_t, k_edges))
+    sl2, se2, cov = moments(dl, eta)
+    sig0 = sl2 + c_t * c_t * se2 + 2.0 * c_t * cov
+    a0, s0 = fit_a_s(fbar_t, sigf_t)
+    ok = np.isfinite(pk_t)
+
+    def at(th):
+        amp, kcut = float(np.exp(th[0])), float(np.exp(th[1]))
+        sg = np.sqrt(sig0 + sigma_s2_gauss(amp, kcut, dpix))
+        if beff_t is None:
+            a, s = a0, s0
+        else:
+            fit = fit_a_s_bias(fbar_t, beff_t, sg, f * c_t, x0=(a0, s0))
+            if fit is None:
+                return None
+            a, s = fit
+        b = s / sg
+        fbar, pk = statistics_ps(dl, eta, sk, seed, z_t, c_t, a, b, amp, kcut, k_edges, dpix, omega_m)
+        obj = float(np.sum((pk[ok] / pk_t[ok] - 1.0) ** 2))
+        return dict(a=a, b=b, s=s, sigma_g=float(sg), fbar=fbar, p1d=pk, objective=obj)
+
+    return at

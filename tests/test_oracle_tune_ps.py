@@ -189,3 +189,81 @@ def test_outer_steps_reach_the_bias_target():
     assert abs(runs[3][0]["beff"][-1] / beff_t - 1) < abs(runs[1][0]["beff"][-1] / beff_t - 1)
     assert runs[3][1] < runs[1][1]
     assert abs(runs[3][0]["hist"][-1]["fbar"] / fbar_t - 1) < 0.03
+
+
+def test_sigma_s2_of_the_gaussian_form_in_closed_form():
+    for amp, kc, dpix in ((1.0, 1.5, 0.2), (2.5, 0.4, 0.27375), (0.3, 8.0, 0.5)):
+        num = integrate.quad(lambda k: amp * np.exp(-(k / kc) ** 2), 0.0, np.pi / dpix, epsabs=1e-15, limit=200)[0]
+        np.testing.assert_allclose(tune_ps.sigma_s2_gauss(amp, kc, dpix), num / np.pi, rtol=1e-12)
+
+
+def _tiny_subset(n_sk):
+    """The tiny mock's stored pixels without delta_S (oracle box and skewers),
+    restricted to its first n_sk skewers."""
+    cfg = mockinputs.config("tiny")
+    n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
+    box = field.make_box(n, seed, oracle_table(cfg["pk"], n, dx), ("delta", "zz"), f=cfg["f"])
+    sk = mockinputs.skewer_table(cfg)
+    dl, eta = skewers.draw_skewers(box.real, box.imag, sk, seed)
+    sub = dict(sk)
+    for key in ("npix", "offset", "chi0", "origin_fx", "step_fx"):
+        if key in sub:
+            sub[key] = np.asarray(sk[key])[:n_sk]
+    used = int(sub["offset"][-1] + sub["npix"][-1])
+    sub["total"] = used
+    return cfg, sub, np.asarray(dl)[:used], np.asarray(eta)[:used]
+
+
+def test_statistics_without_small_scale_power_are_the_plain_evaluation():
+    from oracle import tune
+    cfg, sk, dl, eta = _tiny_subset(120)
+    k_edges = p1d.log_k_edges()
+    a, b, c, z = 0.3, 1.5, 1.1, 2.6
+    fb0, pk0 = tune.evaluate(dl, eta, sk, a, b, c, z, k_edges, cfg["dpix"])
+    fb, pk = tune_ps.statistics_ps(dl, eta, sk, 7, z, c, a, b, 1e-300, 1.5, k_edges, cfg["dpix"])
+    np.testing.assert_allclose(fb, fb0, rtol=1e-13)
+    ok = np.isfinite(pk0)
+    np.testing.assert_allclose(pk[ok], pk0[ok], rtol=1e-11)
+    # with small-scale power present the 1D power moves
+    fb2, pk2 = tune_ps.statistics_ps(dl, eta, sk, 7, z, c, a, b, 1.5, 1.2, k_edges, cfg["dpix"])
+    assert np.max(np.abs(pk2[ok] / pk0[ok] - 1)) > 0.05
+
+
+@pytest.mark.parametrize("outer", [False, True])
+def test_small_scale_power_fit_recovers_a_truth_in_the_family(outer):
+    # the truth: delta_S of (amp, kcut) = (1.8, 1.0) with the mock's own key
+    # (skewers.delta_s), (a, s) = (0.3, 2.2), b = s / sigma_g with sigma_g from
+    # the measured moments and a numerical integral of P_s, its P1D from
+    # p1d.p1d; from P_s^0 = (1.0, 1.5) a least-squares solve of the problem
+    # must find (1.8, 1.0)
+    from scipy import optimize
+    cfg, sk, dl, eta = _tiny_subset(120)
+    k_edges = p1d.log_k_edges()
+    dpix, seed, z_t, c_t, f = cfg["dpix"], 11, 2.4, 1.2, cfg["f"]
+    amp, kc, a, s = 1.8, 1.0, 0.3, 2.2
+    g = np.asarray(dl, dtype=np.float64) + c_t * eta
+    ss2 = integrate.quad(lambda k: amp * np.exp(-(k / kc) ** 2), 0.0, np.pi / dpix, epsabs=1e-15)[0] / np.pi
+    sg = np.sqrt(np.var(g) + ss2)
+    dens = np.array(dl, dtype=np.float64, copy=True)
+    for q in range(len(sk["npix"])):
+        o, m = int(sk["offset"][q]), int(sk["npix"][q])
+        dens[o:o + m] += skewers.delta_s(seed, q, m, dpix, amp, kc)
+    F = np.exp(-a * np.exp((s / sg) * (dens + c_t * eta)))
+    fb = float(F.mean())
+    ps, cnt = p1d.p1d(F, sk, [-1e30, 1e30], [fb], k_edges, z_t, dpix)
+    pk_t = np.where(cnt > 0, ps / np.maximum(cnt, 1), np.nan)
+    f1, sf = tune_ps.gauss_fbar_sigf(a, s)
+    kw = dict(beff_t=tune_ps.effective_bias(a, s, sg, f * c_t), f=f) if outer else {}
+    at = tune_ps.ps_fit_problem(dl, eta, sk, seed, z_t, c_t, f1, pk_t, k_edges, dpix, sigf_t=sf, **kw)
+    ok = np.isfinite(pk_t)
+
+    def resid(th):
+        r = at(th)
+        return r["p1d"][ok] / pk_t[ok] - 1.0
+
+    sol = optimize.least_squares(resid, [0.0, np.log(1.5)], xtol=1e-12, ftol=1e-14, gtol=1e-14)
+    got = at(sol.x)
+    print("fit (amp, kcut) = (%.6f, %.6f), objective %.2e" % (np.exp(sol.x[0]), np.exp(sol.x[1]), got["objective"]))
+    np.testing.assert_allclose(np.exp(sol.x), [amp, kc], rtol=1e-5)
+    np.testing.assert_allclose([got["a"], got["s"]], [a, s], rtol=1e-6)
+    assert got["objective"] < 1e-12
