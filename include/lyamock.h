@@ -369,9 +369,30 @@ int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, v
  * beff[z][o] is the effective bias with respect to the box after step o
  * (sigma_g of its last iteration).  fbar and rms then describe the last
  * step's iterations.
+ *
+ * Emulator mode (mode = LYA_TUNE_PS_EMULATOR; not in the paper): P_s keeps
+ * the form ps_amp exp(-(k/ps_kcut)^2) with (amp, kcut) free, and each z_t
+ * solves at once what the iterations above approach step by step: P1D(amp,
+ * kcut) = P_t in least squares over the bins with a target, with (a, s) from
+ * (fbar_t, sigma_F,t) (n_outer <= 1) or from (fbar_t, beff_t) at the sigma_g
+ * of (amp, kcut) (n_outer >= 2), and b = s / sigma_g.  The search runs on
+ * emu[z] (inputs (a, b, amp, kcut) at (c_t, z_t), outputs (Fbar, P_1..P_nk),
+ * trained on lya_emulator_labels_ps) plus a correction: after each search one
+ * GPU evaluation at its optimum sets the model's offset to the measured
+ * statistics there and a Broyden update corrects its slope, as in
+ * lya_tune_params.  It stops when a check moves (ln amp, ln kcut) by at most
+ * 5e-4, or after emu_checks GPU evaluations; a z_t that has not settled by
+ * then runs the plain iteration instead (fallback[z] = 1).  Results: a, b, s
+ * and ps_fit[2 z .. 2 z + 1] = (amp, kcut) of the last check, p1d its P1D,
+ * fbar[z][0] and rms[z][0] its mean flux and relative RMS P1D error, ratio
+ * the fitted P_s over P_s^0 at each bin's centre (geometric mean of its
+ * edges in h/Mpc), beff[z][0] the effective bias there, n_outer_done[z] = 1.
+ * gpu_evals[z] counts GPU evaluations of the statistics in both modes.
  * Synchronous; GPU work on `stream`; errors in lya_tune_ps_last_error(). */
 #define LYA_TUNE_PS_MAX_ITER 16
 #define LYA_TUNE_PS_MAX_OUTER 8
+#define LYA_TUNE_PS_RATIOS 0
+#define LYA_TUNE_PS_EMULATOR 1
 typedef struct {
   const lya_skewers* sk;     /* npix, offset, chi0, dchi, id_base used */
   const float* dens_l;       /* device: delta_L per pixel (no delta_S) */
@@ -389,6 +410,9 @@ typedef struct {
   double beff_t[LYA_TUNE_MAX_Z];  /* outer loop: target effective bias per z_t (> 0) */
   double f;                  /* outer loop: growth rate of the boxes' eta_par (beta = f c_t) */
   int32_t beff_at_z;         /* outer loop: 1 = beff_t is with respect to the matter field at z_t */
+  int32_t mode;              /* LYA_TUNE_PS_RATIOS (the paper's iteration) or LYA_TUNE_PS_EMULATOR */
+  const void* emu[LYA_TUNE_MAX_Z];  /* emulator mode: device emulator per z_t, 1 + n_kbins outputs */
+  int32_t emu_checks;        /* emulator mode: GPU evaluations per z_t, 1..16 */
 } lya_tune_ps_spec;
 
 typedef struct {
@@ -402,11 +426,27 @@ typedef struct {
   double beff[LYA_TUNE_MAX_Z * LYA_TUNE_PS_MAX_OUTER]; /* [z_t][outer step] */
   int32_t n_outer_done[LYA_TUNE_MAX_Z];
   double growth[LYA_TUNE_MAX_Z];                       /* G(z_t) if beff_at_z, else 1 */
+  double ps_fit[2 * LYA_TUNE_MAX_Z];                   /* emulator mode: (amp, kcut) per z_t */
+  int32_t gpu_evals[LYA_TUNE_MAX_Z];                   /* GPU evaluations of the statistics per z_t */
+  int32_t fallback[LYA_TUNE_MAX_Z];                    /* emulator mode: 1 where the plain iteration ran */
 } lya_tune_ps_result;
 
 size_t lya_tune_ps_workspace_size(int64_t n_sk, int64_t n_pixels, int32_t n_kbins);
 int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* work, size_t work_bytes, void* stream);
 const char* lya_tune_ps_last_error(void);
+
+/* Training labels for the emulator of lya_tune_ps's emulator mode at tuning
+ * redshift z_t[zi]: for each host draw (a, b, amp, kcut) (draws[4 i + 0..3],
+ * FP64), delta_S is drawn on every skewer with P_s(k) = amp exp(-(k/kcut)^2)
+ * (Philox stream 1, key spec->seed, as lya_apply_fgpa_ds draws it) and added
+ * to dens_l; F = exp(-a exp(b (delta_L + delta_S + c_t eta))) with c_t =
+ * c_t[zi]; y[i][0] = the mean flux of all pixels and y[i][1 + b] the mean
+ * P1D of k bin b (lya_p1d's estimator with one redshift bin, velocity units
+ * at z_t[zi]) on the device (n_out = 1 + n_kbins).  Skewers must have at
+ * most 2048 pixels (else the label is NaN).  Uses the lya_tune_ps workspace;
+ * asynchronous; errors in lya_tune_ps_last_error(). */
+int lya_emulator_labels_ps(const lya_tune_ps_spec* spec, int32_t zi, const double* draws, int64_t n, float* y,
+                           void* work, size_t work_bytes, void* stream);
 
 /* Tuning emulator (not in the paper: a surrogate for the evaluations of the
  * tuning loop above).  A multilayer perceptron 4 -> 256 -> 256 -> 256 -> n_out

@@ -68,85 +68,6 @@ __device__ __forceinline__ float2 ld_wide(const SkewerArgs& a, int k, size_t i) 
   else return a.wide[k][i];
 }
 
-// Mode Y_m of the small-scale spectrum (0 < m <= ns/2) from its normal pair z.
-__device__ __forceinline__ float2 ps_mode(const SkewerArgs& a, int m, int ns, float amp_scale, float dk2, float2 z) {
-  const float kk = static_cast<float>(m) * static_cast<float>(m) * dk2;   // (k/kcut)^2
-  float ratio = 1.0f;
-  if (a.ps_ratio) {
-    // the mode's k bin (FP64, so the bin decision matches a double-precision
-    // reference): the largest b with edge_b <= k, clamped to the table
-    const double k = (2.0 * M_PI / (static_cast<double>(ns) * a.dpix)) * m;
-    const double* e = a.ps_edges_k;
-    int b = 0;
-    if (k >= e[a.ps_nb]) {
-      b = a.ps_nb - 1;
-    } else if (k >= e[0]) {
-      int lo = 0, hi = a.ps_nb;   // e[lo] <= k < e[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (e[mid] <= k) lo = mid; else hi = mid;
-      }
-      b = lo;
-    }
-    ratio = a.ps_ratio[b];
-  }
-  const float amp = __builtin_amdgcn_sqrtf(amp_scale * __expf(-kk) * ratio);
-  float2 w = (m == ns / 2) ? make_float2(z.x, 0.0f) : make_float2(z.x * kSqrtHalf, z.y * kSqrtHalf);
-  if (a.ps_fixed_amp) {
-    const float r = rsqrtf(w.x * w.x + w.y * w.y);
-    w.x *= r;
-    w.y *= r;
-  }
-  return make_float2(amp * w.x, amp * w.y);
-}
-
-// delta_S of one skewer by one wavefront into buf (pixel 2n in .x and pixel
-// 2n+1 in .y of element pidx(n)); ns = next_pow2(npix) >= 2.
-__device__ void small_scale_wave(const SkewerArgs& a, uint64_t qid, int ns, float2* buf, const float2* tw, int lane) {
-  const int M = ns / 2;
-  const float amp_scale = static_cast<float>(a.ps_amp / (ns * a.dpix));
-  const double dk = 2.0 * M_PI / (ns * a.dpix) / a.ps_kcut;
-  const float dk2 = static_cast<float>(dk * dk);
-  const int twstep = kTw2048 / ns;  // w^k = exp(2 pi i k / ns)
-  // the modes Y_1 .. Y_M into buf (Y_M in slot 0: the DC mode is zero).  Mode
-  // m is linear index (qid << 33) + m of stream 1, so the modes 2i and 2i + 1
-  // share one Philox call (counter = linear index >> 1, words 0-1 and 2-3).
-  for (int i = lane; i <= M / 2; i += 64) {
-    const uint64_t ctr = ((qid << 33) + 2 * static_cast<uint64_t>(i)) >> 1;
-    const uint4 wd = philox10_x3(make_uint4(static_cast<uint32_t>(ctr), static_cast<uint32_t>(ctr >> 32), 1u, 0u),
-                                 static_cast<uint32_t>(a.seed), static_cast<uint32_t>(a.seed >> 32));
-    const int m0 = 2 * i, m1 = 2 * i + 1;
-    if (m0 >= 1 && m0 <= M) buf[pidx(m0 == M ? 0 : m0)] = ps_mode(a, m0, ns, amp_scale, dk2, box_muller(wd.x, wd.y));
-    if (m1 <= M) buf[pidx(m1 == M ? 0 : m1)] = ps_mode(a, m1, ns, amp_scale, dk2, box_muller(wd.z, wd.w));
-  }
-  wave_sync();
-  // Z_k = (Y_k + Y_{k+M}) + i (Y_k - Y_{k+M}) w^k with Y_{k+M} = conj(Y_{M-k});
-  // a lane reads both of its slots k and M - k before writing them
-  for (int k = lane; k <= M / 2; k += 64) {
-    if (k == 0) {
-      const float2 yM = buf[pidx(0)];  // real Nyquist mode
-      buf[pidx(0)] = make_float2(yM.x, -yM.x);
-      continue;
-    }
-    const float2 yk = buf[pidx(k)];
-    const float2 ymk = buf[pidx(M - k)];
-    {
-      const float2 s = make_float2(yk.x + ymk.x, yk.y - ymk.y);   // Y_k + conj(Y_{M-k})
-      const float2 d = make_float2(yk.x - ymk.x, yk.y + ymk.y);   // Y_k - conj(Y_{M-k})
-      const float2 t = cmul(d, tw[k * twstep]);
-      buf[pidx(k)] = make_float2(s.x - t.y, s.y + t.x);
-    }
-    if (M - k != k) {
-      const float2 s = make_float2(ymk.x + yk.x, ymk.y - yk.y);
-      const float2 d = make_float2(ymk.x - yk.x, ymk.y + yk.y);
-      const float2 t = cmul(d, tw[(M - k) * twstep]);
-      buf[pidx(M - k)] = make_float2(s.x - t.y, s.y + t.x);
-    }
-  }
-  wave_sync();
-  wave_ifft(buf, M, tw, lane);
-}
-
 // Interpolation modes of the skewer kernel.
 enum { kSkTri = 0, kSkWide = 1, kSkGauss = 2 };
 
@@ -337,7 +258,7 @@ __global__ void __launch_bounds__(kSkNT) k_skewers(SkewerArgs a) {
         continue;
       }
       // twiddles from global memory: a copy in LDS would cost this kernel its fourth block per CU
-      if (with_ds) small_scale_wave(a, a.id_base + q, ns, buf, a.tw2048, lane);
+      if (with_ds) small_scale_wave(a, a.ps_amp, a.ps_kcut, a.id_base + q, ns, buf, a.tw2048, lane);
       // bin boundaries: jb[b] = first pixel with chi_j < edges[b] (chi_j decreases with j)
       if (want_bins) {
         bin_bounds(a.chi_edges, a.n_bins, chi0, a.dchi, np, jb, lane);

@@ -2,6 +2,9 @@
 // (a, b, c) held constant over every stored pixel (the paper's reuse of saved
 // forests, section "Adjusting mock parameters"), the mean flux of all pixels
 // and the binned P1D of delta_F = F/Fbar - 1 with velocity units of the draw.
+// Optionally each draw also carries a small-scale spectrum P_s, and delta_S is
+// drawn again per draw and skewer (the P_s iteration's redraw) and added to
+// the stored delta_L before the FGPA.
 //
 // One pass over the pixels for all G draws: a wavefront owns a skewer, holds
 // its first 2048 (dens, eta) pixels in registers and, per draw, forms F, adds
@@ -25,7 +28,10 @@ __global__ void __launch_bounds__(64) k_te_reset(unsigned int* queue) {
   if (threadIdx.x == 0) queue[0] = 0u;
 }
 
-__global__ void __launch_bounds__(kTeNT) k_tune_eval(TuneEvalArgs a) {
+// DS: delta_S redrawn per draw (a separate instantiation, so that the plain
+// evaluation keeps its register budget).
+template <bool DS>
+__global__ void __launch_bounds__(kTeNT, 2) k_tune_eval(TuneEvalArgs a) {
   __shared__ float2 sbuf[kTeWaves][kHalfBuf];
   __shared__ float spw[kTeWaves][kHalfMax + 1];
   __shared__ int smlo[kTeWaves][kMaxKBins + 1];
@@ -58,25 +64,45 @@ __global__ void __launch_bounds__(kTeNT) k_tune_eval(TuneEvalArgs a) {
         d[i] = j < np ? a.dens[off + j] : 0.0f;
         e[i] = j < np ? a.eta[off + j] : 0.0f;
       }
+      int ns = 1;
+      while (ns < np) ns <<= 1;
+      const bool with_ds = DS && ns >= 2;
       for (int g = 0; g < a.G; ++g) {
         const float ca = a.draw[g][0], cb = a.draw[g][1], cc = a.draw[g][2];
+        double* ps = a.ps + static_cast<int64_t>(g) * nk * ld + q;
+        int* pc = a.pc + static_cast<int64_t>(g) * nk * ld + q;
+        if (with_ds && ns > 2 * kHalfMax) {
+          // delta_S exists on lines of at most 2048 pixels: an input error,
+          // which makes this draw's mean flux (and so its P1D) NaN
+          if (lane == 0) a.fs[g * ld + q] = __builtin_nan("");
+          for (int b = lane; b < nk; b += 64) {
+            ps[b * ld] = 0.0;
+            pc[b * ld] = 0;
+          }
+          continue;
+        }
+        if (with_ds) {
+          // delta_S into the LDS line; each lane then reads and overwrites
+          // only its own pixels' slots (pixel j at bf[2 pidx(j/2) + j%2])
+          small_scale_wave(a, a.ds_amp[g], a.ds_kcut[g], static_cast<uint64_t>(a.id_base + q), ns, buf, stw, lane);
+        }
         double fsum = 0.0;
 #pragma unroll
         for (int i = 0; i < kTeReg; ++i) {
           const int j = lane + 64 * i;
           if (j < np) {
-            const float F = __expf(-ca * __expf(cb * (d[i] + cc * e[i])));
+            const int slot = 2 * pidx(j >> 1) + (j & 1);
+            const float delta = with_ds ? d[i] + bf[slot] : d[i];
+            const float F = __expf(-ca * __expf(cb * (delta + cc * e[i])));
             fsum += F;
-            if (j < n_p) bf[2 * pidx(j >> 1) + (j & 1)] = F;
+            if (j < n_p) bf[slot] = F;
           }
         }
-        for (int j = 64 * kTeReg + lane; j < np; j += 64)  // pixels beyond the register window
+        for (int j = 64 * kTeReg + lane; j < np; j += 64)  // pixels beyond the register window (no delta_S here)
           fsum += __expf(-ca * __expf(cb * (a.dens[off + j] + cc * a.eta[off + j])));
 #pragma unroll
         for (int w = 32; w >= 1; w >>= 1) fsum += __shfl_xor(fsum, w);
         if (lane == 0) a.fs[g * ld + q] = fsum;
-        double* ps = a.ps + static_cast<int64_t>(g) * nk * ld + q;
-        int* pc = a.pc + static_cast<int64_t>(g) * nk * ld + q;
         if (M == 0) {
           for (int b = lane; b < nk; b += 64) {
             ps[b * ld] = 0.0;
@@ -190,9 +216,11 @@ hipError_t launch_tune_eval(const TuneEvalArgs& a, double* sums, int64_t* counts
   int64_t blocks = static_cast<int64_t>(device_cus()) * 3;
   if (blocks * kTeWaves > nchunks) blocks = (nchunks + kTeWaves - 1) / kTeWaves;
   if (blocks < 1) blocks = 1;
-  if (a.n_sk > 0)
-    LYA_TIMED("tune_eval", st,
-              hipLaunchKernelGGL(k_tune_eval, dim3(static_cast<unsigned>(blocks)), dim3(kTeNT), 0, st, a));
+  const dim3 grid(static_cast<unsigned>(blocks));
+  if (a.n_sk > 0 && a.with_ds)
+    LYA_TIMED("tune_eval_ds", st, hipLaunchKernelGGL(k_tune_eval<true>, grid, dim3(kTeNT), 0, st, a));
+  else if (a.n_sk > 0)
+    LYA_TIMED("tune_eval", st, hipLaunchKernelGGL(k_tune_eval<false>, grid, dim3(kTeNT), 0, st, a));
   LYA_TIMED("tune_eval_reduce", st,
             hipLaunchKernelGGL(k_te_reduce, dim3(a.nk + 1, a.G), dim3(256), 0, st, a, sums, counts));
   LYA_TIMED("tune_eval_stats", st,

@@ -203,11 +203,50 @@ struct TuneEvalArgs {
   const float2* tw2048;
   unsigned int* queue;
   int chunk;
+  // delta_S redrawn per draw (with_ds): P_s(k) = ds_amp[g] exp(-(k/ds_kcut[g])^2)
+  // on every skewer (Philox key seed, line id_base + q, pixel length dpix),
+  // added to dens before the FGPA; skewers above 2048 pixels then give NaN
+  int with_ds;
+  double ds_amp[kTuneEvalMaxG], ds_kcut[kTuneEvalMaxG];
+  double dpix;
+  uint64_t seed;
+  int64_t id_base;
+  // what the shared delta_S synthesis reads besides: no P_s table, random phases
+  int ps_nb;
+  const double* ps_edges_k;
+  const float* ps_ratio;
+  int ps_fixed_amp;
 };
 // sums/counts: [G][nk + 1] (bins, then flux and pixels); rows (FP64) and rows32
 // (FP32, may be NULL): [G][1 + nk] = Fbar, P_1..P_nk.
 hipError_t launch_tune_eval(const TuneEvalArgs& a, double* sums, int64_t* counts, double* rows, float* rows32,
                             hipStream_t st);
+
+// Tuning statistics with delta_S redrawn per draw (lya_tune.hip), for the
+// small-scale power tuning: stored pixels without delta_S and their table,
+// device k edges (s/km), Philox key of delta_S.  The workspace w is laid out
+// as the tuning workspace of (n_sk, nk): tune_workspace_bytes bytes.
+struct DsSource {
+  int64_t n_sk, id_base;
+  const int32_t* npix;
+  const int64_t* offset;
+  const float* dens;
+  const float* eta;
+  const double* k_edges;
+  int nk;
+  double dpix, omega_m;
+  uint64_t seed;
+};
+struct DsDraw {
+  double a, b, c, z, amp, kcut;   // FGPA (a, b, c) at redshift z; P_s = amp exp(-(k/kcut)^2)
+};
+size_t tune_workspace_bytes(int64_t n_sk, int nk);
+hipError_t tune_eval_prepare(char* w, hipStream_t st);           // twiddles into w
+char* tune_eval_scratch(char* w, int64_t n_sk, int nk);          // the emulator search's output slot in w
+// G <= kTuneEvalMaxG draws: rows [G][1 + nk] = Fbar, P_1..P_nk into rows_host
+// (then synchronises the stream) and/or into rows32 (device FP32).
+hipError_t tune_eval_ds(const DsSource& src, char* w, const DsDraw* d, int G, double* rows_host, float* rows32,
+                        hipStream_t st);
 
 // Lognormal quasar field (lya_qso.hip).
 struct LognormalArgs {
@@ -297,6 +336,11 @@ struct EmuSearchSpec {
   const double* off;    // [1 + nk]
   const double* jac;    // [1 + nk][2]
   double xk[2];
+  // small-scale power mode: x = (ln amp, ln kcut) of P_s; emulator inputs
+  // (a, b, amp, kcut) with sigma_g^2 = sig0 + sigma_s^2(amp, kcut; dpix),
+  // (ln a, ln s) = lin[0..1] + lin[2..3] (ln sigma_g - lin[4]), b = s / sigma_g
+  int ps = 0;
+  double sig0 = 0.0, dpix = 0.0, lin[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 };
 hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2], double* fbest, int* nev,
                            double* pred, char* scratch, hipStream_t st);

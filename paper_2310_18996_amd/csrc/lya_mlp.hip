@@ -547,6 +547,11 @@ struct SearchArgs {
   const float* params;
   double fbar_t, c, z, x0[2], xk[2], step, xatol, fatol, sigma;
   int nk, max_evals;
+  // small-scale power mode (ps = 1): th = (ln amp, ln kcut) of P_s, emulator
+  // inputs (a, b, amp, kcut) with sigma_g^2 = sig0 + sigma_s^2(amp, kcut; dpix),
+  // (ln a, ln s) = lin[0..1] + lin[2..3] (ln sigma_g - lin[4]) and b = s / sigma_g
+  int ps;
+  double sig0, dpix, lin[5];
   double pk_t[kMaxOut];
   double off[kMaxOut];       // model offset per statistic (Fbar first)
   double jac[kMaxOut][2];    // model slope per statistic in (ln a, ln b) about xk
@@ -640,7 +645,9 @@ __device__ void forward_batch(const EmuHeader* __restrict__ h, const float* __re
 //   stat(th) = emulator(th) + off + jac (th - xk),
 //   r_0 = (stat_0 - Fbar_t)/(s Fbar_t), r_{1+b} = (stat_{1+b} - P_t,b)/(s P_t,b)
 // (0 where the target or the value is not finite; chi^2 = sum r^2), entirely
-// on the device in one block.  Each iteration runs one batched forward pass at
+// on the device in one block.  In the small-scale power mode th = (ln amp,
+// ln kcut) of P_s instead, a and b follow from th (SearchArgs), and only the
+// P1D residuals count (Fbar is fixed by a and b sigma_g).  Each iteration runs one batched forward pass at
 // the trial point and its two forward-difference steps (h = 1e-3), so the
 // Jacobian of an accepted point comes with it.  Wave 0 forms the residuals
 // (one statistic per lane) and the 2x2 normal equations (fixed-order shuffle
@@ -656,12 +663,37 @@ __global__ void __launch_bounds__(kSearchNT) k_emu_search(SearchArgs a) {
   __shared__ int sstate;  // 0 evaluate strial, 1 done
   const Offs o = param_offsets(a.h->n_out);
   const int nk = a.nk, t = threadIdx.x;
-  // the emulator's (a, b) input range in (ln a, ln b); a non-positive lower
-  // limit leaves that side open
+  // the emulator's input ranges in logarithms; a non-positive lower limit
+  // leaves that side open
   auto lnlim = [](float v) { return v > 0.0f ? log(static_cast<double>(v)) : -HUGE_VAL; };
-  const double alo = lnlim(a.h->in_lo[0]), ahi = log(static_cast<double>(a.h->in_hi[0]));
-  const double blo = lnlim(a.h->in_lo[1]), bhi = log(static_cast<double>(a.h->in_hi[1]));
+  double lo[4], hi[4];
+  for (int i = 0; i < 4; ++i) {
+    lo[i] = lnlim(a.h->in_lo[i]);
+    hi[i] = log(static_cast<double>(a.h->in_hi[i]));
+  }
   constexpr double kH = 1e-3;
+  // emulator inputs at th: (a, b, c, z), or (a, b, amp, kcut) in the
+  // small-scale power mode, with (ln a, ln b) returned for the range check
+  auto inputs = [&](double p0, double p1, float* x, double* lab) {
+    if (!a.ps) {
+      x[0] = static_cast<float>(exp(p0));
+      x[1] = static_cast<float>(exp(p1));
+      x[2] = static_cast<float>(a.c);
+      x[3] = static_cast<float>(a.z);
+      lab[0] = p0;
+      lab[1] = p1;
+      return;
+    }
+    const double amp = exp(p0), kc = exp(p1);
+    const double ss2 = amp * kc * erf(M_PI / (a.dpix * kc)) / (2.0 * sqrt(M_PI));
+    const double lsg = 0.5 * log(a.sig0 + ss2);
+    lab[0] = a.lin[0] + a.lin[2] * (lsg - a.lin[4]);
+    lab[1] = a.lin[1] + a.lin[3] * (lsg - a.lin[4]) - lsg;
+    x[0] = static_cast<float>(exp(lab[0]));
+    x[1] = static_cast<float>(exp(lab[1]));
+    x[2] = static_cast<float>(amp);
+    x[3] = static_cast<float>(kc);
+  };
   // lane-0 state
   double th[2] = {a.x0[0], a.x0[1]}, chi2 = HUGE_VAL, lam = 1e-3, A00 = 0, A01 = 0, A11 = 0, g0 = 0, g1 = 0;
   bool have = false;
@@ -676,16 +708,17 @@ __global__ void __launch_bounds__(kSearchNT) k_emu_search(SearchArgs a) {
   for (int it = 0; it < max_iter + 1; ++it) {
     const double p0 = strial[0], p1 = strial[1];
     const int state = sstate;
-    const float fc = static_cast<float>(a.c), fz = static_cast<float>(a.z);
-    const float xin[kLmS][4] = {{static_cast<float>(exp(p0)), static_cast<float>(exp(p1)), fc, fz},
-                                {static_cast<float>(exp(p0 + kH)), static_cast<float>(exp(p1)), fc, fz},
-                                {static_cast<float>(exp(p0)), static_cast<float>(exp(p1 + kH)), fc, fz}};
+    float xin[kLmS][4];
+    double lab[2], lab1[2];
+    inputs(p0, p1, xin[0], lab);
+    inputs(p0 + kH, p1, xin[1], lab1);
+    inputs(p0, p1 + kH, xin[2], lab1);
     forward_batch(a.h, a.params, o, xin, state ? 1 : kLmS, hs, part, outv);
     if (state) break;  // the last pass: the raw prediction at the optimum
     if (t < 64) {
       double r = 0.0, j0 = 0.0, j1 = 0.0;
       const int i = t;
-      if (i <= nk) {
+      if (i <= nk && !(a.ps && i == 0)) {
         const double tgt = i == 0 ? a.fbar_t : a.pk_t[i - 1];
         const double inv = 1.0 / (a.sigma * tgt);
         const double d0 = p0 - a.xk[0], d1 = p1 - a.xk[1];
@@ -711,7 +744,8 @@ __global__ void __launch_bounds__(kSearchNT) k_emu_search(SearchArgs a) {
       }
       if (t == 0) {
         nev += kLmS;
-        const bool inside = p0 >= alo && p0 <= ahi && p1 >= blo && p1 <= bhi;
+        bool inside = lab[0] >= lo[0] && lab[0] <= hi[0] && lab[1] >= lo[1] && lab[1] <= hi[1];
+        if (a.ps) inside = inside && p0 >= lo[2] && p0 <= hi[2] && p1 >= lo[3] && p1 <= hi[3];
         bool done = false;
         if (inside && c2 < chi2) {  // accept the point (and its Jacobian)
           const double step = have ? fmax(fabs(p0 - th[0]), fabs(p1 - th[1])) : HUGE_VAL;
@@ -778,6 +812,10 @@ hipError_t emulator_search(const void* emu, const EmuSearchSpec& sp, double x[2]
   a.sigma = sp.sigma;
   a.nk = sp.nk;
   a.max_evals = sp.max_evals;
+  a.ps = sp.ps;
+  a.sig0 = sp.sig0;
+  a.dpix = sp.dpix;
+  for (int i = 0; i < 5; ++i) a.lin[i] = sp.lin[i];
   for (int i = 0; i <= sp.nk; ++i) {
     if (i < sp.nk) a.pk_t[i] = sp.pk_t[i];
     a.off[i] = sp.off[i];

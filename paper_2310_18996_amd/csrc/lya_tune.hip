@@ -128,6 +128,53 @@ void quad_fit(const double* x, const double* y, int n, double out[3]) {
 
 size_t tune_workspace_bytes(int64_t n_sk, int nk) { return carve_tune(n_sk, nk).total; }
 
+hipError_t tune_eval_prepare(char* w, hipStream_t st) {
+  return launch_twiddles(reinterpret_cast<float2*>(w + carve_tune(1, 1).tw), kTw2048, st);
+}
+
+char* tune_eval_scratch(char* w, int64_t n_sk, int nk) { return w + carve_tune(n_sk, nk).emu; }
+
+hipError_t tune_eval_ds(const DsSource& src, char* w, const DsDraw* d, int G, double* rows_host, float* rows32,
+                        hipStream_t st) {
+  const TuneCarve c = carve_tune(src.n_sk, src.nk);
+  TuneEvalArgs a{};
+  a.n_sk = src.n_sk;
+  a.npix = src.npix;
+  a.offset = src.offset;
+  a.dens = src.dens;
+  a.eta = src.eta;
+  a.nk = src.nk;
+  a.k_edges = src.k_edges;
+  a.fs = reinterpret_cast<double*>(w + c.fs);
+  a.ps = reinterpret_cast<double*>(w + c.ps);
+  a.pc = reinterpret_cast<int*>(w + c.pc);
+  a.tw2048 = reinterpret_cast<const float2*>(w + c.tw);
+  a.queue = reinterpret_cast<unsigned int*>(w + c.queue);
+  a.chunk = 4;
+  a.with_ds = 1;
+  a.dpix = src.dpix;
+  a.seed = src.seed;
+  a.id_base = src.id_base;
+  a.G = G;
+  for (int g = 0; g < G; ++g) {
+    a.draw[g][0] = static_cast<float>(d[g].a);
+    a.draw[g][1] = static_cast<float>(d[g].b);
+    a.draw[g][2] = static_cast<float>(d[g].c);
+    a.ds_amp[g] = d[g].amp;
+    a.ds_kcut[g] = d[g].kcut;
+    const double x = 1.0 + d[g].z, om = src.omega_m;
+    a.dv[g] = src.dpix * (100.0 * sqrt(om * (x * x * x) + (1.0 - om)) / x);
+  }
+  double* rows = reinterpret_cast<double*>(w + c.rows);
+  hipError_t e = launch_tune_eval(a, reinterpret_cast<double*>(w + c.sums), reinterpret_cast<int64_t*>(w + c.counts),
+                                  rows, rows32, st);
+  if (e != hipSuccess || !rows_host) return e;
+  if ((e = hipMemcpyAsync(rows_host, rows, sizeof(double) * G * (src.nk + 1), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return e;
+  return hipStreamSynchronize(st);
+}
+
 // Emulator training labels: for each host draw (a, b, c, z) the mean flux and
 // mean P1D per bin (velocity units at z) of the stored pixels, written to
 // y[i][0] and y[i][1 + b] on the device, kTuneEvalMaxG draws per pass over

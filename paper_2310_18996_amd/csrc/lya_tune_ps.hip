@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kMomBlocks) k_moments_reduce(const double* __r
 size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct PsCarve {
-  size_t sk, p1d, flux, ratio, edges, zb, psum, pcnt, part, mom, total;
+  size_t sk, p1d, flux, ratio, edges, zb, psum, pcnt, part, mom, te, total;
 };
 
 PsCarve carve_ps(int64_t n_sk, int64_t n_pix, int nk) {
@@ -92,16 +92,19 @@ PsCarve carve_ps(int64_t n_sk, int64_t n_pix, int nk) {
   o += al(sizeof(double) * 5 * kMomBlocks);
   c.mom = o;
   o += al(sizeof(double) * 5);
+  c.te = o;  // the batched evaluation with delta_S (emulator mode and its labels)
+  o += al(tune_workspace_bytes(n_sk, nk));
   c.total = o;
   return c;
 }
 
 // F = exp(-a exp(s x)), x a unit normal: mean and dispersion, and
-// E[e^{s x} F] (the flux bias), by the trapezoid rule on [-12, 12] (the
-// Gaussian weight makes it converge geometrically; 4800 intervals leave
-// ~1e-15).
+// E[e^{s x} F] (the flux bias), by the trapezoid rule on [-12, 12].  The
+// integrands are analytic in a strip about the real axis, so the rule
+// converges geometrically in 1/h: 960 intervals (h = 0.025) agree with
+// 96,000 to 1e-14 relative for 1e-4 <= a <= 3 and s <= 10.
 void gauss_flux(double a, double s, double* f1, double* sf, double* mb = nullptr) {
-  const int n = 4800;
+  const int n = 960;
   const double h = 24.0 / n;
   double m1 = 0.0, m2 = 0.0, m3 = 0.0;
   for (int i = 0; i <= n; ++i) {
@@ -206,6 +209,39 @@ bool fit_a_s_bias(double fbar_t, double beff_t, double sigma_g, double beta, dou
       a, s);
 }
 
+// d(ln a, ln s)/d ln sigma_g along the solutions of fit_a_s_bias at (a, s):
+// the effective bias goes as 1/sigma_g, so with J the Jacobian of (ln Fbar,
+// ln b_eff) in (ln a, ln s) the slope is J^-1 (0, 1) (implicit functions).
+bool bias_slope(double a, double s, double sigma_g, double beta, double* dla, double* dls) {
+  double J[2][2];
+  const double h = 1e-5;
+  for (int k = 0; k < 2; ++k) {
+    double r[2][2];
+    for (int sg = 0; sg < 2; ++sg) {
+      const double d = sg ? -h : h;
+      const double aa = k == 0 ? a * exp(d) : a, sa = k == 1 ? s * exp(d) : s;
+      double f1;
+      const double be = effective_bias(aa, sa, sigma_g, beta, &f1);
+      if (!(f1 > 0.0) || !(be > 0.0)) return false;
+      r[sg][0] = log(f1);
+      r[sg][1] = log(be);
+    }
+    J[0][k] = (r[0][0] - r[1][0]) / (2.0 * h);
+    J[1][k] = (r[0][1] - r[1][1]) / (2.0 * h);
+  }
+  const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  if (!(fabs(det) > 1e-300)) return false;
+  *dla = -J[0][1] / det;
+  *dls = J[0][0] / det;
+  return true;
+}
+
+// sigma_s^2 of P_s = amp exp(-(k/kcut)^2) on a line of pixel length dpix:
+// (1/pi) int_0^{pi/dpix} P_s dk = amp kcut erf(pi/(dpix kcut)) / (2 sqrt(pi))
+double sigma_s2_gauss(double amp, double kcut, double dpix) {
+  return amp * kcut * erf(M_PI / (dpix * kcut)) / (2.0 * sqrt(M_PI));
+}
+
 // (1/pi) int_0^{pi/dpix} amp exp(-(k/kcut)^2) r(k) dk, r piecewise constant
 // on the edges (h/Mpc), clamped at both ends.
 double sigma_s2(double amp, double kcut, const double* ratio, const double* edges, int nk, double dpix) {
@@ -259,6 +295,14 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
     return pfail(LYA_EINVAL, "P1D bins (1..64 with edges) and targets are required");
   if (spec->n_iter < 1 || spec->n_iter > LYA_TUNE_PS_MAX_ITER) return pfail(LYA_EINVAL, "n_iter must be in [1, 16]");
   if (spec->n_outer < 0 || spec->n_outer > LYA_TUNE_PS_MAX_OUTER) return pfail(LYA_EINVAL, "n_outer must be in [0, 8]");
+  if (spec->mode != LYA_TUNE_PS_RATIOS && spec->mode != LYA_TUNE_PS_EMULATOR)
+    return pfail(LYA_EINVAL, "mode must be LYA_TUNE_PS_RATIOS or LYA_TUNE_PS_EMULATOR");
+  const bool emu_mode = spec->mode == LYA_TUNE_PS_EMULATOR;
+  if (emu_mode) {
+    if (spec->emu_checks < 1 || spec->emu_checks > 16) return pfail(LYA_EINVAL, "emu_checks must be in [1, 16]");
+    for (int z = 0; z < spec->n_zt; ++z)
+      if (!spec->emu[z]) return pfail(LYA_EINVAL, "emulator mode needs an emulator at every z_t");
+  }
   const int n_outer = spec->n_outer < 1 ? 1 : spec->n_outer;
   if (n_outer > 1) {
     if (!(spec->f > 0.0)) return pfail(LYA_EINVAL, "the outer loop needs f > 0");
@@ -285,11 +329,23 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
   double* d_mom = reinterpret_cast<double*>(w + c.mom);
   memset(res, 0, sizeof(*res));
 
+  hipError_t e;
+  if (emu_mode) {  // each emulator must predict (Fbar, P_1..P_nk)
+    for (int z = 0; z < spec->n_zt; ++z) {
+      int32_t n_out = 0;
+      if ((e = hipMemcpyAsync(&n_out, spec->emu[z], sizeof(n_out), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (e = hipStreamSynchronize(st)) != hipSuccess)
+        return phip(e, "reading an emulator header");
+      if (n_out != 1 + nk) return pfail(LYA_EINVAL, "an emulator's outputs are not 1 + n_kbins");
+    }
+    if ((e = tune_eval_prepare(w + c.te, st)) != hipSuccess) return phip(e, "evaluation set-up");
+  }
+
   // moments of the stored pixels
   hipLaunchKernelGGL(k_moments, dim3(kMomBlocks), dim3(kMomNT), 0, st, sk->n_sk, sk->npix, sk->offset, spec->dens_l,
                      spec->eta, d_part);
   hipLaunchKernelGGL(k_moments_reduce, dim3(5), dim3(kMomBlocks), 0, st, d_part, d_mom);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return phip(e, "moments");
   double mom[5];
   std::vector<int32_t> npix(sk->n_sk);
@@ -316,6 +372,7 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
   lya_zbins zb{1, d_zb, d_zb + 2, reinterpret_cast<int64_t*>(d_zb + 3)};
   lya_ps1d ps{spec->ps_amp, spec->ps_kcut, spec->p1d.dpix, 0};
   lya_ps_table tab{nk, d_edges, d_ratio};
+  const double dpix = spec->p1d.dpix;
 
   for (int z = 0; z < spec->n_zt; ++z) {
     const double zt = spec->z_t[z], ct = spec->c_t[z], ft = spec->fbar_t[z];
@@ -328,38 +385,152 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
         if (isfinite(pt[b])) v += pt[b] * (kv[b + 1] - kv[b]);
       sigf = ft * sqrt(v / M_PI);
     }
-    double a = 0.0, s = 0.0;
-    if (!(sigf > 0.0) || !fit_a_s(ft, sigf, &a, &s))
+    double a0 = 0.0, s0 = 0.0;
+    if (!(sigf > 0.0) || !fit_a_s(ft, sigf, &a0, &s0))
       return pfail(LYA_EINVAL, "no (a, b sigma_g) reaches the target mean flux and dispersion");
     const double opz = 1.0 + zt;
     const double E = sqrt(spec->cosmo.omega_m * opz * opz * opz + 1.0 - spec->cosmo.omega_m);
     const double dvdchi = 100.0 * E / opz;
     std::vector<double> ek(nk + 1);
     for (int b = 0; b <= nk; ++b) ek[b] = kv[b] * dvdchi;
-    std::vector<double> ratio(nk, 1.0);
-    std::vector<float> ratio32(nk);
-    std::vector<double> psum(nk);
-    std::vector<int64_t> pcnt(nk);
-    double fbar = 0.0, b_used = 0.0;
     const double beta = spec->f * ct;
     // the bias target with respect to the z = 0 box the pixels come from
     res->growth[z] = spec->beff_at_z ? growth_lcdm(zt, spec->cosmo.omega_m) : 1.0;
     const double beff_box = spec->beff_t[z] * res->growth[z];
+    const double sig0 = sl2 + ct * ct * se2 + 2.0 * ct * cov;  // sigma_g^2 without delta_S
+    auto rel_rms = [&](const double* p) {
+      double se = 0.0;
+      int ne = 0;
+      for (int b = 0; b < nk; ++b)
+        if (isfinite(pt[b]) && isfinite(p[b]) && pt[b] != 0.0) {
+          se += (p[b] / pt[b] - 1.0) * (p[b] / pt[b] - 1.0);
+          ++ne;
+        }
+      return ne ? sqrt(se / ne) : NAN;
+    };
+
+    // ---- emulator mode: (amp, kcut) of P_s by a corrected emulator search
+    bool plain = !emu_mode;
+    if (emu_mode) {
+      const bool outer = n_outer > 1;
+      const int checks = spec->emu_checks;
+      const double xtol = 5e-4;
+      double th[2] = {log(spec->ps_amp), log(spec->ps_kcut)};
+      double off[kMaxKBins + 1] = {0.0}, jac[2 * (kMaxKBins + 1)] = {0.0}, dprev[kMaxKBins + 1] = {0.0};
+      double xk[2] = {th[0], th[1]};
+      double a = a0, s = s0, step = 0.3;
+      bool converged = false, ok = true;
+      int gpu_ev = 0;
+      double rows[kMaxKBins + 1];
+      // (a, s) and their slope in ln sigma_g at the sigma_g of th
+      auto solve_as = [&](const double* t, double* la, double* ls, double* dla, double* dls, double* lsg) {
+        const double sg = sqrt(sig0 + sigma_s2_gauss(exp(t[0]), exp(t[1]), dpix));
+        if (!(sg > 0.0)) return false;
+        *lsg = log(sg);
+        if (outer) {
+          if (!fit_a_s_bias(ft, beff_box, sg, beta, &a, &s) || !bias_slope(a, s, sg, beta, dla, dls)) return false;
+        } else {
+          *dla = *dls = 0.0;
+        }
+        *la = log(a);
+        *ls = log(s);
+        return true;
+      };
+      double lin[5];
+      ok = solve_as(th, &lin[0], &lin[1], &lin[2], &lin[3], &lin[4]);
+      for (int it = 0; ok && it < checks; ++it) {
+        EmuSearchSpec ss{ft, ct, zt, step, 0.01 * xtol, HUGE_VAL, 0.002, nk, 600, pt, off, jac, {xk[0], xk[1]}};
+        ss.ps = 1;
+        ss.sig0 = sig0;
+        ss.dpix = dpix;
+        for (int i = 0; i < 5; ++i) ss.lin[i] = lin[i];
+        double x[2] = {th[0], th[1]}, fbest = 0.0, pe[kMaxKBins + 1];
+        int n1 = 0;
+        if ((e = emulator_search(spec->emu[z], ss, x, &fbest, &n1, pe, tune_eval_scratch(w + c.te, sk->n_sk, nk),
+                                 st)) != hipSuccess)
+          return phip(e, "emulator search");
+        // the exact (a, s) at the new point, then one GPU evaluation there
+        if (!solve_as(x, &lin[0], &lin[1], &lin[2], &lin[3], &lin[4])) {
+          ok = false;
+          break;
+        }
+        DsSource src{sk->n_sk, sk->id_base, sk->npix, sk->offset, spec->dens_l, spec->eta, spec->p1d.k_edges, nk,
+                     dpix, spec->cosmo.omega_m, spec->seed};
+        DsDraw dd{a, s / exp(lin[4]), ct, zt, exp(x[0]), exp(x[1])};
+        if ((e = tune_eval_ds(src, w + c.te, &dd, 1, rows, nullptr, st)) != hipSuccess) return phip(e, "evaluation");
+        ++gpu_ev;
+        double d[kMaxKBins + 1];
+        for (int j = 0; j <= nk; ++j) d[j] = rows[j] - pe[j];
+        const double dx0 = xk[0] - x[0], dx1 = xk[1] - x[1], dxx = dx0 * dx0 + dx1 * dx1;
+        if (it > 0 && dxx > 1e-24) {
+          for (int j = 0; j <= nk; ++j) {
+            if (!isfinite(d[j]) || !isfinite(dprev[j])) {
+              jac[2 * j] = jac[2 * j + 1] = 0.0;
+              continue;
+            }
+            const double r = (dprev[j] - d[j]) - (jac[2 * j] * dx0 + jac[2 * j + 1] * dx1);
+            jac[2 * j] += r * dx0 / dxx;
+            jac[2 * j + 1] += r * dx1 / dxx;
+          }
+        }
+        const double moved = fmax(fabs(dx0), fabs(dx1));
+        for (int j = 0; j <= nk; ++j) off[j] = dprev[j] = d[j];
+        xk[0] = th[0] = x[0];
+        xk[1] = th[1] = x[1];
+        step = 0.05;
+        if (it > 0 && moved <= xtol) {
+          converged = true;
+          break;
+        }
+      }
+      res->gpu_evals[z] = gpu_ev;
+      if (ok && converged) {
+        const double sg = exp(lin[4]), amp = exp(th[0]), kc = exp(th[1]);
+        res->a[z] = a;
+        res->b[z] = s / sg;
+        res->s[z] = s;
+        res->ps_fit[2 * z] = amp;
+        res->ps_fit[2 * z + 1] = kc;
+        for (int b = 0; b < nk; ++b) {
+          res->p1d[z * 64 + b] = rows[1 + b];
+          const double kc_b = sqrt(ek[b] * ek[b + 1]);
+          res->ratio[z * 64 + b] =
+              (amp * exp(-(kc_b / kc) * (kc_b / kc))) / (spec->ps_amp * exp(-(kc_b / spec->ps_kcut) * (kc_b / spec->ps_kcut)));
+        }
+        res->fbar[z * LYA_TUNE_PS_MAX_ITER] = rows[0];
+        res->rms[z * LYA_TUNE_PS_MAX_ITER] = rel_rms(rows + 1);
+        res->beff[z * LYA_TUNE_PS_MAX_OUTER] = effective_bias(a, s, sg, beta, nullptr);
+        res->n_outer_done[z] = 1;
+        continue;
+      }
+      // not settled within emu_checks GPU evaluations (or no (a, s) for the
+      // targets along the way): the plain iteration runs instead
+      res->fallback[z] = 1;
+      plain = true;
+    }
+    if (!plain) continue;
+
+    // ---- the paper's iteration: P_s multiplied per k bin by P_target / P1D
+    std::vector<double> ratio(nk, 1.0);
+    std::vector<float> ratio32(nk);
+    std::vector<double> psum(nk);
+    std::vector<int64_t> pcnt(nk);
+    double fbar = 0.0, b_used = 0.0, a = a0, s = s0;
     int done = 0;
     for (int o = 0; o < n_outer; ++o) {
       if (o > 0) {
         // re-solve (a, s) for Fbar and the target effective bias at the
         // sigma_g of the current ratios
-        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
-        const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
+        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, dpix);
+        const double sg2 = sig0 + ss2;
         double a2 = a, s2 = s;
         if (!(sg2 > 0.0) || !fit_a_s_bias(ft, beff_box, sqrt(sg2), beta, &a2, &s2)) break;
         a = a2;
         s = s2;
       }
       for (int it = 0; it < spec->n_iter; ++it) {
-        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, spec->p1d.dpix);
-        const double sg2 = sl2 + ss2 + ct * ct * se2 + 2.0 * ct * cov;
+        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, dpix);
+        const double sg2 = sig0 + ss2;
         if (!(sg2 > 0.0)) return pfail(LYA_EINVAL, "sigma_g^2 is not positive");
         b_used = s / sqrt(sg2);
         for (int b = 0; b < nk; ++b) ratio32[b] = static_cast<float>(ratio[b]);
@@ -393,22 +564,16 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
                 hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess)
           return phip(e, "statistics read-back");
+        ++res->gpu_evals[z];
         int64_t count;
         memcpy(&count, &zsum[1], sizeof(count));
         fbar = count > 0 ? zsum[0] / static_cast<double>(count) : NAN;
-        double se = 0.0;
-        int ne = 0;
         for (int b = 0; b < nk; ++b) {
-          const double p = pcnt[b] > 0 ? psum[b] / static_cast<double>(pcnt[b]) : NAN;
-          res->p1d[z * 64 + b] = p;
+          res->p1d[z * 64 + b] = pcnt[b] > 0 ? psum[b] / static_cast<double>(pcnt[b]) : NAN;
           res->ratio[z * 64 + b] = ratio[b];
-          if (isfinite(pt[b]) && isfinite(p) && pt[b] != 0.0) {
-            se += (p / pt[b] - 1.0) * (p / pt[b] - 1.0);
-            ++ne;
-          }
         }
         res->fbar[z * LYA_TUNE_PS_MAX_ITER + it] = fbar;
-        res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = ne ? sqrt(se / ne) : NAN;
+        res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = rel_rms(res->p1d + z * 64);
         // P_s^{n+1} = P_s^n P_target / P1D in every bin with both values
         for (int b = 0; b < nk; ++b) {
           const double p = res->p1d[z * 64 + b];
@@ -424,6 +589,42 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
     res->s[z] = s;
   }
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return LYA_OK;
+}
+
+int lya_emulator_labels_ps(const lya_tune_ps_spec* spec, int32_t zi, const double* draws, int64_t n, float* y,
+                           void* work, size_t work_bytes, void* stream) {
+  using namespace lya;
+  g_perr[0] = 0;
+  if (!spec || !spec->sk || !draws || !y || !work || n < 0) return pfail(LYA_EINVAL, "NULL argument or n < 0");
+  const lya_skewers* sk = spec->sk;
+  const int nk = spec->p1d.n_kbins;
+  if (zi < 0 || zi >= spec->n_zt || spec->n_zt > LYA_TUNE_MAX_Z) return pfail(LYA_EINVAL, "zi outside the z_t list");
+  if (nk < 1 || nk > kMaxKBins || !spec->p1d.k_edges) return pfail(LYA_EINVAL, "P1D bins (1..64 with edges) required");
+  if (!(spec->p1d.dpix > 0.0)) return pfail(LYA_EINVAL, "dpix must be positive");
+  if (sk->n_sk < 1 || !sk->npix || !sk->offset || !spec->dens_l || !spec->eta)
+    return pfail(LYA_EINVAL, "stored pixels and their skewer table are required");
+  if (!(spec->cosmo.omega_m >= 0.0 && spec->cosmo.omega_m <= 1.0)) return pfail(LYA_EINVAL, "omega_m out of [0,1]");
+  for (int64_t i = 0; i < n; ++i)
+    if (!(draws[4 * i + 2] > 0.0) || !(draws[4 * i + 3] > 0.0))
+      return pfail(LYA_EINVAL, "P_s amplitude and cut-off of every draw must be positive");
+  const PsCarve c = carve_ps(sk->n_sk, spec->n_pixels, nk);
+  if (work_bytes < c.total) return pfail(LYA_EWORKSPACE, "workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(work) + c.te;
+  hipError_t e = tune_eval_prepare(w, st);
+  const DsSource src{sk->n_sk, sk->id_base, sk->npix, sk->offset, spec->dens_l, spec->eta, spec->p1d.k_edges, nk,
+                     spec->p1d.dpix, spec->cosmo.omega_m, spec->seed};
+  for (int64_t i0 = 0; i0 < n && e == hipSuccess; i0 += kTuneEvalMaxG) {
+    const int G = static_cast<int>(n - i0 < kTuneEvalMaxG ? n - i0 : kTuneEvalMaxG);
+    DsDraw dd[kTuneEvalMaxG];
+    for (int g = 0; g < G; ++g) {
+      const double* d = draws + 4 * (i0 + g);
+      dd[g] = DsDraw{d[0], d[1], spec->c_t[zi], spec->z_t[zi], d[2], d[3]};
+    }
+    e = tune_eval_ds(src, w, dd, G, nullptr, y + i0 * (1 + nk), st);
+  }
+  if (e != hipSuccess) return phip(e, "label evaluation");
   return LYA_OK;
 }
 

@@ -24,6 +24,7 @@ EXPORTS = ("lya_field_elems", "lya_plane_pitch", "lya_workspace_size", "lya_make
            "lya_draw_quasars", "lya_quasar_skewers",
            "lya_draw_skewers", "lya_draw_skewers_static", "lya_draw_skewers_gauss", "lya_draw_skewers_wide", "lya_apply_fgpa",
            "lya_apply_fgpa_ds", "lya_tune_ps_workspace_size", "lya_tune_ps", "lya_tune_ps_last_error",
+           "lya_emulator_labels_ps",
            "lya_p1d_workspace_size", "lya_p1d",
            "lya_tune_workspace_size",
            "lya_tune_params", "lya_emulator_labels", "lya_emulator_bytes", "lya_emulator_param_offset",
@@ -320,6 +321,8 @@ class TuneResult(ctypes.Structure):
 
 TUNE_PS_MAX_ITER = 16
 TUNE_PS_MAX_OUTER = 8
+TUNE_PS_RATIOS = 0
+TUNE_PS_EMULATOR = 1
 
 
 class PsTable(ctypes.Structure):
@@ -333,7 +336,8 @@ class TunePsSpec(ctypes.Structure):
                 ("fbar_t", ctypes.c_double * TUNE_MAX_Z), ("sigf_t", ctypes.c_double * TUNE_MAX_Z),
                 ("p1d_t", ctypes.c_void_p), ("p1d", P1dSpec), ("ps_amp", ctypes.c_double),
                 ("ps_kcut", ctypes.c_double), ("n_iter", ctypes.c_int32), ("n_outer", ctypes.c_int32),
-                ("beff_t", ctypes.c_double * TUNE_MAX_Z), ("f", ctypes.c_double), ("beff_at_z", ctypes.c_int32)]
+                ("beff_t", ctypes.c_double * TUNE_MAX_Z), ("f", ctypes.c_double), ("beff_at_z", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("emu", ctypes.c_void_p * TUNE_MAX_Z), ("emu_checks", ctypes.c_int32)]
 
 
 class TunePsResult(ctypes.Structure):
@@ -343,7 +347,9 @@ class TunePsResult(ctypes.Structure):
                 ("fbar", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)),
                 ("rms", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_ITER)), ("seconds", ctypes.c_double),
                 ("beff", ctypes.c_double * (TUNE_MAX_Z * TUNE_PS_MAX_OUTER)),
-                ("n_outer_done", ctypes.c_int32 * TUNE_MAX_Z), ("growth", ctypes.c_double * TUNE_MAX_Z)]
+                ("n_outer_done", ctypes.c_int32 * TUNE_MAX_Z), ("growth", ctypes.c_double * TUNE_MAX_Z),
+                ("ps_fit", ctypes.c_double * (2 * TUNE_MAX_Z)), ("gpu_evals", ctypes.c_int32 * TUNE_MAX_Z),
+                ("fallback", ctypes.c_int32 * TUNE_MAX_Z)]
 
 
 FFT_VARIANTS = 14
@@ -453,6 +459,9 @@ def _bind_more(lib):
     lib.lya_tune_ps.restype = ctypes.c_int
     lib.lya_tune_ps.argtypes = [P(TunePsSpec), P(TunePsResult), VP, ctypes.c_size_t, VP]
     lib.lya_tune_ps_last_error.restype = ctypes.c_char_p
+    lib.lya_emulator_labels_ps.restype = ctypes.c_int
+    lib.lya_emulator_labels_ps.argtypes = [P(TunePsSpec), ctypes.c_int32, VP, ctypes.c_int64, VP, VP, ctypes.c_size_t,
+                                           VP]
     lib.lya_make_box_pair.restype = ctypes.c_int
     lib.lya_make_box_pair.argtypes = [P(Box), P(Pk), P(Pk), ctypes.c_uint64, VP, VP, ctypes.c_size_t, VP]
     lib.lya_lognormal_workspace_size.restype = ctypes.c_size_t
@@ -513,6 +522,16 @@ def tune_ps(spec, work, stream=None):
     if rc != LYA_OK:
         raise LyaError(rc, _lib2().lya_tune_ps_last_error().decode())
     return res
+
+
+def emulator_labels_ps(spec, zi, draws_host, y, work, stream=None):
+    """lya_emulator_labels_ps: draws_host is a C-contiguous float64 numpy array [n, 4] of (a, b, amp, kcut)."""
+    import numpy as np
+    d = np.ascontiguousarray(draws_host, dtype=np.float64)
+    rc = _lib2().lya_emulator_labels_ps(ctypes.byref(spec), int(zi), d.ctypes.data, int(d.shape[0]), _ptr(y),
+                                        _ptr(work), work.numel() * work.element_size(), _stream(stream))
+    if rc != LYA_OK:
+        raise LyaError(rc, _lib2().lya_tune_ps_last_error().decode())
 
 
 def tune_workspace_size(n_sk, n_kbins):

@@ -38,7 +38,9 @@ def test_library_exports_every_declared_function():
 STRUCTS = {
     "lya_box": L.Box, "lya_pk": L.Pk, "lya_skewers": L.Skewers, "lya_ps1d": L.Ps1d, "lya_fgpa": L.Fgpa,
     "lya_cosmo": L.Cosmo, "lya_zbins": L.ZBins, "lya_p1d_spec": L.P1dSpec, "lya_tune_spec": L.TuneSpec,
-    "lya_tune_result": L.TuneResult, "lya_tuning": L.Tuning,
+    "lya_tune_result": L.TuneResult, "lya_tuning": L.Tuning, "lya_ps_table": L.PsTable,
+    "lya_tune_ps_spec": L.TunePsSpec, "lya_tune_ps_result": L.TunePsResult, "lya_qso_spec": L.QsoSpec,
+    "lya_qso_los_spec": L.QsoLosSpec,
 }
 
 
