@@ -35,6 +35,7 @@ skewer table, and the skewer pass with FGPA over those lines of sight.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -630,7 +631,104 @@ def truth_targets(L, torch, mock, cosmo, z_t, b_t, c_t, fbar_t, k_edges, dpix):
     return np.array(a_t), np.stack(pk_t)
 
 
-def tune_ps_leg(L, torch, n_iter=10):
+def ps_emulator_run(L, torch, spec, tw, emock, n_outer, n_labels, train_steps, seed):
+    """lya_tune_ps in emulator mode for the z_t of spec, with one emulator per
+    z_t trained on lya_emulator_labels_ps of the emulator mock (256^3, 20,000
+    skewers, pixels without delta_S).  The label draws centre on the (a, s)
+    of one plain iteration (with one bias re-solve when the outer loop runs):
+    (amp, kcut) log-uniform over [0.3, 12] x [0.35, 4] h/Mpc, a and s within
+    e^{+-0.5} and e^{+-0.35} of that point, b = s / sigma_g(amp, kcut).
+    Returns the result and the costs (set-up, labels, training)."""
+    import ctypes
+    nz, nk = spec.n_zt, spec.p1d.n_kbins
+    saved = (spec.mode, spec.n_iter, spec.n_outer)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    spec.mode, spec.n_iter, spec.n_outer = L.TUNE_PS_RATIOS, 1, (2 if n_outer > 1 else 1)
+    r1 = L.tune_ps(spec, tw)
+    t_setup = time.perf_counter() - t0
+    sl2, se2, cov = r1.sigma2[0], r1.sigma2[1], r1.sigma2[2]
+    es = L.TunePsSpec()
+    es.sk = ctypes.pointer(emock["s"])
+    es.dens_l, es.eta = emock["dens"].data_ptr(), emock["eta"].data_ptr()
+    es.n_pixels = int(emock["pixels"])
+    es.cosmo = spec.cosmo
+    es.seed = seed
+    es.n_zt = nz
+    for i in range(nz):
+        es.z_t[i], es.c_t[i] = spec.z_t[i], spec.c_t[i]
+    es.p1d = L.P1dSpec(nk, spec.p1d.k_edges, 0.0, spec.p1d.dpix)
+    ew = torch.empty(L.tune_ps_workspace_size(emock["n_sk"], emock["pixels"], nk), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(seed)
+    B = 512
+    twork = torch.empty(L.emulator_train_workspace_size(B, 1 + nk), dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(train_steps, dtype=torch.float32, device="cuda")
+    emus, t_lab, t_train, losses = [], 0.0, 0.0, []
+    dpix = spec.p1d.dpix
+    for i in range(nz):
+        c = spec.c_t[i]
+        amp = np.exp(rng.uniform(np.log(0.3), np.log(12.0), n_labels))
+        kc = np.exp(rng.uniform(np.log(0.35), np.log(4.0), n_labels))
+        ss2 = amp * kc * np.array([math.erf(np.pi / (dpix * k)) for k in kc]) / (2.0 * np.sqrt(np.pi))
+        sg = np.sqrt(sl2 + c * c * se2 + 2.0 * c * cov + ss2)
+        a = r1.a[i] * np.exp(rng.uniform(-0.5, 0.5, n_labels))
+        sv = r1.s[i] * np.exp(rng.uniform(-0.35, 0.35, n_labels))
+        draws = np.ascontiguousarray(np.stack([a, sv / sg, amp, kc], axis=1))
+        y = torch.empty((n_labels, 1 + nk), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.emulator_labels_ps(es, i, draws, y, ew)
+        torch.cuda.synchronize()
+        t_lab += time.perf_counter() - t0
+        emu = torch.zeros(L.emulator_bytes(1 + nk), dtype=torch.uint8, device="cuda")
+        L.emulator_init(emu, 1 + nk, 1, seed + i, draws.min(axis=0) * 0.99, draws.max(axis=0) * 1.01, 0b1101)
+        L.emulator_set_scaling(emu, y, n_labels)
+        x = torch.from_numpy(draws.astype(np.float32)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n1 = (3 * train_steps) // 4
+        L.emulator_train(emu, x, y, n_labels, n1, B, 1e-3, True, hist, twork)
+        L.emulator_train(emu, x, y, n_labels, train_steps - n1, B, 2e-4, True, hist[n1:], twork)
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t0
+        losses.append(float(hist[-100:].mean().item()))
+        emus.append(emu)
+    del ew
+    spec.mode, spec.n_iter, spec.n_outer = L.TUNE_PS_EMULATOR, saved[1], n_outer
+    for i in range(nz):
+        spec.emu[i] = emus[i].data_ptr()
+    spec.emu_checks = 10
+    re_ = L.tune_ps(spec, tw)
+    spec.mode, spec.n_iter, spec.n_outer = saved
+    costs = dict(setup_s=t_setup, labels_s=t_lab, train_s=t_train, labels_per_z=n_labels, train_steps_per_z=train_steps,
+                 train_loss_final=losses)
+    return re_, costs
+
+
+def ps_emulator_record(L, re_, plain, nz, n_iter, costs):
+    """The emulator-mode result beside the plain iteration's (whose last
+    iteration, n_iter - 1, holds its final statistics; a z_t that fell back
+    to the plain iteration reports that one's)."""
+    M = L.TUNE_PS_MAX_ITER
+    last = [n_iter - 1] * nz
+    rec = dict(emulator_s=re_.seconds, plain_s=plain.seconds, speedup=plain.seconds / re_.seconds,
+               speedup_incl_labels_training=plain.seconds / (re_.seconds + costs["setup_s"] + costs["labels_s"] +
+                                                             costs["train_s"]),
+               gpu_evals_emulator=[re_.gpu_evals[i] for i in range(nz)],
+               gpu_evals_plain=[plain.gpu_evals[i] for i in range(nz)],
+               fallback=[re_.fallback[i] for i in range(nz)],
+               ps_fit=[[re_.ps_fit[2 * i], re_.ps_fit[2 * i + 1]] for i in range(nz)],
+               a_emulator=list(re_.a[:nz]), b_emulator=list(re_.b[:nz]),
+               fbar_emulator=[re_.fbar[i * M] if not re_.fallback[i] else re_.fbar[i * M + last[i]] for i in range(nz)],
+               fbar_plain=[plain.fbar[i * M + last[i]] for i in range(nz)],
+               p1d_rel_rms_emulator=[re_.rms[i * M] if not re_.fallback[i] else re_.rms[i * M + last[i]]
+                                     for i in range(nz)],
+               p1d_rel_rms_plain=[plain.rms[i * M + last[i]] for i in range(nz)])
+    rec.update(costs)
+    return rec
+
+
+def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
     """The small-scale power iteration (lya_tune_ps) on the 512^3 mock with
     50,000 skewers: stored delta_L and eta_par without delta_S; the targets
     (Fbar, sigma_F and P1D at the five z_t) come from a truth made of the
@@ -695,6 +793,14 @@ def tune_ps_leg(L, torch, n_iter=10):
     tw = torch.empty(L.tune_ps_workspace_size(mock["n_sk"], mock["pixels"], nk), dtype=torch.uint8, device="cuda")
     res = L.tune_ps(spec, tw)
     M = L.TUNE_PS_MAX_ITER
+    # the emulator mode on the same targets, its emulators trained on the
+    # 256^3 emulator mock without delta_S
+    ecfg = dict(mockinputs.config("emulator"), ps_amp=0.0)
+    emock = stored_pixels(L, torch, ecfg, ecfg["seed"], ecfg["seed"])
+    re_a, costs_a = ps_emulator_run(L, torch, spec, tw, emock, 0, emu_labels, emu_steps, ecfg["seed"])
+    emu_inner = ps_emulator_record(L, re_a, res, len(z_t), n_iter, costs_a)
+    print("bench: tune_ps emulator mode (inner) %.3f s against plain %.3f s" % (re_a.seconds, res.seconds),
+          file=sys.stderr, flush=True)
     # the outer loop (five steps) against the paper's own targets: Fbar(z) of
     # Calura et al., c_t = beta(z_t)/f and the effective bias of its power law,
     # taken with respect to the matter field at z_t (the library scales it by
@@ -747,6 +853,13 @@ def tune_ps_leg(L, torch, n_iter=10):
     spec.p1d_t = pk_p.ctypes.data
     spec.n_outer = 5
     res5 = L.tune_ps(spec, tw)
+    re_b, costs_b = ps_emulator_run(L, torch, spec, tw, emock, 5, emu_labels, emu_steps, ecfg["seed"] + 100)
+    del emock
+    emu_outer = ps_emulator_record(L, re_b, res5, len(z_t), n_iter, costs_b)
+    emu_outer["beff_over_target"] = [re_b.beff[i * MO] / (beff_p[i] * re_b.growth[i]) if not re_b.fallback[i]
+                                     else None for i in range(len(z_t))]
+    print("bench: tune_ps emulator mode (outer) %.3f s against plain %.3f s" % (re_b.seconds, res5.seconds),
+          file=sys.stderr, flush=True)
     steps = [res5.n_outer_done[i] for i in range(len(z_t))]
     ratio = [[res5.beff[i * MO + o] / (beff_p[i] * res5.growth[i]) for o in range(steps[i])] for i in range(len(z_t))]
     outer = dict(targets="paper: b_eff = 0.183 ((1+z)/3.3)^3.47 with respect to the matter field at z_t, "
@@ -759,7 +872,7 @@ def tune_ps_leg(L, torch, n_iter=10):
                  stopped_unreachable=[bool(steps[i] < 5) for i in range(len(z_t))],
                  a=list(res5.a[:len(z_t)]), b=list(res5.b[:len(z_t)]),
                  fbar_last=[res5.fbar[i * M + n_iter - 1] for i in range(len(z_t))],
-                 p1d_rel_rms_last=[res5.rms[i * M + n_iter - 1] for i in range(len(z_t))])
+                 p1d_rel_rms_last=[res5.rms[i * M + n_iter - 1] for i in range(len(z_t))], emulator=emu_outer)
     return dict(workload="P_s iteration, %d iterations at z_t=%s on the 512^3 mock (%d skewers, %d pixels); truth: "
                           "same delta_L and eta_par, delta_S with amplitude 1.6 and cut-off 1.1 h/Mpc (other key), "
                           "P_s start amplitude 1.0, cut-off 1.5" % (n_iter, list(z_t), mock["n_sk"], mock["pixels"]),
@@ -767,7 +880,8 @@ def tune_ps_leg(L, torch, n_iter=10):
                 b_truth=list(map(float, b_true)),
                 fbar_last=[res.fbar[i * M + n_iter - 1] for i in range(len(z_t))], fbar_target=list(map(float, fbar_t)),
                 p1d_rel_rms_first=[res.rms[i * M] for i in range(len(z_t))],
-                p1d_rel_rms_last=[res.rms[i * M + n_iter - 1] for i in range(len(z_t))], outer_loop=outer)
+                p1d_rel_rms_last=[res.rms[i * M + n_iter - 1] for i in range(len(z_t))], emulator=emu_inner,
+                outer_loop=outer)
 
 
 def tune_leg(L, torch, n_labels, train_steps):

@@ -381,8 +381,9 @@ int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, v
  * GPU evaluation at its optimum sets the model's offset to the measured
  * statistics there and a Broyden update corrects its slope, as in
  * lya_tune_params.  It stops when a check moves (ln amp, ln kcut) by at most
- * 5e-4, or after emu_checks GPU evaluations; a z_t that has not settled by
- * then runs the plain iteration instead (fallback[z] = 1).  Results: a, b, s
+ * 5e-4, or by at most 0.05 with the measured relative RMS P1D error changed
+ * by at most 1e-3 of itself, or after emu_checks GPU evaluations; a z_t that
+ * has not settled by then runs the plain iteration instead (fallback[z] = 1).  Results: a, b, s
  * and ps_fit[2 z .. 2 z + 1] = (amp, kcut) of the last check, p1d its P1D,
  * fbar[z][0] and rms[z][0] its mean flux and relative RMS P1D error, ratio
  * the fitted P_s over P_s^0 at each bin's centre (geometric mean of its

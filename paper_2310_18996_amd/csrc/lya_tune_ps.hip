@@ -420,6 +420,7 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
       double xk[2] = {th[0], th[1]};
       double a = a0, s = s0, step = 0.3;
       bool converged = false, ok = true;
+      double rms_prev = HUGE_VAL;
       int gpu_ev = 0;
       double rows[kMaxKBins + 1];
       // (a, s) and their slope in ln sigma_g at the sigma_g of th
@@ -478,10 +479,15 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
         xk[0] = th[0] = x[0];
         xk[1] = th[1] = x[1];
         step = 0.05;
-        if (it > 0 && moved <= xtol) {
+        // settled: the point no longer moves, or it moves a little along a
+        // valley (amp and kcut trade against each other through sigma_s)
+        // without changing the measured P1D error
+        const double rms_now = rel_rms(rows + 1);
+        if (it > 0 && (moved <= xtol || (moved <= 0.05 && fabs(rms_now - rms_prev) <= 1e-3 * rms_now))) {
           converged = true;
           break;
         }
+        rms_prev = rms_now;
       }
       res->gpu_evals[z] = gpu_ev;
       if (ok && converged) {
