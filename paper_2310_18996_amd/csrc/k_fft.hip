@@ -413,7 +413,13 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
     if (tile < P::kPairedTiles) {
       paired = true;
       outer = 1 + tile / (N / P::H);
-      t0 = (tile % (N / P::H)) * P::H;
+      // iy blocks in mirrored pairs: blocks j and N/H - j follow each other,
+      // so the pencils (ix, iy) and (ix, -iy), which need the same amplitude
+      // table entries (n^2 = nx^2 + ny^2 + nz^2), are made back to back on one
+      // XCD and the second finds the entries in its L2
+      constexpr int nb = N / P::H;
+      const int r = tile % nb;
+      t0 = (r == 0 ? 0 : r == 1 ? nb / 2 : (r & 1) ? nb - (r >> 1) : (r >> 1)) * P::H;
     } else {
       const int u = tile - P::kPairedTiles;
       outer = u < N / T ? 0 : N / 2;
