@@ -84,7 +84,9 @@ __global__ void __launch_bounds__(kTeNT, 2) k_tune_eval(TuneEvalArgs a) {
         if (with_ds) {
           // delta_S into the LDS line; each lane then reads and overwrites
           // only its own pixels' slots (pixel j at bf[2 pidx(j/2) + j%2])
-          small_scale_wave(a, a.ds_amp[g], a.ds_kcut[g], static_cast<uint64_t>(a.id_base + q), ns, buf, stw, lane);
+          // (the radix-4 FFT: this kernel keeps 64 pixel registers live)
+          small_scale_wave<TuneEvalArgs, false>(a, a.ds_amp[g], a.ds_kcut[g], static_cast<uint64_t>(a.id_base + q),
+                                                ns, buf, stw, lane);
         }
         double fsum = 0.0;
 #pragma unroll

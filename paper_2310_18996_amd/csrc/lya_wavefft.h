@@ -93,6 +93,51 @@ __device__ __forceinline__ void wave_ifft(float2* buf, int M, const float2* tw20
   }
 }
 
+// One radix-R stage of the in-place Stockham FFT wave_ifft8: s = product of the
+// radices before it; every lane first reads all of its inputs, then writes.
+template <int R>
+__device__ __forceinline__ void wave_stage(float2* buf, int M, int s, const float2* tw2048, int lane) {
+  constexpr int TMAX = kHalfMax / R / 64 > 0 ? kHalfMax / R / 64 : 1;  // butterflies per lane at M = kHalfMax
+  const int nb = M / R;
+  float2 v[TMAX][R];
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    const int j = lane + 64 * t;
+    if (j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[t][r] = buf[pidx(j + r * nb)];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < TMAX; ++t) {
+    const int j = lane + 64 * t;
+    if (j < nb) {
+      const int k = j % s;
+      if (s > 1) {
+        const int step = kTw2048 / (s * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[t][r] = cmul(v[t][r], tw2048[r * k * step]);
+      }
+      dft<R>(v[t]);
+      const int base = (j / s) * s * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx(base + r * s)] = v[t][r];
+    }
+  }
+  wave_sync();
+}
+
+// The same inverse DFT as wave_ifft by radix-8 stages (then one radix-4 or
+// radix-2 stage for what remains): fewer passes through LDS, more registers.
+__device__ __forceinline__ void wave_ifft8(float2* buf, int M, const float2* tw2048, int lane) {
+  int s = 1;
+  for (; M / s >= 8; s *= 8) wave_stage<8>(buf, M, s, tw2048, lane);
+  if (M / s == 4) wave_stage<4>(buf, M, s, tw2048, lane);
+  else if (M / s == 2) wave_stage<2>(buf, M, s, tw2048, lane);
+}
+
+
 // ---- the small-scale field delta_S along one line (section "Gaussian fields
 // along lines of sight"), shared by the skewer and tuning-evaluation kernels:
 // Philox normals (stream 1, counter (qid << 33) + m) on the modes m = 1 ..
@@ -137,8 +182,9 @@ __device__ __forceinline__ float2 ps_mode(const A& a, int m, int ns, float amp_s
 // amp exp(-(k/kcut)^2), times the ratio of k's bin when a.ps_ratio is set.
 // A supplies the Philox key (seed), the pixel length (dpix), the optional
 // table (ps_nb, ps_edges_k, ps_ratio) and the fixed-amplitude switch
-// (ps_fixed_amp).
-template <class A>
+// (ps_fixed_amp).  R8: the radix-8 FFT (fewer LDS passes); otherwise the
+// radix-4 one, for callers that cannot spare its registers.
+template <class A, bool R8 = true>
 __device__ void small_scale_wave(const A& a, double amp, double kcut, uint64_t qid, int ns, float2* buf,
                                  const float2* tw, int lane) {
   const int M = ns / 2;
@@ -182,7 +228,8 @@ __device__ void small_scale_wave(const A& a, double amp, double kcut, uint64_t q
     }
   }
   wave_sync();
-  wave_ifft(buf, M, tw, lane);
+  if constexpr (R8) wave_ifft8(buf, M, tw, lane);
+  else wave_ifft(buf, M, tw, lane);
 }
 
 }  // namespace lya
