@@ -128,10 +128,16 @@ __device__ __forceinline__ void wave_stage(float2* buf, int M, int s, const floa
   wave_sync();
 }
 
-// The same inverse DFT as wave_ifft by radix-8 stages (then one radix-4 or
-// radix-2 stage for what remains): fewer passes through LDS, more registers.
+// The same inverse DFT as wave_ifft by radix-8 stages (with radix-16 ones
+// where they save a stage, then one radix-4 or radix-2 stage for what
+// remains): fewer passes through LDS, more registers.
 __device__ __forceinline__ void wave_ifft8(float2* buf, int M, const float2* tw2048, int lane) {
+  const int lg = 31 - __clz(M);
   int s = 1;
+  // radix-16 stages where they save a stage: 16 x 8^k for lg = 1 mod 3,
+  // 16 x 16 x 8^k for lg = 2 mod 3 from 256 up
+  const int n16 = (lg % 3 == 1 && lg >= 4) ? 1 : (lg % 3 == 2 && lg >= 8) ? 2 : 0;
+  for (int i = 0; i < n16; ++i, s *= 16) wave_stage<16>(buf, M, s, tw2048, lane);
   for (; M / s >= 8; s *= 8) wave_stage<8>(buf, M, s, tw2048, lane);
   if (M / s == 4) wave_stage<4>(buf, M, s, tw2048, lane);
   else if (M / s == 2) wave_stage<2>(buf, M, s, tw2048, lane);
