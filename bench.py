@@ -56,8 +56,8 @@ HBM_PEAK_GBS = 8000.0
 # for the strided passes and by (chunk, blocks per CU, unroll) for the skewer
 # kernel; valid only for the kernels as they were when the counters were taken
 # (a changed kernel must drop its entry) and reported only for that workload.
-TRAFFIC = {("fft_x", 9): 137505215170, ("fft_y", 8): 140257527650, ("fft_z_gen", None): 95813927866,
-           ("skewers", (4, 4, 1)): 14509553350, ("qso_draw", None): 137560151198}
+TRAFFIC = {("fft_x", 9): 137490967113, ("fft_y", 8): 140316083069, ("fft_z_gen", None): 86264066663,
+           ("skewers", (4, 4, 1)): 14516776205, ("qso_draw", None): 137560151198}
 TRAFFIC_CONFIG = "big"
 
 
