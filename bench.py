@@ -61,8 +61,10 @@ TRAFFIC = {("fft_x", 9): 137490967113, ("fft_y", 8): 140316083069, ("fft_z_gen",
 TRAFFIC_CONFIG = "big"
 
 
-def measured_traffic(L, name, n):
+def measured_traffic(L, name, n, box_order="inplace"):
     t = L.get_tuning(n)
+    if name == "fft_z_gen":
+        return TRAFFIC.get((name, None if box_order == "inplace" else box_order))
     if name in ("fft_y", "fft_x"):
         return TRAFFIC.get((name, t.fft_y if name == "fft_y" else t.fft_x))
     if name == "skewers":
@@ -74,7 +76,7 @@ def algorithmic_bytes(name, n, pixels, n_sk, voxel_bytes):
     cells = float(n) ** 3
     if name == "fft_z_gen":
         return 8.0 * cells                   # writes the complex64 box
-    if name in ("fft_y", "fft_x"):
+    if name in ("fft_y", "fft_x", "fft_x2", "fft_y2"):
         return 16.0 * cells                  # reads and writes it
     if name == "skewers":
         return 12.0 * pixels + voxel_bytes + 68.0 * n_sk   # table: 2 x int64[3], int32, int64, f64
@@ -243,7 +245,7 @@ def host_facts():
 
 
 # ---------------------------------------------------------------- precision leg
-def precision_leg(L, torch, stream, reps=3):
+def precision_leg(L, torch, stream, box_order="2buf", reps=3):
     """The precision configuration (1024^3 box, 200,000 skewers): FP32 and
     BF16 storage of {delta, eta_par}, each timed (box; skewer pass with
     delta_S, FGPA and bins), and the BF16 results against the FP32 ones over
@@ -277,7 +279,8 @@ def precision_leg(L, torch, stream, reps=3):
         box = L.box_struct(n, dx, storage)
         fld = (torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda") if storage == L.LYA_F32
                else torch.empty((L.field_elems(box),), dtype=torch.int32, device="cuda"))
-        bw = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+        bw = torch.empty(L.workspace_size(L.LYA_OP_BOX_2BUF if box_order == "2buf" else L.LYA_OP_BOX, box),
+                         dtype=torch.uint8, device="cuda")
         sw = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
         d, e, fl = (torch.empty(tot, dtype=torch.float32, device="cuda") for _ in range(3))
         fs = torch.zeros(edges.numel() - 1, dtype=torch.float64, device="cuda")
@@ -996,6 +999,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the 1024^3 FP32/BF16 precision leg")
     ap.add_argument("--tune-labels", type=int, default=100_000)
     ap.add_argument("--tune-steps", type=int, default=20_000)
+    ap.add_argument("--box-order", default="2buf", choices=["2buf", "inplace"],
+                    help="FFT passes of the box: two-buffer order (one more box of workspace) or in place")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 4 GiB device copy first (reference for rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
@@ -1019,7 +1024,8 @@ def main():
     box = L.box_struct(n, dx)
     pk = L.pk_struct(**cfg["pk"])
     field = torch.empty((L.field_elems(box), 2), dtype=torch.float32, device="cuda")
-    bwork = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    box_op = L.LYA_OP_BOX_2BUF if args.box_order == "2buf" else L.LYA_OP_BOX
+    bwork = torch.empty(L.workspace_size(box_op, box), dtype=torch.uint8, device="cuda")
     swork = torch.empty(L.workspace_size(L.LYA_OP_SKEWERS, box), dtype=torch.uint8, device="cuda")
     dev = {k: torch.from_numpy(np.ascontiguousarray(sk[k])).cuda()
            for k in ("origin_fx", "step_fx", "npix", "offset", "chi0")}
@@ -1057,19 +1063,22 @@ def main():
         # launch shapes for this box size (untimed; clobbers the buffers, which
         # the warm-up steps then rewrite)
         t0 = time.perf_counter()
-        tf, ms_fft = L.autotune_fft(box, field, bwork, reps=2, stream=stream)
+        fft_auto = {}
+        if args.box_order == "inplace":  # the strided-pass variants belong to the in-place order
+            tf, ms_fft = L.autotune_fft(box, field, bwork, reps=2, stream=stream)
+            fft_auto = dict(fft_y=tf.fft_y, fft_x=tf.fft_x, fft_ms={"y": ms_fft[0], "x": ms_fft[1]})
         L.make_box(box, pk, seed, cfg["f"], True, field, bwork, stream)
         ts, ms_sk = L.autotune_skewers(box, field, s, ps, seed, cosmo, fg, dens, eta, flux, zb, swork, reps=1,
                                        stream=stream)
         torch.cuda.synchronize()
-        autotune = dict(fft_y=tf.fft_y, fft_x=tf.fft_x, sk_chunk=ts.sk_chunk, sk_blocks_per_cu=ts.sk_blocks_per_cu,
-                        sk_unroll=ts.sk_unroll, fft_ms={"y": ms_fft[0], "x": ms_fft[1]},
+        autotune = dict(fft_auto, sk_chunk=ts.sk_chunk, sk_blocks_per_cu=ts.sk_blocks_per_cu,
+                        sk_unroll=ts.sk_unroll,
                         skewer_ms={"chunks": list(L.SK_CHUNKS), "blocks_per_cu": list(L.SK_BLOCKS_PER_CU),
                                    "unroll": list(L.SK_UNROLL), "ms": ms_sk},
                         seconds=time.perf_counter() - t0)
-        print("bench: autotuned fft y=%d x=%d, skewer chunk %d blocks/CU %d unroll %d (%.1f s)" % (
-            tf.fft_y, tf.fft_x, ts.sk_chunk, ts.sk_blocks_per_cu, ts.sk_unroll, autotune["seconds"]), file=sys.stderr,
-            flush=True)
+        print("bench: autotuned %sskewer chunk %d blocks/CU %d unroll %d (%.1f s)" % (
+            "fft y=%d x=%d, " % (fft_auto["fft_y"], fft_auto["fft_x"]) if fft_auto else "", ts.sk_chunk,
+            ts.sk_blocks_per_cu, ts.sk_unroll, autotune["seconds"]), file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         step()
@@ -1117,7 +1126,7 @@ def main():
         gms = (time.perf_counter() - t2) * 1e3 / 2
         gauss = dict(what="lya_draw_skewers_gauss: 7^3 Gaussian-kernel average (343 voxels per pixel) with "
                           "delta_S, FGPA and bins, same box and skewers", ms=gms, pixels_per_s=pixels / (gms * 1e-3))
-    box_names = ("pk_sigma8", "pk_finalize", "pk_table", "fft_z_gen", "fft_y", "fft_x")
+    box_names = ("pk_sigma8", "pk_finalize", "pk_table", "fft_z_gen", "fft_y", "fft_x", "fft_x2", "fft_y2")
     sk_names = ("zchi_table", "twiddles", "skewer_reset", "skewers", "skewer_finalize")
     box_ms = sum(kt[k][0] for k in box_names if k in kt) / args.steps
     sk_ms = sum(kt[k][0] for k in sk_names if k in kt) / args.steps
@@ -1129,7 +1138,7 @@ def main():
     achieved = ab / (avg_ms * 1e-3) / 1e9 if ab else None
     roof = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=(achieved / HBM_PEAK_GBS) if achieved else None,
-                traffic=measured_traffic(L, dom, n) if args.config == TRAFFIC_CONFIG else None,
+                traffic=measured_traffic(L, dom, n, args.box_order) if args.config == TRAFFIC_CONFIG else None,
                 algorithmic_bytes_per_launch=ab, mean_launch_ms=avg_ms)
     kernels = {k: dict(mean_ms=v[0] / v[1], launches=v[1]) for k, v in sorted(kt.items())}
     for k in kernels:
@@ -1141,7 +1150,7 @@ def main():
                dtype="f32", data="synthetic",
                config=dict(workload="%s: %d^3 box at %.2f Mpc/h, %d skewers, %d pixels (%d-%d per skewer)" % (
                    args.config, n, dx, n_sk, pixels, int(sk["npix"].min()), int(sk["npix"].max())),
-                   n=n, dx=dx, n_skewers=n_sk, pixels=pixels, seed=seed),
+                   n=n, dx=dx, n_skewers=n_sk, pixels=pixels, seed=seed, box_order=args.box_order),
                box_cells_per_s=cells / (box_ms * 1e-3), box_ms=box_ms,
                skewer_pixels_per_s=pixels / (sk_ms * 1e-3), skewer_ms=sk_ms,
                distinct_voxels_per_pixel=vox_per_pix, roofline=roof, kernels=kernels, autotune=autotune,
@@ -1160,13 +1169,14 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_rocfft:
         print("bench: rocFFT comparison line", file=sys.stderr, flush=True)
-        fft_ms = sum(kernels[k]["mean_ms"] for k in ("fft_z_gen", "fft_y", "fft_x") if k in kernels)
+        fft_ms = sum(kernels[k]["mean_ms"] for k in ("fft_z_gen", "fft_y", "fft_x", "fft_x2", "fft_y2")
+                     if k in kernels)
         out["rocfft"] = rocfft_leg(torch, n, fft_ms)
     else:
         out["rocfft"] = None
     if not args.no_precision:
         print("bench: precision configuration (FP32 and BF16 storage)", file=sys.stderr, flush=True)
-        out["precision"] = precision_leg(L, torch, stream)
+        out["precision"] = precision_leg(L, torch, stream, args.box_order)
     else:
         out["precision"] = None
     if not args.no_quasars:

@@ -48,7 +48,7 @@ enum { LYA_C_NONE = -1, LYA_C_DELTA = 0, LYA_C_XX = 1, LYA_C_YY = 2, LYA_C_ZZ = 
        LYA_C_XY = 4, LYA_C_XZ = 5, LYA_C_YZ = 6, LYA_C_VX = 7, LYA_C_VY = 8, LYA_C_VZ = 9 };
 
 /* Workspace kinds for lya_workspace_size. */
-enum { LYA_OP_BOX = 0, LYA_OP_SKEWERS = 1, LYA_OP_QUASARS = 2 };
+enum { LYA_OP_BOX = 0, LYA_OP_SKEWERS = 1, LYA_OP_QUASARS = 2, LYA_OP_BOX_2BUF = 3 };
 
 /* Periodic box (section "Mock generation"). */
 typedef struct {
@@ -128,7 +128,10 @@ size_t lya_plane_pitch(const lya_box* box);
 
 /* Bytes of device workspace a call needs.  op = LYA_OP_BOX for lya_make_box,
  * lya_make_eta and lya_make_box_pair (for LYA_BF16 storage this includes an
- * n^3 complex64 staging box), LYA_OP_SKEWERS for lya_draw_skewers and
+ * n^3 complex64 staging box); LYA_OP_BOX_2BUF for the same calls with one more
+ * complex64 box of workspace, with which they run their FFT passes in the
+ * two-buffer order (faster for large boxes; see lya_make_box);
+ * LYA_OP_SKEWERS for lya_draw_skewers and
  * lya_apply_fgpa, LYA_OP_QUASARS for lya_box_moments, lya_draw_quasars and
  * lya_quasar_skewers.
  * Returns 0 for invalid arguments. */
@@ -140,7 +143,16 @@ size_t lya_workspace_size(int op, const lya_box* box);
  * eta_par_hat = f mu_z^2 delta_hat (line of sight = z axis), and writes the
  * real-space box {delta, eta_par} = inverse DFT (unnormalised, exp(+i k.x)).
  * field: device, n^3 cells of the box's storage type.  with_eta = 0 writes
- * eta_par = 0.  work: device, >= lya_workspace_size(LYA_OP_BOX, box) bytes. */
+ * eta_par = 0.  work: device, >= lya_workspace_size(LYA_OP_BOX, box) bytes.
+ * The inverse DFT runs as three 1D passes.  With work_bytes >=
+ * lya_workspace_size(LYA_OP_BOX_2BUF, box) the z pass writes its pencils
+ * with x and y exchanged into the workspace's second box, the x pass reads
+ * them there within planes and writes field transposed back, and the y pass
+ * finishes in place: no pass reads across the x planes, and the box is the
+ * same up to rounding (the x and y
+ * transforms run in the other order).  With less workspace the passes run
+ * z, y, x in place in field.  Either way the result for a given workspace
+ * size is deterministic. */
 int lya_make_box(const lya_box* box, const lya_pk* pk, uint64_t seed, double f, int with_eta,
                  void* field, void* work, size_t work_bytes, void* stream);
 

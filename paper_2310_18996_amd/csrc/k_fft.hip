@@ -15,6 +15,15 @@
 //           registers (no spectrum is ever written to memory), FFT along z;
 //   pass Y: tiles of N (y) x T (z contiguous) elements, FFT along y;
 //   pass X: tiles of N (x) x T (z contiguous) elements, FFT along x.
+// The X pass reads pencils whose elements lie in N planes 32 MB apart (at
+// 2048^3), which costs address translation.  With a second box buffer the
+// passes run in the two-buffer order instead:
+//   pass Z writes the pencil of modes (kx, ky) at plane ky, row kx of buffer A;
+//   pass YT transforms along the rows of A (over kx) and writes plane kx,
+//           row ky of the field: a strided write, and writes do not wait;
+//   pass Y  transforms the field in place along its rows (over ky).
+// Both strided passes then read within one plane, the result is the same
+// box with the two 1D transforms in the other order (equal up to rounding).
 // Each tile is transformed by a Stockham autosort FFT with radix-4/8/16
 // butterflies: stage 0 works on registers filled from global memory (or the
 // synthesiser), middle stages exchange through LDS, the last stage writes
@@ -27,7 +36,7 @@
 
 namespace lya {
 
-enum { KIND_GENZ = 0, KIND_Y = 1, KIND_X = 2 };
+enum { KIND_GENZ = 0, KIND_Y = 1, KIND_X = 2, KIND_YT = 3 };
 
 constexpr int radix_of(int n, int s) {
   return n == 2048 ? (s < 2 ? 16 : 8)
@@ -146,7 +155,8 @@ __device__ __forceinline__ float2 gen_mode(const GenParams& g, int ix, int iy, i
   return make_float2(s * (w.x * ma - w.y * mb), s * (w.y * ma + w.x * mb));
 }
 
-template <int N, int T, int E, int KIND>
+// SWZ (pass Z of the two-buffer order): pencil (kx, ky) goes to plane ky, row kx.
+template <int N, int T, int E, int KIND, bool SWZ = false>
 struct Pass {
   static constexpr int NT = N * T / E;
   static constexpr bool PF = KIND != KIND_GENZ;  // lanes walk the T contiguous pencils first
@@ -164,12 +174,20 @@ struct Pass {
   // synthesising pass outer is ix and t0 is iy0 (paired flags the tile kind)
   __device__ static __forceinline__ size_t gidx(int outer, int t0, int i, int p, bool paired = false) {
     if (KIND == KIND_GENZ) {
-      if (paired && p >= H)
-        return static_cast<size_t>(N - outer) * kPitch + static_cast<size_t>((N - t0 - (p - H)) & (N - 1)) * N + i;
-      return static_cast<size_t>(outer) * kPitch + static_cast<size_t>(t0 + p) * N + i;
+      const int px = paired && p >= H ? N - outer : outer;
+      const int py = paired && p >= H ? (N - t0 - (p - H)) & (N - 1) : t0 + p;
+      return SWZ ? static_cast<size_t>(py) * kPitch + static_cast<size_t>(px) * N + i
+                 : static_cast<size_t>(px) * kPitch + static_cast<size_t>(py) * N + i;
     }
-    if (KIND == KIND_Y) return static_cast<size_t>(outer) * kPitch + static_cast<size_t>(i) * N + t0 + p;
+    if (KIND == KIND_Y || KIND == KIND_YT)
+      return static_cast<size_t>(outer) * kPitch + static_cast<size_t>(i) * N + t0 + p;
     return static_cast<size_t>(i) * kPitch + static_cast<size_t>(outer) * N + t0 + p;
+  }
+  // where the last stage stores element i of pencil p: KIND_YT writes plane
+  // i, row outer (of the other buffer); every other pass where it read
+  __device__ static __forceinline__ size_t gidx_out(int outer, int t0, int i, int p, bool paired) {
+    if (KIND == KIND_YT) return static_cast<size_t>(i) * kPitch + static_cast<size_t>(outer) * N + t0 + p;
+    return gidx(outer, t0, i, p, paired);
   }
   // LDS layout with one padding slot per R0 elements along the FFT axis (R0 =
   // first radix): the first stage scatters its outputs with stride R0, which
@@ -278,7 +296,7 @@ struct Pass {
       coords<R>(tid + b * NT, p, j);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const size_t gi = gidx(outer, t0, j + r * (N / R), p, paired);
+        const size_t gi = gidx_out(outer, t0, j + r * (N / R), p, paired);
         // a single requested component: the other half is exactly zero, not FFT rounding residue
         const float2 o = make_float2(v[b * R + r].x, zero_b ? 0.0f : v[b * R + r].y);
         if (out_bf16) {
@@ -397,10 +415,13 @@ __device__ __forceinline__ void gen_paired(const GenParams& g, int ix, int iy0, 
   }
 }
 
-template <int N, int T, int E, int KIND, int ORDER = 1, int GM = GEN_GENERIC>
+// SWZ: pass Z of the two-buffer order; LAST: the box's last pass (BF16 output,
+// exact zeros for a single requested component).  KIND_YT stores to g.dst.
+template <int N, int T, int E, int KIND, int ORDER = 1, int GM = GEN_GENERIC, bool SWZ = false,
+          bool LAST = KIND == KIND_X>
 __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ data, uint32_t* __restrict__ out_bf16,
                                                         const float2* __restrict__ tw, GenParams g) {
-  using P = Pass<N, T, E, KIND>;
+  using P = Pass<N, T, E, KIND, SWZ>;
   constexpr int NT = P::NT;
   __shared__ float2 lds[P::LDS_ELEMS];
   float2 v[E];
@@ -450,8 +471,8 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
   } else {
     P::load_global0(v, data, outer, t0, tid);
   }
-  P::transform_store(v, lds, data, KIND == KIND_X ? out_bf16 : nullptr, tw, KIND == KIND_X && g.comp_b < 0, outer,
-                     t0, paired, tid);
+  P::transform_store(v, lds, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr, tw, LAST && g.comp_b < 0,
+                     outer, t0, paired, tid);
 }
 
 // Persistent, software-pipelined strided pass: each block walks tiles
@@ -460,7 +481,7 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
 // next tile before transforming the current one, so that their latency hides
 // behind the FFT and the stores.  Two register copies of a tile: the waves
 // are allowed the larger register budget of two waves per SIMD.
-template <int N, int T, int E, int KIND, int ORDER>
+template <int N, int T, int E, int KIND, int ORDER, bool LAST = KIND == KIND_X>
 __global__ void __launch_bounds__(N * T / E) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const float2* __restrict__ tw, GenParams g) {
   using P = Pass<N, T, E, KIND>;
@@ -490,7 +511,7 @@ k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const flo
       strided_tile<N, T, ORDER>(bn, on, tn);
       P::load_global0(nv, data, on, tn, tid);
     }
-    P::transform_store(v, lds, data, KIND == KIND_X ? out_bf16 : nullptr, stw, KIND == KIND_X && g.comp_b < 0,
+    P::transform_store(v, lds, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr, stw, LAST && g.comp_b < 0,
                        outer, t0, false, tid);
     if (!more) break;
     __syncthreads();  // every thread has read this tile's LDS before the next one is written
@@ -588,29 +609,76 @@ hipError_t launch_strided(int variant, float2* field, uint32_t* bf16, const floa
   return launch_strided_tile<N, S::TS, S::ES, KIND, 0, false>(field, bf16, tw, g, st);
 }
 
-template <int N>
-hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16, hipStream_t st) {
+template <int N, bool SWZ>
+hipError_t launch_zgen(const GenParams& g, int gm, const float2* tw, float2* out, hipStream_t st) {
   using S = Shape<N>;
   const int tz = N * (N / S::TZ);
+  if (gm == GEN_DELTA_ETAZ) {
+    LYA_TIMED("fft_z_gen", st,
+              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_DELTA_ETAZ, SWZ>), dim3(tz),
+                                 dim3(N * S::TZ / S::EZ), 0, st, out, nullptr, tw, g));
+  } else if (gm == GEN_DELTA) {
+    LYA_TIMED("fft_z_gen", st,
+              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_DELTA, SWZ>), dim3(tz),
+                                 dim3(N * S::TZ / S::EZ), 0, st, out, nullptr, tw, g));
+  } else {
+    LYA_TIMED("fft_z_gen", st,
+              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_GENERIC, SWZ>), dim3(tz),
+                                 dim3(N * S::TZ / S::EZ), 0, st, out, nullptr, tw, g));
+  }
+  return hipGetLastError();
+}
+
+// The two strided passes of the two-buffer order: the transposing pass
+// (second -> field, over kx) and the last pass (field in place, over ky);
+// from 1024 up in the pipelined kernel with full tiles of half the elements
+// per thread and tile order 1 (the shape of strided variant 9: at 2048^3,
+// 38.1 + 33.5 ms against 39.3 + 34.2 ms in order 0), below as one tile per
+// block.
+template <int N>
+hipError_t launch_two_buffer(GenParams g, const float2* tw, float2* second, float2* field, uint32_t* field_bf16,
+                             hipStream_t st) {
+  using S = Shape<N>;
+  g.dst = field;
+  if constexpr (N >= 1024) {
+    constexpr int T = S::TS, E = S::ES / 2, ntiles = N * (N / T), nt = N * T / E;
+    int blocks = (device_cus() + 7) / 8 * 8;
+    if (blocks > ntiles) blocks = ntiles;
+    LYA_TIMED("fft_x2", st,
+              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_YT, 1>), dim3(blocks), dim3(nt), 0, st, second, nullptr,
+                                 tw, g));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LYA_TIMED("fft_y2", st,
+              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_Y, 1, true>), dim3(blocks), dim3(nt), 0, st, field,
+                                 field_bf16, tw, g));
+  } else {
+    constexpr int T = S::TS, E = S::ES, ntiles = N * (N / T), nt = N * T / E;
+    LYA_TIMED("fft_x2", st,
+              hipLaunchKernelGGL((k_fft_pass<N, T, E, KIND_YT, 0>), dim3(ntiles), dim3(nt), 0, st, second, nullptr,
+                                 tw, g));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LYA_TIMED("fft_y2", st,
+              hipLaunchKernelGGL((k_fft_pass<N, T, E, KIND_Y, 0, GEN_GENERIC, false, true>), dim3(ntiles), dim3(nt),
+                                 0, st, field, field_bf16, tw, g));
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16, float2* second,
+                       hipStream_t st) {
   const bool hooks = g.fixed_amp || g.only_n2 >= 0 || g.table_b;
   const int gm = (!hooks && g.comp_a == 0 && g.comp_b == 3)    ? GEN_DELTA_ETAZ
                  : (!hooks && g.comp_a == 0 && g.comp_b == -1) ? GEN_DELTA
                                                                : GEN_GENERIC;
-  if (gm == GEN_DELTA_ETAZ) {
-    LYA_TIMED("fft_z_gen", st,
-              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_DELTA_ETAZ>), dim3(tz),
-                                 dim3(N * S::TZ / S::EZ), 0, st, field, nullptr, tw, g));
-  } else if (gm == GEN_DELTA) {
-    LYA_TIMED("fft_z_gen", st,
-              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_DELTA>), dim3(tz),
-                                 dim3(N * S::TZ / S::EZ), 0, st, field, nullptr, tw, g));
-  } else {
-    LYA_TIMED("fft_z_gen", st,
-              hipLaunchKernelGGL((k_fft_pass<N, S::TZ, S::EZ, KIND_GENZ, 0, GEN_GENERIC>), dim3(tz),
-                                 dim3(N * S::TZ / S::EZ), 0, st, field, nullptr, tw, g));
+  hipError_t e;
+  if (second) {
+    if ((e = launch_zgen<N, true>(g, gm, tw, second, st)) != hipSuccess) return e;
+    return launch_two_buffer<N>(g, tw, second, field, field_bf16, st);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if ((e = launch_zgen<N, false>(g, gm, tw, field, st)) != hipSuccess) return e;
   if ((e = launch_strided<N, KIND_Y>(fft_variant(N, 0), field, nullptr, tw, g, st)) != hipSuccess) return e;
   return launch_strided<N, KIND_X>(fft_variant(N, 1), field, field_bf16, tw, g, st);
 }
@@ -631,15 +699,15 @@ hipError_t launch_fft_strided_pass(int n, int pass, int variant, const float2* t
 }
 
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
-                          hipStream_t st) {
+                          float2* second, hipStream_t st) {
   switch (n) {
-    case 32: return run_box_fft<32>(g, tw, field, field_bf16, st);
-    case 64: return run_box_fft<64>(g, tw, field, field_bf16, st);
-    case 128: return run_box_fft<128>(g, tw, field, field_bf16, st);
-    case 256: return run_box_fft<256>(g, tw, field, field_bf16, st);
-    case 512: return run_box_fft<512>(g, tw, field, field_bf16, st);
-    case 1024: return run_box_fft<1024>(g, tw, field, field_bf16, st);
-    case 2048: return run_box_fft<2048>(g, tw, field, field_bf16, st);
+    case 32: return run_box_fft<32>(g, tw, field, field_bf16, second, st);
+    case 64: return run_box_fft<64>(g, tw, field, field_bf16, second, st);
+    case 128: return run_box_fft<128>(g, tw, field, field_bf16, second, st);
+    case 256: return run_box_fft<256>(g, tw, field, field_bf16, second, st);
+    case 512: return run_box_fft<512>(g, tw, field, field_bf16, second, st);
+    case 1024: return run_box_fft<1024>(g, tw, field, field_bf16, second, st);
+    case 2048: return run_box_fft<2048>(g, tw, field, field_bf16, second, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -53,10 +53,12 @@ bool pow2_in_range(int n) { return n >= 32 && n <= 2048 && (n & (n - 1)) == 0; }
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct BoxCarve {
-  size_t partial, amp, tw, table, table_b, staging, total;
+  size_t partial, amp, tw, table, table_b, staging, second, total;
 };
 
-BoxCarve carve_box(const lya_box* b) {
+// two_buffer: room for a second complex64 box after the staging box (the
+// two-buffer order of the FFT passes)
+BoxCarve carve_box(const lya_box* b, bool two_buffer = false) {
   BoxCarve c{};
   size_t o = 0;
   c.partial = o; o += align256(sizeof(double) * lya::kSigmaBlocks);
@@ -66,6 +68,8 @@ BoxCarve carve_box(const lya_box* b) {
   c.table_b = o; o += align256(sizeof(float) * lya::amp_table_entries(b->n));
   c.staging = o;
   if (b->storage == LYA_BF16) o += align256(sizeof(float2) * lya::box_elems(b->n));
+  c.second = o;
+  if (two_buffer) o += align256(sizeof(float2) * lya::box_elems(b->n));
   c.total = o;
   return c;
 }
@@ -200,6 +204,7 @@ int make_pair(const lya_box* box, const lya_pk* pk, const lya_pk* pk_b, uint64_t
     return fail(LYA_EINVAL, "unknown field component%s");
   const BoxCarve c = carve_box(box);
   if (work_bytes < c.total) return fail(LYA_EWORKSPACE, "workspace too small for the box%s");
+  const bool two_buffer = work_bytes >= carve_box(box, true).total;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(work);
   lya::TableWork tw{reinterpret_cast<double*>(w + c.partial), reinterpret_cast<double*>(w + c.amp),
@@ -219,7 +224,8 @@ int make_pair(const lya_box* box, const lya_pk* pk, const lya_pk* pk_b, uint64_t
                    static_cast<float>(vscale)};
   float2* f32 = box->storage == LYA_F32 ? static_cast<float2*>(field) : reinterpret_cast<float2*>(w + c.staging);
   uint32_t* b16 = box->storage == LYA_BF16 ? static_cast<uint32_t*>(field) : nullptr;
-  e = lya::launch_box_fft(box->n, g, tw.tw, f32, b16, st);
+  e = lya::launch_box_fft(box->n, g, tw.tw, f32, b16, two_buffer ? reinterpret_cast<float2*>(w + c.second) : nullptr,
+                          st);
   if (e != hipSuccess) return hip_fail(e, "box FFT");
   return LYA_OK;
 }
@@ -463,9 +469,9 @@ size_t lya_plane_pitch(const lya_box* box) {
 }
 
 size_t lya_workspace_size(int op, const lya_box* box) {
-  if (op == LYA_OP_BOX) {
+  if (op == LYA_OP_BOX || op == LYA_OP_BOX_2BUF) {
     if (!box || !pow2_in_range(box->n) || (box->storage != LYA_F32 && box->storage != LYA_BF16)) return 0;
-    return carve_box(box).total;
+    return carve_box(box, op == LYA_OP_BOX_2BUF).total;
   }
   if (op == LYA_OP_SKEWERS) return carve_sk().total;
   if (op == LYA_OP_QUASARS) return carve_qso().total;

@@ -56,6 +56,7 @@ struct GenParams {
   int fixed_amp;
   int only_n2;
   float vscale;        // velocities: f 100 L / (2 pi), km/s
+  float2* dst;         // the transposing pass of the two-buffer order writes here
 };
 
 // Optional event timing around each launch (see lya_timing_enable).
@@ -80,8 +81,10 @@ hipError_t launch_zchi_table(double omega_m, float* ztab, hipStream_t st);
 hipError_t launch_xi_weights(const PkParams& p, double s, double h, int m, double* partial, double* amp,
                              double* f, hipStream_t st);
 hipError_t launch_twiddles(float2* tw, int ntw, hipStream_t st);
+// second: a complex64 box buffer of the same size (workspace) for the
+// two-buffer order, or null for the in-place order.
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
-                          hipStream_t st);
+                          float2* second, hipStream_t st);
 // Strided-pass variants (0..kFftVariants-1) per box size and pass (0 = y, 1 = x).
 constexpr int kFftVariants = 14;
 int fft_variant(int n, int pass);

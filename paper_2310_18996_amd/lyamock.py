@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "liblyamock.so")
 
 LYA_OK, LYA_EINVAL, LYA_EWORKSPACE, LYA_EUNSUPPORTED, LYA_EHIP = 0, -1, -2, -3, -4
 LYA_F32, LYA_BF16 = 0, 1
-LYA_OP_BOX, LYA_OP_SKEWERS, LYA_OP_QUASARS = 0, 1, 2
+LYA_OP_BOX, LYA_OP_SKEWERS, LYA_OP_QUASARS, LYA_OP_BOX_2BUF = 0, 1, 2, 3
 LYA_C_NONE, LYA_C_DELTA, LYA_C_XX, LYA_C_YY, LYA_C_ZZ, LYA_C_XY, LYA_C_XZ, LYA_C_YZ = -1, 0, 1, 2, 3, 4, 5, 6
 LYA_C_VX, LYA_C_VY, LYA_C_VZ = 7, 8, 9
 COMPONENTS = {"none": -1, "delta": 0, "xx": 1, "yy": 2, "zz": 3, "xy": 4, "xz": 5, "yz": 6, "vx": 7, "vy": 8,

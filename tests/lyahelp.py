@@ -41,12 +41,13 @@ def oracle_table(cfg_pk, n, dx, smooth=0.0):
     return power.amplitude_table(pk, n, dx, smooth)
 
 
-def gpu_box(L, n, dx, seed, f=1.0, with_eta=True, storage=0, comps=None, **pkkw):
+def gpu_box(L, n, dx, seed, f=1.0, with_eta=True, storage=0, comps=None, two_buffer=False, **pkkw):
     """Run lya_make_box (or lya_make_eta when comps is given) and return the
-    device field tensor."""
+    device field tensor; two_buffer gives it the workspace of the two-buffer
+    order of the FFT passes."""
     box = L.box_struct(n, dx, storage)
     pk = L.pk_struct(**pkkw)
-    ws = L.workspace_size(L.LYA_OP_BOX, box)
+    ws = L.workspace_size(L.LYA_OP_BOX_2BUF if two_buffer else L.LYA_OP_BOX, box)
     work = torch.empty(ws, dtype=torch.uint8, device="cuda")
     elems = L.field_elems(box)
     if storage == L.LYA_F32:

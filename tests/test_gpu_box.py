@@ -22,11 +22,12 @@ def L():
     return lyamock
 
 
+@pytest.mark.parametrize("two_buffer", [False, True])
 @pytest.mark.parametrize("n", [32, 64, 128])
-def test_box_matches_oracle(L, n):
+def test_box_matches_oracle(L, n, two_buffer):
     dx, seed, f = 2.19, 1234, 1.0
-    print("box parity n=%d seed=%d" % (n, seed), flush=True)
-    g = gpu_box(L, n, dx, seed, f, **PK).cpu().numpy().astype(np.float64)
+    print("box parity n=%d seed=%d two-buffer %s" % (n, seed, two_buffer), flush=True)
+    g = gpu_box(L, n, dx, seed, f, two_buffer=two_buffer, **PK).cpu().numpy().astype(np.float64)
     tab = oracle_table(PK, n, dx)
     ref = field.make_box(n, seed, tab, ("delta", "zz"), f=f)
     e_d = rel_rms(g[..., 0], ref.real)
@@ -47,10 +48,11 @@ def test_box_without_eta_and_f(L):
     assert rel_rms(g2[..., 1], ref.imag) < TOL
 
 
+@pytest.mark.parametrize("two_buffer", [False, True])
 @pytest.mark.parametrize("comps", [("xy", "yz"), ("xx", "yy"), ("xz", "none"), ("zz", "delta")])
-def test_make_eta_components(L, comps):
+def test_make_eta_components(L, comps, two_buffer):
     n, dx = 64, 2.19
-    g = gpu_box(L, n, dx, 5, 0.9, comps=comps, **PK).cpu().numpy().astype(np.float64)
+    g = gpu_box(L, n, dx, 5, 0.9, comps=comps, two_buffer=two_buffer, **PK).cpu().numpy().astype(np.float64)
     tab = oracle_table(PK, n, dx)
     oc = (comps[0],) if comps[1] == "none" else comps
     ref = field.make_box(n, 5, tab, oc, f=0.9)
@@ -99,12 +101,13 @@ def test_deterministic(L):
     np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("two_buffer", [False, True])
 @pytest.mark.parametrize("n", [256, 512])
-def test_box_lines_against_c_oracle(L, n):
+def test_box_lines_against_c_oracle(L, n, two_buffer):
     """Sampled whole z-lines (exact FP64, plain C oracle) plus Parseval."""
     dx, seed = 2.19, 1234
-    print("line parity n=%d" % n, flush=True)
-    gt = gpu_box(L, n, dx, seed, 1.0, **PK)   # [n, n, n, 2] view of the padded box
+    print("line parity n=%d two-buffer %s" % (n, two_buffer), flush=True)
+    gt = gpu_box(L, n, dx, seed, 1.0, two_buffer=two_buffer, **PK)   # [n, n, n, 2] view of the padded box
     cols = [(0, 0), (1, n - 1), (n // 2, 3), (n - 1, n // 2)]
     tab = oracle_table(PK, n, dx)
     re, im = lines.field_lines(n, seed, tab, cols)
@@ -133,3 +136,36 @@ def test_tabulated_power_spectrum(L):
         L.pk_struct(k_tab=kt)
     with pytest.raises(L.LyaError):
         gpu_box(L, n, dx, seed, 1.0, k_tab=kt[:1], p_tab=pt[:1])
+
+
+@pytest.mark.parametrize("n", [64, 1024])
+def test_two_buffer_order_against_in_place(L, n):
+    """The two orders of the FFT passes give the same box up to rounding
+    (FP32), and BF16 storage differs by at most one bf16 step where the FP32
+    values straddle a rounding boundary; with fixed amplitudes (the generic
+    synthesiser) too.  The plane padding is never written."""
+    import torch
+    dx, seed = 2.19, 99
+    print("two-buffer against in-place n=%d" % n, flush=True)
+    for kw in (dict(), dict(fixed_amp=True)):
+        a = gpu_box(L, n, dx, seed, 1.0, **dict(PK, **kw)).clone()
+        b = gpu_box(L, n, dx, seed, 1.0, two_buffer=True, **dict(PK, **kw))
+        e = (rel_rms(b[..., 0].cpu().numpy().astype(np.float64), a[..., 0].cpu().numpy().astype(np.float64)),
+             rel_rms(b[..., 1].cpu().numpy().astype(np.float64), a[..., 1].cpu().numpy().astype(np.float64)))
+        print("FP32 %s: rel rms %.2e %.2e" % (kw, e[0], e[1]), flush=True)
+        assert max(e) < 1e-6
+        del a, b
+        torch.cuda.empty_cache()
+    a = gpu_box(L, n, dx, seed, 1.0, storage=L.LYA_BF16, **PK).clone()
+    b = gpu_box(L, n, dx, seed, 1.0, storage=L.LYA_BF16, two_buffer=True, **PK)
+    fa, fb = bf16_to_f32(a), bf16_to_f32(b)
+    diff = np.abs(fa - fb)
+    # one bf16 step at the value's magnitude, plus what the FP32 values may
+    # differ by (2e-5 of the field's RMS, tens of times their RMS difference),
+    # which decides the rounding near zero
+    rms = np.sqrt(np.mean(fa.astype(np.float64) ** 2, axis=(0, 1, 2)))
+    step = np.maximum(np.abs(fa), np.abs(fb)) * 2.0 ** -7 + 2e-5 * rms
+    frac = float(np.mean(diff > 0))
+    print("BF16: fraction of cells that differ %.2e, largest excess %.2e" % (frac, float(np.max(diff - step))),
+          flush=True)
+    assert np.all(diff <= step) and frac < 1e-2

@@ -122,13 +122,16 @@ def gpu_p1d(L, torch, handles, k_edges, z_ref, cfg, n_sk):
     return ps.cpu().numpy(), pc.cpu().numpy()
 
 
-def make_box(L, torch, cfg, storage, **pk_over):
+def make_box(L, torch, cfg, storage, two_buffer=True, **pk_over):
+    """The box in the two-buffer order of the FFT passes, as the benchmark
+    makes it (two_buffer=False: the in-place order)."""
     n = cfg["n"]
     box = L.box_struct(n, cfg["dx"], storage)
     elems = L.field_elems(box)
     fld = (torch.empty((elems, 2), dtype=torch.float32, device="cuda") if storage == L.LYA_F32
            else torch.empty((elems,), dtype=torch.int32, device="cuda"))
-    work = torch.empty(L.workspace_size(L.LYA_OP_BOX, box), dtype=torch.uint8, device="cuda")
+    work = torch.empty(L.workspace_size(L.LYA_OP_BOX_2BUF if two_buffer else L.LYA_OP_BOX, box), dtype=torch.uint8,
+                       device="cuda")
     L.make_box(box, L.pk_struct(**dict(cfg["pk"], **pk_over)), cfg["seed"], cfg["f"], True, fld, work)
     torch.cuda.synchronize()
     del work
@@ -142,12 +145,13 @@ def bin_sums_close(gpu_fsum, fs, cnt):
 
 
 @pytest.mark.timeout(600)
-def test_big_box_lines(L):
+@pytest.mark.parametrize("two_buffer", [True, False])
+def test_big_box_lines(L, two_buffer):
     import torch
     cfg = mockinputs.config("big")
     n = cfg["n"]
-    print("2048^3 box: lines against the C oracle", flush=True)
-    box, fld = make_box(L, torch, cfg, L.LYA_F32)
+    print("2048^3 box (two-buffer order %s): lines against the C oracle" % two_buffer, flush=True)
+    box, fld = make_box(L, torch, cfg, L.LYA_F32, two_buffer)
     view = L.box_view(fld, n)
     cols = [(0, 0), (1, n - 1), (n // 2, 3), (1234, 777)]
     re, im = lines.field_lines(n, cfg["seed"], oracle_table(cfg["pk"], n, cfg["dx"]), cols)
