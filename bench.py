@@ -702,10 +702,22 @@ def ps_emulator_run(L, torch, spec, tw, emock, n_outer, n_labels, train_steps, s
     for i in range(nz):
         spec.emu[i] = emus[i].data_ptr()
     spec.emu_checks = 10
+    spec.emu_refine = 0
     re_ = L.tune_ps(spec, tw)
+    # the fit followed by five per-bin iterations at its (a, s)
+    spec.emu_refine = 5
+    rr = L.tune_ps(spec, tw)
+    spec.emu_refine = 0
     spec.mode, spec.n_iter, spec.n_outer = saved
+    M = L.TUNE_PS_MAX_ITER
+    refined = dict(emu_refine=5, seconds=rr.seconds, gpu_evals=[rr.gpu_evals[i] for i in range(nz)],
+                   fallback=[rr.fallback[i] for i in range(nz)],
+                   p1d_rel_rms=[rr.rms[i * M + 4] for i in range(nz)],
+                   fbar=[rr.fbar[i * M + 4] for i in range(nz)],
+                   beff=[rr.beff[i * L.TUNE_PS_MAX_OUTER] for i in range(nz)],
+                   growth=[rr.growth[i] for i in range(nz)])
     costs = dict(setup_s=t_setup, labels_s=t_lab, train_s=t_train, labels_per_z=n_labels, train_steps_per_z=train_steps,
-                 train_loss_final=losses)
+                 train_loss_final=losses, refined=refined)
     return re_, costs
 
 
@@ -803,6 +815,7 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
     emock = stored_pixels(L, torch, ecfg, ecfg["seed"], ecfg["seed"])
     re_a, costs_a = ps_emulator_run(L, torch, spec, tw, emock, 0, emu_labels, emu_steps, ecfg["seed"])
     emu_inner = ps_emulator_record(L, re_a, res, len(z_t), n_iter, costs_a)
+    emu_inner["refined"]["speedup"] = res.seconds / emu_inner["refined"]["seconds"]
     print("bench: tune_ps emulator mode (inner) %.3f s against plain %.3f s" % (re_a.seconds, res.seconds),
           file=sys.stderr, flush=True)
     # the outer loop (five steps) against the paper's own targets: Fbar(z) of
@@ -862,6 +875,9 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
     emu_outer = ps_emulator_record(L, re_b, res5, len(z_t), n_iter, costs_b)
     emu_outer["beff_over_target"] = [re_b.beff[i * MO] / (beff_p[i] * re_b.growth[i]) if not re_b.fallback[i]
                                      else None for i in range(len(z_t))]
+    rf = emu_outer["refined"]
+    rf["beff_over_target"] = [rf["beff"][i] / (beff_p[i] * rf["growth"][i]) for i in range(len(z_t))]
+    rf["speedup"] = res5.seconds / rf["seconds"]
     print("bench: tune_ps emulator mode (outer) %.3f s against plain %.3f s" % (re_b.seconds, res5.seconds),
           file=sys.stderr, flush=True)
     steps = [res5.n_outer_done[i] for i in range(len(z_t))]

@@ -400,6 +400,11 @@ int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, v
  * fbar[z][0] and rms[z][0] its mean flux and relative RMS P1D error, ratio
  * the fitted P_s over P_s^0 at each bin's centre (geometric mean of its
  * edges in h/Mpc), beff[z][0] the effective bias there, n_outer_done[z] = 1.
+ * With emu_refine = n > 0, n iterations of the per-bin update (step 2 above)
+ * follow the fit, with P_s^0 the fitted form and (a, s) those of the fit (b
+ * from sigma_g at each iteration); fbar, rms and p1d then describe them,
+ * ratio holds the per-bin factors on top of the fitted form, and beff[z][0]
+ * the effective bias at the last iteration's sigma_g.
  * gpu_evals[z] counts GPU evaluations of the statistics in both modes.
  * Synchronous; GPU work on `stream`; errors in lya_tune_ps_last_error(). */
 #define LYA_TUNE_PS_MAX_ITER 16
@@ -426,6 +431,7 @@ typedef struct {
   int32_t mode;              /* LYA_TUNE_PS_RATIOS (the paper's iteration) or LYA_TUNE_PS_EMULATOR */
   const void* emu[LYA_TUNE_MAX_Z];  /* emulator mode: device emulator per z_t, 1 + n_kbins outputs */
   int32_t emu_checks;        /* emulator mode: GPU evaluations per z_t, 1..16 */
+  int32_t emu_refine;        /* emulator mode: per-bin iterations after the fit, 0..16 */
 } lya_tune_ps_spec;
 
 typedef struct {

@@ -300,6 +300,8 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
   const bool emu_mode = spec->mode == LYA_TUNE_PS_EMULATOR;
   if (emu_mode) {
     if (spec->emu_checks < 1 || spec->emu_checks > 16) return pfail(LYA_EINVAL, "emu_checks must be in [1, 16]");
+    if (spec->emu_refine < 0 || spec->emu_refine > LYA_TUNE_PS_MAX_ITER)
+      return pfail(LYA_EINVAL, "emu_refine must be in [0, 16]");
     for (int z = 0; z < spec->n_zt; ++z)
       if (!spec->emu[z]) return pfail(LYA_EINVAL, "emulator mode needs an emulator at every z_t");
   }
@@ -370,7 +372,6 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
     return phip(e, "k edges read-back");
   const double zb_edges[2] = {-1e30, 1e30};
   lya_zbins zb{1, d_zb, d_zb + 2, reinterpret_cast<int64_t*>(d_zb + 3)};
-  lya_ps1d ps{spec->ps_amp, spec->ps_kcut, spec->p1d.dpix, 0};
   lya_ps_table tab{nk, d_edges, d_ratio};
   const double dpix = spec->p1d.dpix;
 
@@ -407,6 +408,90 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
           ++ne;
         }
       return ne ? sqrt(se / ne) : NAN;
+    };
+
+    // ---- the paper's iteration: P_s = psA exp(-(k/psK)^2) r(bin of k), r
+    // multiplied per k bin by P_target / P1D, n_it iterations per outer step
+    // from (a, s); outer steps after the first re-solve (a, s) for Fbar and
+    // the target effective bias at the sigma_g of the current ratios
+    auto run_plain = [&](double psA, double psK, double a, double s, int n_out, int n_it, bool outer_fit) -> int {
+      std::vector<double> ratio(nk, 1.0);
+      std::vector<float> ratio32(nk);
+      std::vector<double> psum(nk);
+      std::vector<int64_t> pcnt(nk);
+      const lya_ps1d psl{psA, psK, dpix, 0};
+      double fbar = 0.0, b_used = 0.0;
+      int done = 0;
+      for (int o = 0; o < n_out; ++o) {
+        if (o > 0 && outer_fit) {
+          const double ss2 = sigma_s2(psA, psK, ratio.data(), ek.data(), nk, dpix);
+          const double sg2 = sig0 + ss2;
+          double a2 = a, s2 = s;
+          if (!(sg2 > 0.0) || !fit_a_s_bias(ft, beff_box, sqrt(sg2), beta, &a2, &s2)) break;
+          a = a2;
+          s = s2;
+        }
+        for (int it = 0; it < n_it; ++it) {
+          const double ss2 = sigma_s2(psA, psK, ratio.data(), ek.data(), nk, dpix);
+          const double sg2 = sig0 + ss2;
+          if (!(sg2 > 0.0)) return pfail(LYA_EINVAL, "sigma_g^2 is not positive");
+          b_used = s / sqrt(sg2);
+          for (int b = 0; b < nk; ++b) ratio32[b] = static_cast<float>(ratio[b]);
+          if ((e = hipMemcpyAsync(d_ratio, ratio32.data(), sizeof(float) * nk, hipMemcpyHostToDevice, st)) !=
+                  hipSuccess ||
+              (e = hipMemcpyAsync(d_edges, ek.data(), sizeof(double) * (nk + 1), hipMemcpyHostToDevice, st)) !=
+                  hipSuccess ||
+              (e = hipMemcpyAsync(d_zb, zb_edges, sizeof(zb_edges), hipMemcpyHostToDevice, st)) != hipSuccess)
+            return phip(e, "table upload");
+          lya_fgpa fg{};
+          fg.coef[0][0] = a;
+          fg.coef[1][0] = b_used;
+          fg.coef[2][0] = ct;
+          int rc = lya_apply_fgpa_ds(sk, &spec->cosmo, spec->dens_l, spec->eta, &psl, &tab, spec->seed, &fg, flux,
+                                     &zb, w + c.sk, c.p1d - c.sk, stream);
+          if (rc != LYA_OK) {
+            snprintf(g_perr, sizeof(g_perr), "lya_apply_fgpa_ds: %s", lya_last_error());
+            return rc;
+          }
+          lya_p1d_spec pspec = spec->p1d;
+          pspec.z_ref = zt;
+          rc = lya_p1d(sk, &spec->cosmo, flux, &zb, &pspec, d_psum, d_pcnt, w + c.p1d, c.flux - c.p1d, stream);
+          if (rc != LYA_OK) {
+            snprintf(g_perr, sizeof(g_perr), "lya_p1d: %s", lya_last_error());
+            return rc;
+          }
+          double zsum[2];
+          if ((e = hipMemcpyAsync(zsum, d_zb + 2, sizeof(zsum), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+              (e = hipMemcpyAsync(psum.data(), d_psum, sizeof(double) * nk, hipMemcpyDeviceToHost, st)) !=
+                  hipSuccess ||
+              (e = hipMemcpyAsync(pcnt.data(), d_pcnt, sizeof(int64_t) * nk, hipMemcpyDeviceToHost, st)) !=
+                  hipSuccess ||
+              (e = hipStreamSynchronize(st)) != hipSuccess)
+            return phip(e, "statistics read-back");
+          ++res->gpu_evals[z];
+          int64_t count;
+          memcpy(&count, &zsum[1], sizeof(count));
+          fbar = count > 0 ? zsum[0] / static_cast<double>(count) : NAN;
+          for (int b = 0; b < nk; ++b) {
+            res->p1d[z * 64 + b] = pcnt[b] > 0 ? psum[b] / static_cast<double>(pcnt[b]) : NAN;
+            res->ratio[z * 64 + b] = ratio[b];
+          }
+          res->fbar[z * LYA_TUNE_PS_MAX_ITER + it] = fbar;
+          res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = rel_rms(res->p1d + z * 64);
+          // P_s^{n+1} = P_s^n P_target / P1D in every bin with both values
+          for (int b = 0; b < nk; ++b) {
+            const double p = res->p1d[z * 64 + b];
+            if (isfinite(pt[b]) && isfinite(p) && p > 0.0) ratio[b] *= pt[b] / p;
+          }
+        }
+        res->beff[z * LYA_TUNE_PS_MAX_OUTER + o] = effective_bias(a, s, s / b_used, beta, nullptr);
+        done = o + 1;
+      }
+      res->n_outer_done[z] = done;
+      res->a[z] = a;
+      res->b[z] = b_used;
+      res->s[z] = s;
+      return LYA_OK;
     };
 
     // ---- emulator mode: (amp, kcut) of P_s by a corrected emulator search
@@ -507,6 +592,9 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
         res->rms[z * LYA_TUNE_PS_MAX_ITER] = rel_rms(rows + 1);
         res->beff[z * LYA_TUNE_PS_MAX_OUTER] = effective_bias(a, s, sg, beta, nullptr);
         res->n_outer_done[z] = 1;
+        // the paper's per-bin update on top of the fitted form, at the fit's (a, s)
+        if (spec->emu_refine > 0)
+          if (int rc = run_plain(amp, kc, a, s, 1, spec->emu_refine, false)) return rc;
         continue;
       }
       // not settled within emu_checks GPU evaluations (or no (a, s) for the
@@ -515,84 +603,7 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
       plain = true;
     }
     if (!plain) continue;
-
-    // ---- the paper's iteration: P_s multiplied per k bin by P_target / P1D
-    std::vector<double> ratio(nk, 1.0);
-    std::vector<float> ratio32(nk);
-    std::vector<double> psum(nk);
-    std::vector<int64_t> pcnt(nk);
-    double fbar = 0.0, b_used = 0.0, a = a0, s = s0;
-    int done = 0;
-    for (int o = 0; o < n_outer; ++o) {
-      if (o > 0) {
-        // re-solve (a, s) for Fbar and the target effective bias at the
-        // sigma_g of the current ratios
-        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, dpix);
-        const double sg2 = sig0 + ss2;
-        double a2 = a, s2 = s;
-        if (!(sg2 > 0.0) || !fit_a_s_bias(ft, beff_box, sqrt(sg2), beta, &a2, &s2)) break;
-        a = a2;
-        s = s2;
-      }
-      for (int it = 0; it < spec->n_iter; ++it) {
-        const double ss2 = sigma_s2(spec->ps_amp, spec->ps_kcut, ratio.data(), ek.data(), nk, dpix);
-        const double sg2 = sig0 + ss2;
-        if (!(sg2 > 0.0)) return pfail(LYA_EINVAL, "sigma_g^2 is not positive");
-        b_used = s / sqrt(sg2);
-        for (int b = 0; b < nk; ++b) ratio32[b] = static_cast<float>(ratio[b]);
-        if ((e = hipMemcpyAsync(d_ratio, ratio32.data(), sizeof(float) * nk, hipMemcpyHostToDevice, st)) !=
-                hipSuccess ||
-            (e = hipMemcpyAsync(d_edges, ek.data(), sizeof(double) * (nk + 1), hipMemcpyHostToDevice, st)) !=
-                hipSuccess ||
-            (e = hipMemcpyAsync(d_zb, zb_edges, sizeof(zb_edges), hipMemcpyHostToDevice, st)) != hipSuccess)
-          return phip(e, "table upload");
-        lya_fgpa fg{};
-        fg.coef[0][0] = a;
-        fg.coef[1][0] = b_used;
-        fg.coef[2][0] = ct;
-        int rc = lya_apply_fgpa_ds(sk, &spec->cosmo, spec->dens_l, spec->eta, &ps, &tab, spec->seed, &fg, flux, &zb,
-                                   w + c.sk, c.p1d - c.sk, stream);
-        if (rc != LYA_OK) {
-          snprintf(g_perr, sizeof(g_perr), "lya_apply_fgpa_ds: %s", lya_last_error());
-          return rc;
-        }
-        lya_p1d_spec pspec = spec->p1d;
-        pspec.z_ref = zt;
-        rc = lya_p1d(sk, &spec->cosmo, flux, &zb, &pspec, d_psum, d_pcnt, w + c.p1d, c.flux - c.p1d, stream);
-        if (rc != LYA_OK) {
-          snprintf(g_perr, sizeof(g_perr), "lya_p1d: %s", lya_last_error());
-          return rc;
-        }
-        double zsum[2];
-        if ((e = hipMemcpyAsync(zsum, d_zb + 2, sizeof(zsum), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(psum.data(), d_psum, sizeof(double) * nk, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(pcnt.data(), d_pcnt, sizeof(int64_t) * nk, hipMemcpyDeviceToHost, st)) !=
-                hipSuccess ||
-            (e = hipStreamSynchronize(st)) != hipSuccess)
-          return phip(e, "statistics read-back");
-        ++res->gpu_evals[z];
-        int64_t count;
-        memcpy(&count, &zsum[1], sizeof(count));
-        fbar = count > 0 ? zsum[0] / static_cast<double>(count) : NAN;
-        for (int b = 0; b < nk; ++b) {
-          res->p1d[z * 64 + b] = pcnt[b] > 0 ? psum[b] / static_cast<double>(pcnt[b]) : NAN;
-          res->ratio[z * 64 + b] = ratio[b];
-        }
-        res->fbar[z * LYA_TUNE_PS_MAX_ITER + it] = fbar;
-        res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = rel_rms(res->p1d + z * 64);
-        // P_s^{n+1} = P_s^n P_target / P1D in every bin with both values
-        for (int b = 0; b < nk; ++b) {
-          const double p = res->p1d[z * 64 + b];
-          if (isfinite(pt[b]) && isfinite(p) && p > 0.0) ratio[b] *= pt[b] / p;
-        }
-      }
-      res->beff[z * LYA_TUNE_PS_MAX_OUTER + o] = effective_bias(a, s, s / b_used, beta, nullptr);
-      done = o + 1;
-    }
-    res->n_outer_done[z] = done;
-    res->a[z] = a;
-    res->b[z] = b_used;
-    res->s[z] = s;
+    if (int rc = run_plain(spec->ps_amp, spec->ps_kcut, a0, s0, n_outer, spec->n_iter, true)) return rc;
   }
   res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return LYA_OK;

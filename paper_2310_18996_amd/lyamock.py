@@ -337,7 +337,8 @@ class TunePsSpec(ctypes.Structure):
                 ("p1d_t", ctypes.c_void_p), ("p1d", P1dSpec), ("ps_amp", ctypes.c_double),
                 ("ps_kcut", ctypes.c_double), ("n_iter", ctypes.c_int32), ("n_outer", ctypes.c_int32),
                 ("beff_t", ctypes.c_double * TUNE_MAX_Z), ("f", ctypes.c_double), ("beff_at_z", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("emu", ctypes.c_void_p * TUNE_MAX_Z), ("emu_checks", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("emu", ctypes.c_void_p * TUNE_MAX_Z), ("emu_checks", ctypes.c_int32),
+                ("emu_refine", ctypes.c_int32)]
 
 
 class TunePsResult(ctypes.Structure):

@@ -232,6 +232,53 @@ def test_emulator_mode_hands_over_to_the_plain_iteration(L, fam):
     np.testing.assert_array_equal(np.array(re_.fbar[:4]), np.array(rp.fbar[:4]))
 
 
+def test_emulator_mode_refinement_matches_the_oracle(L, fam, emu):
+    # three per-bin iterations after the fit: the oracle's iteration started
+    # from the fitted form (its (a, s) come from the same mean flux and
+    # dispersion targets) gives the same statistics
+    sp = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu, checks=8)
+    sp.spec.emu_refine = 3
+    res = L.tune_ps(sp.spec, sp.work)
+    plain_fit = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu, checks=8)
+    r0 = L.tune_ps(plain_fit.spec, plain_fit.work)
+    assert res.fallback[0] == 0 and res.gpu_evals[0] == r0.gpu_evals[0] + 3
+    assert (res.ps_fit[0], res.ps_fit[1]) == (r0.ps_fit[0], r0.ps_fit[1])
+    nk = len(fam["k_edges"]) - 1
+    ref = tune_ps.iterate(fam["dl"], fam["eta"], fam["sk"], fam["seed"], fam["z_t"], fam["c_t"], fam["fbar_t"],
+                          fam["pk_t"], fam["k_edges"], fam["dpix"], res.ps_fit[0], res.ps_fit[1], n_iter=3,
+                          sigf_t=fam["sigf_t"])
+    np.testing.assert_allclose([res.fbar[i] for i in range(3)], [h["fbar"] for h in ref["hist"]], rtol=TOL)
+    last = ref["hist"][-1]
+    ok = np.isfinite(last["p1d"])
+    gp = np.array(res.p1d[:nk])
+    print("refinement: P1D rel rms vs oracle %.2e; ratios %s" % (rel_rms(gp[ok], last["p1d"][ok]),
+                                                                 np.round(np.array(res.ratio[:4]), 6)), flush=True)
+    assert rel_rms(gp[ok], last["p1d"][ok]) < TOL
+    np.testing.assert_allclose(np.array(res.ratio[:nk]), last["ratio"], rtol=1e-5)
+    np.testing.assert_allclose(res.b[0], last["b"], rtol=1e-6)
+
+
+def test_emulator_mode_at_two_redshifts(L, fam, emu):
+    # two z_t with the same targets and emulator: each row is the
+    # one-redshift result
+    nk = len(fam["k_edges"]) - 1
+    one = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu, checks=8)
+    r1 = L.tune_ps(one.spec, one.work)
+    two = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu, checks=8)
+    sp = two.spec
+    sp.n_zt = 2
+    sp.z_t[1], sp.c_t[1], sp.fbar_t[1], sp.sigf_t[1] = sp.z_t[0], sp.c_t[0], sp.fbar_t[0], sp.sigf_t[0]
+    pk2 = np.ascontiguousarray(np.concatenate([fam["pk_t"], fam["pk_t"]]))
+    sp.p1d_t = pk2.ctypes.data
+    sp.emu[1] = emu.data_ptr()
+    r2 = L.tune_ps(sp, two.work)
+    for z in (0, 1):
+        assert r2.fallback[z] == 0 and r2.gpu_evals[z] == r1.gpu_evals[0]
+        assert (r2.a[z], r2.b[z], r2.ps_fit[2 * z], r2.ps_fit[2 * z + 1]) == (r1.a[0], r1.b[0], r1.ps_fit[0],
+                                                                            r1.ps_fit[1])
+        np.testing.assert_array_equal(np.array(r2.p1d[64 * z:64 * z + nk]), np.array(r1.p1d[:nk]))
+
+
 def test_emulator_mode_rejects_bad_input(L, fam, emu):
     import torch
     sp = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=None)
@@ -240,6 +287,10 @@ def test_emulator_mode_rejects_bad_input(L, fam, emu):
     sp = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu, checks=0)
     with pytest.raises(L.LyaError):
         L.tune_ps(sp.spec, sp.work)                     # no GPU check allowed
+    sp = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu)
+    sp.spec.emu_refine = 17
+    with pytest.raises(L.LyaError):
+        L.tune_ps(sp.spec, sp.work)                     # refinement beyond 16 iterations
     sp = Spec(L, fam, 7, emu=emu)
     with pytest.raises(L.LyaError):
         L.tune_ps(sp.spec, sp.work)                     # unknown mode
