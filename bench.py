@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 # kernel; valid only for the kernels as they were when the counters were taken
 # (a changed kernel must drop its entry) and reported only for that workload.
 TRAFFIC = {("fft_x", 9): 137490967113, ("fft_y", 8): 140316083069, ("fft_z_gen", None): 86264066663,
-           ("fft_z_gen", "2buf"): 86232205602, ("fft_x2", None): 137715612383, ("fft_y2", None): 154246313062,
-           ("skewers", (4, 4, 1)): 14516776205, ("qso_draw", None): 137560151198}
+           ("fft_z_gen", "2buf"): 86235288356, ("fft_x2", None): 137736433140, ("fft_y2", None): 138597946620,
+           ("skewers", (4, 4, 1)): 14517634220, ("qso_draw", None): 137560151198}
 TRAFFIC_CONFIG = "big"
 
 
