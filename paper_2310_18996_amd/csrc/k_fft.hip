@@ -431,7 +431,13 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
   int outer, t0;
   bool paired = false;
   if (KIND == KIND_GENZ) {
-    if (tile < P::kPairedTiles) {
+    if (P::H == 1 && tile < P::kPairedTiles && g.order) {
+      // in bands of nx^2 + ny^2 (k_zo_band_write)
+      paired = true;
+      const uint32_t o = g.order[tile];
+      outer = static_cast<int>(o >> 16);
+      t0 = static_cast<int>(o & 0xffffu);
+    } else if (tile < P::kPairedTiles) {
       paired = true;
       outer = 1 + tile / (N / P::H);
       // iy blocks in mirrored pairs: blocks j and N/H - j follow each other,
@@ -609,6 +615,146 @@ hipError_t launch_strided(int variant, float2* field, uint32_t* bf16, const floa
   return launch_strided_tile<N, S::TS, S::ES, KIND, 0, false>(field, bf16, tw, g, st);
 }
 
+// Tile order of the synthesising pass (boxes from kZOrderMinN up, where a
+// paired tile is one pencil and its partner).  Pencil (nx, ny) reads the
+// amplitude-table entries nx^2 + ny^2 + nz^2 for every nz: pencils with close
+// key nx^2 + ny^2 read the same cache lines of the table (whose entries are
+// spaced 2|nz| + 1 apart, one line each for most nz).  The paired tiles are
+// visited band by band of kZoBand consecutive keys, so that the tiles in
+// flight on one XCD span a few hundred keys and share their table lines in
+// its L2.  Within a band the order is ix, then |ny|, then +ny before -ny (a
+// pencil and its mirror, which read the same entries, back to back).  Built
+// on every call without atomics, so the order is deterministic: the tiles of
+// each band counted per band (closed form per ix), the band counts scanned,
+// then each band's tiles written from the scan of its per-ix counts.
+constexpr int kZoBand = 128;
+constexpr int kZoNT = 256;
+
+// floor(sqrt(x)) for 0 <= x < 2^24
+__device__ __forceinline__ int zo_isqrt(int x) {
+  int r = static_cast<int>(sqrtf(static_cast<float>(x)));
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
+// |ny| range [m0, m1] of the pencils (ix, ny) with key in [lo, lo + kZoBand)
+__device__ __forceinline__ void zo_range(int ix, int lo, int n, int& m0, int& m1) {
+  const int a = lo - ix * ix, b = a + kZoBand;
+  m0 = a <= 0 ? 0 : zo_isqrt(a - 1) + 1;
+  m1 = b <= 0 ? -1 : zo_isqrt(b - 1);
+  if (m1 > n / 2) m1 = n / 2;
+}
+
+// tiles of (ix, +-m), m in [m0, m1]: +m exists up to n/2 - 1, -m from 1 to n/2
+__device__ __forceinline__ int zo_count(int m0, int m1, int n) {
+  if (m1 < m0) return 0;
+  const int hp = m1 < n / 2 - 1 ? m1 : n / 2 - 1, lm = m0 > 1 ? m0 : 1;
+  return (hp >= m0 ? hp - m0 + 1 : 0) + (m1 >= lm ? m1 - lm + 1 : 0);
+}
+
+template <int N>
+__device__ __forceinline__ int zo_band_tiles(int band, int (&cnt)[(N / 2 + kZoNT - 1) / kZoNT]) {
+  constexpr int PER = (N / 2 + kZoNT - 1) / kZoNT;
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int ix = 1 + static_cast<int>(threadIdx.x) * PER + k;
+    int m0 = 0, m1 = -1;
+    if (ix < N / 2) zo_range(ix, band * kZoBand, N, m0, m1);
+    cnt[k] = zo_count(m0, m1, N);
+    tot += cnt[k];
+  }
+  return tot;
+}
+
+// block-wide exclusive scan of one value per thread (kZoNT threads)
+__device__ __forceinline__ int zo_exclusive(int v, int* s, int& total) {
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 1; d < kZoNT; d <<= 1) {
+    const int a = static_cast<int>(threadIdx.x) >= d ? s[threadIdx.x - d] : 0;
+    __syncthreads();
+    s[threadIdx.x] += a;
+    __syncthreads();
+  }
+  total = s[kZoNT - 1];
+  return s[threadIdx.x] - v;
+}
+
+// tiles per band (a block per band)
+template <int N>
+__global__ void __launch_bounds__(kZoNT) k_zo_band_count(int* __restrict__ bcount) {
+  __shared__ int s[kZoNT];
+  int cnt[(N / 2 + kZoNT - 1) / kZoNT];
+  int total;
+  zo_exclusive(zo_band_tiles<N>(blockIdx.x, cnt), s, total);
+  if (threadIdx.x == 0) bcount[blockIdx.x] = total;
+}
+
+// exclusive scan of the band counts in place (one block, each thread a run)
+__global__ void __launch_bounds__(kZoNT) k_zo_band_scan(int* __restrict__ bcount, int nbands) {
+  __shared__ int s[kZoNT];
+  const int per = (nbands + kZoNT - 1) / kZoNT, c0 = static_cast<int>(threadIdx.x) * per;
+  int tot = 0;
+  for (int k = 0; k < per && c0 + k < nbands; ++k) tot += bcount[c0 + k];
+  int total;
+  int run = zo_exclusive(tot, s, total);
+  for (int k = 0; k < per && c0 + k < nbands; ++k) {
+    const int c = bcount[c0 + k];
+    bcount[c0 + k] = run;
+    run += c;
+  }
+}
+
+// order[position] = (ix << 16) | iy for the tiles of each band (a block per band)
+template <int N>
+__global__ void __launch_bounds__(kZoNT) k_zo_band_write(const int* __restrict__ boff, uint32_t* __restrict__ order) {
+  constexpr int PER = (N / 2 + kZoNT - 1) / kZoNT;
+  __shared__ int s[kZoNT];
+  int cnt[PER];
+  int total;
+  int pos = boff[blockIdx.x] + zo_exclusive(zo_band_tiles<N>(blockIdx.x, cnt), s, total);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (cnt[k] == 0) continue;
+    const int ix = 1 + static_cast<int>(threadIdx.x) * PER + k;
+    int m0, m1;
+    zo_range(ix, blockIdx.x * kZoBand, N, m0, m1);
+    for (int m = m0; m <= m1; ++m) {
+      if (m <= N / 2 - 1) order[pos++] = (static_cast<uint32_t>(ix) << 16) | static_cast<uint32_t>(m);
+      if (m >= 1) order[pos++] = (static_cast<uint32_t>(ix) << 16) | static_cast<uint32_t>(N - m);
+    }
+  }
+}
+
+struct ZOrderSizes {
+  int ntiles, nbands;
+  size_t words;  // order + band counts
+};
+
+template <int N>
+constexpr ZOrderSizes zorder_sizes() {
+  static_assert(Shape<N>::TZ == 2, "one pencil and its partner per paired tile");
+  constexpr int ntiles = (N / 2 - 1) * N;
+  constexpr int nkeys = (N / 2 - 1) * (N / 2 - 1) + (N / 2) * (N / 2) + 1;
+  constexpr int nbands = (nkeys + kZoBand - 1) / kZoBand;
+  return ZOrderSizes{ntiles, nbands, static_cast<size_t>(ntiles) + nbands};
+}
+
+template <int N>
+hipError_t launch_zorder(uint32_t* work, hipStream_t st) {
+  constexpr ZOrderSizes z = zorder_sizes<N>();
+  uint32_t* order = work;
+  int* bcount = reinterpret_cast<int*>(work + z.ntiles);
+  LYA_TIMED("zorder", st, {
+    hipLaunchKernelGGL(k_zo_band_count<N>, dim3(z.nbands), dim3(kZoNT), 0, st, bcount);
+    hipLaunchKernelGGL(k_zo_band_scan, dim3(1), dim3(kZoNT), 0, st, bcount, z.nbands);
+    hipLaunchKernelGGL(k_zo_band_write<N>, dim3(z.nbands), dim3(kZoNT), 0, st, bcount, order);
+  });
+  return hipGetLastError();
+}
+
 template <int N, bool SWZ>
 hipError_t launch_zgen(const GenParams& g, int gm, const float2* tw, float2* out, hipStream_t st) {
   using S = Shape<N>;
@@ -670,13 +816,20 @@ hipError_t launch_two_buffer(GenParams g, const float2* tw, float2* second, floa
 }
 
 template <int N>
-hipError_t run_box_fft(const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16, float2* second,
-                       hipStream_t st) {
+hipError_t run_box_fft(GenParams g, const float2* tw, float2* field, uint32_t* field_bf16, float2* second,
+                       uint32_t* zorder, hipStream_t st) {
   const bool hooks = g.fixed_amp || g.only_n2 >= 0 || g.table_b;
   const int gm = (!hooks && g.comp_a == 0 && g.comp_b == 3)    ? GEN_DELTA_ETAZ
                  : (!hooks && g.comp_a == 0 && g.comp_b == -1) ? GEN_DELTA
                                                                : GEN_GENERIC;
   hipError_t e;
+  g.order = nullptr;
+  if constexpr (N >= kZOrderMinN) {
+    if (zorder) {
+      if ((e = launch_zorder<N>(zorder, st)) != hipSuccess) return e;
+      g.order = zorder;
+    }
+  }
   if (second) {
     if ((e = launch_zgen<N, true>(g, gm, tw, second, st)) != hipSuccess) return e;
     return launch_two_buffer<N>(g, tw, second, field, field_bf16, st);
@@ -702,17 +855,19 @@ hipError_t launch_fft_strided_pass(int n, int pass, int variant, const float2* t
 }
 
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
-                          float2* second, hipStream_t st) {
+                          float2* second, uint32_t* zorder, hipStream_t st) {
   switch (n) {
-    case 32: return run_box_fft<32>(g, tw, field, field_bf16, second, st);
-    case 64: return run_box_fft<64>(g, tw, field, field_bf16, second, st);
-    case 128: return run_box_fft<128>(g, tw, field, field_bf16, second, st);
-    case 256: return run_box_fft<256>(g, tw, field, field_bf16, second, st);
-    case 512: return run_box_fft<512>(g, tw, field, field_bf16, second, st);
-    case 1024: return run_box_fft<1024>(g, tw, field, field_bf16, second, st);
-    case 2048: return run_box_fft<2048>(g, tw, field, field_bf16, second, st);
+    case 32: return run_box_fft<32>(g, tw, field, field_bf16, second, zorder, st);
+    case 64: return run_box_fft<64>(g, tw, field, field_bf16, second, zorder, st);
+    case 128: return run_box_fft<128>(g, tw, field, field_bf16, second, zorder, st);
+    case 256: return run_box_fft<256>(g, tw, field, field_bf16, second, zorder, st);
+    case 512: return run_box_fft<512>(g, tw, field, field_bf16, second, zorder, st);
+    case 1024: return run_box_fft<1024>(g, tw, field, field_bf16, second, zorder, st);
+    case 2048: return run_box_fft<2048>(g, tw, field, field_bf16, second, zorder, st);
     default: return hipErrorInvalidValue;
   }
 }
+
+size_t zorder_words(int n) { return n == 2048 ? zorder_sizes<2048>().words : 0; }
 
 }  // namespace lya

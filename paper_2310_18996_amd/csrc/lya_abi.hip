@@ -53,7 +53,7 @@ bool pow2_in_range(int n) { return n >= 32 && n <= 2048 && (n & (n - 1)) == 0; }
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct BoxCarve {
-  size_t partial, amp, tw, table, table_b, staging, second, total;
+  size_t partial, amp, tw, table, table_b, zorder, staging, second, total;
 };
 
 // two_buffer: room for a second complex64 box after the staging box (the
@@ -66,6 +66,7 @@ BoxCarve carve_box(const lya_box* b, bool two_buffer = false) {
   c.tw = o;      o += align256(sizeof(float2) * b->n);
   c.table = o;   o += align256(sizeof(float) * lya::amp_table_entries(b->n));
   c.table_b = o; o += align256(sizeof(float) * lya::amp_table_entries(b->n));
+  c.zorder = o;  o += align256(sizeof(uint32_t) * lya::zorder_words(b->n));
   c.staging = o;
   if (b->storage == LYA_BF16) o += align256(sizeof(float2) * lya::box_elems(b->n));
   c.second = o;
@@ -224,8 +225,9 @@ int make_pair(const lya_box* box, const lya_pk* pk, const lya_pk* pk_b, uint64_t
                    static_cast<float>(vscale)};
   float2* f32 = box->storage == LYA_F32 ? static_cast<float2*>(field) : reinterpret_cast<float2*>(w + c.staging);
   uint32_t* b16 = box->storage == LYA_BF16 ? static_cast<uint32_t*>(field) : nullptr;
+  uint32_t* zorder = lya::zorder_words(box->n) ? reinterpret_cast<uint32_t*>(w + c.zorder) : nullptr;
   e = lya::launch_box_fft(box->n, g, tw.tw, f32, b16, two_buffer ? reinterpret_cast<float2*>(w + c.second) : nullptr,
-                          st);
+                          zorder, st);
   if (e != hipSuccess) return hip_fail(e, "box FFT");
   return LYA_OK;
 }

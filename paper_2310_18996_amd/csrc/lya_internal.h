@@ -57,6 +57,7 @@ struct GenParams {
   int only_n2;
   float vscale;        // velocities: f 100 L / (2 pi), km/s
   float2* dst;         // the transposing pass of the two-buffer order writes here
+  const uint32_t* order;  // paired tiles of the synthesising pass in this order (null: the mirrored order)
 };
 
 // Optional event timing around each launch (see lya_timing_enable).
@@ -82,9 +83,13 @@ hipError_t launch_xi_weights(const PkParams& p, double s, double h, int m, doubl
                              double* f, hipStream_t st);
 hipError_t launch_twiddles(float2* tw, int ntw, hipStream_t st);
 // second: a complex64 box buffer of the same size (workspace) for the
-// two-buffer order, or null for the in-place order.
+// two-buffer order, or null for the in-place order.  zorder: zorder_words(n)
+// words of workspace for the synthesising pass's tile order (boxes from
+// kZOrderMinN up; null or below: the mirrored order).
+constexpr int kZOrderMinN = 2048;
+size_t zorder_words(int n);
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
-                          float2* second, hipStream_t st);
+                          float2* second, uint32_t* zorder, hipStream_t st);
 // Strided-pass variants (0..kFftVariants-1) per box size and pass (0 = y, 1 = x).
 constexpr int kFftVariants = 14;
 int fft_variant(int n, int pass);
