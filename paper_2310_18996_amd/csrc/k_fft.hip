@@ -189,6 +189,17 @@ struct Pass {
     if (KIND == KIND_YT) return static_cast<size_t>(i) * kPitch + static_cast<size_t>(outer) * N + t0 + p;
     return gidx(outer, t0, i, p, paired);
   }
+  // The same addresses split as base + offset, so that an access costs one
+  // add: the y passes read (and KIND_Y writes) within plane outer, offset
+  // i N + p in 32 bits from a block-uniform base; a synthesised pencil is
+  // contiguous, offset i from its start; KIND_YT writes at i kPitch + p from
+  // the block-uniform row (outer, t0).
+  __device__ static __forceinline__ size_t base_in(int outer, int t0) {
+    return static_cast<size_t>(outer) * kPitch + t0;
+  }
+  __device__ static __forceinline__ uint32_t off_in(int i, int p) {
+    return static_cast<uint32_t>(i) * N + static_cast<uint32_t>(p);
+  }
   // LDS layout with one padding slot per R0 elements along the FFT axis (R0 =
   // first radix): the first stage scatters its outputs with stride R0, which
   // without padding lands every lane group on the same banks.
@@ -229,12 +240,24 @@ struct Pass {
   __device__ static __forceinline__ void load_global0(float2 (&v)[E], const float2* __restrict__ data, int outer,
                                                       int t0, int tid) {
     constexpr int R = radix_of(N, 0), B = E / R;
+    if constexpr (KIND == KIND_Y || KIND == KIND_YT) {
+      const float2* __restrict__ plane = data + base_in(outer, t0);
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      int p, j;
-      coords<R>(tid + b * NT, p, j);
+      for (int b = 0; b < B; ++b) {
+        int p, j;
+        coords<R>(tid + b * NT, p, j);
+        const uint32_t o = off_in(j, p);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b * R + r] = data[gidx(outer, t0, j + r * (N / R), p)];
+        for (int r = 0; r < R; ++r) v[b * R + r] = plane[o + static_cast<uint32_t>(r * (N / R) * N)];
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        int p, j;
+        coords<R>(tid + b * NT, p, j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b * R + r] = data[gidx(outer, t0, j + r * (N / R), p)];
+      }
     }
   }
 
@@ -294,9 +317,27 @@ struct Pass {
     for (int b = 0; b < B; ++b) {
       int p, j;
       coords<R>(tid + b * NT, p, j);
+      // base + offset of element j + r N/R (see base_in)
+      size_t base;
+      if constexpr (KIND == KIND_Y) {
+        base = base_in(outer, t0) + off_in(j, p);
+      } else if constexpr (KIND == KIND_YT) {
+        base = static_cast<size_t>(outer) * N + t0 + static_cast<size_t>(j) * kPitch + p;
+      } else if constexpr (KIND == KIND_GENZ) {
+        base = gidx(outer, t0, j, p, paired);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const size_t gi = gidx_out(outer, t0, j + r * (N / R), p, paired);
+        size_t gi;
+        if constexpr (KIND == KIND_Y) {
+          gi = base + static_cast<uint32_t>(r * (N / R) * N);
+        } else if constexpr (KIND == KIND_YT) {
+          gi = base + static_cast<size_t>(r * (N / R)) * kPitch;
+        } else if constexpr (KIND == KIND_GENZ) {
+          gi = base + static_cast<uint32_t>(r * (N / R));
+        } else {
+          gi = gidx_out(outer, t0, j + r * (N / R), p, paired);
+        }
         // a single requested component: the other half is exactly zero, not FFT rounding residue
         const float2 o = make_float2(v[b * R + r].x, zero_b ? 0.0f : v[b * R + r].y);
         if (out_bf16) {
