@@ -261,6 +261,23 @@ struct Pass {
     }
   }
 
+  // stages 0.. of the tile held in v, the results left in v for store_global<NSTAGE - 1>
+  __device__ static __forceinline__ void transform(float2 (&v)[E], float2* lds, const float2* __restrict__ tw,
+                                                   int tid) {
+    butterflies<0>(v, tw, tid);
+    store_lds<0>(v, lds, tid);
+    __syncthreads();
+    load_lds<1>(v, lds, tid);
+    butterflies<1>(v, tw, tid);
+    if constexpr (NSTAGE == 3) {
+      __syncthreads();
+      store_lds<1>(v, lds, tid);
+      __syncthreads();
+      load_lds<2>(v, lds, tid);
+      butterflies<2>(v, tw, tid);
+    }
+  }
+
   // stages 0.. of the tile held in v, ending with the natural-order global store
   __device__ static __forceinline__ void transform_store(float2 (&v)[E], float2* lds, float2* data,
                                                          uint32_t* out_bf16, const float2* __restrict__ tw,
@@ -527,8 +544,13 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
 // block stays on one XCD's range of tiles) and issues the global loads of its
 // next tile before transforming the current one, so that their latency hides
 // behind the FFT and the stores.  Two register copies of a tile: the waves
-// are allowed the larger register budget of two waves per SIMD.
-template <int N, int T, int E, int KIND, int ORDER, bool LAST = KIND == KIND_X>
+// are allowed the larger register budget of two waves per SIMD.  DEFER keeps
+// a third copy, the transformed tile, and issues its stores in the next
+// iteration after that iteration's loads: a store waits for its address
+// translation, and loads issued behind it wait too, which for stores spread
+// over N planes (the transposing pass) held the next tile's loads back
+// (2048^3: 37.0-37.2 ms against 37.9-38.0 ms, bit-identical).
+template <int N, int T, int E, int KIND, int ORDER, bool LAST = KIND == KIND_X, bool DEFER = false>
 __global__ void __launch_bounds__(N * T / E) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const float2* __restrict__ tw, GenParams g) {
   using P = Pass<N, T, E, KIND>;
@@ -540,6 +562,9 @@ k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const flo
   for (int i = threadIdx.x; i < N; i += P::NT) stw[i] = tw[i];
   __syncthreads();
   float2 v[E], nv[E];
+  [[maybe_unused]] float2 ov[DEFER ? E : 1];
+  [[maybe_unused]] int po = 0, pt = 0;
+  [[maybe_unused]] bool have = false;
   int b = blockIdx.x;
   if (b >= ntiles) return;
   int outer, t0;
@@ -558,8 +583,20 @@ k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const flo
       strided_tile<N, T, ORDER>(bn, on, tn);
       P::load_global0(nv, data, on, tn, tid);
     }
-    P::transform_store(v, lds, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr, stw, LAST && g.comp_b < 0,
-                       outer, t0, false, tid);
+    if constexpr (DEFER) {
+      // the previous tile's stores, issued after the next tile's loads
+      if (have) P::template store_global<P::NSTAGE - 1>(ov, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr,
+                                                         LAST && g.comp_b < 0, po, pt, false, tid);
+      P::transform(v, lds, stw, tid);
+#pragma unroll
+      for (int e = 0; e < E; ++e) ov[e] = v[e];
+      po = outer;
+      pt = t0;
+      have = true;
+    } else {
+      P::transform_store(v, lds, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr, stw, LAST && g.comp_b < 0,
+                         outer, t0, false, tid);
+    }
     if (!more) break;
     __syncthreads();  // every thread has read this tile's LDS before the next one is written
 #pragma unroll
@@ -567,6 +604,11 @@ k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const flo
     b = bn;
     outer = on;
     t0 = tn;
+  }
+  if constexpr (DEFER) {
+    int tid = threadIdx.x;
+    P::template store_global<P::NSTAGE - 1>(ov, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr,
+                                            LAST && g.comp_b < 0, po, pt, false, tid);
   }
 }
 
@@ -820,7 +862,7 @@ hipError_t launch_zgen(const GenParams& g, int gm, const float2* tw, float2* out
 // (second -> field, over kx) and the last pass (field in place, over ky);
 // from 1024 up in the pipelined kernel with full tiles and tile order 1, the
 // transposing pass with half the elements per thread (the shape of strided
-// variant 9), the last pass with the full count (at 2048^3: 38.0 + 32.0 ms,
+// variant 9) and deferred stores, the last pass with the full count (at 2048^3: 38.0 + 32.0 ms,
 // against 38.0 + 33.8 ms with half the elements in both, 40.5 ms for the
 // transposing pass with the full count, 39.3 + 34.2 ms in tile order 0 and
 // 53.6 ms for the transposing pass in order 3), below as one tile per block.
@@ -835,8 +877,8 @@ hipError_t launch_two_buffer(GenParams g, const float2* tw, float2* second, floa
     if (blocks > ntiles) blocks = ntiles;
     constexpr int EL = S::ES, ntl = N * T / EL;
     LYA_TIMED("fft_x2", st,
-              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_YT, 1>), dim3(blocks), dim3(nt), 0, st, second, nullptr,
-                                 tw, g));
+              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_YT, 1, false, true>), dim3(blocks), dim3(nt), 0, st,
+                                 second, nullptr, tw, g));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     LYA_TIMED("fft_y2", st,
