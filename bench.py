@@ -704,20 +704,26 @@ def ps_emulator_run(L, torch, spec, tw, emock, n_outer, n_labels, train_steps, s
     spec.emu_checks = 10
     spec.emu_refine = 0
     re_ = L.tune_ps(spec, tw)
-    # the fit followed by five per-bin iterations at its (a, s)
+    # the fit followed by five per-bin iterations at its (a, s), with the
+    # paper's update and with the secant one
     spec.emu_refine = 5
     rr = L.tune_ps(spec, tw)
+    spec.update = L.PS_UPDATE_SECANT
+    rs = L.tune_ps(spec, tw)
+    spec.update = L.PS_UPDATE_PAPER
     spec.emu_refine = 0
     spec.mode, spec.n_iter, spec.n_outer = saved
     M = L.TUNE_PS_MAX_ITER
-    refined = dict(emu_refine=5, seconds=rr.seconds, gpu_evals=[rr.gpu_evals[i] for i in range(nz)],
-                   fallback=[rr.fallback[i] for i in range(nz)],
-                   p1d_rel_rms=[rr.rms[i * M + 4] for i in range(nz)],
-                   fbar=[rr.fbar[i * M + 4] for i in range(nz)],
-                   beff=[rr.beff[i * L.TUNE_PS_MAX_OUTER] for i in range(nz)],
-                   growth=[rr.growth[i] for i in range(nz)])
+
+    def refined_rec(r):
+        return dict(emu_refine=5, seconds=r.seconds, gpu_evals=[r.gpu_evals[i] for i in range(nz)],
+                    fallback=[r.fallback[i] for i in range(nz)],
+                    p1d_rel_rms=[r.rms[i * M + 4] for i in range(nz)],
+                    fbar=[r.fbar[i * M + 4] for i in range(nz)],
+                    beff=[r.beff[i * L.TUNE_PS_MAX_OUTER] for i in range(nz)],
+                    growth=[r.growth[i] for i in range(nz)])
     costs = dict(setup_s=t_setup, labels_s=t_lab, train_s=t_train, labels_per_z=n_labels, train_steps_per_z=train_steps,
-                 train_loss_final=losses, refined=refined)
+                 train_loss_final=losses, refined=refined_rec(rr), refined_secant=refined_rec(rs))
     return re_, costs
 
 
@@ -809,6 +815,16 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
     tw = torch.empty(L.tune_ps_workspace_size(mock["n_sk"], mock["pixels"], nk), dtype=torch.uint8, device="cuda")
     res = L.tune_ps(spec, tw)
     M = L.TUNE_PS_MAX_ITER
+    # the same iteration with the secant per-bin update (not in the paper)
+    spec.update = L.PS_UPDATE_SECANT
+    res_sec = L.tune_ps(spec, tw)
+    spec.update = L.PS_UPDATE_PAPER
+    secant_inner = dict(seconds=res_sec.seconds,
+                        p1d_rel_rms_per_iteration=[[res_sec.rms[i * M + j] for j in range(n_iter)]
+                                                   for i in range(len(z_t))],
+                        p1d_rel_rms_last=[res_sec.rms[i * M + n_iter - 1] for i in range(len(z_t))],
+                        fbar_last=[res_sec.fbar[i * M + n_iter - 1] for i in range(len(z_t))],
+                        b=list(res_sec.b[:len(z_t)]))
     # the emulator mode on the same targets, its emulators trained on the
     # 256^3 emulator mock without delta_S
     ecfg = dict(mockinputs.config("emulator"), ps_amp=0.0)
@@ -816,6 +832,7 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
     re_a, costs_a = ps_emulator_run(L, torch, spec, tw, emock, 0, emu_labels, emu_steps, ecfg["seed"])
     emu_inner = ps_emulator_record(L, re_a, res, len(z_t), n_iter, costs_a)
     emu_inner["refined"]["speedup"] = res.seconds / emu_inner["refined"]["seconds"]
+    emu_inner["refined_secant"]["speedup"] = res.seconds / emu_inner["refined_secant"]["seconds"]
     print("bench: tune_ps emulator mode (inner) %.3f s against plain %.3f s" % (re_a.seconds, res.seconds),
           file=sys.stderr, flush=True)
     # the outer loop (five steps) against the paper's own targets: Fbar(z) of
@@ -870,6 +887,9 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
     spec.p1d_t = pk_p.ctypes.data
     spec.n_outer = 5
     res5 = L.tune_ps(spec, tw)
+    spec.update = L.PS_UPDATE_SECANT
+    res5s = L.tune_ps(spec, tw)
+    spec.update = L.PS_UPDATE_PAPER
     re_b, costs_b = ps_emulator_run(L, torch, spec, tw, emock, 5, emu_labels, emu_steps, ecfg["seed"] + 100)
     del emock
     emu_outer = ps_emulator_record(L, re_b, res5, len(z_t), n_iter, costs_b)
@@ -878,6 +898,9 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
     rf = emu_outer["refined"]
     rf["beff_over_target"] = [rf["beff"][i] / (beff_p[i] * rf["growth"][i]) for i in range(len(z_t))]
     rf["speedup"] = res5.seconds / rf["seconds"]
+    rs_ = emu_outer["refined_secant"]
+    rs_["beff_over_target"] = [rs_["beff"][i] / (beff_p[i] * rs_["growth"][i]) for i in range(len(z_t))]
+    rs_["speedup"] = res5.seconds / rs_["seconds"]
     print("bench: tune_ps emulator mode (outer) %.3f s against plain %.3f s" % (re_b.seconds, res5.seconds),
           file=sys.stderr, flush=True)
     steps = [res5.n_outer_done[i] for i in range(len(z_t))]
@@ -892,7 +915,12 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
                  stopped_unreachable=[bool(steps[i] < 5) for i in range(len(z_t))],
                  a=list(res5.a[:len(z_t)]), b=list(res5.b[:len(z_t)]),
                  fbar_last=[res5.fbar[i * M + n_iter - 1] for i in range(len(z_t))],
-                 p1d_rel_rms_last=[res5.rms[i * M + n_iter - 1] for i in range(len(z_t))], emulator=emu_outer)
+                 p1d_rel_rms_last=[res5.rms[i * M + n_iter - 1] for i in range(len(z_t))], emulator=emu_outer,
+                 secant=dict(seconds=res5s.seconds, steps=[res5s.n_outer_done[i] for i in range(len(z_t))],
+                             beff_over_target=[res5s.beff[i * MO + res5s.n_outer_done[i] - 1] /
+                                               (beff_p[i] * res5s.growth[i]) for i in range(len(z_t))],
+                             fbar_last=[res5s.fbar[i * M + n_iter - 1] for i in range(len(z_t))],
+                             p1d_rel_rms_last=[res5s.rms[i * M + n_iter - 1] for i in range(len(z_t))]))
     return dict(workload="P_s iteration, %d iterations at z_t=%s on the 512^3 mock (%d skewers, %d pixels); truth: "
                           "same delta_L and eta_par, delta_S with amplitude 1.6 and cut-off 1.1 h/Mpc (other key), "
                           "P_s start amplitude 1.0, cut-off 1.5" % (n_iter, list(z_t), mock["n_sk"], mock["pixels"]),
@@ -901,7 +929,7 @@ def tune_ps_leg(L, torch, n_iter=10, emu_labels=4000, emu_steps=4000):
                 fbar_last=[res.fbar[i * M + n_iter - 1] for i in range(len(z_t))], fbar_target=list(map(float, fbar_t)),
                 p1d_rel_rms_first=[res.rms[i * M] for i in range(len(z_t))],
                 p1d_rel_rms_last=[res.rms[i * M + n_iter - 1] for i in range(len(z_t))], emulator=emu_inner,
-                outer_loop=outer)
+                secant=secant_inner, outer_loop=outer)
 
 
 def tune_leg(L, torch, n_labels, train_steps):

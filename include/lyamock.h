@@ -405,12 +405,22 @@ int lya_tune_params(const lya_tune_spec* spec, lya_tune_result* res, int mode, v
  * from sigma_g at each iteration); fbar, rms and p1d then describe them,
  * ratio holds the per-bin factors on top of the fitted form, and beff[z][0]
  * the effective bias at the last iteration's sigma_g.
+ * Per-bin update (both modes; update = LYA_PS_UPDATE_SECANT is not in the
+ * paper): the paper's r_{n+1} = r_n P_t/P1D assumes a bin's P1D answers one
+ * to one to its r, while with b sigma_g held it answers less.  The secant
+ * update estimates each bin's response gamma = d ln P1D / d ln r from the
+ * last two iterations of the run and steps r_{n+1} = r_n (P_t/P1D)^w with
+ * w = 1/gamma clipped to [1, 3]; w = 1 at a run's first iteration and
+ * where the secant is undefined (|d ln r| <= 1e-6 or gamma <= 0.05).  Each
+ * outer step, and the refinement after an emulator fit, starts a new run.
  * gpu_evals[z] counts GPU evaluations of the statistics in both modes.
  * Synchronous; GPU work on `stream`; errors in lya_tune_ps_last_error(). */
 #define LYA_TUNE_PS_MAX_ITER 16
 #define LYA_TUNE_PS_MAX_OUTER 8
 #define LYA_TUNE_PS_RATIOS 0
 #define LYA_TUNE_PS_EMULATOR 1
+#define LYA_PS_UPDATE_PAPER 0
+#define LYA_PS_UPDATE_SECANT 1
 typedef struct {
   const lya_skewers* sk;     /* npix, offset, chi0, dchi, id_base used */
   const float* dens_l;       /* device: delta_L per pixel (no delta_S) */
@@ -432,6 +442,7 @@ typedef struct {
   const void* emu[LYA_TUNE_MAX_Z];  /* emulator mode: device emulator per z_t, 1 + n_kbins outputs */
   int32_t emu_checks;        /* emulator mode: GPU evaluations per z_t, 1..16 */
   int32_t emu_refine;        /* emulator mode: per-bin iterations after the fit, 0..16 */
+  int32_t update;            /* per-bin update: LYA_PS_UPDATE_PAPER (0) or LYA_PS_UPDATE_SECANT */
 } lya_tune_ps_spec;
 
 typedef struct {

@@ -15,6 +15,16 @@ Follows section "Adjusting mock parameters": at each tuning redshift z_t,
    P_s^{n+1} = P_s^n P_target / P1D;
 4. ten iterations (the paper's number; an argument here).
 
+A second per-bin update (not in the paper; update="secant"): the paper's
+rule multiplies each bin's P_s by P_t/P1D as if the bin's P1D answered one
+to one, while with b sigma_g fixed it answers less.  From the second
+iteration of a run on, each bin's response gamma = d ln P1D / d ln r is
+estimated from the last two iterations (the secant) and the step becomes
+r <- r (P_t/P1D)^w with w = 1/gamma clipped to [1, 3] (w = 1 where the
+secant is undefined: the ratio moved by 1e-6 or less in log, or gamma
+<= 0.05).  Each outer step starts a new run (no secant across a change of
+(a, s)).
+
 Readings (the paper is silent or states these loosely):
 
 * sigma_F,t comes from the target P1D integrated over its own bins (unless
@@ -194,8 +204,36 @@ def moments(dl, eta):
     return float(np.mean(dl * dl) - ml * ml), float(np.mean(eta * eta) - me * me), float(np.mean(dl * eta) - ml * me)
 
 
+def update_ratio(ratio, pk, pk_t, prev=None, update="paper"):
+    """The per-bin update of step 3 (update="paper") or the secant form
+    above (update="secant"; prev = (ratio, P1D) of the previous iteration of
+    the run, None at its first).  Bins without a finite positive P1D and a
+    finite target keep their ratio."""
+    ratio = np.asarray(ratio, dtype=np.float64)
+    pk = np.asarray(pk, dtype=np.float64)
+    pk_t = np.asarray(pk_t, dtype=np.float64)
+    upd = np.isfinite(pk_t) & np.isfinite(pk) & (pk > 0)
+    w = np.ones_like(ratio)
+    if update == "secant" and prev is not None:
+        r0, p0 = (np.asarray(x, dtype=np.float64) for x in prev)
+        for b in np.flatnonzero(upd):
+            if not (np.isfinite(p0[b]) and p0[b] > 0):
+                continue
+            dr = np.log(ratio[b]) - np.log(r0[b])
+            if abs(dr) <= 1e-6:
+                continue
+            gam = (np.log(pk[b]) - np.log(p0[b])) / dr
+            if gam > 0.05:
+                w[b] = min(max(1.0 / gam, 1.0), 3.0)
+    elif update not in ("paper", "secant"):
+        raise ValueError("update is 'paper' or 'secant'")
+    out = ratio.copy()
+    out[upd] = ratio[upd] * (pk_t[upd] / pk[upd]) ** w[upd]
+    return out
+
+
 def iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, dpix, amp0, kcut0, n_iter=10,
-            omega_m=cosmology.OMEGA_M, sigf_t=None, n_outer=1, beff_t=None, f=1.0):
+            omega_m=cosmology.OMEGA_M, sigf_t=None, n_outer=1, beff_t=None, f=1.0, update="paper"):
     """The procedure above at one z_t.  Returns a, b of the last iteration, the
     ratios it used, and per iteration (Fbar, P1D, sigma_g).  sigf_t, when
     given, is the target flux dispersion itself (a synthetic truth knows it);
@@ -223,17 +261,18 @@ def iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, dpix, amp0, kcut
                 break
             a, s = fit
         hist, ratio = _inner(dl, eta, sk, seed, z_t, c_t, pk_t, k_edges, edges_k, dpix, amp0, kcut0, n_iter,
-                             omega_m, a, s, ratio, sl2, se2, cov, npix, off)
+                             omega_m, a, s, ratio, sl2, se2, cov, npix, off, update)
         beff.append(effective_bias(a, s, hist[-1]["sigma_g"], beta))
     return dict(a=a, s=s, b=hist[-1]["b"], ratio=hist[-1]["ratio"], hist=hist,
                 moments=(sl2, se2, cov), beff=beff)
 
 
 def _inner(dl, eta, sk, seed, z_t, c_t, pk_t, k_edges, edges_k, dpix, amp0, kcut0, n_iter, omega_m, a, s, ratio,
-           sl2, se2, cov, npix, off):
+           sl2, se2, cov, npix, off, update="paper"):
     """n_iter P_s iterations from the given ratios; returns their history and
     the ratios after the last update."""
     hist = []
+    prev = None
     for it in range(n_iter):
         used = ratio.copy()
         ss2 = sigma_s2(amp0, kcut0, used, edges_k, dpix)
@@ -241,9 +280,8 @@ def _inner(dl, eta, sk, seed, z_t, c_t, pk_t, k_edges, edges_k, dpix, amp0, kcut
         b = s / sg
         fbar, pk = _statistics(dl, eta, sk, seed, z_t, c_t, a, b, amp0, kcut0, used, edges_k, k_edges, dpix, omega_m)
         hist.append(dict(fbar=fbar, p1d=pk, sigma_g=float(sg), b=float(b), ratio=used))
-        upd = np.isfinite(pk_t) & np.isfinite(pk) & (pk > 0)
-        ratio = used.copy()
-        ratio[upd] = used[upd] * np.asarray(pk_t)[upd] / pk[upd]
+        ratio = update_ratio(used, pk, pk_t, prev, update)
+        prev = (used, pk)
     return hist, ratio
 
 

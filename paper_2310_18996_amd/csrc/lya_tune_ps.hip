@@ -298,6 +298,9 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
   if (spec->mode != LYA_TUNE_PS_RATIOS && spec->mode != LYA_TUNE_PS_EMULATOR)
     return pfail(LYA_EINVAL, "mode must be LYA_TUNE_PS_RATIOS or LYA_TUNE_PS_EMULATOR");
   const bool emu_mode = spec->mode == LYA_TUNE_PS_EMULATOR;
+  if (spec->update != LYA_PS_UPDATE_PAPER && spec->update != LYA_PS_UPDATE_SECANT)
+    return pfail(LYA_EINVAL, "update must be LYA_PS_UPDATE_PAPER or LYA_PS_UPDATE_SECANT");
+  const bool secant = spec->update == LYA_PS_UPDATE_SECANT;
   if (emu_mode) {
     if (spec->emu_checks < 1 || spec->emu_checks > 16) return pfail(LYA_EINVAL, "emu_checks must be in [1, 16]");
     if (spec->emu_refine < 0 || spec->emu_refine > LYA_TUNE_PS_MAX_ITER)
@@ -422,7 +425,10 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
       const lya_ps1d psl{psA, psK, dpix, 0};
       double fbar = 0.0, b_used = 0.0;
       int done = 0;
+      // the secant update's previous iteration of this run, per bin (NaN: none)
+      std::vector<double> prev_r(nk), prev_p(nk);
       for (int o = 0; o < n_out; ++o) {
+        std::fill(prev_p.begin(), prev_p.end(), NAN);
         if (o > 0 && outer_fit) {
           const double ss2 = sigma_s2(psA, psK, ratio.data(), ek.data(), nk, dpix);
           const double sg2 = sig0 + ss2;
@@ -478,10 +484,26 @@ int lya_tune_ps(const lya_tune_ps_spec* spec, lya_tune_ps_result* res, void* wor
           }
           res->fbar[z * LYA_TUNE_PS_MAX_ITER + it] = fbar;
           res->rms[z * LYA_TUNE_PS_MAX_ITER + it] = rel_rms(res->p1d + z * 64);
-          // P_s^{n+1} = P_s^n P_target / P1D in every bin with both values
+          // P_s^{n+1} = P_s^n (P_target / P1D)^w in every bin with both
+          // values: w = 1 (the paper's rule), or with the secant update w =
+          // 1/gamma clipped to [1, 3], gamma = d ln P1D / d ln r from the last
+          // two iterations of this run (w = 1 where it is undefined)
           for (int b = 0; b < nk; ++b) {
             const double p = res->p1d[z * 64 + b];
-            if (isfinite(pt[b]) && isfinite(p) && p > 0.0) ratio[b] *= pt[b] / p;
+            const double r = ratio[b];
+            if (isfinite(pt[b]) && isfinite(p) && p > 0.0) {
+              double w = 1.0;
+              if (secant && isfinite(prev_p[b]) && prev_p[b] > 0.0) {
+                const double dr = log(r) - log(prev_r[b]);
+                if (fabs(dr) > 1e-6) {
+                  const double gam = (log(p) - log(prev_p[b])) / dr;
+                  if (gam > 0.05) w = fmin(fmax(1.0 / gam, 1.0), 3.0);
+                }
+              }
+              ratio[b] = w == 1.0 ? r * (pt[b] / p) : r * pow(pt[b] / p, w);
+            }
+            prev_r[b] = r;
+            prev_p[b] = p;
           }
         }
         res->beff[z * LYA_TUNE_PS_MAX_OUTER + o] = effective_bias(a, s, s / b_used, beta, nullptr);

@@ -323,6 +323,8 @@ TUNE_PS_MAX_ITER = 16
 TUNE_PS_MAX_OUTER = 8
 TUNE_PS_RATIOS = 0
 TUNE_PS_EMULATOR = 1
+PS_UPDATE_PAPER = 0
+PS_UPDATE_SECANT = 1
 
 
 class PsTable(ctypes.Structure):
@@ -338,7 +340,7 @@ class TunePsSpec(ctypes.Structure):
                 ("ps_kcut", ctypes.c_double), ("n_iter", ctypes.c_int32), ("n_outer", ctypes.c_int32),
                 ("beff_t", ctypes.c_double * TUNE_MAX_Z), ("f", ctypes.c_double), ("beff_at_z", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("emu", ctypes.c_void_p * TUNE_MAX_Z), ("emu_checks", ctypes.c_int32),
-                ("emu_refine", ctypes.c_int32)]
+                ("emu_refine", ctypes.c_int32), ("update", ctypes.c_int32)]
 
 
 class TunePsResult(ctypes.Structure):

@@ -79,8 +79,8 @@ def test_apply_fgpa_ds_matches_oracle(L, mock):
         assert e < TOL
 
 
-@pytest.mark.parametrize("known_sigf", [True, False])
-def test_tune_ps_matches_oracle(L, mock, known_sigf):
+@pytest.mark.parametrize("known_sigf,update", [(True, "paper"), (False, "paper"), (True, "secant")])
+def test_tune_ps_matches_oracle(L, mock, known_sigf, update):
     import torch
     cfg, sk = mock["cfg"], mock["sk"]
     s, keep = skewer_tensors(L, sk)
@@ -102,11 +102,12 @@ def test_tune_ps_matches_oracle(L, mock, known_sigf):
     spec.p1d_t = pk_t.ctypes.data
     spec.p1d = L.P1dSpec(nk, ke.data_ptr(), mock["z_t"], cfg["dpix"])
     spec.ps_amp, spec.ps_kcut, spec.n_iter = 1.0, 1.5, n_iter
+    spec.update = L.PS_UPDATE_SECANT if update == "secant" else L.PS_UPDATE_PAPER
     work = torch.empty(L.tune_ps_workspace_size(len(sk["npix"]), sk["total"], nk), dtype=torch.uint8, device="cuda")
     res = L.tune_ps(spec, work)
     ref = tune_ps.iterate(mock["dl"], mock["eta"], sk, cfg["seed"], mock["z_t"], mock["c_t"], mock["fbar_t"], pk_t,
                           k_edges, cfg["dpix"], 1.0, 1.5, n_iter=n_iter,
-                          sigf_t=mock["sigf_t"] if known_sigf else None)
+                          sigf_t=mock["sigf_t"] if known_sigf else None, update=update)
     np.testing.assert_allclose([res.a[0], res.s[0]], [ref["a"], ref["s"]], rtol=1e-6)
     np.testing.assert_allclose(res.b[0], ref["b"], rtol=1e-6)
     np.testing.assert_allclose(list(res.sigma2), list(ref["moments"]), rtol=1e-6)
@@ -138,7 +139,34 @@ def test_tune_ps_rejects_bad_input(L, mock):
         L.tune_ps(spec, work)
 
 
-def test_tune_ps_outer_loop_matches_oracle(L, mock):
+def test_tune_ps_rejects_an_unknown_update(L, mock):
+    import torch
+    cfg, sk = mock["cfg"], mock["sk"]
+    s, keep = skewer_tensors(L, sk)
+    k_edges = mock["k_edges"]
+    nk = len(k_edges) - 1
+    dl, eta = _dev(torch, mock["dl"], np.float32), _dev(torch, mock["eta"], np.float32)
+    ke = _dev(torch, k_edges, np.float64)
+    spec = L.TunePsSpec()
+    spec.sk = ctypes_pointer(L, s)
+    spec.dens_l, spec.eta = dl.data_ptr(), eta.data_ptr()
+    spec.n_pixels = int(sk["total"])
+    spec.cosmo = L.Cosmo(0.3147)
+    spec.seed = cfg["seed"]
+    spec.n_zt = 1
+    spec.z_t[0], spec.c_t[0], spec.fbar_t[0], spec.sigf_t[0] = mock["z_t"], mock["c_t"], mock["fbar_t"], mock["sigf_t"]
+    pk_t = np.ascontiguousarray(mock["pk_t"], dtype=np.float64)
+    spec.p1d_t = pk_t.ctypes.data
+    spec.p1d = L.P1dSpec(nk, ke.data_ptr(), mock["z_t"], cfg["dpix"])
+    spec.ps_amp, spec.ps_kcut, spec.n_iter = 1.0, 1.5, 2
+    spec.update = 2
+    work = torch.empty(L.tune_ps_workspace_size(len(sk["npix"]), sk["total"], nk), dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.LyaError, match="update"):
+        L.tune_ps(spec, work)
+
+
+@pytest.mark.parametrize("update", ["paper", "secant"])
+def test_tune_ps_outer_loop_matches_oracle(L, mock, update):
     # three outer steps (the bias-matched re-solve of (a, s) between P_s runs)
     import torch
     cfg, sk = mock["cfg"], mock["sk"]
@@ -163,11 +191,12 @@ def test_tune_ps_outer_loop_matches_oracle(L, mock):
     spec.ps_amp, spec.ps_kcut, spec.n_iter = 1.0, 1.5, n_iter
     spec.n_outer, spec.f = n_outer, cfg["f"]
     spec.beff_t[0] = mock["beff_t"]
+    spec.update = L.PS_UPDATE_SECANT if update == "secant" else L.PS_UPDATE_PAPER
     work = torch.empty(L.tune_ps_workspace_size(len(sk["npix"]), sk["total"], nk), dtype=torch.uint8, device="cuda")
     res = L.tune_ps(spec, work)
     ref = tune_ps.iterate(mock["dl"], mock["eta"], sk, cfg["seed"], mock["z_t"], mock["c_t"], mock["fbar_t"], pk_t,
                           k_edges, cfg["dpix"], 1.0, 1.5, n_iter=n_iter, sigf_t=mock["sigf_t"], n_outer=n_outer,
-                          beff_t=mock["beff_t"], f=cfg["f"])
+                          beff_t=mock["beff_t"], f=cfg["f"], update=update)
     got_beff = [res.beff[o] for o in range(res.n_outer_done[0])]
     print("outer loop: steps %d; b_eff / target %s (oracle %s); a %.6f b %.6f (oracle %.6f %.6f)"
           % (res.n_outer_done[0], ["%.5f" % (v / mock["beff_t"]) for v in got_beff],

@@ -232,12 +232,14 @@ def test_emulator_mode_hands_over_to_the_plain_iteration(L, fam):
     np.testing.assert_array_equal(np.array(re_.fbar[:4]), np.array(rp.fbar[:4]))
 
 
-def test_emulator_mode_refinement_matches_the_oracle(L, fam, emu):
+@pytest.mark.parametrize("update", ["paper", "secant"])
+def test_emulator_mode_refinement_matches_the_oracle(L, fam, emu, update):
     # three per-bin iterations after the fit: the oracle's iteration started
     # from the fitted form (its (a, s) come from the same mean flux and
     # dispersion targets) gives the same statistics
     sp = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu, checks=8)
     sp.spec.emu_refine = 3
+    sp.spec.update = L.PS_UPDATE_SECANT if update == "secant" else L.PS_UPDATE_PAPER
     res = L.tune_ps(sp.spec, sp.work)
     plain_fit = Spec(L, fam, L.TUNE_PS_EMULATOR, emu=emu, checks=8)
     r0 = L.tune_ps(plain_fit.spec, plain_fit.work)
@@ -246,7 +248,7 @@ def test_emulator_mode_refinement_matches_the_oracle(L, fam, emu):
     nk = len(fam["k_edges"]) - 1
     ref = tune_ps.iterate(fam["dl"], fam["eta"], fam["sk"], fam["seed"], fam["z_t"], fam["c_t"], fam["fbar_t"],
                           fam["pk_t"], fam["k_edges"], fam["dpix"], res.ps_fit[0], res.ps_fit[1], n_iter=3,
-                          sigf_t=fam["sigf_t"])
+                          sigf_t=fam["sigf_t"], update=update)
     np.testing.assert_allclose([res.fbar[i] for i in range(3)], [h["fbar"] for h in ref["hist"]], rtol=TOL)
     last = ref["hist"][-1]
     ok = np.isfinite(last["p1d"])

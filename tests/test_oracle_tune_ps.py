@@ -85,6 +85,40 @@ def test_ratios_scale_the_mode_amplitudes():
     np.testing.assert_allclose(mod[~inside], base[~inside], rtol=1e-12, atol=1e-12)
 
 
+def test_paper_update_is_the_ratio_of_target_to_measured_power():
+    r = np.array([1.0, 2.0, 0.5, 1.5, 3.0])
+    pk = np.array([2.0, 1.0, np.nan, 0.0, 4.0])
+    pk_t = np.array([1.0, 3.0, 1.0, 1.0, np.nan])
+    out = tune_ps.update_ratio(r, pk, pk_t)
+    np.testing.assert_array_equal(out, [0.5, 6.0, 0.5, 1.5, 3.0])   # bins 2-4: no finite positive pair
+    # the secant form at the first iteration of a run is the same step
+    np.testing.assert_array_equal(tune_ps.update_ratio(r, pk, pk_t, None, "secant"), out)
+    with pytest.raises(ValueError):
+        tune_ps.update_ratio(r, pk, pk_t, None, "newton")
+
+
+def test_secant_update_lands_on_the_target_for_a_power_law_response():
+    # P1D_b = c_b r_b^gamma_b: the secant of two iterations is gamma_b exactly,
+    # and the step (P_t/P1D)^(1/gamma) reaches the target in one move when
+    # 1/gamma lies in [1, 3]; outside, the exponent is clipped (gamma = 2: the
+    # paper's step; gamma = 0.1: exponent 3), and gamma <= 0.05 (here a
+    # response that falls) or a ratio that did not move takes the paper's step
+    c = np.array([2.0, 0.7, 1.3, 0.9, 1.1, 1.6, 0.8])
+    gam = np.array([1.0, 0.5, 0.4, 2.0, 0.1, -0.3, 0.6])
+    pk_t = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+    P = lambda r: c * r ** gam
+    r0 = np.ones(7)
+    r1 = tune_ps.update_ratio(r0, P(r0), pk_t, None, "secant")
+    r1[6] = r0[6] * (1 + 1e-8)             # this bin's ratio barely moved
+    r2 = tune_ps.update_ratio(r1, P(r1), pk_t, (r0, P(r0)), "secant")
+    p1, p2 = P(r1), P(r2)
+    np.testing.assert_allclose(p2[:3], pk_t[:3], rtol=1e-12)
+    np.testing.assert_allclose(p2[3], p1[3] * (pk_t[3] / p1[3]) ** 2, rtol=1e-12)
+    np.testing.assert_allclose(p2[4], p1[4] * (pk_t[4] / p1[4]) ** 0.3, rtol=1e-12)
+    np.testing.assert_allclose(r2[5], r1[5] * pk_t[5] / p1[5], rtol=1e-12)
+    np.testing.assert_allclose(r2[6], r1[6] * pk_t[6] / p1[6], rtol=1e-12)
+
+
 def test_iteration_converges_towards_a_target_from_another_small_scale_power():
     cfg = mockinputs.config("tiny")
     n, dx, seed = cfg["n"], cfg["dx"], cfg["seed"]
@@ -113,6 +147,13 @@ def test_iteration_converges_towards_a_target_from_another_small_scale_power():
     assert err[-1] < 0.7 * err[0]
     assert abs(res["hist"][-1]["fbar"] / fbar_t - 1) < 0.03
     assert abs(res["b"] / 1.4 - 1) < 0.03
+    # the secant update: the same first step, then larger ones
+    sec = tune_ps.iterate(dl, eta, sk, seed, z_t, c_t, fbar_t, pk_t, k_edges, cfg["dpix"], 1.0, 1.5, n_iter=6,
+                          sigf_t=float(F.std()), update="secant")
+    err_s = [np.sqrt(np.mean((h["p1d"][ok] / pk_t[ok] - 1) ** 2)) for h in sec["hist"]]
+    print("secant update: P1D relative RMS error per iteration", ["%.3f" % e for e in err_s])
+    assert err_s[:2] == pytest.approx(err[:2], rel=1e-12)
+    assert err_s[-1] < 0.8 * err[-1]
 
 
 @pytest.mark.parametrize("a,s,sg", [(0.3, 0.8, 2.0), (0.05, 2.5, 3.1), (1.2, 0.4, 1.0)])
