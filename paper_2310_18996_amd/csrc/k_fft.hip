@@ -31,6 +31,7 @@
 // each XCD walks a contiguous range of tiles (neighbouring z chunks share
 // cache lines).
 #include <atomic>
+#include <type_traits>
 
 #include "lya_internal.h"
 
@@ -237,6 +238,8 @@ struct Pass {
   }
 
   // stage-0 registers of a strided tile straight from global memory
+  // (EL..EH: the part of the thread's elements b R + r to load)
+  template <int EL = 0, int EH = E>
   __device__ static __forceinline__ void load_global0(float2 (&v)[E], const float2* __restrict__ data, int outer,
                                                       int t0, int tid) {
     constexpr int R = radix_of(N, 0), B = E / R;
@@ -244,36 +247,45 @@ struct Pass {
       const float2* __restrict__ plane = data + base_in(outer, t0);
 #pragma unroll
       for (int b = 0; b < B; ++b) {
+        if (b * R + R <= EL || b * R >= EH) continue;
         int p, j;
         coords<R>(tid + b * NT, p, j);
         const uint32_t o = off_in(j, p);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b * R + r] = plane[o + static_cast<uint32_t>(r * (N / R) * N)];
+        for (int r = 0; r < R; ++r)
+          if (b * R + r >= EL && b * R + r < EH) v[b * R + r] = plane[o + static_cast<uint32_t>(r * (N / R) * N)];
       }
     } else {
 #pragma unroll
       for (int b = 0; b < B; ++b) {
+        if (b * R + R <= EL || b * R >= EH) continue;
         int p, j;
         coords<R>(tid + b * NT, p, j);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b * R + r] = data[gidx(outer, t0, j + r * (N / R), p)];
+        for (int r = 0; r < R; ++r)
+          if (b * R + r >= EL && b * R + r < EH) v[b * R + r] = data[gidx(outer, t0, j + r * (N / R), p)];
       }
     }
   }
 
-  // stages 0.. of the tile held in v, the results left in v for store_global<NSTAGE - 1>
+  // stages 0.. of the tile held in v, the results left in v for
+  // store_global<NSTAGE - 1>; hook(k) runs before stage k's butterflies
+  template <typename H>
   __device__ static __forceinline__ void transform(float2 (&v)[E], float2* lds, const float2* __restrict__ tw,
-                                                   int tid) {
+                                                   int tid, H hook) {
+    hook(std::integral_constant<int, 0>());
     butterflies<0>(v, tw, tid);
     store_lds<0>(v, lds, tid);
     __syncthreads();
     load_lds<1>(v, lds, tid);
+    hook(std::integral_constant<int, 1>());
     butterflies<1>(v, tw, tid);
     if constexpr (NSTAGE == 3) {
       __syncthreads();
       store_lds<1>(v, lds, tid);
       __syncthreads();
       load_lds<2>(v, lds, tid);
+      hook(std::integral_constant<int, 2>());
       butterflies<2>(v, tw, tid);
     }
   }
@@ -325,13 +337,15 @@ struct Pass {
     }
   }
 
-  template <int S>
+  // EL..EH: the part of the thread's elements (b R + r) to store
+  template <int S, int EL = 0, int EH = E>
   __device__ static __forceinline__ void store_global(const float2 (&v)[E], float2* data, uint32_t* out_bf16,
                                                       bool zero_b, int outer, int t0, bool paired, int tid) {
     constexpr int R = radix_of(N, S), B = E / R;
     static_assert(ns_before(N, S) * R == N, "last stage");
 #pragma unroll
     for (int b = 0; b < B; ++b) {
+      if (b * R + R <= EL || b * R >= EH) continue;
       int p, j;
       coords<R>(tid + b * NT, p, j);
       // base + offset of element j + r N/R (see base_in)
@@ -345,6 +359,7 @@ struct Pass {
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
+        if (b * R + r < EL || b * R + r >= EH) continue;
         size_t gi;
         if constexpr (KIND == KIND_Y) {
           gi = base + static_cast<uint32_t>(r * (N / R) * N);
@@ -549,8 +564,14 @@ __global__ void __launch_bounds__(N * T / E) k_fft_pass(float2* __restrict__ dat
 // iteration after that iteration's loads: a store waits for its address
 // translation, and loads issued behind it wait too, which for stores spread
 // over N planes (the transposing pass) held the next tile's loads back
-// (2048^3: 37.0-37.2 ms against 37.9-38.0 ms, bit-identical).
-template <int N, int T, int E, int KIND, int ORDER, bool LAST = KIND == KIND_X, bool DEFER = false>
+// (2048^3: 37.0-37.2 ms against 37.9-38.0 ms, bit-identical).  SPLIT issues
+// the next tile's loads (and the deferred stores) in three parts, one before
+// each FFT stage, instead of all at the start of the iteration: a wave that
+// issues its 16 loads and 16 stores at once stalls on the full memory queue
+// before it reaches the FFT, while in parts the memory traffic runs under the
+// stages (the transposing pass at 2048^3: 31.6-31.8 ms, bit-identical; the
+// same kernel without its FFT moves the box in 29.4 ms).
+template <int N, int T, int E, int KIND, int ORDER, bool LAST = KIND == KIND_X, bool DEFER = false, bool SPLIT = false>
 __global__ void __launch_bounds__(N * T / E) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const float2* __restrict__ tw, GenParams g) {
   using P = Pass<N, T, E, KIND>;
@@ -579,23 +600,38 @@ k_fft_pipe(float2* __restrict__ data, uint32_t* __restrict__ out_bf16, const flo
     const int bn = b + static_cast<int>(gridDim.x);
     const bool more = bn < ntiles;
     int on = 0, tn = 0;
-    if (more) {
-      strided_tile<N, T, ORDER>(bn, on, tn);
-      P::load_global0(nv, data, on, tn, tid);
+    if (more) strided_tile<N, T, ORDER>(bn, on, tn);
+    float2* dst = KIND == KIND_YT ? g.dst : data;
+    uint32_t* bf = LAST ? out_bf16 : nullptr;
+    const bool zb = LAST && g.comp_b < 0;
+    constexpr int NS = P::NSTAGE, LS = NS - 1;
+    if constexpr (SPLIT) {
+      // the next tile's loads, and the previous tile's deferred stores, in
+      // parts before each stage of this tile's FFT
+      P::transform(v, lds, stw, tid, [&](auto k) {
+        constexpr int K = decltype(k)::value, EL = E * K / NS, EH = E * (K + 1) / NS;
+        if (more) P::template load_global0<EL, EH>(nv, data, on, tn, tid);
+        if constexpr (DEFER)
+          if (have) P::template store_global<LS, EL, EH>(ov, dst, bf, zb, po, pt, false, tid);
+      });
+    } else {
+      if (more) P::load_global0(nv, data, on, tn, tid);
+      if constexpr (DEFER) {
+        // the previous tile's stores, issued after the next tile's loads
+        if (have) P::template store_global<LS>(ov, dst, bf, zb, po, pt, false, tid);
+        P::transform(v, lds, stw, tid, [](auto) {});
+      } else {
+        P::transform_store(v, lds, dst, bf, stw, zb, outer, t0, false, tid);
+      }
     }
     if constexpr (DEFER) {
-      // the previous tile's stores, issued after the next tile's loads
-      if (have) P::template store_global<P::NSTAGE - 1>(ov, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr,
-                                                         LAST && g.comp_b < 0, po, pt, false, tid);
-      P::transform(v, lds, stw, tid);
 #pragma unroll
       for (int e = 0; e < E; ++e) ov[e] = v[e];
       po = outer;
       pt = t0;
       have = true;
-    } else {
-      P::transform_store(v, lds, KIND == KIND_YT ? g.dst : data, LAST ? out_bf16 : nullptr, stw, LAST && g.comp_b < 0,
-                         outer, t0, false, tid);
+    } else if constexpr (SPLIT) {
+      P::template store_global<LS>(v, dst, bf, zb, outer, t0, false, tid);
     }
     if (!more) break;
     __syncthreads();  // every thread has read this tile's LDS before the next one is written
@@ -862,7 +898,8 @@ hipError_t launch_zgen(const GenParams& g, int gm, const float2* tw, float2* out
 // (second -> field, over kx) and the last pass (field in place, over ky);
 // from 1024 up in the pipelined kernel with full tiles and tile order 1, the
 // transposing pass with half the elements per thread (the shape of strided
-// variant 9) and deferred stores, the last pass with the full count (at 2048^3: 38.0 + 32.0 ms,
+// variant 9), deferred stores and loads and stores split over the FFT stages,
+// the last pass with the full count (at 2048^3: 38.0 + 32.0 ms,
 // against 38.0 + 33.8 ms with half the elements in both, 40.5 ms for the
 // transposing pass with the full count, 39.3 + 34.2 ms in tile order 0 and
 // 53.6 ms for the transposing pass in order 3), below as one tile per block.
@@ -877,7 +914,7 @@ hipError_t launch_two_buffer(GenParams g, const float2* tw, float2* second, floa
     if (blocks > ntiles) blocks = ntiles;
     constexpr int EL = S::ES, ntl = N * T / EL;
     LYA_TIMED("fft_x2", st,
-              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_YT, 1, false, true>), dim3(blocks), dim3(nt), 0, st,
+              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_YT, 1, false, true, true>), dim3(blocks), dim3(nt), 0, st,
                                  second, nullptr, tw, g));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
