@@ -658,15 +658,17 @@ int lya_quasar_skewers(const lya_box* box, const lya_qso_los_spec* spec, const l
  *                     waves), order 0/1; 8/9 those in the pipelined kernel;
  *                     10/11 full tiles with tile order 2 (plain block order) /
  *                     3 (outer index fastest within an XCD); 12/13 full tiles
- *                     in the pipelined kernel, order 0/1.  Boxes below 1024
- *                     have variants 0 and 1 only.  Defaults: y 8, x 9 from
- *                     1024 up, y 0, x 1 below.
+ *                     in the pipelined kernel, order 0/1; 14/15 as 8/9 with
+ *                     the next tile's loads issued in parts, one before each
+ *                     FFT stage.  All variants give bit-identical boxes.
+ *                     Boxes below 1024 have variants 0 and 1 only.
+ *                     Defaults: y 8, x 15 from 1024 up, y 0, x 1 below.
  *   sk_chunk          skewers taken per pull from the skewer work queue (default 4);
  *   sk_blocks_per_cu  persistent skewer blocks per CU, 1..4 (default 4);
  *   sk_unroll         pixels per lane whose gathers are issued together, 1, 2 or 4
  *                     (default 1).
  * The table is process-wide and applies to every later call for that n. */
-#define LYA_FFT_VARIANTS 14
+#define LYA_FFT_VARIANTS 16
 typedef struct {
   int32_t fft_y, fft_x, sk_chunk, sk_blocks_per_cu, sk_unroll;
 } lya_tuning;

@@ -667,13 +667,17 @@ template <> struct Shape<2048> { static constexpr int TZ = 2,  EZ = 16, TS = 8, 
 //   6/7: full tiles with half the elements per thread (twice the waves), order 0/1;
 //   8/9: as 6/7 in the persistent pipelined kernel;
 //   10/11: full tiles, one per block, tile order 2 (plain) / 3 (outer index fastest);
-//   12/13: full tiles in the persistent pipelined kernel, order 0/1.
+//   12/13: full tiles in the persistent pipelined kernel, order 0/1;
+//   14/15: as 8/9 with the next tile's loads issued in parts before the FFT
+//          stages (SPLIT).
 // Boxes below 1024 have variants 0 and 1 only.
 namespace {
 // [pass y/x][log2 N]; defaults: below 1024 one tile per block, y with tile
 // order 0 and x with order 1; from 1024 up the pipelined kernel with full
-// tiles of half the elements per thread, y order 0 (variant 8), x order 1 (9)
-std::atomic<int> g_variant[2][12] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 8, 8}, {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 9, 9}};
+// tiles of half the elements per thread, y order 0 (variant 8), x order 1
+// with its loads split over the FFT stages (15: 36.6 ms against 42.0 ms for
+// 9 at 2048^3, bit-identical; for y the split measured 31.4 against 31.1 ms)
+std::atomic<int> g_variant[2][12] = {{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 8, 8}, {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 15, 15}};
 int ilog2(int n) {
   int l = 0;
   while ((1 << l) < n && l < 11) ++l;
@@ -690,7 +694,7 @@ int set_fft_variant(int n, int pass, int v) {
   return 0;
 }
 
-template <int N, int T, int E, int KIND, int ORDER, bool PIPE>
+template <int N, int T, int E, int KIND, int ORDER, bool PIPE, bool SPL = false>
 hipError_t launch_strided_tile(float2* field, uint32_t* bf16, const float2* tw, const GenParams& g, hipStream_t st) {
   const char* name = KIND == KIND_Y ? "fft_y" : "fft_x";
   constexpr int ntiles = N * (N / T), nt = N * T / E;
@@ -698,8 +702,8 @@ hipError_t launch_strided_tile(float2* field, uint32_t* bf16, const float2* tw, 
     int blocks = (device_cus() + 7) / 8 * 8;
     if (blocks > ntiles) blocks = ntiles;
     LYA_TIMED(name, st,
-              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND, ORDER>), dim3(blocks), dim3(nt), 0, st, field, bf16, tw,
-                                 g));
+              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND, ORDER, KIND == KIND_X, false, SPL>), dim3(blocks), dim3(nt),
+                                 0, st, field, bf16, tw, g));
   } else {
     LYA_TIMED(name, st,
               hipLaunchKernelGGL((k_fft_pass<N, T, E, KIND, ORDER>), dim3(ntiles), dim3(nt), 0, st, field, bf16, tw,
@@ -727,6 +731,8 @@ hipError_t launch_strided(int variant, float2* field, uint32_t* bf16, const floa
       case 11: return launch_strided_tile<N, S::TS, S::ES, KIND, 3, false>(field, bf16, tw, g, st);
       case 12: return launch_strided_tile<N, S::TS, S::ES, KIND, 0, true>(field, bf16, tw, g, st);
       case 13: return launch_strided_tile<N, S::TS, S::ES, KIND, 1, true>(field, bf16, tw, g, st);
+      case 14: return launch_strided_tile<N, S::TS, EH, KIND, 0, true, true>(field, bf16, tw, g, st);
+      case 15: return launch_strided_tile<N, S::TS, EH, KIND, 1, true, true>(field, bf16, tw, g, st);
       default: break;
     }
   }

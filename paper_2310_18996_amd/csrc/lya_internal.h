@@ -91,7 +91,7 @@ size_t zorder_words(int n);
 hipError_t launch_box_fft(int n, const GenParams& g, const float2* tw, float2* field, uint32_t* field_bf16,
                           float2* second, uint32_t* zorder, hipStream_t st);
 // Strided-pass variants (0..kFftVariants-1) per box size and pass (0 = y, 1 = x).
-constexpr int kFftVariants = 14;
+constexpr int kFftVariants = 16;
 int fft_variant(int n, int pass);
 int set_fft_variant(int n, int pass, int v);
 hipError_t launch_fft_strided_pass(int n, int pass, int variant, const float2* tw, float2* field, hipStream_t st);

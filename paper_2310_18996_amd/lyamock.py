@@ -355,7 +355,7 @@ class TunePsResult(ctypes.Structure):
                 ("fallback", ctypes.c_int32 * TUNE_MAX_Z)]
 
 
-FFT_VARIANTS = 14
+FFT_VARIANTS = 16
 SK_CHUNKS = (1, 2, 4, 8, 16, 32, 64)
 SK_BLOCKS_PER_CU = (1, 2, 3, 4)
 SK_UNROLL = (1, 2, 4)

@@ -96,7 +96,7 @@ def test_chi_of_z_on_the_host_matches_the_oracle():
 
 def test_tuning_table_on_the_host():
     t = L.get_tuning(2048)
-    assert (t.fft_y, t.fft_x, t.sk_chunk, t.sk_blocks_per_cu, t.sk_unroll) == (8, 9, 4, 4, 1)
+    assert (t.fft_y, t.fft_x, t.sk_chunk, t.sk_blocks_per_cu, t.sk_unroll) == (8, 15, 4, 4, 1)
     L.set_tuning(2048, L.Tuning(4, 5, 16, 2, 4))
     u = L.get_tuning(2048)
     assert (u.fft_y, u.fft_x, u.sk_chunk, u.sk_blocks_per_cu, u.sk_unroll) == (4, 5, 16, 2, 4)
