@@ -902,13 +902,14 @@ hipError_t launch_zgen(const GenParams& g, int gm, const float2* tw, float2* out
 
 // The two strided passes of the two-buffer order: the transposing pass
 // (second -> field, over kx) and the last pass (field in place, over ky);
-// from 1024 up in the pipelined kernel with full tiles and tile order 1, the
-// transposing pass with half the elements per thread (the shape of strided
-// variant 9), deferred stores and loads and stores split over the FFT stages,
-// the last pass with the full count (at 2048^3: 38.0 + 32.0 ms,
-// against 38.0 + 33.8 ms with half the elements in both, 40.5 ms for the
-// transposing pass with the full count, 39.3 + 34.2 ms in tile order 0 and
-// 53.6 ms for the transposing pass in order 3), below as one tile per block.
+// from 1024 up in the pipelined kernel with full tiles of half the elements
+// per thread (the shape of strided variant 9) and tile order 1, the
+// transposing pass with deferred stores and its loads and stores split over
+// the FFT stages.  At 2048^3: 31.5 + 30.3 ms.  The last pass took 32.0 ms
+// with the full element count per thread and 32.7 ms with its loads split,
+// 33.4 ms in tile order 0 (it ran at 33.8 ms with half the elements and
+// 32.0 ms with the full count while the transposing pass still issued its
+// stores at once).  Below 1024 one tile per block.
 template <int N>
 hipError_t launch_two_buffer(GenParams g, const float2* tw, float2* second, float2* field, uint32_t* field_bf16,
                              hipStream_t st) {
@@ -918,14 +919,13 @@ hipError_t launch_two_buffer(GenParams g, const float2* tw, float2* second, floa
     constexpr int T = S::TS, E = S::ES / 2, ntiles = N * (N / T), nt = N * T / E;
     int blocks = (device_cus() + 7) / 8 * 8;
     if (blocks > ntiles) blocks = ntiles;
-    constexpr int EL = S::ES, ntl = N * T / EL;
     LYA_TIMED("fft_x2", st,
               hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_YT, 1, false, true, true>), dim3(blocks), dim3(nt), 0, st,
                                  second, nullptr, tw, g));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     LYA_TIMED("fft_y2", st,
-              hipLaunchKernelGGL((k_fft_pipe<N, T, EL, KIND_Y, 1, true>), dim3(blocks), dim3(ntl), 0, st, field,
+              hipLaunchKernelGGL((k_fft_pipe<N, T, E, KIND_Y, 1, true>), dim3(blocks), dim3(nt), 0, st, field,
                                  field_bf16, tw, g));
   } else {
     constexpr int T = S::TS, E = S::ES, ntiles = N * (N / T), nt = N * T / E;
