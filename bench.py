@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 # kernel; valid only for the kernels as they were when the counters were taken
 # (a changed kernel must drop its entry) and reported only for that workload.
 TRAFFIC = {("fft_x", 9): 137490967113, ("fft_y", 8): 140316083069,
-           ("fft_z_gen", "2buf"): 71344317729, ("fft_x2", None): 137464313749, ("fft_y2", None): 138784574436,
-           ("skewers", (4, 4, 1)): 14518703898, ("qso_draw", None): 137560151198}
+           ("fft_z_gen", "2buf"): 71343721648, ("fft_x2", None): 137466313366, ("fft_y2", None): 137819123443,
+           ("skewers", (4, 4, 1)): 14514918370, ("qso_draw", None): 137560151198}
 TRAFFIC_CONFIG = "big"
 
 
